@@ -1,0 +1,81 @@
+"""Oracle: one Gauss-Newton step of SketchPrec and the sketch-reuse test.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+One GN iteration (Sec. 2.2, eqs. (gniter), (gniterf1), (pcgsystem); Sec. 3.2):
+  1. x = x_b + Gamma^{1/2} v, forward model, innovations        (one FWD)
+  2. g_v = v + A^T d                                             (one ADJ)
+  3. b = -g_v
+  4. optionally test a resident preconditioner with kappa_re (eq. (condtext2))
+  5. otherwise sketch H (Nystrom, Alg. 2 or RandSVD, Alg. 1)    (l TLM + l ADJ)
+  6. PCG on (I + H) dv = b, preconditioned by eq. (woodbury)     (one TLM+ADJ / iter)
+  7. v <- v + alpha dv (alpha = 1: the paper's More-Thuente line search is an
+     external toolbox; the unit GN step is the reading used here)
+
+Counters follow Sec. 5 / Tables 2, 4: offline TLM/ADJ are those spent building
+sketches; online FWD/TLM/ADJ are spent in the cost/gradient and in PCG.
+"""
+import numpy as np
+
+from . import sketch as _sketch
+from .pcg import pcg as _pcg
+
+
+def kappa_re(prob, traj, V, lam, vhat):
+    """kappa_re = ||(I + H^(k)) (I + H_hat^(k-i))^{-1} v||_2 with v a unit vector
+    (eq. (condtext2); also kappa_sk of eq. (condtext) when the sketch is fresh)."""
+    v = np.asarray(vhat, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    z = _sketch.lmp_apply(V, lam, v)
+    return float(np.linalg.norm(prob.hessian(traj, z)))
+
+
+def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
+    if method == 'nystrom':
+        V, lam, _ = _sketch.nystrom(lambda X: prob.misfit_hessian(traj, X), Omega, eps=eps)
+    elif method == 'randsvd':
+        m = prob.m
+        V, lam = _sketch.randsvd(lambda X: prob.A(traj, X).reshape(m, -1),
+                                 lambda W: prob.AT(traj, W.reshape(prob.n_t, prob.n_obs, -1)),
+                                 Omega)
+    else:
+        raise ValueError(method)
+    return V, lam
+
+
+def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
+            precond=None, reuse_eps=None, vhat=None, counters=None):
+    """One GN step from control vector v.
+
+    method: 'nystrom' | 'randsvd' | 'none' (Prec_Gamma).
+    precond: optional resident (V, lam) from an earlier iterate; with reuse_eps
+    set it is kept when kappa_re(vhat) < reuse_eps, otherwise rebuilt from Omega.
+    Returns (v_new, dv, x_new, info)."""
+    c = counters if counters is not None else dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
+    J, g, traj, x = prob.cost_grad(v)
+    c['fwd'] += 1
+    c['adj_on'] += 1
+    b = -g
+    reused = False
+    kre = None
+    P = None
+    if method != 'none':
+        if precond is not None and reuse_eps is not None:
+            kre = kappa_re(prob, traj, precond[0], precond[1], vhat)
+            if kre < reuse_eps:
+                P = precond
+                reused = True
+        if P is None:
+            P = build_precond(prob, traj, method, Omega)
+            ell = Omega.shape[1]
+            c['tlm_off'] += ell
+            c['adj_off'] += ell
+    prec = (lambda r: _sketch.lmp_apply(P[0], P[1], r)) if P is not None else None
+    dv, pinfo = _pcg(lambda p: prob.hessian(traj, p), b, prec=prec, rtol=rtol, maxit=maxit)
+    c['tlm_on'] += pinfo['iters']
+    c['adj_on'] += pinfo['iters']
+    v_new = v + dv
+    x_new = prob.state(v_new)
+    info = dict(J=J, gnorm_inf=float(np.max(np.abs(g))), g=g, pcg=pinfo, reused=reused,
+                kappa_re=kre, precond=P, counters=c, x=x)
+    return v_new, dv, x_new, info

@@ -1,0 +1,96 @@
+"""Oracle: randomized low-rank approximations of the data-misfit Hessian and the
+limited-memory preconditioner they define.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+  * RandSVD      Sec. 3.1.1, Alg. 1 (randsvd)
+  * Nystrom      Sec. 3.1.1, Alg. 2 (nystrom), Tropp et al. fixed-rank Nystrom
+  * LMP          eq. (woodbury): (I + V L V^T)^{-1} = I - V (L^{-1} + I)^{-1} V^T
+  * W-form       Remark 1, eq. (randsvdsv): (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W
+
+Readings: no truncation (target rank r = l); machine epsilon of Nystrom's shift
+is that of the precision Y was computed in (2^-52 for float64, 2^-23 for
+float32); ||Y||_2 is the exact spectral norm; if the Cholesky factorisation of
+the shifted core matrix fails the shift is multiplied by 10 (at most 3 times);
+D = lambda / (1 + lambda) is the diagonal (Lambda^{-1} + I)^{-1} written so that
+lambda = 0 is allowed.
+"""
+import numpy as np
+from scipy.linalg import solve_triangular
+
+EPS64 = 2.0 ** -52
+EPS32 = 2.0 ** -23
+
+
+class NotSPDError(RuntimeError):
+    pass
+
+
+def nystrom(H_apply, Omega, eps=EPS64, max_retries=3):
+    """Alg. 2: returns (V_hat (n x l), lambda_hat (l,), nu)."""
+    Omega = np.asarray(Omega, dtype=np.float64)
+    n, ell = Omega.shape
+    Y0 = H_apply(Omega)                                  # step 2: Y = H Omega
+    nu = np.sqrt(n) * eps * np.linalg.norm(Y0, 2)         # step 3
+    for _ in range(max_retries + 1):
+        Y = Y0 + nu * Omega                               # step 4
+        C = Omega.T @ Y                                   # step 5
+        try:
+            L = np.linalg.cholesky(0.5 * (C + C.T))
+        except np.linalg.LinAlgError:
+            nu *= 10.0
+            continue
+        W = solve_triangular(L, Y.T, lower=True)          # step 6: W = L^{-1} Y^T
+        _, S, Vt = np.linalg.svd(W, full_matrices=False)  # step 7: thin SVD
+        lam = np.maximum(0.0, S * S - nu)                 # return Lambda = max(0, S^2 - nu)
+        return Vt.T.copy(), lam, nu
+    raise NotSPDError("Nystrom core matrix not positive definite after shift retries")
+
+
+def randsvd(A_apply, AT_apply, Omega):
+    """Alg. 1: Y = A Omega, Y = QR, W^T = A^T Q, thin SVD of W, Lambda = Sigma^2.
+    A_apply maps (n, l) -> (m, l); AT_apply maps (m, l) -> (n, l)."""
+    Omega = np.asarray(Omega, dtype=np.float64)
+    Y = A_apply(Omega)                                    # step 2
+    Q, _ = np.linalg.qr(Y)                                # step 3 (Householder)
+    Wt = AT_apply(Q)                                      # step 4: W^T = A^T Q
+    _, S, Vt = np.linalg.svd(Wt.T, full_matrices=False)   # step 5
+    return Vt.T.copy(), S * S
+
+
+def randsvd_W(A_apply, AT_apply, Omega):
+    """Alg. 1 steps 1-4 only: returns W (l x n) with H_hat = W^T W (Remark 1)."""
+    Y = A_apply(np.asarray(Omega, dtype=np.float64))
+    Q, _ = np.linalg.qr(Y)
+    return AT_apply(Q).T.copy()
+
+
+def lmp_diag(lam):
+    """(Lambda^{-1} + I)^{-1} = lambda / (1 + lambda)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return lam / (1.0 + lam)
+
+
+def lmp_apply(V, lam, r):
+    """(I + V diag(lam) V^T)^{-1} r via eq. (woodbury); r is (n,) or (n, k)."""
+    D = lmp_diag(lam)
+    t = V.T @ r
+    t = D * t if t.ndim == 1 else D[:, None] * t
+    return r - V @ t
+
+
+def woodbury_W_apply(W, r):
+    """(I + W^T W)^{-1} r via eq. (randsvdsv), using an l x l Cholesky."""
+    ell = W.shape[0]
+    Lc = np.linalg.cholesky(np.eye(ell) + W @ W.T)
+    t = W @ r
+    t = solve_triangular(Lc, t, lower=True)
+    t = solve_triangular(Lc.T, t, lower=False)
+    return r - W.T @ t
+
+
+def hhat_apply(V, lam, X):
+    """H_hat X = V diag(lam) V^T X."""
+    t = V.T @ X
+    t = lam * t if t.ndim == 1 else lam[:, None] * t
+    return V @ t

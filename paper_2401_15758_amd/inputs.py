@@ -1,0 +1,96 @@
+"""Seeded synthetic workloads: configurations and raw random draws.
+
+This module holds no arithmetic of the method: it only states the workload
+shapes and parameters and draws the random numbers that the method consumes
+(background noise xi, observation noise eta, Gaussian test matrices Omega,
+unit test vectors).  Both the HIP library (through its Python binding) and the
+CPU oracle take these arrays as inputs; neither computes them.
+
+Workloads (all synthetic; the paper's own data -- figure-only observation
+locations, a spun-up gyre truth -- are not available and not needed):
+
+  burgers-128    periodic Burgers n=128, nu=0.01, dt=1e-3, 50 RK4 steps, observe
+                 every 4th point every 10 steps, sigma_o=0.01, Gaussian prior
+                 sigma_b=0.05, L=0.05; sketch l=20.
+  burgers-4096   same at n=4096, 500 steps, every 16th point every 25 steps,
+                 sketch l=64, 3 GN iterations.  The configured dt=2.5e-5 is outside
+                 RK4's stability interval at this resolution (4 nu dt/dx^2 = 16.8 >
+                 2.785); the step is reduced to dt = 0.5 dx^2/nu (the step count
+                 and observation cadence are kept).
+  batch-64       64 independent Burgers problems, n log-uniform in [256, 4096],
+                 N uniform in [50, 500], per-problem seeds; sketch l=32.
+
+Truth: u0(x) = sin(2 pi x) + 0.5 sin(4 pi x) on x_j = j/n.
+"""
+import math
+import numpy as np
+
+RK4_DIFFUSIVE_LIMIT = 2.785   # RK4 real-axis stability interval (|z| <= 2.785)
+
+
+def stable_dt(n, nu, dt_cfg):
+    """Reading for configured steps outside RK4's stability interval: keep the
+    configured step when 4 nu dt/dx^2 <= 2.785, else use dt = 0.5 dx^2 / nu."""
+    dx = 1.0 / n
+    if 4.0 * nu * dt_cfg / (dx * dx) <= RK4_DIFFUSIVE_LIMIT:
+        return dt_cfg
+    return 0.5 * dx * dx / nu
+
+
+def burgers_config(n, nsteps, obs_stride, obs_every, dt_cfg=1e-3, nu=0.01,
+                   sigma_o=0.01, sigma_b=0.05, L_b=0.05, ell=20, name=None):
+    return dict(model='burgers', name=name or f'burgers-{n}', n=int(n), nu=float(nu),
+                dt=float(stable_dt(n, nu, dt_cfg)), dt_cfg=float(dt_cfg), nsteps=int(nsteps),
+                obs_stride=int(obs_stride), obs_every=int(obs_every), sigma_o=float(sigma_o),
+                sigma_b=float(sigma_b), L_b=float(L_b), ell=int(ell))
+
+
+CFG_SMALL = burgers_config(128, 50, 4, 10, dt_cfg=1e-3, ell=20, name='burgers-128')
+CFG_LARGE = burgers_config(4096, 500, 16, 25, dt_cfg=2.5e-5, ell=64, name='burgers-4096')
+
+
+def n_obs(cfg):
+    return len(range(0, cfg['n'], cfg['obs_stride']))
+
+
+def n_t(cfg):
+    return cfg['nsteps'] // cfg['obs_every']
+
+
+def truth(cfg):
+    x = np.arange(cfg['n']) / cfg['n']
+    return np.sin(2 * np.pi * x) + 0.5 * np.sin(4 * np.pi * x)
+
+
+def draws(cfg, seed=0):
+    """Raw draws for one problem: x_true, xi (n), eta (n_t, n_obs)."""
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal(cfg['n'])
+    eta = rng.standard_normal((n_t(cfg), n_obs(cfg)))
+    return dict(x_true=truth(cfg), xi=xi, eta=eta)
+
+
+def omega(n, ell, seed=1000):
+    """Gaussian test matrix Omega (n x ell), row-major (grid point major)."""
+    return np.random.default_rng(seed).standard_normal((n, ell))
+
+
+def unit_vector(n, seed=2000):
+    w = np.random.default_rng(seed).standard_normal(n)
+    return w / np.linalg.norm(w)
+
+
+def batch_configs(nprob=64, seed=0, n_lo=256, n_hi=4096, N_lo=50, N_hi=500, ell=32):
+    """Uneven batch: n = round(exp(U[ln n_lo, ln n_hi])), N ~ U{N_lo..N_hi};
+    observation layout and prior as in the 128-point workload, dt reduced where
+    the configured 1e-3 is outside RK4's stability interval."""
+    ss = np.random.SeedSequence(seed)
+    rng = np.random.default_rng(ss)
+    out = []
+    for p, child in enumerate(ss.spawn(nprob)):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        N = int(rng.integers(N_lo, N_hi + 1))
+        cfg = burgers_config(n, N, 4, 10, dt_cfg=1e-3, ell=ell, name=f'batch-{p}')
+        cfg['seed'] = int(child.generate_state(1)[0])
+        out.append(cfg)
+    return out

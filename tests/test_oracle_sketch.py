@@ -1,0 +1,142 @@
+"""Pins of the sketch oracle: Nystrom and RandSVD against their closed-form
+projector definitions (pseudo-inverse formulas of Sec. 3.1.1 / Sec. 4.4), exactness
+when l >= rank, the Loewner ordering H_hat <= H (Sec. 4.3-4.4), the deterministic
+condition-number bound of Thm. (bound_loew), the expectation bound of Thms.
+(RandSVD)/(Nystrom), the Woodbury identities and the intrinsic-dimension closed forms."""
+import numpy as np
+import pytest
+from scipy.special import zeta
+
+from oracle import analysis, sketch
+
+
+def _lowrank_psd(n, r, seed, decay=0.5):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    lam = 100.0 * decay ** np.arange(r)
+    return (U * lam) @ U.T, U, lam
+
+
+def test_nystrom_matches_pseudoinverse_formula():
+    H, _, _ = _lowrank_psd(60, 30, 1, decay=0.7)
+    Om = np.random.default_rng(2).standard_normal((60, 12))
+    V, lam, nu = sketch.nystrom(lambda X: H @ X, Om)
+    Y = H @ Om
+    ref = Y @ np.linalg.pinv(Om.T @ Y) @ Y.T
+    Hh = sketch.hhat_apply(V, lam, np.eye(60))
+    assert np.linalg.norm(Hh - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.allclose(V.T @ V, np.eye(12), atol=1e-10)
+
+
+def test_nystrom_exact_when_sketch_exceeds_rank():
+    H, _, _ = _lowrank_psd(50, 6, 3)
+    Om = np.random.default_rng(4).standard_normal((50, 10))
+    V, lam, nu = sketch.nystrom(lambda X: H @ X, Om)
+    Hh = sketch.hhat_apply(V, lam, np.eye(50))
+    assert np.linalg.norm(Hh - H, 2) <= 100 * nu + 1e-12 * np.linalg.norm(H, 2)
+
+
+def test_randsvd_matches_projector_formula():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((40, 70)) * (0.6 ** np.arange(70))[None, :]
+    Om = rng.standard_normal((70, 15))
+    V, lam = sketch.randsvd(lambda X: A @ X, lambda W: A.T @ W, Om)
+    Y = A @ Om
+    P = Y @ np.linalg.pinv(Y)
+    ref = A.T @ P @ A
+    Hh = sketch.hhat_apply(V, lam, np.eye(70))
+    assert np.linalg.norm(Hh - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_lmp_inverts_one_plus_hhat_and_woodbury_W_form():
+    rng = np.random.default_rng(6)
+    n, ell = 80, 10
+    V, _ = np.linalg.qr(rng.standard_normal((n, ell)))
+    lam = np.abs(rng.standard_normal(ell)) * 10
+    lam[-1] = 0.0
+    M = np.eye(n) + (V * lam) @ V.T
+    P = sketch.lmp_apply(V, lam, np.eye(n))
+    assert np.linalg.norm(P @ M - np.eye(n)) <= 1e-13 * n
+    W = rng.standard_normal((ell, n))
+    r = rng.standard_normal(n)
+    ref = np.linalg.solve(np.eye(n) + W.T @ W, r)
+    assert np.allclose(sketch.woodbury_W_apply(W, r), ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_loewner_order_and_condition_bound_on_burgers(small_problem, small_dense, method):
+    """Thm. (bound_loew) special case: E = H - H_hat >= 0 and
+    kappa_2 <= 1 + ||E||_2 for every seed and sketch size (deterministic)."""
+    p = small_problem
+    traj, Hs, _ = small_dense
+    A = None
+    if method == 'randsvd':
+        A = p.A(traj, np.eye(p.n)).reshape(p.m, p.n)
+    for ell in (5, 10, 20, 40):
+        for seed in range(4):
+            Om = np.random.default_rng(1000 + seed).standard_normal((p.n, ell))
+            if method == 'nystrom':
+                V, lam, nu = sketch.nystrom(lambda X: Hs @ X, Om)
+            else:
+                V, lam = sketch.randsvd(lambda X: A @ X, lambda W: A.T @ W, Om)
+                nu = 0.0
+            Hh = sketch.hhat_apply(V, lam, np.eye(p.n))
+            E = Hs - 0.5 * (Hh + Hh.T)
+            wE = np.linalg.eigvalsh(E)
+            tol = 1e-13 * np.linalg.norm(Hs, 2) + 10 * nu
+            assert wE[0] >= -tol
+            kap = analysis.precond_kappa(Hs, Hh)
+            assert kap <= 1 + wE[-1] + 1e-8 * (1 + wE[-1])
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_expected_condition_bound(small_problem, small_dense, method):
+    """Thms. (RandSVD), (Nystrom): E[kappa_2] <= 1 + Psi_H(r, p), checked with the
+    sample mean over 40 seeds (the bound holds with margin for this spectrum)."""
+    p = small_problem
+    traj, Hs, _ = small_dense
+    lamH = np.linalg.eigvalsh(Hs)[::-1]
+    ell, r = 20, 14
+    A = p.A(traj, np.eye(p.n)).reshape(p.m, p.n) if method == 'randsvd' else None
+    kaps = []
+    for seed in range(40):
+        Om = np.random.default_rng(5000 + seed).standard_normal((p.n, ell))
+        if method == 'nystrom':
+            V, lam, _ = sketch.nystrom(lambda X: Hs @ X, Om)
+        else:
+            V, lam = sketch.randsvd(lambda X: A @ X, lambda W: A.T @ W, Om)
+        kaps.append(analysis.precond_kappa(Hs, sketch.hhat_apply(V, lam, np.eye(p.n))))
+    bound = 1 + analysis.psi_bound(lamH, r, ell - r)
+    assert np.mean(kaps) <= bound, (np.mean(kaps), bound)
+
+
+def test_intrinsic_dimension_closed_forms():
+    """Sec. 4.2: for lambda_j = j^-alpha the tail ratio is (r+1)^alpha zeta(alpha, r+1)
+    (Hurwitz zeta), which equals the paper's zeta(alpha) bound at r = 0 and exceeds it
+    for r > 0 (the printed bound holds only for the untruncated spectrum); for
+    lambda_j = exp(-alpha j) it is exactly 1/(1 - exp(-alpha)) for an infinite tail."""
+    j = np.arange(1, 200001, dtype=np.float64)
+    for alpha in (2.0, 3.0, 4.0):
+        lam = j ** (-alpha)
+        assert analysis.intrinsic_dimension(lam, 0) <= zeta(alpha) + 1e-12
+        for r in (0, 3, 10):
+            ref = (r + 1) ** alpha * zeta(alpha, r + 1)
+            assert analysis.intrinsic_dimension(lam, r) == pytest.approx(ref, rel=1e-3)
+    for alpha in (0.1, 0.5, 2.0):
+        lam = np.exp(-alpha * np.arange(1, 4000))
+        idr = analysis.intrinsic_dimension(lam, 5)
+        assert idr <= 1 / (1 - np.exp(-alpha)) + 1e-12
+        assert idr == pytest.approx(1 / (1 - np.exp(-alpha)), rel=1e-9)
+
+
+def test_sample_size_rule():
+    """Sec. 4.2 'Number of samples': l = ceil(6 r_eps/5 + 1) gives Psi <= (1 + 5 id) eps."""
+    lam = 10.0 * 0.7 ** np.arange(200)
+    for eps in (1e-1, 1e-2, 1e-3):
+        r_eps = int(np.sum(lam > eps))
+        ell = int(np.ceil(6 * r_eps / 5 + 1))
+        p = ell - r_eps
+        if p < 2:
+            continue
+        psi = analysis.psi_bound(lam, r_eps, p)
+        assert psi <= (1 + 5 * analysis.intrinsic_dimension(lam, r_eps)) * eps
