@@ -1,0 +1,249 @@
+/*
+ * rp4d.h -- C ABI of the MI355X (gfx950) randomized-preconditioned SC-4DVAR hot path.
+ *
+ * The operations follow Subrahmanya, Rao, Saibaba, "Randomized Preconditioned
+ * Solvers for Strong Constraint 4D-Var Data Assimilation" (arXiv:2401.15758):
+ *   model / TLM / ADJ            Sec. 2.1 eq. (model), Sec. 2.2, discrete RK adjoints
+ *   A, H = A^T A, I + H          Sec. 2.2 eq. (Rhalf)
+ *   gradient                     Sec. 2.2 eq. (4dvar_gradient)
+ *   GN system                    eqs. (gniter), (gniterf1), (pcgsystem)
+ *   Nystrom / RandSVD sketches   Sec. 3.1.1 Alg. 2 / Alg. 1
+ *   limited-memory precond.      eq. (woodbury)
+ *   reuse test kappa_re          Sec. 3.2 eq. (condtext2)
+ *
+ * Conventions (all entry points)
+ *   - Every vector / block argument is a DEVICE pointer owned by the caller
+ *     (e.g. a torch tensor's data_ptr()).  Host pointers are marked "host".
+ *   - Blocks of k vectors in state space are row-major (n, k): grid point major,
+ *     vector minor (the k vectors are interleaved per grid point).  For the 2-D
+ *     model the grid is flattened j*nx + i (x fastest).
+ *   - Observation-space blocks are row-major (n_t, n_obs, k), m = n_obs * n_t.
+ *   - `dtype` selects the arithmetic of a block call: RP4D_F64 (double buffers)
+ *     or RP4D_F32 (float buffers).  The trajectory is always stored in FP64.
+ *   - Work is enqueued on the context's HIP stream and ordered on it.  Calls that
+ *     return host scalars (J, info structs, kappa) synchronise that stream.
+ *   - Handles are opaque, created and freed only by the library (*_create /
+ *     *_destroy).  A problem must outlive the trajectories, preconditioners and
+ *     GN states made from it; a context must outlive its problems.
+ *   - Return value: RP4D_OK (0) or a negative error code; the message of the
+ *     last failure on the calling thread is returned by rp4d_last_error().
+ *     No C++ exception crosses this boundary.  On error, output buffers are
+ *     left in an unspecified state unless stated otherwise.
+ *   - Calls on one context must not overlap from several threads.
+ */
+#ifndef RP4D_H
+#define RP4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RP4D_OK          0
+#define RP4D_EINVAL     -1   /* bad argument or shape */
+#define RP4D_ENOMEM     -2   /* device allocation failed / HBM budget exceeded */
+#define RP4D_EUNSTABLE  -3   /* time step outside the RK4 stability interval */
+#define RP4D_ENOTSPD    -4   /* Nystrom core matrix not SPD after shift retries */
+#define RP4D_ENOCONV    -5   /* PCG reached maxit before rtol (last iterate kept) */
+#define RP4D_ENONFINITE -6   /* NaN/Inf detected in a state or result */
+#define RP4D_EHIP       -7   /* HIP runtime error */
+#define RP4D_ESTATE     -8   /* call out of order (e.g. data not set) */
+
+typedef struct rp4d_ctx rp4d_ctx;
+typedef struct rp4d_problem rp4d_problem;
+typedef struct rp4d_traj rp4d_traj;
+typedef struct rp4d_precond rp4d_precond;
+typedef struct rp4d_gn_state rp4d_gn_state;
+
+enum { RP4D_F64 = 0, RP4D_F32 = 1 };
+enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2 };
+enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
+
+/* Problem description (Sec. 2.1): model, window, observation layout, prior.
+ *   Burgers:  nx grid points on [0,1) (ny ignored), viscosity nu.
+ *   BVE:      nx*ny periodic grid on [0,1)^2, viscosity nu.
+ *   dt, nsteps: RK4 step and number of steps N of the window.
+ *   obs_stride, obs_every: observe every obs_stride-th grid point (2-D: cell in
+ *     both directions) at steps s_i = i*obs_every, i = 1..floor(N/obs_every).
+ *   sigma_o: R_i = sigma_o^2 I.  sigma_b, L_b: Gaussian prior std and length
+ *     (Burgers: L_b in domain units; BVE: L_b in cells).
+ *   ckpt_every: 0 or 1 store every state of the trajectory; C > 1 store every
+ *     C-th state and recompute segments during the sweeps (bitwise identical). */
+typedef struct {
+    int model;
+    int nx, ny;
+    double nu;
+    double dt;
+    int nsteps;
+    int obs_stride, obs_every;
+    double sigma_o, sigma_b, L_b;
+    int ckpt_every;
+} rp4d_problem_desc;
+
+typedef struct {
+    int iters;            /* PCG iterations = (I+H) products spent */
+    int converged;        /* 1 if ||r|| <= rtol ||b|| */
+    double relres;        /* recurrence residual ||r_k|| / ||b|| at exit */
+    double true_relres;   /* ||b - (I+H) x|| / ||b|| (one extra product; -1 if not computed) */
+} rp4d_pcg_info;
+
+/* Counters as in Sec. 5 / Tables 2 and 4: offline TLM/ADJ are spent building
+ * sketches; online FWD/TLM/ADJ in cost/gradient evaluations and in PCG. */
+typedef struct {
+    long long fwd;
+    long long tlm_online, adj_online;
+    long long tlm_offline, adj_offline;
+    long long sketches, reuses;
+    long long hv_columns;   /* Hessian-vector columns applied (any purpose) */
+} rp4d_counters;
+
+/* Options of one Gauss-Newton step (Sec. 2.2, Sec. 3.2). */
+typedef struct {
+    int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD or RP4D_NOPREC (Prec_Gamma) */
+    int ell;                /* sketch size l */
+    uint64_t seed;          /* Philox seed for Omega when omega == NULL */
+    const double* omega;    /* device (n, ell) test matrix or NULL */
+    int sketch_dtype;       /* RP4D_F64 or RP4D_F32 sweeps for the sketch */
+    double rtol;            /* PCG relative residual tolerance */
+    int maxit;              /* PCG iteration cap (<= 0: n) */
+    double reuse_eps;       /* eps_re of eq. (condtext2); <= 0: always re-sketch */
+    const double* vhat;     /* device unit vector for kappa_re, or NULL (Philox) */
+} rp4d_gn_opts;
+
+typedef struct {
+    double J;               /* cost at the start of the step (v-form) */
+    double gnorm_inf;       /* ||g_v||_inf at the start of the step */
+    int pcg_iters;
+    int pcg_converged;
+    double pcg_relres;
+    int sketched;           /* 1 if a new sketch was built in this step */
+    int reused;             /* 1 if the resident preconditioner was kept */
+    double kappa_re;        /* value of the reuse test, or -1 if not run */
+} rp4d_gn_info;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* rp4d_last_error(void);
+/* Library version string. */
+const char* rp4d_version(void);
+
+/* Context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The stream must outlive the context. */
+int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out);
+int rp4d_ctx_destroy(rp4d_ctx* ctx);
+/* Change the stream subsequent calls are enqueued on. */
+int rp4d_ctx_set_stream(rp4d_ctx* ctx, void* hip_stream);
+
+/* Create a problem.  Fails with RP4D_EUNSTABLE when 4 nu dt / dx^2 > 2.785 or
+ * the advective CFL number exceeds 2.8 for |u| <= 10 (RK4 stability).  The
+ * background x_b and observations y must be set with rp4d_problem_set_data
+ * before any call that needs them (fwd innovations, gradient, gn_step). */
+int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_problem** out);
+int rp4d_problem_destroy(rp4d_problem* p);
+/* Host outputs: n (state size), n_obs, n_t. */
+int rp4d_problem_dims(const rp4d_problem* p, int* n, int* n_obs, int* n_t);
+/* Copy x_b (n) and y (n_t, n_obs) from device buffers into the problem. */
+int rp4d_problem_set_data(rp4d_problem* p, const double* xb, const double* y);
+
+/* Trajectory storage for one problem (every state, or checkpoints). */
+int rp4d_traj_create(rp4d_problem* p, rp4d_traj** out);
+int rp4d_traj_destroy(rp4d_traj* t);
+
+/* FWD (eq. (model)): run the nonlinear RK4 model from x0 (n) over the window,
+ * storing the trajectory in `traj`.  If data are set, also records the
+ * innovations d_i = R^{-1/2}(O x_{s_i} - y_i) and, if J_obs != NULL (host),
+ * returns 1/2 sum_i |d_i|^2 (synchronises).  Counts one online FWD. */
+int rp4d_fwd(rp4d_problem* p, const double* x0, rp4d_traj* traj, double* J_obs);
+
+/* y_out (n_t, n_obs) = O x_{s_i}: observations of the stored trajectory. */
+int rp4d_observe(rp4d_problem* p, const rp4d_traj* traj, double* y_out);
+
+/* U (n,k) = Gamma^{1/2} V (n,k): the symmetric square root of the Gaussian prior
+ * (circulant Gaussian square-root kernel; 2-D separable). */
+int rp4d_bhalf(rp4d_problem* p, int k, const void* V, void* U, int dtype);
+
+/* Z (n_t,n_obs,k) = A V = [R^{-1/2} O M_i Gamma^{1/2} V]_i (eq. (Rhalf)):
+ * k tangent-linear sweeps around the stored trajectory. */
+int rp4d_tlm(rp4d_problem* p, const rp4d_traj* traj, int k, const void* V, void* Z, int dtype);
+
+/* U (n,k) = A^T W = Gamma^{1/2} sum_i M_i^T O^T R^{-1/2} W_i: k adjoint sweeps
+ * (discrete RK4 adjoint) with observation forcing, W shaped (n_t,n_obs,k). */
+int rp4d_adj(rp4d_problem* p, const rp4d_traj* traj, int k, const void* W, void* U, int dtype);
+
+/* HV (n,k) = (add_identity ? V : 0) + A^T A V: block GN Hessian product
+ * (eq. (Rhalf), (pcgsystem)); one TLM and one ADJ sweep per column.  V and HV
+ * must not alias. */
+int rp4d_hessian_block(rp4d_problem* p, const rp4d_traj* traj, int k, const void* V, void* HV,
+                       int dtype, int add_identity);
+
+/* g (n) = v + A^T d: gradient of the v-form cost (eq. (4dvar_gradient) times
+ * Gamma^{1/2}) using the innovations recorded by the last rp4d_fwd on `traj`.
+ * Counts one online ADJ. */
+int rp4d_gradient(rp4d_problem* p, const rp4d_traj* traj, const double* v, double* g);
+
+/* Build the low-rank preconditioner {V_hat, Lambda_hat} by Nystrom (Alg. 2) or
+ * RandSVD (Alg. 1) with `ell` test vectors; omega is a device (n, ell) Gaussian
+ * matrix or NULL (drawn on device with Philox4x32-10 + Box-Muller from `seed`).
+ * sketch_dtype selects FP64 or FP32 sweeps; post-processing is FP64.
+ * Counts ell offline TLM and ell offline ADJ.  RP4D_ENOTSPD if the shifted
+ * Nystrom core matrix stays indefinite after 3 tenfold shift increases. */
+int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* traj, int method, int ell, uint64_t seed,
+                       const double* omega, int sketch_dtype, rp4d_precond** out);
+int rp4d_precond_destroy(rp4d_precond* pc);
+/* Host outputs (each nullable): ell, lambda_hat (ell, descending), Nystrom shift nu. */
+int rp4d_precond_info(const rp4d_precond* pc, int* ell, double* lambda_host, double* nu_host);
+/* Copy V_hat (n, ell) row-major into a device buffer. */
+int rp4d_precond_basis(const rp4d_precond* pc, double* V_out);
+/* Z (n,k) = (I + V_hat Lambda_hat V_hat^T)^{-1} R = R - V_hat diag(lam/(1+lam)) V_hat^T R
+ * (eq. (woodbury)). */
+int rp4d_precond_apply(const rp4d_precond* pc, int k, const double* R, double* Z);
+
+/* PCG on (I + H) x = b (eq. (pcgsystem)) preconditioned by `pc` (NULL: identity,
+ * the paper's Prec_Gamma), x0 = 0, stop when ||r_k|| <= rtol ||b||.  FP64.
+ * Returns RP4D_ENOCONV (with x = last iterate and info filled) at maxit. */
+int rp4d_pcg_solve(rp4d_problem* p, const rp4d_traj* traj, const rp4d_precond* pc,
+                   const double* b, double* x, double rtol, int maxit, rp4d_pcg_info* info);
+
+/* kappa_re = ||(I + H) (I + H_hat)^{-1} v||_2 for the unit vector v (eq. (condtext2));
+ * host output. */
+int rp4d_kappa_re(rp4d_problem* p, const rp4d_traj* traj, const rp4d_precond* pc,
+                  const double* v, double* kappa);
+
+/* Gauss-Newton iterate state: control vector v (starts at 0), state x = x_b +
+ * Gamma^{1/2} v, its trajectory and a resident preconditioner. */
+int rp4d_gn_state_create(rp4d_problem* p, rp4d_gn_state** out);
+int rp4d_gn_state_destroy(rp4d_gn_state* s);
+/* Copy v and/or x (each nullable, device, n) out of the state. */
+int rp4d_gn_state_get(const rp4d_gn_state* s, double* v, double* x);
+/* Copy the last GN direction dv (device, n). */
+int rp4d_gn_state_last_step(const rp4d_gn_state* s, double* dv);
+
+/* One GN step (Sec. 2.2 / 3.2): FWD at x, gradient, optional kappa_re reuse test
+ * of the resident preconditioner, sketch, PCG, v <- v + dv, x <- x_b + Gamma^{1/2} v.
+ * Returns RP4D_ENOCONV if PCG hit maxit (the step is still applied). */
+int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* opts, rp4d_gn_info* info);
+
+/* Cost counters of a problem (host output) and their reset. */
+int rp4d_counters_get(const rp4d_problem* p, rp4d_counters* out);
+int rp4d_counters_reset(rp4d_problem* p);
+
+/* Fill `count` doubles with standard normals from Philox4x32-10 (Salmon et al.
+ * 2011) + Box-Muller: element i uses counter (i/4 pairs) under key `seed`. */
+int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out);
+
+/* Sweep tiling of a problem's block sweeps (used by the autotuner): points per
+ * thread `ppt`, vectors per workgroup `kc`, threads per workgroup `threads`,
+ * tile length `tile` (grid points owned per workgroup) and steps per launch
+ * `steps`.  Any argument <= 0 restores the built-in heuristic for that field.
+ * `dtype`/`k` select the entry (k = 0: every k). */
+int rp4d_set_sweep_tiling(rp4d_problem* p, int dtype, int k, int ppt, int kc, int threads,
+                          int tile, int steps);
+/* Host output: the tiling the next sweep with (dtype, k) would use. */
+int rp4d_get_sweep_tiling(const rp4d_problem* p, int dtype, int k, int* ppt, int* kc, int* threads,
+                          int* tile, int* steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RP4D_H */

@@ -1,0 +1,471 @@
+// Burgers RK4 sweeps for gfx950: nonlinear forward (FWD), block tangent-linear
+// (TLM) and block discrete adjoint (ADJ), Sec. 2.1 eq. (model) and the discrete
+// Runge-Kutta TLM/ADJ used in Sec. 5.1.
+//
+// Decomposition.  A launch advances S steps.  Workgroup (tile, group) owns the
+// grid points [tile*T, tile*T + T) of the vectors in `group` (KC vectors,
+// interleaved per grid point) and computes an extended region of
+// T + 2*halo points (periodic wrap), halo >= 4 S + 4: every RK4 step consumes a
+// stencil radius of one point per stage, so after S steps the owned points are
+// exact (overlapped temporal blocking).  Between launches the block state lives
+// in HBM in the blocked layout [group][point][KC]; inside a launch it lives in
+// registers: thread t holds P consecutive points of the region for the KC vectors
+// and exchanges only its two edge points through LDS, once per RK stage
+// (double-buffered, one workgroup barrier per stage).  The base trajectory u_s
+// is read once per step per point (shared by the KC vectors) and the nonlinear
+// stage states Y_1..Y_4 are recomputed from it on the fly.
+#include "internal.hpp"
+
+// Every multiply-add of the sweeps is written as an explicit fma() and automatic
+// contraction is off, so the rounding of each grid point's update is fixed by
+// the source alone: results are bitwise independent of the tiling (points per
+// thread, vectors per group, tile length, steps per launch) and of checkpointing.
+#pragma clang fp contract(off)
+
+namespace rp4d {
+namespace {
+
+// Nonlinear RHS at a point: -Y (Y+ - Y-)/(2dx) + nu (Y+ - 2Y + Y-)/dx^2.
+template <typename T>
+__device__ __forceinline__ T rhs_pt(T Y, T ym, T yp, T i2, T nd) {
+    const T Dy = (yp - ym) * i2;
+    const T lap = fma(T(-2), Y, yp + ym);
+    return fma(nd, lap, -(Y * Dy));
+}
+
+__device__ __forceinline__ int wrap_index(long v, int n) {
+    long r = v % n;
+    return static_cast<int>(r < 0 ? r + n : r);
+}
+
+// RK4 stage offsets for Y2, Y3, Y4 and weights.
+__device__ __forceinline__ double rk_c(int st) { return st < 2 ? 0.5 : 1.0; }
+__device__ __forceinline__ double rk_b(int st) { return (st == 0 || st == 3) ? (1.0 / 6.0) : (1.0 / 3.0); }
+
+template <int P>
+__global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
+    extern __shared__ double sh_fwd[];
+    const int NT = blockDim.x, t = threadIdx.x;
+    const int n = a.n;
+    const int tstart = blockIdx.x * a.tile;
+    const int tlen = min(a.tile, n - tstart);
+    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
+    const double h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
+
+    int g[P];
+    bool own[P];
+    double u[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int r = t * P + p;
+        g[p] = wrap_index(static_cast<long>(tstart) - a.halo + r, n);
+        own[p] = (r >= a.halo) && (r < a.halo + tlen);
+        u[p] = a.xin[g[p]];
+    }
+    int buf = 0;
+    for (int s = a.s0; s < a.s0 + a.S; ++s) {
+        double Y[P], acc[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            Y[p] = u[p];
+            acc[p] = 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            double* B = sh_fwd + buf * 2 * NT;
+            B[t] = Y[0];
+            B[NT + t] = Y[P - 1];
+            __syncthreads();
+            const double Yl = B[NT + tl], Yr = B[tr];
+            double Yn[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double ym = p > 0 ? Y[p - 1] : Yl;
+                const double yp = p < P - 1 ? Y[p + 1] : Yr;
+                const double K = rhs_pt<double>(Y[p], ym, yp, i2, nd);
+                acc[p] = fma(rk_b(st), K, acc[p]);
+                if (st < 3) Yn[p] = fma(rk_c(st) * h, K, u[p]);
+            }
+            if (st < 3) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) Y[p] = Yn[p];
+            }
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) u[p] = fma(h, acc[p], u[p]);
+        const int s1 = s + 1;
+        if (a.store != nullptr && (s1 % a.store_every) == 0) {
+            const int row = s1 / a.store_every - a.store_row0;
+            if (row >= 0 && row < a.store_rows) {
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    if (own[p]) a.store[static_cast<size_t>(row) * n + g[p]] = u[p];
+            }
+        }
+        if ((s1 % a.obs_every) == 0) {
+            const int i = s1 / a.obs_every;
+            if (i >= 1 && i <= a.n_t) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (own[p] && (g[p] % a.obs_stride) == 0) {
+                        const size_t idx = static_cast<size_t>(i - 1) * a.n_obs + g[p] / a.obs_stride;
+                        if (a.obs_out) a.obs_out[idx] = u[p];
+                        if (a.innov) a.innov[idx] = (u[p] - a.y[idx]) * a.inv_sigma_o;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (own[p]) a.xout[g[p]] = u[p];
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char sh_raw[];
+    T* sh = reinterpret_cast<T*>(sh_raw);
+    constexpr int W = 1 + KC;
+    const int NT = blockDim.x, t = threadIdx.x, grp = blockIdx.y;
+    const int n = a.n;
+    const int tstart = blockIdx.x * a.tile;
+    const int tlen = min(a.tile, n - tstart);
+    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
+    const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
+
+    int g[P];
+    bool own[P];
+    T d[P][KC];
+    const T* xin = a.xin + static_cast<size_t>(grp) * n * KC;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int r = t * P + p;
+        g[p] = wrap_index(static_cast<long>(tstart) - a.halo + r, n);
+        own[p] = (r >= a.halo) && (r < a.halo + tlen);
+#pragma unroll
+        for (int c = 0; c < KC; ++c) d[p][c] = xin[static_cast<size_t>(g[p]) * KC + c];
+    }
+    T unext[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) unext[p] = static_cast<T>(a.base[static_cast<size_t>(a.s0 - a.base_row0) * n + g[p]]);
+
+    int buf = 0;
+    for (int s = a.s0; s < a.s0 + a.S; ++s) {
+        T u[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) u[p] = unext[p];
+        if (s + 1 < a.s0 + a.S) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                unext[p] = static_cast<T>(a.base[static_cast<size_t>(s + 1 - a.base_row0) * n + g[p]]);
+        }
+        T Y[P], dY[P][KC], acc[P][KC];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            Y[p] = u[p];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                dY[p][c] = d[p][c];
+                acc[p][c] = T(0);
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
+            B[t * W] = Y[0];
+            B[(NT + t) * W] = Y[P - 1];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                B[t * W + 1 + c] = dY[0][c];
+                B[(NT + t) * W + 1 + c] = dY[P - 1][c];
+            }
+            __syncthreads();
+            const T Yl = B[(NT + tl) * W], Yr = B[tr * W];
+            T dl[KC], dr[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                dl[c] = B[(NT + tl) * W + 1 + c];
+                dr[c] = B[tr * W + 1 + c];
+            }
+            const T cb = static_cast<T>(rk_b(st));
+            const T ch = static_cast<T>(rk_c(st)) * h;
+            T Yn[P], dYn[P][KC];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const T ym = p > 0 ? Y[p - 1] : Yl;
+                const T yp = p < P - 1 ? Y[p + 1] : Yr;
+                const T Dy = (yp - ym) * i2;
+                const T Yh = Y[p] * i2;
+                if (st < 3) {
+                    const T K = rhs_pt<T>(Y[p], ym, yp, i2, nd);
+                    Yn[p] = fma(ch, K, u[p]);
+                }
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    const T dm = p > 0 ? dY[p - 1][c] : dl[c];
+                    const T dp = p < P - 1 ? dY[p + 1][c] : dr[c];
+                    // J(Y) dY = -dY Dy - Y (d+ - d-)/(2dx) + nu (d+ - 2 dY + d-)/dx^2
+                    const T lap = fma(T(-2), dY[p][c], dp + dm);
+                    const T adv = fma(-dY[p][c], Dy, -(Yh * (dp - dm)));
+                    const T dK = fma(nd, lap, adv);
+                    acc[p][c] = fma(cb, dK, acc[p][c]);
+                    if (st < 3) dYn[p][c] = fma(ch, dK, d[p][c]);
+                }
+            }
+            if (st < 3) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    Y[p] = Yn[p];
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) dY[p][c] = dYn[p][c];
+                }
+            }
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int c = 0; c < KC; ++c) d[p][c] = fma(h, acc[p][c], d[p][c]);
+        const int s1 = s + 1;
+        if ((s1 % a.obs_every) == 0) {
+            const int i = s1 / a.obs_every;
+            if (i >= 1 && i <= a.n_t) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (own[p] && (g[p] % a.obs_stride) == 0) {
+                        const size_t row = static_cast<size_t>(i - 1) * a.n_obs + g[p] / a.obs_stride;
+#pragma unroll
+                        for (int c = 0; c < KC; ++c) {
+                            const int col = grp * KC + c;
+                            if (col < a.k) a.z[row * a.k + col] = d[p][c] * a.inv_sigma_o;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    T* xout = a.xout + static_cast<size_t>(grp) * n * KC;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (own[p]) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) xout[static_cast<size_t>(g[p]) * KC + c] = d[p][c];
+        }
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(1024) burgers_adj_kernel(SweepArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char sh_raw[];
+    T* sh = reinterpret_cast<T*>(sh_raw);
+    constexpr int W = 1 + KC;
+    const int NT = blockDim.x, t = threadIdx.x, grp = blockIdx.y;
+    const int n = a.n;
+    const int tstart = blockIdx.x * a.tile;
+    const int tlen = min(a.tile, n - tstart);
+    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
+    const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
+
+    int g[P];
+    bool own[P];
+    T lam[P][KC];
+    const T* xin = a.xin + static_cast<size_t>(grp) * n * KC;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int r = t * P + p;
+        g[p] = wrap_index(static_cast<long>(tstart) - a.halo + r, n);
+        own[p] = (r >= a.halo) && (r < a.halo + tlen);
+#pragma unroll
+        for (int c = 0; c < KC; ++c) lam[p][c] = xin[static_cast<size_t>(g[p]) * KC + c];
+    }
+    const int s_hi = a.s0 + a.S - 1;
+    T unext[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) unext[p] = static_cast<T>(a.base[static_cast<size_t>(s_hi - a.base_row0) * n + g[p]]);
+
+    int buf = 0;
+    for (int s = s_hi; s >= a.s0; --s) {
+        // observation forcing at state index s+1, before transposing step s -> s+1
+        const int s1 = s + 1;
+        if ((s1 % a.obs_every) == 0) {
+            const int i = s1 / a.obs_every;
+            if (i >= 1 && i <= a.n_t) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if ((g[p] % a.obs_stride) == 0) {
+                        const size_t row = static_cast<size_t>(i - 1) * a.n_obs + g[p] / a.obs_stride;
+#pragma unroll
+                        for (int c = 0; c < KC; ++c) {
+                            const int col = grp * KC + c;
+                            if (col < a.k) lam[p][c] = fma(a.w[row * a.k + col], a.inv_sigma_o, lam[p][c]);
+                        }
+                    }
+                }
+            }
+        }
+        T u[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) u[p] = unext[p];
+        if (s - 1 >= a.s0) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                unext[p] = static_cast<T>(a.base[static_cast<size_t>(s - 1 - a.base_row0) * n + g[p]]);
+        }
+        // nonlinear stage states Y1..Y4 of step s (recomputed) and their edge neighbours
+        T Ys[4][P], YL[4], YR[4];
+#pragma unroll
+        for (int p = 0; p < P; ++p) Ys[0][p] = u[p];
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
+            B[t * W] = Ys[st][0];
+            B[(NT + t) * W] = Ys[st][P - 1];
+            __syncthreads();
+            YL[st] = B[(NT + tl) * W];
+            YR[st] = B[tr * W];
+            const T ch = static_cast<T>(rk_c(st)) * h;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const T ym = p > 0 ? Ys[st][p - 1] : YL[st];
+                const T yp = p < P - 1 ? Ys[st][p + 1] : YR[st];
+                const T K = rhs_pt<T>(Ys[st][p], ym, yp, i2, nd);
+                Ys[st + 1][p] = fma(ch, K, u[p]);
+            }
+            buf ^= 1;
+        }
+        // reverse stages: mu_i = adjoint of dK_i, theta_i = J(Y_i)^T mu_i
+        T mu[P][KC], lu[P][KC];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                mu[p][c] = (h / T(6)) * lam[p][c];
+                lu[p][c] = lam[p][c];
+            }
+#pragma unroll
+        for (int st = 3; st >= 0; --st) {
+            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
+            if (st == 3) {
+                B[t * W] = Ys[3][0];
+                B[(NT + t) * W] = Ys[3][P - 1];
+            }
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                B[t * W + 1 + c] = mu[0][c];
+                B[(NT + t) * W + 1 + c] = mu[P - 1][c];
+            }
+            __syncthreads();
+            if (st == 3) {
+                YL[3] = B[(NT + tl) * W];
+                YR[3] = B[tr * W];
+            }
+            T ml[KC], mr[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                ml[c] = B[(NT + tl) * W + 1 + c];
+                mr[c] = B[tr * W + 1 + c];
+            }
+            // coefficients of the next mu: mu_{st} = a_lam * lam + a_th * theta
+            const T a_lam = st == 1 ? h / T(6) : h / T(3);
+            const T a_th = st == 3 ? h : h * T(0.5);
+            T mun[P][KC];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const T ym = p > 0 ? Ys[st][p - 1] : YL[st];
+                const T yp = p < P - 1 ? Ys[st][p + 1] : YR[st];
+                const T Dy = (yp - ym) * i2;
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    const T mm = p > 0 ? mu[p - 1][c] : ml[c];
+                    const T mp = p < P - 1 ? mu[p + 1][c] : mr[c];
+                    // J(Y)^T mu = -Dy mu + (Y+ mu+ - Y- mu-)/(2dx) + nu (mu+ - 2 mu + mu-)/dx^2
+                    const T flux = fma(yp, mp, -(ym * mm));
+                    const T adv = fma(-Dy, mu[p][c], flux * i2);
+                    const T lap = fma(T(-2), mu[p][c], mp + mm);
+                    const T th = fma(nd, lap, adv);
+                    lu[p][c] += th;
+                    if (st > 0) mun[p][c] = fma(a_th, th, a_lam * lam[p][c]);
+                }
+            }
+            if (st > 0) {
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) mu[p][c] = mun[p][c];
+            }
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int c = 0; c < KC; ++c) lam[p][c] = lu[p][c];
+    }
+    T* xout = a.xout + static_cast<size_t>(grp) * n * KC;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (own[p]) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) xout[static_cast<size_t>(g[p]) * KC + c] = lam[p][c];
+        }
+}
+
+void check_tiling(const Tiling& t, int n, int halo, int S) {
+    RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0, RP4D_EINVAL,
+                 "sweep tiling: threads must be a multiple of 64 in [64, 1024]");
+    RP4D_REQUIRE(t.tile >= 1 && t.tile <= n, RP4D_EINVAL, "sweep tiling: tile out of range");
+    RP4D_REQUIRE(halo >= 4 * S + 4, RP4D_EINVAL, "sweep tiling: halo too small for steps per launch");
+    RP4D_REQUIRE(static_cast<long>(t.threads) * t.ppt >= static_cast<long>(t.tile) + 2L * halo, RP4D_EINVAL,
+                 "sweep tiling: region (threads * ppt) smaller than tile + 2 * halo");
+}
+
+}  // namespace
+
+void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st) {
+    check_tiling(t, a.n, a.halo, a.S);
+    dim3 grid((a.n + t.tile - 1) / t.tile), block(t.threads);
+    const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * sizeof(double);
+    switch (t.ppt) {
+        case 1: burgers_fwd_kernel<1><<<grid, block, shmem, st>>>(a); break;
+        case 2: burgers_fwd_kernel<2><<<grid, block, shmem, st>>>(a); break;
+        case 4: burgers_fwd_kernel<4><<<grid, block, shmem, st>>>(a); break;
+        case 8: burgers_fwd_kernel<8><<<grid, block, shmem, st>>>(a); break;
+        default: fail(RP4D_EINVAL, "sweep tiling: unsupported points per thread for fwd");
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename T, int P, int KC>
+static void launch_one(int mode, const SweepArgs<T>& a, dim3 grid, dim3 block, size_t shmem, hipStream_t st) {
+    if (mode == MODE_TLM)
+        burgers_tlm_kernel<T, P, KC><<<grid, block, shmem, st>>>(a);
+    else
+        burgers_adj_kernel<T, P, KC><<<grid, block, shmem, st>>>(a);
+}
+
+template <typename T>
+void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st) {
+    check_tiling(t, a.n, a.halo, a.S);
+    RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "sweep: bad mode");
+    dim3 grid((a.n + t.tile - 1) / t.tile, ngroups), block(t.threads);
+    const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
+    RP4D_REQUIRE(shmem <= 64 * 1024, RP4D_EINVAL, "sweep tiling: LDS exchange buffer too large");
+    const int key = t.ppt * 100 + t.kc;
+    switch (key) {
+        case 101: launch_one<T, 1, 1>(mode, a, grid, block, shmem, st); break;
+        case 102: launch_one<T, 1, 2>(mode, a, grid, block, shmem, st); break;
+        case 104: launch_one<T, 1, 4>(mode, a, grid, block, shmem, st); break;
+        case 201: launch_one<T, 2, 1>(mode, a, grid, block, shmem, st); break;
+        case 202: launch_one<T, 2, 2>(mode, a, grid, block, shmem, st); break;
+        case 204: launch_one<T, 2, 4>(mode, a, grid, block, shmem, st); break;
+        case 401: launch_one<T, 4, 1>(mode, a, grid, block, shmem, st); break;
+        case 402: launch_one<T, 4, 2>(mode, a, grid, block, shmem, st); break;
+        case 404: launch_one<T, 4, 4>(mode, a, grid, block, shmem, st); break;
+        default: fail(RP4D_EINVAL, "sweep tiling: unsupported (points per thread, vectors per group)");
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template void launch_burgers_sweep<double>(int, const SweepArgs<double>&, const Tiling&, int, hipStream_t);
+template void launch_burgers_sweep<float>(int, const SweepArgs<float>&, const Tiling&, int, hipStream_t);
+
+}  // namespace rp4d

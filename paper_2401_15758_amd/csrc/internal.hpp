@@ -1,0 +1,193 @@
+// Internal declarations of the rp4d HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "rp4d.h"
+
+namespace rp4d {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define RP4D_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::rp4d::fail(RP4D_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RP4D_REQUIRE(cond, code, msg)          \
+    do {                                       \
+        if (!(cond)) ::rp4d::fail((code), (msg)); \
+    } while (0)
+
+// Growable device buffer owned by a library handle.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t b);
+    void release();
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// Block sweeps of the Burgers model
+// ---------------------------------------------------------------------------
+enum SweepMode { MODE_TLM = 1, MODE_ADJ = 2 };
+
+struct Tiling {
+    int ppt = 0, kc = 0, threads = 0, tile = 0, steps = 0;
+};
+
+template <typename T>
+struct SweepArgs {
+    const double* base;   // u_s stored at base[(s - base_row0) * n + g]
+    int base_row0;
+    int n;
+    T h, inv2dx, nu_dx2;
+    int s0, S;            // TLM: steps s0 .. s0+S-1 forward; ADJ: s0+S-1 .. s0 backward
+    int tile, halo;
+    int k;                // number of vectors
+    const T* xin;         // blocked state [grp][n][KC]
+    T* xout;
+    int obs_stride, obs_every, n_obs, n_t;
+    T inv_sigma_o;
+    T* z;                 // TLM observation output (n_t, n_obs, k)
+    const T* w;           // ADJ observation forcing (n_t, n_obs, k)
+};
+
+struct FwdArgs {
+    const double* xin;    // state at s0 (n)
+    double* xout;         // state at s0+S (n)
+    double* store;        // trajectory rows: u_s at store[(s/store_every - store_row0) * n + g]
+    int store_every, store_row0, store_rows;
+    int n;
+    double h, inv2dx, nu_dx2;
+    int s0, S, tile, halo;
+    int obs_stride, obs_every, n_obs, n_t;
+    double inv_sigma_o;
+    const double* y;      // observations (n_t, n_obs) or null
+    double* innov;        // innovations out (n_t, n_obs) or null
+    double* obs_out;      // O x_{s_i} out (n_t, n_obs) or null
+};
+
+void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st);
+template <typename T>
+void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Prior square root, layouts and tall-skinny dense kernels
+// ---------------------------------------------------------------------------
+// Blocked layout of k vectors of length n in groups of kc: element (j, c) at
+// ((c / kc) * n + j) * kc + c % kc.  The row-major (n, k) layout is kc = k.
+template <typename T>
+void launch_circ_conv(const T* in, int in_kc, T* out, int out_kc, const double* gk, int D, int n, int k,
+                      const T* addv, hipStream_t st);
+template <typename TI, typename TO>
+void launch_relayout(const TI* in, int in_kc, TO* out, int out_kc, int n, int k, hipStream_t st);
+template <typename T>
+void launch_fill(T* p, size_t count, T v, hipStream_t st);
+
+// C (a x b, row-major, FP64) = X^T Y; X (n x a, ld lx), Y (n x b, ld ly).
+// Deterministic two-stage reduction; `work` must hold gram_work_doubles(n,a,b).
+template <typename TX, typename TY>
+void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
+                 hipStream_t st);
+size_t gram_work_doubles(int n, int a, int b);
+// Out (n x b) = beta * Cin + alpha * X (n x a) * diag(dscale) * M (a x b); M row-major a x b (FP64).
+// Cin may equal Out (in-place) ; dscale may be null.
+template <typename TX, typename TO>
+void launch_tsmm(const TX* X, int lx, const double* M, const double* dscale, int n, int a, int b, double alpha,
+                 const TO* Cin, int lc, double beta, TO* Out, int lo, hipStream_t st);
+// y = alpha * x + beta * y over count elements (FP64)
+void launch_axpby(const double* x, double alpha, double* y, double beta, size_t count, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Small dense FP64 linear algebra on one workgroup (l <= 128)
+// ---------------------------------------------------------------------------
+// In-place lower Cholesky of sym((A + A^T)/2) (lda = l); info[0] = 0 ok, j+1 if pivot j <= 0.
+void launch_chol(double* A, int l, int* info, hipStream_t st);
+// Linv = inverse of lower-triangular L (both l x l row-major).
+void launch_trinv(const double* L, double* Linv, int l, hipStream_t st);
+// C = op(A) op(B) (l x l row-major each); ta/tb: transpose flags; alpha scaling.
+void launch_small_gemm(const double* A, int ta, const double* B, int tb, double* C, int l, double alpha,
+                       hipStream_t st);
+// Symmetric eigendecomposition (cyclic Jacobi): A (l x l, destroyed) -> evals (desc), evecs (columns, row-major).
+void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Reductions, PCG helpers and RNG
+// ---------------------------------------------------------------------------
+// out[0] = sum x*y (deterministic); work >= dot_work_doubles(count)
+void launch_dot(const double* x, const double* y, size_t count, double* out, double* work, hipStream_t st);
+size_t dot_work_doubles(size_t count);
+void launch_philox_normal(uint64_t seed, size_t count, double* out, hipStream_t st);
+template <typename T>
+void launch_philox_normal_t(uint64_t seed, size_t count, T* out, hipStream_t st);
+
+}  // namespace rp4d
+
+// ---------------------------------------------------------------------------
+// Opaque handle definitions
+// ---------------------------------------------------------------------------
+struct rp4d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct rp4d_problem {
+    rp4d_ctx* ctx = nullptr;
+    rp4d_problem_desc d{};
+    int n = 0, n_obs = 0, n_t = 0, m = 0, s_last = 0;
+    double dx = 0, inv2dx = 0, nu_dx2 = 0;
+    rp4d::DevBuf xb, y;
+    bool has_data = false;
+    rp4d::DevBuf gk;  // prior square-root kernel g_0..g_D
+    int D = 0;
+    // workspaces
+    rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg;
+    rp4d_counters cnt{};
+    std::map<std::tuple<int, int>, rp4d::Tiling> tiling;
+};
+
+struct rp4d_traj {
+    rp4d_problem* p = nullptr;
+    rp4d::DevBuf states;  // rows of u_s (every C-th when checkpointing)
+    rp4d::DevBuf innov;   // (n_t, n_obs)
+    int C = 1;
+    int rows = 0;
+    bool valid = false, has_innov = false;
+};
+
+struct rp4d_precond {
+    rp4d_problem* p = nullptr;
+    int ell = 0;
+    rp4d::DevBuf V;       // (n, ell) row-major
+    rp4d::DevBuf Dg;      // lam / (1 + lam)
+    std::vector<double> lam;
+    double nu = 0.0;
+};
+
+struct rp4d_gn_state {
+    rp4d_problem* p = nullptr;
+    rp4d::DevBuf v, x, dv, g, b;
+    rp4d_traj* traj = nullptr;
+    rp4d_precond* pc = nullptr;
+};

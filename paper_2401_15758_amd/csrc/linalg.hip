@@ -1,0 +1,634 @@
+// Dense and reduction kernels of the rp4d library (gfx950, FP64 unless noted):
+//   * circulant prior square root Gamma^{1/2} (banded periodic convolution)
+//   * layout conversion between row-major (n, k) and the blocked sweep layout
+//   * tall-skinny Gram X^T Y and tall-skinny X * M products (deterministic)
+//   * dot products with a fixed reduction tree
+//   * Philox4x32-10 + Box-Muller Gaussian generator
+//   * one-workgroup l x l Cholesky, triangular inverse, small GEMM and a cyclic
+//     Jacobi symmetric eigensolver (l <= 128)
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace rp4d {
+namespace {
+
+__device__ __forceinline__ size_t blk_off(int j, int c, int kc, int n) {
+    return (static_cast<size_t>(c / kc) * n + j) * kc + (c % kc);
+}
+
+__device__ __forceinline__ int wrapi(long v, int n) {
+    long r = v % n;
+    return static_cast<int>(r < 0 ? r + n : r);
+}
+
+// ---------------------------------------------------------------------------
+// Gamma^{1/2}: out(j, c) = sum_{d=-Dm..Dp} g(|d|) in((j - d) mod n, c) [+ addv(j, c)]
+// One workgroup per (segment of 4*blockDim outputs, vector); the input segment
+// with its halo is staged in LDS; each thread slides a 4-point window.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) circ_conv_kernel(const T* in, int in_kc, T* out, int out_kc,
+                                                        const double* gk, int Dm, int Dp, int n, int k,
+                                                        const T* addv) {
+    extern __shared__ double seg[];
+    const int c = blockIdx.y;
+    const int TJ = 4 * blockDim.x;
+    const int j0 = blockIdx.x * TJ;
+    // seg[e + 1] = in(j0 - Dp + e); seg[0] is a pad read by the last window shift
+    const int len = TJ + Dm + Dp;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        const int j = wrapi(static_cast<long>(j0) - Dp + e, n);
+        seg[e + 1] = static_cast<double>(in[blk_off(j, c, in_kc, n)]);
+    }
+    if (threadIdx.x == 0) seg[0] = 0.0;
+    __syncthreads();
+    const int t = threadIdx.x;
+    // output q = j0 + 4t + i needs in(q - d): seg index 4t + i - d + Dp + 1
+    const int base = 4 * t + Dp + 1;
+    double w0 = seg[base + Dm], w1 = seg[base + Dm + 1], w2 = seg[base + Dm + 2], w3 = seg[base + Dm + 3];
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int d = -Dm; d <= Dp; ++d) {
+        const double gd = gk[d < 0 ? -d : d];
+        a0 = fma(gd, w0, a0);
+        a1 = fma(gd, w1, a1);
+        a2 = fma(gd, w2, a2);
+        a3 = fma(gd, w3, a3);
+        w3 = w2;
+        w2 = w1;
+        w1 = w0;
+        w0 = seg[base - d - 1];
+    }
+    const double acc[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = j0 + 4 * t + i;
+        if (q < n) {
+            const size_t o = blk_off(q, c, out_kc, n);
+            double v = acc[i];
+            if (addv) v += static_cast<double>(addv[o]);
+            out[o] = static_cast<T>(v);
+        }
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void relayout_kernel(const TI* in, int in_kc, TO* out, int out_kc, int n, int k) {
+    const size_t total = static_cast<size_t>(n) * k;
+    for (size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; idx < total;
+         idx += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int j = static_cast<int>(idx / k), c = static_cast<int>(idx % k);
+        out[blk_off(j, c, out_kc, n)] = static_cast<TO>(in[blk_off(j, c, in_kc, n)]);
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, size_t count, T v) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void axpby_kernel(const double* x, double alpha, double* y, double beta, size_t count) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        y[i] = alpha * x[i] + beta * y[i];
+}
+
+// ---------------------------------------------------------------------------
+// Tall-skinny Gram: partial[chunk][a][b] over row chunks, 64x64 output tiles,
+// 4x4 register blocking; fixed-order reduction over chunks afterwards.
+// ---------------------------------------------------------------------------
+constexpr int GR = 16;  // rows staged per LDS pass
+
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) gram_partial_kernel(const TX* X, int lx, const TY* Y, int ly, int n, int a,
+                                                           int b, int rows_per_chunk, double* part) {
+    __shared__ double xs[GR][64];
+    __shared__ double ys[GR][64];
+    const int chunk = blockIdx.x;
+    const int tiles_b = (b + 63) / 64;
+    const int ta = blockIdx.y / tiles_b, tb = blockIdx.y % tiles_b;
+    const int i0 = ta * 64, j0 = tb * 64;
+    const int r0 = chunk * rows_per_chunk;
+    const int r1 = min(n, r0 + rows_per_chunk);
+    const int tid = threadIdx.x;
+    const int ti = tid / 16, tj = tid % 16;
+    double acc[4][4] = {};
+    for (int rr = r0; rr < r1; rr += GR) {
+        for (int e = tid; e < GR * 64; e += 256) {
+            const int r = e / 64, col = e % 64;
+            const int row = rr + r;
+            xs[r][col] = (row < r1 && i0 + col < a) ? static_cast<double>(X[static_cast<size_t>(row) * lx + i0 + col]) : 0.0;
+            ys[r][col] = (row < r1 && j0 + col < b) ? static_cast<double>(Y[static_cast<size_t>(row) * ly + j0 + col]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < GR; ++r) {
+            double xv[4], yv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xv[q] = xs[r][ti * 4 + q];
+                yv[q] = ys[r][tj * 4 + q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(xv[p], yv[q], acc[p][q]);
+        }
+        __syncthreads();
+    }
+    double* P = part + static_cast<size_t>(chunk) * a * b;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + ti * 4 + p, j = j0 + tj * 4 + q;
+            if (i < a && j < b) P[static_cast<size_t>(i) * b + j] = acc[p][q];
+        }
+}
+
+__global__ void reduce_chunks_kernel(const double* part, int nchunks, size_t stride, double* out) {
+    const size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+    if (idx >= stride) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[static_cast<size_t>(c) * stride + idx];
+    out[idx] = s;
+}
+
+int gram_chunks(int n) {
+    int rows = (n + 127) / 128;
+    rows = ((rows + GR - 1) / GR) * GR;
+    if (rows < 64) rows = 64;
+    return (n + rows - 1) / rows;
+}
+
+// ---------------------------------------------------------------------------
+// Out (n x b) = beta * C + alpha * X diag(ds) M ; 64-row x 64-col output tiles.
+// ---------------------------------------------------------------------------
+template <typename TX, typename TO>
+__global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const double* M, const double* ds, int n,
+                                                   int a, int b, double alpha, const TO* C, int lc, double beta,
+                                                   TO* Out, int lo) {
+    __shared__ double xs[64][17];
+    __shared__ double ms[16][64];
+    const int r0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+    double acc[4][4] = {};
+    for (int kk = 0; kk < a; kk += 16) {
+        for (int e = tid; e < 64 * 16; e += 256) {
+            const int r = e / 16, q = e % 16;
+            const int row = r0 + r, col = kk + q;
+            xs[r][q] = (row < n && col < a) ? static_cast<double>(X[static_cast<size_t>(row) * lx + col]) : 0.0;
+        }
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int q = e / 64, j = e % 64;
+            const int i = kk + q, col = j0 + j;
+            double v = (i < a && col < b) ? M[static_cast<size_t>(i) * b + col] : 0.0;
+            if (ds && i < a) v *= ds[i];
+            ms[q][j] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+            double xv[4], mv[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                xv[p] = xs[ti * 4 + p][q];
+                mv[p] = ms[q][tj * 4 + p];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[p][s] = fma(xv[p], mv[s], acc[p][s]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int row = r0 + ti * 4 + p, col = j0 + tj * 4 + s;
+            if (row < n && col < b) {
+                double v = alpha * acc[p][s];
+                if (beta != 0.0) v += beta * static_cast<double>(C[static_cast<size_t>(row) * lc + col]);
+                Out[static_cast<size_t>(row) * lo + col] = static_cast<TO>(v);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Dot product with a fixed reduction tree.
+// ---------------------------------------------------------------------------
+constexpr int DOT_THREADS = 256;
+
+__global__ void __launch_bounds__(DOT_THREADS) dot_partial_kernel(const double* x, const double* y, size_t count,
+                                                                  double* part) {
+    __shared__ double red[DOT_THREADS];
+    double s = 0.0;
+    for (size_t i = blockIdx.x * static_cast<size_t>(DOT_THREADS) + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * DOT_THREADS)
+        s = fma(x[i], y[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = DOT_THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(DOT_THREADS) dot_final_kernel(const double* part, int nb, double* out) {
+    __shared__ double red[DOT_THREADS];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += DOT_THREADS) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = DOT_THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+int dot_blocks(size_t count) {
+    size_t b = (count + 4 * DOT_THREADS - 1) / (4 * DOT_THREADS);
+    if (b < 1) b = 1;
+    if (b > 256) b = 256;
+    return static_cast<int>(b);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) + Box-Muller.
+// Counter (i, 0, 0, 0) under key (seed lo, seed hi) gives normals 2i and 2i+1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                             uint32_t k1) {
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+}
+
+template <typename T>
+__global__ void philox_normal_kernel(uint64_t seed, size_t count, T* out) {
+    const size_t npairs = (count + 1) / 2;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < npairs;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        uint32_t c0 = static_cast<uint32_t>(i), c1 = static_cast<uint32_t>(i >> 32), c2 = 0, c3 = 0;
+        uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            philox_round(c0, c1, c2, c3, k0, k1);
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        // two uniforms in (0, 1] with 53 random bits each
+        const uint64_t a = (static_cast<uint64_t>(c0) << 21) ^ (c1 >> 11);
+        const uint64_t b = (static_cast<uint64_t>(c2) << 21) ^ (c3 >> 11);
+        const double u1 = (static_cast<double>(a & ((1ull << 53) - 1)) + 1.0) * (1.0 / 9007199254740992.0);
+        const double u2 = static_cast<double>(b & ((1ull << 53) - 1)) * (1.0 / 9007199254740992.0);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double ang = 6.283185307179586476925286766559 * u2;
+        out[2 * i] = static_cast<T>(rad * cos(ang));
+        if (2 * i + 1 < count) out[2 * i + 1] = static_cast<T>(rad * sin(ang));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup l x l kernels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) chol_kernel(double* A, int l, int* info) {
+    extern __shared__ double sA[];
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < l * l; e += nt) {
+        const int i = e / l, j = e % l;
+        sA[e] = 0.5 * (A[i * l + j] + A[j * l + i]);
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < l; ++j) {
+        if (tid == 0) {
+            const double dj = sA[j * l + j];
+            if (!(dj > 0.0) || !isfinite(dj))
+                bad = j + 1;
+            else
+                sA[j * l + j] = sqrt(dj);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double djj = sA[j * l + j];
+        for (int i = j + 1 + tid; i < l; i += nt) sA[i * l + j] /= djj;
+        __syncthreads();
+        const int rem = l - j - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= i) sA[i * l + c] -= sA[i * l + j] * sA[c * l + j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < l * l; e += nt) {
+        const int i = e / l, j = e % l;
+        A[e] = (j <= i) ? sA[e] : 0.0;
+    }
+    if (tid == 0) info[0] = bad;
+}
+
+__global__ void __launch_bounds__(256) trinv_kernel(const double* L, double* X, int l) {
+    extern __shared__ double sL[];
+    for (int e = threadIdx.x; e < l * l; e += blockDim.x) sL[e] = L[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < l; c += blockDim.x) {
+        for (int i = 0; i < l; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int q = c; q < i; ++q) s -= sL[i * l + q] * X[q * l + c];
+            X[i * l + c] = (i < c) ? 0.0 : s / sL[i * l + i];
+        }
+    }
+}
+
+__global__ void small_gemm_kernel(const double* A, int ta, const double* B, int tb, double* C, int l, double alpha) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= l * l) return;
+    const int i = idx / l, j = idx % l;
+    double s = 0.0;
+    for (int q = 0; q < l; ++q) {
+        const double av = ta ? A[q * l + i] : A[i * l + q];
+        const double bv = tb ? B[j * l + q] : B[q * l + j];
+        s = fma(av, bv, s);
+    }
+    C[idx] = alpha * s;
+}
+
+// Cyclic Jacobi (round-robin parallel ordering, Golub & Van Loan Alg. 8.5.3 /
+// sym.schur2).  A lives in LDS; V in LDS when it fits, otherwise in `evecs`.
+template <bool VLDS>
+__global__ void __launch_bounds__(1024) jacobi_kernel(double* A, double* evals, double* evecs, double* vwork, int l) {
+    extern __shared__ double sm[];
+    double* sA = sm;
+    double* V = VLDS ? (sm + l * l) : vwork;
+    __shared__ double cs[64], sn[64];
+    __shared__ int pp[64], qq[64];
+    __shared__ int rotated;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int m = l + (l & 1);
+    const int half = m / 2;
+    for (int e = tid; e < l * l; e += nt) {
+        const int i = e / l, j = e % l;
+        sA[e] = 0.5 * (A[i * l + j] + A[j * l + i]);
+    }
+    __syncthreads();  // V may alias A's global storage: stage A fully first
+    for (int e = tid; e < l * l; e += nt) V[e] = ((e / l) == (e % l)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < m - 1; ++round) {
+            if (tid < half) {
+                // circle method: position 0 fixed, the others rotate
+                auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
+                int p = player(tid), q = player(m - 1 - tid);
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < l) {
+                    const double apq = sA[p * l + q];
+                    const double app = sA[p * l + p], aqq = sA[q * l + q];
+                    if (fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                     : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                        rotated = 1;
+                    }
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+                pp[tid] = p;
+                qq[tid] = q < l ? q : -1;
+            }
+            __syncthreads();
+            // rows p, q <- J^T A
+            for (int e = tid; e < half * l; e += nt) {
+                const int i = e / l, col = e % l;
+                const int q = qq[i];
+                if (q < 0 || sn[i] == 0.0) continue;
+                const int p = pp[i];
+                const double c = cs[i], s = sn[i];
+                const double ap = sA[p * l + col], aq = sA[q * l + col];
+                sA[p * l + col] = c * ap - s * aq;
+                sA[q * l + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q <- A J and V J
+            for (int e = tid; e < half * l; e += nt) {
+                const int i = e / l, row = e % l;
+                const int q = qq[i];
+                if (q < 0 || sn[i] == 0.0) continue;
+                const int p = pp[i];
+                const double c = cs[i], s = sn[i];
+                const double ap = sA[row * l + p], aq = sA[row * l + q];
+                sA[row * l + p] = c * ap - s * aq;
+                sA[row * l + q] = s * ap + c * aq;
+                const double vp = V[row * l + p], vq = V[row * l + q];
+                V[row * l + p] = c * vp - s * vq;
+                V[row * l + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+    // sort descending (ties by index) and write out
+    for (int i = tid; i < l; i += nt) {
+        const double li = sA[i * l + i];
+        int rank = 0;
+        for (int j = 0; j < l; ++j) {
+            const double lj = sA[j * l + j];
+            if (lj > li || (lj == li && j < i)) ++rank;
+        }
+        evals[rank] = li;
+        for (int row = 0; row < l; ++row) evecs[row * l + rank] = V[row * l + i];
+    }
+}
+
+inline dim3 grid_for(size_t count, int threads = 256) {
+    size_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return dim3(static_cast<unsigned>(b));
+}
+
+}  // namespace
+
+template <typename T>
+void launch_circ_conv(const T* in, int in_kc, T* out, int out_kc, const double* gk, int D, int n, int k,
+                      const T* addv, hipStream_t st) {
+    int Dm = D, Dp = D;
+    if (2 * D + 1 > n) {  // kernel support covers the circle: each residue once
+        Dm = (n - 1) / 2;
+        Dp = n / 2;
+    }
+    int threads = 256;
+    while (threads > 64 && 4 * (threads / 2) >= n) threads /= 2;
+    const int TJ = 4 * threads;
+    const size_t shmem = static_cast<size_t>(TJ + Dm + Dp + 1) * sizeof(double);
+    RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "bhalf: prior kernel band too wide for LDS staging");
+    if (shmem > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&circ_conv_kernel<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    dim3 grid((n + TJ - 1) / TJ, k);
+    circ_conv_kernel<T><<<grid, threads, shmem, st>>>(in, in_kc, out, out_kc, gk, Dm, Dp, n, k, addv);
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename TI, typename TO>
+void launch_relayout(const TI* in, int in_kc, TO* out, int out_kc, int n, int k, hipStream_t st) {
+    relayout_kernel<TI, TO><<<grid_for(static_cast<size_t>(n) * k), 256, 0, st>>>(in, in_kc, out, out_kc, n, k);
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_fill(T* p, size_t count, T v, hipStream_t st) {
+    if (count == 0) return;
+    fill_kernel<T><<<grid_for(count), 256, 0, st>>>(p, count, v);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_axpby(const double* x, double alpha, double* y, double beta, size_t count, hipStream_t st) {
+    if (count == 0) return;
+    axpby_kernel<<<grid_for(count), 256, 0, st>>>(x, alpha, y, beta, count);
+    RP4D_HIP(hipGetLastError());
+}
+
+size_t gram_work_doubles(int n, int a, int b) {
+    return static_cast<size_t>(gram_chunks(n)) * a * b;
+}
+
+template <typename TX, typename TY>
+void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
+                 hipStream_t st) {
+    const int nch = gram_chunks(n);
+    const int rows = (n + nch - 1) / nch;
+    const int rows_r = ((rows + GR - 1) / GR) * GR;
+    const int nchunks = (n + rows_r - 1) / rows_r;
+    dim3 grid(nchunks, ((a + 63) / 64) * ((b + 63) / 64));
+    gram_partial_kernel<TX, TY><<<grid, 256, 0, st>>>(X, lx, Y, ly, n, a, b, rows_r, work);
+    RP4D_HIP(hipGetLastError());
+    const size_t stride = static_cast<size_t>(a) * b;
+    reduce_chunks_kernel<<<grid_for(stride), 256, 0, st>>>(work, nchunks, stride, C);
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename TX, typename TO>
+void launch_tsmm(const TX* X, int lx, const double* M, const double* dscale, int n, int a, int b, double alpha,
+                 const TO* Cin, int lc, double beta, TO* Out, int lo, hipStream_t st) {
+    dim3 grid((n + 63) / 64, (b + 63) / 64);
+    tsmm_kernel<TX, TO><<<grid, 256, 0, st>>>(X, lx, M, dscale, n, a, b, alpha, Cin, lc, beta, Out, lo);
+    RP4D_HIP(hipGetLastError());
+}
+
+size_t dot_work_doubles(size_t count) { return static_cast<size_t>(dot_blocks(count)); }
+
+void launch_dot(const double* x, const double* y, size_t count, double* out, double* work, hipStream_t st) {
+    const int nb = dot_blocks(count);
+    dot_partial_kernel<<<nb, DOT_THREADS, 0, st>>>(x, y, count, work);
+    RP4D_HIP(hipGetLastError());
+    dot_final_kernel<<<1, DOT_THREADS, 0, st>>>(work, nb, out);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_philox_normal(uint64_t seed, size_t count, double* out, hipStream_t st) {
+    launch_philox_normal_t<double>(seed, count, out, st);
+}
+
+template <typename T>
+void launch_philox_normal_t(uint64_t seed, size_t count, T* out, hipStream_t st) {
+    if (count == 0) return;
+    philox_normal_kernel<T><<<grid_for((count + 1) / 2), 256, 0, st>>>(seed, count, out);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_chol(double* A, int l, int* info, hipStream_t st) {
+    RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "cholesky: l must be in [1, 128]");
+    const size_t shmem = static_cast<size_t>(l) * l * sizeof(double);
+    if (shmem > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(shmem));
+    chol_kernel<<<1, 1024, shmem, st>>>(A, l, info);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_trinv(const double* L, double* Linv, int l, hipStream_t st) {
+    RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "trinv: l must be in [1, 128]");
+    const size_t shmem = static_cast<size_t>(l) * l * sizeof(double);
+    if (shmem > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&trinv_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(shmem));
+    trinv_kernel<<<1, 256, shmem, st>>>(L, Linv, l);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_small_gemm(const double* A, int ta, const double* B, int tb, double* C, int l, double alpha,
+                       hipStream_t st) {
+    small_gemm_kernel<<<grid_for(static_cast<size_t>(l) * l), 256, 0, st>>>(A, ta, B, tb, C, l, alpha);
+    RP4D_HIP(hipGetLastError());
+}
+
+void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st) {
+    RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "eigensolver: l must be in [1, 128]");
+    const size_t both = 2 * static_cast<size_t>(l) * l * sizeof(double);
+    const size_t one = static_cast<size_t>(l) * l * sizeof(double);
+    if (both <= 150 * 1024) {
+        if (both > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(both));
+        jacobi_kernel<true><<<1, 1024, both, st>>>(A, evals, evecs, nullptr, l);
+    } else {
+        // V in global memory: use A's storage after it has been staged in LDS
+        if (one > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<false>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(one));
+        jacobi_kernel<false><<<1, 1024, one, st>>>(A, evals, evecs, A, l);
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template void launch_circ_conv<double>(const double*, int, double*, int, const double*, int, int, int,
+                                       const double*, hipStream_t);
+template void launch_circ_conv<float>(const float*, int, float*, int, const double*, int, int, int, const float*,
+                                      hipStream_t);
+template void launch_relayout<double, double>(const double*, int, double*, int, int, int, hipStream_t);
+template void launch_relayout<double, float>(const double*, int, float*, int, int, int, hipStream_t);
+template void launch_relayout<float, double>(const float*, int, double*, int, int, int, hipStream_t);
+template void launch_relayout<float, float>(const float*, int, float*, int, int, int, hipStream_t);
+template void launch_fill<double>(double*, size_t, double, hipStream_t);
+template void launch_fill<float>(float*, size_t, float, hipStream_t);
+template void launch_gram<double, double>(const double*, int, const double*, int, int, int, int, double*, double*,
+                                          hipStream_t);
+template void launch_gram<float, float>(const float*, int, const float*, int, int, int, int, double*, double*,
+                                        hipStream_t);
+template void launch_gram<double, float>(const double*, int, const float*, int, int, int, int, double*, double*,
+                                         hipStream_t);
+template void launch_gram<float, double>(const float*, int, const double*, int, int, int, int, double*, double*,
+                                         hipStream_t);
+template void launch_tsmm<double, double>(const double*, int, const double*, const double*, int, int, int, double,
+                                          const double*, int, double, double*, int, hipStream_t);
+template void launch_tsmm<float, double>(const float*, int, const double*, const double*, int, int, int, double,
+                                         const double*, int, double, double*, int, hipStream_t);
+template void launch_tsmm<double, float>(const double*, int, const double*, const double*, int, int, int, double,
+                                         const float*, int, double, float*, int, hipStream_t);
+template void launch_philox_normal_t<double>(uint64_t, size_t, double*, hipStream_t);
+template void launch_philox_normal_t<float>(uint64_t, size_t, float*, hipStream_t);
+
+}  // namespace rp4d

@@ -1,0 +1,193 @@
+"""GPU parity of the sketches (Nystrom Alg. 2, RandSVD Alg. 1), the limited-memory
+preconditioner, PCG, the reuse test and the Gauss-Newton step with the FP64 oracle.
+
+Sketch factors are unique only up to sign/rotation, so operators are compared:
+Lambda_hat (sorted), H_hat and P applied to probes.  The FP64 GN step is
+compared at PCG rtol 1e-12 (two correct CG runs at rtol 1e-6 may differ by
+~kappa 1e-6, which is not a parity statement)."""
+import numpy as np
+import pytest
+
+from gpu_util import Pair, colwise_relerr, need_gpu, relerr, to_dev, to_np
+from oracle import gn as ogn
+from oracle import sketch as osk
+from oracle.pcg import pcg as opcg
+from paper_2401_15758_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_GN = 1e-10   # FP64 GN step, relative
+
+
+@pytest.fixture(scope="module")
+def small():
+    need_gpu()
+    return Pair(inputs.CFG_SMALL)
+
+
+def _probe(n, k=4, seed=7):
+    return np.random.default_rng(seed).standard_normal((n, k))
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+@pytest.mark.parametrize("ell", [20, 7])
+def test_sketch_parity(small, method, ell):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    Om = inputs.omega(pr.orc.n, ell, seed=1000 + ell)
+    V, lam = ogn.build_precond(pr.orc, pr.otraj, method, Om)
+    code = rp4d.NYSTROM if method == "nystrom" else rp4d.RANDSVD
+    pc = pr.gpu.build_precond(pr.traj, code, ell, omega=to_dev(Om))
+    glam, gnu = pc.info()
+    glam = np.array(glam)
+    assert np.max(np.abs(glam - lam)) <= 1e-10 * lam[0]
+    if method == "nystrom":
+        Y0 = pr.orc.misfit_hessian(pr.otraj, Om)
+        nu = np.sqrt(pr.orc.n) * 2.0 ** -52 * np.linalg.norm(Y0, 2)
+        assert gnu == pytest.approx(nu, rel=1e-12)
+    R = _probe(pr.orc.n)
+    PR = to_np(pc.apply(to_dev(R)))
+    assert colwise_relerr(PR, osk.lmp_apply(V, lam, R)) <= 1e-10
+    Vg = to_np(pc.basis())
+    Hh = osk.hhat_apply(Vg, glam, R)
+    assert colwise_relerr(Hh, osk.hhat_apply(V, lam, R)) <= 1e-9
+
+
+def test_precond_inverts_one_plus_hhat(small):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 20, omega=to_dev(inputs.omega(pr.orc.n, 20)))
+    Vg = to_np(pc.basis())
+    lam = np.array(pc.info()[0])
+    R = _probe(pr.orc.n)
+    M = R + osk.hhat_apply(Vg, lam, R)            # (I + H_hat) R
+    back = to_np(pc.apply(to_dev(M)))
+    assert colwise_relerr(back, R) <= 1e-10
+
+
+def test_philox_sketch_statistics(small):
+    """Device-drawn Omega: moments of Philox4x32-10 + Box-Muller normals."""
+    torch = need_gpu()
+    pr = small
+    out = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+    pr.ctx.philox_normal(1234, out.numel(), out)
+    x = to_np(out)
+    assert abs(x.mean()) < 5e-3 and abs(x.var() - 1) < 5e-3
+    assert abs(np.mean(x ** 4) - 3) < 3e-2
+    from scipy import stats
+    assert stats.kstest(x[:200000], 'norm').pvalue > 1e-4
+    y = to_np(pr.ctx.philox_normal(1234, out.numel(), torch.empty_like(out)))
+    assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", [None, "nystrom"])
+def test_pcg_parity(small, prec):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    b = np.random.default_rng(3).standard_normal(pr.orc.n)
+    P = None
+    pc = None
+    if prec:
+        Om = inputs.omega(pr.orc.n, 20)
+        P = ogn.build_precond(pr.orc, pr.otraj, prec, Om)
+        pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 20, omega=to_dev(Om))
+    xr, ir = opcg(lambda v: pr.orc.hessian(pr.otraj, v), b,
+                  prec=(lambda r: osk.lmp_apply(P[0], P[1], r)) if P else None, rtol=1e-12)
+    x, info = pr.gpu.pcg_solve(pr.traj, to_dev(b), precond=pc, rtol=1e-12)
+    x = to_np(x)
+    assert info['converged'] and abs(info['iters'] - ir['iters']) <= 1
+    assert relerr(x, xr) <= TOL_GN
+    assert info['true_relres'] <= 1e-10
+
+
+def test_pcg_noconv_keeps_iterate(small):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    b = to_dev(np.ones(pr.orc.n))
+    x, info = pr.gpu.pcg_solve(pr.traj, b, rtol=1e-14, maxit=2, raise_noconv=False)
+    assert info['iters'] == 2 and not info['converged']
+    with pytest.raises(rp4d.Rp4dError) as e:
+        pr.gpu.pcg_solve(pr.traj, b, rtol=1e-14, maxit=1)
+    assert e.value.code == rp4d.ENOCONV
+
+
+def test_kappa_re_parity(small):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    Om = inputs.omega(pr.orc.n, 10)
+    V, lam = ogn.build_precond(pr.orc, pr.otraj, "nystrom", Om)
+    pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 10, omega=to_dev(Om))
+    vh = inputs.unit_vector(pr.orc.n)
+    k = pr.gpu.kappa_re(pr.traj, pc, to_dev(vh))
+    assert k == pytest.approx(ogn.kappa_re(pr.orc, pr.otraj, V, lam, vh), rel=1e-10)
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd", "none"])
+def test_gn_step_parity(method):
+    """One FP64 GN step on burgers-128: dv and x+ within 1e-10 of the oracle."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    ell = 20
+    Om = inputs.omega(pr.orc.n, ell, seed=1000)
+    v0 = np.zeros(pr.orc.n)
+    v1, dv, x1, info = ogn.gn_step(pr.orc, v0, method=method, Omega=Om, rtol=1e-12)
+    st = pr.gpu.gn_state()
+    code = dict(nystrom=rp4d.NYSTROM, randsvd=rp4d.RANDSVD, none=rp4d.NOPREC)[method]
+    gi = pr.gpu.gn_step(st, sketch=code, ell=ell, omega=to_dev(Om), rtol=1e-12)
+    gdv = to_np(st.last_step())
+    gv, gx = st.get()
+    assert gi['J'] == pytest.approx(info['J'], rel=1e-12)
+    assert gi['gnorm_inf'] == pytest.approx(info['gnorm_inf'], rel=1e-11)
+    assert abs(gi['pcg_iters'] - info['pcg']['iters']) <= 1
+    assert relerr(gdv, dv) <= TOL_GN
+    assert relerr(to_np(gx), x1) <= TOL_GN
+    c = pr.gpu.counters()
+    assert c['fwd'] == 2            # data check at construction + the step
+    assert c['tlm_online'] == gi['pcg_iters'] and c['adj_online'] == gi['pcg_iters'] + 1
+    if method != "none":
+        assert c['tlm_offline'] == c['adj_offline'] == ell and c['sketches'] == 1
+
+
+def test_three_gn_steps_with_reuse_test():
+    """Three GN steps with the kappa_re reuse test: J decreases, the reuse
+    decision matches the oracle's, and iterates stay within 1e-10."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    ell, eps_re = 20, 10.0
+    v = np.zeros(pr.orc.n)
+    st = pr.gpu.gn_state()
+    P = None
+    vh = inputs.unit_vector(pr.orc.n, seed=77)
+    for k in range(3):
+        Om = inputs.omega(pr.orc.n, ell, seed=2000 + k)
+        v, dv, x, info = ogn.gn_step(pr.orc, v, method='nystrom', Omega=Om, rtol=1e-12, precond=P,
+                                     reuse_eps=eps_re, vhat=vh)
+        P = info['precond']
+        gi = pr.gpu.gn_step(st, sketch=rp4d.NYSTROM, ell=ell, omega=to_dev(Om), rtol=1e-12, reuse_eps=eps_re,
+                            vhat=to_dev(vh))
+        assert gi['reused'] == int(info['reused'])
+        if info['kappa_re'] is not None:
+            assert gi['kappa_re'] == pytest.approx(info['kappa_re'], rel=1e-8)
+        gv, gx = st.get()
+        assert relerr(to_np(gv), v) <= TOL_GN
+        assert relerr(to_np(gx), x) <= TOL_GN
+
+
+def test_fp32_sketch_then_fp64_pcg(small):
+    """Mixed precision: FP32 sketch sweeps, FP64 post-processing and PCG; the solve
+    still meets its FP64 tolerance and the preconditioner stays effective."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    b = np.random.default_rng(9).standard_normal(pr.orc.n)
+    Om = to_dev(inputs.omega(pr.orc.n, 20))
+    p64 = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 20, omega=Om)
+    p32 = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 20, omega=Om, sketch_dtype=rp4d.F32)
+    l64, l32 = np.array(p64.info()[0]), np.array(p32.info()[0])
+    # FP32 sweeps perturb H Omega by ~1e-4 relative; the sketch eigenvalues move by ~1e-3 of the largest
+    assert np.max(np.abs(l64 - l32)) <= 5e-3 * l64[0]
+    x64, i64 = pr.gpu.pcg_solve(pr.traj, to_dev(b), precond=p64, rtol=1e-10)
+    x32, i32 = pr.gpu.pcg_solve(pr.traj, to_dev(b), precond=p32, rtol=1e-10)
+    assert i32['converged'] and i32['iters'] <= i64['iters'] + 2
+    assert relerr(to_np(x32), to_np(x64)) <= 1e-8
