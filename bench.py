@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the randomized-preconditioned SC-4DVAR hot path on one MI355X.
+
+Workload (N=1): burgers-4096 -- periodic Burgers, n = 4096, 500 RK4 steps,
+observations every 16th point every 25 steps (m = 5120), Gaussian prior,
+FP64 throughout.  One timed step is the whole hot path for one assimilation:
+3 Gauss-Newton iterations from the background, each = FWD + gradient (ADJ) +
+a 64-column Nystrom sketch of the data-misfit Hessian (64 TLM + 64 ADJ sweeps)
++ PCG to relative residual 1e-6 with the limited-memory preconditioner + update.
+Inputs are synthesised on the device before timing (x_b = x_true + Gamma^{1/2} xi,
+y = O M(x_true) + sigma_o eta from seeded draws).
+
+value = Hessian-vector products per second over the timed steps (sketch columns
+plus PCG products, counted by the library), ms_per_step = one assimilation
+(3 GN iterations).  The roofline object describes the dominant sweep kernel,
+timed with HIP events on the library's stream inside the timed region; the
+cpu_baseline object times the FP64 numpy oracle on one GN iteration.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X FP64 vector peak
+PEAK_FP32_VALU_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sketch", default="nystrom", choices=["nystrom", "randsvd"])
+    ap.add_argument("--sketch-dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--gn-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning-cache", default=None, help="JSON tiling cache (default: the package's tuning.json)")
+    ap.add_argument("--tune-budget", type=float, default=20.0, help="seconds per tuned shape when not cached")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, ell, rtol):
+    """The oracle as it stands, one GN iteration of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gn as ogn
+    from oracle.problem import burgers_problem
+    from paper_2401_15758_amd import inputs
+    cores = len(os.sched_getaffinity(0))
+    with threadpool_limits(limits=cores):
+        orc = burgers_problem(cfg, inputs.draws(cfg, seed=0))
+        Om = inputs.omega(cfg["n"], ell, seed=1000)
+        t0 = time.perf_counter()
+        _, _, _, info = ogn.gn_step(orc, np.zeros(cfg["n"]), method="nystrom", Omega=Om, rtol=rtol)
+        dt = time.perf_counter() - t0
+    hv = ell + info["pcg"]["iters"]
+    return {"value": hv / dt, "unit": "Hv/s", "cores": cores, "kind": "oracle",
+            "sample": f"one GN iteration of burgers-4096 ({ell}-column Nystrom sketch + "
+                      f"{info['pcg']['iters']} PCG products to rtol {rtol:g}), FP64 numpy, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build measures one GPU only (requested --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the sharded multi-GPU path is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2401_15758_amd import autotune, inputs, rp4d
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = dict(inputs.CFG_LARGE)
+    ell, rtol = cfg["ell"], 1e-6
+    sk = rp4d.NYSTROM if args.sketch == "nystrom" else rp4d.RANDSVD
+    skd = rp4d.F64 if args.sketch_dtype == "f64" else rp4d.F32
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+    ctx = rp4d.Context(0)
+    prob = rp4d.Problem(ctx, cfg)
+    d = inputs.draws(cfg, seed=0)
+    xb, y = prob.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
+    prob.set_data(xb, y.reshape(-1))
+    state = prob.gn_state()
+
+    # sweep tilings for the sketch block (k = ell) and the single-vector products
+    # of the gradient and PCG: tuned on the device unless cached
+    cache_path = args.tuning_cache or autotune.CACHE_PATH
+    traj0 = prob.traj()
+    prob.fwd(xb, traj0, want_J=False)
+    tilings = {}
+    for k, dt in ((ell, skd), (1, rp4d.F64)):
+        tilings[f"k{k}-{'f64' if dt == rp4d.F64 else 'f32'}"] = autotune.tune_or_load(
+            prob, traj0, cfg["nsteps"], k, dt, budget_s=args.tune_budget, cache_path=cache_path)
+    del traj0
+
+    def step():
+        state.reset()
+        infos = []
+        for it in range(args.gn_iters):
+            infos.append(prob.gn_step(state, sketch=sk, ell=ell, seed=1000 + it, sketch_dtype=skd, rtol=rtol))
+        return infos
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.reset_counters()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.extend(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    cnt = prob.counters()
+    kst = {name: ctx.kernel_stats(kind) for name, kind in
+           (("tlm", rp4d.K_TLM), ("adj", rp4d.K_ADJ), ("fwd", rp4d.K_FWD), ("bhalf", rp4d.K_BHALF))}
+    ctx.set_timing(False)
+
+    hv_per_s = cnt["hv_columns"] / elapsed
+    dom = max(("tlm", "adj"), key=lambda k: kst[k]["total_ms"])
+    ks = kst[dom]
+    achieved = ks["alg_flops"] / (ks["total_ms"] * 1e-3) / 1e12 if ks["total_ms"] > 0 else 0.0
+    peak = PEAK_FP64_VALU_TFLOPS if skd == rp4d.F64 else PEAK_FP32_VALU_TFLOPS
+    roofline = {"bound": "alu", "kernel": f"burgers_{dom}_kernel", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "avg_launch_us": 1e3 * ks["total_ms"] / max(1, ks["launches"]),
+                "launches": ks["launches"]}
+
+    # isolated block Hessian product, k = 64, FP64 (sketch shape)
+    traj = prob.traj()
+    prob.fwd(xb, traj, want_J=False)
+    V = torch.empty((cfg["n"], ell), dtype=torch.float64, device="cuda")
+    ctx.philox_normal(7, V.numel(), V)
+    HV = torch.empty_like(V)
+    for _ in range(2):
+        prob.hessian_block(traj, V, HV)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        prob.hessian_block(traj, V, HV)
+    e1.record()
+    torch.cuda.synchronize()
+    block_ms = e0.elapsed_time(e1) / reps
+
+    out = {
+        "metric": "Hessian-vec products/s; time per GN step to 1e-6 residual; p50/p99 latency",
+        "value": hv_per_s,
+        "unit": "Hv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if skd == rp4d.F64 else "f64 (sketch sweeps f32)",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "dt": cfg["dt"],
+                   "obs_stride": cfg["obs_stride"], "obs_every": cfg["obs_every"], "k": ell,
+                   "sketch": args.sketch, "gn_iters": args.gn_iters, "pcg_rtol": rtol},
+        "gn_step_ms": 1e3 * elapsed / (args.steps * args.gn_iters),
+        "pcg_iters_per_gn": [i["pcg_iters"] for i in infos[: args.gn_iters]],
+        "hessian_block_ms": block_ms,
+        "hessian_block_hv_per_s": ell / (block_ms * 1e-3),
+        "roofline": roofline,
+        "kernels": {k: {"launches": v["launches"], "total_ms": v["total_ms"],
+                        "tflops": (v["alg_flops"] / (v["total_ms"] * 1e-3) / 1e12) if v["total_ms"] > 0 else 0.0}
+                    for k, v in kst.items()},
+        "counters": cnt,
+        "tiling": tilings,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -232,15 +232,38 @@ int rp4d_counters_reset(rp4d_problem* p);
  * 2011) + Box-Muller: element i uses counter (i/4 pairs) under key `seed`. */
 int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out);
 
+/* Problem synthesis (Sec. 5.1 'Data and Background'), all device buffers:
+ * xb_out (n) = x_true + Gamma^{1/2} xi;  y_out (n_t, n_obs) = O M(x_true) + sigma_o eta
+ * (perfect model: the truth is propagated by the same FWD).  Does not set the
+ * problem's data (call rp4d_problem_set_data with the outputs). */
+int rp4d_problem_synthesize(rp4d_problem* p, const double* x_true, const double* xi, const double* eta,
+                            double* xb_out, double* y_out);
+
+/* Reset a GN state to v = 0, x = x_b and drop its resident preconditioner. */
+int rp4d_gn_state_reset(rp4d_gn_state* s);
+
+/* Kernel timing with HIP events recorded on the context stream around every
+ * launch of the timed kernel classes (enable = 1 clears the statistics).
+ * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps), RP4D_K_FWD, RP4D_K_BHALF.
+ * rp4d_ctx_kernel_stats synchronises the stream and returns the number of
+ * launches, their summed duration (ms) and the algorithmic flops they performed
+ * (owned grid points only; FP64 or FP32 as launched). */
+enum { RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3, RP4D_K_COUNT = 4 };
+int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
+int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
+
 /* Sweep tiling of a problem's block sweeps (used by the autotuner): points per
  * thread `ppt`, vectors per workgroup `kc`, threads per workgroup `threads`,
  * tile length `tile` (grid points owned per workgroup) and steps per launch
- * `steps`.  Any argument <= 0 restores the built-in heuristic for that field.
- * `dtype`/`k` select the entry (k = 0: every k). */
-int rp4d_set_sweep_tiling(rp4d_problem* p, int dtype, int k, int ppt, int kc, int threads,
+ * `steps`.  `mode` selects the sweep: 0 both, RP4D_MODE_TLM or RP4D_MODE_ADJ;
+ * `dtype`/`k` select the entry (k = 0: every k).  Any argument <= 0 restores
+ * the built-in heuristic for that field; all <= 0 removes the entry.  Invalid
+ * tilings are reported by the sweep call that uses them (RP4D_EINVAL). */
+enum { RP4D_MODE_TLM = 1, RP4D_MODE_ADJ = 2 };
+int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, int kc, int threads,
                           int tile, int steps);
-/* Host output: the tiling the next sweep with (dtype, k) would use. */
-int rp4d_get_sweep_tiling(const rp4d_problem* p, int dtype, int k, int* ppt, int* kc, int* threads,
+/* Host output: the tiling the next sweep of `mode` (0 = TLM) with (dtype, k) would use. */
+int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int* ppt, int* kc, int* threads,
                           int* tile, int* steps);
 
 #ifdef __cplusplus

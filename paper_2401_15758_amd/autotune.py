@@ -1,0 +1,154 @@
+"""Autotuner for the block-sweep tiling of the rp4d library.
+
+The TLM/ADJ sweeps are parameterised by points per thread (ppt), vectors per
+workgroup (kc), threads per workgroup, tile length (grid points owned per
+workgroup) and steps per launch (which fixes the halo, 4*steps+4 points per
+side).  For a problem shape (n, nsteps, k, dtype) the tuner enumerates valid
+tilings, times rp4d_tlm and rp4d_adj with each on the device (HIP events on the
+library stream), and keeps the fastest.  Results are cached as JSON keyed by
+the shape so later runs apply them without searching.
+"""
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import rp4d
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+PPTS = (1, 2, 4)
+KCS = (1, 2, 4, 8)
+LDS_LIMIT = 160 * 1024
+
+
+def key(n, nsteps, k, dtype):
+    return f"n{n}-N{nsteps}-k{k}-{'f64' if dtype == rp4d.F64 else 'f32'}"
+
+
+def candidates(n, k, dtype=rp4d.F64, min_groups_tiles=32):
+    """Valid tilings for an n-point problem with k vectors."""
+    es = 8 if dtype == rp4d.F64 else 4
+    out = []
+    for kc in KCS:
+        if kc > max(1, k) and kc != 1:
+            continue
+        groups = -(-k // kc)
+        for ntiles in (1, 2, 4, 8, 16, 32, 64, 128):
+            tile = -(-n // ntiles)
+            if tile < 16:
+                continue
+            if groups * ntiles < min(min_groups_tiles, groups * 128):
+                continue
+            for steps in (2, 4, 8, 12, 16, 25, 32, 50):
+                halo = 4 * steps + 4
+                region = tile + 2 * halo
+                if region > 3 * tile + 64:          # halo-dominated: wasteful
+                    continue
+                for ppt in PPTS:
+                    if kc == 8 and ppt > 2:
+                        continue
+                    threads = -(-region // ppt)
+                    threads = -(-threads // 64) * 64
+                    if threads > (512 if ppt * kc >= 8 else 1024) or threads < 64:
+                        continue
+                    if 2 * 2 * threads * (1 + kc) * es > LDS_LIMIT:
+                        continue
+                    out.append(dict(ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps))
+    return out
+
+
+def _time(fn, reps):
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+FIELDS = ("ppt", "kc", "threads", "tile", "steps")
+
+
+def tune(prob, traj, k, dtype=rp4d.F64, reps=2, budget_s=30.0, verbose=False):
+    """Search tilings for the TLM and the ADJ sweep of (prob, k, dtype) separately
+    (timing rp4d_tlm / rp4d_adj); applies the best of each and returns
+    {"tlm": {...tiling, ms}, "adj": {...}}."""
+    tdtype = torch.float64 if dtype == rp4d.F64 else torch.float32
+    V = torch.empty((prob.n, k), dtype=torch.float64, device=prob.dev)
+    prob.ctx.philox_normal(11, V.numel(), V)
+    V = V.to(tdtype)
+    W = torch.empty((prob.n_t, prob.n_obs, k), dtype=torch.float64, device=prob.dev)
+    prob.ctx.philox_normal(12, W.numel(), W)
+    W = W.to(tdtype)
+    Z = torch.empty_like(W)
+    U = torch.empty_like(V)
+    ops = {rp4d.MODE_TLM: lambda: prob.tlm(traj, V, Z), rp4d.MODE_ADJ: lambda: prob.adj(traj, W, U)}
+    cands = candidates(prob.n, k, dtype)
+    cands.sort(key=lambda c: (-c["steps"], -c["tile"]))
+    out = {}
+    for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
+        prob.set_sweep_tiling(dtype, k, mode=mode)          # heuristic baseline
+        best = dict(prob.get_sweep_tiling(dtype, k, mode=mode))
+        best_ms = _time(ops[mode], reps)
+        t_end = time.perf_counter() + budget_s / 2
+        timed = 0
+        for c in cands:
+            if time.perf_counter() > t_end:
+                break
+            prob.set_sweep_tiling(dtype, k, mode=mode, **c)
+            try:
+                ms = _time(ops[mode], reps)
+            except rp4d.Rp4dError:
+                continue
+            timed += 1
+            if verbose:
+                print(f"  {name} {c} {ms:.3f} ms", flush=True)
+            if ms < best_ms:
+                best, best_ms = dict(c), ms
+        prob.set_sweep_tiling(dtype, k, mode=mode, **best)
+        out[name] = dict(best, ms=best_ms, timed=timed, total=len(cands))
+    return out
+
+
+def load_cache(path=CACHE_PATH):
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache, path=CACHE_PATH):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply_cached(prob, nsteps, k, dtype=rp4d.F64, cache=None):
+    """Apply a cached tiling for this shape if there is one; returns it or None."""
+    cache = load_cache() if cache is None else cache
+    ent = cache.get(key(prob.n, nsteps, k, dtype))
+    if not ent or "tlm" not in ent or "adj" not in ent:
+        return None
+    for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
+        prob.set_sweep_tiling(dtype, k, mode=mode, **{f: ent[name][f] for f in FIELDS})
+    return ent
+
+
+def tune_or_load(prob, traj, nsteps, k, dtype=rp4d.F64, budget_s=30.0, cache_path=CACHE_PATH, save=True):
+    cache = load_cache(cache_path)
+    ent = apply_cached(prob, nsteps, k, dtype, cache)
+    if ent is not None:
+        return ent
+    best = tune(prob, traj, k, dtype, budget_s=budget_s)
+    cache[key(prob.n, nsteps, k, dtype)] = best
+    if save:
+        try:
+            save_cache(cache, cache_path)
+        except OSError:
+            pass
+    return best

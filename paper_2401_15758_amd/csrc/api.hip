@@ -36,7 +36,65 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+KernelTimer::KernelTimer(rp4d_ctx* ctx, int k, double fl) : c(ctx), kind(k), flops(fl) {
+    if (!c->timing) return;
+    if (c->event_pool.empty()) {
+        hipEvent_t e;
+        RP4D_HIP(hipEventCreate(&e));
+        c->event_pool.push_back(e);
+    }
+    a = c->event_pool.back();
+    c->event_pool.pop_back();
+    RP4D_HIP(hipEventRecord(a, c->stream));
+}
+
+KernelTimer::~KernelTimer() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (c->event_pool.empty()) {
+        if (hipEventCreate(&b) != hipSuccess) {
+            c->event_pool.push_back(a);
+            return;
+        }
+    } else {
+        b = c->event_pool.back();
+        c->event_pool.pop_back();
+    }
+    if (hipEventRecord(b, c->stream) != hipSuccess) {
+        c->event_pool.push_back(a);
+        c->event_pool.push_back(b);
+        return;
+    }
+    c->pending.push_back(rp4d_ctx::Pending{kind, a, b, flops});
+}
+
 namespace {
+
+// Resolve recorded event pairs into the per-class statistics (synchronises).
+void resolve_timing(rp4d_ctx* c) {
+    if (c->pending.empty()) return;
+    RP4D_HIP(hipStreamSynchronize(c->stream));
+    for (auto& pe : c->pending) {
+        float ms = 0.f;
+        RP4D_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
+        c->launches[pe.kind] += 1;
+        c->ms[pe.kind] += ms;
+        c->flops[pe.kind] += pe.flops;
+        c->event_pool.push_back(pe.a);
+        c->event_pool.push_back(pe.b);
+    }
+    c->pending.clear();
+}
+
+// Algorithmic flops per owned grid point and step, counted from the sweep
+// kernels' source (sub/mul/add = 1, fma = 2): per vector and shared base part.
+//   TLM vector: 4 stages x (dK 5 + acc 2) + 3 x dY 2 + update 2 = 36
+//   TLM base:   4 x (Dy 2, Y/2dx 1, 3 coefficients 3) + 3 x (RHS 6 + stage 2) = 48
+//   ADJ vector: mu 1 + 4 x (theta 5 + sum 1) + 3 x next mu 3 = 34
+//   ADJ base:   3 x (RHS 8 + stage 2) + 4 x (Dy 2 + 3 coefficients 5) = 58
+constexpr double FL_TLM_VEC = 36.0, FL_TLM_BASE = 48.0;
+constexpr double FL_ADJ_VEC = 34.0, FL_ADJ_BASE = 58.0;
+constexpr double FL_FWD = 48.0;
 
 template <typename F>
 int guarded(F&& f) {
@@ -158,9 +216,10 @@ Tiling heuristic_tiling(int n, int k) {
     return t;
 }
 
-Tiling tiling_for(const rp4d_problem* p, int dtype, int k) {
+Tiling tiling_for(const rp4d_problem* p, int mode, int dtype, int k) {
     Tiling t = heuristic_tiling(p->n, k);
-    for (auto key : {std::make_tuple(dtype, k), std::make_tuple(dtype, 0)}) {
+    for (auto key : {std::make_tuple(mode, dtype, k), std::make_tuple(0, dtype, k), std::make_tuple(mode, dtype, 0),
+                     std::make_tuple(0, dtype, 0)}) {
         auto it = p->tiling.find(key);
         if (it != p->tiling.end()) {
             const Tiling& o = it->second;
@@ -232,7 +291,10 @@ void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* sto
         a.S = std::min(t.steps, s_to - s0);
         a.xin = in;
         a.xout = out;
-        launch_burgers_fwd(a, t, st);
+        {
+            KernelTimer kt(p->ctx, RP4D_K_FWD, FL_FWD * a.S * static_cast<double>(n));
+            launch_burgers_fwd(a, t, st);
+        }
         std::swap(in, out);
     }
 }
@@ -260,8 +322,9 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
     T* in = buf0;
     T* out = buf1;
     const int C = tr->C;
-    for (int seg0 = 0; seg0 < p->s_last; seg0 += C) {
-        const int seg1 = std::min(p->s_last, seg0 + C);
+    const int seglen = C == 1 ? std::max(1, p->s_last) : C;  // full storage: one segment
+    for (int seg0 = 0; seg0 < p->s_last; seg0 += seglen) {
+        const int seg1 = std::min(p->s_last, seg0 + seglen);
         if (C == 1) {
             a.base = tr->states.as<double>();
             a.base_row0 = 0;
@@ -281,7 +344,11 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
             a.S = std::min(t.steps, seg1 - s0);
             a.xin = in;
             a.xout = out;
-            launch_burgers_sweep<T>(MODE_TLM, a, t, groups, st);
+            {
+                KernelTimer kt(p->ctx, RP4D_K_TLM,
+                               static_cast<double>(a.S) * n * (FL_TLM_VEC * k + FL_TLM_BASE));
+                launch_burgers_sweep<T>(MODE_TLM, a, t, groups, st);
+            }
             std::swap(in, out);
         }
     }
@@ -311,10 +378,11 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
     T* in = buf0;
     T* out = buf1;
     const int C = tr->C;
-    const int nseg = (p->s_last + C - 1) / C;
+    const int seglen = C == 1 ? std::max(1, p->s_last) : C;  // full storage: one segment
+    const int nseg = (p->s_last + seglen - 1) / seglen;
     for (int sg = nseg - 1; sg >= 0; --sg) {
-        const int seg0 = sg * C;
-        const int seg1 = std::min(p->s_last, seg0 + C);
+        const int seg0 = sg * seglen;
+        const int seg1 = std::min(p->s_last, seg0 + seglen);
         if (C == 1) {
             a.base = tr->states.as<double>();
             a.base_row0 = 0;
@@ -336,7 +404,11 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
             a.S = Sc;
             a.xin = in;
             a.xout = out;
-            launch_burgers_sweep<T>(MODE_ADJ, a, t, groups, st);
+            {
+                KernelTimer kt(p->ctx, RP4D_K_ADJ,
+                               static_cast<double>(a.S) * n * (FL_ADJ_VEC * k + FL_ADJ_BASE));
+                launch_burgers_sweep<T>(MODE_ADJ, a, t, groups, st);
+            }
             std::swap(in, out);
             s_hi -= Sc;
         }
@@ -344,9 +416,27 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
     return in;
 }
 
+// Gamma^{1/2} on k vectors.  Spectral form when few Fourier modes survive:
+// T = F^T in (r x k), out = F diag(lam) T (+ addv); otherwise the banded
+// periodic convolution with the square-root kernel.
 template <typename T>
 void bhalf_into(rp4d_problem* p, int k, const T* in, int in_kc, T* out, int out_kc, const T* addv) {
-    launch_circ_conv<T>(in, in_kc, out, out_kc, p->gk.as<double>(), p->D, p->n, k, addv, stream_of(p));
+    hipStream_t st = stream_of(p);
+    if (p->spec) {
+        const int r = p->r, n = p->n;
+        const size_t need = static_cast<size_t>(r) * k + gram_work_doubles(n, r, k);
+        p->ws_bh.ensure(need * sizeof(double));
+        double* Tm = p->ws_bh.as<double>();
+        double* gw = Tm + static_cast<size_t>(r) * k;
+        KernelTimer kt(p->ctx, RP4D_K_BHALF, 4.0 * n * static_cast<double>(r) * k);
+        launch_gram<double, T>(p->F.as<double>(), r, in, in_kc, n, r, k, Tm, gw, st);
+        launch_tsmm<double, T>(p->F.as<double>(), r, Tm, p->lamF.as<double>(), n, r, k, 1.0, addv, out_kc,
+                               addv ? 1.0 : 0.0, out, out_kc, st);
+        return;
+    }
+    const int band = std::min(2 * p->D + 1, p->n);
+    KernelTimer kt(p->ctx, RP4D_K_BHALF, 2.0 * p->n * static_cast<double>(k) * band);
+    launch_circ_conv<T>(in, in_kc, out, out_kc, p->gk.as<double>(), p->D, p->n, k, addv, st);
 }
 
 template <typename T>
@@ -354,15 +444,17 @@ struct SweepWork {
     T* s0;
     T* s1;
     T* obs;
-    Tiling t;
+    Tiling tt, ta;  // TLM and ADJ tilings
 };
 
 template <typename T>
 SweepWork<T> sweep_work(rp4d_problem* p, int k, int dtype) {
     SweepWork<T> w{};
-    w.t = tiling_for(p, dtype, k);
-    const int groups = (k + w.t.kc - 1) / w.t.kc;
-    const size_t blk = static_cast<size_t>(groups) * w.t.kc * p->n * sizeof(T);
+    w.tt = tiling_for(p, MODE_TLM, dtype, k);
+    w.ta = tiling_for(p, MODE_ADJ, dtype, k);
+    const int kcmax = std::max(w.tt.kc, w.ta.kc);
+    const int groups = (k + kcmax - 1) / kcmax + 1;  // covers the padding of either layout
+    const size_t blk = static_cast<size_t>(groups) * kcmax * p->n * sizeof(T);
     p->ws_s0.ensure(blk);
     p->ws_s1.ensure(blk);
     p->ws_obs.ensure(static_cast<size_t>(p->m) * k * sizeof(T));
@@ -375,28 +467,28 @@ SweepWork<T> sweep_work(rp4d_problem* p, int k, int dtype) {
 template <typename T>
 void tlm_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* Z) {
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
-    const int groups = (k + w.t.kc - 1) / w.t.kc;
-    if (groups * w.t.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.t.kc * p->n, T(0), stream_of(p));
-    bhalf_into<T>(p, k, V, k, w.s0, w.t.kc, nullptr);
-    run_tlm<T>(p, tr, k, w.t, w.s0, w.s1, Z);
+    const int groups = (k + w.tt.kc - 1) / w.tt.kc;
+    if (groups * w.tt.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.tt.kc * p->n, T(0), stream_of(p));
+    bhalf_into<T>(p, k, V, k, w.s0, w.tt.kc, nullptr);
+    run_tlm<T>(p, tr, k, w.tt, w.s0, w.s1, Z);
 }
 
 template <typename T>
 void adj_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* U, const T* addv) {
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
-    T* lam = run_adj<T>(p, tr, k, w.t, w.s0, w.s1, W);
-    bhalf_into<T>(p, k, lam, w.t.kc, U, k, addv);
+    T* lam = run_adj<T>(p, tr, k, w.ta, w.s0, w.s1, W);
+    bhalf_into<T>(p, k, lam, w.ta.kc, U, k, addv);
 }
 
 template <typename T>
 void hessian_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV, bool add_identity) {
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
-    const int groups = (k + w.t.kc - 1) / w.t.kc;
-    if (groups * w.t.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.t.kc * p->n, T(0), stream_of(p));
-    bhalf_into<T>(p, k, V, k, w.s0, w.t.kc, nullptr);
-    run_tlm<T>(p, tr, k, w.t, w.s0, w.s1, w.obs);
-    T* lam = run_adj<T>(p, tr, k, w.t, w.s0, w.s1, w.obs);
-    bhalf_into<T>(p, k, lam, w.t.kc, HV, k, add_identity ? V : nullptr);
+    const int groups = (k + w.tt.kc - 1) / w.tt.kc;
+    if (groups * w.tt.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.tt.kc * p->n, T(0), stream_of(p));
+    bhalf_into<T>(p, k, V, k, w.s0, w.tt.kc, nullptr);
+    run_tlm<T>(p, tr, k, w.tt, w.s0, w.s1, w.obs);
+    T* lam = run_adj<T>(p, tr, k, w.ta, w.s0, w.s1, w.obs);
+    bhalf_into<T>(p, k, lam, w.ta.kc, HV, k, add_identity ? V : nullptr);
     p->cnt.hv_columns += k;
 }
 
@@ -417,6 +509,14 @@ void check_common(const rp4d_problem* p, int k, const void* a, const void* b) {
 
 }  // namespace
 }  // namespace rp4d
+
+rp4d_ctx::~rp4d_ctx() {
+    for (auto& pe : pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (auto e : event_pool) (void)hipEventDestroy(e);
+}
 
 using namespace rp4d;
 
@@ -496,6 +596,48 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
             }
             p->gk.ensure(g.size() * sizeof(double));
             RP4D_HIP(hipMemcpy(p->gk.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
+            // Spectral form: the circulant's eigenvalues are the DFT of the kernel,
+            // ~ exp(-pi^2 kappa^2 L^2) of the largest, below 2^-60 beyond
+            // kappa_max = sqrt(60 ln 2)/(pi L); keep kappa <= kappa_max + 2 when that
+            // is a small fraction of the grid.
+            const int K = static_cast<int>(std::ceil(std::sqrt(60.0 * std::log(2.0)) / (M_PI * L))) + 2;
+            if (2 * K + 1 <= d.nx / 4) {
+                const int n = d.nx, r = 2 * K + 1;
+                std::vector<double> Fh(static_cast<size_t>(n) * r), lh(r);
+                std::vector<double> full(n);
+                for (int i = 0; i < n; ++i) {
+                    const int dd = std::min(i, n - i);
+                    const double rr = dd * dx;
+                    full[i] = d.sigma_b * a * std::exp(-(rr * rr) / (L * L));
+                }
+                auto cosn = [n](long q) { return std::cos(2.0 * M_PI * static_cast<double>(q % n) / n); };
+                auto sinn = [n](long q) { return std::sin(2.0 * M_PI * static_cast<double>(q % n) / n); };
+                const double c0 = 1.0 / std::sqrt(static_cast<double>(n)), c1 = std::sqrt(2.0 / n);
+                for (int kap = 0; kap <= K; ++kap) {
+                    double s = 0.0;
+                    for (int i = 0; i < n; ++i) s += full[i] * cosn(static_cast<long>(kap) * i);
+                    if (kap == 0) {
+                        lh[0] = s;
+                    } else {
+                        lh[2 * kap - 1] = s;
+                        lh[2 * kap] = s;
+                    }
+                }
+                for (int j = 0; j < n; ++j) {
+                    double* row = Fh.data() + static_cast<size_t>(j) * r;
+                    row[0] = c0;
+                    for (int kap = 1; kap <= K; ++kap) {
+                        row[2 * kap - 1] = c1 * cosn(static_cast<long>(kap) * j);
+                        row[2 * kap] = c1 * sinn(static_cast<long>(kap) * j);
+                    }
+                }
+                p->spec = true;
+                p->r = r;
+                p->F.ensure(Fh.size() * sizeof(double));
+                p->lamF.ensure(lh.size() * sizeof(double));
+                RP4D_HIP(hipMemcpy(p->F.p, Fh.data(), Fh.size() * sizeof(double), hipMemcpyHostToDevice));
+                RP4D_HIP(hipMemcpy(p->lamF.p, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
+            }
             p->xb.ensure(p->n * sizeof(double));
             p->y.ensure(static_cast<size_t>(p->m) * sizeof(double));
             p->ws_scal.ensure(64 * sizeof(double));
@@ -753,7 +895,7 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
     // step 3: nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
     launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
-    launch_jacobi_eig(s.S2, s.lam, s.S3, l, st);
+    launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
@@ -823,7 +965,7 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s) {
         return;
     }
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
-    launch_jacobi_eig(s.S2, s.lam, s.S3, l, st);
+    launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double sh = 11.0 * (static_cast<double>(rows) * l + l * (l + 1.0)) * std::ldexp(1.0, -53) * ymax2;
@@ -1221,6 +1363,59 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
     });
 }
 
+int rp4d_gn_state_reset(rp4d_gn_state* s) {
+    return guarded([&] {
+        RP4D_REQUIRE(s != nullptr, RP4D_EINVAL, "null state");
+        rp4d_problem* p = s->p;
+        set_device(p->ctx);
+        hipStream_t st = stream_of(p);
+        launch_fill<double>(s->v.as<double>(), p->n, 0.0, st);
+        launch_fill<double>(s->dv.as<double>(), p->n, 0.0, st);
+        launch_relayout<double, double>(p->xb.as<double>(), 1, s->x.as<double>(), 1, p->n, 1, st);
+        if (s->pc) {
+            rp4d_precond_destroy(s->pc);
+            s->pc = nullptr;
+        }
+    });
+}
+
+int rp4d_problem_synthesize(rp4d_problem* p, const double* x_true, const double* xi, const double* eta,
+                            double* xb_out, double* y_out) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && x_true && xi && eta && xb_out && y_out, RP4D_EINVAL, "null argument");
+        set_device(p->ctx);
+        hipStream_t st = stream_of(p);
+        bhalf_into<double>(p, 1, xi, 1, xb_out, 1, x_true);
+        run_fwd(p, x_true, 0, p->s_last, nullptr, 1, 0, 0, nullptr, y_out);
+        launch_axpby(eta, p->d.sigma_o, y_out, 1.0, p->m, st);
+    });
+}
+
+int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
+        set_device(ctx);
+        resolve_timing(ctx);
+        ctx->timing = enable != 0;
+        for (int i = 0; i < RP4D_K_COUNT; ++i) {
+            ctx->launches[i] = 0;
+            ctx->ms[i] = 0.0;
+            ctx->flops[i] = 0.0;
+        }
+    });
+}
+
+int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr && kind >= 0 && kind < RP4D_K_COUNT, RP4D_EINVAL, "bad argument");
+        set_device(ctx);
+        resolve_timing(ctx);
+        if (launches) *launches = ctx->launches[kind];
+        if (total_ms) *total_ms = ctx->ms[kind];
+        if (alg_flops) *alg_flops = ctx->flops[kind];
+    });
+}
+
 int rp4d_counters_get(const rp4d_problem* p, rp4d_counters* out) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
@@ -1243,9 +1438,11 @@ int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out) 
     });
 }
 
-int rp4d_set_sweep_tiling(rp4d_problem* p, int dtype, int k, int ppt, int kc, int threads, int tile, int steps) {
+int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, int kc, int threads, int tile,
+                          int steps) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
+        RP4D_REQUIRE(mode == 0 || mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "bad sweep mode");
         Tiling t;
         t.ppt = ppt;
         t.kc = kc;
@@ -1253,17 +1450,17 @@ int rp4d_set_sweep_tiling(rp4d_problem* p, int dtype, int k, int ppt, int kc, in
         t.tile = tile;
         t.steps = steps;
         if (ppt <= 0 && kc <= 0 && threads <= 0 && tile <= 0 && steps <= 0)
-            p->tiling.erase(std::make_tuple(dtype, k));
+            p->tiling.erase(std::make_tuple(mode, dtype, k));
         else
-            p->tiling[std::make_tuple(dtype, k)] = t;
+            p->tiling[std::make_tuple(mode, dtype, k)] = t;
     });
 }
 
-int rp4d_get_sweep_tiling(const rp4d_problem* p, int dtype, int k, int* ppt, int* kc, int* threads, int* tile,
-                          int* steps) {
+int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int* ppt, int* kc, int* threads,
+                          int* tile, int* steps) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
-        Tiling t = tiling_for(p, dtype, k > 0 ? k : 1);
+        Tiling t = tiling_for(p, mode == 0 ? MODE_TLM : mode, dtype, k > 0 ? k : 1);
         if (ppt) *ppt = t.ppt;
         if (kc) *kc = t.kc;
         if (threads) *threads = t.threads;

@@ -122,8 +122,13 @@ __global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
         if (own[p]) a.xout[g[p]] = u[p];
 }
 
+// Instances holding P*KC >= 8 point-vectors per thread are limited to 512
+// threads per workgroup so that they get 256 VGPRs instead of spilling.
+template <int P, int KC>
+constexpr int sweep_max_threads() { return P * KC >= 8 ? 512 : 1024; }
+
 template <typename T, int P, int KC>
-__global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_tlm_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char sh_raw[];
     T* sh = reinterpret_cast<T*>(sh_raw);
     constexpr int W = 1 + KC;
@@ -133,6 +138,7 @@ __global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
     const int tlen = min(a.tile, n - tstart);
     const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
+    const T nd2 = T(2) * nd;
 
     int g[P];
     bool own[P];
@@ -197,6 +203,10 @@ __global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
                 const T yp = p < P - 1 ? Y[p + 1] : Yr;
                 const T Dy = (yp - ym) * i2;
                 const T Yh = Y[p] * i2;
+                // J(Y) d = ca d + cp d+ + cm d-  (coefficients shared by the KC vectors)
+                const T ca = -Dy - nd2;
+                const T cp = nd - Yh;
+                const T cm = nd + Yh;
                 if (st < 3) {
                     const T K = rhs_pt<T>(Y[p], ym, yp, i2, nd);
                     Yn[p] = fma(ch, K, u[p]);
@@ -205,10 +215,7 @@ __global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
                 for (int c = 0; c < KC; ++c) {
                     const T dm = p > 0 ? dY[p - 1][c] : dl[c];
                     const T dp = p < P - 1 ? dY[p + 1][c] : dr[c];
-                    // J(Y) dY = -dY Dy - Y (d+ - d-)/(2dx) + nu (d+ - 2 dY + d-)/dx^2
-                    const T lap = fma(T(-2), dY[p][c], dp + dm);
-                    const T adv = fma(-dY[p][c], Dy, -(Yh * (dp - dm)));
-                    const T dK = fma(nd, lap, adv);
+                    const T dK = fma(cm, dm, fma(cp, dp, ca * dY[p][c]));
                     acc[p][c] = fma(cb, dK, acc[p][c]);
                     if (st < 3) dYn[p][c] = fma(ch, dK, d[p][c]);
                 }
@@ -255,7 +262,7 @@ __global__ void __launch_bounds__(1024) burgers_tlm_kernel(SweepArgs<T> a) {
 }
 
 template <typename T, int P, int KC>
-__global__ void __launch_bounds__(1024) burgers_adj_kernel(SweepArgs<T> a) {
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char sh_raw[];
     T* sh = reinterpret_cast<T*>(sh_raw);
     constexpr int W = 1 + KC;
@@ -265,6 +272,7 @@ __global__ void __launch_bounds__(1024) burgers_adj_kernel(SweepArgs<T> a) {
     const int tlen = min(a.tile, n - tstart);
     const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
+    const T nd2 = T(2) * nd;
 
     int g[P];
     bool own[P];
@@ -374,15 +382,16 @@ __global__ void __launch_bounds__(1024) burgers_adj_kernel(SweepArgs<T> a) {
                 const T ym = p > 0 ? Ys[st][p - 1] : YL[st];
                 const T yp = p < P - 1 ? Ys[st][p + 1] : YR[st];
                 const T Dy = (yp - ym) * i2;
+                // J(Y)^T mu = ca mu + cp mu+ + cm mu-, with ca = -Dy - 2nu/dx^2,
+                // cp = nu/dx^2 + Y+/(2dx), cm = nu/dx^2 - Y-/(2dx)
+                const T ca = -Dy - nd2;
+                const T cp = fma(yp, i2, nd);
+                const T cm = fma(-ym, i2, nd);
 #pragma unroll
                 for (int c = 0; c < KC; ++c) {
                     const T mm = p > 0 ? mu[p - 1][c] : ml[c];
                     const T mp = p < P - 1 ? mu[p + 1][c] : mr[c];
-                    // J(Y)^T mu = -Dy mu + (Y+ mu+ - Y- mu-)/(2dx) + nu (mu+ - 2 mu + mu-)/dx^2
-                    const T flux = fma(yp, mp, -(ym * mm));
-                    const T adv = fma(-Dy, mu[p][c], flux * i2);
-                    const T lap = fma(T(-2), mu[p][c], mp + mm);
-                    const T th = fma(nd, lap, adv);
+                    const T th = fma(cm, mm, fma(cp, mp, ca * mu[p][c]));
                     lu[p][c] += th;
                     if (st > 0) mun[p][c] = fma(a_th, th, a_lam * lam[p][c]);
                 }
@@ -436,10 +445,19 @@ void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st) {
 
 template <typename T, int P, int KC>
 static void launch_one(int mode, const SweepArgs<T>& a, dim3 grid, dim3 block, size_t shmem, hipStream_t st) {
-    if (mode == MODE_TLM)
+    RP4D_REQUIRE((static_cast<int>(block.x) <= sweep_max_threads<P, KC>()), RP4D_EINVAL,
+                 "sweep tiling: too many threads for this (points per thread, vectors per group)");
+    if (mode == MODE_TLM) {
+        if (shmem > 64 * 1024)
+            RP4D_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&burgers_tlm_kernel<T, P, KC>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
         burgers_tlm_kernel<T, P, KC><<<grid, block, shmem, st>>>(a);
-    else
+    } else {
+        if (shmem > 64 * 1024)
+            RP4D_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&burgers_adj_kernel<T, P, KC>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
         burgers_adj_kernel<T, P, KC><<<grid, block, shmem, st>>>(a);
+    }
 }
 
 template <typename T>
@@ -448,7 +466,7 @@ void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int 
     RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "sweep: bad mode");
     dim3 grid((a.n + t.tile - 1) / t.tile, ngroups), block(t.threads);
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
-    RP4D_REQUIRE(shmem <= 64 * 1024, RP4D_EINVAL, "sweep tiling: LDS exchange buffer too large");
+    RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "sweep tiling: LDS exchange buffer too large");
     const int key = t.ppt * 100 + t.kc;
     switch (key) {
         case 101: launch_one<T, 1, 1>(mode, a, grid, block, shmem, st); break;
@@ -460,6 +478,8 @@ void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int 
         case 401: launch_one<T, 4, 1>(mode, a, grid, block, shmem, st); break;
         case 402: launch_one<T, 4, 2>(mode, a, grid, block, shmem, st); break;
         case 404: launch_one<T, 4, 4>(mode, a, grid, block, shmem, st); break;
+        case 108: launch_one<T, 1, 8>(mode, a, grid, block, shmem, st); break;
+        case 208: launch_one<T, 2, 8>(mode, a, grid, block, shmem, st); break;
         default: fail(RP4D_EINVAL, "sweep tiling: unsupported (points per thread, vectors per group)");
     }
     RP4D_HIP(hipGetLastError());

@@ -105,7 +105,10 @@ void launch_relayout(const TI* in, int in_kc, TO* out, int out_kc, int n, int k,
 template <typename T>
 void launch_fill(T* p, size_t count, T v, hipStream_t st);
 
-// C (a x b, row-major, FP64) = X^T Y; X (n x a, ld lx), Y (n x b, ld ly).
+// Matrix operands below use the blocked layout: element (row, col) of an
+// n-row operand with layout parameter kc sits at ((col / kc) * n + row) * kc + col % kc,
+// so a row-major n x w matrix is kc = w.
+// C (a x b, row-major, FP64) = X^T Y; X (n x a, layout lx), Y (n x b, layout ly).
 // Deterministic two-stage reduction; `work` must hold gram_work_doubles(n,a,b).
 template <typename TX, typename TY>
 void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
@@ -150,7 +153,32 @@ void launch_philox_normal_t(uint64_t seed, size_t count, T* out, hipStream_t st)
 struct rp4d_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // kernel timing (HIP events around launches of the timed kernel classes)
+    bool timing = false;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+        double flops;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    long long launches[RP4D_K_COUNT] = {};
+    double ms[RP4D_K_COUNT] = {};
+    double flops[RP4D_K_COUNT] = {};
+    ~rp4d_ctx();
 };
+
+namespace rp4d {
+// Timing scope: records an event pair around the launches issued in its lifetime.
+struct KernelTimer {
+    rp4d_ctx* c;
+    int kind;
+    double flops;
+    hipEvent_t a = nullptr;
+    KernelTimer(rp4d_ctx* ctx, int k, double fl);
+    ~KernelTimer();
+};
+}  // namespace rp4d
 
 struct rp4d_problem {
     rp4d_ctx* ctx = nullptr;
@@ -161,10 +189,15 @@ struct rp4d_problem {
     bool has_data = false;
     rp4d::DevBuf gk;  // prior square-root kernel g_0..g_D
     int D = 0;
+    // spectral form of the circulant prior square root: F (n x r) real Fourier
+    // basis of the retained modes, lam (r) their eigenvalues
+    bool spec = false;
+    int r = 0;
+    rp4d::DevBuf F, lamF, ws_bh;
     // workspaces
     rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg;
     rp4d_counters cnt{};
-    std::map<std::tuple<int, int>, rp4d::Tiling> tiling;
+    std::map<std::tuple<int, int, int>, rp4d::Tiling> tiling;  // (mode, dtype, k)
 };
 
 struct rp4d_traj {

@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const TX* X, int lx, 
         for (int e = tid; e < GR * 64; e += 256) {
             const int r = e / 64, col = e % 64;
             const int row = rr + r;
-            xs[r][col] = (row < r1 && i0 + col < a) ? static_cast<double>(X[static_cast<size_t>(row) * lx + i0 + col]) : 0.0;
-            ys[r][col] = (row < r1 && j0 + col < b) ? static_cast<double>(Y[static_cast<size_t>(row) * ly + j0 + col]) : 0.0;
+            xs[r][col] = (row < r1 && i0 + col < a) ? static_cast<double>(X[blk_off(row, i0 + col, lx, n)]) : 0.0;
+            ys[r][col] = (row < r1 && j0 + col < b) ? static_cast<double>(Y[blk_off(row, j0 + col, ly, n)]) : 0.0;
         }
         __syncthreads();
 #pragma unroll 4
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const do
         for (int e = tid; e < 64 * 16; e += 256) {
             const int r = e / 16, q = e % 16;
             const int row = r0 + r, col = kk + q;
-            xs[r][q] = (row < n && col < a) ? static_cast<double>(X[static_cast<size_t>(row) * lx + col]) : 0.0;
+            xs[r][q] = (row < n && col < a) ? static_cast<double>(X[blk_off(row, col, lx, n)]) : 0.0;
         }
         for (int e = tid; e < 16 * 64; e += 256) {
             const int q = e / 64, j = e % 64;
@@ -211,8 +211,8 @@ __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const do
             const int row = r0 + ti * 4 + p, col = j0 + tj * 4 + s;
             if (row < n && col < b) {
                 double v = alpha * acc[p][s];
-                if (beta != 0.0) v += beta * static_cast<double>(C[static_cast<size_t>(row) * lc + col]);
-                Out[static_cast<size_t>(row) * lo + col] = static_cast<TO>(v);
+                if (beta != 0.0) v += beta * static_cast<double>(C[blk_off(row, col, lc, n)]);
+                Out[blk_off(row, col, lo, n)] = static_cast<TO>(v);
             }
         }
 }
@@ -366,99 +366,139 @@ __global__ void small_gemm_kernel(const double* A, int ta, const double* B, int 
     C[idx] = alpha * s;
 }
 
-// Cyclic Jacobi (round-robin parallel ordering, Golub & Van Loan Alg. 8.5.3 /
-// sym.schur2).  A lives in LDS; V in LDS when it fits, otherwise in `evecs`.
-template <bool VLDS>
+// Cyclic Jacobi (round-robin parallel ordering; rotation as in Golub & Van Loan
+// sym.schur2).  The matrix is padded to even order m (a zero row/column when l
+// is odd) and kept in LDS with an odd row stride.  Each round: the m/2 disjoint
+// rotations are computed, then every thread applies J^T B J to its own 2x2
+// blocks B = A[{p_i,q_i}, {p_j,q_j}] in place (blocks are disjoint, so one
+// barrier suffices) and V <- V J on its (row, pair) items.
+template <bool VLDS, bool WANTV>
 __global__ void __launch_bounds__(1024) jacobi_kernel(double* A, double* evals, double* evecs, double* vwork, int l) {
     extern __shared__ double sm[];
+    const int m = l + (l & 1);
+    const int ld = m + 1;
     double* sA = sm;
-    double* V = VLDS ? (sm + l * l) : vwork;
+    double* V = VLDS ? (sm + m * ld) : vwork;
+    const int vld = VLDS ? ld : m;
     __shared__ double cs[64], sn[64];
     __shared__ int pp[64], qq[64];
     __shared__ int rotated;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int m = l + (l & 1);
     const int half = m / 2;
-    for (int e = tid; e < l * l; e += nt) {
-        const int i = e / l, j = e % l;
-        sA[e] = 0.5 * (A[i * l + j] + A[j * l + i]);
+    for (int e = tid; e < m * m; e += nt) {
+        const int i = e / m, j = e % m;
+        sA[i * ld + j] = (i < l && j < l) ? 0.5 * (A[i * l + j] + A[j * l + i]) : 0.0;
     }
     __syncthreads();  // V may alias A's global storage: stage A fully first
-    for (int e = tid; e < l * l; e += nt) V[e] = ((e / l) == (e % l)) ? 1.0 : 0.0;
+    for (int e = tid; WANTV && e < m * m; e += nt) {
+        const int i = e / m, j = e % m;
+        V[i * vld + j] = (i == j) ? 1.0 : 0.0;
+    }
     __syncthreads();
+    const int nblk = half * half;      // 2x2 blocks of A
+    const int nvit = m * half;         // (row, pair) items of V
+    // Frobenius norm (invariant under the rotations).  Applying rotations leaves
+    // roundoff of order eps |A|_F in every entry, so off-diagonal entries below
+    // 1e-15 |A|_F are not rotated away (otherwise pairs of eigenvalues near the
+    // noise level of a numerically singular Gram matrix never converge); above it
+    // the relative test |a_pq| > eps sqrt(|a_pp a_qq|) applies.
+    __shared__ double red[1024];
+    double f2 = 0.0;
+    for (int e = tid; e < m * m; e += nt) {
+        const double v = sA[(e / m) * ld + (e % m)];
+        f2 = fma(v, v, f2);
+    }
+    red[tid] = f2;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double floor_abs = 1e-15 * sqrt(red[0]);
+    // this thread's 2x2-block and V items (fixed across rounds; m <= 128, nt = 1024)
+    int tb_i[4], tb_j[4], tv_i[8], tv_r[8];
+    int nbt = 0, nvt = 0;
+    for (int e = tid; e < nblk && nbt < 4; e += nt, ++nbt) {
+        tb_i[nbt] = e / half;
+        tb_j[nbt] = e % half;
+    }
+    for (int e = tid; e < nvit && nvt < 8; e += nt, ++nvt) {
+        tv_i[nvt] = e / m;
+        tv_r[nvt] = e % m;
+    }
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {
             if (tid < half) {
                 // circle method: position 0 fixed, the others rotate
-                auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
-                int p = player(tid), q = player(m - 1 - tid);
+                const int a0 = tid, b0 = m - 1 - tid;
+                int p = a0 == 0 ? 0 : ((a0 - 1 + round) % (m - 1)) + 1;
+                int q = ((b0 - 1 + round) % (m - 1)) + 1;
                 if (p > q) {
                     const int tmp = p;
                     p = q;
                     q = tmp;
                 }
                 double c = 1.0, s = 0.0;
-                if (q < l) {
-                    const double apq = sA[p * l + q];
-                    const double app = sA[p * l + p], aqq = sA[q * l + q];
-                    if (fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                                     : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                        rotated = 1;
-                    }
+                const double apq = sA[p * ld + q];
+                const double app = sA[p * ld + p], aqq = sA[q * ld + q];
+                if (fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs && fabs(apq) > 1e-300) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                 : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                    rotated = 1;
                 }
                 cs[tid] = c;
                 sn[tid] = s;
                 pp[tid] = p;
-                qq[tid] = q < l ? q : -1;
+                qq[tid] = q;
             }
             __syncthreads();
-            // rows p, q <- J^T A
-            for (int e = tid; e < half * l; e += nt) {
-                const int i = e / l, col = e % l;
-                const int q = qq[i];
-                if (q < 0 || sn[i] == 0.0) continue;
-                const int p = pp[i];
-                const double c = cs[i], s = sn[i];
-                const double ap = sA[p * l + col], aq = sA[q * l + col];
-                sA[p * l + col] = c * ap - s * aq;
-                sA[q * l + col] = s * ap + c * aq;
+            for (int q8 = 0; q8 < nbt; ++q8) {
+                const int bi = tb_i[q8], bj = tb_j[q8];
+                const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+                if (si == 0.0 && sj == 0.0) continue;
+                const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
+                const double b00 = sA[pi * ld + pj], b01 = sA[pi * ld + qj];
+                const double b10 = sA[qi * ld + pj], b11 = sA[qi * ld + qj];
+                // rows: [c -s; s c] B
+                const double r00 = ci * b00 - si * b10, r01 = ci * b01 - si * b11;
+                const double r10 = si * b00 + ci * b10, r11 = si * b01 + ci * b11;
+                // columns: R [c s; -s c]
+                sA[pi * ld + pj] = cj * r00 - sj * r01;
+                sA[pi * ld + qj] = sj * r00 + cj * r01;
+                sA[qi * ld + pj] = cj * r10 - sj * r11;
+                sA[qi * ld + qj] = sj * r10 + cj * r11;
             }
-            __syncthreads();
-            // columns p, q <- A J and V J
-            for (int e = tid; e < half * l; e += nt) {
-                const int i = e / l, row = e % l;
-                const int q = qq[i];
-                if (q < 0 || sn[i] == 0.0) continue;
-                const int p = pp[i];
-                const double c = cs[i], s = sn[i];
-                const double ap = sA[row * l + p], aq = sA[row * l + q];
-                sA[row * l + p] = c * ap - s * aq;
-                sA[row * l + q] = s * ap + c * aq;
-                const double vp = V[row * l + p], vq = V[row * l + q];
-                V[row * l + p] = c * vp - s * vq;
-                V[row * l + q] = s * vp + c * vq;
+            for (int q8 = 0; WANTV && q8 < nvt; ++q8) {
+                const int i = tv_i[q8], row = tv_r[q8];
+                const double s = sn[i];
+                if (s == 0.0) continue;
+                const double c = cs[i];
+                const int p = pp[i], q = qq[i];
+                const double vp = V[row * vld + p], vq = V[row * vld + q];
+                V[row * vld + p] = c * vp - s * vq;
+                V[row * vld + q] = s * vp + c * vq;
             }
             __syncthreads();
         }
         if (!rotated) break;
         __syncthreads();
     }
-    // sort descending (ties by index) and write out
+    // sort descending (ties by index) and write out the l x l part
     for (int i = tid; i < l; i += nt) {
-        const double li = sA[i * l + i];
+        const double li = sA[i * ld + i];
         int rank = 0;
         for (int j = 0; j < l; ++j) {
-            const double lj = sA[j * l + j];
+            const double lj = sA[j * ld + j];
             if (lj > li || (lj == li && j < i)) ++rank;
         }
         evals[rank] = li;
-        for (int row = 0; row < l; ++row) evecs[row * l + rank] = V[row * l + i];
+        if (WANTV)
+            for (int row = 0; row < l; ++row) evecs[row * l + rank] = V[row * vld + i];
     }
 }
 
@@ -587,19 +627,28 @@ void launch_small_gemm(const double* A, int ta, const double* B, int tb, double*
 
 void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st) {
     RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "eigensolver: l must be in [1, 128]");
-    const size_t both = 2 * static_cast<size_t>(l) * l * sizeof(double);
-    const size_t one = static_cast<size_t>(l) * l * sizeof(double);
-    if (both <= 150 * 1024) {
-        if (both > 64 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(both));
-        jacobi_kernel<true><<<1, 1024, both, st>>>(A, evals, evecs, nullptr, l);
-    } else {
-        // V in global memory: use A's storage after it has been staged in LDS
+    const size_t me = static_cast<size_t>(l + (l & 1));
+    const bool wantv = evecs != nullptr;
+    const size_t both = 2 * me * (me + 1) * sizeof(double);
+    const size_t one = me * (me + 1) * sizeof(double);
+    if (!wantv) {
+        // eigenvalues only: V is never touched
         if (one > 64 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<false>),
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true, false>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(one));
-        jacobi_kernel<false><<<1, 1024, one, st>>>(A, evals, evecs, A, l);
+        jacobi_kernel<true, false><<<1, 1024, one, st>>>(A, evals, nullptr, nullptr, l);
+    } else if (both <= 160 * 1024 - 2048) {
+        if (both > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(both));
+        jacobi_kernel<true, true><<<1, 1024, both, st>>>(A, evals, evecs, nullptr, l);
+    } else {
+        // V in global memory reuses A's storage (l x l), which needs an even order
+        RP4D_REQUIRE((l & 1) == 0, RP4D_EINVAL, "eigensolver: odd l above the LDS limit is not supported");
+        if (one > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<false, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(one));
+        jacobi_kernel<false, true><<<1, 1024, one, st>>>(A, evals, evecs, A, l);
     }
     RP4D_HIP(hipGetLastError());
 }

@@ -23,6 +23,8 @@ OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -
 F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC = 0, 1, 2
 BURGERS1D, BVE2D = 0, 1
+K_TLM, K_ADJ, K_FWD, K_BHALF = 0, 1, 2, 3
+MODE_BOTH, MODE_TLM, MODE_ADJ = 0, 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
           ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE", EHIP: "EHIP", ESTATE: "ESTATE"}
@@ -101,8 +103,12 @@ _SIGS = {
     "rp4d_counters_get": ([_P, ctypes.POINTER(Counters)], _I),
     "rp4d_counters_reset": ([_P], _I),
     "rp4d_philox_normal": ([_P, ctypes.c_uint64, ctypes.c_size_t, _P], _I),
-    "rp4d_set_sweep_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I], _I),
-    "rp4d_get_sweep_tiling": ([_P, _I, _I] + [ctypes.POINTER(_I)] * 5, _I),
+    "rp4d_problem_synthesize": ([_P, _P, _P, _P, _P, _P], _I),
+    "rp4d_gn_state_reset": ([_P], _I),
+    "rp4d_ctx_set_timing": ([_P, _I], _I),
+    "rp4d_ctx_kernel_stats": ([_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
+    "rp4d_set_sweep_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I, _I], _I),
+    "rp4d_get_sweep_tiling": ([_P, _I, _I, _I] + [ctypes.POINTER(_I)] * 5, _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -160,6 +166,14 @@ class Context:
         _check(_lib.rp4d_philox_normal(self._h, seed, count, _ptr(out, torch.float64, count, "out")))
         return out
 
+    def set_timing(self, enable=True):
+        _check(_lib.rp4d_ctx_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self, kind):
+        n, ms, fl = ctypes.c_longlong(), _D(), _D()
+        _check(_lib.rp4d_ctx_kernel_stats(self._h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        return dict(launches=n.value, total_ms=ms.value, alg_flops=fl.value)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.rp4d_ctx_destroy(self._h)
@@ -198,6 +212,15 @@ class Problem:
 
     def traj(self):
         return Traj(self)
+
+    def synthesize(self, x_true, xi, eta):
+        """x_b = x_true + Gamma^{1/2} xi and y = O M(x_true) + sigma_o eta on the device."""
+        xb = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        y = torch.empty((self.n_t, self.n_obs), dtype=torch.float64, device=self.dev)
+        _check(_lib.rp4d_problem_synthesize(self._h, _ptr(x_true, torch.float64, self.n, "x_true"),
+                                            _ptr(xi, torch.float64, self.n, "xi"),
+                                            _ptr(eta, torch.float64, self.m, "eta"), _ptr(xb), _ptr(y)))
+        return xb, y
 
     def fwd(self, x0, traj, want_J=True):
         J = _D()
@@ -292,12 +315,12 @@ class Problem:
     def reset_counters(self):
         _check(_lib.rp4d_counters_reset(self._h))
 
-    def set_sweep_tiling(self, dtype=F64, k=0, ppt=0, kc=0, threads=0, tile=0, steps=0):
-        _check(_lib.rp4d_set_sweep_tiling(self._h, dtype, k, ppt, kc, threads, tile, steps))
+    def set_sweep_tiling(self, dtype=F64, k=0, ppt=0, kc=0, threads=0, tile=0, steps=0, mode=MODE_BOTH):
+        _check(_lib.rp4d_set_sweep_tiling(self._h, mode, dtype, k, ppt, kc, threads, tile, steps))
 
-    def get_sweep_tiling(self, dtype=F64, k=1):
+    def get_sweep_tiling(self, dtype=F64, k=1, mode=MODE_TLM):
         vals = [_I() for _ in range(5)]
-        _check(_lib.rp4d_get_sweep_tiling(self._h, dtype, k, *[ctypes.byref(v) for v in vals]))
+        _check(_lib.rp4d_get_sweep_tiling(self._h, mode, dtype, k, *[ctypes.byref(v) for v in vals]))
         return dict(zip(("ppt", "kc", "threads", "tile", "steps"), (v.value for v in vals)))
 
     def close(self):
@@ -380,6 +403,9 @@ class GNState:
         x = torch.empty_like(v)
         _check(_lib.rp4d_gn_state_get(self._h, _ptr(v, torch.float64, n), _ptr(x, torch.float64, n)))
         return v, x
+
+    def reset(self):
+        _check(_lib.rp4d_gn_state_reset(self._h))
 
     def last_step(self):
         dv = torch.empty(self.prob.n, dtype=torch.float64, device=self.prob.dev)

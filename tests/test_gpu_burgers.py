@@ -186,3 +186,34 @@ def test_large_config_sampled_columns():
     assert colwise_relerr(HV[:, cols], ref) <= 1e-11
     obs = to_np(pr.gpu.observe(pr.traj))
     assert relerr(obs, pr.orc.observe(pr.otraj)) <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [inputs.CFG_SMALL, RAGGED])
+def test_synthesis_parity(cfg):
+    """Device synthesis x_b = x_true + Gamma^{1/2} xi, y = O M(x_true) + sigma_o eta
+    against the oracle's synthesis from the same draws."""
+    need_gpu()
+    from oracle.problem import burgers_problem
+    from paper_2401_15758_amd import rp4d
+    d = inputs.draws(cfg, seed=4)
+    orc = burgers_problem(cfg, d)
+    p = rp4d.Problem(rp4d.Context(0), cfg)
+    xb, y = p.synthesize(to_dev(d['x_true']), to_dev(d['xi']), to_dev(d['eta'].reshape(-1)))
+    assert relerr(to_np(xb), orc.xb) <= 1e-14
+    assert relerr(to_np(y), orc.y) <= 1e-13
+
+
+def test_kernel_timing_counts_launches(small):
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    pr.ctx.set_timing(True)
+    V = to_dev(_rand((pr.orc.n, 4), 111))
+    pr.gpu.hessian_block(pr.traj, V)
+    st = pr.ctx.kernel_stats(rp4d.K_TLM)
+    sa = pr.ctx.kernel_stats(rp4d.K_ADJ)
+    pr.ctx.set_timing(False)
+    t = pr.gpu.get_sweep_tiling(rp4d.F64, 4)
+    launches = -(-50 // t['steps'])
+    assert st['launches'] == launches and sa['launches'] == launches
+    assert st['total_ms'] > 0 and st['alg_flops'] == pytest.approx(50 * 128 * (36 * 4 + 48))
