@@ -143,6 +143,10 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
 int rp4d_problem_destroy(rp4d_problem* p);
 /* Host outputs: n (state size), n_obs, n_t. */
 int rp4d_problem_dims(const rp4d_problem* p, int* n, int* n_obs, int* n_t);
+/* Caller-chosen identity of a problem (default 0).  Batched calls derive each
+ * problem's random draws (Omega, kappa_re test vectors) from (seed, id), so a
+ * problem's results do not depend on its position in a batch. */
+int rp4d_problem_set_id(rp4d_problem* p, uint64_t id);
 /* Copy x_b (n) and y (n_t, n_obs) from device buffers into the problem. */
 int rp4d_problem_set_data(rp4d_problem* p, const double* xb, const double* y);
 
@@ -251,6 +255,37 @@ int rp4d_gn_state_reset(rp4d_gn_state* s);
 enum { RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3, RP4D_K_COUNT = 4 };
 int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent Burgers problems (uneven n and window length)
+ * advanced together.  Each phase is one launch over all problems (the sweeps:
+ * one fused launch per time interval covering every problem's tiles); per-problem
+ * reductions use one workgroup per problem with a fixed order, so each result is
+ * the same whatever else shares the batch.  Batched sweeps need full trajectory
+ * storage (ckpt_every <= 1).  Arrays are indexed like the batch's problems.
+ * ------------------------------------------------------------------------- */
+typedef struct rp4d_batch rp4d_batch;
+/* Group `nprob` problems of one context (the batch does not own them). */
+int rp4d_batch_create(rp4d_ctx* ctx, int nprob, rp4d_problem* const* probs, rp4d_batch** out);
+int rp4d_batch_destroy(rp4d_batch* b);
+/* Tiling of the batched block sweeps (mode RP4D_MODE_TLM / RP4D_MODE_ADJ, dtype):
+ * points per thread, vectors per workgroup, threads per workgroup, steps per
+ * launch; each problem's tile is threads*ppt - 2*(4*steps+4) points (at most n).
+ * Values <= 0 keep the defaults. */
+int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps);
+/* FWD of every problem from x0[i] (device, n_i) into trajs[i]; J_obs (host, nprob,
+ * nullable) receives 1/2 |d_i|^2. */
+int rp4d_batch_fwd(rp4d_batch* b, const double* const* x0, rp4d_traj* const* trajs, double* J_obs);
+/* HV[i] (n_i, k) = (add_identity ? V[i] : 0) + H_i V[i] for every problem. */
+int rp4d_batch_hessian_block(rp4d_batch* b, rp4d_traj* const* trajs, int k, const void* const* V, void* const* HV,
+                             int dtype, int add_identity);
+/* One GN step for every problem (states[i] belongs to problem i): batched FWD,
+ * gradient, kappa_re reuse test (when opts->reuse_eps > 0 and a preconditioner is
+ * resident), Nystrom sketches (opts->sketch = RP4D_NYSTROM, omega must be NULL:
+ * Omega drawn with Philox from seed ^ (0x9E3779B97F4A7C15 * (id + 1))) or none
+ * (RP4D_NOPREC), lockstep FP64 PCG, update.
+ * infos (host, nprob, nullable).  RP4D_ENOCONV if some PCG hit maxit. */
+int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_gn_opts* opts, rp4d_gn_info* infos);
 
 /* Sweep tiling of a problem's block sweeps (used by the autotuner): points per
  * thread `ppt`, vectors per workgroup `kc`, threads per workgroup `threads`,

@@ -180,7 +180,10 @@ inline int nblk(long count, int t = 256) {
 // ---------------------------------------------------------------------------
 // problem helpers
 // ---------------------------------------------------------------------------
-void set_device(const rp4d_ctx* c) { RP4D_HIP(hipSetDevice(c->device)); }
+void set_device(const rp4d_ctx* c) {
+    RP4D_HIP(hipSetDevice(c->device));
+    (void)hipGetLastError();  // drop errors left by calls outside this library
+}
 
 hipStream_t stream_of(const rp4d_problem* p) { return p->ctx->stream; }
 
@@ -665,6 +668,13 @@ int rp4d_problem_dims(const rp4d_problem* p, int* n, int* n_obs, int* n_t) {
         if (n) *n = p->n;
         if (n_obs) *n_obs = p->n_obs;
         if (n_t) *n_t = p->n_t;
+    });
+}
+
+int rp4d_problem_set_id(rp4d_problem* p, uint64_t id) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
+        p->id = id;
     });
 }
 
@@ -1466,6 +1476,1012 @@ int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int
         if (threads) *threads = t.threads;
         if (tile) *tile = t.tile;
         if (steps) *steps = t.steps;
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches: many independent Burgers problems advanced together.  Every phase
+// is one launch (or one fused launch per time interval for the sweeps) over all
+// problems; per-problem arguments travel as descriptor arrays staged through a
+// pinned host ring.
+// ===========================================================================
+struct rp4d_batch {
+    rp4d_ctx* ctx = nullptr;
+    std::vector<rp4d_problem*> probs;
+    // staging ring: pinned host memory mirrored into device memory
+    char* host = nullptr;
+    rp4d::DevBuf dev;
+    size_t cap = 0, off = 0;
+    rp4d::DevBuf scal;  // 16 doubles per problem of batch scalars
+    rp4d::Tiling bt[2][2];  // [mode-1][dtype] overrides (threads, ppt, kc, steps)
+    ~rp4d_batch() {
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+namespace rp4d {
+namespace {
+
+template <typename T>
+T* stage(rp4d_batch* b, const std::vector<T>& v) {
+    const size_t bytes = ((v.size() * sizeof(T)) + 255) / 256 * 256;
+    if (bytes == 0) return nullptr;
+    RP4D_REQUIRE(bytes <= b->cap, RP4D_ENOMEM, "batch staging ring too small for a descriptor table");
+    if (b->off + bytes > b->cap) {
+        RP4D_HIP(hipStreamSynchronize(b->ctx->stream));  // earlier copies out of the ring have completed
+        b->off = 0;
+    }
+    char* h = b->host + b->off;
+    char* d = b->dev.as<char>() + b->off;
+    std::memcpy(h, v.data(), v.size() * sizeof(T));
+    RP4D_HIP(hipMemcpyAsync(d, h, v.size() * sizeof(T), hipMemcpyHostToDevice, b->ctx->stream));
+    b->off += bytes;
+    return reinterpret_cast<T*>(d);
+}
+
+// Work items (problem, block) covering count_p elements per problem in blocks of 2048.
+std::vector<int4> elem_items(const std::vector<size_t>& counts) {
+    std::vector<int4> it;
+    for (size_t p = 0; p < counts.size(); ++p)
+        for (size_t blk = 0; blk * 2048 < counts[p]; ++blk) it.push_back(make_int4(static_cast<int>(p), static_cast<int>(blk), 0, 0));
+    return it;
+}
+
+Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd) {
+    Tiling t;
+    if (fwd) {
+        t.ppt = 2;
+        t.kc = 1;
+        t.threads = 384;
+        t.steps = 16;
+        return t;
+    }
+    t.ppt = 2;
+    t.kc = 2;
+    t.threads = 256;
+    t.steps = 16;
+    const Tiling& o = b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+    if (o.ppt > 0) t.ppt = o.ppt;
+    if (o.kc > 0) t.kc = o.kc;
+    if (o.threads > 0) t.threads = o.threads;
+    if (o.steps > 0) t.steps = o.steps;
+    return t;
+}
+
+int batch_tile(const Tiling& t, int n) {
+    RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0 && t.steps >= 1, RP4D_EINVAL,
+                 "batch tiling: threads must be a multiple of 64 in [64, 1024] and steps >= 1");
+    const int halo = 4 * t.steps + 4;
+    const int room = t.threads * t.ppt - 2 * halo;
+    RP4D_REQUIRE(room >= 1, RP4D_EINVAL, "batch tiling: threads * ppt too small for the halo of steps per launch");
+    return std::min(n, room);
+}
+
+// Batched Gram matrices: each descriptor's chunking and partial-sum buffer come
+// from its problem (rows per chunk depend on n only); `owner[i]` is the problem
+// whose ws_bg holds descriptor i's partials (one Gram per problem per call).
+template <typename TX, typename TY>
+void batch_gram(rp4d_batch* b, std::vector<BGram> gd, const std::vector<rp4d_problem*>& owner) {
+    std::vector<int4> items, ritems;
+    for (size_t i = 0; i < gd.size(); ++i) {
+        BGram& g = gd[i];
+        g.rows = std::max(64, ((g.n + 15) / 16 + 15) / 16 * 16);
+        const int nch = (g.n + g.rows - 1) / g.rows;
+        const size_t need = static_cast<size_t>(nch) * g.a * g.b * sizeof(double);
+        rp4d_problem* p = owner[i];
+        p->ws_bg.ensure(std::max(p->ws_bg.bytes, need));
+        g.part = p->ws_bg.as<double>();
+        const int tiles = ((g.a + 63) / 64) * ((g.b + 63) / 64);
+        for (int c = 0; c < nch; ++c)
+            for (int t = 0; t < tiles; ++t) items.push_back(make_int4(static_cast<int>(i), c, t, 0));
+        const size_t stride = static_cast<size_t>(g.a) * g.b;
+        for (size_t blk = 0; blk * 256 < stride; ++blk) ritems.push_back(make_int4(static_cast<int>(i), static_cast<int>(blk), 0, 0));
+    }
+    if (gd.empty()) return;
+    launch_bgram<TX, TY>(stage(b, gd), stage(b, items), static_cast<int>(items.size()), stage(b, ritems),
+                         static_cast<int>(ritems.size()), b->ctx->stream);
+}
+
+void check_batch_traj(const rp4d_problem* p, const rp4d_traj* tr) {
+    check_traj(p, tr);
+    RP4D_REQUIRE(tr->C == 1, RP4D_EINVAL, "batched sweeps need full trajectory storage (ckpt_every <= 1)");
+}
+
+// Fused FWD of every problem in `sel` (indices into b->probs): u_0 = x0[i].
+void batch_fwd_run(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const double*>& x0,
+                   const std::vector<rp4d_traj*>& trajs) {
+    hipStream_t st = b->ctx->stream;
+    const Tiling t = batch_tiling(b, MODE_TLM, RP4D_F64, true);
+    const int np = static_cast<int>(sel.size());
+    std::vector<double*> bufA(np), bufB(np);
+    int nl = 0;
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, (2 * static_cast<size_t>(p->n) + 512) * sizeof(double)));
+        bufA[i] = p->ws_red.as<double>();
+        bufB[i] = bufA[i] + p->n;
+        nl = std::max(nl, (p->s_last + t.steps - 1) / t.steps);
+    }
+    // initial state and trajectory row 0
+    {
+        std::vector<BCopy> cd;
+        std::vector<size_t> cnt;
+        for (int i = 0; i < np; ++i) {
+            rp4d_problem* p = b->probs[sel[i]];
+            cd.push_back(BCopy{x0[i], bufA[i], p->n, 1, 1, 1, 0});
+            cd.push_back(BCopy{x0[i], trajs[i]->states.as<double>(), p->n, 1, 1, 1, 0});
+            cnt.push_back(p->n);
+            cnt.push_back(p->n);
+        }
+        auto it = elem_items(cnt);
+        launch_bcopy<double, double>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+    }
+    std::vector<FwdArgs> args;
+    std::vector<int4> items;
+    std::vector<int> off(nl + 1, 0), aoff(nl + 1, 0);
+    for (int j = 0; j < nl; ++j) {
+        off[j] = static_cast<int>(items.size());
+        aoff[j] = static_cast<int>(args.size());
+        for (int i = 0; i < np; ++i) {
+            rp4d_problem* p = b->probs[sel[i]];
+            const int s0 = j * t.steps;
+            FwdArgs a{};
+            if (s0 < p->s_last) {
+                a.xin = (j % 2 == 0) ? bufA[i] : bufB[i];
+                a.xout = (j % 2 == 0) ? bufB[i] : bufA[i];
+                a.store = trajs[i]->states.as<double>();
+                a.store_every = 1;
+                a.store_row0 = 0;
+                a.store_rows = trajs[i]->rows;
+                a.n = p->n;
+                a.h = p->d.dt;
+                a.inv2dx = p->inv2dx;
+                a.nu_dx2 = p->nu_dx2;
+                a.s0 = s0;
+                a.S = std::min(t.steps, p->s_last - s0);
+                a.tile = batch_tile(t, p->n);
+                a.halo = 4 * t.steps + 4;
+                a.obs_stride = p->d.obs_stride;
+                a.obs_every = p->d.obs_every;
+                a.n_obs = p->n_obs;
+                a.n_t = p->n_t;
+                a.inv_sigma_o = 1.0 / p->d.sigma_o;
+                a.y = p->has_data ? p->y.as<double>() : nullptr;
+                a.innov = p->has_data ? trajs[i]->innov.as<double>() : nullptr;
+                a.obs_out = trajs[i]->innov.as<double>() + p->m;
+                const int ntile = (p->n + a.tile - 1) / a.tile;
+                for (int tl = 0; tl < ntile; ++tl)
+                    items.push_back(make_int4(static_cast<int>(args.size()) - aoff[j], tl, 0, 0));
+            } else {
+                a.n = p->n;  // inactive: no work items reference it
+            }
+            args.push_back(a);
+        }
+    }
+    off[nl] = static_cast<int>(items.size());
+    FwdArgs* dargs = stage(b, args);
+    int4* ditems = stage(b, items);
+    for (int j = 0; j < nl; ++j) {
+        KernelTimer kt(b->ctx, RP4D_K_FWD, 0.0);
+        launch_burgers_fwd_batched(dargs + aoff[j], ditems + off[j], off[j + 1] - off[j], t, st);
+    }
+    for (int i = 0; i < np; ++i) {
+        trajs[i]->valid = true;
+        trajs[i]->has_innov = b->probs[sel[i]]->has_data;
+        b->probs[sel[i]]->cnt.fwd += 1;
+    }
+}
+
+// Fused TLM (mode MODE_TLM) or ADJ sweeps of k vectors for the problems in sel.
+// TLM: in[i] holds Gamma^{1/2} V (blocked kc), z[i] receives (n_t, n_obs, k).
+// ADJ: forcing w[i]; returns the buffer holding lambda_0 for each problem.
+template <typename T>
+std::vector<T*> batch_sweep_run(rp4d_batch* b, int mode, const std::vector<int>& sel,
+                                const std::vector<const rp4d_traj*>& trajs, int k, const Tiling& t,
+                                const std::vector<T*>& buf0, const std::vector<T*>& buf1,
+                                const std::vector<T*>& z, const std::vector<const T*>& w) {
+    hipStream_t st = b->ctx->stream;
+    const int np = static_cast<int>(sel.size());
+    const int groups = (k + t.kc - 1) / t.kc;
+    int nl = 0;
+    for (int i = 0; i < np; ++i) nl = std::max(nl, (b->probs[sel[i]]->s_last + t.steps - 1) / t.steps);
+    if (mode == MODE_ADJ) {
+        std::vector<BCopy> cd;
+        std::vector<size_t> cnt;
+        for (int i = 0; i < np; ++i) {
+            rp4d_problem* p = b->probs[sel[i]];
+            cd.push_back(BCopy{nullptr, buf0[i], p->n, groups * t.kc, 1, 1, 1});
+            cnt.push_back(static_cast<size_t>(p->n) * groups * t.kc);
+        }
+        auto it = elem_items(cnt);
+        launch_bcopy<T, T>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+    }
+    std::vector<SweepArgs<T>> args;
+    std::vector<int4> items;
+    std::vector<int> off(nl + 1, 0), aoff(nl + 1, 0);
+    std::vector<double> flops(nl, 0.0);
+    std::vector<T*> result(np);
+    for (int j = 0; j < nl; ++j) {
+        off[j] = static_cast<int>(items.size());
+        aoff[j] = static_cast<int>(args.size());
+        for (int i = 0; i < np; ++i) {
+            rp4d_problem* p = b->probs[sel[i]];
+            const int nlp = (p->s_last + t.steps - 1) / t.steps;
+            SweepArgs<T> a{};
+            a.n = p->n;
+            if (j < nlp) {
+                a.base = trajs[i]->states.as<double>();
+                a.base_row0 = 0;
+                a.h = static_cast<T>(p->d.dt);
+                a.inv2dx = static_cast<T>(p->inv2dx);
+                a.nu_dx2 = static_cast<T>(p->nu_dx2);
+                if (mode == MODE_TLM) {
+                    a.s0 = j * t.steps;
+                    a.S = std::min(t.steps, p->s_last - a.s0);
+                } else {
+                    const int s_hi = p->s_last - j * t.steps;
+                    a.s0 = std::max(0, s_hi - t.steps);
+                    a.S = s_hi - a.s0;
+                }
+                a.tile = batch_tile(t, p->n);
+                a.halo = 4 * t.steps + 4;
+                a.k = k;
+                a.xin = (j % 2 == 0) ? buf0[i] : buf1[i];
+                a.xout = (j % 2 == 0) ? buf1[i] : buf0[i];
+                a.obs_stride = p->d.obs_stride;
+                a.obs_every = p->d.obs_every;
+                a.n_obs = p->n_obs;
+                a.n_t = p->n_t;
+                a.inv_sigma_o = static_cast<T>(1.0 / p->d.sigma_o);
+                a.z = mode == MODE_TLM ? z[i] : nullptr;
+                a.w = mode == MODE_ADJ ? w[i] : nullptr;
+                const int ntile = (p->n + a.tile - 1) / a.tile;
+                for (int g = 0; g < groups; ++g)
+                    for (int tl = 0; tl < ntile; ++tl)
+                        items.push_back(make_int4(static_cast<int>(args.size()) - aoff[j], tl, g, 0));
+                flops[j] += static_cast<double>(a.S) * p->n *
+                            (mode == MODE_TLM ? (FL_TLM_VEC * k + FL_TLM_BASE) : (FL_ADJ_VEC * k + FL_ADJ_BASE));
+                if (j == nlp - 1) result[i] = a.xout;
+            }
+            args.push_back(a);
+        }
+    }
+    off[nl] = static_cast<int>(items.size());
+    SweepArgs<T>* dargs = stage(b, args);
+    int4* ditems = stage(b, items);
+    for (int j = 0; j < nl; ++j) {
+        KernelTimer kt(b->ctx, mode == MODE_TLM ? RP4D_K_TLM : RP4D_K_ADJ, flops[j]);
+        launch_burgers_sweep_batched<T>(mode, dargs + aoff[j], ditems + off[j], off[j + 1] - off[j], t, st);
+    }
+    for (int i = 0; i < np; ++i)
+        if (!result[i]) result[i] = buf0[i];  // no steps: state unchanged
+    return result;
+}
+
+// Gamma^{1/2} for every selected problem: out[i] (layout out_kc) = Gamma^{1/2} in[i]
+// (layout in_kc) (+ addv[i]).  Spectral problems in one batched Gram + GEMM pair.
+template <typename T>
+void batch_bhalf(rp4d_batch* b, const std::vector<int>& sel, int k, const std::vector<const T*>& in, int in_kc,
+                 const std::vector<T*>& out, int out_kc, const std::vector<const T*>& addv) {
+    hipStream_t st = b->ctx->stream;
+    std::vector<BGram> gd;
+    std::vector<rp4d_problem*> gown;
+    std::vector<BTsmm> md;
+    std::vector<int4> items;
+    for (size_t i = 0; i < sel.size(); ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        if (!p->spec) {
+            bhalf_into<T>(p, k, in[i], in_kc, out[i], out_kc, addv[i]);
+            continue;
+        }
+        p->ws_bh.ensure(std::max<size_t>(p->ws_bh.bytes, static_cast<size_t>(p->r) * k * sizeof(double)));
+        double* Tm = p->ws_bh.as<double>();
+        gd.push_back(BGram{p->F.as<double>(), in[i], Tm, p->n, p->r, k, p->r, in_kc, 0, nullptr});
+        gown.push_back(p);
+        const int pi = static_cast<int>(md.size());
+        md.push_back(BTsmm{p->F.as<double>(), Tm, p->lamF.as<double>(), addv[i], out[i], p->n, p->r, k, p->r, out_kc,
+                           out_kc, 1.0, addv[i] ? 1.0 : 0.0});
+        for (int rb = 0; rb * 64 < p->n; ++rb)
+            for (int cb = 0; cb * 64 < k; ++cb) items.push_back(make_int4(pi, rb, cb, 0));
+    }
+    if (gd.empty()) return;
+    batch_gram<double, T>(b, gd, gown);
+    launch_btsmm<double, T>(stage(b, md), stage(b, items), static_cast<int>(items.size()), st);
+}
+
+// Workspace of the batched block sweeps of problem p for k vectors.
+template <typename T>
+void batch_ensure_ws(rp4d_problem* p, int k, int kc) {
+    const size_t blk = static_cast<size_t>((k + kc - 1) / kc + 1) * kc * p->n * sizeof(T);
+    p->ws_s0.ensure(std::max(p->ws_s0.bytes, blk));
+    p->ws_s1.ensure(std::max(p->ws_s1.bytes, blk));
+    p->ws_obs.ensure(std::max(p->ws_obs.bytes, static_cast<size_t>(p->m) * k * sizeof(T)));
+}
+
+// HV[i] = (add_identity ? V[i] : 0) + H_i V[i] for the selected problems.
+template <typename T>
+void batch_hessian(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs, int k,
+                   const std::vector<const T*>& V, const std::vector<T*>& HV, bool add_identity) {
+    hipStream_t st = b->ctx->stream;
+    const int dt = sizeof(T) == 8 ? RP4D_F64 : RP4D_F32;
+    Tiling tt = batch_tiling(b, MODE_TLM, dt, false), ta = batch_tiling(b, MODE_ADJ, dt, false);
+    while (tt.kc > 1 && tt.kc > k) tt.kc /= 2;   // no padded vectors for small k
+    while (ta.kc > 1 && ta.kc > k) ta.kc /= 2;
+    const int np = static_cast<int>(sel.size());
+    std::vector<T*> s0(np), s1(np), obs(np);
+    std::vector<const T*> cobs(np), none(np, nullptr);
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        batch_ensure_ws<T>(p, k, std::max(tt.kc, ta.kc));
+        s0[i] = p->ws_s0.as<T>();
+        s1[i] = p->ws_s1.as<T>();
+        obs[i] = p->ws_obs.as<T>();
+        cobs[i] = obs[i];
+    }
+    const int gt = (k + tt.kc - 1) / tt.kc;
+    if (gt * tt.kc != k) {
+        std::vector<BCopy> cd;
+        std::vector<size_t> cnt;
+        for (int i = 0; i < np; ++i) {
+            cd.push_back(BCopy{nullptr, s0[i], b->probs[sel[i]]->n, gt * tt.kc, 1, 1, 1});
+            cnt.push_back(static_cast<size_t>(b->probs[sel[i]]->n) * gt * tt.kc);
+        }
+        auto it = elem_items(cnt);
+        launch_bcopy<T, T>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+    }
+    batch_bhalf<T>(b, sel, k, V, k, s0, tt.kc, none);
+    batch_sweep_run<T>(b, MODE_TLM, sel, trajs, k, tt, s0, s1, obs, none);
+    std::vector<T*> lam = batch_sweep_run<T>(b, MODE_ADJ, sel, trajs, k, ta, s0, s1, obs, cobs);
+    std::vector<const T*> clam(lam.begin(), lam.end());
+    std::vector<const T*> add(np, nullptr);
+    if (add_identity) add = V;
+    batch_bhalf<T>(b, sel, k, clam, ta.kc, HV, k, add);
+    for (int i = 0; i < np; ++i) b->probs[sel[i]]->cnt.hv_columns += k;
+}
+
+// Batched gradient g[i] = v[i] + A_i^T d_i (FP64, one ADJ sweep per problem).
+void batch_gradient(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs,
+                    const std::vector<const double*>& v, const std::vector<double*>& g) {
+    const Tiling ta = batch_tiling(b, MODE_ADJ, RP4D_F64, false);
+    Tiling t1 = ta;
+    t1.kc = 1;
+    const int np = static_cast<int>(sel.size());
+    std::vector<double*> s0(np), s1(np);
+    std::vector<const double*> w(np), none(np, nullptr);
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        batch_ensure_ws<double>(p, 1, 1);
+        s0[i] = p->ws_s0.as<double>();
+        s1[i] = p->ws_s1.as<double>();
+        w[i] = trajs[i]->innov.as<double>();
+    }
+    std::vector<double*> lam = batch_sweep_run<double>(b, MODE_ADJ, sel, trajs, 1, t1, s0, s1, {}, w);
+    std::vector<const double*> clam(lam.begin(), lam.end());
+    batch_bhalf<double>(b, sel, 1, clam, 1, g, 1, v);
+    for (int i = 0; i < np; ++i) b->probs[sel[i]]->cnt.adj_online += 1;
+}
+
+// Batched preconditioner application z = P_i r (k = 1); pcs[i] may be null (copy).
+void batch_precond_apply(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_precond*>& pcs,
+                         const std::vector<const double*>& r, const std::vector<double*>& z) {
+    hipStream_t st = b->ctx->stream;
+    std::vector<BGram> gd;
+    std::vector<rp4d_problem*> gown;
+    std::vector<BTsmm> md;
+    std::vector<int4> items;
+    std::vector<BCopy> cd;
+    std::vector<size_t> cnt;
+    for (size_t i = 0; i < sel.size(); ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        const rp4d_precond* pc = pcs[i];
+        if (!pc) {
+            cd.push_back(BCopy{r[i], z[i], p->n, 1, 1, 1, 0});
+            cnt.push_back(p->n);
+            continue;
+        }
+        const int l = pc->ell;
+        p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, (2 * static_cast<size_t>(p->n) + 512 + l) * sizeof(double)));
+        double* T = p->ws_red.as<double>() + 2 * p->n + 512;
+        gd.push_back(BGram{pc->V.as<double>(), r[i], T, p->n, l, 1, l, 1, 0, nullptr});
+        gown.push_back(p);
+        const int pi = static_cast<int>(md.size());
+        md.push_back(BTsmm{pc->V.as<double>(), T, pc->Dg.as<double>(), r[i], z[i], p->n, l, 1, l, 1, 1, -1.0, 1.0});
+        for (int rb = 0; rb * 64 < p->n; ++rb) items.push_back(make_int4(pi, rb, 0, 0));
+    }
+    if (!cd.empty()) {
+        auto it = elem_items(cnt);
+        launch_bcopy<double, double>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+    }
+    if (!gd.empty()) {
+        batch_gram<double, double>(b, gd, gown);
+        launch_btsmm<double, double>(stage(b, md), stage(b, items), static_cast<int>(items.size()), st);
+    }
+}
+
+// Batched dot products into the batch scalar array slot `slot` of each problem.
+void batch_dot(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const double*>& x,
+               const std::vector<const double*>& y, int slot, bool absmax = false) {
+    std::vector<BVec> vd;
+    for (size_t i = 0; i < sel.size(); ++i)
+        vd.push_back(BVec{x[i], y[i], b->scal.as<double>() + 16 * sel[i] + slot, b->probs[sel[i]]->n});
+    launch_bdot(stage(b, vd), static_cast<int>(vd.size()), absmax, b->ctx->stream);
+}
+
+std::vector<double> batch_read_scal(rp4d_batch* b) {
+    std::vector<double> h(16 * b->probs.size());
+    RP4D_HIP(hipMemcpyAsync(h.data(), b->scal.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, b->ctx->stream));
+    RP4D_HIP(hipStreamSynchronize(b->ctx->stream));
+    return h;
+}
+
+void batch_axpby(rp4d_batch* b, std::vector<BAxpby> ad) {
+    std::vector<size_t> cnt;
+    for (auto& a : ad) cnt.push_back(a.count);
+    auto it = elem_items(cnt);
+    launch_baxpby(stage(b, ad), stage(b, it), static_cast<int>(it.size()), b->ctx->stream);
+}
+
+// Batched lockstep PCG (FP64) on (I + H_i) x_i = b_i; returns per-problem iterations.
+std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs,
+                           const std::vector<const rp4d_precond*>& pcs, const std::vector<const double*>& rhs,
+                           const std::vector<double*>& x, double rtol, int maxit, std::vector<int>& conv) {
+    hipStream_t st = b->ctx->stream;
+    const int np = static_cast<int>(sel.size());
+    std::vector<double*> r(np), z(np), pv(np), q(np);
+    std::vector<BPcg> pd(np);
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        p->ws_pcg.ensure(std::max<size_t>(p->ws_pcg.bytes, (5 * static_cast<size_t>(p->n) + 1024) * sizeof(double)));
+        r[i] = p->ws_pcg.as<double>();
+        z[i] = r[i] + p->n;
+        pv[i] = z[i] + p->n;
+        q[i] = pv[i] + p->n;
+        pd[i] = BPcg{x[i], r[i], pv[i], q[i], z[i], b->scal.as<double>() + 16 * sel[i], p->n};
+    }
+    {
+        std::vector<BAxpby> ad;
+        for (int i = 0; i < np; ++i) {
+            ad.push_back(BAxpby{nullptr, x[i], static_cast<size_t>(b->probs[sel[i]]->n), 0.0, nullptr, 0.0});
+            ad.push_back(BAxpby{rhs[i], r[i], static_cast<size_t>(b->probs[sel[i]]->n), 1.0, nullptr, 0.0});
+        }
+        batch_axpby(b, ad);
+    }
+    std::vector<const double*> cr(r.begin(), r.end()), cz(z.begin(), z.end()), cp(pv.begin(), pv.end()),
+        cq(q.begin(), q.end());
+    batch_precond_apply(b, sel, pcs, cr, z);
+    {
+        std::vector<BAxpby> ad;
+        for (int i = 0; i < np; ++i) ad.push_back(BAxpby{z[i], pv[i], static_cast<size_t>(b->probs[sel[i]]->n), 1.0, nullptr, 0.0});
+        batch_axpby(b, ad);
+    }
+    batch_dot(b, sel, cr, cz, SC_RZ);
+    batch_dot(b, sel, rhs, rhs, SC_BB);
+    std::vector<double> sc = batch_read_scal(b);
+    std::vector<double> bnorm(np);
+    std::vector<int> iters(np, 0);
+    conv.assign(np, 0);
+    std::vector<int> act;
+    for (int i = 0; i < np; ++i) {
+        bnorm[i] = std::sqrt(sc[16 * sel[i] + SC_BB]);
+        RP4D_REQUIRE(std::isfinite(bnorm[i]), RP4D_ENONFINITE, "non-finite right-hand side in batch");
+        if (bnorm[i] == 0.0)
+            conv[i] = 1;
+        else
+            act.push_back(i);
+    }
+    if (maxit <= 0) {
+        maxit = 1;
+        for (int i = 0; i < np; ++i) maxit = std::max(maxit, b->probs[sel[i]]->n);
+    }
+    for (int it = 0; it < maxit && !act.empty(); ++it) {
+        std::vector<int> asel;
+        std::vector<const rp4d_traj*> atr;
+        std::vector<const double*> ap;
+        std::vector<double*> aq;
+        std::vector<const rp4d_precond*> apc;
+        std::vector<BPcg> apd;
+        std::vector<size_t> cnt;
+        for (int i : act) {
+            asel.push_back(sel[i]);
+            atr.push_back(trajs[i]);
+            ap.push_back(pv[i]);
+            aq.push_back(q[i]);
+            apc.push_back(pcs[i]);
+            apd.push_back(pd[i]);
+            cnt.push_back(b->probs[sel[i]]->n);
+        }
+        batch_hessian<double>(b, asel, atr, 1, ap, aq, true);
+        std::vector<const double*> caq(aq.begin(), aq.end());
+        batch_dot(b, asel, ap, caq, SC_PQ);
+        auto items = elem_items(cnt);
+        BPcg* dpd = stage(b, apd);
+        int4* dit = stage(b, items);
+        launch_bpcg_xr(dpd, dit, static_cast<int>(items.size()), st);
+        std::vector<const double*> ar, az;
+        std::vector<double*> azm;
+        for (int i : act) {
+            ar.push_back(r[i]);
+            az.push_back(z[i]);
+            azm.push_back(z[i]);
+        }
+        batch_dot(b, asel, ar, ar, SC_RR);
+        std::vector<double> s2 = batch_read_scal(b);
+        std::vector<int> still;
+        std::vector<int> ssel;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int i = act[a];
+            iters[i] += 1;
+            const double rn = std::sqrt(s2[16 * sel[i] + SC_RR]);
+            RP4D_REQUIRE(std::isfinite(rn), RP4D_ENONFINITE, "non-finite PCG residual in batch");
+            if (rn <= rtol * bnorm[i])
+                conv[i] = 1;
+            else
+                still.push_back(i);
+        }
+        if (still.empty()) break;
+        // z = P r, rz_new = r.z, p = z + beta p for problems still iterating
+        std::vector<int> ssel2;
+        std::vector<const rp4d_precond*> spc;
+        std::vector<const double*> sr;
+        std::vector<double*> sz;
+        std::vector<BPcg> spd;
+        std::vector<size_t> scnt;
+        for (int i : still) {
+            ssel2.push_back(sel[i]);
+            spc.push_back(pcs[i]);
+            sr.push_back(r[i]);
+            sz.push_back(z[i]);
+            spd.push_back(pd[i]);
+            scnt.push_back(b->probs[sel[i]]->n);
+        }
+        batch_precond_apply(b, ssel2, spc, sr, sz);
+        std::vector<const double*> csz(sz.begin(), sz.end());
+        batch_dot(b, ssel2, sr, csz, SC_RZN);
+        auto sitems = elem_items(scnt);
+        launch_bpcg_p(stage(b, spd), stage(b, sitems), static_cast<int>(sitems.size()),
+                      static_cast<int>(spd.size()), st);
+        act = still;
+    }
+    for (int i = 0; i < np; ++i) {
+        b->probs[sel[i]]->cnt.tlm_online += iters[i];
+        b->probs[sel[i]]->cnt.adj_online += iters[i];
+    }
+    return iters;
+}
+
+// Batched Nystrom sketches (Alg. 2) for the selected problems (uniform l), Omega
+// from Philox with seed ^ problem index.  Returns new preconditioners.
+std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& sel,
+                                          const std::vector<const rp4d_traj*>& trajs, int l, uint64_t seed, int dtype) {
+    hipStream_t st = b->ctx->stream;
+    const int np = static_cast<int>(sel.size());
+    std::vector<Scratch> S(np);
+    for (int i = 0; i < np; ++i) S[i] = sketch_scratch(b->probs[sel[i]], l, dtype);
+    // Omega
+    {
+        std::vector<BRand> rd;
+        std::vector<size_t> cnt;
+        for (int i = 0; i < np; ++i) {
+            const size_t c = static_cast<size_t>(b->probs[sel[i]]->n) * l;
+            rd.push_back(BRand{S[i].Om, c, seed ^ (0x9E3779B97F4A7C15ULL * (b->probs[sel[i]]->id + 1))});
+            cnt.push_back((c + 1) / 2);
+        }
+        auto it = elem_items(cnt);
+        launch_bphilox(stage(b, rd), stage(b, it), static_cast<int>(it.size()), st);
+    }
+    auto copyall = [&](auto tag_in, auto tag_out, auto src, auto dst, bool rows_m) {
+        using TI = decltype(tag_in);
+        using TO = decltype(tag_out);
+        std::vector<BCopy> cd;
+        std::vector<size_t> cnt;
+        for (int i = 0; i < np; ++i) {
+            rp4d_problem* p = b->probs[sel[i]];
+            const int rows = rows_m ? p->m : p->n;
+            cd.push_back(BCopy{src(i), dst(i), rows, l, l, l, 0});
+            cnt.push_back(static_cast<size_t>(rows) * l);
+        }
+        auto it = elem_items(cnt);
+        launch_bcopy<TI, TO>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+    };
+    // Y0 = H Omega (data-misfit part) in the sketch precision, kept as FP64 in Yd
+    if (dtype == RP4D_F64) {
+        std::vector<const double*> om(np);
+        std::vector<double*> y(np);
+        for (int i = 0; i < np; ++i) {
+            om[i] = S[i].Om;
+            y[i] = S[i].Yd;
+        }
+        batch_hessian<double>(b, sel, trajs, l, om, y, false);
+    } else {
+        copyall(double(), float(), [&](int i) { return static_cast<const void*>(S[i].Om); },
+                [&](int i) { return S[i].Omt; }, false);
+        std::vector<const float*> om(np);
+        std::vector<float*> y(np);
+        for (int i = 0; i < np; ++i) {
+            om[i] = static_cast<const float*>(S[i].Omt);
+            y[i] = static_cast<float*>(S[i].Yt);
+        }
+        batch_hessian<float>(b, sel, trajs, l, om, y, false);
+        copyall(float(), double(), [&](int i) { return static_cast<const void*>(S[i].Yt); },
+                [&](int i) { return static_cast<void*>(S[i].Yd); }, false);
+    }
+    std::vector<BSmall> sm(np);
+    std::vector<BSketch> sk(np);
+    std::vector<BGram> gd(np);
+    std::vector<rp4d_problem*> owners(np);
+    for (int i = 0; i < np; ++i) owners[i] = b->probs[sel[i]];
+    // nu = sqrt(n) eps ||Y||_2
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        gd[i] = BGram{S[i].Yd, S[i].Yd, S[i].S2, p->n, l, l, l, l, 0, nullptr};
+        sm[i] = BSmall{S[i].S2, nullptr, S[i].ev, nullptr};
+        sk[i] = BSketch{S[i].ev, S[i].nu, S[i].lam, S[i].D, S[i].S2, p->n};
+    }
+    batch_gram<double, double>(b, gd, owners);
+    launch_bjacobi(stage(b, sm), np, l, false, st);
+    const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    BSketch* dsk = stage(b, sk);
+    launch_bnu(dsk, np, eps, st);
+    // shifted core matrix and its Cholesky factor, with tenfold shift retries
+    std::vector<int> todo(np);
+    for (int i = 0; i < np; ++i) todo[i] = i;
+    for (int attempt = 0; attempt <= 3 && !todo.empty(); ++attempt) {
+        std::vector<BAxpby> ad;
+        std::vector<BGram> cg;
+        std::vector<BSmall> cs;
+        for (int i : todo) {
+            rp4d_problem* p = b->probs[sel[i]];
+            const size_t c = static_cast<size_t>(p->n) * l;
+            ad.push_back(BAxpby{S[i].Yd, S[i].Y2, c, 1.0, nullptr, 0.0});
+            ad.push_back(BAxpby{S[i].Om, S[i].Y2, c, 1.0, S[i].nu, 1.0});
+            cg.push_back(BGram{S[i].Om, S[i].Y2, S[i].S2, p->n, l, l, l, l, 0, nullptr});
+            cs.push_back(BSmall{S[i].S2, nullptr, nullptr, S[i].info});
+        }
+        // two passes so that Y2 = Yd is complete before the shift is added
+        std::vector<BAxpby> a1, a2;
+        for (size_t q = 0; q < ad.size(); q += 2) {
+            a1.push_back(ad[q]);
+            a2.push_back(ad[q + 1]);
+        }
+        batch_axpby(b, a1);
+        batch_axpby(b, a2);
+        std::vector<rp4d_problem*> cown;
+        for (int i : todo) cown.push_back(b->probs[sel[i]]);
+        batch_gram<double, double>(b, cg, cown);
+        launch_bchol(stage(b, cs), static_cast<int>(cs.size()), l, st);
+        std::vector<int> failed;
+        std::vector<int> infos(todo.size(), 0);
+        for (size_t q = 0; q < todo.size(); ++q)
+            RP4D_HIP(hipMemcpyAsync(&infos[q], S[todo[q]].info, sizeof(int), hipMemcpyDeviceToHost, st));
+        RP4D_HIP(hipStreamSynchronize(st));
+        for (size_t q = 0; q < todo.size(); ++q)
+            if (infos[q] != 0) failed.push_back(todo[q]);
+        for (int i : failed) {
+            std::vector<BAxpby> sc1{BAxpby{nullptr, S[i].nu, 1, 0.0, nullptr, 10.0}};
+            batch_axpby(b, sc1);
+        }
+        todo = failed;
+    }
+    RP4D_REQUIRE(todo.empty(), RP4D_ENOTSPD, "Nystrom core matrix not positive definite after shift retries (batch)");
+    // W W^T = L^{-1} (Y^T Y) L^{-T}; eig; V = Y L^{-T} U Sigma^{-1}
+    std::vector<BSmall> t1(np), g1(np), g2(np), ej(np), g3(np);
+    std::vector<BGram> yy(np);
+    std::vector<BTsmm> vm(np);
+    std::vector<int4> vit;
+    std::vector<rp4d_precond*> out(np, nullptr);
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        t1[i] = BSmall{S[i].S2, S[i].S3, nullptr, nullptr};         // S3 = L^{-1}
+        yy[i] = BGram{S[i].Y2, S[i].Y2, S[i].S4, p->n, l, l, l, l, 0, nullptr};  // S4 = Y^T Y
+        g1[i] = BSmall{S[i].S3, S[i].S4, S[i].S2, nullptr};         // S2 = L^{-1} Y^T Y
+        g2[i] = BSmall{S[i].S2, S[i].S3, S[i].S4, nullptr};         // S4 = S2 L^{-T}
+        ej[i] = BSmall{S[i].S4, S[i].S2, S[i].ev, nullptr};         // ev, U = S2
+        g3[i] = BSmall{S[i].S3, S[i].S2, S[i].S4, nullptr};         // S4 = L^{-T} U Sigma^{-1}
+        auto* pc = new rp4d_precond();
+        pc->p = p;
+        pc->ell = l;
+        pc->V.ensure(static_cast<size_t>(p->n) * l * sizeof(double));
+        pc->Dg.ensure(static_cast<size_t>(l) * sizeof(double));
+        out[i] = pc;
+        vm[i] = BTsmm{S[i].Y2, S[i].S4, nullptr, nullptr, pc->V.p, p->n, l, l, l, l, l, 1.0, 0.0};
+        for (int rb = 0; rb * 64 < p->n; ++rb)
+            for (int cb = 0; cb * 64 < l; ++cb) vit.push_back(make_int4(i, rb, cb, 0));
+    }
+    try {
+        launch_btrinv(stage(b, t1), np, l, st);
+        batch_gram<double, double>(b, yy, owners);
+        launch_bgemm_small(stage(b, g1), np, l, 0, 0, 1.0, st);
+        launch_bgemm_small(stage(b, g2), np, l, 0, 1, 1.0, st);
+        launch_bjacobi(stage(b, ej), np, l, true, st);
+        launch_bfinalize(dsk, np, l, true, st);  // lam, D and U <- U diag(1/sigma)
+        launch_bgemm_small(stage(b, g3), np, l, 1, 0, 1.0, st);
+        launch_btsmm<double, double>(stage(b, vm), stage(b, vit), static_cast<int>(vit.size()), st);
+        std::vector<double> nuh(np);
+        for (int i = 0; i < np; ++i) {
+            launch_relayout<double, double>(S[i].D, 1, out[i]->Dg.as<double>(), 1, l, 1, st);
+            out[i]->lam.resize(l);
+            RP4D_HIP(hipMemcpyAsync(out[i]->lam.data(), S[i].lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
+            RP4D_HIP(hipMemcpyAsync(&nuh[i], S[i].nu, sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        RP4D_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < np; ++i) {
+            out[i]->nu = nuh[i];
+            for (double v : out[i]->lam) RP4D_REQUIRE(std::isfinite(v), RP4D_ENONFINITE, "non-finite sketch (batch)");
+            b->probs[sel[i]]->cnt.tlm_offline += l;
+            b->probs[sel[i]]->cnt.adj_offline += l;
+            b->probs[sel[i]]->cnt.sketches += 1;
+        }
+    } catch (...) {
+        for (auto* pc : out) delete pc;
+        throw;
+    }
+    return out;
+}
+
+}  // namespace
+}  // namespace rp4d
+
+extern "C" {
+
+int rp4d_batch_create(rp4d_ctx* ctx, int nprob, rp4d_problem* const* probs, rp4d_batch** out) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr && out != nullptr && probs != nullptr && nprob >= 1, RP4D_EINVAL, "bad argument");
+        set_device(ctx);
+        auto* b = new rp4d_batch();
+        try {
+            b->ctx = ctx;
+            for (int i = 0; i < nprob; ++i) {
+                RP4D_REQUIRE(probs[i] != nullptr && probs[i]->ctx == ctx, RP4D_EINVAL,
+                             "batch problems must share the context");
+                RP4D_REQUIRE(probs[i]->d.model == RP4D_BURGERS1D, RP4D_EINVAL, "batches hold Burgers problems");
+                b->probs.push_back(probs[i]);
+            }
+            b->cap = 32u << 20;
+            RP4D_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->host), b->cap, hipHostMallocDefault));
+            b->dev.ensure(b->cap);
+            b->scal.ensure(16 * sizeof(double) * nprob);
+        } catch (...) {
+            delete b;
+            throw;
+        }
+        *out = b;
+    });
+}
+
+int rp4d_batch_destroy(rp4d_batch* b) {
+    return guarded([&] {
+        if (b) {
+            set_device(b->ctx);
+            (void)hipStreamSynchronize(b->ctx->stream);
+        }
+        delete b;
+    });
+}
+
+int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps) {
+    return guarded([&] {
+        RP4D_REQUIRE(b != nullptr && (mode == MODE_TLM || mode == MODE_ADJ) &&
+                         (dtype == RP4D_F64 || dtype == RP4D_F32), RP4D_EINVAL, "bad argument");
+        Tiling& t = b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+        t.ppt = ppt;
+        t.kc = kc;
+        t.threads = threads;
+        t.steps = steps;
+    });
+}
+
+int rp4d_batch_fwd(rp4d_batch* b, const double* const* x0, rp4d_traj* const* trajs, double* J_obs) {
+    return guarded([&] {
+        RP4D_REQUIRE(b != nullptr && x0 != nullptr && trajs != nullptr, RP4D_EINVAL, "null argument");
+        set_device(b->ctx);
+        const int np = static_cast<int>(b->probs.size());
+        std::vector<int> sel(np);
+        std::vector<const double*> xs(np);
+        std::vector<rp4d_traj*> tr(np);
+        for (int i = 0; i < np; ++i) {
+            sel[i] = i;
+            xs[i] = x0[i];
+            tr[i] = trajs[i];
+            RP4D_REQUIRE(tr[i] && tr[i]->p == b->probs[i] && tr[i]->C == 1, RP4D_EINVAL,
+                         "batch trajectories must match the problems and store every state");
+        }
+        batch_fwd_run(b, sel, xs, tr);
+        if (J_obs) {
+            std::vector<const double*> in(np);
+            for (int i = 0; i < np; ++i) {
+                RP4D_REQUIRE(b->probs[i]->has_data, RP4D_ESTATE, "J requested but data not set");
+                in[i] = tr[i]->innov.as<double>();
+            }
+            std::vector<BVec> vd;
+            for (int i = 0; i < np; ++i) vd.push_back(BVec{in[i], in[i], b->scal.as<double>() + 16 * i + SC_T0, b->probs[i]->m});
+            launch_bdot(stage(b, vd), np, false, b->ctx->stream);
+            std::vector<double> sc = batch_read_scal(b);
+            for (int i = 0; i < np; ++i) J_obs[i] = 0.5 * sc[16 * i + SC_T0];
+        }
+    });
+}
+
+int rp4d_batch_hessian_block(rp4d_batch* b, rp4d_traj* const* trajs, int k, const void* const* V, void* const* HV,
+                             int dtype, int add_identity) {
+    return guarded([&] {
+        RP4D_REQUIRE(b != nullptr && trajs != nullptr && V != nullptr && HV != nullptr && k >= 1 && k <= 4096,
+                     RP4D_EINVAL, "bad argument");
+        set_device(b->ctx);
+        const int np = static_cast<int>(b->probs.size());
+        std::vector<int> sel(np);
+        std::vector<const rp4d_traj*> tr(np);
+        for (int i = 0; i < np; ++i) {
+            sel[i] = i;
+            tr[i] = trajs[i];
+            check_batch_traj(b->probs[i], tr[i]);
+            RP4D_REQUIRE(V[i] != nullptr && HV[i] != nullptr && V[i] != HV[i], RP4D_EINVAL, "bad block pointer");
+        }
+        if (dtype == RP4D_F64) {
+            std::vector<const double*> v(np);
+            std::vector<double*> h(np);
+            for (int i = 0; i < np; ++i) {
+                v[i] = static_cast<const double*>(V[i]);
+                h[i] = static_cast<double*>(HV[i]);
+            }
+            batch_hessian<double>(b, sel, tr, k, v, h, add_identity != 0);
+        } else if (dtype == RP4D_F32) {
+            std::vector<const float*> v(np);
+            std::vector<float*> h(np);
+            for (int i = 0; i < np; ++i) {
+                v[i] = static_cast<const float*>(V[i]);
+                h[i] = static_cast<float*>(HV[i]);
+            }
+            batch_hessian<float>(b, sel, tr, k, v, h, add_identity != 0);
+        } else {
+            fail(RP4D_EINVAL, "bad dtype");
+        }
+    });
+}
+
+int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_gn_opts* o, rp4d_gn_info* infos) {
+    return guarded([&] {
+        RP4D_REQUIRE(b != nullptr && states != nullptr && o != nullptr, RP4D_EINVAL, "null argument");
+        RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_NOPREC, RP4D_EINVAL,
+                     "batched GN step supports Nystrom sketches or no preconditioner");
+        RP4D_REQUIRE(o->omega == nullptr, RP4D_EINVAL, "batched GN step draws Omega on the device (omega must be NULL)");
+        set_device(b->ctx);
+        hipStream_t st = b->ctx->stream;
+        const int np = static_cast<int>(b->probs.size());
+        std::vector<int> sel(np);
+        std::vector<rp4d_traj*> tr(np);
+        std::vector<const rp4d_traj*> ctr(np);
+        std::vector<const double*> x(np), v(np), xb(np), g(np);
+        std::vector<double*> gm(np), bm(np), dv(np), vm(np), xm(np);
+        for (int i = 0; i < np; ++i) {
+            rp4d_gn_state* s = states[i];
+            RP4D_REQUIRE(s != nullptr && s->p == b->probs[i], RP4D_EINVAL, "GN state does not match the batch problem");
+            RP4D_REQUIRE(s->traj->C == 1, RP4D_EINVAL, "batched GN step needs full trajectory storage");
+            sel[i] = i;
+            tr[i] = s->traj;
+            ctr[i] = s->traj;
+            x[i] = s->x.as<double>();
+            v[i] = s->v.as<double>();
+            xb[i] = b->probs[i]->xb.as<double>();
+            gm[i] = s->g.as<double>();
+            g[i] = gm[i];
+            bm[i] = s->b.as<double>();
+            dv[i] = s->dv.as<double>();
+            vm[i] = s->v.as<double>();
+            xm[i] = s->x.as<double>();
+        }
+        std::vector<rp4d_gn_info> inf(np);
+        // 1. FWD, J
+        batch_fwd_run(b, sel, x, tr);
+        {
+            std::vector<BVec> vd;
+            for (int i = 0; i < np; ++i) {
+                const double* in = tr[i]->innov.as<double>();
+                vd.push_back(BVec{in, in, b->scal.as<double>() + 16 * i + SC_T0, b->probs[i]->m});
+                vd.push_back(BVec{v[i], v[i], b->scal.as<double>() + 16 * i + SC_T2, b->probs[i]->n});
+            }
+            launch_bdot(stage(b, vd), static_cast<int>(vd.size()), false, st);
+        }
+        // 2. gradient, |g|_inf, b = -g
+        batch_gradient(b, sel, ctr, v, gm);
+        batch_dot(b, sel, g, g, SC_T1, true);
+        {
+            std::vector<BAxpby> ad;
+            for (int i = 0; i < np; ++i) ad.push_back(BAxpby{g[i], bm[i], static_cast<size_t>(b->probs[i]->n), -1.0, nullptr, 0.0});
+            batch_axpby(b, ad);
+        }
+        std::vector<double> sc = batch_read_scal(b);
+        for (int i = 0; i < np; ++i) {
+            inf[i].J = 0.5 * sc[16 * i + SC_T2] + 0.5 * sc[16 * i + SC_T0];
+            inf[i].gnorm_inf = sc[16 * i + SC_T1];
+            inf[i].kappa_re = -1.0;
+            RP4D_REQUIRE(std::isfinite(inf[i].J) && std::isfinite(inf[i].gnorm_inf), RP4D_ENONFINITE,
+                         "non-finite cost or gradient in batch");
+        }
+        // 3-4. reuse test for resident preconditioners, sketch the rest
+        std::vector<const rp4d_precond*> use(np, nullptr);
+        if (o->sketch != RP4D_NOPREC) {
+            std::vector<int> test;
+            for (int i = 0; i < np; ++i)
+                if (states[i]->pc && o->reuse_eps > 0) test.push_back(i);
+            if (!test.empty()) {
+                // unit test vectors from Philox, z = P v, q = (I + H) z, kappa = |q| / |v|
+                std::vector<BRand> rd;
+                std::vector<size_t> cnt;
+                std::vector<const double*> vh, cz;
+                std::vector<double*> zz, qq;
+                std::vector<const rp4d_precond*> tp;
+                std::vector<const rp4d_traj*> ttr;
+                for (int i : test) {
+                    rp4d_problem* p = b->probs[i];
+                    p->ws_pcg.ensure(std::max<size_t>(p->ws_pcg.bytes, (5 * static_cast<size_t>(p->n) + 1024) * sizeof(double)));
+                    double* base = p->ws_pcg.as<double>();
+                    rd.push_back(BRand{base + 2 * p->n, static_cast<size_t>(p->n),
+                                       o->seed ^ 0x5DEECE66DULL ^ (0xBF58476D1CE4E5B9ULL * (p->id + 1))});
+                    cnt.push_back((p->n + 1) / 2);
+                    vh.push_back(base + 2 * p->n);
+                    zz.push_back(base);
+                    qq.push_back(base + p->n);
+                    tp.push_back(states[i]->pc);
+                    ttr.push_back(tr[i]);
+                }
+                auto it = elem_items(cnt);
+                launch_bphilox(stage(b, rd), stage(b, it), static_cast<int>(it.size()), st);
+                batch_precond_apply(b, test, tp, vh, zz);
+                cz.assign(zz.begin(), zz.end());
+                batch_hessian<double>(b, test, ttr, 1, cz, qq, true);
+                std::vector<const double*> cq(qq.begin(), qq.end());
+                batch_dot(b, test, cq, cq, SC_T0);
+                batch_dot(b, test, vh, vh, SC_T1);
+                std::vector<double> s2 = batch_read_scal(b);
+                for (int i : test) {
+                    inf[i].kappa_re = std::sqrt(s2[16 * i + SC_T0] / s2[16 * i + SC_T1]);
+                    if (inf[i].kappa_re < o->reuse_eps) {
+                        use[i] = states[i]->pc;
+                        inf[i].reused = 1;
+                        b->probs[i]->cnt.reuses += 1;
+                    }
+                }
+            }
+            std::vector<int> need;
+            std::vector<const rp4d_traj*> ntr;
+            for (int i = 0; i < np; ++i)
+                if (!use[i]) {
+                    need.push_back(i);
+                    ntr.push_back(tr[i]);
+                }
+            if (!need.empty()) {
+                std::vector<rp4d_precond*> pcs = batch_nystrom(b, need, ntr, o->ell, o->seed, o->sketch_dtype);
+                for (size_t q = 0; q < need.size(); ++q) {
+                    const int i = need[q];
+                    if (states[i]->pc) rp4d_precond_destroy(states[i]->pc);
+                    states[i]->pc = pcs[q];
+                    use[i] = pcs[q];
+                    inf[i].sketched = 1;
+                }
+            }
+        }
+        // 5. PCG
+        std::vector<const double*> rhs(bm.begin(), bm.end());
+        std::vector<int> conv;
+        std::vector<int> its = batch_pcg(b, sel, ctr, use, rhs, dv, o->rtol, o->maxit, conv);
+        // 6. v += dv, x = x_b + Gamma^{1/2} v
+        {
+            std::vector<BAxpby> ad;
+            for (int i = 0; i < np; ++i) ad.push_back(BAxpby{dv[i], vm[i], static_cast<size_t>(b->probs[i]->n), 1.0, nullptr, 1.0});
+            batch_axpby(b, ad);
+        }
+        batch_bhalf<double>(b, sel, 1, v, 1, xm, 1, xb);
+        bool all_conv = true;
+        for (int i = 0; i < np; ++i) {
+            inf[i].pcg_iters = its[i];
+            inf[i].pcg_converged = conv[i];
+            all_conv = all_conv && conv[i];
+            if (infos) infos[i] = inf[i];
+        }
+        RP4D_HIP(hipStreamSynchronize(st));
+        if (!all_conv) fail(RP4D_ENOCONV, "PCG reached maxit before the tolerance for some problem (steps applied)");
     });
 }
 

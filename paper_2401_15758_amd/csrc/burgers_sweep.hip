@@ -43,11 +43,11 @@ __device__ __forceinline__ double rk_c(int st) { return st < 2 ? 0.5 : 1.0; }
 __device__ __forceinline__ double rk_b(int st) { return (st == 0 || st == 3) ? (1.0 / 6.0) : (1.0 / 3.0); }
 
 template <int P>
-__global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
+__device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
     extern __shared__ double sh_fwd[];
     const int NT = blockDim.x, t = threadIdx.x;
     const int n = a.n;
-    const int tstart = blockIdx.x * a.tile;
+    const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
     const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const double h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
@@ -122,19 +122,33 @@ __global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
         if (own[p]) a.xout[g[p]] = u[p];
 }
 
+template <int P>
+__global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
+    fwd_body<P>(a, blockIdx.x);
+}
+
+// Batched: work item (problem, tile) from `items`, arguments per problem.
+template <int P>
+__global__ void __launch_bounds__(1024) burgers_fwd_batched_kernel(const FwdArgs* __restrict__ args,
+                                                                   const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const FwdArgs a = args[it.x];  // private copy: no aliasing with the kernel's stores
+    fwd_body<P>(a, it.y);
+}
+
 // Instances holding P*KC >= 8 point-vectors per thread are limited to 512
 // threads per workgroup so that they get 256 VGPRs instead of spilling.
 template <int P, int KC>
 constexpr int sweep_max_threads() { return P * KC >= 8 ? 512 : 1024; }
 
 template <typename T, int P, int KC>
-__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_tlm_kernel(SweepArgs<T> a) {
+__device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int grp) {
     extern __shared__ __align__(16) unsigned char sh_raw[];
     T* sh = reinterpret_cast<T*>(sh_raw);
     constexpr int W = 1 + KC;
-    const int NT = blockDim.x, t = threadIdx.x, grp = blockIdx.y;
+    const int NT = blockDim.x, t = threadIdx.x;
     const int n = a.n;
-    const int tstart = blockIdx.x * a.tile;
+    const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
     const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
@@ -262,13 +276,13 @@ __global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_tlm_kern
 }
 
 template <typename T, int P, int KC>
-__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kernel(SweepArgs<T> a) {
+__device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int grp) {
     extern __shared__ __align__(16) unsigned char sh_raw[];
     T* sh = reinterpret_cast<T*>(sh_raw);
     constexpr int W = 1 + KC;
-    const int NT = blockDim.x, t = threadIdx.x, grp = blockIdx.y;
+    const int NT = blockDim.x, t = threadIdx.x;
     const int n = a.n;
-    const int tstart = blockIdx.x * a.tile;
+    const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
     const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
@@ -418,6 +432,34 @@ __global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kern
         }
 }
 
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_tlm_kernel(SweepArgs<T> a) {
+    tlm_body<T, P, KC>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kernel(SweepArgs<T> a) {
+    adj_body<T, P, KC>(a, blockIdx.x, blockIdx.y);
+}
+
+// Batched sweeps: one launch covers the current interval of every problem of a
+// batch; work item (problem, tile, group) from `items`, arguments per problem.
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>()))
+    burgers_tlm_batched_kernel(const SweepArgs<T>* __restrict__ args, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const SweepArgs<T> a = args[it.x];
+    tlm_body<T, P, KC>(a, it.y, it.z);
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__((sweep_max_threads<P, KC>()))
+    burgers_adj_batched_kernel(const SweepArgs<T>* __restrict__ args, const int4* __restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const SweepArgs<T> a = args[it.x];
+    adj_body<T, P, KC>(a, it.y, it.z);
+}
+
 void check_tiling(const Tiling& t, int n, int halo, int S) {
     RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0, RP4D_EINVAL,
                  "sweep tiling: threads must be a multiple of 64 in [64, 1024]");
@@ -485,6 +527,63 @@ void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int 
     RP4D_HIP(hipGetLastError());
 }
 
+void launch_burgers_fwd_batched(const FwdArgs* args, const int4* items, int nitems, const Tiling& t, hipStream_t st) {
+    if (nitems <= 0) return;
+    const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * sizeof(double);
+    switch (t.ppt) {
+        case 1: burgers_fwd_batched_kernel<1><<<nitems, t.threads, shmem, st>>>(args, items); break;
+        case 2: burgers_fwd_batched_kernel<2><<<nitems, t.threads, shmem, st>>>(args, items); break;
+        case 4: burgers_fwd_batched_kernel<4><<<nitems, t.threads, shmem, st>>>(args, items); break;
+        case 8: burgers_fwd_batched_kernel<8><<<nitems, t.threads, shmem, st>>>(args, items); break;
+        default: fail(RP4D_EINVAL, "batched fwd: unsupported points per thread");
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename T, int P, int KC>
+static void launch_one_batched(int mode, const SweepArgs<T>* args, const int4* items, int nitems, int threads,
+                               size_t shmem, hipStream_t st) {
+    RP4D_REQUIRE((threads <= sweep_max_threads<P, KC>()), RP4D_EINVAL,
+                 "batched sweep: too many threads for this (points per thread, vectors per group)");
+    if (mode == MODE_TLM) {
+        if (shmem > 64 * 1024)
+            RP4D_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&burgers_tlm_batched_kernel<T, P, KC>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+        burgers_tlm_batched_kernel<T, P, KC><<<nitems, threads, shmem, st>>>(args, items);
+    } else {
+        if (shmem > 64 * 1024)
+            RP4D_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&burgers_adj_batched_kernel<T, P, KC>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+        burgers_adj_batched_kernel<T, P, KC><<<nitems, threads, shmem, st>>>(args, items);
+    }
+}
+
+template <typename T>
+void launch_burgers_sweep_batched(int mode, const SweepArgs<T>* args, const int4* items, int nitems, const Tiling& t,
+                                  hipStream_t st) {
+    if (nitems <= 0) return;
+    RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "batched sweep: bad mode");
+    const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
+    RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "batched sweep: LDS exchange buffer too large");
+    switch (t.ppt * 100 + t.kc) {
+        case 101: launch_one_batched<T, 1, 1>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 102: launch_one_batched<T, 1, 2>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 104: launch_one_batched<T, 1, 4>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 108: launch_one_batched<T, 1, 8>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 201: launch_one_batched<T, 2, 1>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 202: launch_one_batched<T, 2, 2>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 204: launch_one_batched<T, 2, 4>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 401: launch_one_batched<T, 4, 1>(mode, args, items, nitems, t.threads, shmem, st); break;
+        case 402: launch_one_batched<T, 4, 2>(mode, args, items, nitems, t.threads, shmem, st); break;
+        default: fail(RP4D_EINVAL, "batched sweep: unsupported (points per thread, vectors per group)");
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template void launch_burgers_sweep_batched<double>(int, const SweepArgs<double>*, const int4*, int, const Tiling&,
+                                                   hipStream_t);
+template void launch_burgers_sweep_batched<float>(int, const SweepArgs<float>*, const int4*, int, const Tiling&,
+                                                  hipStream_t);
 template void launch_burgers_sweep<double>(int, const SweepArgs<double>&, const Tiling&, int, hipStream_t);
 template void launch_burgers_sweep<float>(int, const SweepArgs<float>&, const Tiling&, int, hipStream_t);
 

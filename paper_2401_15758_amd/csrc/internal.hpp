@@ -89,6 +89,12 @@ struct FwdArgs {
 };
 
 void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st);
+// Batched forms: `args` (device) holds one argument block per problem, `items`
+// (device) one int4 (problem, tile, group, -) per workgroup.
+void launch_burgers_fwd_batched(const FwdArgs* args, const int4* items, int nitems, const Tiling& t, hipStream_t st);
+template <typename T>
+void launch_burgers_sweep_batched(int mode, const SweepArgs<T>* args, const int4* items, int nitems, const Tiling& t,
+                                  hipStream_t st);
 template <typename T>
 void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st);
 
@@ -145,6 +151,88 @@ void launch_philox_normal(uint64_t seed, size_t count, double* out, hipStream_t 
 template <typename T>
 void launch_philox_normal_t(uint64_t seed, size_t count, T* out, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Batched kernels (batch_kernels.hip): descriptor arrays in device memory, one
+// entry per problem; `items` = int4 work items (problem, block, block, -).
+// ---------------------------------------------------------------------------
+struct BGram {        // C (a x b, row-major) = X^T Y over n rows, chunks of `rows` rows
+    const void* X;
+    const void* Y;
+    double* C;
+    int n, a, b, lx, ly;
+    int rows;         // rows per chunk (set by the batch driver)
+    double* part;     // chunk partial sums: ceil(n/rows) * a * b doubles
+};
+struct BTsmm {        // Out = beta C + alpha X diag(ds) M
+    const void* X;
+    const double* M;
+    const double* ds;
+    const void* C;
+    void* Out;
+    int n, a, b, lx, lc, lo;
+    double alpha, beta;
+};
+struct BSmall {       // l x l operands
+    double* A;
+    double* B;
+    double* C;
+    int* info;
+};
+struct BVec {         // out = x . y (or max |x|)
+    const double* x;
+    const double* y;
+    double* out;
+    int n;
+};
+struct BAxpby {       // y = alpha (alpha_d ? *alpha_d : 1) x + beta y (x may be null: 0)
+    const double* x;
+    double* y;
+    size_t count;
+    double alpha;
+    const double* alpha_d;
+    double beta;
+};
+struct BPcg {         // PCG vectors and scalars (sc[0] = rz, sc[1] = pq, sc[2] = rz_new)
+    double *x, *r, *p, *q, *z;
+    double* sc;
+    int n;
+};
+struct BSketch {      // sketch finalisation
+    const double* ev;
+    double* nu;
+    double* lam;
+    double* D;
+    double* U;
+    int n;
+};
+struct BRand {
+    double* out;
+    size_t count;
+    uint64_t seed;
+};
+struct BCopy {        // dst(j, c) = src(j, c) (or 0), layouts skc / dkc
+    const void* src;
+    void* dst;
+    int n, k, skc, dkc, zero;
+};
+template <typename TX, typename TY>
+void launch_bgram(const BGram* d, const int4* items, int nitems, const int4* ritems, int nritems, hipStream_t st);
+template <typename TX, typename TO>
+void launch_btsmm(const BTsmm* d, const int4* items, int nitems, hipStream_t st);
+void launch_bchol(const BSmall* d, int np, int l, hipStream_t st);
+void launch_btrinv(const BSmall* d, int np, int l, hipStream_t st);
+void launch_bgemm_small(const BSmall* d, int np, int l, int ta, int tb, double alpha, hipStream_t st);
+void launch_bjacobi(const BSmall* d, int np, int l, bool wantv, hipStream_t st);
+void launch_bdot(const BVec* d, int np, bool absmax, hipStream_t st);
+void launch_baxpby(const BAxpby* d, const int4* items, int nitems, hipStream_t st);
+void launch_bpcg_xr(const BPcg* d, const int4* items, int nitems, hipStream_t st);
+void launch_bpcg_p(const BPcg* d, const int4* items, int nitems, int np, hipStream_t st);
+void launch_bnu(const BSketch* d, int np, double eps, hipStream_t st);
+void launch_bfinalize(const BSketch* d, int np, int l, bool use_nu, hipStream_t st);
+void launch_bphilox(const BRand* d, const int4* items, int nitems, hipStream_t st);
+template <typename TI, typename TO>
+void launch_bcopy(const BCopy* d, const int4* items, int nitems, hipStream_t st);
+
 }  // namespace rp4d
 
 // ---------------------------------------------------------------------------
@@ -195,8 +283,9 @@ struct rp4d_problem {
     int r = 0;
     rp4d::DevBuf F, lamF, ws_bh;
     // workspaces
-    rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg;
+    rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg, ws_bg;
     rp4d_counters cnt{};
+    uint64_t id = 0;  // caller-chosen identity: seeds the batched random draws
     std::map<std::tuple<int, int, int>, rp4d::Tiling> tiling;  // (mode, dtype, k)
 };
 

@@ -92,7 +92,7 @@ __global__ void fill_kernel(T* p, size_t count, T v) {
 __global__ void axpby_kernel(const double* x, double alpha, double* y, double beta, size_t count) {
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
          i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        y[i] = alpha * x[i] + beta * y[i];
+        y[i] = beta == 0.0 ? alpha * x[i] : alpha * x[i] + beta * y[i];  // beta = 0 overwrites
 }
 
 // ---------------------------------------------------------------------------

@@ -79,6 +79,7 @@ _SIGS = {
     "rp4d_problem_destroy": ([_P], _I),
     "rp4d_problem_dims": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "rp4d_problem_set_data": ([_P, _P, _P], _I),
+    "rp4d_problem_set_id": ([_P, ctypes.c_uint64], _I),
     "rp4d_traj_create": ([_P, ctypes.POINTER(_P)], _I),
     "rp4d_traj_destroy": ([_P], _I),
     "rp4d_fwd": ([_P, _P, _P, ctypes.POINTER(_D)], _I),
@@ -107,6 +108,12 @@ _SIGS = {
     "rp4d_gn_state_reset": ([_P], _I),
     "rp4d_ctx_set_timing": ([_P, _I], _I),
     "rp4d_ctx_kernel_stats": ([_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
+    "rp4d_batch_create": ([_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
+    "rp4d_batch_destroy": ([_P], _I),
+    "rp4d_batch_set_tiling": ([_P, _I, _I, _I, _I, _I, _I], _I),
+    "rp4d_batch_fwd": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_D)], _I),
+    "rp4d_batch_hessian_block": ([_P, ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P), _I, _I], _I),
+    "rp4d_batch_gn_step": ([_P, ctypes.POINTER(_P), ctypes.POINTER(GnOpts), ctypes.POINTER(GnInfo)], _I),
     "rp4d_set_sweep_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I, _I], _I),
     "rp4d_get_sweep_tiling": ([_P, _I, _I, _I] + [ctypes.POINTER(_I)] * 5, _I),
 }
@@ -206,6 +213,9 @@ class Problem:
         self.dev = ctx.device
 
     # -- data and trajectory -------------------------------------------------
+    def set_id(self, pid):
+        _check(_lib.rp4d_problem_set_id(self._h, int(pid)))
+
     def set_data(self, xb, y):
         _check(_lib.rp4d_problem_set_data(self._h, _ptr(xb, torch.float64, self.n, "xb"),
                                           _ptr(y, torch.float64, self.m, "y")))
@@ -415,6 +425,65 @@ class GNState:
     def close(self):
         if getattr(self, "_h", None):
             _lib.rp4d_gn_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _parr(vals):
+    arr = (ctypes.c_void_p * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+class Batch:
+    """rp4d_batch over a list of Problems of one Context."""
+
+    def __init__(self, ctx, problems):
+        self.ctx, self.problems = ctx, list(problems)
+        h = ctypes.c_void_p()
+        _check(_lib.rp4d_batch_create(ctx._h, len(self.problems), _parr([p._h.value for p in self.problems]),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def set_tiling(self, mode, dtype=F64, ppt=0, kc=0, threads=0, steps=0):
+        _check(_lib.rp4d_batch_set_tiling(self._h, mode, dtype, ppt, kc, threads, steps))
+
+    def fwd(self, x0s, trajs, want_J=True):
+        J = (_D * len(self.problems))()
+        _check(_lib.rp4d_batch_fwd(self._h, _parr([_ptr(x, torch.float64, p.n).value for x, p in zip(x0s, self.problems)]),
+                                   _parr([t._h.value for t in trajs]), J if want_J else None))
+        return list(J) if want_J else None
+
+    def hessian_block(self, trajs, Vs, HVs=None, add_identity=True):
+        k = Vs[0].shape[1] if Vs[0].dim() == 2 else 1
+        HVs = HVs if HVs is not None else [torch.empty_like(v) for v in Vs]
+        dt = _dt(Vs[0])
+        _check(_lib.rp4d_batch_hessian_block(
+            self._h, _parr([t._h.value for t in trajs]), k,
+            _parr([_ptr(v, Vs[0].dtype, p.n * k).value for v, p in zip(Vs, self.problems)]),
+            _parr([_ptr(h, Vs[0].dtype, p.n * k).value for h, p in zip(HVs, self.problems)]), dt,
+            1 if add_identity else 0))
+        return HVs
+
+    def gn_step(self, states, sketch=NYSTROM, ell=32, seed=0, sketch_dtype=F64, rtol=1e-6, maxit=0, reuse_eps=0.0,
+                raise_noconv=True):
+        o = GnOpts(sketch=sketch, ell=ell, seed=seed, omega=None, sketch_dtype=sketch_dtype, rtol=rtol, maxit=maxit,
+                   reuse_eps=reuse_eps, vhat=None)
+        infos = (GnInfo * len(self.problems))()
+        rc = _lib.rp4d_batch_gn_step(self._h, _parr([s._h.value for s in states]), ctypes.byref(o), infos)
+        if rc != ENOCONV or raise_noconv:
+            _check(rc)
+        return [{f: getattr(inf, f) for f, _ in GnInfo._fields_} for inf in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rp4d_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

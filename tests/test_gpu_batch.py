@@ -1,0 +1,133 @@
+"""GPU tests of the batched path (many uneven Burgers problems per launch):
+batched FWD / block Hessian / GN step against the FP64 oracle, and the batch
+invariance property (a problem's result is bitwise the same alone and in a mix)."""
+import numpy as np
+import pytest
+
+from gpu_util import colwise_relerr, need_gpu, relerr, to_dev, to_np
+from paper_2401_15758_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# uneven sizes and windows, ragged observation layouts; the 256-point problem
+# uses the banded prior path, the others the spectral one
+CFGS = [inputs.burgers_config(256, 50, 4, 10, dt_cfg=1e-3, name='b256'),
+        inputs.burgers_config(400, 77, 3, 7, dt_cfg=1e-3, name='b400'),
+        inputs.burgers_config(1000, 120, 5, 12, dt_cfg=1e-3, name='b1000'),
+        inputs.burgers_config(611, 33, 4, 11, dt_cfg=1e-3, name='b611')]
+
+
+def _setup(cfgs, seeds=None):
+    from oracle.problem import burgers_problem
+    from paper_2401_15758_amd import rp4d
+    ctx = rp4d.Context(0)
+    orcs, probs, trajs = [], [], []
+    for i, cfg in enumerate(cfgs):
+        orc = burgers_problem(cfg, inputs.draws(cfg, seed=(seeds[i] if seeds else i)))
+        p = rp4d.Problem(ctx, cfg)
+        p.set_id(100 + i)
+        p.set_data(to_dev(orc.xb), to_dev(orc.y.reshape(-1)))
+        orcs.append(orc)
+        probs.append(p)
+        trajs.append(p.traj())
+    return ctx, orcs, probs, trajs
+
+
+def test_batched_fwd_and_hessian_match_oracle():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    J = b.fwd([to_dev(o.xb) for o in orcs], trajs)
+    k = 5
+    Vs = [np.random.default_rng(10 + i).standard_normal((o.n, k)) for i, o in enumerate(orcs)]
+    HVs = b.hessian_block(trajs, [to_dev(v) for v in Vs])
+    for i, o in enumerate(orcs):
+        otr = o.fwd(o.xb)
+        d = o.innovations(otr)
+        assert J[i] == pytest.approx(0.5 * np.sum(d * d), rel=1e-12)
+        assert relerr(to_np(probs[i].observe(trajs[i])), o.observe(otr)) <= 1e-13
+        assert colwise_relerr(to_np(HVs[i]), o.hessian(otr, Vs[i])) <= 1e-12
+
+
+def test_batched_hessian_matches_single_problem_path():
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    b.fwd([to_dev(o.xb) for o in orcs], trajs, want_J=False)
+    Vs = [to_dev(np.random.default_rng(20 + i).standard_normal((o.n, 8))).to(torch.float32) for i, o in enumerate(orcs)]
+    HB = b.hessian_block(trajs, Vs)
+    for i, p in enumerate(probs):
+        HS = p.hessian_block(trajs[i], Vs[i])
+        assert colwise_relerr(to_np(HB[i]), to_np(HS)) <= 1e-6   # FP32 sweeps, different prior reduction order
+
+
+def test_batch_invariance_alone_and_in_mix():
+    """Each problem's batched block Hessian is bitwise identical whether it runs
+    alone or with the other problems."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    b.fwd([to_dev(o.xb) for o in orcs], trajs, want_J=False)
+    Vs = [to_dev(np.random.default_rng(30 + i).standard_normal((o.n, 6))) for i, o in enumerate(orcs)]
+    mix = [h.clone() for h in b.hessian_block(trajs, Vs)]
+    for i, p in enumerate(probs):
+        alone = rp4d.Batch(ctx, [p]).hessian_block([trajs[i]], [Vs[i]])[0]
+        torch.cuda.synchronize()
+        assert torch.equal(alone, mix[i]), i
+
+
+def _omega_seed(seed, index):
+    return (seed ^ ((0x9E3779B97F4A7C15 * (index + 1)) & 0xFFFFFFFFFFFFFFFF)) & 0xFFFFFFFFFFFFFFFF
+
+
+def test_batched_gn_step_matches_oracle():
+    torch = need_gpu()
+    from oracle import gn as ogn
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    states = [p.gn_state() for p in probs]
+    ell, seed = 12, 77
+    infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=ell, seed=seed, rtol=1e-12)
+    for i, (o, p) in enumerate(zip(orcs, probs)):
+        om = torch.empty(o.n * ell, dtype=torch.float64, device="cuda")
+        ctx.philox_normal(_omega_seed(seed, 100 + i), om.numel(), om)
+        Om = to_np(om).reshape(o.n, ell)
+        v1, dv, x1, info = ogn.gn_step(o, np.zeros(o.n), method='nystrom', Omega=Om, rtol=1e-12)
+        gv, gx = states[i].get()
+        assert infos[i]['J'] == pytest.approx(info['J'], rel=1e-12)
+        # at rtol 1e-12 the last iterations are at roundoff: counts may differ by a few
+        assert abs(infos[i]['pcg_iters'] - info['pcg']['iters']) <= 3
+        assert relerr(to_np(gx), x1) <= 1e-10, i
+        c = p.counters()
+        assert c['tlm_offline'] == ell and c['tlm_online'] == infos[i]['pcg_iters']
+
+
+def test_batched_gn_fp32_sketch_and_mix_invariance():
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    states = [p.gn_state() for p in probs]
+    Js = []
+    for it in range(3):
+        infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=16, seed=5 + it, sketch_dtype=rp4d.F32, rtol=1e-6,
+                          reuse_eps=10.0)
+        Js.append([inf['J'] for inf in infos])
+        assert all(inf['pcg_converged'] for inf in infos)
+    for i in range(len(probs)):
+        assert Js[1][i] < Js[0][i]
+    # the last problem alone, same three steps: bitwise equal final state
+    p = probs[-1]
+    st = p.gn_state()
+    bb = rp4d.Batch(ctx, [p])
+    for it in range(3):
+        bb.gn_step([st], sketch=rp4d.NYSTROM, ell=16, seed=5 + it, sketch_dtype=rp4d.F32, rtol=1e-6, reuse_eps=10.0)
+    _, xa = st.get()
+    _, xm = states[-1].get()
+    torch.cuda.synchronize()
+    # random draws follow the problem id, reductions are per problem: bitwise equal
+    assert torch.equal(xa, xm)
