@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import burgers as _burgers
+from . import bve as _bve
 from . import prior as _prior
 
 
@@ -179,3 +180,19 @@ def burgers_problem(cfg, draws=None):
     if draws is not None:
         prob.xb, prob.y = synthesize(prob, draws['x_true'], draws['xi'], draws['eta'])
     return prob
+
+
+def bve_problem(cfg, draws=None):
+    """Build a barotropic-vorticity Problem from a config dict (keys: nx, ny, nu, dt,
+    nsteps, obs_stride, obs_every, sigma_o, sigma_b, L_b in cells) and optional draws."""
+    model = _bve.BVEModel(nx=int(cfg['nx']), ny=int(cfg['ny']), nu=float(cfg['nu']), dt=float(cfg['dt']))
+    prob = Problem(model=model, nsteps=int(cfg['nsteps']), obs_stride=int(cfg['obs_stride']),
+                   obs_every=int(cfg['obs_every']), sigma_o=float(cfg['sigma_o']),
+                   sigma_b=float(cfg['sigma_b']), L_b=float(cfg['L_b']))
+    if draws is not None:
+        prob.xb, prob.y = synthesize(prob, draws['x_true'], draws['xi'], draws['eta'])
+    return prob
+
+
+def make_problem(cfg, draws=None):
+    return bve_problem(cfg, draws) if cfg.get('model') == 'bve' else burgers_problem(cfg, draws)

@@ -19,6 +19,12 @@ locations, a spun-up gyre truth -- are not available and not needed):
                  and observation cadence are kept).
   batch-64       64 independent Burgers problems, n log-uniform in [256, 4096],
                  N uniform in [50, 500], per-problem seeds; sketch l=32.
+  bve-256        periodic barotropic vorticity on a 256 x 256 grid of [0,1)^2,
+                 nu = 1e-4, dt = 2e-3, 200 RK4 steps, observe every 16th cell in
+                 both directions every 20 steps (n_obs = 256, n_t = 10), sigma_o =
+                 0.01, separable Gaussian prior sigma_b = 0.05, L = 8 cells; sketch
+                 l = 100.  Truth: random-phase vorticity with |zeta_hat(k)| ~ 1/|k|
+                 (energy spectrum k^-3) for 1 <= |k| <= n/3, scaled to unit rms.
 
 Truth: u0(x) = sin(2 pi x) + 0.5 sin(4 pi x) on x_j = j/n.
 """
@@ -49,7 +55,19 @@ CFG_SMALL = burgers_config(128, 50, 4, 10, dt_cfg=1e-3, ell=20, name='burgers-12
 CFG_LARGE = burgers_config(4096, 500, 16, 25, dt_cfg=2.5e-5, ell=64, name='burgers-4096')
 
 
+def bve_config(nx, nsteps=200, obs_stride=16, obs_every=20, dt=2e-3, nu=1e-4, sigma_o=0.01, sigma_b=0.05,
+               L_cells=8.0, ell=100, name=None):
+    return dict(model='bve', name=name or f'bve-{nx}', nx=int(nx), ny=int(nx), n=int(nx) * int(nx), nu=float(nu),
+                dt=float(dt), nsteps=int(nsteps), obs_stride=int(obs_stride), obs_every=int(obs_every),
+                sigma_o=float(sigma_o), sigma_b=float(sigma_b), L_b=float(L_cells), ell=int(ell))
+
+
+CFG_BVE = bve_config(256, name='bve-256')
+
+
 def n_obs(cfg):
+    if cfg.get('model') == 'bve':
+        return len(range(0, cfg['nx'], cfg['obs_stride'])) * len(range(0, cfg['ny'], cfg['obs_stride']))
     return len(range(0, cfg['n'], cfg['obs_stride']))
 
 
@@ -62,12 +80,28 @@ def truth(cfg):
     return np.sin(2 * np.pi * x) + 0.5 * np.sin(4 * np.pi * x)
 
 
+def bve_truth(cfg, rng):
+    """Random-phase vorticity with |zeta_hat(k)| ~ 1/|k| on 1 <= |k| <= nx/3, unit rms,
+    flattened j*nx + i."""
+    nx, ny = cfg['nx'], cfg['ny']
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    kk = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
+    amp = np.where((kk >= 1) & (kk <= nx / 3), 1.0 / np.maximum(kk, 1.0), 0.0)
+    phase = rng.uniform(0.0, 2 * np.pi, size=amp.shape)
+    z = np.fft.irfft2(amp * np.exp(1j * phase), s=(ny, nx))
+    z = z / np.sqrt(np.mean(z * z))
+    return z.reshape(-1)
+
+
 def draws(cfg, seed=0):
-    """Raw draws for one problem: x_true, xi (n), eta (n_t, n_obs)."""
+    """Raw draws for one problem: x_true, xi (n), eta (n_t, n_obs).  BVE draws the
+    truth's phases first."""
     rng = np.random.default_rng(seed)
+    x_true = bve_truth(cfg, rng) if cfg.get('model') == 'bve' else truth(cfg)
     xi = rng.standard_normal(cfg['n'])
     eta = rng.standard_normal((n_t(cfg), n_obs(cfg)))
-    return dict(x_true=truth(cfg), xi=xi, eta=eta)
+    return dict(x_true=x_true, xi=xi, eta=eta)
 
 
 def omega(n, ell, seed=1000):
