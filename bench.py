@@ -41,7 +41,34 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning-cache", default=None, help="JSON tiling cache (default: the package's tuning.json)")
     ap.add_argument("--tune-budget", type=float, default=20.0, help="seconds per tuned shape when not cached")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB with a plain elementwise kernel "
+                         "(reference dispatch for the HBM byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "burgers_sweep_k64_traffic.json")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2401_15758_amd", "csrc", "burgers_sweep.hip")
+
+
+def measured_traffic(kname, tiling, cfg):
+    """HBM bytes per launch of the dominant sweep kernel, from the counter runs
+    recorded next to the profiles (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy).  None unless the record is for this kernel source,
+    kernel instantiation, tiling and workload."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(SWEEP_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    keys = ("ppt", "kc", "threads", "tile", "steps")
+    if (rec.get("source_sha256") != sha or rec.get("kernel") != kname or rec.get("workload") != cfg["name"]
+            or any(rec.get("tiling", {}).get(k) != tiling.get(k) for k in keys)):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(cfg, ell, rtol):
@@ -125,7 +152,8 @@ def main():
     elapsed = t1 - t0
     cnt = prob.counters()
     kst = {name: ctx.kernel_stats(kind) for name, kind in
-           (("tlm", rp4d.K_TLM), ("adj", rp4d.K_ADJ), ("fwd", rp4d.K_FWD), ("bhalf", rp4d.K_BHALF))}
+           (("tlm", rp4d.K_TLM), ("adj", rp4d.K_ADJ), ("tlm1", rp4d.K_TLM1), ("adj1", rp4d.K_ADJ1),
+            ("fwd", rp4d.K_FWD), ("bhalf", rp4d.K_BHALF), ("eig", rp4d.K_EIG))}
     ctx.set_timing(False)
 
     hv_per_s = cnt["hv_columns"] / elapsed
@@ -133,8 +161,11 @@ def main():
     ks = kst[dom]
     achieved = ks["alg_flops"] / (ks["total_ms"] * 1e-3) / 1e12 if ks["total_ms"] > 0 else 0.0
     peak = PEAK_FP64_VALU_TFLOPS if skd == rp4d.F64 else PEAK_FP32_VALU_TFLOPS
-    roofline = {"bound": "alu", "kernel": f"burgers_{dom}_kernel", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+    tl = tilings[f"k{ell}-{'f64' if skd == rp4d.F64 else 'f32'}"][dom]
+    kname = f"burgers_{dom}_kernel<{'double' if skd == rp4d.F64 else 'float'}, {tl['ppt']}, {tl['kc']}>"
+    roofline = {"bound": "alu", "kernel": kname + f" (k={ell} block sweep)", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(kname, tl, cfg),
                 "avg_launch_us": 1e3 * ks["total_ms"] / max(1, ks["launches"]),
                 "launches": ks["launches"]}
 
@@ -185,6 +216,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)      # reads and writes calib_copy_mib MiB once
+        torch.cuda.synchronize()
+        out["calib_copy_mib"] = args.calib_copy_mib
     print(json.dumps(out), flush=True)
 
 

@@ -248,11 +248,16 @@ int rp4d_gn_state_reset(rp4d_gn_state* s);
 
 /* Kernel timing with HIP events recorded on the context stream around every
  * launch of the timed kernel classes (enable = 1 clears the statistics).
- * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps), RP4D_K_FWD, RP4D_K_BHALF.
+ * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps, k > 1), RP4D_K_FWD, RP4D_K_BHALF,
+ * RP4D_K_TLM1, RP4D_K_ADJ1 (single-vector sweeps, k = 1) and RP4D_K_EIG (the
+ * small symmetric eigensolves of the sketch post-processing; flops reported 0).
  * rp4d_ctx_kernel_stats synchronises the stream and returns the number of
  * launches, their summed duration (ms) and the algorithmic flops they performed
  * (owned grid points only; FP64 or FP32 as launched). */
-enum { RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3, RP4D_K_COUNT = 4 };
+enum {
+    RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3,
+    RP4D_K_TLM1 = 4, RP4D_K_ADJ1 = 5, RP4D_K_EIG = 6, RP4D_K_COUNT = 7
+};
 int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
 

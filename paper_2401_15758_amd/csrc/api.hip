@@ -348,7 +348,7 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
             a.xin = in;
             a.xout = out;
             {
-                KernelTimer kt(p->ctx, RP4D_K_TLM,
+                KernelTimer kt(p->ctx, k == 1 ? RP4D_K_TLM1 : RP4D_K_TLM,
                                static_cast<double>(a.S) * n * (FL_TLM_VEC * k + FL_TLM_BASE));
                 launch_burgers_sweep<T>(MODE_TLM, a, t, groups, st);
             }
@@ -408,7 +408,7 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
             a.xin = in;
             a.xout = out;
             {
-                KernelTimer kt(p->ctx, RP4D_K_ADJ,
+                KernelTimer kt(p->ctx, k == 1 ? RP4D_K_ADJ1 : RP4D_K_ADJ,
                                static_cast<double>(a.S) * n * (FL_ADJ_VEC * k + FL_ADJ_BASE));
                 launch_burgers_sweep<T>(MODE_ADJ, a, t, groups, st);
             }
@@ -905,7 +905,10 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
     // step 3: nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
     launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
-    launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+    }
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
@@ -930,7 +933,10 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     launch_gram<double, double>(s.Y2, l, s.Y2, l, n, l, l, s.S4, s.gw, st);  // S4 = Y^T Y
     launch_small_gemm(s.S3, 0, s.S4, 0, s.S2, l, 1.0, st);            // S2 = L^{-1} Y^T Y
     launch_small_gemm(s.S2, 0, s.S3, 1, s.S4, l, 1.0, st);            // S4 = S2 L^{-T}
-    launch_jacobi_eig(s.S4, s.ev, s.S2, l, st);                       // ev = Sigma^2, S2 = U
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(s.S4, s.ev, s.S2, l, st);                       // ev = Sigma^2, S2 = U
+    }
     sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, nu, l, s.lam, s.D, s.cs);
     RP4D_HIP(hipGetLastError());
     // V_hat = W^T U Sigma^{-1} = Y L^{-T} U Sigma^{-1}
@@ -975,7 +981,10 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s) {
         return;
     }
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
-    launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+    }
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double sh = 11.0 * (static_cast<double>(rows) * l + l * (l + 1.0)) * std::ldexp(1.0, -53) * ymax2;
@@ -1008,7 +1017,10 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     }
     // step 5: thin SVD of W via eig(W W^T): V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
     launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S2, s.gw, st);
-    launch_jacobi_eig(s.S2, s.ev, s.S3, l, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(s.S2, s.ev, s.S3, l, st);
+    }
     sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, 0.0, l, s.lam, s.D, s.cs);
     RP4D_HIP(hipGetLastError());
     scale_cols<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, l, s.cs);

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -
 F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC = 0, 1, 2
 BURGERS1D, BVE2D = 0, 1
-K_TLM, K_ADJ, K_FWD, K_BHALF = 0, 1, 2, 3
+K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG = 0, 1, 2, 3, 4, 5, 6
 MODE_BOTH, MODE_TLM, MODE_ADJ = 0, 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
