@@ -70,7 +70,16 @@ enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
  *   sigma_o: R_i = sigma_o^2 I.  sigma_b, L_b: Gaussian prior std and length
  *     (Burgers: L_b in domain units; BVE: L_b in cells).
  *   ckpt_every: 0 or 1 store every state of the trajectory; C > 1 store every
- *     C-th state and recompute segments during the sweeps (bitwise identical). */
+ *     C-th state and recompute segments during the sweeps (bitwise identical).
+ *     Burgers only: the 2-D model always stores every state and, per step, its
+ *     RK4 stage values and stream functions (7 fields per step).
+ * 2-D model (Sec. 5.2, periodic form): vorticity zeta on a square grid
+ * (nx == ny, a multiple of 16, 16..2048), flattened j*nx + i; stream function
+ * psi = L zeta with L the spectral inverse Laplacian (zero mean); RHS
+ * -J_A(psi, zeta) + nu lap(zeta) with Arakawa's Jacobian J_A and the 5-point
+ * Laplacian; separable prior sigma_b (S_y kron S_x), S the circulant square
+ * root of the unit Gaussian kernel exp(-r^2/L_b^2) (r in cells); observations
+ * at cells (j, i) with j, i multiples of obs_stride, ordered j-major. */
 typedef struct {
     int model;
     int nx, ny;
@@ -243,6 +252,11 @@ int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out);
 int rp4d_problem_synthesize(rp4d_problem* p, const double* x_true, const double* xi, const double* eta,
                             double* xb_out, double* y_out);
 
+/* 2-D model only: psi = L zeta for k fields, in and out row-major (n x k) in
+ * `dtype` on the device (in == out allowed).  L is applied as four dense
+ * products with the real Fourier basis (MFMA).  RP4D_EINVAL for a 1-D problem. */
+int rp4d_bve_inv_laplacian(rp4d_problem* p, int k, const void* in, void* out, int dtype);
+
 /* Reset a GN state to v = 0, x = x_b and drop its resident preconditioner. */
 int rp4d_gn_state_reset(rp4d_gn_state* s);
 
@@ -250,13 +264,17 @@ int rp4d_gn_state_reset(rp4d_gn_state* s);
  * launch of the timed kernel classes (enable = 1 clears the statistics).
  * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps, k > 1), RP4D_K_FWD, RP4D_K_BHALF,
  * RP4D_K_TLM1, RP4D_K_ADJ1 (single-vector sweeps, k = 1) and RP4D_K_EIG (the
- * small symmetric eigensolves of the sketch post-processing; flops reported 0).
+ * small symmetric eigensolves of the sketch post-processing; flops reported 0),
+ * and for the 2-D model RP4D_K_GEMM (the dense Fourier-basis products of the
+ * spectral inverse Laplacian and prior, 2MNK flops each) and RP4D_K_STENCIL
+ * (the Arakawa / Laplacian stage kernels).
  * rp4d_ctx_kernel_stats synchronises the stream and returns the number of
  * launches, their summed duration (ms) and the algorithmic flops they performed
  * (owned grid points only; FP64 or FP32 as launched). */
 enum {
     RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3,
-    RP4D_K_TLM1 = 4, RP4D_K_ADJ1 = 5, RP4D_K_EIG = 6, RP4D_K_COUNT = 7
+    RP4D_K_TLM1 = 4, RP4D_K_ADJ1 = 5, RP4D_K_EIG = 6, RP4D_K_GEMM = 7, RP4D_K_STENCIL = 8,
+    RP4D_K_COUNT = 9
 };
 int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);

@@ -424,6 +424,10 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
 // periodic convolution with the square-root kernel.
 template <typename T>
 void bhalf_into(rp4d_problem* p, int k, const T* in, int in_kc, T* out, int out_kc, const T* addv) {
+    if (p->bve) {
+        bve_bhalf<T>(p, k, in, in_kc, out, out_kc, addv);
+        return;
+    }
     hipStream_t st = stream_of(p);
     if (p->spec) {
         const int r = p->r, n = p->n;
@@ -469,6 +473,10 @@ SweepWork<T> sweep_work(rp4d_problem* p, int k, int dtype) {
 
 template <typename T>
 void tlm_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* Z) {
+    if (p->bve) {
+        bve_tlm<T>(p, tr, k, V, Z);
+        return;
+    }
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
     const int groups = (k + w.tt.kc - 1) / w.tt.kc;
     if (groups * w.tt.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.tt.kc * p->n, T(0), stream_of(p));
@@ -478,6 +486,10 @@ void tlm_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* Z) {
 
 template <typename T>
 void adj_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* U, const T* addv) {
+    if (p->bve) {
+        bve_adj<T>(p, tr, k, W, U, addv);
+        return;
+    }
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
     T* lam = run_adj<T>(p, tr, k, w.ta, w.s0, w.s1, W);
     bhalf_into<T>(p, k, lam, w.ta.kc, U, k, addv);
@@ -485,6 +497,11 @@ void adj_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* U, con
 
 template <typename T>
 void hessian_impl(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV, bool add_identity) {
+    if (p->bve) {
+        bve_hessian<T>(p, tr, k, V, HV, add_identity);
+        p->cnt.hv_columns += k;
+        return;
+    }
     SweepWork<T> w = sweep_work<T>(p, k, sizeof(T) == 8 ? RP4D_F64 : RP4D_F32);
     const int groups = (k + w.tt.kc - 1) / w.tt.kc;
     if (groups * w.tt.kc != k) launch_fill<T>(w.s0, static_cast<size_t>(groups) * w.tt.kc * p->n, T(0), stream_of(p));
@@ -522,6 +539,43 @@ rp4d_ctx::~rp4d_ctx() {
 }
 
 using namespace rp4d;
+
+namespace {
+rp4d_problem* create_bve(rp4d_ctx* ctx, const rp4d_problem_desc& d) {
+    RP4D_REQUIRE(d.nx == d.ny && d.nx >= 16 && d.nx <= 2048 && d.nx % 16 == 0, RP4D_EINVAL,
+                 "2-D grid must be square with nx a multiple of 16 in [16, 2048]");
+    RP4D_REQUIRE(d.nsteps >= 1 && d.obs_every >= 1 && d.obs_stride >= 1 && d.obs_stride <= d.nx, RP4D_EINVAL,
+                 "bad window / observation layout");
+    RP4D_REQUIRE(d.nsteps / d.obs_every >= 1, RP4D_EINVAL, "window has no observation step");
+    RP4D_REQUIRE(d.dt > 0 && d.nu >= 0 && d.sigma_o > 0 && d.sigma_b > 0 && d.L_b > 0, RP4D_EINVAL,
+                 "bad physical parameters");
+    RP4D_REQUIRE(d.ckpt_every <= 1, RP4D_EINVAL, "the 2-D model stores the full trajectory (ckpt_every 0 or 1)");
+    const double dx = 1.0 / d.nx;
+    RP4D_REQUIRE(8.0 * d.nu * d.dt / (dx * dx) <= 2.785, RP4D_EUNSTABLE,
+                 "time step outside the RK4 diffusive stability interval (8 nu dt/dx^2 > 2.785)");
+    auto* p = new rp4d_problem();
+    try {
+        p->ctx = ctx;
+        p->d = d;
+        p->d.ckpt_every = 1;
+        p->n = d.nx * d.ny;
+        const int nox = (d.nx + d.obs_stride - 1) / d.obs_stride, noy = (d.ny + d.obs_stride - 1) / d.obs_stride;
+        p->n_obs = nox * noy;
+        p->n_t = d.nsteps / d.obs_every;
+        p->m = p->n_obs * p->n_t;
+        p->s_last = p->n_t * d.obs_every;
+        p->dx = dx;
+        bve_setup(p);
+        p->xb.ensure(p->n * sizeof(double));
+        p->y.ensure(static_cast<size_t>(p->m) * sizeof(double));
+        p->ws_scal.ensure(64 * sizeof(double));
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    return p;
+}
+}  // namespace
 
 // ===========================================================================
 // ABI
@@ -561,7 +615,11 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
         RP4D_REQUIRE(ctx != nullptr && desc != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
         set_device(ctx);
         const rp4d_problem_desc& d = *desc;
-        RP4D_REQUIRE(d.model == RP4D_BURGERS1D, RP4D_EINVAL, "model not supported by this library build");
+        RP4D_REQUIRE(d.model == RP4D_BURGERS1D || d.model == RP4D_BVE2D, RP4D_EINVAL, "unknown model");
+        if (d.model == RP4D_BVE2D) {
+            *out = create_bve(ctx, d);
+            return;
+        }
         RP4D_REQUIRE(d.nx >= 8 && d.nx <= (1 << 22), RP4D_EINVAL, "nx out of range");
         RP4D_REQUIRE(d.nsteps >= 1 && d.obs_every >= 1 && d.obs_stride >= 1 && d.obs_stride <= d.nx, RP4D_EINVAL,
                      "bad window / observation layout");
@@ -698,6 +756,7 @@ int rp4d_traj_create(rp4d_problem* p, rp4d_traj** out) {
             t->C = p->d.ckpt_every;
             t->rows = p->s_last / t->C + 1;
             t->states.ensure(static_cast<size_t>(t->rows) * p->n * sizeof(double));
+            if (p->bve) t->stages.ensure(bve_traj_stage_bytes(p));
             t->innov.ensure(2 * static_cast<size_t>(p->m) * sizeof(double));
         } catch (...) {
             delete t;
@@ -723,10 +782,14 @@ int rp4d_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* J_obs) {
         set_device(p->ctx);
         hipStream_t st = stream_of(p);
         double* rows = tr->states.as<double>();
-        launch_relayout<double, double>(x0, 1, rows, 1, p->n, 1, st);  // row 0 = x0
         double* innov = tr->innov.as<double>();
         double* obs = innov + p->m;
-        run_fwd(p, x0, 0, p->s_last, rows, tr->C, 0, tr->rows, innov, obs);
+        if (p->bve) {
+            bve_fwd(p, x0, tr, innov, obs);
+        } else {
+            launch_relayout<double, double>(x0, 1, rows, 1, p->n, 1, st);  // row 0 = x0
+            run_fwd(p, x0, 0, p->s_last, rows, tr->C, 0, tr->rows, innov, obs);
+        }
         tr->valid = true;
         tr->has_innov = p->has_data;
         p->cnt.fwd += 1;
@@ -800,6 +863,20 @@ int rp4d_hessian_block(rp4d_problem* p, const rp4d_traj* tr, int k, const void* 
         check_traj(p, tr);
         set_device(p->ctx);
         hessian_dispatch(p, tr, k, V, HV, dtype, add_identity != 0);
+    });
+}
+
+int rp4d_bve_inv_laplacian(rp4d_problem* p, int k, const void* in, void* out, int dtype) {
+    return guarded([&] {
+        check_common(p, k, in, out);
+        RP4D_REQUIRE(p->bve != nullptr, RP4D_EINVAL, "inverse Laplacian needs a 2-D problem");
+        set_device(p->ctx);
+        if (dtype == RP4D_F64)
+            bve_inv_laplacian<double>(p, k, static_cast<const double*>(in), static_cast<double*>(out));
+        else if (dtype == RP4D_F32)
+            bve_inv_laplacian<float>(p, k, static_cast<const float*>(in), static_cast<float*>(out));
+        else
+            fail(RP4D_EINVAL, "bad dtype");
     });
 }
 
@@ -1408,7 +1485,10 @@ int rp4d_problem_synthesize(rp4d_problem* p, const double* x_true, const double*
         set_device(p->ctx);
         hipStream_t st = stream_of(p);
         bhalf_into<double>(p, 1, xi, 1, xb_out, 1, x_true);
-        run_fwd(p, x_true, 0, p->s_last, nullptr, 1, 0, 0, nullptr, y_out);
+        if (p->bve)
+            bve_fwd(p, x_true, nullptr, nullptr, y_out);
+        else
+            run_fwd(p, x_true, 0, p->s_last, nullptr, 1, 0, 0, nullptr, y_out);
         launch_axpby(eta, p->d.sigma_o, y_out, 1.0, p->m, st);
     });
 }

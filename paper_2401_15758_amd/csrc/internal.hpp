@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -268,6 +269,31 @@ struct KernelTimer {
 };
 }  // namespace rp4d
 
+namespace rp4d {
+// Barotropic-vorticity model data: nx x ny periodic grid (fields flattened j*nx+i).
+struct BveData {
+    int nx = 0, ny = 0;
+    double d = 0;               // grid spacing 1/nx
+    DevBuf basis, basis_f;      // Bx, Bx^T (nx x nx), By, By^T (ny x ny): FP64 and FP32
+    DevBuf dlap, dlap_f;        // (ny, nx): -1/|k|^2 in the product basis, 0 for k = 0
+    DevBuf dpri, dpri_f;        // (ny, nx): sigma_b s_y s_x, the prior square root's eigenvalues
+    DevBuf ws, ws_fwd, ws_bh, ws_obs;
+};
+void bve_setup(rp4d_problem* p);
+size_t bve_traj_stage_bytes(const rp4d_problem* p);
+void bve_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* innov, double* obs_out);
+template <typename T>
+void bve_bhalf(rp4d_problem* p, int k, const T* in, int in_kc, T* out, int out_kc, const T* addv);
+template <typename T>
+void bve_inv_laplacian(rp4d_problem* p, int k, const T* in, T* out);
+template <typename T>
+void bve_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* Z);
+template <typename T>
+void bve_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* U, const T* addv);
+template <typename T>
+void bve_hessian(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV, bool add_identity);
+}  // namespace rp4d
+
 struct rp4d_problem {
     rp4d_ctx* ctx = nullptr;
     rp4d_problem_desc d{};
@@ -287,12 +313,14 @@ struct rp4d_problem {
     rp4d_counters cnt{};
     uint64_t id = 0;  // caller-chosen identity: seeds the batched random draws
     std::map<std::tuple<int, int, int>, rp4d::Tiling> tiling;  // (mode, dtype, k)
+    std::unique_ptr<rp4d::BveData> bve;                          // set for the 2-D model
 };
 
 struct rp4d_traj {
     rp4d_problem* p = nullptr;
     rp4d::DevBuf states;  // rows of u_s (every C-th when checkpointing)
     rp4d::DevBuf innov;   // (n_t, n_obs)
+    rp4d::DevBuf stages;  // 2-D model: per step the stage values Y2..Y4 and stream functions psi1..psi4
     int C = 1;
     int rows = 0;
     bool valid = false, has_innov = false;

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -
 F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC = 0, 1, 2
 BURGERS1D, BVE2D = 0, 1
-K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG = 0, 1, 2, 3, 4, 5, 6
+K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ = 0, 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
@@ -89,6 +89,7 @@ _SIGS = {
     "rp4d_adj": ([_P, _P, _I, _P, _P, _I], _I),
     "rp4d_hessian_block": ([_P, _P, _I, _P, _P, _I, _I], _I),
     "rp4d_gradient": ([_P, _P, _P, _P], _I),
+    "rp4d_bve_inv_laplacian": ([_P, _I, _P, _P, _I], _I),
     "rp4d_build_precond": ([_P, _P, _I, _I, ctypes.c_uint64, _P, _I, ctypes.POINTER(_P)], _I),
     "rp4d_precond_destroy": ([_P], _I),
     "rp4d_precond_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
@@ -199,7 +200,8 @@ class Problem:
     def __init__(self, ctx, cfg, ckpt_every=0):
         self.ctx = ctx
         d = ProblemDesc(model=BURGERS1D if cfg.get("model", "burgers") == "burgers" else BVE2D,
-                        nx=int(cfg.get("n", cfg.get("nx", 0))), ny=int(cfg.get("ny", 1)), nu=float(cfg["nu"]),
+                        nx=int(cfg["nx"] if cfg.get("model") == "bve" else cfg["n"]), ny=int(cfg.get("ny", 1)),
+                        nu=float(cfg["nu"]),
                         dt=float(cfg["dt"]), nsteps=int(cfg["nsteps"]), obs_stride=int(cfg["obs_stride"]),
                         obs_every=int(cfg["obs_every"]), sigma_o=float(cfg["sigma_o"]),
                         sigma_b=float(cfg["sigma_b"]), L_b=float(cfg["L_b"]), ckpt_every=int(ckpt_every))
@@ -249,6 +251,14 @@ class Problem:
         out = out if out is not None else torch.empty_like(V)
         _check(_lib.rp4d_bhalf(self._h, k, _ptr(V, None, self.n * k, "V"), _ptr(out, V.dtype, self.n * k, "U"),
                                _dt(V)))
+        return out
+
+    def inv_laplacian(self, X, out=None):
+        """2-D model: psi = L zeta for the columns of X (n,) or (n, k)."""
+        k = X.shape[1] if X.dim() == 2 else 1
+        out = out if out is not None else torch.empty_like(X)
+        _check(_lib.rp4d_bve_inv_laplacian(self._h, k, _ptr(X, None, self.n * k, "X"),
+                                           _ptr(out, X.dtype, self.n * k, "out"), _dt(X)))
         return out
 
     def tlm(self, traj, V, out=None):

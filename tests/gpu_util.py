@@ -42,10 +42,10 @@ class Pair:
     `gpu` (rp4d.Problem) with identical x_b and y, plus the GPU trajectory at x_b."""
 
     def __init__(self, cfg, seed=0, ckpt_every=0, ctx=None):
-        from oracle.problem import burgers_problem
+        from oracle.problem import make_problem
         from paper_2401_15758_amd import inputs, rp4d
         self.cfg = cfg
-        self.orc = burgers_problem(cfg, inputs.draws(cfg, seed=seed))
+        self.orc = make_problem(cfg, inputs.draws(cfg, seed=seed))
         self.ctx = ctx or rp4d.Context(0)
         self.gpu = rp4d.Problem(self.ctx, cfg, ckpt_every=ckpt_every)
         self.gpu.set_data(to_dev(self.orc.xb), to_dev(self.orc.y.reshape(-1)))

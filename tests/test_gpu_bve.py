@@ -1,0 +1,177 @@
+"""GPU parity of the barotropic-vorticity path (2-D model) with the FP64 oracle:
+the spectral inverse Laplacian and the separable prior square root (dense
+Fourier-basis products on the matrix cores), the RK4 trajectory and cost, the
+TLM / ADJ block sweeps, the block Hessian, the gradient and one Gauss-Newton
+step; sampled checks at the 256 x 256 size; FP32 sweeps; argument errors.
+
+The oracle computes L with a library FFT and the prior with dense circulant
+matrices, the GPU with the real Fourier basis, so the two share no arithmetic;
+they differ by rounding only (~1e-15 per operator application, ~1e-13 after a
+few hundred RK4 stages)."""
+import numpy as np
+import pytest
+
+from gpu_util import Pair, colwise_relerr, need_gpu, relerr, to_dev, to_np
+from paper_2401_15758_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-12
+SMALL = inputs.bve_config(32, nsteps=12, obs_stride=8, obs_every=4, L_cells=3.0, ell=10, name='bve-32')
+# ragged observation layout (48 not a multiple of the stride 5), odd window
+RAGGED = inputs.bve_config(48, nsteps=9, obs_stride=5, obs_every=4, L_cells=2.5, ell=6, name='bve-48')
+
+
+@pytest.fixture(scope="module")
+def small():
+    need_gpu()
+    return Pair(SMALL)
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+@pytest.mark.parametrize("nx,k", [(32, 3), (64, 1), (256, 2)])
+def test_inverse_laplacian_parity(nx, k):
+    torch = need_gpu()
+    from oracle import bve
+    from paper_2401_15758_amd import rp4d
+    cfg = inputs.bve_config(nx, nsteps=4, obs_stride=8, obs_every=2)
+    p = rp4d.Problem(rp4d.Context(0), cfg)
+    Z = _rand((nx * nx, k), 5)
+    got = to_np(p.inv_laplacian(to_dev(Z)))
+    ref = bve.inv_lap(Z.reshape(nx, nx, k)).reshape(nx * nx, k)
+    assert colwise_relerr(got, ref) <= 1e-13
+    got32 = to_np(p.inv_laplacian(to_dev(Z, torch.float32)))
+    assert colwise_relerr(got32, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("nx,k,L", [(32, 2, 3.0), (64, 3, 8.0), (256, 1, 8.0)])
+def test_prior_sqrt_parity(nx, k, L):
+    need_gpu()
+    from oracle import prior
+    from paper_2401_15758_amd import rp4d
+    cfg = inputs.bve_config(nx, nsteps=4, obs_stride=8, obs_every=2, L_cells=L)
+    p = rp4d.Problem(rp4d.Context(0), cfg)
+    V = _rand((nx * nx, k), 6)
+    got = to_np(p.bhalf(to_dev(V)))
+    ref = prior.bhalf_2d(V, nx, nx, cfg['sigma_b'], L)
+    assert colwise_relerr(got, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("cfg", [SMALL, RAGGED], ids=["bve-32", "bve-48-ragged"])
+def test_fwd_observations_and_cost(cfg):
+    need_gpu()
+    pr = Pair(cfg, seed=2)
+    obs = to_np(pr.gpu.observe(pr.traj))
+    assert relerr(obs, pr.orc.observe(pr.otraj)) <= 1e-13
+    d = pr.orc.innovations(pr.otraj)
+    assert pr.Jobs == pytest.approx(0.5 * float(np.sum(d * d)), rel=1e-12)
+
+
+@pytest.mark.parametrize("cfg", [SMALL, RAGGED], ids=["bve-32", "bve-48-ragged"])
+def test_tlm_adj_hessian_parity(cfg):
+    need_gpu()
+    pr = Pair(cfg, seed=3)
+    o, g = pr.orc, pr.gpu
+    k = 3
+    V = _rand((o.n, k), 7)
+    Z = to_np(g.tlm(pr.traj, to_dev(V)))
+    assert colwise_relerr(Z.reshape(-1, k), o.A(pr.otraj, V).reshape(-1, k)) <= TOL_OP
+    W = _rand((o.n_t, o.n_obs, k), 8)
+    U = to_np(g.adj(pr.traj, to_dev(W)))
+    assert colwise_relerr(U, o.AT(pr.otraj, W)) <= TOL_OP
+    HV = to_np(g.hessian_block(pr.traj, to_dev(V)))
+    assert colwise_relerr(HV, o.hessian(pr.otraj, V)) <= TOL_OP
+
+
+def test_dot_product_identity(small):
+    """<A v, w> = <v, A^T w> on the GPU alone (FP64)."""
+    pr = small
+    v = _rand((pr.orc.n, 1), 9)
+    w = _rand((pr.orc.n_t, pr.orc.n_obs, 1), 10)
+    Av = to_np(pr.gpu.tlm(pr.traj, to_dev(v)))
+    ATw = to_np(pr.gpu.adj(pr.traj, to_dev(w)))
+    lhs, rhs = float(np.sum(Av.reshape(-1) * w.reshape(-1))), float(np.sum(v * ATw))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(Av) * np.linalg.norm(w)
+
+
+def test_gradient_parity(small):
+    pr = small
+    v = np.zeros(pr.orc.n)
+    J, gref, _, _ = pr.orc.cost_grad(v)
+    g = to_np(pr.gpu.gradient(pr.traj, to_dev(v)))
+    assert relerr(g, gref) <= TOL_OP
+
+
+def test_fp32_sweeps_close_to_oracle(small):
+    torch = need_gpu()
+    pr = small
+    V = _rand((pr.orc.n, 4), 11)
+    HV = to_np(pr.gpu.hessian_block(pr.traj, to_dev(V, torch.float32)))
+    assert colwise_relerr(HV, pr.orc.hessian(pr.otraj, V)) <= 1e-4
+
+
+def test_synthesis_parity():
+    need_gpu()
+    from oracle.problem import bve_problem
+    from paper_2401_15758_amd import rp4d
+    cfg = SMALL
+    d = inputs.draws(cfg, seed=4)
+    orc = bve_problem(cfg, d)
+    p = rp4d.Problem(rp4d.Context(0), cfg)
+    xb, y = p.synthesize(to_dev(d['x_true']), to_dev(d['xi']), to_dev(d['eta'].reshape(-1)))
+    assert relerr(to_np(xb), orc.xb) <= 1e-14
+    assert relerr(to_np(y), orc.y) <= 1e-13
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_gn_step_parity(method):
+    need_gpu()
+    from oracle import gn as ogn
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(SMALL, seed=5)
+    ell = SMALL['ell']
+    Om = inputs.omega(pr.orc.n, ell, seed=1000)
+    v1, dv, x1, info = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method=method, Omega=Om, rtol=1e-12)
+    st = pr.gpu.gn_state()
+    code = rp4d.NYSTROM if method == "nystrom" else rp4d.RANDSVD
+    gi = pr.gpu.gn_step(st, sketch=code, ell=ell, omega=to_dev(Om), rtol=1e-12)
+    _, gx = st.get()
+    assert gi['J'] == pytest.approx(info['J'], rel=1e-12)
+    assert abs(gi['pcg_iters'] - info['pcg']['iters']) <= 2
+    assert relerr(to_np(st.last_step()), dv) <= 1e-10
+    assert relerr(to_np(gx), x1) <= 1e-10
+
+
+def test_full_size_sampled():
+    """256 x 256 grid (the bve-256 grid and observation layout), 20-step window:
+    observations, cost and two Hessian columns against the oracle."""
+    need_gpu()
+    cfg = inputs.bve_config(256, nsteps=20, obs_stride=16, obs_every=10)
+    pr = Pair(cfg, seed=6)
+    obs = to_np(pr.gpu.observe(pr.traj))
+    assert relerr(obs, pr.orc.observe(pr.otraj)) <= 1e-13
+    V = _rand((pr.orc.n, 2), 12)
+    HV = to_np(pr.gpu.hessian_block(pr.traj, to_dev(V)))
+    assert colwise_relerr(HV, pr.orc.hessian(pr.otraj, V)) <= TOL_OP
+
+
+def test_bad_arguments():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx = rp4d.Context(0)
+    with pytest.raises(rp4d.Rp4dError):
+        rp4d.Problem(ctx, inputs.bve_config(40, nsteps=4, obs_every=2))      # not a multiple of 16
+    with pytest.raises(rp4d.Rp4dError):
+        rp4d.Problem(ctx, SMALL, ckpt_every=4)                               # 2-D stores every state
+    with pytest.raises(rp4d.Rp4dError):
+        rp4d.Problem(ctx, inputs.bve_config(32, nsteps=4, obs_every=2, nu=1.0))   # unstable
+    p = rp4d.Problem(ctx, SMALL)
+    with pytest.raises(rp4d.Rp4dError):
+        rp4d.Batch(ctx, [p])                                                  # batches hold 1-D problems
+    b = rp4d.Problem(ctx, inputs.CFG_SMALL)
+    import torch
+    with pytest.raises(rp4d.Rp4dError):
+        b.inv_laplacian(torch.zeros(128, dtype=torch.float64, device="cuda"))
