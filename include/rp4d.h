@@ -277,6 +277,14 @@ enum {
     RP4D_K_COUNT = 9
 };
 int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
+
+/* PCG solves (rp4d_pcg_solve, rp4d_gn_step) that run past two iterations
+ * capture the iteration body -- the Hessian product, the dot products, the
+ * x/r/p updates and the preconditioner -- once into a HIP graph on a
+ * library-owned stream and replay it on the context stream for the remaining
+ * iterations (results are bitwise those of the eager loop).  Enabled by
+ * default; enable = 0 runs every iteration eagerly. */
+int rp4d_ctx_set_graphs(rp4d_ctx* ctx, int enable);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
 
 /* ---------------------------------------------------------------------------

@@ -37,7 +37,7 @@ void DevBuf::release() {
 }
 
 KernelTimer::KernelTimer(rp4d_ctx* ctx, int k, double fl) : c(ctx), kind(k), flops(fl) {
-    if (!c->timing) return;
+    if (!c->timing || c->capturing) return;
     if (c->event_pool.empty()) {
         hipEvent_t e;
         RP4D_HIP(hipEventCreate(&e));
@@ -531,6 +531,7 @@ void check_common(const rp4d_problem* p, int k, const void* a, const void* b) {
 }  // namespace rp4d
 
 rp4d_ctx::~rp4d_ctx() {
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& pe : pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
@@ -1207,6 +1208,41 @@ int rp4d_precond_apply(const rp4d_precond* pc, int k, const double* R, double* Z
 namespace rp4d {
 namespace {
 
+// Capture the work `f` enqueues on the context stream into an executable graph
+// (recorded on a library-owned stream; nothing runs during capture).
+struct GraphExec {
+    hipGraphExec_t ex = nullptr;
+    ~GraphExec() {
+        if (ex) (void)hipGraphExecDestroy(ex);
+    }
+};
+
+template <typename F>
+void capture(rp4d_ctx* c, F&& f, GraphExec& out) {
+    if (!c->cap_stream) RP4D_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t orig = c->stream;
+    RP4D_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    c->capturing = true;
+    hipGraph_t g = nullptr;
+    try {
+        f();
+    } catch (...) {
+        (void)hipStreamEndCapture(c->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        c->stream = orig;
+        c->capturing = false;
+        throw;
+    }
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = orig;
+    c->capturing = false;
+    RP4D_HIP(e);
+    const hipError_t e2 = hipGraphInstantiate(&out.ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    RP4D_HIP(e2);
+}
+
 void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, const double* b, double* x,
               double rtol, int maxit, rp4d_pcg_info* info, bool true_res, rp4d::DevBuf& vecs) {
     hipStream_t st = stream_of(p);
@@ -1233,28 +1269,45 @@ void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, cons
     double rnorm = bnorm;
     int it = 0;
     bool conv = bnorm == 0.0 || rnorm <= rtol * bnorm;
-    while (!conv && it < maxit) {
+    // One iteration: q = (I+H)p, alpha, x, r, |r|^2, then speculatively z = P r,
+    // beta and the next p (unused once |r| meets the tolerance).  The stream is
+    // read at each launch so that the same body can be captured into a graph.
+    auto body = [&]() {
         hessian_dispatch(p, tr, 1, pv, q, RP4D_F64, true);
-        launch_dot(pv, q, n, sc + SC_PQ, red, st);
-        pcg_update_xr<<<nblk(n), 256, 0, st>>>(x, r, pv, q, sc, n);
+        hipStream_t s = stream_of(p);
+        launch_dot(pv, q, n, sc + SC_PQ, red, s);
+        pcg_update_xr<<<nblk(n), 256, 0, s>>>(x, r, pv, q, sc, n);
         RP4D_HIP(hipGetLastError());
-        ++it;
-        launch_dot(r, r, n, sc + SC_RR, red, st);
-        rnorm = std::sqrt(read_scalar(p, sc + SC_RR));
-        RP4D_REQUIRE(std::isfinite(rnorm), RP4D_ENONFINITE, "non-finite PCG residual");
-        if (rnorm <= rtol * bnorm) {
-            conv = true;
-            break;
-        }
+        launch_dot(r, r, n, sc + SC_RR, red, s);
         if (pc)
             precond_apply_impl(p, pc, 1, r, z);
         else
-            launch_relayout<double, double>(r, 1, z, 1, n, 1, st);
-        launch_dot(r, z, n, sc + SC_RZN, red, st);
-        pcg_update_p<<<nblk(n), 256, 0, st>>>(pv, z, sc, n);
+            launch_relayout<double, double>(r, 1, z, 1, n, 1, s);
+        launch_dot(r, z, n, sc + SC_RZN, red, s);
+        pcg_update_p<<<nblk(n), 256, 0, s>>>(pv, z, sc, n);
         RP4D_HIP(hipGetLastError());
-        scal_copy<<<1, 1, 0, st>>>(sc, SC_RZ, SC_RZN);
+        scal_copy<<<1, 1, 0, s>>>(sc, SC_RZ, SC_RZN);
         RP4D_HIP(hipGetLastError());
+    };
+    // Long solves replay the body as a graph from the third iteration on (the
+    // first two run eagerly and size every workspace the body touches).
+    GraphExec gx;
+    while (!conv && it < maxit) {
+        if (p->ctx->graphs && it >= 2) {
+            if (!gx.ex) {
+                const long long hv = p->cnt.hv_columns;
+                capture(p->ctx, body, gx);
+                p->cnt.hv_columns = hv;
+            }
+            RP4D_HIP(hipGraphLaunch(gx.ex, st));
+            p->cnt.hv_columns += 1;
+        } else {
+            body();
+        }
+        ++it;
+        rnorm = std::sqrt(read_scalar(p, sc + SC_RR));
+        RP4D_REQUIRE(std::isfinite(rnorm), RP4D_ENONFINITE, "non-finite PCG residual");
+        if (rnorm <= rtol * bnorm) conv = true;
     }
     p->cnt.tlm_online += it;
     p->cnt.adj_online += it;
@@ -1504,6 +1557,13 @@ int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable) {
             ctx->ms[i] = 0.0;
             ctx->flops[i] = 0.0;
         }
+    });
+}
+
+int rp4d_ctx_set_graphs(rp4d_ctx* ctx, int enable) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
+        ctx->graphs = enable != 0;
     });
 }
 

@@ -71,74 +71,78 @@ struct GemmArgs {
     int M, N, K;
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
+constexpr int GBK = 16, GPAD = 16;
 
-// 64 x 64 output tile per workgroup of four waves (2 x 2, 32 x 32 each, as
-// 2 x 2 MFMA 16x16x4 blocks).  Operand fragments: lane l holds A[l%16][l/16]
+// Output tile (32 TM) x (32 TN) per workgroup of four waves (2 x 2), each wave
+// TM x TN MFMA 16x16x4 blocks.  Operand fragments: lane l holds A[l%16][l/16]
 // and B[l/16][l%16]; the accumulator rows held by a lane differ between the
-// FP64 and FP32 instructions (Mfma<T>::row).
-// K is consumed in chunks of 16 staged through LDS (k-major, rows padded by
-// 16 elements so the two half-waves of a fragment read hit disjoint banks);
-// the next chunk's global loads are issued before the current chunk's MFMAs.
-template <typename T>
+// FP64 and FP32 instructions (Mfma<T>::row).  K is consumed in chunks of 16
+// staged through LDS (k-major, rows padded by 16 elements so the two
+// half-waves of a fragment read hit disjoint banks); the next chunk's global
+// loads are issued before the current chunk's MFMAs.
+template <typename T, int TM, int TN>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs<T> g) {
-    __shared__ T As[GBK][GBM + GPAD];
-    __shared__ T Bs[GBK][GBN + GPAD];
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    constexpr int AQ = BM * GBK / 256, BQ = BN * GBK / 256;  // elements per thread per chunk
+    __shared__ T As[GBK][BM + GPAD];
+    __shared__ T Bs[GBK][BN + GPAD];
     typedef typename Mfma<T>::acc_t acc_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int wm = (wave >> 1) * 16 * TM, wn = (wave & 1) * 16 * TN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const long b = blockIdx.z;
     const T* A = g.A + b * g.sA;
     const T* B = g.B + b * g.sB;
     T* C = g.C + b * g.sC;
-    // loader coordinates
-    const int ar = tid >> 2, ak = (tid & 3) * 4;     // A: row, first k of 4
-    const int bk = tid >> 4, bn = (tid & 15) * 4;    // B: k, first column of 4
+    // loader coordinates: AQ consecutive k of one A row, BQ consecutive columns of one B row
+    const int ar = tid / (GBK / AQ), ak = (tid % (GBK / AQ)) * AQ;
+    const int bk = tid / (BN / BQ), bn = (tid % (BN / BQ)) * BQ;
     const bool arow_ok = m0 + ar < g.M;
-    T ra[4], rb[4];
+    T ra[AQ], rb[BQ];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < AQ; ++q) {
             const int kk = k0 + ak + q;
             ra[q] = (arow_ok && kk < g.K) ? A[static_cast<long>(m0 + ar) * g.lda + kk] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
             const int cc = n0 + bn + q;
             rb[q] = (k0 + bk < g.K && cc < g.N) ? B[static_cast<long>(k0 + bk) * g.ldb + cc] : T(0);
         }
     };
-    acc_t acc[2][2];
+    acc_t acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
     load(0);
     const int fr = lane >> 4, fc = lane & 15;
     for (int k0 = 0; k0 < g.K; k0 += GBK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            As[ak + q][ar] = ra[q];
-            Bs[bk][bn + q] = rb[q];
-        }
+        for (int q = 0; q < AQ; ++q) As[ak + q][ar] = ra[q];
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) Bs[bk][bn + q] = rb[q];
         __syncthreads();
         if (k0 + GBK < g.K) load(k0 + GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
-            T af[2], bf[2];
+            T af[TM], bf[TN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = As[kk + fr][wm + i * 16 + fc];
+            for (int i = 0; i < TM; ++i) af[i] = As[kk + fr][wm + i * 16 + fc];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bf[j] = Bs[kk + fr][wn + j * 16 + fc];
+            for (int j = 0; j < TN; ++j) bf[j] = Bs[kk + fr][wn + j * 16 + fc];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mac(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(af[i], bf[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + Mfma<T>::row(fr, r);
@@ -363,8 +367,15 @@ template <typename T>
 void gemm(rp4d_problem* p, const GemmArgs<T>& g, int batch) {
     const double fl = 2.0 * g.M * static_cast<double>(g.N) * g.K * batch;
     KernelTimer kt(p->ctx, RP4D_K_GEMM, fl);
-    dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, batch);
-    gemm_kernel<T><<<grid, 256, 0, bst(p)>>>(g);
+    // 64 x 64 tiles when they give at least two workgroups per CU, else 32 x 32
+    const long big = static_cast<long>((g.N + 63) / 64) * ((g.M + 63) / 64) * batch;
+    if (big >= 512) {
+        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch);
+        gemm_kernel<T, 2, 2><<<grid, 256, 0, bst(p)>>>(g);
+    } else {
+        dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, batch);
+        gemm_kernel<T, 1, 1><<<grid, 256, 0, bst(p)>>>(g);
+    }
     RP4D_HIP(hipGetLastError());
 }
 

@@ -625,6 +625,16 @@ void launch_small_gemm(const double* A, int ta, const double* B, int tb, double*
     RP4D_HIP(hipGetLastError());
 }
 
+// Whether `dyn` bytes of dynamic LDS fit beside the kernel's static LDS.
+bool lds_fits(const void* fn, size_t dyn) {
+    hipFuncAttributes at{};
+    int dev = 0, lim = 0;
+    RP4D_HIP(hipFuncGetAttributes(&at, fn));
+    RP4D_HIP(hipGetDevice(&dev));
+    RP4D_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    return at.sharedSizeBytes + dyn <= static_cast<size_t>(lim);
+}
+
 void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st) {
     RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "eigensolver: l must be in [1, 128]");
     const size_t me = static_cast<size_t>(l + (l & 1));
@@ -637,7 +647,7 @@ void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true, false>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(one));
         jacobi_kernel<true, false><<<1, 1024, one, st>>>(A, evals, nullptr, nullptr, l);
-    } else if (both <= 160 * 1024 - 2048) {
+    } else if (lds_fits(reinterpret_cast<const void*>(&jacobi_kernel<true, true>), both)) {
         if (both > 64 * 1024)
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true, true>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(both));

@@ -108,6 +108,7 @@ _SIGS = {
     "rp4d_problem_synthesize": ([_P, _P, _P, _P, _P, _P], _I),
     "rp4d_gn_state_reset": ([_P], _I),
     "rp4d_ctx_set_timing": ([_P, _I], _I),
+    "rp4d_ctx_set_graphs": ([_P, _I], _I),
     "rp4d_ctx_kernel_stats": ([_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
     "rp4d_batch_create": ([_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
     "rp4d_batch_destroy": ([_P], _I),
@@ -176,6 +177,9 @@ class Context:
 
     def set_timing(self, enable=True):
         _check(_lib.rp4d_ctx_set_timing(self._h, 1 if enable else 0))
+
+    def set_graphs(self, enable=True):
+        _check(_lib.rp4d_ctx_set_graphs(self._h, 1 if enable else 0))
 
     def kernel_stats(self, kind):
         n, ms, fl = ctypes.c_longlong(), _D(), _D()

@@ -191,3 +191,24 @@ def test_fp32_sketch_then_fp64_pcg(small):
     x32, i32 = pr.gpu.pcg_solve(pr.traj, to_dev(b), precond=p32, rtol=1e-10)
     assert i32['converged'] and i32['iters'] <= i64['iters'] + 2
     assert relerr(to_np(x32), to_np(x64)) <= 1e-8
+
+
+@pytest.mark.parametrize("use_prec", [False, True])
+def test_pcg_graph_replay_is_bitwise_eager(small, use_prec):
+    """PCG iterations after the second replay a captured HIP graph of the
+    iteration body; every replay is followed by the eager residual read-back,
+    and the solution must equal the all-eager solve bit for bit."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 7, omega=to_dev(inputs.omega(pr.orc.n, 7))) if use_prec else None
+    b = to_dev(_probe(pr.orc.n, 1, seed=31)[:, 0])
+    out = {}
+    for graphs in (False, True):
+        pr.ctx.set_graphs(graphs)
+        x, info = pr.gpu.pcg_solve(pr.traj, b, precond=pc, rtol=1e-11)
+        torch.cuda.synchronize()
+        out[graphs] = (x.clone(), info['iters'])
+    pr.ctx.set_graphs(True)
+    assert out[True][1] == out[False][1] and out[True][1] >= 5
+    assert torch.equal(out[True][0], out[False][0])
