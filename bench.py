@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning-cache", default=None, help="JSON tiling cache (default: the package's tuning.json)")
     ap.add_argument("--tune-budget", type=float, default=20.0, help="seconds per tuned shape when not cached")
+    ap.add_argument("--no-bve", action="store_true", help="skip the bve-256 section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-64 section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB with a plain elementwise kernel "
                          "(reference dispatch for the HBM byte counters)")
@@ -69,6 +71,101 @@ def measured_traffic(kname, tiling, cfg):
             or any(rec.get("tiling", {}).get(k) != tiling.get(k) for k in keys)):
         return None
     return rec["bytes_per_launch"]
+
+
+def bve_section(rp4d, inputs, torch, np):
+    """bve-256: the 2-D workload.  One FP64 block Hessian product with k = 100
+    (timed per kernel class: the Fourier-basis MFMA GEMMs are the dominant
+    kernel) and one Gauss-Newton iteration (100-column Nystrom sketch, PCG to
+    1e-6) from the background."""
+    cfg = dict(inputs.CFG_BVE)
+    ell = cfg["ell"]
+    ctx = rp4d.Context(0)
+    p = rp4d.Problem(ctx, cfg)
+    d = inputs.draws(cfg, seed=0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    xb, y = p.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
+    p.set_data(xb, y.reshape(-1))
+    tr = p.traj()
+    p.fwd(xb, tr, want_J=False)
+    V = torch.empty((cfg["n"], ell), dtype=torch.float64, device="cuda")
+    ctx.philox_normal(11, V.numel(), V)
+    HV = torch.empty_like(V)
+    p.hessian_block(tr, V, HV)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    p.hessian_block(tr, V, HV)
+    torch.cuda.synchronize()
+    hb = time.perf_counter() - t0
+    g, sten = ctx.kernel_stats(rp4d.K_GEMM), ctx.kernel_stats(rp4d.K_STENCIL)
+    ctx.set_timing(False)
+    gemm_tf = g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12
+    st = p.gn_state()
+    p.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = p.gn_step(st, sketch=rp4d.NYSTROM, ell=ell, seed=1000, sketch_dtype=rp4d.F64, rtol=1e-6)
+    torch.cuda.synchronize()
+    gn = time.perf_counter() - t0
+    cnt = p.counters()
+    return {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "k": ell,
+            "gn_step_s": gn, "pcg_iters": info["pcg_iters"], "hv_per_s": cnt["hv_columns"] / gn,
+            "hessian_block_k100_ms": 1e3 * hb, "hessian_block_hv_per_s": ell / hb,
+            "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double, 2, 2> (Fourier-basis products, k=100)",
+                         "achieved": gemm_tf, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": gemm_tf / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                         "avg_launch_us": 1e3 * g["total_ms"] / max(1, g["launches"]), "launches": g["launches"]},
+            "stencil_ms": sten["total_ms"], "gemm_ms": g["total_ms"]}
+
+
+def batch_section(rp4d, inputs, torch, np):
+    """batch-64: 64 uneven Burgers problems (n in [256, 4096], N in [50, 500]),
+    one batched Gauss-Newton iteration each (32-column Nystrom sketch, FP64 PCG
+    to 1e-6), with FP64 and with FP32 sketch sweeps, against the same 64
+    iterations run one problem at a time through the single-problem FP64 path."""
+    cfgs = inputs.batch_configs(64, seed=0)
+    ctx = rp4d.Context(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    probs, states = [], []
+    for i, cfg in enumerate(cfgs):
+        p = rp4d.Problem(ctx, cfg)
+        p.set_id(i)
+        d = inputs.draws(cfg, seed=cfg["seed"] % (2 ** 31))
+        xb, y = p.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
+        p.set_data(xb, y.reshape(-1))
+        probs.append(p)
+        states.append(p.gn_state())
+    b = rp4d.Batch(ctx, probs)
+    res = {"workload": "batch-64", "problems": len(cfgs), "k": 32}
+    for name, skd in (("f64", rp4d.F64), ("f32", rp4d.F32)):
+        times = []
+        for rep in range(3):
+            for s in states:
+                s.reset()
+            for p in probs:
+                p.reset_counters()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=32, seed=1, sketch_dtype=skd, rtol=1e-6)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        hv = sum(p.counters()["hv_columns"] for p in probs)
+        t = min(times[1:])
+        res[f"sketch_{name}"] = {"gn_step_ms": 1e3 * t, "hv_per_s": hv / t,
+                                 "pcg_iters_max": max(i["pcg_iters"] for i in infos),
+                                 "pcg_iters_total": sum(i["pcg_iters"] for i in infos)}
+    for s in states:
+        s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, s in zip(probs, states):
+        p.gn_step(s, sketch=rp4d.NYSTROM, ell=32, seed=1, sketch_dtype=rp4d.F64, rtol=1e-6)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    res["sequential_f64_gn_ms"] = 1e3 * seq
+    res["speedup_vs_sequential"] = seq / (res["sketch_f64"]["gn_step_ms"] * 1e-3)
+    return res
 
 
 def cpu_baseline(cfg, ell, rtol):
@@ -214,6 +311,10 @@ def main():
         "counters": cnt,
         "tiling": tilings,
     }
+    if not args.no_bve:
+        out["bve"] = bve_section(rp4d, inputs, torch, np)
+    if not args.no_batch:
+        out["batch"] = batch_section(rp4d, inputs, torch, np)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
     if args.calib_copy_mib > 0:

@@ -10,7 +10,7 @@ scheme; the periodic RK4 variant is the measured workload and is recorded as a
 reading in the design notes.
 
 The tangent-linear and adjoint are the *discrete* Runge-Kutta TLM and adjoint
-(Sec. 2.1, last paragraph; Sec. 5.1: "the discrete Runge Kutta TLM and ADJ"),
+(Sec. 2.1, last paragraph; Sec. 5.1 names the discrete Runge-Kutta versions),
 i.e. the exact linearisation of the stage recurrences and its exact transpose,
 not a discretisation of the continuous adjoint PDE.
 

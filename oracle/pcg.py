@@ -6,8 +6,7 @@ Follows Sec. 2.2.2 (SketchPrec, eq. (pcgsystem)): CG on the first-level
 preconditioned GN system, preconditioned by the limited-memory preconditioner of
 eq. (woodbury) (or by the identity: the paper's Prec_Gamma).  Readings: x_0 = 0;
 the loop stops when the recurrence residual satisfies ||r_k||_2 <= rtol ||b||_2
-(Sec. 5, "PCG is terminated when the relative residual ... achieves a
-prespecified tolerance"); every iteration costs exactly one (I + H) product
+(Sec. 5 stops PCG on a prescribed relative residual); every iteration costs exactly one (I + H) product
 (online TLM = number of PCG iterations, Tables 2 and 4).
 """
 import numpy as np

@@ -155,6 +155,58 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs<T> g) {
             }
 }
 
+// Small products (single fields): a 16 x 16 output tile per workgroup of four
+// waves, each wave accumulating a contiguous quarter of K straight from global
+// memory into registers (16 MFMA steps per batch of loads, so one memory
+// latency per batch), then the four partial tiles are summed in a fixed order
+// through LDS.  K must be a multiple of 16.
+template <typename T>
+__global__ void __launch_bounds__(256) gemm_ksplit_kernel(GemmArgs<T> g) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    __shared__ T part[3][64][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
+    const long b = blockIdx.z;
+    const T* A = g.A + b * g.sA;
+    const T* B = g.B + b * g.sB;
+    T* C = g.C + b * g.sC;
+    const int fr = lane >> 4, fc = lane & 15;
+    const int arow = m0 + fc, bcol = n0 + fc;
+    const bool aok = arow < g.M, bok = bcol < g.N;
+    const int kq = g.K / 4, kw0 = wave * kq, kw1 = kw0 + kq;
+    acc_t acc = acc_t{0, 0, 0, 0};
+    for (int kb = kw0; kb < kw1; kb += 64) {
+        T a[16], bb[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int k = kb + 4 * s + fr;
+            const bool kin = k < kw1;
+            a[s] = (aok && kin) ? A[static_cast<long>(arow) * g.lda + k] : T(0);
+            bb[s] = (bok && kin) ? B[static_cast<long>(k) * g.ldb + bcol] : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = Mfma<T>::mac(a[s], bb[s], acc);
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[wave - 1][lane][r] = acc[r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const T v0 = acc[r] + part[0][lane][r];
+            const T v1 = part[1][lane][r] + part[2][lane][r];
+            const int row = m0 + Mfma<T>::row(fr, r), col = n0 + fc;
+            if (row < g.M && col < g.N) {
+                T v = v0 + v1;
+                if (g.D) v = v * g.D[static_cast<long>(row) * g.ldd + col / g.cdiv];
+                C[static_cast<long>(row) * g.ldc + col] = v;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // stencils
 // ---------------------------------------------------------------------------
@@ -367,14 +419,20 @@ template <typename T>
 void gemm(rp4d_problem* p, const GemmArgs<T>& g, int batch) {
     const double fl = 2.0 * g.M * static_cast<double>(g.N) * g.K * batch;
     KernelTimer kt(p->ctx, RP4D_K_GEMM, fl);
-    // 64 x 64 tiles when they give at least two workgroups per CU, else 32 x 32
+    RP4D_REQUIRE(g.K % 16 == 0, RP4D_EINVAL, "Fourier-basis product: K must be a multiple of 16");
+    // 64 x 64 tiles when they give at least two workgroups per CU, 32 x 32 when
+    // those fill the CUs, else (single fields) 16 x 16 tiles with K split over waves
     const long big = static_cast<long>((g.N + 63) / 64) * ((g.M + 63) / 64) * batch;
+    const long mid = static_cast<long>((g.N + 31) / 32) * ((g.M + 31) / 32) * batch;
     if (big >= 512) {
         dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch);
         gemm_kernel<T, 2, 2><<<grid, 256, 0, bst(p)>>>(g);
-    } else {
+    } else if (mid >= 256) {
         dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, batch);
         gemm_kernel<T, 1, 1><<<grid, 256, 0, bst(p)>>>(g);
+    } else {
+        dim3 grid((g.N + 15) / 16, (g.M + 15) / 16, batch);
+        gemm_ksplit_kernel<T><<<grid, 256, 0, bst(p)>>>(g);
     }
     RP4D_HIP(hipGetLastError());
 }
