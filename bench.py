@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--tune-budget", type=float, default=20.0, help="seconds per tuned shape when not cached")
     ap.add_argument("--no-bve", action="store_true", help="skip the bve-256 section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-64 section")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serve-mix section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB with a plain elementwise kernel "
                          "(reference dispatch for the HBM byte counters)")
@@ -166,6 +167,25 @@ def batch_section(rp4d, inputs, torch, np):
     res["sequential_f64_gn_ms"] = 1e3 * seq
     res["speedup_vs_sequential"] = seq / (res["sketch_f64"]["gn_step_ms"] * 1e-3)
     return res
+
+
+def serve_section():
+    """serve-mix: a Poisson stream of 24 solves (70 % Burgers, n 512-8192, 100-500
+    steps; 30 % vorticity at 64^2-128^2, 100-200 steps; 3 GN iterations to 1e-6
+    each).  The served path's capacity is measured with every request queued at
+    once; the same stream then arrives at 0.7 x that rate and runs through the
+    served path and through the plain FP64 one-at-a-time path."""
+    from paper_2401_15758_amd import serve
+    kw = dict(bve_nx=(64, 128), bve_N=(100, 200))
+    cap = serve.summary(serve.serve(serve.make_trace(24, 0.0, seed=7, **kw)))
+    rate = 0.7 * cap["solves_per_s"]
+    trace = serve.make_trace(24, rate, seed=7, **kw)
+    served = serve.summary(serve.serve(serve.clone_trace(trace)))
+    seq = serve.summary(serve.serve_sequential(serve.clone_trace(trace)))
+    return {"workload": "serve-mix", "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate": rate,
+            "served": served, "sequential_fp64": seq,
+            "throughput_ratio": served["solves_per_s"] / seq["solves_per_s"],
+            "p99_ratio": seq["p99_latency_s"] / served["p99_latency_s"]}
 
 
 def cpu_baseline(cfg, ell, rtol):
@@ -315,6 +335,8 @@ def main():
         out["bve"] = bve_section(rp4d, inputs, torch, np)
     if not args.no_batch:
         out["batch"] = batch_section(rp4d, inputs, torch, np)
+    if not args.no_serve:
+        out["serve"] = serve_section()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
     if args.calib_copy_mib > 0:

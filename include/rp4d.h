@@ -282,8 +282,10 @@ int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
  * capture the iteration body -- the Hessian product, the dot products, the
  * x/r/p updates and the preconditioner -- once into a HIP graph on a
  * library-owned stream and replay it on the context stream for the remaining
- * iterations (results are bitwise those of the eager loop).  Enabled by
- * default; enable = 0 runs every iteration eagerly. */
+ * iterations (results are bitwise those of the eager loop).  Off by default:
+ * capture must not overlap legacy-stream operations (synchronous copies,
+ * frees) issued by other threads of the process, so enable it only where one
+ * thread drives the device. */
 int rp4d_ctx_set_graphs(rp4d_ctx* ctx, int enable);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
 

@@ -657,7 +657,8 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
                 g[i] = d.sigma_b * a * std::exp(-(r * r) / (L * L));
             }
             p->gk.ensure(g.size() * sizeof(double));
-            RP4D_HIP(hipMemcpy(p->gk.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
+            RP4D_HIP(hipMemcpyAsync(p->gk.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            RP4D_HIP(hipStreamSynchronize(ctx->stream));
             // Spectral form: the circulant's eigenvalues are the DFT of the kernel,
             // ~ exp(-pi^2 kappa^2 L^2) of the largest, below 2^-60 beyond
             // kappa_max = sqrt(60 ln 2)/(pi L); keep kappa <= kappa_max + 2 when that
@@ -697,8 +698,9 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
                 p->r = r;
                 p->F.ensure(Fh.size() * sizeof(double));
                 p->lamF.ensure(lh.size() * sizeof(double));
-                RP4D_HIP(hipMemcpy(p->F.p, Fh.data(), Fh.size() * sizeof(double), hipMemcpyHostToDevice));
-                RP4D_HIP(hipMemcpy(p->lamF.p, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
+                RP4D_HIP(hipMemcpyAsync(p->F.p, Fh.data(), Fh.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+                RP4D_HIP(hipMemcpyAsync(p->lamF.p, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+                RP4D_HIP(hipStreamSynchronize(ctx->stream));  // Fh, lh are freed at the end of this block
             }
             p->xb.ensure(p->n * sizeof(double));
             p->y.ensure(static_cast<size_t>(p->m) * sizeof(double));

@@ -549,12 +549,15 @@ void bve_setup(rp4d_problem* p) {
             dl[static_cast<size_t>(r) * nx + c] = k2 > 0 ? -1.0 / k2 : 0.0;
             dp[static_cast<size_t>(r) * nx + c] = d.sigma_b * sy[r] * sx[c];
         }
+    // copies on the context stream (never the legacy stream), completed before the
+    // host tables go out of scope
     auto upload = [&](DevBuf& dst, DevBuf& dstf, const std::vector<double>& h) {
         dst.ensure(h.size() * sizeof(double));
-        RP4D_HIP(hipMemcpy(dst.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+        RP4D_HIP(hipMemcpyAsync(dst.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, bst(p)));
         std::vector<float> f(h.begin(), h.end());
         dstf.ensure(f.size() * sizeof(float));
-        RP4D_HIP(hipMemcpy(dstf.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        RP4D_HIP(hipMemcpyAsync(dstf.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, bst(p)));
+        RP4D_HIP(hipStreamSynchronize(bst(p)));
     };
     upload(b->basis, b->basis_f, all);
     upload(b->dlap, b->dlap_f, dl);

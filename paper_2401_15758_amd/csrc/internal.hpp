@@ -252,7 +252,7 @@ struct rp4d_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     // graph replay of the PCG iteration body (captured on a library stream)
-    bool graphs = true;
+    bool graphs = false;
     bool capturing = false;
     hipStream_t cap_stream = nullptr;
     long long launches[RP4D_K_COUNT] = {};

@@ -1,0 +1,60 @@
+"""GPU tests of the serving loop: each request's result is bitwise the same
+served in a mix (continuous batching, concurrent 2-D lanes, sketch reuse) and
+alone; admission never holds more than the budget; the footprint estimate
+bounds the device memory a request actually holds."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu
+from paper_2401_15758_amd import inputs, serve
+
+pytestmark = pytest.mark.gpu
+
+SMALL_MIX = dict(burgers_n=(256, 700), burgers_N=(40, 80), bve_nx=(32, 48), bve_N=(20, 40))
+
+
+def test_alone_and_in_mix_bitwise():
+    need_gpu()
+    trace = serve.make_trace(8, rate=40.0, seed=11, frac_burgers=0.65, **SMALL_MIX)
+    assert {r.model for r in trace} == {"burgers", "bve"}
+    mixed = serve.serve(serve.clone_trace(trace))
+    for r in mixed:
+        assert r.gn_done == 3 and len(r.J) == 3 and r.J[-1] < r.J[0]
+        alone = serve.serve([serve.Request(rid=r.rid, cfg=dict(r.cfg), arrival=0.0, seed=r.seed)])[0]
+        assert np.array_equal(alone.x, r.x), r.cfg["name"]
+        assert alone.pcg_iters == r.pcg_iters and alone.reused == r.reused
+
+
+def test_admission_respects_budget():
+    need_gpu()
+    trace = serve.make_trace(10, rate=0.0, seed=12, frac_burgers=0.8, **SMALL_MIX)
+    fps = {r.rid: serve.footprint_bytes(r.cfg) for r in trace}
+    budget = int(2.5 * max(fps.values()))
+    done = serve.serve(serve.clone_trace(trace), budget_bytes=budget)
+    events = sorted({r.admitted for r in done} | {r.done for r in done})
+    for t in events:
+        held = sum(fps[r.rid] for r in done if r.admitted <= t < r.done)
+        assert held <= budget
+    assert all(r.gn_done == 3 for r in done)
+
+
+@pytest.mark.parametrize("which", ["burgers", "bve"])
+def test_footprint_estimate_bounds_device_memory(which):
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    cfg = (inputs.burgers_config(2048, 200, 4, 10, ell=32) if which == "burgers"
+           else inputs.bve_config(64, nsteps=60, obs_stride=16, obs_every=20, ell=100))
+    req = serve.Request(rid=0, cfg=cfg, arrival=0.0, seed=5)
+    torch.cuda.synchronize()
+    free0, res0 = torch.cuda.mem_get_info()[0], torch.cuda.memory_reserved()
+    ctx = rp4d.Context(0)
+    p, st = serve._setup(rp4d, torch, ctx, req)
+    p.gn_step(st, ell=cfg["ell"], seed=1, rtol=1e-6)
+    torch.cuda.synchronize()
+    free1, res1 = torch.cuda.mem_get_info()[0], torch.cuda.memory_reserved()
+    held = (free0 - free1) - (res1 - res0)        # library allocations only
+    est = serve.footprint_bytes(cfg)
+    assert 0 < held <= est, (held, est)
+    assert est <= 3 * held + (64 << 20)           # not uselessly loose
+    st.close()
+    p.close()

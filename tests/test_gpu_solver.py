@@ -209,6 +209,6 @@ def test_pcg_graph_replay_is_bitwise_eager(small, use_prec):
         x, info = pr.gpu.pcg_solve(pr.traj, b, precond=pc, rtol=1e-11)
         torch.cuda.synchronize()
         out[graphs] = (x.clone(), info['iters'])
-    pr.ctx.set_graphs(True)
+    pr.ctx.set_graphs(False)
     assert out[True][1] == out[False][1] and out[True][1] >= 5
     assert torch.equal(out[True][0], out[False][0])
