@@ -987,7 +987,7 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
-        launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+        launch_sym_lmax(s.S2, l, s.lam, s.S3, st);
     }
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
@@ -1063,7 +1063,7 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s) {
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
-        launch_jacobi_eig(s.S2, s.lam, nullptr, l, st);
+        launch_sym_lmax(s.S2, l, s.lam, s.S3, st);
     }
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));

@@ -502,6 +502,89 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(double* A, double* evals, 
     }
 }
 
+// Largest eigenvalue of a symmetric PSD l x l matrix G (l <= 64), padded with
+// zeros to 64 x 64 (which adds only zero eigenvalues).  NSQ normalised squarings
+// B <- B^2 / max diag(B^2), each a 64 x 64 x 64 product on FP64 MFMA (one
+// 16 x 16 output block per wave), concentrate B on the top eigenspace; the
+// Rayleigh quotient of G at B's heaviest column is then lambda_max.  Its error
+// is second order in the angle to that eigenspace: at most ~2^-(NSQ+1) relative
+// when the two largest eigenvalues nearly coincide, and rounding otherwise.
+constexpr int LMAX_SQUARINGS = 24;
+typedef double lmax_v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(1024) lmax_squaring_kernel(const double* __restrict__ G, int l, double* out) {
+    constexpr int M = 64, LD = 65;
+    __shared__ double S[2][M * LD];
+    __shared__ double w[M];
+    __shared__ double scal[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < M * M; e += 1024) {
+        const int i = e / M, j = e % M;
+        S[0][i * LD + j] = (i < l && j < l) ? 0.5 * (G[i * l + j] + G[j * l + i]) : 0.0;
+    }
+    if (tid == 0) scal[0] = 1.0;
+    __syncthreads();
+    const int bi = wave >> 2, bj = wave & 3;   // this wave's 16 x 16 output block
+    const int fr = lane >> 4, fc = lane & 15;
+    int cur = 0;
+    for (int it = 0; it < LMAX_SQUARINGS; ++it) {
+        const double* B = S[cur];
+        double* B2 = S[cur ^ 1];
+        const double inv = scal[0];
+        lmax_v4d acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < M / 4; ++ks) {
+            const double a = inv * B[(bi * 16 + fc) * LD + 4 * ks + fr];
+            const double b = inv * B[(4 * ks + fr) * LD + bj * 16 + fc];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        // FP64 16x16x4 accumulator: element r of lane l is row 4r + l/16, column l%16
+#pragma unroll
+        for (int r = 0; r < 4; ++r) B2[(bi * 16 + 4 * r + fr) * LD + bj * 16 + fc] = acc[r];
+        __syncthreads();
+        if (wave == 0) {
+            double d = B2[lane * LD + lane];
+            for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o));
+            if (lane == 0) scal[0] = d > 0.0 ? 1.0 / d : 1.0;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // heaviest column of B (largest diagonal entry; lowest index on ties)
+    const double* B = S[cur];
+    if (wave == 0) {
+        double d = B[lane * LD + lane];
+        int idx = lane;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double d2 = __shfl_xor(d, o);
+            const int i2 = __shfl_xor(idx, o);
+            if (d2 > d || (d2 == d && i2 < idx)) {
+                d = d2;
+                idx = i2;
+            }
+        }
+        if (lane == 0) scal[1] = static_cast<double>(idx);
+    }
+    __syncthreads();
+    const int jc = static_cast<int>(scal[1]);
+    // w = G v (v = column jc of B), then v.w / v.v
+    if (tid < l) {
+        double acc = 0.0;
+        for (int k = 0; k < l; ++k) acc = fma(0.5 * (G[tid * l + k] + G[k * l + tid]), B[k * LD + jc], acc);
+        w[tid] = acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const double v = lane < l ? B[lane * LD + jc] : 0.0;
+        double num = lane < l ? v * w[lane] : 0.0, den = v * v;
+        for (int o = 32; o > 0; o >>= 1) {
+            num += __shfl_xor(num, o);
+            den += __shfl_xor(den, o);
+        }
+        if (lane == 0) out[0] = den > 0.0 ? num / den : 0.0;
+    }
+}
+
 inline dim3 grid_for(size_t count, int threads = 256) {
     size_t b = (count + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -633,6 +716,17 @@ bool lds_fits(const void* fn, size_t dyn) {
     RP4D_HIP(hipGetDevice(&dev));
     RP4D_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
     return at.sharedSizeBytes + dyn <= static_cast<size_t>(lim);
+}
+
+void launch_sym_lmax(const double* G, int l, double* out, double* work, hipStream_t st) {
+    if (l <= 64) {
+        lmax_squaring_kernel<<<1, 1024, 0, st>>>(G, l, out);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    // larger orders: eigenvalues of a copy by the Jacobi solver (descending: out[0])
+    launch_relayout<double, double>(G, 1, work, 1, l * l, 1, st);
+    launch_jacobi_eig(work, out, nullptr, l, st);
 }
 
 void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st) {
