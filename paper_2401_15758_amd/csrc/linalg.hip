@@ -502,6 +502,124 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(double* A, double* evals, 
     }
 }
 
+// Cyclic Jacobi for orders m <= 64 (l padded to even m), the same rotations,
+// ordering and stopping rule as jacobi_kernel with fewer dependent LDS trips per
+// round: pair indices come from the round number in closed form, thread
+// (bi, bj) owns the 2 x 2 block of pairs (bi, bj) of A and the eigenvector
+// entries of rows 2bj, 2bj+1 in the columns of pair bi, so after the rotation
+// parameters are published (one barrier) each thread loads its block, its V
+// entries and two (c, s) pairs at once, updates them and stores (one barrier).
+__device__ __forceinline__ void circle_pair(int t, int round, int m, int& p, int& q) {
+    const int mm = m - 1;
+    int a = t == 0 ? 0 : t - 1 + round;
+    if (t != 0) a = (a >= mm ? a - mm : a) + 1;
+    int b = m - 2 - t + round;
+    b = (b >= mm ? b - mm : b) + 1;
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+template <bool WANTV>
+__global__ void __launch_bounds__(1024) jacobi64_kernel(const double* A, double* evals, double* evecs, int l) {
+    constexpr int LD = 65;
+    __shared__ double sA[64 * LD];
+    __shared__ double V[WANTV ? 64 * LD : 1];
+    __shared__ double cs[32], sn[32];
+    __shared__ double red[16];
+    __shared__ int rotated;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = l + (l & 1), half = m / 2;
+    for (int e = tid; e < m * m; e += 1024) {
+        const int i = e / m, j = e % m;
+        sA[i * LD + j] = (i < l && j < l) ? 0.5 * (A[i * l + j] + A[j * l + i]) : 0.0;
+        if (WANTV) V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // Frobenius norm (invariant under rotations): noise floor 1e-15 |A|_F
+    double f2 = 0.0;
+    for (int e = tid; e < m * m; e += 1024) {
+        const double v = sA[(e / m) * LD + (e % m)];
+        f2 = fma(v, v, f2);
+    }
+    for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o);
+    if (lane == 0) red[wave] = f2;
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < 16; ++w) fro2 += red[w];
+    const double floor_abs = 1e-15 * sqrt(fro2);
+    const bool own = tid < half * half;
+    const int bi = own ? tid / half : 0, bj = own ? tid % half : 0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < m - 1; ++round) {
+            if (tid < half) {
+                int p, q;
+                circle_pair(tid, round, m, p, q);
+                double c = 1.0, s = 0.0;
+                const double apq = sA[p * LD + q], app = sA[p * LD + p], aqq = sA[q * LD + q];
+                if (fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs && fabs(apq) > 1e-300) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                 : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                    rotated = 1;
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+            }
+            __syncthreads();
+            if (own) {
+                int pi, qi, pj, qj;
+                circle_pair(bi, round, m, pi, qi);
+                circle_pair(bj, round, m, pj, qj);
+                const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+                const double b00 = sA[pi * LD + pj], b01 = sA[pi * LD + qj];
+                const double b10 = sA[qi * LD + pj], b11 = sA[qi * LD + qj];
+                double v0p = 0, v0q = 0, v1p = 0, v1q = 0;
+                const int r0 = 2 * bj, r1 = 2 * bj + 1;
+                if (WANTV) {
+                    v0p = V[r0 * LD + pi];
+                    v0q = V[r0 * LD + qi];
+                    v1p = V[r1 * LD + pi];
+                    v1q = V[r1 * LD + qi];
+                }
+                if (si != 0.0 || sj != 0.0) {
+                    // rows: [c -s; s c] B ; columns: R [c s; -s c]
+                    const double r00 = ci * b00 - si * b10, r01 = ci * b01 - si * b11;
+                    const double r10 = si * b00 + ci * b10, r11 = si * b01 + ci * b11;
+                    sA[pi * LD + pj] = cj * r00 - sj * r01;
+                    sA[pi * LD + qj] = sj * r00 + cj * r01;
+                    sA[qi * LD + pj] = cj * r10 - sj * r11;
+                    sA[qi * LD + qj] = sj * r10 + cj * r11;
+                }
+                if (WANTV && si != 0.0) {
+                    V[r0 * LD + pi] = ci * v0p - si * v0q;
+                    V[r0 * LD + qi] = si * v0p + ci * v0q;
+                    V[r1 * LD + pi] = ci * v1p - si * v1q;
+                    V[r1 * LD + qi] = si * v1p + ci * v1q;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+    // sort descending (ties by index) and write out the l x l part
+    for (int i = tid; i < l; i += 1024) {
+        const double li = sA[i * LD + i];
+        int rank = 0;
+        for (int j = 0; j < l; ++j) {
+            const double lj = sA[j * LD + j];
+            if (lj > li || (lj == li && j < i)) ++rank;
+        }
+        evals[rank] = li;
+        if (WANTV)
+            for (int row = 0; row < l; ++row) evecs[row * l + rank] = V[row * LD + i];
+    }
+}
+
 // Largest eigenvalue of a symmetric PSD l x l matrix G (l <= 64), padded with
 // zeros to 64 x 64 (which adds only zero eigenvalues).  NSQ normalised squarings
 // B <- B^2 / max diag(B^2), each a 64 x 64 x 64 product on FP64 MFMA (one
@@ -735,7 +853,12 @@ void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream
     const bool wantv = evecs != nullptr;
     const size_t both = 2 * me * (me + 1) * sizeof(double);
     const size_t one = me * (me + 1) * sizeof(double);
-    if (!wantv) {
+    if (me <= 64) {
+        if (wantv)
+            jacobi64_kernel<true><<<1, 1024, 0, st>>>(A, evals, evecs, l);
+        else
+            jacobi64_kernel<false><<<1, 1024, 0, st>>>(A, evals, nullptr, l);
+    } else if (!wantv) {
         // eigenvalues only: V is never touched
         if (one > 64 * 1024)
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true, false>),
