@@ -204,9 +204,17 @@ def cpu_baseline(cfg, ell, rtol):
         _, _, _, info = ogn.gn_step(orc, np.zeros(cfg["n"]), method="nystrom", Omega=Om, rtol=rtol)
         dt = time.perf_counter() - t0
     hv = ell + info["pcg"]["iters"]
+    # one thread: four Hessian columns around the background trajectory
+    with threadpool_limits(limits=1):
+        tr = orc.fwd(orc.xb)
+        t0 = time.perf_counter()
+        orc.hessian(tr, Om[:, :4])
+        dt1 = time.perf_counter() - t0
     return {"value": hv / dt, "unit": "Hv/s", "cores": cores, "kind": "oracle",
             "sample": f"one GN iteration of burgers-4096 ({ell}-column Nystrom sketch + "
-                      f"{info['pcg']['iters']} PCG products to rtol {rtol:g}), FP64 numpy, {dt:.1f} s"}
+                      f"{info['pcg']['iters']} PCG products to rtol {rtol:g}), FP64 numpy, {dt:.1f} s",
+            "one_thread": {"value": 4 / dt1, "unit": "Hv/s", "cores": 1,
+                           "sample": f"4 Hessian columns of burgers-4096, {dt1:.1f} s"}}
 
 
 def main():
@@ -261,10 +269,12 @@ def main():
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, step_ms = [], []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         infos.extend(step())
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
     t1 = time.perf_counter()
     elapsed = t1 - t0
     cnt = prob.counters()
@@ -304,6 +314,32 @@ def main():
     torch.cuda.synchronize()
     block_ms = e0.elapsed_time(e1) / reps
 
+    # single-vector product (the PCG's), FP64
+    v1 = V[:, :1].contiguous()
+    hv1 = torch.empty_like(v1)
+    prob.hessian_block(traj, v1, hv1)
+    torch.cuda.synchronize()
+    reps1 = 20
+    e0.record()
+    for _ in range(reps1):
+        prob.hessian_block(traj, v1, hv1)
+    e1.record()
+    torch.cuda.synchronize()
+    hv1_ms = e0.elapsed_time(e1) / reps1
+
+    # achievable HBM bandwidth: a plain 1 GiB device copy (reads and writes 1 GiB)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    hbm_gbs = 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    del src, dst
+
     out = {
         "metric": "Hessian-vec products/s; time per GN step to 1e-6 residual; p50/p99 latency",
         "value": hv_per_s,
@@ -322,8 +358,12 @@ def main():
                    "sketch": args.sketch, "gn_iters": args.gn_iters, "pcg_rtol": rtol},
         "gn_step_ms": 1e3 * elapsed / (args.steps * args.gn_iters),
         "pcg_iters_per_gn": [i["pcg_iters"] for i in infos[: args.gn_iters]],
+        "step_ms_median": float(np.median(step_ms)), "step_ms_p10": float(np.percentile(step_ms, 10)),
+        "step_ms_p90": float(np.percentile(step_ms, 90)),
         "hessian_block_ms": block_ms,
         "hessian_block_hv_per_s": ell / (block_ms * 1e-3),
+        "hessian_k1_ms": hv1_ms, "hessian_k1_hv_per_s": 1.0 / (hv1_ms * 1e-3),
+        "hbm_copy_gbs_measured": hbm_gbs,
         "roofline": roofline,
         "kernels": {k: {"launches": v["launches"], "total_ms": v["total_ms"],
                         "tflops": (v["alg_flops"] / (v["total_ms"] * 1e-3) / 1e12) if v["total_ms"] > 0 else 0.0}

@@ -152,3 +152,4 @@ def tune_or_load(prob, traj, nsteps, k, dtype=rp4d.F64, budget_s=30.0, cache_pat
         except OSError:
             pass
     return best
+

@@ -1658,14 +1658,22 @@ struct rp4d_batch {
 namespace rp4d {
 namespace {
 
+// Descriptor tables are staged through a pinned host ring and its device copy,
+// used as two halves.  A table never straddles the halves; when the current
+// half is full the stream is drained (every launch that read the other half has
+// completed) and staging moves to the other half.  Tables staged together for
+// one launch therefore stay intact until that launch is enqueued: a switch
+// never overwrites the half holding the earlier tables of the same group.
 template <typename T>
 T* stage(rp4d_batch* b, const std::vector<T>& v) {
     const size_t bytes = ((v.size() * sizeof(T)) + 255) / 256 * 256;
     if (bytes == 0) return nullptr;
-    RP4D_REQUIRE(bytes <= b->cap, RP4D_ENOMEM, "batch staging ring too small for a descriptor table");
-    if (b->off + bytes > b->cap) {
-        RP4D_HIP(hipStreamSynchronize(b->ctx->stream));  // earlier copies out of the ring have completed
-        b->off = 0;
+    const size_t half = b->cap / 2;
+    RP4D_REQUIRE(bytes <= half, RP4D_ENOMEM, "batch staging ring too small for a descriptor table");
+    const size_t base = b->off < half ? 0 : half;
+    if (b->off + bytes > base + half) {
+        RP4D_HIP(hipStreamSynchronize(b->ctx->stream));
+        b->off = base == 0 ? half : 0;
     }
     char* h = b->host + b->off;
     char* d = b->dev.as<char>() + b->off;

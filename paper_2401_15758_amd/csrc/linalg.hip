@@ -842,9 +842,10 @@ void launch_sym_lmax(const double* G, int l, double* out, double* work, hipStrea
         RP4D_HIP(hipGetLastError());
         return;
     }
-    // larger orders: eigenvalues of a copy by the Jacobi solver (descending: out[0])
-    launch_relayout<double, double>(G, 1, work, 1, l * l, 1, st);
-    launch_jacobi_eig(work, out, nullptr, l, st);
+    // larger orders: eigenvalues by the Jacobi solver, which only reads G
+    // without eigenvectors (descending: out[0])
+    (void)work;
+    launch_jacobi_eig(const_cast<double*>(G), out, nullptr, l, st);
 }
 
 void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st) {

@@ -203,6 +203,7 @@ class Problem:
 
     def __init__(self, ctx, cfg, ckpt_every=0):
         self.ctx = ctx
+        self.cfg = dict(cfg)
         d = ProblemDesc(model=BURGERS1D if cfg.get("model", "burgers") == "burgers" else BVE2D,
                         nx=int(cfg["nx"] if cfg.get("model") == "bve" else cfg["n"]), ny=int(cfg.get("ny", 1)),
                         nu=float(cfg["nu"]),
