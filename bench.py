@@ -371,13 +371,21 @@ def main():
         "counters": cnt,
         "tiling": tilings,
     }
+    def note(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    note("burgers-4096 done")
     if not args.no_bve:
+        note("bve-256 section")
         out["bve"] = bve_section(rp4d, inputs, torch, np)
     if not args.no_batch:
+        note("batch-64 section")
         out["batch"] = batch_section(rp4d, inputs, torch, np)
     if not args.no_serve:
+        note("serve-mix section")
         out["serve"] = serve_section()
     if not args.no_cpu_baseline:
+        note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
