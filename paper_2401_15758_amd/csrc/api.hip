@@ -117,7 +117,8 @@ int guarded(F&& f) {
 // ---------------------------------------------------------------------------
 // small device helpers for PCG / GN control scalars
 // ---------------------------------------------------------------------------
-enum { SC_RZ = 0, SC_PQ, SC_RZN, SC_RR, SC_BB, SC_T0, SC_T1, SC_T2, SC_COUNT };
+enum { SC_RZ = 0, SC_PQ, SC_RZN, SC_RR, SC_BB, SC_T0, SC_T1, SC_T2, SC_DD, SC_VV, SC_GI, SC_COUNT };
+static_assert(SC_COUNT <= 16, "per-problem scalar block of the batched path holds 16");
 
 __global__ void pcg_update_xr(double* x, double* r, const double* p, const double* q, const double* sc, int n) {
     const double alpha = sc[SC_RZ] / sc[SC_PQ];
@@ -532,6 +533,9 @@ void check_common(const rp4d_problem* p, int k, const void* a, const void* b) {
 
 rp4d_ctx::~rp4d_ctx() {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     for (auto& pe : pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
@@ -1210,6 +1214,42 @@ int rp4d_precond_apply(const rp4d_precond* pc, int k, const double* R, double* Z
 namespace rp4d {
 namespace {
 
+// Enqueue the work `f` on the context's side stream after everything already on
+// the main stream, with the problem's side workspaces swapped in (the kernels
+// capture the buffer addresses at launch); ev_join marks its completion.
+template <typename F>
+void on_side_lane(rp4d_problem* p, F&& f) {
+    rp4d_ctx* c = p->ctx;
+    if (!c->side) {
+        RP4D_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        RP4D_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        RP4D_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    hipStream_t main = c->stream;
+    RP4D_HIP(hipEventRecord(c->ev_fork, main));
+    RP4D_HIP(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    auto swap_all = [p]() {
+        p->ws_s0.swap(p->side_s0);
+        p->ws_s1.swap(p->side_s1);
+        p->ws_obs.swap(p->side_obs);
+        p->ws_bh.swap(p->side_bh);
+        p->ws_seg.swap(p->side_seg);
+        p->ws_red.swap(p->side_red);
+    };
+    swap_all();
+    c->stream = c->side;
+    try {
+        f();
+    } catch (...) {
+        c->stream = main;
+        swap_all();
+        throw;
+    }
+    c->stream = main;
+    swap_all();
+    RP4D_HIP(hipEventRecord(c->ev_join, c->side));
+}
+
 // Capture the work `f` enqueues on the context stream into an executable graph
 // (recorded on a library-owned stream; nothing runs during capture).
 struct GraphExec {
@@ -1448,25 +1488,30 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         rp4d::DevBuf& vecs = pcg_buf(p);
         vecs.ensure(5 * static_cast<size_t>(n) * sizeof(double) + 1024 * sizeof(double));
         double* red = vecs.as<double>() + 5 * static_cast<size_t>(n);
-        // 1. FWD at x, J
-        double Jobs = 0.0;
-        int rc = rp4d_fwd(p, s->x.as<double>(), s->traj, &Jobs);
+        // 1. FWD at x; |d|^2 and |v|^2 stay on the device until the join below
+        int rc = rp4d_fwd(p, s->x.as<double>(), s->traj, nullptr);
         RP4D_REQUIRE(rc == RP4D_OK, rc, g_last_error);
-        launch_dot(s->v.as<double>(), s->v.as<double>(), n, sc + SC_T2, red, st);
-        const double vv = read_scalar(p, sc + SC_T2);
-        // 2. gradient g = v + A^T d
-        adj_impl<double>(p, s->traj, 1, s->traj->innov.as<double>(), s->g.as<double>(), s->v.as<double>());
+        RP4D_REQUIRE(s->traj->has_innov, RP4D_ESTATE, "data not set");
+        launch_dot(s->traj->innov.as<double>(), s->traj->innov.as<double>(), p->m, sc + SC_DD, red, st);
+        launch_dot(s->v.as<double>(), s->v.as<double>(), n, sc + SC_VV, red, st);
+        // 2-3. gradient g = v + A^T d and b = -g.  The 1-D model runs them on the
+        // side stream with the side workspaces, overlapping the sketch below.
+        const bool overlap = p->bve == nullptr;
+        auto gradient = [&]() {
+            hipStream_t gs = stream_of(p);
+            adj_impl<double>(p, s->traj, 1, s->traj->innov.as<double>(), s->g.as<double>(), s->v.as<double>());
+            absmax_kernel<<<1, 256, 0, gs>>>(s->g.as<double>(), n, sc + SC_GI);
+            RP4D_HIP(hipGetLastError());
+            launch_fill<double>(s->b.as<double>(), n, 0.0, gs);
+            launch_axpby(s->g.as<double>(), -1.0, s->b.as<double>(), 0.0, n, gs);
+        };
+        if (overlap) {
+            on_side_lane(p, gradient);
+        } else {
+            gradient();
+        }
         p->cnt.adj_online += 1;
-        absmax_kernel<<<1, 256, 0, st>>>(s->g.as<double>(), n, sc + SC_T1);
-        RP4D_HIP(hipGetLastError());
-        const double ginf = read_scalar(p, sc + SC_T1);
-        RP4D_REQUIRE(std::isfinite(ginf), RP4D_ENONFINITE, "non-finite gradient");
-        // 3. b = -g
-        launch_fill<double>(s->b.as<double>(), n, 0.0, st);
-        launch_axpby(s->g.as<double>(), -1.0, s->b.as<double>(), 0.0, n, st);
         rp4d_gn_info inf{};
-        inf.J = 0.5 * vv + Jobs;
-        inf.gnorm_inf = ginf;
         inf.kappa_re = -1.0;
         // 4-5. reuse test or sketch
         const rp4d_precond* use = nullptr;
@@ -1497,6 +1542,15 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 inf.sketched = 1;
             }
         }
+        // join the gradient; J, |g|_inf
+        if (overlap) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
+        double sch[SC_COUNT];
+        RP4D_HIP(hipMemcpyAsync(sch, sc, sizeof(sch), hipMemcpyDeviceToHost, st));
+        RP4D_HIP(hipStreamSynchronize(st));
+        RP4D_REQUIRE(std::isfinite(sch[SC_DD]), RP4D_ENONFINITE, "non-finite innovations (state blew up or bad input)");
+        RP4D_REQUIRE(std::isfinite(sch[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
+        inf.J = 0.5 * sch[SC_VV] + 0.5 * sch[SC_DD];
+        inf.gnorm_inf = sch[SC_GI];
         // 6. PCG
         rp4d_pcg_info pi{};
         int pcg_rc = RP4D_OK;

@@ -9,6 +9,7 @@
 #include <memory>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "rp4d.h"
@@ -42,6 +43,10 @@ struct DevBuf {
     void release();
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
+    void swap(DevBuf& o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -254,6 +259,10 @@ struct rp4d_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
+    // second stream (default priority) for work that overlaps the main stream,
+    // with the two events that fork and join it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graph replay of the PCG iteration body (captured on a library stream)
     bool graphs = false;
     bool capturing = false;
@@ -317,6 +326,9 @@ struct rp4d_problem {
     rp4d::DevBuf F, lamF, ws_bh;
     // workspaces
     rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg, ws_bg;
+    // the side lane's copies of the sweep / prior / segment workspaces (the
+    // gradient's ADJ sweep runs there while the sketch runs on the main stream)
+    rp4d::DevBuf side_s0, side_s1, side_obs, side_bh, side_seg, side_red;
     rp4d_counters cnt{};
     uint64_t id = 0;  // caller-chosen identity: seeds the batched random draws
     std::map<std::tuple<int, int, int>, rp4d::Tiling> tiling;  // (mode, dtype, k)
