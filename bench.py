@@ -252,7 +252,8 @@ def main():
     tilings = {}
     for k, dt in ((ell, skd), (1, rp4d.F64)):
         tilings[f"k{k}-{'f64' if dt == rp4d.F64 else 'f32'}"] = autotune.tune_or_load(
-            prob, traj0, cfg["nsteps"], k, dt, budget_s=args.tune_budget, cache_path=cache_path)
+            prob, traj0, cfg["nsteps"], k, dt, budget_s=args.tune_budget, cache_path=cache_path,
+            x0=xb if k == 1 else None)
     del traj0
 
     def step():

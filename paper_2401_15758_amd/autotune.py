@@ -114,6 +114,53 @@ def tune(prob, traj, k, dtype=rp4d.F64, reps=2, budget_s=30.0, verbose=False):
     return out
 
 
+def fwd_candidates(n):
+    """Valid tilings of the single nonlinear forward sweep."""
+    out = []
+    for ntiles in (1, 2, 4, 8, 16, 32, 64, 128):
+        tile = -(-n // ntiles)
+        if tile < 16:
+            continue
+        for steps in (4, 8, 12, 16, 25, 32, 50):
+            region = tile + 2 * (4 * steps + 4)
+            if region > 3 * tile + 64:
+                continue
+            for ppt in (1, 2, 4, 8):
+                threads = -(-region // ppt)
+                threads = -(-threads // 64) * 64
+                if 64 <= threads <= 1024:
+                    out.append(dict(ppt=ppt, kc=1, threads=threads, tile=tile, steps=steps))
+    return out
+
+
+def tune_fwd(prob, traj, x0, reps=2, budget_s=10.0, verbose=False):
+    """Search the forward sweep's tiling (timing rp4d_fwd from x0 into traj);
+    applies the best and returns it with its time."""
+    op = lambda: prob.fwd(x0, traj, want_J=False)
+    prob.set_sweep_tiling(mode=rp4d.MODE_FWD)               # heuristic baseline
+    best = dict(prob.get_sweep_tiling(mode=rp4d.MODE_FWD))
+    best_ms = _time(op, reps)
+    cands = fwd_candidates(prob.n)
+    cands.sort(key=lambda c: (-c["steps"], -c["tile"]))
+    t_end = time.perf_counter() + budget_s
+    timed = 0
+    for c in cands:
+        if time.perf_counter() > t_end:
+            break
+        prob.set_sweep_tiling(mode=rp4d.MODE_FWD, **c)
+        try:
+            ms = _time(op, reps)
+        except rp4d.Rp4dError:
+            continue
+        timed += 1
+        if verbose:
+            print(f"  fwd {c} {ms:.3f} ms", flush=True)
+        if ms < best_ms:
+            best, best_ms = dict(c), ms
+    prob.set_sweep_tiling(mode=rp4d.MODE_FWD, **{f: best[f] for f in FIELDS})
+    return dict(best, ms=best_ms, timed=timed, total=len(cands))
+
+
 def load_cache(path=CACHE_PATH):
     if os.path.exists(path):
         with open(path) as f:
@@ -136,15 +183,22 @@ def apply_cached(prob, nsteps, k, dtype=rp4d.F64, cache=None):
         return None
     for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
         prob.set_sweep_tiling(dtype, k, mode=mode, **{f: ent[name][f] for f in FIELDS})
+    if "fwd" in ent:
+        prob.set_sweep_tiling(mode=rp4d.MODE_FWD, **{f: ent["fwd"][f] for f in FIELDS})
     return ent
 
 
-def tune_or_load(prob, traj, nsteps, k, dtype=rp4d.F64, budget_s=30.0, cache_path=CACHE_PATH, save=True):
+def tune_or_load(prob, traj, nsteps, k, dtype=rp4d.F64, budget_s=30.0, cache_path=CACHE_PATH, save=True, x0=None):
+    """Apply the cached tilings of this shape or search them.  With k = 1 and an
+    initial state x0 the forward sweep's tiling is searched too (kept in the
+    same entry)."""
     cache = load_cache(cache_path)
     ent = apply_cached(prob, nsteps, k, dtype, cache)
-    if ent is not None:
+    if ent is not None and (x0 is None or k != 1 or "fwd" in ent):
         return ent
-    best = tune(prob, traj, k, dtype, budget_s=budget_s)
+    best = dict(ent) if ent is not None else tune(prob, traj, k, dtype, budget_s=budget_s)
+    if x0 is not None and k == 1:
+        best["fwd"] = tune_fwd(prob, traj, x0, budget_s=budget_s / 2)
     cache[key(prob.n, nsteps, k, dtype)] = best
     if save:
         try:

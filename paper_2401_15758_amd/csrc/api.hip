@@ -250,6 +250,15 @@ Tiling fwd_tiling(const rp4d_problem* p) {
         t.threads = ((R + t.ppt - 1) / t.ppt + 63) / 64 * 64;
     }
     if (t.ppt == 8 && t.threads > 1024) t.threads = 1024;
+    auto it = p->tiling.find(std::make_tuple(static_cast<int>(RP4D_MODE_FWD), static_cast<int>(RP4D_F64), 1));
+    if (it != p->tiling.end()) {
+        const Tiling& o = it->second;
+        if (o.ppt > 0) t.ppt = o.ppt;
+        if (o.threads > 0) t.threads = o.threads;
+        if (o.tile > 0) t.tile = o.tile;
+        if (o.steps > 0) t.steps = o.steps;
+    }
+    t.kc = 1;
     return t;
 }
 
@@ -1660,7 +1669,13 @@ int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, 
                           int steps) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
-        RP4D_REQUIRE(mode == 0 || mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "bad sweep mode");
+        RP4D_REQUIRE(mode == 0 || mode == MODE_TLM || mode == MODE_ADJ || mode == RP4D_MODE_FWD, RP4D_EINVAL,
+                     "bad sweep mode");
+        if (mode == RP4D_MODE_FWD) {
+            dtype = RP4D_F64;
+            k = 1;
+            kc = 1;
+        }
         Tiling t;
         t.ppt = ppt;
         t.kc = kc;
@@ -1678,7 +1693,7 @@ int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int
                           int* tile, int* steps) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
-        Tiling t = tiling_for(p, mode == 0 ? MODE_TLM : mode, dtype, k > 0 ? k : 1);
+        Tiling t = mode == RP4D_MODE_FWD ? fwd_tiling(p) : tiling_for(p, mode == 0 ? MODE_TLM : mode, dtype, k > 0 ? k : 1);
         if (ppt) *ppt = t.ppt;
         if (kc) *kc = t.kc;
         if (threads) *threads = t.threads;

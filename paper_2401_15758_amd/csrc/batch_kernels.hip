@@ -168,17 +168,25 @@ __global__ void __launch_bounds__(1024) bchol_kernel(const BSmall* __restrict__ 
     if (tid == 0) d.info[0] = bad;
 }
 
+// XLDS: the inverse is formed in LDS (two l x l tiles) and written once;
+// otherwise in place in global memory.
+template <bool XLDS>
 __global__ void __launch_bounds__(256) btrinv_kernel(const BSmall* __restrict__ desc, int l) {
     extern __shared__ double sL[];
     const BSmall d = desc[blockIdx.x];
+    double* X = XLDS ? sL + l * l : d.B;
     for (int e = threadIdx.x; e < l * l; e += blockDim.x) sL[e] = d.A[e];
     __syncthreads();
     for (int c = threadIdx.x; c < l; c += blockDim.x) {
         for (int i = 0; i < l; ++i) {
             double s = (i == c) ? 1.0 : 0.0;
-            for (int q = c; q < i; ++q) s -= sL[i * l + q] * d.B[q * l + c];
-            d.B[i * l + c] = (i < c) ? 0.0 : s / sL[i * l + i];
+            for (int q = c; q < i; ++q) s -= sL[i * l + q] * X[q * l + c];
+            X[i * l + c] = (i < c) ? 0.0 : s / sL[i * l + i];
         }
+    }
+    if (XLDS) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < l * l; e += blockDim.x) d.B[e] = X[e];
     }
 }
 
@@ -479,11 +487,18 @@ void launch_bchol(const BSmall* d, int np, int l, hipStream_t st) {
 
 void launch_btrinv(const BSmall* d, int np, int l, hipStream_t st) {
     if (np <= 0) return;
-    const size_t sh = static_cast<size_t>(l) * l * sizeof(double);
-    if (sh > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&btrinv_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  static_cast<int>(sh));
-    btrinv_kernel<<<np, 256, sh, st>>>(d, l);
+    const size_t one = static_cast<size_t>(l) * l * sizeof(double);
+    if (lds_fits(reinterpret_cast<const void*>(&btrinv_kernel<true>), 2 * one)) {
+        if (2 * one > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&btrinv_kernel<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(2 * one));
+        btrinv_kernel<true><<<np, 256, 2 * one, st>>>(d, l);
+    } else {
+        if (one > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&btrinv_kernel<false>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(one));
+        btrinv_kernel<false><<<np, 256, one, st>>>(d, l);
+    }
     RP4D_HIP(hipGetLastError());
 }
 

@@ -146,6 +146,8 @@ void launch_small_gemm(const double* A, int ta, const double* B, int tb, double*
                        hipStream_t st);
 // Symmetric eigendecomposition (cyclic Jacobi): A (l x l, destroyed) -> evals (desc), evecs (columns, row-major).
 void launch_jacobi_eig(double* A, double* evals, double* evecs, int l, hipStream_t st);
+// Whether `dyn` bytes of dynamic LDS fit beside kernel `fn`'s static LDS on this device.
+bool lds_fits(const void* fn, size_t dyn);
 // lambda_max of a symmetric PSD l x l matrix into out[0] (G untouched; `work`
 // holds l*l doubles, used when l > 64; for l > 64 out must hold l doubles).
 void launch_sym_lmax(const double* G, int l, double* out, double* work, hipStream_t st);

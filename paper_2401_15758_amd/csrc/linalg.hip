@@ -340,6 +340,25 @@ __global__ void __launch_bounds__(1024) chol_kernel(double* A, int l, int* info)
     if (tid == 0) info[0] = bad;
 }
 
+// X = L^{-1} with L and X both in LDS: thread c forms column c by forward
+// substitution (orders with 2 l^2 doubles within the LDS budget).
+__global__ void __launch_bounds__(256) trinv_lds_kernel(const double* L, double* X, int l) {
+    extern __shared__ double sm[];
+    double* sL = sm;
+    double* sX = sm + l * l;
+    for (int e = threadIdx.x; e < l * l; e += blockDim.x) sL[e] = L[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < l; c += blockDim.x) {
+        for (int i = 0; i < l; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int q = c; q < i; ++q) s -= sL[i * l + q] * sX[q * l + c];
+            sX[i * l + c] = (i < c) ? 0.0 : s / sL[i * l + i];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < l * l; e += blockDim.x) X[e] = sX[e];
+}
+
 __global__ void __launch_bounds__(256) trinv_kernel(const double* L, double* X, int l) {
     extern __shared__ double sL[];
     for (int e = threadIdx.x; e < l * l; e += blockDim.x) sL[e] = L[e];
@@ -812,6 +831,15 @@ void launch_chol(double* A, int l, int* info, hipStream_t st) {
 
 void launch_trinv(const double* L, double* Linv, int l, hipStream_t st) {
     RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "trinv: l must be in [1, 128]");
+    const size_t both = 2 * static_cast<size_t>(l) * l * sizeof(double);
+    if (lds_fits(reinterpret_cast<const void*>(&trinv_lds_kernel), both)) {
+        if (both > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&trinv_lds_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(both));
+        trinv_lds_kernel<<<1, 256, both, st>>>(L, Linv, l);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
     const size_t shmem = static_cast<size_t>(l) * l * sizeof(double);
     if (shmem > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&trinv_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,

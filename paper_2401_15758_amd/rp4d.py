@@ -24,7 +24,7 @@ F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC = 0, 1, 2
 BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
-MODE_BOTH, MODE_TLM, MODE_ADJ = 0, 1, 2
+MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
           ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE", EHIP: "EHIP", ESTATE: "ESTATE"}

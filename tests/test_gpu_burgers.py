@@ -133,6 +133,26 @@ def test_tilings_are_bitwise_identical(ragged):
     pr.gpu.set_sweep_tiling(k=9)
 
 
+def test_fwd_tilings_are_bitwise_identical(ragged):
+    """The forward sweep's tiling (autotuned like the block sweeps) changes no bit
+    of the trajectory: observations and the Hessian built on it are identical."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = ragged
+    V = to_dev(_rand((pr.orc.n, 3), 83))
+    obs0 = pr.gpu.observe(pr.traj).clone()
+    hv0 = pr.gpu.hessian_block(pr.traj, V).clone()
+    tr = pr.gpu.traj()
+    for ppt, threads, tile, steps in [(1, 128, 50, 4), (2, 192, 100, 8), (8, 64, 200, 12), (4, 256, 200, 25)]:
+        pr.gpu.set_sweep_tiling(mode=rp4d.MODE_FWD, ppt=ppt, threads=threads, tile=tile, steps=steps)
+        assert pr.gpu.get_sweep_tiling(mode=rp4d.MODE_FWD)["steps"] == steps
+        pr.gpu.fwd(pr.xb_dev, tr, want_J=False)
+        torch.cuda.synchronize()
+        assert torch.equal(pr.gpu.observe(tr), obs0), (ppt, threads, tile, steps)
+        assert torch.equal(pr.gpu.hessian_block(tr, V), hv0), (ppt, threads, tile, steps)
+    pr.gpu.set_sweep_tiling(mode=rp4d.MODE_FWD)
+
+
 def test_checkpointed_trajectory_bitwise(small):
     torch = need_gpu()
     pr = small
