@@ -20,6 +20,8 @@ TOL_OP = 1e-12
 SMALL = inputs.bve_config(32, nsteps=12, obs_stride=8, obs_every=4, L_cells=3.0, ell=10, name='bve-32')
 # ragged observation layout (48 not a multiple of the stride 5), odd window
 RAGGED = inputs.bve_config(48, nsteps=9, obs_stride=5, obs_every=4, L_cells=2.5, ell=6, name='bve-48')
+# grid width not a multiple of 64 (the stencils' column strips are 40 wide)
+WIDE = inputs.bve_config(80, nsteps=6, obs_stride=16, obs_every=3, L_cells=3.0, ell=6, name='bve-80')
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +62,7 @@ def test_prior_sqrt_parity(nx, k, L):
     assert colwise_relerr(got, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("cfg", [SMALL, RAGGED], ids=["bve-32", "bve-48-ragged"])
+@pytest.mark.parametrize("cfg", [SMALL, RAGGED, WIDE], ids=["bve-32", "bve-48-ragged", "bve-80"])
 def test_fwd_observations_and_cost(cfg):
     need_gpu()
     pr = Pair(cfg, seed=2)
@@ -70,7 +72,7 @@ def test_fwd_observations_and_cost(cfg):
     assert pr.Jobs == pytest.approx(0.5 * float(np.sum(d * d)), rel=1e-12)
 
 
-@pytest.mark.parametrize("cfg", [SMALL, RAGGED], ids=["bve-32", "bve-48-ragged"])
+@pytest.mark.parametrize("cfg", [SMALL, RAGGED, WIDE], ids=["bve-32", "bve-48-ragged", "bve-80"])
 def test_tlm_adj_hessian_parity(cfg):
     need_gpu()
     pr = Pair(cfg, seed=3)
