@@ -297,6 +297,16 @@ def main():
                 "avg_launch_us": 1e3 * ks["total_ms"] / max(1, ks["launches"]),
                 "launches": ks["launches"]}
 
+    # the same assimilation with the sketch-reuse test (kappa_re < 10 keeps the
+    # resident preconditioner, Sec. 3.2): fewer products per GN step
+    state.reset()
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    reuse_infos = [prob.gn_step(state, sketch=sk, ell=ell, seed=1000 + it, sketch_dtype=skd, rtol=rtol, reuse_eps=10.0)
+                   for it in range(args.gn_iters)]
+    torch.cuda.synchronize()
+    reuse_ms = 1e3 * (time.perf_counter() - tr0) / args.gn_iters
+
     # isolated block Hessian product, k = 64, FP64 (sketch shape)
     traj = prob.traj()
     prob.fwd(xb, traj, want_J=False)
@@ -361,6 +371,9 @@ def main():
         "pcg_iters_per_gn": [i["pcg_iters"] for i in infos[: args.gn_iters]],
         "step_ms_median": float(np.median(step_ms)), "step_ms_p10": float(np.percentile(step_ms, 10)),
         "step_ms_p90": float(np.percentile(step_ms, 90)),
+        "gn_step_ms_with_reuse": reuse_ms,
+        "reuse_decisions": [i["reused"] for i in reuse_infos],
+        "pcg_iters_with_reuse": [i["pcg_iters"] for i in reuse_infos],
         "hessian_block_ms": block_ms,
         "hessian_block_hv_per_s": ell / (block_ms * 1e-3),
         "hessian_k1_ms": hv1_ms, "hessian_k1_hv_per_s": 1.0 / (hv1_ms * 1e-3),
