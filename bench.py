@@ -67,7 +67,7 @@ def measured_traffic(kname, tiling, cfg):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    keys = ("ppt", "kc", "threads", "tile", "steps")
+    keys = ("ppt", "kc", "threads", "tile", "steps", "xch")
     if (rec.get("source_sha256") != sha or rec.get("kernel") != kname or rec.get("workload") != cfg["name"]
             or any(rec.get("tiling", {}).get(k) != tiling.get(k) for k in keys)):
         return None
@@ -290,7 +290,8 @@ def main():
     achieved = ks["alg_flops"] / (ks["total_ms"] * 1e-3) / 1e12 if ks["total_ms"] > 0 else 0.0
     peak = PEAK_FP64_VALU_TFLOPS if skd == rp4d.F64 else PEAK_FP32_VALU_TFLOPS
     tl = tilings[f"k{ell}-{'f64' if skd == rp4d.F64 else 'f32'}"][dom]
-    kname = f"burgers_{dom}_kernel<{'double' if skd == rp4d.F64 else 'float'}, {tl['ppt']}, {tl['kc']}>"
+    kname = (f"burgers_{dom}{'_wave' if tl.get('xch') == rp4d.XCH_WAVE else ''}_kernel"
+             f"<{'double' if skd == rp4d.F64 else 'float'}, {tl['ppt']}, {tl['kc']}>")
     roofline = {"bound": "alu", "kernel": kname + f" (k={ell} block sweep)", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(kname, tl, cfg),

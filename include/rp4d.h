@@ -321,19 +321,27 @@ int rp4d_batch_hessian_block(rp4d_batch* b, rp4d_traj* const* trajs, int k, cons
 int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_gn_opts* opts, rp4d_gn_info* infos);
 
 /* Sweep tiling of a problem's block sweeps (used by the autotuner): points per
- * thread `ppt`, vectors per workgroup `kc`, threads per workgroup `threads`,
- * tile length `tile` (grid points owned per workgroup) and steps per launch
- * `steps`.  `mode` selects the sweep: 0 both, RP4D_MODE_TLM or RP4D_MODE_ADJ,
- * or RP4D_MODE_FWD for the single nonlinear forward sweep (dtype, k and kc
- * ignored); `dtype`/`k` select the entry (k = 0: every k).  Any argument <= 0
- * restores the built-in heuristic for that field; all <= 0 removes the entry.
- * Invalid tilings are reported by the sweep call that uses them (RP4D_EINVAL). */
+ * thread `ppt`, vectors per region `kc`, threads per workgroup `threads`,
+ * tile length `tile` (grid points owned per region), steps per launch `steps`
+ * and the region's neighbour exchange `xch`:
+ *   RP4D_XCH_LDS  - one region per workgroup (threads * ppt points), edge
+ *                   values through LDS with a barrier per RK stage;
+ *   RP4D_XCH_WAVE - one region per 64-lane wave (64 * ppt points), edge values
+ *                   through lane shifts; `threads` (64, 128 or 256) only groups
+ *                   waves into workgroups.
+ * Both give bitwise the same results.  `mode` selects the sweep: 0 both,
+ * RP4D_MODE_TLM or RP4D_MODE_ADJ, or RP4D_MODE_FWD for the single nonlinear
+ * forward sweep (dtype, k and kc ignored); `dtype`/`k` select the entry (k = 0:
+ * every k).  Any argument <= 0 restores the built-in heuristic for that field;
+ * all <= 0 removes the entry.  Invalid tilings are reported by the sweep call
+ * that uses them (RP4D_EINVAL). */
 enum { RP4D_MODE_TLM = 1, RP4D_MODE_ADJ = 2, RP4D_MODE_FWD = 3 };
+enum { RP4D_XCH_LDS = 1, RP4D_XCH_WAVE = 2 };
 int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, int kc, int threads,
-                          int tile, int steps);
+                          int tile, int steps, int xch);
 /* Host output: the tiling the next sweep of `mode` (0 = TLM) with (dtype, k) would use. */
 int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int* ppt, int* kc, int* threads,
-                          int* tile, int* steps);
+                          int* tile, int* steps, int* xch);
 
 #ifdef __cplusplus
 }

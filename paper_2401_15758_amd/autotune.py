@@ -55,7 +55,30 @@ def candidates(n, k, dtype=rp4d.F64, min_groups_tiles=32):
                         continue
                     if 2 * 2 * threads * (1 + kc) * es > LDS_LIMIT:
                         continue
-                    out.append(dict(ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps))
+                    out.append(dict(ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps, xch=rp4d.XCH_LDS))
+    out.extend(wave_candidates(n, WAVE_PK))
+    return out
+
+
+# (ppt, kc) pairs with a wave-region kernel instance
+WAVE_PK = ((1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (8, 1))
+WAVE_STEPS = (2, 3, 4, 6, 8, 12, 16, 25, 32, 50)
+
+
+def wave_candidates(n, pk):
+    """Wave-region tilings: each 64-lane wave covers 64 * ppt points, the owned
+    tile the rest after two halos of 4 * steps + 4; tiles are balanced over n."""
+    out = []
+    for ppt, kc in pk:
+        for steps in WAVE_STEPS:
+            tmax = 64 * ppt - 2 * (4 * steps + 4)
+            if tmax < 16 and tmax < n:
+                continue
+            tmax = min(tmax, n)
+            ntiles = -(-n // tmax)
+            tile = -(-n // ntiles)
+            for threads in (64, 256):
+                out.append(dict(ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps, xch=rp4d.XCH_WAVE))
     return out
 
 
@@ -70,7 +93,7 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-FIELDS = ("ppt", "kc", "threads", "tile", "steps")
+FIELDS = ("ppt", "kc", "threads", "tile", "steps", "xch")
 
 
 def tune(prob, traj, k, dtype=rp4d.F64, reps=2, budget_s=30.0, verbose=False):
@@ -129,7 +152,8 @@ def fwd_candidates(n):
                 threads = -(-region // ppt)
                 threads = -(-threads // 64) * 64
                 if 64 <= threads <= 1024:
-                    out.append(dict(ppt=ppt, kc=1, threads=threads, tile=tile, steps=steps))
+                    out.append(dict(ppt=ppt, kc=1, threads=threads, tile=tile, steps=steps, xch=rp4d.XCH_LDS))
+    out.extend(wave_candidates(n, ((1, 1), (2, 1), (4, 1), (8, 1))))
     return out
 
 
@@ -182,9 +206,9 @@ def apply_cached(prob, nsteps, k, dtype=rp4d.F64, cache=None):
     if not ent or "tlm" not in ent or "adj" not in ent:
         return None
     for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
-        prob.set_sweep_tiling(dtype, k, mode=mode, **{f: ent[name][f] for f in FIELDS})
+        prob.set_sweep_tiling(dtype, k, mode=mode, **{f: ent[name].get(f, 0) for f in FIELDS})
     if "fwd" in ent:
-        prob.set_sweep_tiling(mode=rp4d.MODE_FWD, **{f: ent["fwd"][f] for f in FIELDS})
+        prob.set_sweep_tiling(mode=rp4d.MODE_FWD, **{f: ent["fwd"].get(f, 0) for f in FIELDS})
     return ent
 
 

@@ -232,6 +232,7 @@ Tiling tiling_for(const rp4d_problem* p, int mode, int dtype, int k) {
             if (o.threads > 0) t.threads = o.threads;
             if (o.tile > 0) t.tile = o.tile;
             if (o.steps > 0) t.steps = o.steps;
+            if (o.xch > 0) t.xch = o.xch;
             break;
         }
     }
@@ -257,6 +258,7 @@ Tiling fwd_tiling(const rp4d_problem* p) {
         if (o.threads > 0) t.threads = o.threads;
         if (o.tile > 0) t.tile = o.tile;
         if (o.steps > 0) t.steps = o.steps;
+        if (o.xch > 0) t.xch = o.xch;
     }
     t.kc = 1;
     return t;
@@ -1666,7 +1668,7 @@ int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out) 
 }
 
 int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, int kc, int threads, int tile,
-                          int steps) {
+                          int steps, int xch) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
         RP4D_REQUIRE(mode == 0 || mode == MODE_TLM || mode == MODE_ADJ || mode == RP4D_MODE_FWD, RP4D_EINVAL,
@@ -1682,7 +1684,8 @@ int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, 
         t.threads = threads;
         t.tile = tile;
         t.steps = steps;
-        if (ppt <= 0 && kc <= 0 && threads <= 0 && tile <= 0 && steps <= 0)
+        t.xch = xch > 0 ? xch : 0;
+        if (ppt <= 0 && kc <= 0 && threads <= 0 && tile <= 0 && steps <= 0 && xch <= 0)
             p->tiling.erase(std::make_tuple(mode, dtype, k));
         else
             p->tiling[std::make_tuple(mode, dtype, k)] = t;
@@ -1690,7 +1693,7 @@ int rp4d_set_sweep_tiling(rp4d_problem* p, int mode, int dtype, int k, int ppt, 
 }
 
 int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int* ppt, int* kc, int* threads,
-                          int* tile, int* steps) {
+                          int* tile, int* steps, int* xch) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
         Tiling t = mode == RP4D_MODE_FWD ? fwd_tiling(p) : tiling_for(p, mode == 0 ? MODE_TLM : mode, dtype, k > 0 ? k : 1);
@@ -1699,6 +1702,7 @@ int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int
         if (threads) *threads = t.threads;
         if (tile) *tile = t.tile;
         if (steps) *steps = t.steps;
+        if (xch) *xch = t.xch;
     });
 }
 

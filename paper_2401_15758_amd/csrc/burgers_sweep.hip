@@ -10,10 +10,20 @@
 // exact (overlapped temporal blocking).  Between launches the block state lives
 // in HBM in the blocked layout [group][point][KC]; inside a launch it lives in
 // registers: thread t holds P consecutive points of the region for the KC vectors
-// and exchanges only its two edge points through LDS, once per RK stage
-// (double-buffered, one workgroup barrier per stage).  The base trajectory u_s
-// is read once per step per point (shared by the KC vectors) and the nonlinear
-// stage states Y_1..Y_4 are recomputed from it on the fly.
+// and exchanges only its two edge points with its neighbours, once per RK stage.
+// The base trajectory u_s is read once per step per point (shared by the KC
+// vectors) and the nonlinear stage states Y_1..Y_4 are recomputed from it on the
+// fly.
+//
+// Two region shapes share the same per-point arithmetic (the bodies below are
+// templated on the exchange):
+//  * workgroup regions: the whole workgroup covers one region and the edge
+//    values travel through LDS (double-buffered, one barrier per exchange);
+//  * wave regions: every 64-lane wave is an independent region of 64 P points
+//    and the edge values move between neighbouring lanes with DPP wave shifts,
+//    so a stage needs neither LDS nor a barrier.  The waves of a workgroup are
+//    different vector groups of the same tile, so their base-trajectory loads
+//    hit the same cache lines.
 #include "internal.hpp"
 
 // Every multiply-add of the sweeps is written as an explicit fma() and automatic
@@ -42,14 +52,77 @@ __device__ __forceinline__ int wrap_index(long v, int n) {
 __device__ __forceinline__ double rk_c(int st) { return st < 2 ? 0.5 : 1.0; }
 __device__ __forceinline__ double rk_b(int st) { return (st == 0 || st == 3) ? (1.0 / 6.0) : (1.0 / 3.0); }
 
-template <int P>
-__device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
-    extern __shared__ double sh_fwd[];
-    const int NT = blockDim.x, t = threadIdx.x;
+// Edge exchange: each thread hands over the values of its first and last point
+// and receives its left neighbour's last-point values and its right
+// neighbour's first-point values.  The region's end threads receive values of
+// their own region (any finite values do: they lie in the halo, which the
+// temporal blocking discards).
+template <typename T, int W>
+struct LdsExchange {
+    T* sh;
+    int NT, t, tl, tr;
+    int buf;
+    __device__ LdsExchange(T* sh_, int NT_, int t_) : sh(sh_), NT(NT_), t(t_), buf(0) {
+        tl = t > 0 ? t - 1 : 0;
+        tr = t < NT - 1 ? t + 1 : NT - 1;
+    }
+    template <int N>
+    __device__ __forceinline__ void operator()(const T (&first)[N], const T (&last)[N], T (&from_left)[N],
+                                               T (&from_right)[N]) {
+        static_assert(N <= W, "exchange record wider than the LDS slot");
+        T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            B[t * W + i] = first[i];
+            B[(NT + t) * W + i] = last[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            from_left[i] = B[(NT + tl) * W + i];
+            from_right[i] = B[tr * W + i];
+        }
+        buf ^= 1;
+    }
+};
+
+// DPP wave shifts by one lane (lane i reads lane i - 1, resp. i + 1); the end
+// lane of the shift keeps its own value.  Every lane of the wave must be active.
+__device__ __forceinline__ int lane_from_lower(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int lane_from_upper(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+
+template <bool FromLower>
+__device__ __forceinline__ double lane_shift(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    int lo = static_cast<int>(b), hi = static_cast<int>(b >> 32);
+    lo = FromLower ? lane_from_lower(lo) : lane_from_upper(lo);
+    hi = FromLower ? lane_from_lower(hi) : lane_from_upper(hi);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <bool FromLower>
+__device__ __forceinline__ float lane_shift(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, FromLower ? lane_from_lower(b) : lane_from_upper(b));
+}
+
+struct WaveExchange {
+    template <typename T, int N>
+    __device__ __forceinline__ void operator()(const T (&first)[N], const T (&last)[N], T (&from_left)[N],
+                                               T (&from_right)[N]) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            from_left[i] = lane_shift<true>(last[i]);
+            from_right[i] = lane_shift<false>(first[i]);
+        }
+    }
+};
+
+// Thread t of a region holds region points t*P .. t*P+P-1.
+template <int P, typename X>
+__device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id, int t, X& xch) {
     const int n = a.n;
     const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
-    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const double h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
 
     int g[P];
@@ -62,7 +135,6 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
         own[p] = (r >= a.halo) && (r < a.halo + tlen);
         u[p] = a.xin[g[p]];
     }
-    int buf = 0;
     for (int s = a.s0; s < a.s0 + a.S; ++s) {
         double Y[P], acc[P];
 #pragma unroll
@@ -72,11 +144,10 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
         }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            double* B = sh_fwd + buf * 2 * NT;
-            B[t] = Y[0];
-            B[NT + t] = Y[P - 1];
-            __syncthreads();
-            const double Yl = B[NT + tl], Yr = B[tr];
+            const double e0[1] = {Y[0]}, e1[1] = {Y[P - 1]};
+            double fl[1], fr[1];
+            xch(e0, e1, fl, fr);
+            const double Yl = fl[0], Yr = fr[0];
             double Yn[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -90,7 +161,6 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
 #pragma unroll
                 for (int p = 0; p < P; ++p) Y[p] = Yn[p];
             }
-            buf ^= 1;
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) u[p] = fma(h, acc[p], u[p]);
@@ -124,16 +194,29 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int tile_id) {
 
 template <int P>
 __global__ void __launch_bounds__(1024) burgers_fwd_kernel(FwdArgs a) {
-    fwd_body<P>(a, blockIdx.x);
+    extern __shared__ double sh_fwd[];
+    LdsExchange<double, 1> x(sh_fwd, blockDim.x, threadIdx.x);
+    fwd_body<P>(a, blockIdx.x, threadIdx.x, x);
+}
+
+// Wave regions: wave w of workgroup b is tile b * (blockDim.x / 64) + w.
+template <int P>
+__global__ void __launch_bounds__(256) burgers_fwd_wave_kernel(FwdArgs a, int ntiles) {
+    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;  // the whole wave leaves
+    WaveExchange x;
+    fwd_body<P>(a, tile, threadIdx.x & 63, x);
 }
 
 // Batched: work item (problem, tile) from `items`, arguments per problem.
 template <int P>
 __global__ void __launch_bounds__(1024) burgers_fwd_batched_kernel(const FwdArgs* __restrict__ args,
                                                                    const int4* __restrict__ items) {
+    extern __shared__ double sh_fwd[];
     const int4 it = items[blockIdx.x];
     const FwdArgs a = args[it.x];  // private copy: no aliasing with the kernel's stores
-    fwd_body<P>(a, it.y);
+    LdsExchange<double, 1> x(sh_fwd, blockDim.x, threadIdx.x);
+    fwd_body<P>(a, it.y, threadIdx.x, x);
 }
 
 // Instances holding P*KC >= 8 point-vectors per thread are limited to 512
@@ -141,16 +224,11 @@ __global__ void __launch_bounds__(1024) burgers_fwd_batched_kernel(const FwdArgs
 template <int P, int KC>
 constexpr int sweep_max_threads() { return P * KC >= 8 ? 512 : 1024; }
 
-template <typename T, int P, int KC>
-__device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int grp) {
-    extern __shared__ __align__(16) unsigned char sh_raw[];
-    T* sh = reinterpret_cast<T*>(sh_raw);
-    constexpr int W = 1 + KC;
-    const int NT = blockDim.x, t = threadIdx.x;
+template <typename T, int P, int KC, typename X>
+__device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int grp, int t, X& xch) {
     const int n = a.n;
     const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
-    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
     const T nd2 = T(2) * nd;
 
@@ -170,7 +248,6 @@ __device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int
 #pragma unroll
     for (int p = 0; p < P; ++p) unext[p] = static_cast<T>(a.base[static_cast<size_t>(a.s0 - a.base_row0) * n + g[p]]);
 
-    int buf = 0;
     for (int s = a.s0; s < a.s0 + a.S; ++s) {
         T u[P];
 #pragma unroll
@@ -192,21 +269,22 @@ __device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int
         }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
-            B[t * W] = Y[0];
-            B[(NT + t) * W] = Y[P - 1];
+            // base and perturbation edges travel together
+            T e0[1 + KC], e1[1 + KC], fl[1 + KC], fr[1 + KC];
+            e0[0] = Y[0];
+            e1[0] = Y[P - 1];
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
-                B[t * W + 1 + c] = dY[0][c];
-                B[(NT + t) * W + 1 + c] = dY[P - 1][c];
+                e0[1 + c] = dY[0][c];
+                e1[1 + c] = dY[P - 1][c];
             }
-            __syncthreads();
-            const T Yl = B[(NT + tl) * W], Yr = B[tr * W];
+            xch(e0, e1, fl, fr);
+            const T Yl = fl[0], Yr = fr[0];
             T dl[KC], dr[KC];
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
-                dl[c] = B[(NT + tl) * W + 1 + c];
-                dr[c] = B[tr * W + 1 + c];
+                dl[c] = fl[1 + c];
+                dr[c] = fr[1 + c];
             }
             const T cb = static_cast<T>(rk_b(st));
             const T ch = static_cast<T>(rk_c(st)) * h;
@@ -242,7 +320,6 @@ __device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int
                     for (int c = 0; c < KC; ++c) dY[p][c] = dYn[p][c];
                 }
             }
-            buf ^= 1;
         }
 #pragma unroll
         for (int p = 0; p < P; ++p)
@@ -275,16 +352,11 @@ __device__ __forceinline__ void tlm_body(const SweepArgs<T>& a, int tile_id, int
         }
 }
 
-template <typename T, int P, int KC>
-__device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int grp) {
-    extern __shared__ __align__(16) unsigned char sh_raw[];
-    T* sh = reinterpret_cast<T*>(sh_raw);
-    constexpr int W = 1 + KC;
-    const int NT = blockDim.x, t = threadIdx.x;
+template <typename T, int P, int KC, typename X>
+__device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int grp, int t, X& xch) {
     const int n = a.n;
     const int tstart = tile_id * a.tile;
     const int tlen = min(a.tile, n - tstart);
-    const int tl = t > 0 ? t - 1 : 0, tr = t < NT - 1 ? t + 1 : NT - 1;
     const T h = a.h, i2 = a.inv2dx, nd = a.nu_dx2;
     const T nd2 = T(2) * nd;
 
@@ -305,7 +377,6 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
 #pragma unroll
     for (int p = 0; p < P; ++p) unext[p] = static_cast<T>(a.base[static_cast<size_t>(s_hi - a.base_row0) * n + g[p]]);
 
-    int buf = 0;
     for (int s = s_hi; s >= a.s0; --s) {
         // observation forcing at state index s+1, before transposing step s -> s+1
         const int s1 = s + 1;
@@ -339,12 +410,13 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
         for (int p = 0; p < P; ++p) Ys[0][p] = u[p];
 #pragma unroll
         for (int st = 0; st < 3; ++st) {
-            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
-            B[t * W] = Ys[st][0];
-            B[(NT + t) * W] = Ys[st][P - 1];
-            __syncthreads();
-            YL[st] = B[(NT + tl) * W];
-            YR[st] = B[tr * W];
+            {
+                const T e0[1] = {Ys[st][0]}, e1[1] = {Ys[st][P - 1]};
+                T fl[1], fr[1];
+                xch(e0, e1, fl, fr);
+                YL[st] = fl[0];
+                YR[st] = fr[0];
+            }
             const T ch = static_cast<T>(rk_c(st)) * h;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -353,7 +425,6 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
                 const T K = rhs_pt<T>(Ys[st][p], ym, yp, i2, nd);
                 Ys[st + 1][p] = fma(ch, K, u[p]);
             }
-            buf ^= 1;
         }
         // reverse stages: mu_i = adjoint of dK_i, theta_i = J(Y_i)^T mu_i
         T mu[P][KC], lu[P][KC];
@@ -366,26 +437,33 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
             }
 #pragma unroll
         for (int st = 3; st >= 0; --st) {
-            T* B = sh + static_cast<size_t>(buf) * 2 * NT * W;
-            if (st == 3) {
-                B[t * W] = Ys[3][0];
-                B[(NT + t) * W] = Ys[3][P - 1];
-            }
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                B[t * W + 1 + c] = mu[0][c];
-                B[(NT + t) * W + 1 + c] = mu[P - 1][c];
-            }
-            __syncthreads();
-            if (st == 3) {
-                YL[3] = B[(NT + tl) * W];
-                YR[3] = B[tr * W];
-            }
             T ml[KC], mr[KC];
+            if (st == 3) {
+                // the last stage state's edges travel with the first adjoint stage
+                T e0[1 + KC], e1[1 + KC], fl[1 + KC], fr[1 + KC];
+                e0[0] = Ys[3][0];
+                e1[0] = Ys[3][P - 1];
 #pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                ml[c] = B[(NT + tl) * W + 1 + c];
-                mr[c] = B[tr * W + 1 + c];
+                for (int c = 0; c < KC; ++c) {
+                    e0[1 + c] = mu[0][c];
+                    e1[1 + c] = mu[P - 1][c];
+                }
+                xch(e0, e1, fl, fr);
+                YL[3] = fl[0];
+                YR[3] = fr[0];
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    ml[c] = fl[1 + c];
+                    mr[c] = fr[1 + c];
+                }
+            } else {
+                T e0[KC], e1[KC];
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    e0[c] = mu[0][c];
+                    e1[c] = mu[P - 1][c];
+                }
+                xch(e0, e1, ml, mr);
             }
             // coefficients of the next mu: mu_{st} = a_lam * lam + a_th * theta
             const T a_lam = st == 1 ? h / T(6) : h / T(3);
@@ -416,7 +494,6 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
 #pragma unroll
                     for (int c = 0; c < KC; ++c) mu[p][c] = mun[p][c];
             }
-            buf ^= 1;
         }
 #pragma unroll
         for (int p = 0; p < P; ++p)
@@ -434,12 +511,35 @@ __device__ __forceinline__ void adj_body(const SweepArgs<T>& a, int tile_id, int
 
 template <typename T, int P, int KC>
 __global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_tlm_kernel(SweepArgs<T> a) {
-    tlm_body<T, P, KC>(a, blockIdx.x, blockIdx.y);
+    extern __shared__ __align__(16) unsigned char sh_raw[];
+    LdsExchange<T, 1 + KC> x(reinterpret_cast<T*>(sh_raw), blockDim.x, threadIdx.x);
+    tlm_body<T, P, KC>(a, blockIdx.x, blockIdx.y, threadIdx.x, x);
 }
 
 template <typename T, int P, int KC>
 __global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kernel(SweepArgs<T> a) {
-    adj_body<T, P, KC>(a, blockIdx.x, blockIdx.y);
+    extern __shared__ __align__(16) unsigned char sh_raw[];
+    LdsExchange<T, 1 + KC> x(reinterpret_cast<T*>(sh_raw), blockDim.x, threadIdx.x);
+    adj_body<T, P, KC>(a, blockIdx.x, blockIdx.y, threadIdx.x, x);
+}
+
+// Wave regions: wave item = blockIdx.x * (blockDim.x / 64) + wave index, with
+// tile = item / ngroups and group = item % ngroups, so that the waves of one
+// workgroup share a tile.
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(256) burgers_tlm_wave_kernel(SweepArgs<T> a, int ngroups, int nitems) {
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= nitems) return;  // the whole wave leaves
+    WaveExchange x;
+    tlm_body<T, P, KC>(a, item / ngroups, item % ngroups, threadIdx.x & 63, x);
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(256) burgers_adj_wave_kernel(SweepArgs<T> a, int ngroups, int nitems) {
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    WaveExchange x;
+    adj_body<T, P, KC>(a, item / ngroups, item % ngroups, threadIdx.x & 63, x);
 }
 
 // Batched sweeps: one launch covers the current interval of every problem of a
@@ -447,33 +547,56 @@ __global__ void __launch_bounds__((sweep_max_threads<P, KC>())) burgers_adj_kern
 template <typename T, int P, int KC>
 __global__ void __launch_bounds__((sweep_max_threads<P, KC>()))
     burgers_tlm_batched_kernel(const SweepArgs<T>* __restrict__ args, const int4* __restrict__ items) {
+    extern __shared__ __align__(16) unsigned char sh_raw[];
     const int4 it = items[blockIdx.x];
     const SweepArgs<T> a = args[it.x];
-    tlm_body<T, P, KC>(a, it.y, it.z);
+    LdsExchange<T, 1 + KC> x(reinterpret_cast<T*>(sh_raw), blockDim.x, threadIdx.x);
+    tlm_body<T, P, KC>(a, it.y, it.z, threadIdx.x, x);
 }
 
 template <typename T, int P, int KC>
 __global__ void __launch_bounds__((sweep_max_threads<P, KC>()))
     burgers_adj_batched_kernel(const SweepArgs<T>* __restrict__ args, const int4* __restrict__ items) {
+    extern __shared__ __align__(16) unsigned char sh_raw[];
     const int4 it = items[blockIdx.x];
     const SweepArgs<T> a = args[it.x];
-    adj_body<T, P, KC>(a, it.y, it.z);
+    LdsExchange<T, 1 + KC> x(reinterpret_cast<T*>(sh_raw), blockDim.x, threadIdx.x);
+    adj_body<T, P, KC>(a, it.y, it.z, threadIdx.x, x);
 }
 
 void check_tiling(const Tiling& t, int n, int halo, int S) {
+    RP4D_REQUIRE(t.xch == XCH_LDS || t.xch == XCH_WAVE, RP4D_EINVAL, "sweep tiling: unknown exchange");
+    if (t.xch == XCH_WAVE)
+        RP4D_REQUIRE(t.threads == 64 || t.threads == 128 || t.threads == 256, RP4D_EINVAL,
+                     "sweep tiling: wave regions take 64, 128 or 256 threads per workgroup");
     RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0, RP4D_EINVAL,
                  "sweep tiling: threads must be a multiple of 64 in [64, 1024]");
     RP4D_REQUIRE(t.tile >= 1 && t.tile <= n, RP4D_EINVAL, "sweep tiling: tile out of range");
     RP4D_REQUIRE(halo >= 4 * S + 4, RP4D_EINVAL, "sweep tiling: halo too small for steps per launch");
-    RP4D_REQUIRE(static_cast<long>(t.threads) * t.ppt >= static_cast<long>(t.tile) + 2L * halo, RP4D_EINVAL,
-                 "sweep tiling: region (threads * ppt) smaller than tile + 2 * halo");
+    const long region = static_cast<long>(t.xch == XCH_WAVE ? 64 : t.threads) * t.ppt;
+    RP4D_REQUIRE(region >= static_cast<long>(t.tile) + 2L * halo, RP4D_EINVAL,
+                 "sweep tiling: region (threads per region * ppt) smaller than tile + 2 * halo");
 }
 
 }  // namespace
 
 void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st) {
     check_tiling(t, a.n, a.halo, a.S);
-    dim3 grid((a.n + t.tile - 1) / t.tile), block(t.threads);
+    const int ntiles = (a.n + t.tile - 1) / t.tile;
+    if (t.xch == XCH_WAVE) {
+        const int wpg = t.threads / 64;
+        dim3 grid((ntiles + wpg - 1) / wpg), block(t.threads);
+        switch (t.ppt) {
+            case 1: burgers_fwd_wave_kernel<1><<<grid, block, 0, st>>>(a, ntiles); break;
+            case 2: burgers_fwd_wave_kernel<2><<<grid, block, 0, st>>>(a, ntiles); break;
+            case 4: burgers_fwd_wave_kernel<4><<<grid, block, 0, st>>>(a, ntiles); break;
+            case 8: burgers_fwd_wave_kernel<8><<<grid, block, 0, st>>>(a, ntiles); break;
+            default: fail(RP4D_EINVAL, "sweep tiling: unsupported points per thread for fwd");
+        }
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    dim3 grid(ntiles), block(t.threads);
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * sizeof(double);
     switch (t.ppt) {
         case 1: burgers_fwd_kernel<1><<<grid, block, shmem, st>>>(a); break;
@@ -483,6 +606,16 @@ void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st) {
         default: fail(RP4D_EINVAL, "sweep tiling: unsupported points per thread for fwd");
     }
     RP4D_HIP(hipGetLastError());
+}
+
+template <typename T, int P, int KC>
+static void launch_one_wave(int mode, const SweepArgs<T>& a, int ngroups, int nitems, int threads, hipStream_t st) {
+    const int wpg = threads / 64;
+    dim3 grid((nitems + wpg - 1) / wpg), block(threads);
+    if (mode == MODE_TLM)
+        burgers_tlm_wave_kernel<T, P, KC><<<grid, block, 0, st>>>(a, ngroups, nitems);
+    else
+        burgers_adj_wave_kernel<T, P, KC><<<grid, block, 0, st>>>(a, ngroups, nitems);
 }
 
 template <typename T, int P, int KC>
@@ -506,7 +639,25 @@ template <typename T>
 void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st) {
     check_tiling(t, a.n, a.halo, a.S);
     RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "sweep: bad mode");
-    dim3 grid((a.n + t.tile - 1) / t.tile, ngroups), block(t.threads);
+    const int ntiles = (a.n + t.tile - 1) / t.tile;
+    if (t.xch == XCH_WAVE) {
+        const int nitems = ntiles * ngroups;
+        switch (t.ppt * 100 + t.kc) {
+            case 101: launch_one_wave<T, 1, 1>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 102: launch_one_wave<T, 1, 2>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 104: launch_one_wave<T, 1, 4>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 201: launch_one_wave<T, 2, 1>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 202: launch_one_wave<T, 2, 2>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 204: launch_one_wave<T, 2, 4>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 401: launch_one_wave<T, 4, 1>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 402: launch_one_wave<T, 4, 2>(mode, a, ngroups, nitems, t.threads, st); break;
+            case 801: launch_one_wave<T, 8, 1>(mode, a, ngroups, nitems, t.threads, st); break;
+            default: fail(RP4D_EINVAL, "sweep tiling: unsupported (points per thread, vectors per group) for wave regions");
+        }
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    dim3 grid(ntiles, ngroups), block(t.threads);
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
     RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "sweep tiling: LDS exchange buffer too large");
     const int key = t.ppt * 100 + t.kc;
@@ -563,6 +714,7 @@ void launch_burgers_sweep_batched(int mode, const SweepArgs<T>* args, const int4
                                   hipStream_t st) {
     if (nitems <= 0) return;
     RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "batched sweep: bad mode");
+    RP4D_REQUIRE(t.xch == XCH_LDS, RP4D_EINVAL, "batched sweep: workgroup regions only");
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
     RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "batched sweep: LDS exchange buffer too large");
     switch (t.ppt * 100 + t.kc) {

@@ -58,8 +58,12 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 enum SweepMode { MODE_TLM = 1, MODE_ADJ = 2 };
 
+// Neighbour exchange of a sweep region: the workgroup through LDS, or each
+// 64-lane wave on its own through DPP lane shifts.
+enum SweepExchange { XCH_LDS = 1, XCH_WAVE = 2 };
+
 struct Tiling {
-    int ppt = 0, kc = 0, threads = 0, tile = 0, steps = 0;
+    int ppt = 0, kc = 0, threads = 0, tile = 0, steps = 0, xch = XCH_LDS;
 };
 
 template <typename T>

@@ -25,6 +25,7 @@ NYSTROM, RANDSVD, NOPREC = 0, 1, 2
 BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
+XCH_LDS, XCH_WAVE = 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
           ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE", EHIP: "EHIP", ESTATE: "ESTATE"}
@@ -116,8 +117,8 @@ _SIGS = {
     "rp4d_batch_fwd": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_D)], _I),
     "rp4d_batch_hessian_block": ([_P, ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P), _I, _I], _I),
     "rp4d_batch_gn_step": ([_P, ctypes.POINTER(_P), ctypes.POINTER(GnOpts), ctypes.POINTER(GnInfo)], _I),
-    "rp4d_set_sweep_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I, _I], _I),
-    "rp4d_get_sweep_tiling": ([_P, _I, _I, _I] + [ctypes.POINTER(_I)] * 5, _I),
+    "rp4d_set_sweep_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I, _I, _I], _I),
+    "rp4d_get_sweep_tiling": ([_P, _I, _I, _I] + [ctypes.POINTER(_I)] * 6, _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -340,13 +341,13 @@ class Problem:
     def reset_counters(self):
         _check(_lib.rp4d_counters_reset(self._h))
 
-    def set_sweep_tiling(self, dtype=F64, k=0, ppt=0, kc=0, threads=0, tile=0, steps=0, mode=MODE_BOTH):
-        _check(_lib.rp4d_set_sweep_tiling(self._h, mode, dtype, k, ppt, kc, threads, tile, steps))
+    def set_sweep_tiling(self, dtype=F64, k=0, ppt=0, kc=0, threads=0, tile=0, steps=0, mode=MODE_BOTH, xch=0):
+        _check(_lib.rp4d_set_sweep_tiling(self._h, mode, dtype, k, ppt, kc, threads, tile, steps, xch))
 
     def get_sweep_tiling(self, dtype=F64, k=1, mode=MODE_TLM):
-        vals = [_I() for _ in range(5)]
+        vals = [_I() for _ in range(6)]
         _check(_lib.rp4d_get_sweep_tiling(self._h, mode, dtype, k, *[ctypes.byref(v) for v in vals]))
-        return dict(zip(("ppt", "kc", "threads", "tile", "steps"), (v.value for v in vals)))
+        return dict(zip(("ppt", "kc", "threads", "tile", "steps", "xch"), (v.value for v in vals)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -124,13 +124,38 @@ def test_tilings_are_bitwise_identical(ragged):
     pr = ragged
     V = to_dev(_rand((pr.orc.n, 9), 81))
     base = pr.gpu.hessian_block(pr.traj, V).clone()
-    for ppt, kc, threads, tile, steps in [(1, 1, 128, 50, 1), (2, 2, 128, 64, 5), (4, 4, 128, 200, 7),
-                                          (2, 4, 256, 17, 3), (4, 1, 64, 100, 2)]:
-        pr.gpu.set_sweep_tiling(k=9, ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps)
+    from paper_2401_15758_amd import rp4d
+    L, Wv = rp4d.XCH_LDS, rp4d.XCH_WAVE
+    # workgroup regions, then wave regions (64 * ppt points each; the last one
+    # wraps the 200-point ring more than twice)
+    for ppt, kc, threads, tile, steps, xch in [(1, 1, 128, 50, 1, L), (2, 2, 128, 64, 5, L), (4, 4, 128, 200, 7, L),
+                                               (2, 4, 256, 17, 3, L), (4, 1, 64, 100, 2, L),
+                                               (1, 1, 64, 16, 5, Wv), (2, 2, 128, 40, 9, Wv),
+                                               (4, 1, 256, 100, 15, Wv), (2, 4, 256, 30, 3, Wv),
+                                               (1, 4, 128, 7, 6, Wv), (8, 1, 64, 150, 25, Wv)]:
+        pr.gpu.set_sweep_tiling(k=9, ppt=ppt, kc=kc, threads=threads, tile=tile, steps=steps, xch=xch)
+        assert pr.gpu.get_sweep_tiling(k=9)["xch"] == xch
         out = pr.gpu.hessian_block(pr.traj, V)
         torch.cuda.synchronize()
-        assert torch.equal(out, base), (ppt, kc, threads, tile, steps)
+        assert torch.equal(out, base), (ppt, kc, threads, tile, steps, xch)
     pr.gpu.set_sweep_tiling(k=9)
+
+
+def test_wave_tiling_rejects_short_regions(ragged):
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = ragged
+    V = to_dev(_rand((pr.orc.n, 2), 82))
+    # 64 * 1 points cannot hold a 20-point tile plus two 24-point halos
+    pr.gpu.set_sweep_tiling(k=2, ppt=1, kc=1, threads=64, tile=20, steps=5, xch=rp4d.XCH_WAVE)
+    with pytest.raises(rp4d.Rp4dError):
+        pr.gpu.hessian_block(pr.traj, V)
+    # wave workgroups group at most 4 waves
+    pr.gpu.set_sweep_tiling(k=2, ppt=1, kc=1, threads=512, tile=16, steps=5, xch=rp4d.XCH_WAVE)
+    with pytest.raises(rp4d.Rp4dError):
+        pr.gpu.hessian_block(pr.traj, V)
+    pr.gpu.set_sweep_tiling(k=2)
+    torch.cuda.synchronize()
 
 
 def test_fwd_tilings_are_bitwise_identical(ragged):
@@ -143,13 +168,17 @@ def test_fwd_tilings_are_bitwise_identical(ragged):
     obs0 = pr.gpu.observe(pr.traj).clone()
     hv0 = pr.gpu.hessian_block(pr.traj, V).clone()
     tr = pr.gpu.traj()
-    for ppt, threads, tile, steps in [(1, 128, 50, 4), (2, 192, 100, 8), (8, 64, 200, 12), (4, 256, 200, 25)]:
-        pr.gpu.set_sweep_tiling(mode=rp4d.MODE_FWD, ppt=ppt, threads=threads, tile=tile, steps=steps)
-        assert pr.gpu.get_sweep_tiling(mode=rp4d.MODE_FWD)["steps"] == steps
+    L, Wv = rp4d.XCH_LDS, rp4d.XCH_WAVE
+    for ppt, threads, tile, steps, xch in [(1, 128, 50, 4, L), (2, 192, 100, 8, L), (8, 64, 200, 12, L),
+                                           (4, 256, 200, 25, L), (1, 64, 24, 4, Wv), (2, 128, 56, 8, Wv),
+                                           (4, 256, 120, 16, Wv), (8, 64, 200, 30, Wv)]:
+        pr.gpu.set_sweep_tiling(mode=rp4d.MODE_FWD, ppt=ppt, threads=threads, tile=tile, steps=steps, xch=xch)
+        got = pr.gpu.get_sweep_tiling(mode=rp4d.MODE_FWD)
+        assert got["steps"] == steps and got["xch"] == xch
         pr.gpu.fwd(pr.xb_dev, tr, want_J=False)
         torch.cuda.synchronize()
-        assert torch.equal(pr.gpu.observe(tr), obs0), (ppt, threads, tile, steps)
-        assert torch.equal(pr.gpu.hessian_block(tr, V), hv0), (ppt, threads, tile, steps)
+        assert torch.equal(pr.gpu.observe(tr), obs0), (ppt, threads, tile, steps, xch)
+        assert torch.equal(pr.gpu.hessian_block(tr, V), hv0), (ppt, threads, tile, steps, xch)
     pr.gpu.set_sweep_tiling(mode=rp4d.MODE_FWD)
 
 
@@ -198,7 +227,10 @@ def test_large_config_sampled_columns():
     """burgers-4096 (n=4096, 500 steps, k=64) in the launch configuration the
     benchmark times; the oracle checks 3 sampled columns."""
     need_gpu()
+    from paper_2401_15758_amd import autotune
     pr = Pair(inputs.CFG_LARGE)
+    for k in (64, 1):
+        autotune.apply_cached(pr.gpu, inputs.CFG_LARGE["nsteps"], k)
     V = inputs.omega(4096, 64, seed=1000)
     HV = to_np(pr.gpu.hessian_block(pr.traj, to_dev(V)))
     cols = [0, 31, 63]
