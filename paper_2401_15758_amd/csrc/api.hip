@@ -168,6 +168,27 @@ __global__ void scale_cols(double* A, int l, const double* cs) {
     if (idx < l * l) A[idx] *= cs[idx % l];
 }
 
+// nu = scale * sqrt(max(lambda_max, 0)) with scale = sqrt(n) eps (Alg. 2's shift).
+__global__ void nystrom_nu_kernel(const double* lmax, double scale, double* nu) {
+    nu[0] = scale * sqrt(fmax(lmax[0], 0.0));
+}
+
+__global__ void scale_scalar(double* v, double f) { v[0] *= f; }
+
+// y += a x with a read from device memory (same rounding as axpby with beta = 1).
+__global__ void axpy_dev(const double* x, const double* a, double* y, size_t count) {
+    const double alpha = a[0], beta = 1.0;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        y[i] = alpha * x[i] + beta * y[i];
+}
+
+// out = v / sqrt(sc[0]) (same rounding as axpby with alpha = 1 / sqrt(sc[0]), beta = 0).
+__global__ void scale_inv_sqrt(const double* v, const double* sc, double* out, int n) {
+    const double alpha = 1.0 / sqrt(sc[0]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = alpha * v[i];
+}
+
 __global__ void transpose_small(const double* A, double* B, int l) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < l * l) B[(idx % l) * l + idx / l] = A[idx];
@@ -1004,25 +1025,28 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_sym_lmax(s.S2, l, s.lam, s.S3, st);
     }
-    double ymax2 = 0.0;
-    copy_host(p, &ymax2, s.lam, sizeof(double));
+    // nu stays on the device (s.nu); a non-finite sketch surfaces as a failed
+    // Cholesky factorisation below
     const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
-    double nu = std::sqrt(static_cast<double>(n)) * eps * std::sqrt(std::max(ymax2, 0.0));
-    RP4D_REQUIRE(std::isfinite(nu), RP4D_ENONFINITE, "non-finite sketch");
+    nystrom_nu_kernel<<<1, 1, 0, st>>>(s.lam, std::sqrt(static_cast<double>(n)) * eps, s.nu);
+    RP4D_HIP(hipGetLastError());
     bool ok = false;
     for (int attempt = 0; attempt <= 3; ++attempt) {
         // step 4: Y <- Y + nu Omega ; step 5: C = Omega^T Y, L = chol((C + C^T)/2)
         launch_relayout<double, double>(s.Yd, 1, s.Y2, 1, n * l, 1, st);
-        launch_axpby(s.Om, nu, s.Y2, 1.0, static_cast<size_t>(n) * l, st);
+        const size_t cnt = static_cast<size_t>(n) * l;
+        axpy_dev<<<nblk(static_cast<long>(cnt)), 256, 0, st>>>(s.Om, s.nu, s.Y2, cnt);
+        RP4D_HIP(hipGetLastError());
         launch_gram<double, double>(s.Om, l, s.Y2, l, n, l, l, s.S2, s.gw, st);
         launch_chol(s.S2, l, s.info, st);
         if (read_info(p, s.info) == 0) {
             ok = true;
             break;
         }
-        nu *= 10.0;
+        scale_scalar<<<1, 1, 0, st>>>(s.nu, 10.0);
+        RP4D_HIP(hipGetLastError());
     }
-    RP4D_REQUIRE(ok, RP4D_ENOTSPD, "Nystrom core matrix not positive definite after shift retries");
+    RP4D_REQUIRE(ok, RP4D_ENOTSPD, "Nystrom core matrix not positive definite after shift retries (or non-finite sketch)");
     // step 6-7: W = L^{-1} Y^T ; W W^T = L^{-1} (Y^T Y) L^{-T}; eig -> U, Sigma^2
     launch_trinv(s.S2, s.S3, l, st);                                  // S3 = L^{-1}
     launch_gram<double, double>(s.Y2, l, s.Y2, l, n, l, l, s.S4, s.gw, st);  // S4 = Y^T Y
@@ -1032,14 +1056,13 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_jacobi_eig(s.S4, s.ev, s.S2, l, st);                       // ev = Sigma^2, S2 = U
     }
-    sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, nu, l, s.lam, s.D, s.cs);
+    sketch_finalize<<<1, 128, 0, st>>>(s.ev, s.nu, 0.0, l, s.lam, s.D, s.cs);
     RP4D_HIP(hipGetLastError());
     // V_hat = W^T U Sigma^{-1} = Y L^{-T} U Sigma^{-1}
     scale_cols<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S2, l, s.cs);
     launch_small_gemm(s.S3, 1, s.S2, 0, s.S4, l, 1.0, st);            // S4 = L^{-T} U Sigma^{-1}
     pc->V.ensure(static_cast<size_t>(n) * l * sizeof(double));
     launch_tsmm<double, double>(s.Y2, l, s.S4, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
-    pc->nu = nu;
 }
 
 // One Cholesky-QR pass on Y (rows x l, FP64, in s.Yd): G = Y^T Y + shift I = L L^T,
@@ -1121,7 +1144,7 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     scale_cols<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, l, s.cs);
     pc->V.ensure(static_cast<size_t>(n) * l * sizeof(double));
     launch_tsmm<double, double>(s.S1, l, s.S3, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
-    pc->nu = 0.0;
+    launch_fill<double>(s.nu, 1, 0.0, st);
 }
 
 void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const double* R, double* Z) {
@@ -1137,6 +1160,51 @@ void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const do
     launch_tsmm<double, double>(pc->V.as<double>(), l, T, pc->Dg.as<double>(), n, l, k, -1.0, R, k, 1.0, Z, k, st);
 }
 
+// Sketch and factor into `pc` (its buffers are reused when large enough).
+// Everything is enqueued on the problem stream; the only host wait is the
+// Nystrom core's Cholesky check.  Host copies of the eigenvalues and the shift
+// are fetched on demand (fetch_host).
+void build_precond_into(rp4d_problem* p, const rp4d_traj* tr, int method, int ell, uint64_t seed,
+                        const double* omega, int sketch_dtype, rp4d_precond* pc) {
+    RP4D_REQUIRE(method == RP4D_NYSTROM || method == RP4D_RANDSVD, RP4D_EINVAL, "unknown sketch method");
+    RP4D_REQUIRE(ell >= 1 && ell <= 128 && ell <= p->n, RP4D_EINVAL, "ell must be in [1, min(128, n)]");
+    RP4D_REQUIRE(sketch_dtype == RP4D_F64 || sketch_dtype == RP4D_F32, RP4D_EINVAL, "bad sketch dtype");
+    hipStream_t st = stream_of(p);
+    Scratch s = sketch_scratch(p, ell, sketch_dtype);
+    if (omega)
+        launch_relayout<double, double>(omega, 1, s.Om, 1, p->n * ell, 1, st);
+    else
+        launch_philox_normal(seed, static_cast<size_t>(p->n) * ell, s.Om, st);
+    pc->p = p;
+    pc->ell = ell;
+    pc->host_ok = false;
+    if (method == RP4D_NYSTROM)
+        build_nystrom(p, tr, ell, sketch_dtype, s, pc);
+    else
+        build_randsvd(p, tr, ell, sketch_dtype, s, pc);
+    pc->Dg.ensure(static_cast<size_t>(ell) * sizeof(double));
+    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, ell, 1, st);
+    pc->lamd.ensure(static_cast<size_t>(ell + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, ell, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + ell, 1, 1, 1, st);
+    p->cnt.tlm_offline += ell;
+    p->cnt.adj_offline += ell;
+    p->cnt.sketches += 1;
+}
+
+// Host copies of Lambda_hat and nu (one copy and wait after each build).
+void fetch_host(const rp4d_precond* pc) {
+    if (pc->host_ok) return;
+    std::vector<double> h(static_cast<size_t>(pc->ell) + 1);
+    RP4D_HIP(hipMemcpyAsync(h.data(), pc->lamd.p, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            stream_of(pc->p)));
+    sync(pc->p);
+    for (double v : h) RP4D_REQUIRE(std::isfinite(v), RP4D_ENONFINITE, "non-finite sketch eigenvalues");
+    pc->lam.assign(h.begin(), h.begin() + pc->ell);
+    pc->nu = h[pc->ell];
+    pc->host_ok = true;
+}
+
 }  // namespace
 }  // namespace rp4d
 
@@ -1147,36 +1215,15 @@ int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* tr, int method, int ell
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
         check_traj(p, tr);
-        RP4D_REQUIRE(method == RP4D_NYSTROM || method == RP4D_RANDSVD, RP4D_EINVAL, "unknown sketch method");
-        RP4D_REQUIRE(ell >= 1 && ell <= 128 && ell <= p->n, RP4D_EINVAL, "ell must be in [1, min(128, n)]");
-        RP4D_REQUIRE(sketch_dtype == RP4D_F64 || sketch_dtype == RP4D_F32, RP4D_EINVAL, "bad sketch dtype");
         set_device(p->ctx);
-        hipStream_t st = stream_of(p);
-        Scratch s = sketch_scratch(p, ell, sketch_dtype);
-        if (omega)
-            launch_relayout<double, double>(omega, 1, s.Om, 1, p->n * ell, 1, st);
-        else
-            launch_philox_normal(seed, static_cast<size_t>(p->n) * ell, s.Om, st);
         auto* pc = new rp4d_precond();
         try {
-            pc->p = p;
-            pc->ell = ell;
-            if (method == RP4D_NYSTROM)
-                build_nystrom(p, tr, ell, sketch_dtype, s, pc);
-            else
-                build_randsvd(p, tr, ell, sketch_dtype, s, pc);
-            pc->Dg.ensure(static_cast<size_t>(ell) * sizeof(double));
-            launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, ell, 1, st);
-            pc->lam.resize(ell);
-            copy_host(p, pc->lam.data(), s.lam, ell * sizeof(double));
-            for (double v : pc->lam) RP4D_REQUIRE(std::isfinite(v), RP4D_ENONFINITE, "non-finite sketch eigenvalues");
+            build_precond_into(p, tr, method, ell, seed, omega, sketch_dtype, pc);
+            fetch_host(pc);
         } catch (...) {
             delete pc;
             throw;
         }
-        p->cnt.tlm_offline += ell;
-        p->cnt.adj_offline += ell;
-        p->cnt.sketches += 1;
         *out = pc;
     });
 }
@@ -1195,6 +1242,10 @@ int rp4d_precond_info(const rp4d_precond* pc, int* ell, double* lambda_host, dou
     return guarded([&] {
         RP4D_REQUIRE(pc != nullptr, RP4D_EINVAL, "null preconditioner");
         if (ell) *ell = pc->ell;
+        if (lambda_host || nu_host) {
+            set_device(pc->p->ctx);
+            fetch_host(pc);
+        }
         if (lambda_host) std::memcpy(lambda_host, pc->lam.data(), pc->lam.size() * sizeof(double));
         if (nu_host) *nu_host = pc->nu;
     });
@@ -1296,8 +1347,12 @@ void capture(rp4d_ctx* c, F&& f, GraphExec& out) {
     RP4D_HIP(e2);
 }
 
+// snap (host, SC_COUNT doubles, nullable) receives the whole scalar block at the
+// first read, so that callers get values they enqueued earlier without a wait
+// of their own.
 void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, const double* b, double* x,
-              double rtol, int maxit, rp4d_pcg_info* info, bool true_res, rp4d::DevBuf& vecs) {
+              double rtol, int maxit, rp4d_pcg_info* info, bool true_res, rp4d::DevBuf& vecs,
+              double* snap = nullptr) {
     hipStream_t st = stream_of(p);
     const int n = p->n;
     vecs.ensure(5 * static_cast<size_t>(n) * sizeof(double) + 1024 * sizeof(double));
@@ -1317,7 +1372,18 @@ void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, cons
     launch_relayout<double, double>(z, 1, pv, 1, n, 1, st);
     launch_dot(r, z, n, sc + SC_RZ, red, st);
     launch_dot(b, b, n, sc + SC_BB, red, st);
-    const double bnorm = std::sqrt(read_scalar(p, sc + SC_BB));
+    double bb = 0.0;
+    if (snap) {
+        RP4D_HIP(hipMemcpyAsync(snap, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync(p);
+        bb = snap[SC_BB];
+    } else {
+        bb = read_scalar(p, sc + SC_BB);
+    }
+    const double bnorm = std::sqrt(bb);
+    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_DD]), RP4D_ENONFINITE,
+                 "non-finite innovations (state blew up or bad input)");
+    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
     RP4D_REQUIRE(std::isfinite(bnorm), RP4D_ENONFINITE, "non-finite right-hand side");
     double rnorm = bnorm;
     int it = 0;
@@ -1389,17 +1455,19 @@ double kappa_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, 
     double* q = z + n;
     double* red = z + 5 * static_cast<size_t>(n);
     double* sc = p->ws_scal.as<double>();
-    // normalise v
+    // normalise v on the device (|v|^2 in SC_T0), then |(I + H) P v_hat|^2 in SC_T1
     launch_dot(v, v, n, sc + SC_T0, red, st);
-    const double vn = std::sqrt(read_scalar(p, sc + SC_T0));
-    RP4D_REQUIRE(vn > 0 && std::isfinite(vn), RP4D_EINVAL, "kappa_re: zero or non-finite test vector");
     double* vu = q + n;
-    launch_fill<double>(vu, n, 0.0, st);
-    launch_axpby(v, 1.0 / vn, vu, 0.0, n, st);
+    scale_inv_sqrt<<<nblk(n), 256, 0, st>>>(v, sc + SC_T0, vu, n);
+    RP4D_HIP(hipGetLastError());
     precond_apply_impl(p, pc, 1, vu, z);
     hessian_dispatch(p, tr, 1, z, q, RP4D_F64, true);
-    launch_dot(q, q, n, sc + SC_T0, red, st);
-    return std::sqrt(read_scalar(p, sc + SC_T0));
+    launch_dot(q, q, n, sc + SC_T1, red, st);
+    double h[2];
+    RP4D_HIP(hipMemcpyAsync(h, sc + SC_T0, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(p);
+    RP4D_REQUIRE(h[0] > 0 && std::isfinite(h[0]), RP4D_EINVAL, "kappa_re: zero or non-finite test vector");
+    return std::sqrt(h[1]);
 }
 
 }  // namespace
@@ -1527,7 +1595,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         // 4-5. reuse test or sketch
         const rp4d_precond* use = nullptr;
         if (o->sketch != RP4D_NOPREC) {
-            if (s->pc && o->reuse_eps > 0) {
+            if (s->pc_live && o->reuse_eps > 0) {
                 const double* vh = o->vhat;
                 double* tmpv = nullptr;
                 if (!vh) {
@@ -1543,34 +1611,30 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 }
             }
             if (!use) {
-                if (s->pc) {
-                    rp4d_precond_destroy(s->pc);
-                    s->pc = nullptr;
-                }
-                rc = rp4d_build_precond(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, &s->pc);
-                RP4D_REQUIRE(rc == RP4D_OK, rc, g_last_error);
+                // rebuild in place: the object and its device buffers persist
+                s->pc_live = false;
+                if (!s->pc) s->pc = new rp4d_precond();
+                build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
+                s->pc_live = true;
                 use = s->pc;
                 inf.sketched = 1;
             }
         }
-        // join the gradient; J, |g|_inf
+        // join the gradient; J and |g|_inf arrive with PCG's first scalar read
         if (overlap) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
         double sch[SC_COUNT];
-        RP4D_HIP(hipMemcpyAsync(sch, sc, sizeof(sch), hipMemcpyDeviceToHost, st));
-        RP4D_HIP(hipStreamSynchronize(st));
-        RP4D_REQUIRE(std::isfinite(sch[SC_DD]), RP4D_ENONFINITE, "non-finite innovations (state blew up or bad input)");
-        RP4D_REQUIRE(std::isfinite(sch[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
-        inf.J = 0.5 * sch[SC_VV] + 0.5 * sch[SC_DD];
-        inf.gnorm_inf = sch[SC_GI];
         // 6. PCG
         rp4d_pcg_info pi{};
         int pcg_rc = RP4D_OK;
         try {
-            pcg_impl(p, s->traj, use, s->b.as<double>(), s->dv.as<double>(), o->rtol, o->maxit, &pi, false, vecs);
+            pcg_impl(p, s->traj, use, s->b.as<double>(), s->dv.as<double>(), o->rtol, o->maxit, &pi, false, vecs,
+                     sch);
         } catch (const Error& e) {
             if (e.code != RP4D_ENOCONV) throw;
             pcg_rc = e.code;
         }
+        inf.J = 0.5 * sch[SC_VV] + 0.5 * sch[SC_DD];
+        inf.gnorm_inf = sch[SC_GI];
         inf.pcg_iters = pi.iters;
         inf.pcg_converged = pi.converged;
         inf.pcg_relres = pi.relres;
@@ -1591,10 +1655,7 @@ int rp4d_gn_state_reset(rp4d_gn_state* s) {
         launch_fill<double>(s->v.as<double>(), p->n, 0.0, st);
         launch_fill<double>(s->dv.as<double>(), p->n, 0.0, st);
         launch_relayout<double, double>(p->xb.as<double>(), 1, s->x.as<double>(), 1, p->n, 1, st);
-        if (s->pc) {
-            rp4d_precond_destroy(s->pc);
-            s->pc = nullptr;
-        }
+        s->pc_live = false;  // the object and its buffers stay for the next build
     });
 }
 
@@ -2443,6 +2504,7 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
         RP4D_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < np; ++i) {
             out[i]->nu = nuh[i];
+            out[i]->host_ok = true;
             for (double v : out[i]->lam) RP4D_REQUIRE(std::isfinite(v), RP4D_ENONFINITE, "non-finite sketch (batch)");
             b->probs[sel[i]]->cnt.tlm_offline += l;
             b->probs[sel[i]]->cnt.adj_offline += l;
@@ -2639,7 +2701,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
         if (o->sketch != RP4D_NOPREC) {
             std::vector<int> test;
             for (int i = 0; i < np; ++i)
-                if (states[i]->pc && o->reuse_eps > 0) test.push_back(i);
+                if (states[i]->pc && states[i]->pc_live && o->reuse_eps > 0) test.push_back(i);
             if (!test.empty()) {
                 // unit test vectors from Philox, z = P v, q = (I + H) z, kappa = |q| / |v|
                 std::vector<BRand> rd;
@@ -2692,6 +2754,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
                     const int i = need[q];
                     if (states[i]->pc) rp4d_precond_destroy(states[i]->pc);
                     states[i]->pc = pcs[q];
+                    states[i]->pc_live = true;
                     use[i] = pcs[q];
                     inf[i].sketched = 1;
                 }

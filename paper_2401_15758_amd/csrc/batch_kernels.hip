@@ -116,6 +116,16 @@ __global__ void __launch_bounds__(256) btsmm_kernel(const BTsmm* __restrict__ de
         }
         __syncthreads();
     }
+    // Out may alias C: read every C element of the thread before any store
+    double cv[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int row = r0 + ti * 4 + p, col = j0 + tj * 4 + s;
+            cv[p][s] = (d.beta != 0.0 && row < d.n && col < d.b) ? static_cast<double>(C[boff(row, col, d.lc, d.n)])
+                                                                  : 0.0;
+        }
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -123,7 +133,7 @@ __global__ void __launch_bounds__(256) btsmm_kernel(const BTsmm* __restrict__ de
             const int row = r0 + ti * 4 + p, col = j0 + tj * 4 + s;
             if (row < d.n && col < d.b) {
                 double v = d.alpha * acc[p][s];
-                if (d.beta != 0.0) v += d.beta * static_cast<double>(C[boff(row, col, d.lc, d.n)]);
+                if (d.beta != 0.0) v += d.beta * cv[p][s];
                 Out[boff(row, col, d.lo, d.n)] = static_cast<TO>(v);
             }
         }

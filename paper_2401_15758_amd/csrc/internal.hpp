@@ -356,13 +356,17 @@ struct rp4d_precond {
     int ell = 0;
     rp4d::DevBuf V;       // (n, ell) row-major
     rp4d::DevBuf Dg;      // lam / (1 + lam)
-    std::vector<double> lam;
-    double nu = 0.0;
+    rp4d::DevBuf lamd;    // device: lam (ell), then nu
+    // host copies of lamd, fetched on first use after a build
+    mutable bool host_ok = false;
+    mutable std::vector<double> lam;
+    mutable double nu = 0.0;
 };
 
 struct rp4d_gn_state {
     rp4d_problem* p = nullptr;
     rp4d::DevBuf v, x, dv, g, b;
     rp4d_traj* traj = nullptr;
-    rp4d_precond* pc = nullptr;
+    rp4d_precond* pc = nullptr;  // kept allocated across resets; rebuilt in place
+    bool pc_live = false;        // pc holds the current resident preconditioner
 };

@@ -96,125 +96,251 @@ __global__ void axpby_kernel(const double* x, double alpha, double* y, double be
 }
 
 // ---------------------------------------------------------------------------
-// Tall-skinny Gram: partial[chunk][a][b] over row chunks, 64x64 output tiles,
-// 4x4 register blocking; fixed-order reduction over chunks afterwards.
+// Tall-skinny products on FP64 MFMA (16x16x4).  Both kernels stage all of a
+// workgroup's operand rows through LDS in one round of global loads, so each
+// launch pays one memory latency; a workgroup owns a 64 x 64 output tile and
+// its four waves 32 x 32 quadrants (2 x 2 MFMA blocks).  Operand fragments:
+// lane l holds A[l%16][l/16] and B[l/16][l%16]; the FP64 accumulator element r
+// of lane l is row 4r + l/16, column l%16.  LDS operands are k-major with rows
+// padded by 16 elements, so the half-waves of a fragment read use disjoint
+// banks.  Accumulation order is fixed by the kernel: results are deterministic.
 // ---------------------------------------------------------------------------
-constexpr int GR = 16;  // rows staged per LDS pass
+typedef double ts_v4d __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ ts_v4d ts_mfma(double a, double b, ts_v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int GR = 64;       // Gram: rows per block (the MFMA k dimension), multiple of 4
+constexpr int TS_PAD = 16;   // LDS row padding of k-major operands (elements)
+constexpr int LDW = 64 + TS_PAD;  // k-major operand: S[k * LDW + col]
+constexpr int LDK = GR + 4;       // col-major operand: S[col * LDK + k]
+
+// Offset of element (j, c) of an n-row matrix in the blocked layout with kc
+// vectors per block.  Blocked layouts have power-of-two kc (shifts and masks);
+// any other kc is a row-major matrix of width <= kc (checked by the launchers).
+__device__ __forceinline__ size_t ts_off(int j, int c, int kc, int n) {
+    if ((kc & (kc - 1)) == 0) {
+        const int sh = __builtin_ctz(kc);
+        return ((static_cast<size_t>(c >> sh) * n + j) << sh) + (c & (kc - 1));
+    }
+    return static_cast<size_t>(j) * kc + c;
+}
+
+template <typename TX>
+__device__ __forceinline__ double ts_ld(const TX* X, int lx, int n, int row, int col, int nrow, int ncol) {
+    return (row < nrow && col < ncol) ? static_cast<double>(X[ts_off(row, col, lx, n)]) : 0.0;
+}
+
+// An operand block of GR rows x 64 columns in LDS.  Loaded with lanes walking
+// the columns when the layout is row-major-like (lx >= 16) and the rows
+// otherwise, and stored in the orientation that keeps those stores contiguous:
+// k-major S[k * LDW + col] or column-major S[col * LDK + k].
+struct TsBlock {
+    bool colwalk;
+    __device__ __forceinline__ void coords(int e, int& k, int& c) const {
+        k = colwalk ? e / 64 : e % GR;
+        c = colwalk ? e % 64 : e / GR;
+    }
+    __device__ __forceinline__ int at(int k, int c) const { return colwalk ? k * LDW + c : c * LDK + k; }
+};
+constexpr int TS_BLOCK_DOUBLES = GR * LDW > 64 * LDK ? GR * LDW : 64 * LDK;
+
+// partial[chunk][i * b + j] = sum over the chunk's rows r of X(r, i0 + i) Y(r, j0 + j);
+// a chunk is `rows` consecutive rows (a multiple of GR), consumed GR at a time
+// with the next block's loads issued before the current block's MFMAs.
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(256) gram_partial_kernel(const TX* X, int lx, const TY* Y, int ly, int n, int a,
-                                                           int b, int rows_per_chunk, double* part) {
-    __shared__ double xs[GR][64];
-    __shared__ double ys[GR][64];
+                                                           int b, int rows, double* part) {
+    __shared__ double Xs[TS_BLOCK_DOUBLES];
+    __shared__ double Ys[TS_BLOCK_DOUBLES];
     const int chunk = blockIdx.x;
     const int tiles_b = (b + 63) / 64;
-    const int ta = blockIdx.y / tiles_b, tb = blockIdx.y % tiles_b;
-    const int i0 = ta * 64, j0 = tb * 64;
-    const int r0 = chunk * rows_per_chunk;
-    const int r1 = min(n, r0 + rows_per_chunk);
-    const int tid = threadIdx.x;
-    const int ti = tid / 16, tj = tid % 16;
-    double acc[4][4] = {};
-    for (int rr = r0; rr < r1; rr += GR) {
-        for (int e = tid; e < GR * 64; e += 256) {
-            const int r = e / 64, col = e % 64;
-            const int row = rr + r;
-            xs[r][col] = (row < r1 && i0 + col < a) ? static_cast<double>(X[blk_off(row, i0 + col, lx, n)]) : 0.0;
-            ys[r][col] = (row < r1 && j0 + col < b) ? static_cast<double>(Y[blk_off(row, j0 + col, ly, n)]) : 0.0;
+    const int i0 = (blockIdx.y / tiles_b) * 64, j0 = (blockIdx.y % tiles_b) * 64;
+    const int r0 = chunk * rows;
+    const int r1 = min(n, r0 + rows);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int PER = GR * 64 / 256;
+    const TsBlock bx{lx >= 16}, by{ly >= 16};
+    double xv[PER], yv[PER];
+    auto load = [&](int rb) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            xv[q] = ts_ld(X, lx, n, rb + k, i0 + c, r1, a);
+            by.coords(e, k, c);
+            yv[q] = ts_ld(Y, ly, n, rb + k, j0 + c, r1, b);
+        }
+    };
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    ts_v4d acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = ts_v4d{0.0, 0.0, 0.0, 0.0};
+    load(r0);
+    for (int rb = r0; rb < r1; rb += GR) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            Xs[bx.at(k, c)] = xv[q];
+            by.coords(e, k, c);
+            Ys[by.at(k, c)] = yv[q];
         }
         __syncthreads();
+        if (rb + GR < r1) load(rb + GR);
+        // C = X^T Y: A[i][k] = X(k, i), B[k][j] = Y(k, j)
 #pragma unroll 4
-        for (int r = 0; r < GR; ++r) {
-            double xv[4], yv[4];
+        for (int k0 = 0; k0 < GR; k0 += 4) {
+            const int kk = k0 + (lane >> 4);
+            double fa[2], fb[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                xv[q] = xs[r][ti * 4 + q];
-                yv[q] = ys[r][tj * 4 + q];
+            for (int u = 0; u < 2; ++u) {
+                fa[u] = Xs[bx.at(kk, wi + 16 * u + (lane & 15))];
+                fb[u] = Ys[by.at(kk, wj + 16 * u + (lane & 15))];
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma(xv[p], yv[q], acc[p][q]);
+                for (int v = 0; v < 2; ++v) acc[u][v] = ts_mfma(fa[u], fb[v], acc[u][v]);
         }
         __syncthreads();
     }
     double* P = part + static_cast<size_t>(chunk) * a * b;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + ti * 4 + p, j = j0 + tj * 4 + q;
-            if (i < a && j < b) P[static_cast<size_t>(i) * b + j] = acc[p][q];
-        }
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * u + 4 * r + (lane >> 4);
+                const int j = j0 + wj + 16 * v + (lane & 15);
+                if (i < a && j < b) P[static_cast<size_t>(i) * b + j] = acc[u][v][r];
+            }
 }
 
+// out[idx] = sum_c part[c][idx], c in increasing order; loads issued 16 at a time.
 __global__ void reduce_chunks_kernel(const double* part, int nchunks, size_t stride, double* out) {
     const size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
     if (idx >= stride) return;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[static_cast<size_t>(c) * stride + idx];
+    int c = 0;
+    for (; c + 16 <= nchunks; c += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = part[static_cast<size_t>(c + q) * stride + idx];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += v[q];
+    }
+    for (; c < nchunks; ++c) s += part[static_cast<size_t>(c) * stride + idx];
     out[idx] = s;
 }
 
-int gram_chunks(int n) {
-    int rows = (n + 127) / 128;
-    rows = ((rows + GR - 1) / GR) * GR;
-    if (rows < 64) rows = 64;
-    return (n + rows - 1) / rows;
+// Rows per Gram chunk: single GR blocks up to 256 chunks, longer chunks beyond.
+int gram_rows(int n) {
+    const int blocks = (n + GR - 1) / GR;
+    return GR * ((blocks + 255) / 256);
 }
 
+int gram_chunks(int n) { return (n + gram_rows(n) - 1) / gram_rows(n); }
+
 // ---------------------------------------------------------------------------
-// Out (n x b) = beta * C + alpha * X diag(ds) M ; 64-row x 64-col output tiles.
+// Out (n x b) = beta * C + alpha * X diag(ds) M, 64 x 64 output tiles; K (= a)
+// in blocks of GR staged through LDS (one block for K <= 64), the next block's
+// loads issued before the current block's MFMAs.  X's block is an operand block
+// indexed (k, row); M's is k-major.
 // ---------------------------------------------------------------------------
 template <typename TX, typename TO>
 __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const double* M, const double* ds, int n,
                                                    int a, int b, double alpha, const TO* C, int lc, double beta,
                                                    TO* Out, int lo) {
-    __shared__ double xs[64][17];
-    __shared__ double ms[16][64];
+    __shared__ double Xs[TS_BLOCK_DOUBLES];
+    __shared__ double Ms[GR * LDW];
     const int r0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-    const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
-    double acc[4][4] = {};
-    for (int kk = 0; kk < a; kk += 16) {
-        for (int e = tid; e < 64 * 16; e += 256) {
-            const int r = e / 16, q = e % 16;
-            const int row = r0 + r, col = kk + q;
-            xs[r][q] = (row < n && col < a) ? static_cast<double>(X[blk_off(row, col, lx, n)]) : 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int PER = GR * 64 / 256;
+    // X(row, k): "columns" of the operand block are rows of the output
+    const TsBlock bx{lx < 16};
+    double xv[PER], mv[PER];
+    auto load = [&](int kk) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            xv[q] = ts_ld(X, lx, n, r0 + c, kk + k, n, a);
+            const int mk = e / 64, mj = e % 64;
+            double m = (kk + mk < a && j0 + mj < b) ? M[static_cast<size_t>(kk + mk) * b + j0 + mj] : 0.0;
+            if (ds != nullptr && kk + mk < a) m *= ds[kk + mk];
+            mv[q] = m;
         }
-        for (int e = tid; e < 16 * 64; e += 256) {
-            const int q = e / 64, j = e % 64;
-            const int i = kk + q, col = j0 + j;
-            double v = (i < a && col < b) ? M[static_cast<size_t>(i) * b + col] : 0.0;
-            if (ds && i < a) v *= ds[i];
-            ms[q][j] = v;
+    };
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    ts_v4d acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = ts_v4d{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (int kk = 0; kk < a; kk += GR) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            Xs[bx.at(k, c)] = xv[q];
+            Ms[(e / 64) * LDW + e % 64] = mv[q];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-            double xv[4], mv[4];
+        if (kk + GR < a) load(kk + GR);
+        const int kend = min(GR, a - kk);
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            double fa[2], fb[2];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                xv[p] = xs[ti * 4 + p][q];
-                mv[p] = ms[q][tj * 4 + p];
+            for (int u = 0; u < 2; ++u) {
+                fa[u] = Xs[bx.at(k, wi + 16 * u + (lane & 15))];
+                fb[u] = Ms[k * LDW + wj + 16 * u + (lane & 15)];
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) acc[p][s] = fma(xv[p], mv[s], acc[p][s]);
+                for (int v = 0; v < 2; ++v) acc[u][v] = ts_mfma(fa[u], fb[v], acc[u][v]);
         }
         __syncthreads();
     }
+    // Out may alias C: every C element of the lane is read before any store, so
+    // the loads go out together instead of one round trip per output
+    double cv[2][2][4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int row = r0 + ti * 4 + p, col = j0 + tj * 4 + s;
-            if (row < n && col < b) {
-                double v = alpha * acc[p][s];
-                if (beta != 0.0) v += beta * static_cast<double>(C[blk_off(row, col, lc, n)]);
-                Out[blk_off(row, col, lo, n)] = static_cast<TO>(v);
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + wi + 16 * u + 4 * r + (lane >> 4);
+                const int col = j0 + wj + 16 * v + (lane & 15);
+                cv[u][v][r] = (beta != 0.0 && row < n && col < b) ? static_cast<double>(C[ts_off(row, col, lc, n)])
+                                                                  : 0.0;
             }
-        }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + wi + 16 * u + 4 * r + (lane >> 4);
+                const int col = j0 + wj + 16 * v + (lane & 15);
+                if (row < n && col < b) {
+                    double val = alpha * acc[u][v][r];
+                    if (beta != 0.0) val += beta * cv[u][v][r];
+                    Out[ts_off(row, col, lo, n)] = static_cast<TO>(val);
+                }
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -775,15 +901,21 @@ size_t gram_work_doubles(int n, int a, int b) {
     return static_cast<size_t>(gram_chunks(n)) * a * b;
 }
 
+// Blocked layouts have power-of-two kc; any other leading size is a row-major
+// matrix whose width must not exceed it.
+static void check_ts_layout(int kc, int width) {
+    RP4D_REQUIRE(kc > 0 && ((kc & (kc - 1)) == 0 || width <= kc), RP4D_EINVAL,
+                 "tall-skinny product: layout width exceeds a non-power-of-two leading size");
+}
+
 template <typename TX, typename TY>
 void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
                  hipStream_t st) {
-    const int nch = gram_chunks(n);
-    const int rows = (n + nch - 1) / nch;
-    const int rows_r = ((rows + GR - 1) / GR) * GR;
-    const int nchunks = (n + rows_r - 1) / rows_r;
+    check_ts_layout(lx, a);
+    check_ts_layout(ly, b);
+    const int nchunks = gram_chunks(n);
     dim3 grid(nchunks, ((a + 63) / 64) * ((b + 63) / 64));
-    gram_partial_kernel<TX, TY><<<grid, 256, 0, st>>>(X, lx, Y, ly, n, a, b, rows_r, work);
+    gram_partial_kernel<TX, TY><<<grid, 256, 0, st>>>(X, lx, Y, ly, n, a, b, gram_rows(n), work);
     RP4D_HIP(hipGetLastError());
     const size_t stride = static_cast<size_t>(a) * b;
     reduce_chunks_kernel<<<grid_for(stride), 256, 0, st>>>(work, nchunks, stride, C);
@@ -793,6 +925,9 @@ void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, 
 template <typename TX, typename TO>
 void launch_tsmm(const TX* X, int lx, const double* M, const double* dscale, int n, int a, int b, double alpha,
                  const TO* Cin, int lc, double beta, TO* Out, int lo, hipStream_t st) {
+    check_ts_layout(lx, a);
+    check_ts_layout(lo, b);
+    if (beta != 0.0) check_ts_layout(lc, b);
     dim3 grid((n + 63) / 64, (b + 63) / 64);
     tsmm_kernel<TX, TO><<<grid, 256, 0, st>>>(X, lx, M, dscale, n, a, b, alpha, Cin, lc, beta, Out, lo);
     RP4D_HIP(hipGetLastError());

@@ -63,6 +63,26 @@ def test_batched_hessian_matches_single_problem_path():
         assert colwise_relerr(to_np(HB[i]), to_np(HS)) <= 1e-6   # FP32 sweeps, different prior reduction order
 
 
+def test_batched_trajectory_serves_single_problem_sweeps_bitwise():
+    """A trajectory filled by the batched FWD serves the single-problem path:
+    observations and FP64 block Hessians on it are bitwise those on a
+    trajectory from rp4d_fwd."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    b.fwd([to_dev(o.xb) for o in orcs], trajs, want_J=False)
+    Vs = [to_dev(np.random.default_rng(40 + i).standard_normal((o.n, 5))) for i, o in enumerate(orcs)]
+    for i, p in enumerate(probs):
+        own = p.traj()
+        p.fwd(to_dev(orcs[i].xb), own, want_J=False)
+        a = p.hessian_block(trajs[i], Vs[i]).clone()
+        c = p.hessian_block(own, Vs[i])
+        torch.cuda.synchronize()
+        assert torch.equal(p.observe(trajs[i]), p.observe(own)), i
+        assert torch.equal(a, c), i
+
+
 def test_batch_invariance_alone_and_in_mix():
     """Each problem's batched block Hessian is bitwise identical whether it runs
     alone or with the other problems."""
