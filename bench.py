@@ -68,10 +68,11 @@ def measured_traffic(kname, tiling, cfg):
     except (OSError, ValueError):
         return None
     keys = ("ppt", "kc", "threads", "tile", "steps", "xch")
-    if (rec.get("source_sha256") != sha or rec.get("kernel") != kname or rec.get("workload") != cfg["name"]
-            or any(rec.get("tiling", {}).get(k) != tiling.get(k) for k in keys)):
-        return None
-    return rec["bytes_per_launch"]
+    for r in rec.get("records", []):
+        if (r.get("source_sha256") == sha and r.get("kernel") == kname and r.get("workload") == cfg["name"]
+                and all(r.get("tiling", {}).get(k) == tiling.get(k) for k in keys)):
+            return r["bytes_per_launch"]
+    return None
 
 
 def bve_section(rp4d, inputs, torch, np):
