@@ -268,7 +268,8 @@ def main():
         step()
     torch.cuda.synchronize()
     prob.reset_counters()
-    ctx.set_timing(True)
+    # one HIP event pair per sweep (not per launch): timing must not slow the steps
+    ctx.set_timing(rp4d.TIMING_SPAN)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos, step_ms = [], []
@@ -297,7 +298,8 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(kname, tl, cfg),
                 "avg_launch_us": 1e3 * ks["total_ms"] / max(1, ks["launches"]),
-                "launches": ks["launches"]}
+                "launches": ks["launches"],
+                "timing": "HIP events on the library stream, one pair around each sweep's launches"}
 
     # the same assimilation with the sketch-reuse test (kappa_re < 10 keeps the
     # resident preconditioner, Sec. 3.2): fewer products per GN step

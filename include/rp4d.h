@@ -260,8 +260,13 @@ int rp4d_bve_inv_laplacian(rp4d_problem* p, int k, const void* in, void* out, in
 /* Reset a GN state to v = 0, x = x_b and drop its resident preconditioner. */
 int rp4d_gn_state_reset(rp4d_gn_state* s);
 
-/* Kernel timing with HIP events recorded on the context stream around every
- * launch of the timed kernel classes (enable = 1 clears the statistics).
+/* Kernel timing with HIP events recorded on the context stream (any call clears
+ * the statistics): enable = 1 records an event pair around every launch of the
+ * timed kernel classes; enable = 2 records one pair around each Burgers sweep's
+ * loop of launches (classes TLM, ADJ, TLM1, ADJ1, FWD; the others per launch),
+ * so that timing barely perturbs what it measures -- per-launch averages are
+ * then span time / launches and include the gaps between the sweep's launches;
+ * enable = 0 stops timing.
  * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps, k > 1), RP4D_K_FWD, RP4D_K_BHALF,
  * RP4D_K_TLM1, RP4D_K_ADJ1 (single-vector sweeps, k = 1) and RP4D_K_EIG (the
  * small symmetric eigensolves of the sketch post-processing; flops reported 0),

@@ -36,36 +36,65 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-KernelTimer::KernelTimer(rp4d_ctx* ctx, int k, double fl) : c(ctx), kind(k), flops(fl) {
-    if (!c->timing || c->capturing) return;
+namespace {
+hipEvent_t pooled_event(rp4d_ctx* c) {
     if (c->event_pool.empty()) {
-        hipEvent_t e;
-        RP4D_HIP(hipEventCreate(&e));
-        c->event_pool.push_back(e);
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
     }
-    a = c->event_pool.back();
+    hipEvent_t e = c->event_pool.back();
     c->event_pool.pop_back();
-    RP4D_HIP(hipEventRecord(a, c->stream));
+    return e;
 }
 
-KernelTimer::~KernelTimer() {
-    if (!a) return;
-    hipEvent_t b = nullptr;
-    if (c->event_pool.empty()) {
-        if (hipEventCreate(&b) != hipSuccess) {
-            c->event_pool.push_back(a);
-            return;
-        }
-    } else {
-        b = c->event_pool.back();
-        c->event_pool.pop_back();
+// Record the closing event of a pair opened with `a` and queue it for resolution.
+void close_pair(rp4d_ctx* c, int kind, hipEvent_t a, double flops, long long nl) {
+    hipEvent_t b = pooled_event(c);
+    if (b == nullptr) {
+        c->event_pool.push_back(a);
+        return;
     }
     if (hipEventRecord(b, c->stream) != hipSuccess) {
         c->event_pool.push_back(a);
         c->event_pool.push_back(b);
         return;
     }
-    c->pending.push_back(rp4d_ctx::Pending{kind, a, b, flops});
+    c->pending.push_back(rp4d_ctx::Pending{kind, a, b, flops, nl});
+}
+}  // namespace
+
+KernelTimer::KernelTimer(rp4d_ctx* ctx, int k, double fl) : c(ctx), kind(k), flops(fl) {
+    if (!c->timing || c->capturing) return;
+    if (c->span_open[kind]) {  // counted by the enclosing span
+        c->span_launches[kind] += 1;
+        c->span_flops[kind] += fl;
+        return;
+    }
+    a = pooled_event(c);
+    if (a == nullptr) RP4D_HIP(hipErrorOutOfMemory);
+    RP4D_HIP(hipEventRecord(a, c->stream));
+}
+
+KernelTimer::~KernelTimer() {
+    if (!a) return;
+    close_pair(c, kind, a, flops, 1);
+}
+
+SpanTimer::SpanTimer(rp4d_ctx* ctx, int k) : c(ctx), kind(k) {
+    if (c->timing != 2 || c->capturing || c->span_open[kind]) return;
+    a = pooled_event(c);
+    if (a == nullptr) RP4D_HIP(hipErrorOutOfMemory);
+    RP4D_HIP(hipEventRecord(a, c->stream));
+    c->span_open[kind] = true;
+    c->span_launches[kind] = 0;
+    c->span_flops[kind] = 0.0;
+}
+
+SpanTimer::~SpanTimer() {
+    if (!a) return;
+    c->span_open[kind] = false;
+    close_pair(c, kind, a, c->span_flops[kind], c->span_launches[kind]);
 }
 
 namespace {
@@ -77,7 +106,7 @@ void resolve_timing(rp4d_ctx* c) {
     for (auto& pe : c->pending) {
         float ms = 0.f;
         RP4D_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
-        c->launches[pe.kind] += 1;
+        c->launches[pe.kind] += pe.nlaunch;
         c->ms[pe.kind] += ms;
         c->flops[pe.kind] += pe.flops;
         c->event_pool.push_back(pe.a);
@@ -322,6 +351,7 @@ void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* sto
     a.y = p->has_data ? p->y.as<double>() : nullptr;
     a.innov = p->has_data ? innov : nullptr;
     a.obs_out = obs_out;
+    SpanTimer span(p->ctx, RP4D_K_FWD);
     for (int s0 = s_from; s0 < s_to; s0 += t.steps) {
         a.s0 = s0;
         a.S = std::min(t.steps, s_to - s0);
@@ -375,6 +405,7 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
             a.base = seg;
             a.base_row0 = seg0;
         }
+        SpanTimer span(p->ctx, k == 1 ? RP4D_K_TLM1 : RP4D_K_TLM);
         for (int s0 = seg0; s0 < seg1; s0 += t.steps) {
             a.s0 = s0;
             a.S = std::min(t.steps, seg1 - s0);
@@ -433,6 +464,7 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
             a.base_row0 = seg0;
         }
         // intervals from the top of the segment down
+        SpanTimer span(p->ctx, k == 1 ? RP4D_K_ADJ1 : RP4D_K_ADJ);
         int s_hi = seg1;
         while (s_hi > seg0) {
             const int Sc = std::min(t.steps, s_hi - seg0);
@@ -1678,8 +1710,9 @@ int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable) {
     return guarded([&] {
         RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
         set_device(ctx);
+        RP4D_REQUIRE(enable >= 0 && enable <= 2, RP4D_EINVAL, "timing mode must be 0, 1 or 2");
         resolve_timing(ctx);
-        ctx->timing = enable != 0;
+        ctx->timing = enable;
         for (int i = 0; i < RP4D_K_COUNT; ++i) {
             ctx->launches[i] = 0;
             ctx->ms[i] = 0.0;

@@ -256,13 +256,19 @@ void launch_bcopy(const BCopy* d, const int4* items, int nitems, hipStream_t st)
 struct rp4d_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    // kernel timing (HIP events around launches of the timed kernel classes)
-    bool timing = false;
+    // kernel timing: 0 off, 1 an event pair around every launch of the timed
+    // classes, 2 one pair around each Burgers sweep's launch loop (SpanTimer)
+    int timing = 0;
     struct Pending {
         int kind;
         hipEvent_t a, b;
         double flops;
+        long long nlaunch;
     };
+    // launches and flops of the open span of each class (timing mode 2)
+    bool span_open[RP4D_K_COUNT] = {};
+    long long span_launches[RP4D_K_COUNT] = {};
+    double span_flops[RP4D_K_COUNT] = {};
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     // second stream (default priority) for work that overlaps the main stream,
@@ -280,7 +286,8 @@ struct rp4d_ctx {
 };
 
 namespace rp4d {
-// Timing scope: records an event pair around the launches issued in its lifetime.
+// Timing scope: records an event pair around the launches issued in its
+// lifetime; inside an open span of its class it only counts the launch.
 struct KernelTimer {
     rp4d_ctx* c;
     int kind;
@@ -288,6 +295,15 @@ struct KernelTimer {
     hipEvent_t a = nullptr;
     KernelTimer(rp4d_ctx* ctx, int k, double fl);
     ~KernelTimer();
+};
+// Span of one class (timing mode 2): one event pair around a loop of launches
+// whose KernelTimers count launches and flops without events of their own.
+struct SpanTimer {
+    rp4d_ctx* c;
+    int kind;
+    hipEvent_t a = nullptr;
+    SpanTimer(rp4d_ctx* ctx, int k);
+    ~SpanTimer();
 };
 }  // namespace rp4d
 

@@ -26,6 +26,7 @@ BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
 XCH_LDS, XCH_WAVE = 1, 2
+TIMING_LAUNCH, TIMING_SPAN = 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
           ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE", EHIP: "EHIP", ESTATE: "ESTATE"}
@@ -177,7 +178,10 @@ class Context:
         return out
 
     def set_timing(self, enable=True):
-        _check(_lib.rp4d_ctx_set_timing(self._h, 1 if enable else 0))
+        """True / TIMING_LAUNCH: events around every timed launch; TIMING_SPAN:
+        one event pair per Burgers sweep; False: off."""
+        mode = (TIMING_LAUNCH if enable else 0) if isinstance(enable, bool) else int(enable)
+        _check(_lib.rp4d_ctx_set_timing(self._h, mode))
 
     def set_graphs(self, enable=True):
         _check(_lib.rp4d_ctx_set_graphs(self._h, 1 if enable else 0))

@@ -255,6 +255,24 @@ def test_synthesis_parity(cfg):
     assert relerr(to_np(y), orc.y) <= 1e-13
 
 
+def test_span_timing_counts_like_per_launch_timing(small):
+    """Timing mode 2 (one event pair per sweep) reports the same launches and
+    flops as per-launch timing, and a duration of the same order."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    V = to_dev(_rand((pr.orc.n, 4), 112))
+    stats = {}
+    for mode in (rp4d.TIMING_LAUNCH, rp4d.TIMING_SPAN):
+        pr.ctx.set_timing(mode)
+        pr.gpu.hessian_block(pr.traj, V)
+        stats[mode] = [pr.ctx.kernel_stats(k) for k in (rp4d.K_TLM, rp4d.K_ADJ)]
+        pr.ctx.set_timing(False)
+    for a, b in zip(stats[rp4d.TIMING_LAUNCH], stats[rp4d.TIMING_SPAN]):
+        assert a['launches'] == b['launches'] and a['alg_flops'] == b['alg_flops']
+        assert b['total_ms'] > 0 and 0.2 * a['total_ms'] < b['total_ms'] < 5 * a['total_ms']
+
+
 def test_kernel_timing_counts_launches(small):
     torch = need_gpu()
     from paper_2401_15758_amd import rp4d
