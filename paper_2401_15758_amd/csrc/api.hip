@@ -1079,22 +1079,24 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         RP4D_HIP(hipGetLastError());
     }
     RP4D_REQUIRE(ok, RP4D_ENOTSPD, "Nystrom core matrix not positive definite after shift retries (or non-finite sketch)");
-    // step 6-7: W = L^{-1} Y^T ; W W^T = L^{-1} (Y^T Y) L^{-T}; eig -> U, Sigma^2
+    // step 6-7: B = Y L^{-T} (n x l); B^T B = U Sigma^2 U^T.  Forming B before the
+    // Gram keeps the error at eps cond(L) |B|^2 (the Gram of Y between two
+    // triangular inverses would square cond(L)).
     launch_trinv(s.S2, s.S3, l, st);                                  // S3 = L^{-1}
-    launch_gram<double, double>(s.Y2, l, s.Y2, l, n, l, l, s.S4, s.gw, st);  // S4 = Y^T Y
-    launch_small_gemm(s.S3, 0, s.S4, 0, s.S2, l, 1.0, st);            // S2 = L^{-1} Y^T Y
-    launch_small_gemm(s.S2, 0, s.S3, 1, s.S4, l, 1.0, st);            // S4 = S2 L^{-T}
+    transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
+    RP4D_HIP(hipGetLastError());
+    launch_tsmm<double, double>(s.Y2, l, s.S4, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, s.S1, l, st);  // S1 = B
+    launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S4, s.gw, st);   // S4 = B^T B
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_jacobi_eig(s.S4, s.ev, s.S2, l, st);                       // ev = Sigma^2, S2 = U
     }
     sketch_finalize<<<1, 128, 0, st>>>(s.ev, s.nu, 0.0, l, s.lam, s.D, s.cs);
     RP4D_HIP(hipGetLastError());
-    // V_hat = W^T U Sigma^{-1} = Y L^{-T} U Sigma^{-1}
+    // V_hat = B U Sigma^{-1}
     scale_cols<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S2, l, s.cs);
-    launch_small_gemm(s.S3, 1, s.S2, 0, s.S4, l, 1.0, st);            // S4 = L^{-T} U Sigma^{-1}
     pc->V.ensure(static_cast<size_t>(n) * l * sizeof(double));
-    launch_tsmm<double, double>(s.Y2, l, s.S4, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
+    launch_tsmm<double, double>(s.S1, l, s.S2, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
 }
 
 // One Cholesky-QR pass on Y (rows x l, FP64, in s.Yd): G = Y^T Y + shift I = L L^T,

@@ -29,8 +29,8 @@ def _probe(n, k=4, seed=7):
     return np.random.default_rng(seed).standard_normal((n, k))
 
 
-@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
-@pytest.mark.parametrize("ell", [20, 7])
+@pytest.mark.parametrize("method,ell", [("nystrom", 20), ("randsvd", 20), ("nystrom", 7), ("randsvd", 7),
+                                        ("nystrom", 33), ("randsvd", 33), ("nystrom", 64)])
 def test_sketch_parity(small, method, ell):
     from paper_2401_15758_amd import rp4d
     pr = small
@@ -51,6 +51,18 @@ def test_sketch_parity(small, method, ell):
     Vg = to_np(pc.basis())
     Hh = osk.hhat_apply(Vg, glam, R)
     assert colwise_relerr(Hh, osk.hhat_apply(V, lam, R)) <= 1e-9
+
+
+def test_randsvd_rank_deficient_sketch_is_reported(small):
+    """64 columns exceed the numerical rank of A on the 128-point problem: the
+    thin QR of Y = A Omega by Cholesky QR (shifted CholeskyQR3 included) cannot
+    orthonormalise it, and the build reports ENOTSPD instead of a wrong basis."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    Om = inputs.omega(pr.orc.n, 64, seed=1064)
+    with pytest.raises(rp4d.Rp4dError) as e:
+        pr.gpu.build_precond(pr.traj, rp4d.RANDSVD, 64, omega=to_dev(Om))
+    assert e.value.code == rp4d.ENOTSPD
 
 
 def test_precond_inverts_one_plus_hhat(small):
