@@ -72,7 +72,7 @@ def wave_candidates(n, pk):
     for ppt, kc in pk:
         for steps in WAVE_STEPS:
             tmax = 64 * ppt - 2 * (4 * steps + 4)
-            if tmax < 16 and tmax < n:
+            if tmax < 4 and tmax < n:   # single-vector sweeps favour many small regions
                 continue
             tmax = min(tmax, n)
             ntiles = -(-n // tmax)
