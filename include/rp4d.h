@@ -306,11 +306,16 @@ typedef struct rp4d_batch rp4d_batch;
 /* Group `nprob` problems of one context (the batch does not own them). */
 int rp4d_batch_create(rp4d_ctx* ctx, int nprob, rp4d_problem* const* probs, rp4d_batch** out);
 int rp4d_batch_destroy(rp4d_batch* b);
-/* Tiling of the batched block sweeps (mode RP4D_MODE_TLM / RP4D_MODE_ADJ, dtype):
- * points per thread, vectors per workgroup, threads per workgroup, steps per
- * launch; each problem's tile is threads*ppt - 2*(4*steps+4) points (at most n).
- * Values <= 0 keep the defaults. */
-int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps);
+/* Tiling of the batched sweeps (mode RP4D_MODE_TLM / RP4D_MODE_ADJ with dtype, or
+ * RP4D_MODE_FWD for the forward sweep, dtype RP4D_F64, kc ignored): points per
+ * thread, vectors per region, threads per workgroup, steps per launch and the
+ * region shape xch (RP4D_XCH_WAVE, the default: one region of 64*ppt points per
+ * wave, threads 64/128/256; RP4D_XCH_LDS: one region of threads*ppt points per
+ * workgroup).  Each problem's tile is the region minus 2*(4*steps+4) points (at
+ * most n).  Values <= 0 keep the defaults (wave regions, 12 steps; ppt 4 and
+ * kc 2 for the block sweeps, ppt 2 for the forward sweep; 256 threads).
+ * Results do not depend on the tiling. */
+int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps, int xch);
 /* FWD of every problem from x0[i] (device, n_i) into trajs[i]; J_obs (host, nprob,
  * nullable) receives 1/2 |d_i|^2. */
 int rp4d_batch_fwd(rp4d_batch* b, const double* const* x0, rp4d_traj* const* trajs, double* J_obs);

@@ -1818,7 +1818,9 @@ struct rp4d_batch {
     rp4d::DevBuf dev;
     size_t cap = 0, off = 0;
     rp4d::DevBuf scal;  // 16 doubles per problem of batch scalars
-    rp4d::Tiling bt[2][2];  // [mode-1][dtype] overrides (threads, ppt, kc, steps)
+    // [mode-1][dtype] overrides (ppt, kc, threads, steps, xch; <= 0: default)
+    rp4d::Tiling bt[2][2] = {{{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}, {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}};
+    rp4d::Tiling bt_fwd = {0, 0, 0, 0, 0, 0};  // forward-sweep overrides
     ~rp4d_batch() {
         if (host) (void)hipHostFree(host);
     }
@@ -1860,33 +1862,37 @@ std::vector<int4> elem_items(const std::vector<size_t>& counts) {
     return it;
 }
 
+// Batched sweep tilings.  Defaults: wave regions (64 ppt points per wave, one
+// work item per wave), 12 steps per launch; overrides per (mode, dtype) and for
+// the forward sweep through rp4d_batch_set_tiling.
 Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd) {
     Tiling t;
-    if (fwd) {
-        t.ppt = 2;
-        t.kc = 1;
-        t.threads = 384;
-        t.steps = 16;
-        return t;
-    }
-    t.ppt = 2;
-    t.kc = 2;
+    t.xch = XCH_WAVE;
     t.threads = 256;
-    t.steps = 16;
-    const Tiling& o = b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
-    if (o.ppt > 0) t.ppt = o.ppt;
-    if (o.kc > 0) t.kc = o.kc;
-    if (o.threads > 0) t.threads = o.threads;
-    if (o.steps > 0) t.steps = o.steps;
+    t.steps = 12;
+    t.kc = 1;
+    t.ppt = 2;
+    const Tiling* o = &b->bt_fwd;
+    if (!fwd) {
+        t.ppt = 4;
+        t.kc = 2;
+        o = &b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+    }
+    if (o->ppt > 0) t.ppt = o->ppt;
+    if (o->kc > 0 && !fwd) t.kc = o->kc;
+    if (o->threads > 0) t.threads = o->threads;
+    if (o->steps > 0) t.steps = o->steps;
+    if (o->xch > 0) t.xch = o->xch;
     return t;
 }
 
+// Tile (owned points per region) of an n-point problem under tiling t.
 int batch_tile(const Tiling& t, int n) {
     RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0 && t.steps >= 1, RP4D_EINVAL,
                  "batch tiling: threads must be a multiple of 64 in [64, 1024] and steps >= 1");
     const int halo = 4 * t.steps + 4;
-    const int room = t.threads * t.ppt - 2 * halo;
-    RP4D_REQUIRE(room >= 1, RP4D_EINVAL, "batch tiling: threads * ppt too small for the halo of steps per launch");
+    const int room = (t.xch == XCH_WAVE ? 64 : t.threads) * t.ppt - 2 * halo;
+    RP4D_REQUIRE(room >= 1, RP4D_EINVAL, "batch tiling: region too small for the halo of steps per launch");
     return std::min(n, room);
 }
 
@@ -2592,15 +2598,18 @@ int rp4d_batch_destroy(rp4d_batch* b) {
     });
 }
 
-int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps) {
+int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps, int xch) {
     return guarded([&] {
-        RP4D_REQUIRE(b != nullptr && (mode == MODE_TLM || mode == MODE_ADJ) &&
+        RP4D_REQUIRE(b != nullptr && (mode == MODE_TLM || mode == MODE_ADJ || mode == RP4D_MODE_FWD) &&
                          (dtype == RP4D_F64 || dtype == RP4D_F32), RP4D_EINVAL, "bad argument");
-        Tiling& t = b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+        RP4D_REQUIRE(xch <= 0 || xch == XCH_LDS || xch == XCH_WAVE, RP4D_EINVAL,
+                     "batched sweeps: workgroup (1) or wave (2) regions");
+        Tiling& t = mode == RP4D_MODE_FWD ? b->bt_fwd : b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
         t.ppt = ppt;
         t.kc = kc;
         t.threads = threads;
         t.steps = steps;
+        t.xch = xch > 0 ? xch : 0;
     });
 }
 

@@ -564,6 +564,40 @@ __global__ void __launch_bounds__((sweep_max_threads<P, KC>()))
     adj_body<T, P, KC>(a, it.y, it.z, threadIdx.x, x);
 }
 
+// Batched wave regions: one work item (problem, tile, group) per 64-lane wave.
+template <int P>
+__global__ void __launch_bounds__(256) burgers_fwd_wave_batched_kernel(const FwdArgs* __restrict__ args,
+                                                                       const int4* __restrict__ items, int nitems) {
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= nitems) return;  // the whole wave leaves
+    const int4 it = items[item];
+    const FwdArgs a = args[it.x];
+    WaveExchange x;
+    fwd_body<P>(a, it.y, threadIdx.x & 63, x);
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(256) burgers_tlm_wave_batched_kernel(const SweepArgs<T>* __restrict__ args,
+                                                                       const int4* __restrict__ items, int nitems) {
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int4 it = items[item];
+    const SweepArgs<T> a = args[it.x];
+    WaveExchange x;
+    tlm_body<T, P, KC>(a, it.y, it.z, threadIdx.x & 63, x);
+}
+
+template <typename T, int P, int KC>
+__global__ void __launch_bounds__(256) burgers_adj_wave_batched_kernel(const SweepArgs<T>* __restrict__ args,
+                                                                       const int4* __restrict__ items, int nitems) {
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int4 it = items[item];
+    const SweepArgs<T> a = args[it.x];
+    WaveExchange x;
+    adj_body<T, P, KC>(a, it.y, it.z, threadIdx.x & 63, x);
+}
+
 void check_tiling(const Tiling& t, int n, int halo, int S) {
     RP4D_REQUIRE(t.xch == XCH_LDS || t.xch == XCH_WAVE, RP4D_EINVAL, "sweep tiling: unknown exchange");
     if (t.xch == XCH_WAVE)
@@ -680,6 +714,21 @@ void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int 
 
 void launch_burgers_fwd_batched(const FwdArgs* args, const int4* items, int nitems, const Tiling& t, hipStream_t st) {
     if (nitems <= 0) return;
+    if (t.xch == XCH_WAVE) {
+        RP4D_REQUIRE(t.threads == 64 || t.threads == 128 || t.threads == 256, RP4D_EINVAL,
+                     "batched fwd: wave regions take 64, 128 or 256 threads per workgroup");
+        const int wpg = t.threads / 64;
+        const dim3 grid((nitems + wpg - 1) / wpg);
+        switch (t.ppt) {
+            case 1: burgers_fwd_wave_batched_kernel<1><<<grid, t.threads, 0, st>>>(args, items, nitems); break;
+            case 2: burgers_fwd_wave_batched_kernel<2><<<grid, t.threads, 0, st>>>(args, items, nitems); break;
+            case 4: burgers_fwd_wave_batched_kernel<4><<<grid, t.threads, 0, st>>>(args, items, nitems); break;
+            case 8: burgers_fwd_wave_batched_kernel<8><<<grid, t.threads, 0, st>>>(args, items, nitems); break;
+            default: fail(RP4D_EINVAL, "batched fwd: unsupported points per thread");
+        }
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * sizeof(double);
     switch (t.ppt) {
         case 1: burgers_fwd_batched_kernel<1><<<nitems, t.threads, shmem, st>>>(args, items); break;
@@ -689,6 +738,17 @@ void launch_burgers_fwd_batched(const FwdArgs* args, const int4* items, int nite
         default: fail(RP4D_EINVAL, "batched fwd: unsupported points per thread");
     }
     RP4D_HIP(hipGetLastError());
+}
+
+template <typename T, int P, int KC>
+static void launch_one_wave_batched(int mode, const SweepArgs<T>* args, const int4* items, int nitems, int threads,
+                                    hipStream_t st) {
+    const int wpg = threads / 64;
+    const dim3 grid((nitems + wpg - 1) / wpg);
+    if (mode == MODE_TLM)
+        burgers_tlm_wave_batched_kernel<T, P, KC><<<grid, threads, 0, st>>>(args, items, nitems);
+    else
+        burgers_adj_wave_batched_kernel<T, P, KC><<<grid, threads, 0, st>>>(args, items, nitems);
 }
 
 template <typename T, int P, int KC>
@@ -714,7 +774,24 @@ void launch_burgers_sweep_batched(int mode, const SweepArgs<T>* args, const int4
                                   hipStream_t st) {
     if (nitems <= 0) return;
     RP4D_REQUIRE(mode == MODE_TLM || mode == MODE_ADJ, RP4D_EINVAL, "batched sweep: bad mode");
-    RP4D_REQUIRE(t.xch == XCH_LDS, RP4D_EINVAL, "batched sweep: workgroup regions only");
+    if (t.xch == XCH_WAVE) {
+        RP4D_REQUIRE(t.threads == 64 || t.threads == 128 || t.threads == 256, RP4D_EINVAL,
+                     "batched sweep: wave regions take 64, 128 or 256 threads per workgroup");
+        switch (t.ppt * 100 + t.kc) {
+            case 101: launch_one_wave_batched<T, 1, 1>(mode, args, items, nitems, t.threads, st); break;
+            case 102: launch_one_wave_batched<T, 1, 2>(mode, args, items, nitems, t.threads, st); break;
+            case 104: launch_one_wave_batched<T, 1, 4>(mode, args, items, nitems, t.threads, st); break;
+            case 201: launch_one_wave_batched<T, 2, 1>(mode, args, items, nitems, t.threads, st); break;
+            case 202: launch_one_wave_batched<T, 2, 2>(mode, args, items, nitems, t.threads, st); break;
+            case 204: launch_one_wave_batched<T, 2, 4>(mode, args, items, nitems, t.threads, st); break;
+            case 401: launch_one_wave_batched<T, 4, 1>(mode, args, items, nitems, t.threads, st); break;
+            case 402: launch_one_wave_batched<T, 4, 2>(mode, args, items, nitems, t.threads, st); break;
+            default: fail(RP4D_EINVAL, "batched sweep: unsupported (points per thread, vectors per group) for wave regions");
+        }
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    RP4D_REQUIRE(t.xch == XCH_LDS, RP4D_EINVAL, "batched sweep: unknown exchange");
     const size_t shmem = 2 * 2 * static_cast<size_t>(t.threads) * (1 + t.kc) * sizeof(T);
     RP4D_REQUIRE(shmem <= 160 * 1024, RP4D_EINVAL, "batched sweep: LDS exchange buffer too large");
     switch (t.ppt * 100 + t.kc) {

@@ -83,6 +83,33 @@ def test_batched_trajectory_serves_single_problem_sweeps_bitwise():
         assert torch.equal(a, c), i
 
 
+def test_batched_tilings_are_bitwise_identical():
+    """Batched sweeps give the same bits with wave regions (the default) and
+    with workgroup regions, for the forward sweep and the block Hessian."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    xs = [to_dev(o.xb) for o in orcs]
+    Vs = [to_dev(np.random.default_rng(50 + i).standard_normal((o.n, 5))) for i, o in enumerate(orcs)]
+    b.fwd(xs, trajs, want_J=False)
+    obs0 = [p.observe(t).clone() for p, t in zip(probs, trajs)]
+    h0 = [h.clone() for h in b.hessian_block(trajs, Vs)]
+    for tiling in [dict(xch=rp4d.XCH_LDS, ppt=2, kc=2, threads=256, steps=16),
+                   dict(xch=rp4d.XCH_WAVE, ppt=2, kc=1, threads=64, steps=5),
+                   dict(xch=rp4d.XCH_WAVE, ppt=4, kc=2, threads=128, steps=20)]:
+        for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+            b.set_tiling(mode, **tiling)
+        b.set_tiling(rp4d.MODE_FWD, ppt=tiling["ppt"], threads=tiling["threads"], steps=tiling["steps"],
+                     xch=tiling["xch"])
+        b.fwd(xs, trajs, want_J=False)
+        h = b.hessian_block(trajs, Vs)
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            assert torch.equal(probs[i].observe(trajs[i]), obs0[i]), (tiling, i)
+            assert torch.equal(h[i], h0[i]), (tiling, i)
+
+
 def test_batch_invariance_alone_and_in_mix():
     """Each problem's batched block Hessian is bitwise identical whether it runs
     alone or with the other problems."""
