@@ -30,6 +30,14 @@ def kappa_re(prob, traj, V, lam, vhat):
     return float(np.linalg.norm(prob.hessian(traj, z)))
 
 
+def build_precond_adaptive(prob, traj, Omegas, v, eps_sk):
+    """Alg. 4 on the problem's A (m x n) and H = A^T A: returns (V, lam, kappas)."""
+    m = prob.m
+    return _sketch.randsvd_adaptive(lambda X: prob.A(traj, X).reshape(m, -1),
+                                    lambda W: prob.AT(traj, W.reshape(prob.n_t, prob.n_obs, -1)),
+                                    lambda X: prob.misfit_hessian(traj, X), Omegas, v, eps_sk)
+
+
 def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
     if method == 'nystrom':
         V, lam, _ = _sketch.nystrom(lambda X: prob.misfit_hessian(traj, X), Omega, eps=eps)

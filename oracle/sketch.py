@@ -7,6 +7,8 @@ Test infrastructure only (see ``oracle/__init__``).
   * Nystrom      Sec. 3.1.1, Alg. 2 (nystrom), Tropp et al. fixed-rank Nystrom
   * LMP          eq. (woodbury): (I + V L V^T)^{-1} = I - V (L^{-1} + I)^{-1} V^T
   * W-form       Remark 1, eq. (randsvdsv): (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W
+  * adaptive     Sec. 3.1.2, Alg. 4 (randsvd_adaptive) with the test kappa_sk of
+                 eq. (condtext)
 
 Readings: no truncation (target rank r = l); machine epsilon of Nystrom's shift
 is that of the precision Y was computed in (2^-52 for float64, 2^-23 for
@@ -63,6 +65,44 @@ def randsvd_W(A_apply, AT_apply, Omega):
     Y = A_apply(np.asarray(Omega, dtype=np.float64))
     Q, _ = np.linalg.qr(Y)
     return AT_apply(Q).T.copy()
+
+
+def kappa_sk(H_apply, W, v):
+    """eq. (condtext): |(I + H)(I + H_hat)^{-1} v|_2 with H_hat = W^T W, the inverse
+    by eq. (randsvdsv); v is normalised here (a unit test vector)."""
+    v = np.asarray(v, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    u = woodbury_W_apply(W, v)
+    return float(np.linalg.norm(u + H_apply(u[:, None])[:, 0]))
+
+
+def randsvd_adaptive(A_apply, AT_apply, H_apply, Omegas, v, eps_sk):
+    """Alg. 4 (adaptive RandSVD).  Omegas is the sequence of Gaussian blocks the
+    algorithm draws (the first of width l, then blocks of width l_hat); v the
+    test vector of kappa_sk (the same at every evaluation).  The loop enlarges
+    the sketch while kappa_sk > eps_sk and blocks remain (the caller's cap on
+    l).  Returns (V_hat, lambda_hat, kappas) with one kappa_sk per evaluation.
+    Readings: the new block is orthogonalised against the accumulated Q twice
+    (classical Gram-Schmidt with one re-orthogonalisation, the "additional
+    steps if necessary" of the algorithm); thin QR by Householder."""
+    Om = np.asarray(Omegas[0], dtype=np.float64)
+    Y = A_apply(Om)                                        # forward pass Y = A Omega
+    Qh, _ = np.linalg.qr(Y)                                # thin QR
+    Wt = AT_apply(Qh)                                      # W^T = A^T Q_hat
+    Q = np.zeros((Y.shape[0], 0))
+    kappas = [kappa_sk(H_apply, Wt.T, v)]
+    for blk in Omegas[1:]:
+        if kappas[-1] <= eps_sk:
+            break
+        Q = np.hstack([Q, Qh])                             # append Q_hat
+        Y = A_apply(np.asarray(blk, dtype=np.float64))     # forward pass on the new block
+        for _ in range(2):
+            Y = Y - Q @ (Q.T @ Y)                          # orthogonalise against Q
+        Qh, _ = np.linalg.qr(Y)
+        Wt = np.hstack([Wt, AT_apply(Qh)])                 # W <- [W; W_hat]
+        kappas.append(kappa_sk(H_apply, Wt.T, v))
+    _, S, Vt = np.linalg.svd(Wt.T, full_matrices=False)    # thin SVD of W
+    return Vt.T.copy(), S * S, kappas
 
 
 def lmp_diag(lam):
