@@ -203,6 +203,31 @@ int rp4d_gradient(rp4d_problem* p, const rp4d_traj* traj, const double* v, doubl
  * Nystrom core matrix stays indefinite after 3 tenfold shift increases. */
 int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* traj, int method, int ell, uint64_t seed,
                        const double* omega, int sketch_dtype, rp4d_precond** out);
+/* Adaptive RandSVD (Sec. 3.1.2, Alg. 4): start from ell0 Gaussian columns and
+ * add ell_hat columns while kappa_sk = ||(I + H)(I + H_hat)^{-1} v||_2
+ * (eq. (condtext), (I + H_hat)^{-1} by eq. (randsvdsv)) exceeds eps_sk and the
+ * sketch stays within ell_max.  Each new block is orthogonalised twice against
+ * the accumulated basis and factored by Cholesky QR; each kappa_sk costs one
+ * single-vector Hessian product.  FP64.  Counts every sketch column and every
+ * kappa_sk product as offline TLM + ADJ. */
+typedef struct {
+    int ell0;               /* initial sketch size, >= 1 */
+    int ell_hat;            /* columns added per extension, >= 1 */
+    int ell_max;            /* largest sketch, ell0 <= ell_max <= min(128, n, m) */
+    double eps_sk;          /* stop once kappa_sk <= eps_sk (> 0; the paper uses 1.01) */
+    uint64_t seed;          /* Philox seed of Omega's blocks and of v when omega / vtest are NULL */
+    const double* omega;    /* device (n, ell_max) row-major: columns [0, ell0) the first block, then
+                               ell_hat columns per extension; or NULL */
+    const double* vtest;    /* device (n) test vector (normalised here), or NULL */
+} rp4d_adaptive_opts;
+typedef struct {
+    int ell;                /* final sketch size */
+    int nkappa;             /* evaluations of kappa_sk */
+    double kappa_sk;        /* the last value */
+    double kappa[16];       /* the first 16 values */
+} rp4d_adaptive_info;
+int rp4d_build_precond_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_adaptive_opts* opts,
+                                rp4d_precond** out, rp4d_adaptive_info* info);
 int rp4d_precond_destroy(rp4d_precond* pc);
 /* Host outputs (each nullable): ell, lambda_hat (ell, descending), Nystrom shift nu. */
 int rp4d_precond_info(const rp4d_precond* pc, int* ell, double* lambda_host, double* nu_host);

@@ -1181,6 +1181,132 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     launch_fill<double>(s.nu, 1, 0.0, st);
 }
 
+__global__ void add_identity(double* G, int l) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < l) G[static_cast<size_t>(i) * l + i] += 1.0;
+}
+
+// Seed of the Gaussian block drawn by extension r of the adaptive sketch, and of
+// its kappa_sk test vector.
+inline uint64_t adaptive_seed(uint64_t seed, int r) { return seed + 0x9E3779B97F4A7C15ULL * static_cast<uint64_t>(r); }
+inline uint64_t adaptive_vseed(uint64_t seed) { return seed ^ 0xD1B54A32D192ED03ULL; }
+
+// Adaptive RandSVD (Sec. 3.1.2, Alg. 4) into pc.  The accumulated basis Q (m x c)
+// and W^T = A^T Q (n x c) are kept row-major with leading size l_max; a new
+// block of b columns is drawn (or read from omega's columns [c, c + b)), swept
+// by the block TLM, orthogonalised against Q twice, factored by Cholesky QR,
+// swept back by the block ADJ and appended.  kappa_sk (eq. (condtext)) uses
+// (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W (eq. (randsvdsv)) and one
+// single-vector Hessian product; the loop stops once kappa_sk <= eps_sk or the
+// next block would pass l_max.  The final thin SVD of W is the eigen-
+// decomposition of W W^T, V_hat = W^T U Sigma^{-1}.  Host waits: the Cholesky
+// QR checks and one scalar read per kappa_sk.
+void build_randsvd_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_adaptive_opts& o, rp4d_precond* pc,
+                            rp4d_adaptive_info* info) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n, m = p->m, L = o.ell_max;
+    Scratch s = sketch_scratch(p, L, RP4D_F64);  // blocks of up to L columns, ell-sized results up to L
+    const size_t ll = static_cast<size_t>(L) * L;
+    const size_t gw = std::max(gram_work_doubles(n, L, L), gram_work_doubles(m, L, L));
+    p->ws_ad.ensure((static_cast<size_t>(m) * L + static_cast<size_t>(n) * L + 3 * ll + 3 * static_cast<size_t>(n) +
+                     1024 + 4 * static_cast<size_t>(L) + gw + 64) * sizeof(double));
+    double* Qa = p->ws_ad.as<double>();            // m x L
+    double* Wt = Qa + static_cast<size_t>(m) * L;  // n x L
+    double* G = Wt + static_cast<size_t>(n) * L;   // L x L
+    double* Gi = G + ll;                           // L x L
+    double* Gt = Gi + ll;                          // L x L
+    double* vu = Gt + ll;                          // n: unit test vector
+    double* u = vu + n;                            // n
+    double* q = u + n;                             // n
+    double* red = q + n;                           // 1024 (dot-product partials)
+    double* tv = red + 1024;                       // L
+    double* zv = tv + L;                           // L
+    double* agw = zv + 2 * L;                      // Gram partials
+    double* sc = p->ws_scal.as<double>();
+    // unit test vector
+    if (o.vtest)
+        launch_relayout<double, double>(o.vtest, 1, u, 1, n, 1, st);
+    else
+        launch_philox_normal(adaptive_vseed(o.seed), n, u, st);
+    launch_dot(u, u, n, sc + SC_T0, red, st);
+    scale_inv_sqrt<<<nblk(n), 256, 0, st>>>(u, sc + SC_T0, vu, n);
+    RP4D_HIP(hipGetLastError());
+    int c = 0, r = 0, nk = 0;
+    double kappa = 0.0;
+    for (;;) {
+        const int b = r == 0 ? o.ell0 : o.ell_hat;
+        if (o.omega)
+            launch_relayout<double, double>(o.omega + c, L, s.Om, b, n, b, st);
+        else
+            launch_philox_normal(adaptive_seed(o.seed, r), static_cast<size_t>(n) * b, s.Om, st);
+        tlm_impl<double>(p, tr, b, s.Om, s.Yd);                        // Y = A Omega (m x b)
+        for (int pass = 0; c > 0 && pass < 2; ++pass) {                // Y <- Y - Q (Q^T Y)
+            launch_gram<double, double>(Qa, L, s.Yd, b, m, c, b, Gt, agw, st);
+            launch_tsmm<double, double>(Qa, L, Gt, nullptr, m, c, b, -1.0, s.Yd, b, 1.0, s.Yd, b, st);
+        }
+        cholqr2(p, m, b, s);                                            // Y = Q_hat R
+        adj_impl<double>(p, tr, b, s.Yd, s.S1, nullptr);                // W_hat^T = A^T Q_hat (n x b)
+        launch_relayout<double, double>(s.Yd, b, Qa + c, L, m, b, st);
+        launch_relayout<double, double>(s.S1, b, Wt + c, L, n, b, st);
+        c += b;
+        ++r;
+        p->cnt.tlm_offline += b;
+        p->cnt.adj_offline += b;
+        // kappa_sk = |(I + H) u|, u = v - W^T (I + W W^T)^{-1} W v
+        launch_gram<double, double>(Wt, L, Wt, L, n, c, c, G, agw, st);   // G = W W^T (c x c)
+        add_identity<<<nblk(c), 256, 0, st>>>(G, c);
+        RP4D_HIP(hipGetLastError());
+        launch_chol(G, c, s.info, st);                                  // I + W W^T = Lc Lc^T (SPD)
+        launch_trinv(G, Gi, c, st);                                     // Gi = Lc^{-1}
+        launch_small_gemm(Gi, 1, Gi, 0, Gt, c, 1.0, st);                // Gt = (I + W W^T)^{-1}
+        launch_gram<double, double>(Wt, L, vu, 1, n, c, 1, tv, agw, st);  // tv = W v
+        launch_tsmm<double, double>(Gt, c, tv, nullptr, c, c, 1, 1.0, nullptr, 0, 0.0, zv, 1, st);
+        launch_tsmm<double, double>(Wt, L, zv, nullptr, n, c, 1, -1.0, vu, 1, 1.0, u, 1, st);
+        hessian_dispatch(p, tr, 1, u, q, RP4D_F64, true);               // (I + H) u
+        p->cnt.tlm_offline += 1;
+        p->cnt.adj_offline += 1;
+        launch_dot(q, q, n, sc + SC_T1, red, st);
+        kappa = std::sqrt(read_scalar(p, sc + SC_T1));
+        RP4D_REQUIRE(std::isfinite(kappa), RP4D_ENONFINITE, "adaptive sketch: non-finite kappa_sk");
+        if (info && nk < 16) info->kappa[nk] = kappa;
+        ++nk;
+        if (kappa <= o.eps_sk || c + o.ell_hat > L) break;
+    }
+    // thin SVD of W: W W^T = U Sigma^2 U^T, V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
+    launch_gram<double, double>(Wt, L, Wt, L, n, c, c, G, agw, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(G, s.ev, Gi, c, st);
+    }
+    sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, 0.0, c, s.lam, s.D, s.cs);
+    RP4D_HIP(hipGetLastError());
+    scale_cols<<<nblk(static_cast<long>(c) * c), 256, 0, st>>>(Gi, c, s.cs);
+    pc->V.ensure(static_cast<size_t>(n) * c * sizeof(double));
+    launch_tsmm<double, double>(Wt, L, Gi, nullptr, n, c, c, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), c, st);
+    launch_fill<double>(s.nu, 1, 0.0, st);
+    pc->p = p;
+    pc->ell = c;
+    pc->host_ok = false;
+    pc->Dg.ensure(static_cast<size_t>(c) * sizeof(double));
+    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, c, 1, st);
+    pc->lamd.ensure(static_cast<size_t>(c + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, c, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + c, 1, 1, 1, st);
+    p->cnt.sketches += 1;
+    if (info) {
+        info->ell = c;
+        info->nkappa = nk;
+        info->kappa_sk = kappa;
+    }
+}
+
+void check_adaptive_opts(const rp4d_problem* p, const rp4d_adaptive_opts& o) {
+    RP4D_REQUIRE(o.ell0 >= 1 && o.ell_hat >= 1 && o.ell_max >= o.ell0 && o.ell_max <= 128 && o.ell_max <= p->n,
+                 RP4D_EINVAL, "adaptive sketch: need 1 <= ell0 <= ell_max <= min(128, n) and ell_hat >= 1");
+    RP4D_REQUIRE(o.ell_max <= p->m, RP4D_EINVAL, "adaptive sketch: ell_max must not exceed the number of observations");
+    RP4D_REQUIRE(o.eps_sk > 0 && std::isfinite(o.eps_sk), RP4D_EINVAL, "adaptive sketch: eps_sk must be positive");
+}
+
 void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const double* R, double* Z) {
     hipStream_t st = stream_of(p);
     const int n = p->n, l = pc->ell;
@@ -1253,6 +1379,25 @@ int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* tr, int method, int ell
         auto* pc = new rp4d_precond();
         try {
             build_precond_into(p, tr, method, ell, seed, omega, sketch_dtype, pc);
+            fetch_host(pc);
+        } catch (...) {
+            delete pc;
+            throw;
+        }
+        *out = pc;
+    });
+}
+
+int rp4d_build_precond_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_adaptive_opts* o,
+                                rp4d_precond** out, rp4d_adaptive_info* info) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && o != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
+        check_traj(p, tr);
+        check_adaptive_opts(p, *o);
+        set_device(p->ctx);
+        auto* pc = new rp4d_precond();
+        try {
+            build_randsvd_adaptive(p, tr, *o, pc, info);
             fetch_host(pc);
         } catch (...) {
             delete pc;

@@ -348,6 +348,7 @@ struct rp4d_problem {
     rp4d::DevBuf F, lamF, ws_bh;
     // workspaces
     rp4d::DevBuf ws_s0, ws_s1, ws_obs, ws_blk, ws_red, ws_scal, ws_seg, ws_pcg, ws_bg;
+    rp4d::DevBuf ws_ad;  // adaptive sketch: accumulated basis Q (m x l_max), W^T (n x l_max), small blocks
     // the side lane's copies of the sweep / prior / segment workspaces (the
     // gradient's ADJ sweep runs there while the sketch runs on the main stream)
     rp4d::DevBuf side_s0, side_s1, side_obs, side_bh, side_seg, side_red;

@@ -62,6 +62,17 @@ class GnOpts(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p)]
 
 
+class AdaptiveOpts(ctypes.Structure):
+    _fields_ = [("ell0", ctypes.c_int), ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int),
+                ("eps_sk", ctypes.c_double), ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p),
+                ("vtest", ctypes.c_void_p)]
+
+
+class AdaptiveInfo(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_int), ("nkappa", ctypes.c_int), ("kappa_sk", ctypes.c_double),
+                ("kappa", ctypes.c_double * 16)]
+
+
 class GnInfo(ctypes.Structure):
     _fields_ = [("J", ctypes.c_double), ("gnorm_inf", ctypes.c_double), ("pcg_iters", ctypes.c_int),
                 ("pcg_converged", ctypes.c_int), ("pcg_relres", ctypes.c_double), ("sketched", ctypes.c_int),
@@ -93,6 +104,8 @@ _SIGS = {
     "rp4d_gradient": ([_P, _P, _P, _P], _I),
     "rp4d_bve_inv_laplacian": ([_P, _I, _P, _P, _I], _I),
     "rp4d_build_precond": ([_P, _P, _I, _I, ctypes.c_uint64, _P, _I, ctypes.POINTER(_P)], _I),
+    "rp4d_build_precond_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
+                                     ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_precond_destroy": ([_P], _I),
     "rp4d_precond_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
     "rp4d_precond_basis": ([_P, _P], _I),
@@ -304,6 +317,19 @@ class Problem:
         om = _ptr(omega, torch.float64, self.n * ell, "omega") if omega is not None else None
         _check(_lib.rp4d_build_precond(self._h, traj._h, method, ell, seed, om, sketch_dtype, ctypes.byref(h)))
         return Precond(self, h, ell)
+
+    def build_precond_adaptive(self, traj, ell0, ell_hat, ell_max, eps_sk=1.01, seed=0, omega=None, vtest=None):
+        """Adaptive RandSVD; omega (n, ell_max) and vtest (n) are optional device
+        tensors.  Returns (Precond, {"ell", "kappa": [...]})."""
+        o = AdaptiveOpts(ell0=ell0, ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, seed=seed,
+                         omega=_ptr(omega, torch.float64, self.n * ell_max, "omega") if omega is not None else None,
+                         vtest=_ptr(vtest, torch.float64, self.n, "vtest") if vtest is not None else None)
+        h = ctypes.c_void_p()
+        info = AdaptiveInfo()
+        _check(_lib.rp4d_build_precond_adaptive(self._h, traj._h, ctypes.byref(o), ctypes.byref(h),
+                                                ctypes.byref(info)))
+        return Precond(self, h, info.ell), dict(ell=info.ell, kappa=list(info.kappa[:min(16, info.nkappa)]),
+                                                 kappa_sk=info.kappa_sk, nkappa=info.nkappa)
 
     def pcg_solve(self, traj, b, precond=None, rtol=1e-6, maxit=0, x=None, raise_noconv=True):
         x = x if x is not None else torch.empty_like(b)

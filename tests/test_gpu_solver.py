@@ -53,6 +53,53 @@ def test_sketch_parity(small, method, ell):
     assert colwise_relerr(Hh, osk.hhat_apply(V, lam, R)) <= 1e-9
 
 
+@pytest.mark.parametrize("ell0,ell_hat,ell_max,eps", [(8, 8, 40, 1.01), (6, 5, 36, 1.5), (8, 8, 16, 1.01)])
+def test_adaptive_randsvd_parity(small, ell0, ell_hat, ell_max, eps):
+    """Adaptive RandSVD (Alg. 4): the same Gaussian blocks and test vector on
+    both sides give the same sequence of kappa_sk, the same final size and the
+    same approximation as the oracle."""
+    pr = small
+    Om = inputs.omega(pr.orc.n, ell_max, seed=700 + ell0)
+    v = inputs.omega(pr.orc.n, 1, seed=50)[:, 0]
+    blocks = [Om[:, :ell0]] + [Om[:, c:c + ell_hat] for c in range(ell0, ell_max - ell_hat + 1, ell_hat)]
+    V, lam, kap = ogn.build_precond_adaptive(pr.orc, pr.otraj, blocks, v, eps)
+    pc, info = pr.gpu.build_precond_adaptive(pr.traj, ell0, ell_hat, ell_max, eps_sk=eps, omega=to_dev(Om),
+                                             vtest=to_dev(v))
+    assert info["ell"] == len(lam) and info["nkappa"] == len(kap)
+    assert np.allclose(info["kappa"], kap, rtol=1e-9)
+    glam, gnu = pc.info()
+    assert gnu == 0.0
+    assert np.max(np.abs(np.array(glam) - lam)) <= 1e-10 * lam[0]
+    R = _probe(pr.orc.n)
+    assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
+
+
+def test_adaptive_randsvd_device_draws_stop_at_tolerance(small):
+    """With device draws the loop ends once kappa_sk <= eps_sk (or at ell_max),
+    and the resulting preconditioner cuts the PCG iterations."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    pc, info = pr.gpu.build_precond_adaptive(pr.traj, 4, 4, 64, eps_sk=1.05, seed=99)
+    k = info["kappa"]
+    assert k[-1] <= 1.05 or info["ell"] + 4 > 64
+    assert all(x > 1.05 for x in k[:-1])
+    assert info["ell"] == 4 + 4 * (info["nkappa"] - 1)
+    b = to_dev(_probe(pr.orc.n, 1, seed=9)[:, 0])
+    _, i0 = pr.gpu.pcg_solve(pr.traj, b, None, rtol=1e-10)
+    _, i1 = pr.gpu.pcg_solve(pr.traj, b, pc, rtol=1e-10)
+    assert i1["iters"] < i0["iters"]
+
+
+def test_adaptive_options_are_checked(small):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    for args in [(0, 4, 16), (8, 0, 16), (8, 4, 4), (8, 4, 200)]:
+        with pytest.raises(rp4d.Rp4dError):
+            pr.gpu.build_precond_adaptive(pr.traj, *args, eps_sk=1.01)
+    with pytest.raises(rp4d.Rp4dError):
+        pr.gpu.build_precond_adaptive(pr.traj, 8, 4, 16, eps_sk=0.0)
+
+
 def test_randsvd_rank_deficient_sketch_is_reported(small):
     """64 columns exceed the numerical rank of A on the 128-point problem: the
     thin QR of Y = A Omega by Cholesky QR (shifted CholeskyQR3 included) cannot
