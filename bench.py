@@ -311,6 +311,27 @@ def main():
     torch.cuda.synchronize()
     reuse_ms = 1e3 * (time.perf_counter() - tr0) / args.gn_iters
 
+    # SketchPrecA: adaptive RandSVD (Alg. 4; 32 columns, 16 more while kappa_sk >
+    # 1.01, at most 128) with the kappa_re < 10 reuse test, as in the paper's
+    # adaptive runs; one warm-up assimilation, then one timed
+    def adaptive_run():
+        state.reset()
+        return [prob.gn_step(state, sketch=rp4d.RANDSVD_ADAPTIVE, ell=32, ell_hat=16, ell_max=128, eps_sk=1.01,
+                             seed=2000 + it, rtol=rtol, reuse_eps=10.0) for it in range(args.gn_iters)]
+    adaptive_run()
+    torch.cuda.synchronize()
+    prob.reset_counters()
+    ta0 = time.perf_counter()
+    ad_infos = adaptive_run()
+    torch.cuda.synchronize()
+    ad_ms = 1e3 * (time.perf_counter() - ta0) / args.gn_iters
+    ad_cnt = prob.counters()
+    adaptive = {"method": "adaptive RandSVD (Alg. 4) + reuse test", "ell0": 32, "ell_hat": 16, "ell_max": 128,
+                "eps_sk": 1.01, "reuse_eps": 10.0, "gn_step_ms": ad_ms,
+                "sketch_ell": [i["sketch_ell"] for i in ad_infos], "kappa_sk": [i["kappa_sk"] for i in ad_infos],
+                "reused": [i["reused"] for i in ad_infos], "pcg_iters": [i["pcg_iters"] for i in ad_infos],
+                "offline_tlm": ad_cnt["tlm_offline"], "online_tlm": ad_cnt["tlm_online"]}
+
     # isolated block Hessian product, k = 64, FP64 (sketch shape)
     traj = prob.traj()
     prob.fwd(xb, traj, want_J=False)
@@ -378,6 +399,7 @@ def main():
         "gn_step_ms_with_reuse": reuse_ms,
         "reuse_decisions": [i["reused"] for i in reuse_infos],
         "pcg_iters_with_reuse": [i["pcg_iters"] for i in reuse_infos],
+        "adaptive": adaptive,
         "hessian_block_ms": block_ms,
         "hessian_block_hv_per_s": ell / (block_ms * 1e-3),
         "hessian_k1_ms": hv1_ms, "hessian_k1_hv_per_s": 1.0 / (hv1_ms * 1e-3),

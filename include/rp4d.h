@@ -58,7 +58,7 @@ typedef struct rp4d_precond rp4d_precond;
 typedef struct rp4d_gn_state rp4d_gn_state;
 
 enum { RP4D_F64 = 0, RP4D_F32 = 1 };
-enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2 };
+enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2, RP4D_RANDSVD_ADAPTIVE = 3 };
 enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
 
 /* Problem description (Sec. 2.1): model, window, observation layout, prior.
@@ -110,15 +110,20 @@ typedef struct {
 
 /* Options of one Gauss-Newton step (Sec. 2.2, Sec. 3.2). */
 typedef struct {
-    int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD or RP4D_NOPREC (Prec_Gamma) */
-    int ell;                /* sketch size l */
+    int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD, RP4D_NOPREC (Prec_Gamma) or
+                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64) */
+    int ell;                /* sketch size l (adaptive: the initial size) */
     uint64_t seed;          /* Philox seed for Omega when omega == NULL */
-    const double* omega;    /* device (n, ell) test matrix or NULL */
+    const double* omega;    /* device (n, ell) test matrix -- adaptive: (n, ell_max) -- or NULL */
     int sketch_dtype;       /* RP4D_F64 or RP4D_F32 sweeps for the sketch */
     double rtol;            /* PCG relative residual tolerance */
     int maxit;              /* PCG iteration cap (<= 0: n) */
     double reuse_eps;       /* eps_re of eq. (condtext2); <= 0: always re-sketch */
-    const double* vhat;     /* device unit vector for kappa_re, or NULL (Philox) */
+    const double* vhat;     /* device unit vector for kappa_re (and for kappa_sk with the
+                               adaptive sketch), or NULL (Philox) */
+    int ell_hat;            /* adaptive sketch: columns per extension */
+    int ell_max;            /* adaptive sketch: largest size */
+    double eps_sk;          /* adaptive sketch: stop once kappa_sk <= eps_sk (eq. (condtext)) */
 } rp4d_gn_opts;
 
 typedef struct {
@@ -130,6 +135,8 @@ typedef struct {
     int sketched;           /* 1 if a new sketch was built in this step */
     int reused;             /* 1 if the resident preconditioner was kept */
     double kappa_re;        /* value of the reuse test, or -1 if not run */
+    int sketch_ell;         /* size of the preconditioner in use (0 without one) */
+    double kappa_sk;        /* last kappa_sk of an adaptive sketch built in this step, or -1 */
 } rp4d_gn_info;
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -52,12 +52,14 @@ def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
 
 
 def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
-            precond=None, reuse_eps=None, vhat=None, counters=None):
+            precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None):
     """One GN step from control vector v.
 
-    method: 'nystrom' | 'randsvd' | 'none' (Prec_Gamma).
+    method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'none' (Prec_Gamma).
     precond: optional resident (V, lam) from an earlier iterate; with reuse_eps
     set it is kept when kappa_re(vhat) < reuse_eps, otherwise rebuilt from Omega.
+    adaptive: dict(ell0, ell_hat, eps_sk) for Alg. 4, whose Gaussian blocks are
+    Omega's columns [0, ell0), then ell_hat at a time; vhat is its test vector.
     Returns (v_new, dv, x_new, info)."""
     c = counters if counters is not None else dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
     J, g, traj, x = prob.cost_grad(v)
@@ -73,7 +75,14 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
             if kre < reuse_eps:
                 P = precond
                 reused = True
-        if P is None:
+        if P is None and method == 'randsvd_adaptive':
+            e0, eh = adaptive['ell0'], adaptive['ell_hat']
+            blocks = [Omega[:, :e0]] + [Omega[:, k:k + eh] for k in range(e0, Omega.shape[1] - eh + 1, eh)]
+            V, lam, kappas = build_precond_adaptive(prob, traj, blocks, vhat, adaptive['eps_sk'])
+            P = (V, lam)
+            c['tlm_off'] += V.shape[1] + len(kappas)
+            c['adj_off'] += V.shape[1] + len(kappas)
+        elif P is None:
             P = build_precond(prob, traj, method, Omega)
             ell = Omega.shape[1]
             c['tlm_off'] += ell

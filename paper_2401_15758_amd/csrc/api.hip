@@ -1737,8 +1737,14 @@ int rp4d_gn_state_last_step(const rp4d_gn_state* s, double* dv) {
 int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_gn_info* info) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && s != nullptr && o != nullptr && s->p == p, RP4D_EINVAL, "bad argument");
-        RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD || o->sketch == RP4D_NOPREC, RP4D_EINVAL,
-                     "unknown sketch method");
+        RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD || o->sketch == RP4D_NOPREC ||
+                         o->sketch == RP4D_RANDSVD_ADAPTIVE,
+                     RP4D_EINVAL, "unknown sketch method");
+        rp4d_adaptive_opts ao{};
+        if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
+            ao = rp4d_adaptive_opts{o->ell, o->ell_hat, o->ell_max, o->eps_sk, o->seed, o->omega, o->vhat};
+            check_adaptive_opts(p, ao);
+        }
         set_device(p->ctx);
         hipStream_t st = stream_of(p);
         const int n = p->n;
@@ -1771,6 +1777,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         p->cnt.adj_online += 1;
         rp4d_gn_info inf{};
         inf.kappa_re = -1.0;
+        inf.kappa_sk = -1.0;
         // 4-5. reuse test or sketch
         const rp4d_precond* use = nullptr;
         if (o->sketch != RP4D_NOPREC) {
@@ -1793,7 +1800,13 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 // rebuild in place: the object and its device buffers persist
                 s->pc_live = false;
                 if (!s->pc) s->pc = new rp4d_precond();
-                build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
+                if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
+                    rp4d_adaptive_info ai{};
+                    build_randsvd_adaptive(p, s->traj, ao, s->pc, &ai);
+                    inf.kappa_sk = ai.kappa_sk;
+                } else {
+                    build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
+                }
                 s->pc_live = true;
                 use = s->pc;
                 inf.sketched = 1;
@@ -1817,6 +1830,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         inf.pcg_iters = pi.iters;
         inf.pcg_converged = pi.converged;
         inf.pcg_relres = pi.relres;
+        inf.sketch_ell = use ? use->ell : 0;
         // 7. v <- v + dv ; x = x_b + Gamma^{1/2} v
         launch_axpby(s->dv.as<double>(), 1.0, s->v.as<double>(), 1.0, n, st);
         bhalf_into<double>(p, 1, s->v.as<double>(), 1, s->x.as<double>(), 1, p->xb.as<double>());
@@ -2882,6 +2896,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
             inf[i].J = 0.5 * sc[16 * i + SC_T2] + 0.5 * sc[16 * i + SC_T0];
             inf[i].gnorm_inf = sc[16 * i + SC_T1];
             inf[i].kappa_re = -1.0;
+            inf[i].kappa_sk = -1.0;
             RP4D_REQUIRE(std::isfinite(inf[i].J) && std::isfinite(inf[i].gnorm_inf), RP4D_ENONFINITE,
                          "non-finite cost or gradient in batch");
         }
@@ -2963,6 +2978,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
         bool all_conv = true;
         for (int i = 0; i < np; ++i) {
             inf[i].pcg_iters = its[i];
+            inf[i].sketch_ell = use[i] ? use[i]->ell : 0;
             inf[i].pcg_converged = conv[i];
             all_conv = all_conv && conv[i];
             if (infos) infos[i] = inf[i];

@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32 = 0, 1
-NYSTROM, RANDSVD, NOPREC = 0, 1, 2
+NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE = 0, 1, 2, 3
 BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
@@ -59,7 +59,8 @@ class Counters(ctypes.Structure):
 class GnOpts(ctypes.Structure):
     _fields_ = [("sketch", ctypes.c_int), ("ell", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p)]
+                ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p),
+                ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double)]
 
 
 class AdaptiveOpts(ctypes.Structure):
@@ -76,7 +77,8 @@ class AdaptiveInfo(ctypes.Structure):
 class GnInfo(ctypes.Structure):
     _fields_ = [("J", ctypes.c_double), ("gnorm_inf", ctypes.c_double), ("pcg_iters", ctypes.c_int),
                 ("pcg_converged", ctypes.c_int), ("pcg_relres", ctypes.c_double), ("sketched", ctypes.c_int),
-                ("reused", ctypes.c_int), ("kappa_re", ctypes.c_double)]
+                ("reused", ctypes.c_int), ("kappa_re", ctypes.c_double), ("sketch_ell", ctypes.c_int),
+                ("kappa_sk", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -352,11 +354,16 @@ class Problem:
         return GNState(self)
 
     def gn_step(self, state, sketch=NYSTROM, ell=20, seed=0, omega=None, sketch_dtype=F64, rtol=1e-6, maxit=0,
-                reuse_eps=0.0, vhat=None, raise_noconv=True):
+                reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0):
+        """One GN step; sketch=RANDSVD_ADAPTIVE takes ell as the initial size and
+        ell_hat, ell_max, eps_sk (omega then holds ell_max columns; vhat is also
+        the test vector of kappa_sk)."""
+        wide = ell_max if sketch == RANDSVD_ADAPTIVE else ell
         o = GnOpts(sketch=sketch, ell=ell, seed=seed,
-                   omega=_ptr(omega, torch.float64, self.n * ell, "omega").value if omega is not None else None,
+                   omega=_ptr(omega, torch.float64, self.n * wide, "omega").value if omega is not None else None,
                    sketch_dtype=sketch_dtype, rtol=rtol, maxit=maxit, reuse_eps=reuse_eps,
-                   vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None)
+                   vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None,
+                   ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk)
         info = GnInfo()
         rc = _lib.rp4d_gn_step(self._h, state._h, ctypes.byref(o), ctypes.byref(info))
         if rc != ENOCONV or raise_noconv:

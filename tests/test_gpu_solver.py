@@ -90,6 +90,26 @@ def test_adaptive_randsvd_device_draws_stop_at_tolerance(small):
     assert i1["iters"] < i0["iters"]
 
 
+def test_gn_step_adaptive_parity():
+    """A GN step with the adaptive RandSVD preconditioner (host blocks and test
+    vector) matches the oracle's GN step to 1e-10."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    Om = inputs.omega(pr.orc.n, 40, seed=810)
+    vh = inputs.omega(pr.orc.n, 1, seed=811)[:, 0]
+    st = pr.gpu.gn_state()
+    info = pr.gpu.gn_step(st, sketch=rp4d.RANDSVD_ADAPTIVE, ell=8, ell_hat=8, ell_max=40, eps_sk=1.01,
+                          omega=to_dev(Om), vhat=to_dev(vh), rtol=1e-12)
+    _, x = st.get()
+    _, _, x1, oinf = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method='randsvd_adaptive', Omega=Om, vhat=vh,
+                                 rtol=1e-12, adaptive=dict(ell0=8, ell_hat=8, eps_sk=1.01))
+    assert relerr(to_np(x), x1) <= 1e-10
+    assert info["sketch_ell"] == oinf["precond"][0].shape[1]
+    assert 0 < info["kappa_sk"] <= 1.01
+    assert info["pcg_iters"] == oinf["pcg"]["iters"]
+
+
 def test_adaptive_options_are_checked(small):
     from paper_2401_15758_amd import rp4d
     pr = small
