@@ -46,6 +46,11 @@ def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
         V, lam = _sketch.randsvd(lambda X: prob.A(traj, X).reshape(m, -1),
                                  lambda W: prob.AT(traj, W.reshape(prob.n_t, prob.n_obs, -1)),
                                  Omega)
+    elif method == 'singleview':
+        m = prob.m
+        Om, Psi = Omega                                    # (n x l1, m x l2)
+        V, lam = _sketch.singleview(lambda X: prob.A(traj, X).reshape(m, -1),
+                                    lambda W: prob.AT(traj, W.reshape(prob.n_t, prob.n_obs, -1)), Om, Psi)
     else:
         raise ValueError(method)
     return V, lam

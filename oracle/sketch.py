@@ -9,6 +9,8 @@ Test infrastructure only (see ``oracle/__init__``).
   * W-form       Remark 1, eq. (randsvdsv): (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W
   * adaptive     Sec. 3.1.2, Alg. 4 (randsvd_adaptive) with the test kappa_sk of
                  eq. (condtext)
+  * SingleView   Sec. 3.1.1, Alg. 3 (singleview), the oblique-projector
+                 approximation of eq. (singleviewlr)
 
 Readings: no truncation (target rank r = l); machine epsilon of Nystrom's shift
 is that of the precision Y was computed in (2^-52 for float64, 2^-23 for
@@ -65,6 +67,23 @@ def randsvd_W(A_apply, AT_apply, Omega):
     Y = A_apply(np.asarray(Omega, dtype=np.float64))
     Q, _ = np.linalg.qr(Y)
     return AT_apply(Q).T.copy()
+
+
+def singleview(A_apply, AT_apply, Omega, Psi):
+    """Alg. 3: Y = A Omega (m x l1) and Z = A^T Psi (n x l2) are independent
+    sketches; Y = Q_Y R_Y; M = Psi^T Q_Y = Q_M R_M; W = R_M^+ (Z Q_M)^T and its
+    thin SVD W = U S V^T give H_hat = V diag(S^2) V^T.  Thin QRs by Householder,
+    R_M^+ by a triangular solve (M has full column rank for Gaussian Psi with
+    l2 >= l1)."""
+    Omega = np.asarray(Omega, dtype=np.float64)
+    Psi = np.asarray(Psi, dtype=np.float64)
+    Y = A_apply(Omega)                                     # step 2 (both sketches)
+    Z = AT_apply(Psi)
+    Qy, _ = np.linalg.qr(Y)                                # step 3
+    Qm, Rm = np.linalg.qr(Psi.T @ Qy)                      # step 4
+    W = solve_triangular(Rm, (Z @ Qm).T, lower=False)      # step 5: W = R_M^{-1} (Z Q_M)^T
+    _, S, Vt = np.linalg.svd(W, full_matrices=False)
+    return Vt.T.copy(), S * S
 
 
 def kappa_sk(H_apply, W, v):
