@@ -58,7 +58,7 @@ typedef struct rp4d_precond rp4d_precond;
 typedef struct rp4d_gn_state rp4d_gn_state;
 
 enum { RP4D_F64 = 0, RP4D_F32 = 1 };
-enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2, RP4D_RANDSVD_ADAPTIVE = 3 };
+enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2, RP4D_RANDSVD_ADAPTIVE = 3, RP4D_SINGLEVIEW = 4 };
 enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
 
 /* Problem description (Sec. 2.1): model, window, observation layout, prior.
@@ -110,9 +110,9 @@ typedef struct {
 
 /* Options of one Gauss-Newton step (Sec. 2.2, Sec. 3.2). */
 typedef struct {
-    int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD, RP4D_NOPREC (Prec_Gamma) or
-                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64) */
-    int ell;                /* sketch size l (adaptive: the initial size) */
+    int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD, RP4D_NOPREC (Prec_Gamma),
+                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64) or RP4D_SINGLEVIEW (Alg. 3) */
+    int ell;                /* sketch size l (adaptive: the initial size; SingleView: l1) */
     uint64_t seed;          /* Philox seed for Omega when omega == NULL */
     const double* omega;    /* device (n, ell) test matrix -- adaptive: (n, ell_max) -- or NULL */
     int sketch_dtype;       /* RP4D_F64 or RP4D_F32 sweeps for the sketch */
@@ -124,6 +124,8 @@ typedef struct {
     int ell_hat;            /* adaptive sketch: columns per extension */
     int ell_max;            /* adaptive sketch: largest size */
     double eps_sk;          /* adaptive sketch: stop once kappa_sk <= eps_sk (eq. (condtext)) */
+    int ell2;               /* SingleView: co-range sketch size l2 (0: min(2 l1 + 1, m)) */
+    const double* psi;      /* SingleView: device (m, ell2) test matrix or NULL (Philox) */
 } rp4d_gn_opts;
 
 typedef struct {
@@ -235,6 +237,27 @@ typedef struct {
 } rp4d_adaptive_info;
 int rp4d_build_precond_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_adaptive_opts* opts,
                                 rp4d_precond** out, rp4d_adaptive_info* info);
+/* SingleView (Sec. 3.1.1, Alg. 3): the range sketch Y = A Omega (l1 TLM columns)
+ * and the co-range sketch Z = A^T Psi (l2 ADJ columns) are independent; the
+ * approximation is A_SV = Q_Y (Psi^T Q_Y)^+ Z^T (eq. (singleviewlr)), returned
+ * as H_hat = A_SV^T A_SV = V_hat Lambda_hat V_hat^T (l1 columns).  Thin QRs by
+ * Cholesky QR2 (shifted Cholesky QR3 when the Gram matrix is numerically
+ * indefinite), FP64 post-processing.  On the 1-D model the ADJ block runs on a
+ * second stream beside the TLM block unless `serial` is set.  H_hat need not
+ * satisfy H_hat <= H.  Counts l1 offline TLM and l2 offline ADJ.  RP4D_ENOTSPD
+ * if Y or M = Psi^T Q_Y is numerically rank deficient. */
+typedef struct {
+    int ell1;               /* range sketch size l1, 1 <= l1 <= min(128, n, m) */
+    int ell2;               /* co-range sketch size l2, l1 <= l2 <= m; 0: min(2 l1 + 1, m) */
+    uint64_t seed;          /* Philox seed of Omega (and, through a fixed mix, of Psi) when NULL */
+    const double* omega;    /* device (n, l1) row-major, or NULL */
+    const double* psi;      /* device (m, l2) row-major, rows ordered (n_t, n_obs) like the
+                               observations, or NULL */
+    int sketch_dtype;       /* RP4D_F64 or RP4D_F32 sweeps */
+    int serial;             /* 1: both sketches on the problem stream */
+} rp4d_singleview_opts;
+int rp4d_build_precond_singleview(rp4d_problem* p, const rp4d_traj* traj, const rp4d_singleview_opts* opts,
+                                  rp4d_precond** out);
 int rp4d_precond_destroy(rp4d_precond* pc);
 /* Host outputs (each nullable): ell, lambda_hat (ell, descending), Nystrom shift nu. */
 int rp4d_precond_info(const rp4d_precond* pc, int* ell, double* lambda_host, double* nu_host);

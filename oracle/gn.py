@@ -60,7 +60,8 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
             precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None):
     """One GN step from control vector v.
 
-    method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'none' (Prec_Gamma).
+    method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'singleview'
+    (Alg. 3; Omega is then the pair (Omega, Psi)) | 'none' (Prec_Gamma).
     precond: optional resident (V, lam) from an earlier iterate; with reuse_eps
     set it is kept when kappa_re(vhat) < reuse_eps, otherwise rebuilt from Omega.
     adaptive: dict(ell0, ell_hat, eps_sk) for Alg. 4, whose Gaussian blocks are
@@ -89,9 +90,12 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
             c['adj_off'] += V.shape[1] + len(kappas)
         elif P is None:
             P = build_precond(prob, traj, method, Omega)
-            ell = Omega.shape[1]
-            c['tlm_off'] += ell
-            c['adj_off'] += ell
+            if method == 'singleview':
+                c['tlm_off'] += Omega[0].shape[1]
+                c['adj_off'] += Omega[1].shape[1]
+            else:
+                c['tlm_off'] += Omega.shape[1]
+                c['adj_off'] += Omega.shape[1]
     prec = (lambda r: _sketch.lmp_apply(P[0], P[1], r)) if P is not None else None
     dv, pinfo = _pcg(lambda p: prob.hessian(traj, p), b, prec=prec, rtol=rtol, maxit=maxit)
     c['tlm_on'] += pinfo['iters']

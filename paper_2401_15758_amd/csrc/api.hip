@@ -1101,7 +1101,10 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
 
 // One Cholesky-QR pass on Y (rows x l, FP64, in s.Yd): G = Y^T Y + shift I = L L^T,
 // Y <- Y L^{-T}.  Returns the Cholesky info (0 = success; Y untouched otherwise).
-int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift) {
+// With Rinv (l x l) the pass's R^{-1} = L^{-T} is accumulated: Rinv <- L^{-T}
+// on the first pass, Rinv <- Rinv L^{-T} after it, so that Q = Y_in Rinv.
+int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift, double* Rinv = nullptr,
+                bool first = true) {
     hipStream_t st = stream_of(p);
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
     if (shift > 0) {
@@ -1119,17 +1122,24 @@ int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift) {
     RP4D_HIP(hipGetLastError());
     launch_tsmm<double, double>(s.Yd, l, s.S4, nullptr, rows, l, l, 1.0, nullptr, 0, 0.0, s.Y2, l, st);
     launch_relayout<double, double>(s.Y2, 1, s.Yd, 1, rows * l, 1, st);
+    if (Rinv && first) {
+        launch_relayout<double, double>(s.S4, 1, Rinv, 1, l * l, 1, st);
+    } else if (Rinv) {
+        launch_small_gemm(Rinv, 0, s.S4, 0, s.S3, l, 1.0, st);
+        launch_relayout<double, double>(s.S3, 1, Rinv, 1, l * l, 1, st);
+    }
     return 0;
 }
 
 // Thin QR of Y (rows x l) by CholeskyQR2; if the Gram matrix is numerically
 // indefinite, shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto,
 // Yanagisawa 2020): one pass with shift 11 (rows l + l(l+1)) u ||Y||_2^2, then two
-// plain passes.  Q overwrites s.Yd.
-void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s) {
+// plain passes.  Q overwrites s.Yd; Rinv (nullable, l x l) receives R^{-1}.
+void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s, double* Rinv = nullptr) {
     hipStream_t st = stream_of(p);
-    if (cholqr_pass(p, rows, l, s, 0.0) == 0) {
-        RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0) == 0, RP4D_ENOTSPD, "RandSVD: Cholesky QR second pass failed");
+    if (cholqr_pass(p, rows, l, s, 0.0, Rinv, true) == 0) {
+        RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD,
+                     "sketch: Cholesky QR second pass failed");
         return;
     }
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
@@ -1140,10 +1150,10 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s) {
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double sh = 11.0 * (static_cast<double>(rows) * l + l * (l + 1.0)) * std::ldexp(1.0, -53) * ymax2;
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, std::max(sh, 1e-300)) == 0, RP4D_ENOTSPD,
-                 "RandSVD: shifted Cholesky QR failed");
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0) == 0, RP4D_ENOTSPD, "RandSVD: Cholesky QR pass failed");
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0) == 0, RP4D_ENOTSPD, "RandSVD: Cholesky QR pass failed");
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, std::max(sh, 1e-300), Rinv, true) == 0, RP4D_ENOTSPD,
+                 "sketch: shifted Cholesky QR failed");
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD, "sketch: Cholesky QR pass failed");
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD, "sketch: Cholesky QR pass failed");
 }
 
 void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc) {
@@ -1491,6 +1501,109 @@ void on_side_lane(rp4d_problem* p, F&& f) {
     RP4D_HIP(hipEventRecord(c->ev_join, c->side));
 }
 
+inline uint64_t singleview_psi_seed(uint64_t seed) { return seed ^ 0x2545F4914F6CDD1DULL; }
+
+void check_singleview_opts(const rp4d_problem* p, rp4d_singleview_opts& o) {
+    if (o.ell2 == 0) o.ell2 = std::min(2 * o.ell1 + 1, p->m);
+    RP4D_REQUIRE(o.ell1 >= 1 && o.ell1 <= 128 && o.ell1 <= p->n && o.ell1 <= p->m, RP4D_EINVAL,
+                 "SingleView: ell1 must be in [1, min(128, n, m)]");
+    RP4D_REQUIRE(o.ell2 >= o.ell1 && o.ell2 <= p->m, RP4D_EINVAL, "SingleView: need ell1 <= ell2 <= m");
+    RP4D_REQUIRE(o.sketch_dtype == RP4D_F64 || o.sketch_dtype == RP4D_F32, RP4D_EINVAL, "bad sketch dtype");
+}
+
+// SingleView (Sec. 3.1.1, Alg. 3) into pc.  The co-range sketch Z = A^T Psi
+// (n x l2) needs nothing from the range sketch, so on the 1-D model it runs on
+// the side stream (with the side sweep workspaces) while the main stream forms
+// Y = A Omega (m x l1), its Cholesky-QR basis Q_Y, M = Psi^T Q_Y (l2 x l1) and
+// M's Cholesky-QR factors Q_M, R_M^{-1}.  Then P = Q_M R_M^{-T} (l2 x l1) and
+// W^T = Z P (n x l1), i.e. W = R_M^{-1} (Z Q_M)^T; the thin SVD of W comes from
+// the eigendecomposition of W W^T: V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2.
+// Host waits: the Cholesky-QR checks.
+void build_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singleview_opts& o, rp4d_precond* pc) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n, m = p->m, l1 = o.ell1, l2 = o.ell2;
+    const bool f64 = o.sketch_dtype == RP4D_F64;
+    Scratch s = sketch_scratch(p, l1, o.sketch_dtype);
+    const size_t gw = std::max({gram_work_doubles(m, l2, l1), gram_work_doubles(m, l1, l1),
+                                gram_work_doubles(n, l1, l1), gram_work_doubles(l2, l1, l1)});
+    const size_t ml2 = static_cast<size_t>(m) * l2, nl2 = static_cast<size_t>(n) * l2;
+    const size_t l21 = static_cast<size_t>(l2) * l1;
+    const size_t typed = f64 ? 0 : (ml2 + nl2) * sizeof(float);
+    p->ws_ad.ensure((ml2 + nl2 + 2 * l21 + static_cast<size_t>(l1) * l1 + gw + 64) * sizeof(double) + typed);
+    double* Psi = p->ws_ad.as<double>();  // m x l2
+    double* Z = Psi + ml2;                // n x l2
+    double* Mb = Z + nl2;                 // l2 x l1
+    double* P = Mb + l21;                 // l2 x l1
+    double* Rinv = P + l21;               // l1 x l1
+    s.gw = Rinv + static_cast<size_t>(l1) * l1;
+    float* Psit = reinterpret_cast<float*>(s.gw + gw + 64);
+    float* Zt = Psit + ml2;
+    // step 1: Omega (n x l1), Psi (m x l2)
+    if (o.omega)
+        launch_relayout<double, double>(o.omega, 1, s.Om, 1, n * l1, 1, st);
+    else
+        launch_philox_normal(o.seed, static_cast<size_t>(n) * l1, s.Om, st);
+    if (o.psi)
+        launch_relayout<double, double>(o.psi, 1, Psi, 1, m * l2, 1, st);
+    else
+        launch_philox_normal(singleview_psi_seed(o.seed), ml2, Psi, st);
+    // step 2: Z = A^T Psi beside Y = A Omega
+    auto corange = [&]() {
+        hipStream_t zs = stream_of(p);
+        if (f64) {
+            adj_impl<double>(p, tr, l2, Psi, Z, nullptr);
+        } else {
+            launch_relayout<double, float>(Psi, l2, Psit, l2, m, l2, zs);
+            adj_impl<float>(p, tr, l2, Psit, Zt, nullptr);
+            launch_relayout<float, double>(Zt, l2, Z, l2, n, l2, zs);
+        }
+    };
+    const bool lane = !o.serial && p->bve == nullptr;
+    if (lane)
+        on_side_lane(p, corange);
+    else
+        corange();
+    if (f64) {
+        tlm_impl<double>(p, tr, l1, s.Om, s.Yd);
+    } else {
+        launch_relayout<double, float>(s.Om, l1, static_cast<float*>(s.Omt), l1, n, l1, st);
+        tlm_impl<float>(p, tr, l1, static_cast<const float*>(s.Omt), static_cast<float*>(s.Yt));
+        launch_relayout<float, double>(static_cast<const float*>(s.Yt), l1, s.Yd, l1, m, l1, st);
+    }
+    cholqr2(p, m, l1, s);                                                        // step 3: Y = Q_Y R_Y
+    launch_gram<double, double>(Psi, l2, s.Yd, l1, m, l2, l1, Mb, s.gw, st);   // step 4: M = Psi^T Q_Y
+    launch_relayout<double, double>(Mb, 1, s.Yd, 1, l2 * l1, 1, st);
+    cholqr2(p, l2, l1, s, Rinv);                                                 // M = Q_M R_M
+    transpose_small<<<nblk(static_cast<long>(l1) * l1), 256, 0, st>>>(Rinv, s.S4, l1);  // S4 = R_M^{-T}
+    RP4D_HIP(hipGetLastError());
+    launch_tsmm<double, double>(s.Yd, l1, s.S4, nullptr, l2, l1, l1, 1.0, nullptr, 0, 0.0, P, l1, st);
+    if (lane) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
+    // step 5: W^T = Z Q_M R_M^{-T} (n x l1); thin SVD of W by eig(W W^T)
+    launch_tsmm<double, double>(Z, l2, P, nullptr, n, l2, l1, 1.0, nullptr, 0, 0.0, s.S1, l1, st);
+    launch_gram<double, double>(s.S1, l1, s.S1, l1, n, l1, l1, s.S2, s.gw, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(s.S2, s.ev, s.S3, l1, st);
+    }
+    sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, 0.0, l1, s.lam, s.D, s.cs);
+    RP4D_HIP(hipGetLastError());
+    scale_cols<<<nblk(static_cast<long>(l1) * l1), 256, 0, st>>>(s.S3, l1, s.cs);
+    pc->V.ensure(static_cast<size_t>(n) * l1 * sizeof(double));
+    launch_tsmm<double, double>(s.S1, l1, s.S3, nullptr, n, l1, l1, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l1, st);
+    launch_fill<double>(s.nu, 1, 0.0, st);
+    pc->p = p;
+    pc->ell = l1;
+    pc->host_ok = false;
+    pc->Dg.ensure(static_cast<size_t>(l1) * sizeof(double));
+    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, l1, 1, st);
+    pc->lamd.ensure(static_cast<size_t>(l1 + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, l1, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + l1, 1, 1, 1, st);
+    p->cnt.tlm_offline += l1;
+    p->cnt.adj_offline += l2;
+    p->cnt.sketches += 1;
+}
+
 // Capture the work `f` enqueues on the context stream into an executable graph
 // (recorded on a library-owned stream; nothing runs during capture).
 struct GraphExec {
@@ -1734,16 +1847,41 @@ int rp4d_gn_state_last_step(const rp4d_gn_state* s, double* dv) {
     });
 }
 
+int rp4d_build_precond_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singleview_opts* o,
+                                  rp4d_precond** out) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && o != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
+        check_traj(p, tr);
+        rp4d_singleview_opts so = *o;
+        check_singleview_opts(p, so);
+        set_device(p->ctx);
+        auto* pc = new rp4d_precond();
+        try {
+            build_singleview(p, tr, so, pc);
+            fetch_host(pc);
+        } catch (...) {
+            delete pc;
+            throw;
+        }
+        *out = pc;
+    });
+}
+
 int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_gn_info* info) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && s != nullptr && o != nullptr && s->p == p, RP4D_EINVAL, "bad argument");
         RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD || o->sketch == RP4D_NOPREC ||
-                         o->sketch == RP4D_RANDSVD_ADAPTIVE,
+                         o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_SINGLEVIEW,
                      RP4D_EINVAL, "unknown sketch method");
         rp4d_adaptive_opts ao{};
         if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
             ao = rp4d_adaptive_opts{o->ell, o->ell_hat, o->ell_max, o->eps_sk, o->seed, o->omega, o->vhat};
             check_adaptive_opts(p, ao);
+        }
+        rp4d_singleview_opts so{};
+        if (o->sketch == RP4D_SINGLEVIEW) {
+            so = rp4d_singleview_opts{o->ell, o->ell2, o->seed, o->omega, o->psi, o->sketch_dtype, 0};
+            check_singleview_opts(p, so);
         }
         set_device(p->ctx);
         hipStream_t st = stream_of(p);
@@ -1804,6 +1942,8 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                     rp4d_adaptive_info ai{};
                     build_randsvd_adaptive(p, s->traj, ao, s->pc, &ai);
                     inf.kappa_sk = ai.kappa_sk;
+                } else if (o->sketch == RP4D_SINGLEVIEW) {
+                    build_singleview(p, s->traj, so, s->pc);
                 } else {
                     build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
                 }

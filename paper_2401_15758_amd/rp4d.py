@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32 = 0, 1
-NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE = 0, 1, 2, 3
+NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW = 0, 1, 2, 3, 4
 BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
@@ -60,13 +60,20 @@ class GnOpts(ctypes.Structure):
     _fields_ = [("sketch", ctypes.c_int), ("ell", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p),
-                ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double)]
+                ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
+                ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p)]
 
 
 class AdaptiveOpts(ctypes.Structure):
     _fields_ = [("ell0", ctypes.c_int), ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int),
                 ("eps_sk", ctypes.c_double), ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p),
                 ("vtest", ctypes.c_void_p)]
+
+
+class SingleViewOpts(ctypes.Structure):
+    _fields_ = [("ell1", ctypes.c_int), ("ell2", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("omega", ctypes.c_void_p), ("psi", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int),
+                ("serial", ctypes.c_int)]
 
 
 class AdaptiveInfo(ctypes.Structure):
@@ -108,6 +115,7 @@ _SIGS = {
     "rp4d_build_precond": ([_P, _P, _I, _I, ctypes.c_uint64, _P, _I, ctypes.POINTER(_P)], _I),
     "rp4d_build_precond_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
                                      ctypes.POINTER(AdaptiveInfo)], _I),
+    "rp4d_build_precond_singleview": ([_P, _P, ctypes.POINTER(SingleViewOpts), ctypes.POINTER(_P)], _I),
     "rp4d_precond_destroy": ([_P], _I),
     "rp4d_precond_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
     "rp4d_precond_basis": ([_P, _P], _I),
@@ -333,6 +341,19 @@ class Problem:
         return Precond(self, h, info.ell), dict(ell=info.ell, kappa=list(info.kappa[:min(16, info.nkappa)]),
                                                  kappa_sk=info.kappa_sk, nkappa=info.nkappa)
 
+    def build_precond_singleview(self, traj, ell1, ell2=0, seed=0, omega=None, psi=None, sketch_dtype=F64,
+                                 serial=False):
+        """SingleView sketch; omega (n, ell1) and psi (m, ell2) are optional
+        device tensors; ell2 = 0 takes min(2 ell1 + 1, m)."""
+        l2 = ell2 if ell2 else min(2 * ell1 + 1, self.m)
+        o = SingleViewOpts(ell1=ell1, ell2=ell2, seed=seed,
+                           omega=_ptr(omega, torch.float64, self.n * ell1, "omega") if omega is not None else None,
+                           psi=_ptr(psi, torch.float64, self.m * l2, "psi") if psi is not None else None,
+                           sketch_dtype=sketch_dtype, serial=1 if serial else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.rp4d_build_precond_singleview(self._h, traj._h, ctypes.byref(o), ctypes.byref(h)))
+        return Precond(self, h, ell1)
+
     def pcg_solve(self, traj, b, precond=None, rtol=1e-6, maxit=0, x=None, raise_noconv=True):
         x = x if x is not None else torch.empty_like(b)
         info = PcgInfo()
@@ -354,16 +375,19 @@ class Problem:
         return GNState(self)
 
     def gn_step(self, state, sketch=NYSTROM, ell=20, seed=0, omega=None, sketch_dtype=F64, rtol=1e-6, maxit=0,
-                reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0):
+                reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0, ell2=0, psi=None):
         """One GN step; sketch=RANDSVD_ADAPTIVE takes ell as the initial size and
         ell_hat, ell_max, eps_sk (omega then holds ell_max columns; vhat is also
-        the test vector of kappa_sk)."""
+        the test vector of kappa_sk); sketch=SINGLEVIEW takes ell as l1 and
+        ell2, psi (m, l2) for the co-range sketch."""
         wide = ell_max if sketch == RANDSVD_ADAPTIVE else ell
+        l2 = ell2 if ell2 else min(2 * ell + 1, self.m)
         o = GnOpts(sketch=sketch, ell=ell, seed=seed,
                    omega=_ptr(omega, torch.float64, self.n * wide, "omega").value if omega is not None else None,
                    sketch_dtype=sketch_dtype, rtol=rtol, maxit=maxit, reuse_eps=reuse_eps,
                    vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None,
-                   ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk)
+                   ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, ell2=ell2,
+                   psi=_ptr(psi, torch.float64, self.m * l2, "psi").value if psi is not None else None)
         info = GnInfo()
         rc = _lib.rp4d_gn_step(self._h, state._h, ctypes.byref(o), ctypes.byref(info))
         if rc != ENOCONV or raise_noconv:

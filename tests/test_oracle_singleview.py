@@ -56,3 +56,15 @@ def test_problem_wrapper_runs():
     Psi = np.random.default_rng(6).standard_normal((orc.m, 21))
     V, lam = ogn.build_precond(orc, tr, 'singleview', (Om, Psi))
     assert V.shape == (orc.n, 10) and np.all(lam >= 0) and np.all(np.diff(lam) <= 1e-9 * lam[0])
+
+
+def test_gn_step_counts_both_sketches():
+    cfg = inputs.CFG_SMALL
+    orc = burgers_problem(cfg, inputs.draws(cfg, seed=0))
+    Om = inputs.omega(orc.n, 6, seed=5)
+    Psi = np.random.default_rng(6).standard_normal((orc.m, 13))
+    c = dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
+    v1, dv, x1, info = ogn.gn_step(orc, np.zeros(orc.n), method='singleview', Omega=(Om, Psi), rtol=1e-8,
+                                   counters=c)
+    assert c['tlm_off'] == 6 and c['adj_off'] == 13
+    assert info['pcg']['converged']
