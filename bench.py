@@ -363,6 +363,45 @@ def main():
     torch.cuda.synchronize()
     hv1_ms = e0.elapsed_time(e1) / reps1
 
+    # SketchPrec with SingleView (Alg. 3): l1 = ell TLM columns and l2 = 2 l1 + 1
+    # ADJ columns (the paper's pairing), the ADJ block on a second stream beside
+    # the TLM block or both on one stream; RandSVD / Nystrom builds of the same
+    # l for comparison.  The l2-column sweeps take the l-column tiling (more
+    # column groups of the same tile shape).
+    l2 = 2 * ell + 1
+    tk = tilings[f"k{ell}-f64"]
+    for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
+        prob.set_sweep_tiling(rp4d.F64, l2, mode=mode, **{f: tk[name].get(f, 0) for f in autotune.FIELDS})
+
+    def build_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - tb) / reps
+
+    sv_two = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5))
+    sv_one = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5, serial=True))
+    rs_build = build_ms(lambda: prob.build_precond(traj, rp4d.RANDSVD, ell, seed=5))
+    ny_build = build_ms(lambda: prob.build_precond(traj, rp4d.NYSTROM, ell, seed=5))
+
+    def sv_run():
+        state.reset()
+        return [prob.gn_step(state, sketch=rp4d.SINGLEVIEW, ell=ell, ell2=l2, seed=3000 + it, rtol=rtol)
+                for it in range(args.gn_iters)]
+    sv_run()
+    torch.cuda.synchronize()
+    tv0 = time.perf_counter()
+    sv_infos = sv_run()
+    torch.cuda.synchronize()
+    singleview = {"method": "SingleView (Alg. 3)", "l1": ell, "l2": l2,
+                  "build_ms_two_streams": sv_two, "build_ms_one_stream": sv_one,
+                  "randsvd_build_ms": rs_build, "nystrom_build_ms": ny_build,
+                  "gn_step_ms": 1e3 * (time.perf_counter() - tv0) / args.gn_iters,
+                  "pcg_iters": [i["pcg_iters"] for i in sv_infos]}
+
     # achievable HBM bandwidth: a plain 1 GiB device copy (reads and writes 1 GiB)
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -400,6 +439,7 @@ def main():
         "reuse_decisions": [i["reused"] for i in reuse_infos],
         "pcg_iters_with_reuse": [i["pcg_iters"] for i in reuse_infos],
         "adaptive": adaptive,
+        "singleview": singleview,
         "hessian_block_ms": block_ms,
         "hessian_block_hv_per_s": ell / (block_ms * 1e-3),
         "hessian_k1_ms": hv1_ms, "hessian_k1_hv_per_s": 1.0 / (hv1_ms * 1e-3),

@@ -38,6 +38,19 @@ def build_precond_adaptive(prob, traj, Omegas, v, eps_sk):
                                     lambda X: prob.misfit_hessian(traj, X), Omegas, v, eps_sk)
 
 
+def build_precond_singleview_adaptive(prob, traj, Omegas, Psis, v, eps_sk, qr='direct'):
+    """Alg. 5 on the problem's A: returns (V, lam, kappas)."""
+    m = prob.m
+    return _sketch.singleview_adaptive(lambda X: prob.A(traj, X).reshape(m, -1),
+                                       lambda W: prob.AT(traj, W.reshape(prob.n_t, prob.n_obs, -1)),
+                                       lambda X: prob.misfit_hessian(traj, X), Omegas, Psis, v, eps_sk, qr=qr)
+
+
+def split_blocks(X, first, step):
+    """Columns [0, first), then `step` at a time while whole blocks remain."""
+    return [X[:, :first]] + [X[:, k:k + step] for k in range(first, X.shape[1] - step + 1, step)]
+
+
 def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
     if method == 'nystrom':
         V, lam, _ = _sketch.nystrom(lambda X: prob.misfit_hessian(traj, X), Omega, eps=eps)
@@ -61,7 +74,9 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
     """One GN step from control vector v.
 
     method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'singleview'
-    (Alg. 3; Omega is then the pair (Omega, Psi)) | 'none' (Prec_Gamma).
+    (Alg. 3; Omega is then the pair (Omega, Psi)) | 'singleview_adaptive'
+    (Alg. 5; the pair again, split by adaptive['ell0'/'ell_hat'] and
+    adaptive['ell2'/'ell2_hat']) | 'none' (Prec_Gamma).
     precond: optional resident (V, lam) from an earlier iterate; with reuse_eps
     set it is kept when kappa_re(vhat) < reuse_eps, otherwise rebuilt from Omega.
     adaptive: dict(ell0, ell_hat, eps_sk) for Alg. 4, whose Gaussian blocks are
@@ -82,12 +97,21 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
                 P = precond
                 reused = True
         if P is None and method == 'randsvd_adaptive':
-            e0, eh = adaptive['ell0'], adaptive['ell_hat']
-            blocks = [Omega[:, :e0]] + [Omega[:, k:k + eh] for k in range(e0, Omega.shape[1] - eh + 1, eh)]
+            blocks = split_blocks(Omega, adaptive['ell0'], adaptive['ell_hat'])
             V, lam, kappas = build_precond_adaptive(prob, traj, blocks, vhat, adaptive['eps_sk'])
             P = (V, lam)
             c['tlm_off'] += V.shape[1] + len(kappas)
             c['adj_off'] += V.shape[1] + len(kappas)
+        elif P is None and method == 'singleview_adaptive':
+            Om, Psi = Omega
+            a = adaptive
+            ob = split_blocks(Om, a['ell0'], a['ell_hat'])
+            pb = split_blocks(Psi, a['ell2'], a['ell2_hat'])
+            V, lam, kappas = build_precond_singleview_adaptive(prob, traj, ob, pb, vhat, a['eps_sk'])
+            P = (V, lam)
+            r = len(kappas) - 1
+            c['tlm_off'] += V.shape[1] + len(kappas)
+            c['adj_off'] += a['ell2'] + r * a['ell2_hat'] + len(kappas)
         elif P is None:
             P = build_precond(prob, traj, method, Omega)
             if method == 'singleview':

@@ -10,7 +10,8 @@ Test infrastructure only (see ``oracle/__init__``).
   * adaptive     Sec. 3.1.2, Alg. 4 (randsvd_adaptive) with the test kappa_sk of
                  eq. (condtext)
   * SingleView   Sec. 3.1.1, Alg. 3 (singleview), the oblique-projector
-                 approximation of eq. (singleviewlr)
+                 approximation of eq. (singleviewlr); adaptive form Alg. 5
+                 (singleview_adaptive) with the QR update of Alg. 6 (qr_update)
 
 Readings: no truncation (target rank r = l); machine epsilon of Nystrom's shift
 is that of the precision Y was computed in (2^-52 for float64, 2^-23 for
@@ -121,6 +122,66 @@ def randsvd_adaptive(A_apply, AT_apply, H_apply, Omegas, v, eps_sk):
         Wt = np.hstack([Wt, AT_apply(Qh)])                 # W <- [W; W_hat]
         kappas.append(kappa_sk(H_apply, Wt.T, v))
     _, S, Vt = np.linalg.svd(Wt.T, full_matrices=False)    # thin SVD of W
+    return Vt.T.copy(), S * S, kappas
+
+
+def qr_update(A1, A2, B1, B2, Q1, R1):
+    """Alg. 6: thin QR of [A1; A2] [B1 B2] given the thin QR Q1 R1 = A1 B1
+    (B1, B2 with orthonormal columns).  Thin QRs by Householder; A2 B1 may be
+    wider than tall, whose reduced QR has a trapezoidal R.  Returns (Q5, R5)."""
+    Q2, R2 = np.linalg.qr(A2 @ B1)                         # step 1
+    Q3, R3 = np.linalg.qr(np.vstack([R1, R2]))             # step 2
+    k1 = R1.shape[0]
+    Q3 = np.vstack([Q1 @ Q3[:k1], Q2 @ Q3[k1:]])           # step 3: diag(Q1, Q2) Q3
+    P1 = np.vstack([A1, A2]) @ B2                          # step 4
+    T = Q3.T @ P1
+    P2 = P1 - Q3 @ T                                       # step 5
+    Q4, R4 = np.linalg.qr(P2)                              # step 6
+    Q5 = np.hstack([Q3, Q4])                               # step 7
+    R5 = np.block([[R3, T], [np.zeros((R4.shape[0], R3.shape[1])), R4]])
+    return Q5, R5
+
+
+def singleview_adaptive(A_apply, AT_apply, H_apply, Omegas, Psis, v, eps_sk, qr='direct'):
+    """Alg. 5 (adaptive SingleView).  Omegas / Psis are the Gaussian blocks the
+    algorithm draws, pairwise (first (l1, l2), then (l1_hat, l2_hat) per
+    extension); v the test vector of kappa_sk.  While kappa_sk > eps_sk and
+    blocks remain: Y_hat = A Omega_hat and Z_hat = A^T Psi_hat, Y_hat is
+    orthogonalised twice against Q_Y and factored, Q_Y, Psi and Z grow by the
+    new blocks, M = Psi^T Q_Y = Q_M R_M is refactored (qr='direct') or updated
+    by Alg. 6 (qr='update'), and W = R_M^{-1} (Z Q_M)^T is formed anew.
+    Readings: the algorithm's lines that form A^T Q_hat and stack it onto W are
+    RandSVD steps that do not fit the SingleView construction (whose W comes
+    from Z and the factors of M, and which draws Psi_hat without sweeping it);
+    they are read as the co-range sketch Z_hat = A^T Psi_hat followed by the
+    SingleView W.  kappa_sk by eq. (condtext) with H_hat = W^T W and eq.
+    (randsvdsv).  Returns (V_hat, lambda_hat, kappas)."""
+    Psi = np.asarray(Psis[0], dtype=np.float64)
+    Y = A_apply(np.asarray(Omegas[0], dtype=np.float64))  # both sketches
+    Z = AT_apply(Psi)
+    Qy, _ = np.linalg.qr(Y)
+    Qm, Rm = np.linalg.qr(Psi.T @ Qy)
+    W = solve_triangular(Rm, (Z @ Qm).T, lower=False)
+    kappas = [kappa_sk(H_apply, W, v)]
+    for Om_h, Psi_h in zip(Omegas[1:], Psis[1:]):
+        if kappas[-1] <= eps_sk:
+            break
+        Psi_h = np.asarray(Psi_h, dtype=np.float64)
+        Y = A_apply(np.asarray(Om_h, dtype=np.float64))   # new range and co-range blocks
+        Zh = AT_apply(Psi_h)
+        for _ in range(2):
+            Y = Y - Qy @ (Qy.T @ Y)                        # orthogonalise against Q_Y
+        Qh, _ = np.linalg.qr(Y)
+        if qr == 'update':
+            Qm, Rm = qr_update(Psi.T, Psi_h.T, Qy, Qh, Qm, Rm)
+        Qy = np.hstack([Qy, Qh])
+        Psi = np.hstack([Psi, Psi_h])
+        Z = np.hstack([Z, Zh])
+        if qr == 'direct':
+            Qm, Rm = np.linalg.qr(Psi.T @ Qy)
+        W = solve_triangular(Rm, (Z @ Qm).T, lower=False)
+        kappas.append(kappa_sk(H_apply, W, v))
+    _, S, Vt = np.linalg.svd(W, full_matrices=False)
     return Vt.T.copy(), S * S, kappas
 
 
