@@ -58,7 +58,14 @@ typedef struct rp4d_precond rp4d_precond;
 typedef struct rp4d_gn_state rp4d_gn_state;
 
 enum { RP4D_F64 = 0, RP4D_F32 = 1 };
-enum { RP4D_NYSTROM = 0, RP4D_RANDSVD = 1, RP4D_NOPREC = 2, RP4D_RANDSVD_ADAPTIVE = 3, RP4D_SINGLEVIEW = 4 };
+enum {
+    RP4D_NYSTROM = 0,
+    RP4D_RANDSVD = 1,
+    RP4D_NOPREC = 2,
+    RP4D_RANDSVD_ADAPTIVE = 3,
+    RP4D_SINGLEVIEW = 4,
+    RP4D_SINGLEVIEW_ADAPTIVE = 5
+};
 enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
 
 /* Problem description (Sec. 2.1): model, window, observation layout, prior.
@@ -111,7 +118,8 @@ typedef struct {
 /* Options of one Gauss-Newton step (Sec. 2.2, Sec. 3.2). */
 typedef struct {
     int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD, RP4D_NOPREC (Prec_Gamma),
-                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64) or RP4D_SINGLEVIEW (Alg. 3) */
+                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64), RP4D_SINGLEVIEW (Alg. 3) or
+                               RP4D_SINGLEVIEW_ADAPTIVE (Alg. 5, FP64) */
     int ell;                /* sketch size l (adaptive: the initial size; SingleView: l1) */
     uint64_t seed;          /* Philox seed for Omega when omega == NULL */
     const double* omega;    /* device (n, ell) test matrix -- adaptive: (n, ell_max) -- or NULL */
@@ -121,11 +129,13 @@ typedef struct {
     double reuse_eps;       /* eps_re of eq. (condtext2); <= 0: always re-sketch */
     const double* vhat;     /* device unit vector for kappa_re (and for kappa_sk with the
                                adaptive sketch), or NULL (Philox) */
-    int ell_hat;            /* adaptive sketch: columns per extension */
-    int ell_max;            /* adaptive sketch: largest size */
+    int ell_hat;            /* adaptive sketch: columns per extension (SingleView: l1_hat) */
+    int ell_max;            /* adaptive sketch: largest size (SingleView: of the range sketch) */
     double eps_sk;          /* adaptive sketch: stop once kappa_sk <= eps_sk (eq. (condtext)) */
     int ell2;               /* SingleView: co-range sketch size l2 (0: min(2 l1 + 1, m)) */
-    const double* psi;      /* SingleView: device (m, ell2) test matrix or NULL (Philox) */
+    const double* psi;      /* SingleView: device (m, ell2) test matrix -- adaptive: (m, l2_max),
+                               see rp4d_sv_adaptive_opts -- or NULL (Philox) */
+    int ell2_hat;           /* adaptive SingleView: co-range columns per extension (0: 2 ell_hat) */
 } rp4d_gn_opts;
 
 typedef struct {
@@ -258,6 +268,30 @@ typedef struct {
 } rp4d_singleview_opts;
 int rp4d_build_precond_singleview(rp4d_problem* p, const rp4d_traj* traj, const rp4d_singleview_opts* opts,
                                   rp4d_precond** out);
+/* Adaptive SingleView (Sec. 3.1.2, Alg. 5): start from Alg. 3 with (l1, l2)
+ * columns and, while kappa_sk (eq. (condtext); H_hat = W^T W, eq. (randsvdsv))
+ * exceeds eps_sk and l1 + l1_hat <= l1_max, draw l1_hat more range and l2_hat
+ * more co-range columns: the new TLM block is orthogonalised twice against
+ * Q_Y and factored by Cholesky QR, its ADJ partner runs on a second stream
+ * (1-D model, unless `serial`), M = Psi^T Q_Y is refactored and W formed anew.
+ * The algorithm's RandSVD-style lines A^T Q_hat / W <- [W; W_hat] are read as
+ * the co-range sketch of the new Psi block followed by the SingleView W.
+ * FP64.  Counts every column and every kappa_sk product offline; info->ell is
+ * the final l1 (the final l2 is ell2 + (info->nkappa - 1) ell2_hat). */
+typedef struct {
+    int ell1, ell2;         /* initial sizes (ell2 = 0: min(2 ell1 + 1, m)), ell1 <= ell2 */
+    int ell1_hat, ell2_hat; /* columns per extension (ell2_hat = 0: 2 ell1_hat), ell1_hat <= ell2_hat */
+    int ell1_max;           /* largest range sketch, <= min(128, n, m) */
+    double eps_sk;          /* stop once kappa_sk <= eps_sk (> 0) */
+    uint64_t seed;          /* Philox seed of the blocks and of v when omega / psi / vtest are NULL */
+    const double* omega;    /* device (n, ell1_max) row-major: ell1 columns, then ell1_hat per extension */
+    const double* psi;      /* device (m, l2_max) row-major, l2_max = ell2 + ell2_hat *
+                               floor((ell1_max - ell1) / ell1_hat) (<= m): ell2, then ell2_hat per extension */
+    const double* vtest;    /* device (n) test vector (normalised here), or NULL */
+    int serial;             /* 1: every sweep on the problem stream */
+} rp4d_sv_adaptive_opts;
+int rp4d_build_precond_singleview_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_sv_adaptive_opts* opts,
+                                           rp4d_precond** out, rp4d_adaptive_info* info);
 int rp4d_precond_destroy(rp4d_precond* pc);
 /* Host outputs (each nullable): ell, lambda_hat (ell, descending), Nystrom shift nu. */
 int rp4d_precond_info(const rp4d_precond* pc, int* ell, double* lambda_host, double* nu_host);

@@ -1201,6 +1201,54 @@ __global__ void add_identity(double* G, int l) {
 inline uint64_t adaptive_seed(uint64_t seed, int r) { return seed + 0x9E3779B97F4A7C15ULL * static_cast<uint64_t>(r); }
 inline uint64_t adaptive_vseed(uint64_t seed) { return seed ^ 0xD1B54A32D192ED03ULL; }
 
+// Device buffers of one kappa_sk evaluation for sketches of up to L columns.
+struct KappaWork {
+    double *G, *Gi, *Gt;  // L x L each
+    double *vu, *u, *q;   // n each: unit test vector, u, (I + H) u
+    double *red, *tv, *zv;  // 1024 dot partials, L, L
+    double* gw;           // Gram partials
+};
+
+// Unit test vector of kappa_sk into w.vu: vtest normalised, or a Philox draw.
+void kappa_test_vector(rp4d_problem* p, const double* vtest, uint64_t vseed, const KappaWork& w) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n;
+    double* sc = p->ws_scal.as<double>();
+    if (vtest)
+        launch_relayout<double, double>(vtest, 1, w.u, 1, n, 1, st);
+    else
+        launch_philox_normal(vseed, n, w.u, st);
+    launch_dot(w.u, w.u, n, sc + SC_T0, w.red, st);
+    scale_inv_sqrt<<<nblk(n), 256, 0, st>>>(w.u, sc + SC_T0, w.vu, n);
+    RP4D_HIP(hipGetLastError());
+}
+
+// kappa_sk = |(I + H) u| with u = v - W^T (I + W W^T)^{-1} W v (eq. (condtext),
+// (randsvdsv)) for H_hat = W^T W, W^T (n x c) with leading size ld.  One
+// single-vector Hessian product (counted offline) and one scalar read.
+double kappa_sk_dev(rp4d_problem* p, const rp4d_traj* tr, const double* Wt, int ld, int c, const KappaWork& w,
+                    int* info) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n;
+    double* sc = p->ws_scal.as<double>();
+    launch_gram<double, double>(Wt, ld, Wt, ld, n, c, c, w.G, w.gw, st);  // G = W W^T (c x c)
+    add_identity<<<nblk(c), 256, 0, st>>>(w.G, c);
+    RP4D_HIP(hipGetLastError());
+    launch_chol(w.G, c, info, st);                                        // I + W W^T = Lc Lc^T (SPD)
+    launch_trinv(w.G, w.Gi, c, st);                                       // Gi = Lc^{-1}
+    launch_small_gemm(w.Gi, 1, w.Gi, 0, w.Gt, c, 1.0, st);                // Gt = (I + W W^T)^{-1}
+    launch_gram<double, double>(Wt, ld, w.vu, 1, n, c, 1, w.tv, w.gw, st);  // tv = W v
+    launch_tsmm<double, double>(w.Gt, c, w.tv, nullptr, c, c, 1, 1.0, nullptr, 0, 0.0, w.zv, 1, st);
+    launch_tsmm<double, double>(Wt, ld, w.zv, nullptr, n, c, 1, -1.0, w.vu, 1, 1.0, w.u, 1, st);
+    hessian_dispatch(p, tr, 1, w.u, w.q, RP4D_F64, true);                 // (I + H) u
+    p->cnt.tlm_offline += 1;
+    p->cnt.adj_offline += 1;
+    launch_dot(w.q, w.q, n, sc + SC_T1, w.red, st);
+    const double kappa = std::sqrt(read_scalar(p, sc + SC_T1));
+    RP4D_REQUIRE(std::isfinite(kappa), RP4D_ENONFINITE, "adaptive sketch: non-finite kappa_sk");
+    return kappa;
+}
+
 // Adaptive RandSVD (Sec. 3.1.2, Alg. 4) into pc.  The accumulated basis Q (m x c)
 // and W^T = A^T Q (n x c) are kept row-major with leading size l_max; a new
 // block of b columns is drawn (or read from omega's columns [c, c + b)), swept
@@ -1222,25 +1270,22 @@ void build_randsvd_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_ada
                      1024 + 4 * static_cast<size_t>(L) + gw + 64) * sizeof(double));
     double* Qa = p->ws_ad.as<double>();            // m x L
     double* Wt = Qa + static_cast<size_t>(m) * L;  // n x L
-    double* G = Wt + static_cast<size_t>(n) * L;   // L x L
-    double* Gi = G + ll;                           // L x L
-    double* Gt = Gi + ll;                          // L x L
-    double* vu = Gt + ll;                          // n: unit test vector
-    double* u = vu + n;                            // n
-    double* q = u + n;                             // n
-    double* red = q + n;                           // 1024 (dot-product partials)
-    double* tv = red + 1024;                       // L
-    double* zv = tv + L;                           // L
-    double* agw = zv + 2 * L;                      // Gram partials
-    double* sc = p->ws_scal.as<double>();
-    // unit test vector
-    if (o.vtest)
-        launch_relayout<double, double>(o.vtest, 1, u, 1, n, 1, st);
-    else
-        launch_philox_normal(adaptive_vseed(o.seed), n, u, st);
-    launch_dot(u, u, n, sc + SC_T0, red, st);
-    scale_inv_sqrt<<<nblk(n), 256, 0, st>>>(u, sc + SC_T0, vu, n);
-    RP4D_HIP(hipGetLastError());
+    KappaWork kw{};
+    kw.G = Wt + static_cast<size_t>(n) * L;        // L x L
+    kw.Gi = kw.G + ll;
+    kw.Gt = kw.Gi + ll;
+    kw.vu = kw.Gt + ll;                            // n
+    kw.u = kw.vu + n;
+    kw.q = kw.u + n;
+    kw.red = kw.q + n;                             // 1024 (dot-product partials)
+    kw.tv = kw.red + 1024;                         // L
+    kw.zv = kw.tv + L;                             // L
+    kw.gw = kw.zv + 2 * L;                         // Gram partials
+    double* G = kw.G;
+    double* Gi = kw.Gi;
+    double* Gt = kw.Gt;
+    double* agw = kw.gw;
+    kappa_test_vector(p, o.vtest, adaptive_vseed(o.seed), kw);
     int c = 0, r = 0, nk = 0;
     double kappa = 0.0;
     for (;;) {
@@ -1262,22 +1307,7 @@ void build_randsvd_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_ada
         ++r;
         p->cnt.tlm_offline += b;
         p->cnt.adj_offline += b;
-        // kappa_sk = |(I + H) u|, u = v - W^T (I + W W^T)^{-1} W v
-        launch_gram<double, double>(Wt, L, Wt, L, n, c, c, G, agw, st);   // G = W W^T (c x c)
-        add_identity<<<nblk(c), 256, 0, st>>>(G, c);
-        RP4D_HIP(hipGetLastError());
-        launch_chol(G, c, s.info, st);                                  // I + W W^T = Lc Lc^T (SPD)
-        launch_trinv(G, Gi, c, st);                                     // Gi = Lc^{-1}
-        launch_small_gemm(Gi, 1, Gi, 0, Gt, c, 1.0, st);                // Gt = (I + W W^T)^{-1}
-        launch_gram<double, double>(Wt, L, vu, 1, n, c, 1, tv, agw, st);  // tv = W v
-        launch_tsmm<double, double>(Gt, c, tv, nullptr, c, c, 1, 1.0, nullptr, 0, 0.0, zv, 1, st);
-        launch_tsmm<double, double>(Wt, L, zv, nullptr, n, c, 1, -1.0, vu, 1, 1.0, u, 1, st);
-        hessian_dispatch(p, tr, 1, u, q, RP4D_F64, true);               // (I + H) u
-        p->cnt.tlm_offline += 1;
-        p->cnt.adj_offline += 1;
-        launch_dot(q, q, n, sc + SC_T1, red, st);
-        kappa = std::sqrt(read_scalar(p, sc + SC_T1));
-        RP4D_REQUIRE(std::isfinite(kappa), RP4D_ENONFINITE, "adaptive sketch: non-finite kappa_sk");
+        kappa = kappa_sk_dev(p, tr, Wt, L, c, kw, s.info);
         if (info && nk < 16) info->kappa[nk] = kappa;
         ++nk;
         if (kappa <= o.eps_sk || c + o.ell_hat > L) break;
@@ -1604,6 +1634,151 @@ void build_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singlevie
     p->cnt.sketches += 1;
 }
 
+// Largest co-range sketch of an adaptive SingleView run: the initial l2 plus
+// l2_hat for every extension that fits within l1_max.
+int sv_adaptive_l2max(const rp4d_sv_adaptive_opts& o) {
+    return o.ell2 + o.ell2_hat * ((o.ell1_max - o.ell1) / o.ell1_hat);
+}
+
+void check_sv_adaptive_opts(const rp4d_problem* p, rp4d_sv_adaptive_opts& o) {
+    if (o.ell2 == 0) o.ell2 = std::min(2 * o.ell1 + 1, p->m);
+    if (o.ell2_hat == 0) o.ell2_hat = 2 * o.ell1_hat;
+    RP4D_REQUIRE(o.ell1 >= 1 && o.ell1_hat >= 1 && o.ell1_max >= o.ell1 && o.ell1_max <= 128 &&
+                     o.ell1_max <= p->n && o.ell1_max <= p->m,
+                 RP4D_EINVAL, "adaptive SingleView: need 1 <= ell1 <= ell1_max <= min(128, n, m) and ell1_hat >= 1");
+    RP4D_REQUIRE(o.ell2 >= o.ell1 && o.ell2_hat >= o.ell1_hat, RP4D_EINVAL,
+                 "adaptive SingleView: need ell2 >= ell1 and ell2_hat >= ell1_hat");
+    RP4D_REQUIRE(sv_adaptive_l2max(o) <= p->m, RP4D_EINVAL,
+                 "adaptive SingleView: the largest co-range sketch exceeds the number of observations");
+    RP4D_REQUIRE(o.eps_sk > 0 && std::isfinite(o.eps_sk), RP4D_EINVAL, "adaptive sketch: eps_sk must be positive");
+}
+
+// Adaptive SingleView (Sec. 3.1.2, Alg. 5) into pc.  Each round draws
+// Omega_hat (n x b1) and Psi_hat (m x b2); Z_hat = A^T Psi_hat runs on the side
+// stream (1-D model) beside Y_hat = A Omega_hat, which is orthogonalised twice
+// against the accumulated Q_Y and factored by Cholesky QR.  Q_Y (m x c1),
+// Psi (m x c2) and Z (n x c2) grow by the new blocks; M = Psi^T Q_Y is
+// refactored by Cholesky QR2 (its QR from scratch, which the algorithm allows
+// beside the update of Alg. 6) and W^T = Z Q_M R_M^{-T} (n x c1) is formed
+// anew; kappa_sk (eq. (condtext)) decides whether to extend.  FP64.
+void build_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_sv_adaptive_opts& o,
+                               rp4d_precond* pc, rp4d_adaptive_info* info) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n, m = p->m, L1 = o.ell1_max, L2 = sv_adaptive_l2max(o);
+    const int B2 = std::max(o.ell2, o.ell2_hat);
+    Scratch s = sketch_scratch(p, L1, RP4D_F64);
+    const size_t ll = static_cast<size_t>(L1) * L1, l21 = static_cast<size_t>(L2) * L1;
+    const size_t gw = std::max({gram_work_doubles(m, L2, L1), gram_work_doubles(m, L1, L1),
+                                gram_work_doubles(n, L1, L1), gram_work_doubles(L2, L1, L1),
+                                gram_work_doubles(n, L1, 1)});
+    const size_t mL1 = static_cast<size_t>(m) * L1, nL1 = static_cast<size_t>(n) * L1;
+    const size_t mL2 = static_cast<size_t>(m) * L2, nL2 = static_cast<size_t>(n) * L2;
+    const size_t mB2 = static_cast<size_t>(m) * B2, nB2 = static_cast<size_t>(n) * B2;
+    p->ws_ad.ensure((mL1 + mL2 + nL2 + mB2 + nB2 + 2 * l21 + 4 * ll + nL1 + 3 * static_cast<size_t>(n) + 1024 +
+                     4 * static_cast<size_t>(L1) + gw + 64) * sizeof(double));
+    double* Qa = p->ws_ad.as<double>();  // m x L1: Q_Y
+    double* Pa = Qa + mL1;               // m x L2: Psi
+    double* Za = Pa + mL2;               // n x L2: Z
+    double* Ph = Za + nL2;               // m x B2: Psi_hat
+    double* Zh = Ph + mB2;               // n x B2: Z_hat
+    double* Mb = Zh + nB2;               // L2 x L1
+    double* P = Mb + l21;                // L2 x L1: Q_M R_M^{-T}
+    double* Rinv = P + l21;              // L1 x L1
+    double* Wt = Rinv + ll;              // n x L1: W^T
+    KappaWork kw{};
+    kw.G = Wt + nL1;
+    kw.Gi = kw.G + ll;
+    kw.Gt = kw.Gi + ll;
+    kw.vu = kw.Gt + ll;
+    kw.u = kw.vu + n;
+    kw.q = kw.u + n;
+    kw.red = kw.q + n;
+    kw.tv = kw.red + 1024;
+    kw.zv = kw.tv + L1;
+    kw.gw = kw.zv + 2 * L1;
+    s.gw = kw.gw;
+    kappa_test_vector(p, o.vtest, adaptive_vseed(o.seed), kw);
+    const bool lane = !o.serial && p->bve == nullptr;
+    int c1 = 0, c2 = 0, r = 0, nk = 0;
+    double kappa = 0.0;
+    for (;;) {
+        const int b1 = r == 0 ? o.ell1 : o.ell1_hat;
+        const int b2 = r == 0 ? o.ell2 : o.ell2_hat;
+        // new test blocks
+        if (o.omega)
+            launch_relayout<double, double>(o.omega + c1, L1, s.Om, b1, n, b1, st);
+        else
+            launch_philox_normal(adaptive_seed(o.seed, r), static_cast<size_t>(n) * b1, s.Om, st);
+        if (o.psi)
+            launch_relayout<double, double>(o.psi + c2, L2, Ph, b2, m, b2, st);
+        else
+            launch_philox_normal(adaptive_seed(singleview_psi_seed(o.seed), r), static_cast<size_t>(m) * b2, Ph, st);
+        launch_relayout<double, double>(Ph, b2, Pa + c2, L2, m, b2, st);
+        // Z_hat = A^T Psi_hat (appended to Z) beside Y_hat = A Omega_hat
+        const int zc = c2;
+        auto corange = [&]() {
+            adj_impl<double>(p, tr, b2, Ph, Zh, nullptr);
+            launch_relayout<double, double>(Zh, b2, Za + zc, L2, n, b2, stream_of(p));
+        };
+        if (lane)
+            on_side_lane(p, corange);
+        else
+            corange();
+        tlm_impl<double>(p, tr, b1, s.Om, s.Yd);
+        for (int pass = 0; c1 > 0 && pass < 2; ++pass) {                  // Y <- Y - Q_Y (Q_Y^T Y)
+            launch_gram<double, double>(Qa, L1, s.Yd, b1, m, c1, b1, kw.Gt, kw.gw, st);
+            launch_tsmm<double, double>(Qa, L1, kw.Gt, nullptr, m, c1, b1, -1.0, s.Yd, b1, 1.0, s.Yd, b1, st);
+        }
+        cholqr2(p, m, b1, s);                                              // Y = Q_hat R
+        launch_relayout<double, double>(s.Yd, b1, Qa + c1, L1, m, b1, st);
+        c1 += b1;
+        c2 += b2;
+        ++r;
+        p->cnt.tlm_offline += b1;
+        p->cnt.adj_offline += b2;
+        // M = Psi^T Q_Y = Q_M R_M (c2 x c1), P = Q_M R_M^{-T}
+        launch_gram<double, double>(Pa, L2, Qa, L1, m, c2, c1, Mb, kw.gw, st);
+        launch_relayout<double, double>(Mb, 1, s.Yd, 1, c2 * c1, 1, st);
+        cholqr2(p, c2, c1, s, Rinv);
+        transpose_small<<<nblk(static_cast<long>(c1) * c1), 256, 0, st>>>(Rinv, s.S4, c1);
+        RP4D_HIP(hipGetLastError());
+        launch_tsmm<double, double>(s.Yd, c1, s.S4, nullptr, c2, c1, c1, 1.0, nullptr, 0, 0.0, P, c1, st);
+        if (lane) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
+        // W^T = Z Q_M R_M^{-T} (n x c1)
+        launch_tsmm<double, double>(Za, L2, P, nullptr, n, c2, c1, 1.0, nullptr, 0, 0.0, Wt, L1, st);
+        kappa = kappa_sk_dev(p, tr, Wt, L1, c1, kw, s.info);
+        if (info && nk < 16) info->kappa[nk] = kappa;
+        ++nk;
+        if (kappa <= o.eps_sk || c1 + o.ell1_hat > L1) break;
+    }
+    // thin SVD of W: W W^T = U Sigma^2 U^T, V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
+    launch_gram<double, double>(Wt, L1, Wt, L1, n, c1, c1, kw.G, kw.gw, st);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
+        launch_jacobi_eig(kw.G, s.ev, kw.Gi, c1, st);
+    }
+    sketch_finalize<<<1, 128, 0, st>>>(s.ev, nullptr, 0.0, c1, s.lam, s.D, s.cs);
+    RP4D_HIP(hipGetLastError());
+    scale_cols<<<nblk(static_cast<long>(c1) * c1), 256, 0, st>>>(kw.Gi, c1, s.cs);
+    pc->V.ensure(static_cast<size_t>(n) * c1 * sizeof(double));
+    launch_tsmm<double, double>(Wt, L1, kw.Gi, nullptr, n, c1, c1, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), c1, st);
+    launch_fill<double>(s.nu, 1, 0.0, st);
+    pc->p = p;
+    pc->ell = c1;
+    pc->host_ok = false;
+    pc->Dg.ensure(static_cast<size_t>(c1) * sizeof(double));
+    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, c1, 1, st);
+    pc->lamd.ensure(static_cast<size_t>(c1 + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, c1, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + c1, 1, 1, 1, st);
+    p->cnt.sketches += 1;
+    if (info) {
+        info->ell = c1;
+        info->nkappa = nk;
+        info->kappa_sk = kappa;
+    }
+}
+
 // Capture the work `f` enqueues on the context stream into an executable graph
 // (recorded on a library-owned stream; nothing runs during capture).
 struct GraphExec {
@@ -1867,12 +2042,39 @@ int rp4d_build_precond_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp
     });
 }
 
+int rp4d_build_precond_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_sv_adaptive_opts* o,
+                                           rp4d_precond** out, rp4d_adaptive_info* info) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && o != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
+        check_traj(p, tr);
+        rp4d_sv_adaptive_opts so = *o;
+        check_sv_adaptive_opts(p, so);
+        set_device(p->ctx);
+        auto* pc = new rp4d_precond();
+        try {
+            build_singleview_adaptive(p, tr, so, pc, info);
+            fetch_host(pc);
+        } catch (...) {
+            delete pc;
+            throw;
+        }
+        *out = pc;
+    });
+}
+
 int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_gn_info* info) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && s != nullptr && o != nullptr && s->p == p, RP4D_EINVAL, "bad argument");
         RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD || o->sketch == RP4D_NOPREC ||
-                         o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_SINGLEVIEW,
+                         o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_SINGLEVIEW ||
+                         o->sketch == RP4D_SINGLEVIEW_ADAPTIVE,
                      RP4D_EINVAL, "unknown sketch method");
+        rp4d_sv_adaptive_opts sao{};
+        if (o->sketch == RP4D_SINGLEVIEW_ADAPTIVE) {
+            sao = rp4d_sv_adaptive_opts{o->ell, o->ell2, o->ell_hat, o->ell2_hat, o->ell_max, o->eps_sk, o->seed,
+                                        o->omega, o->psi, o->vhat, 0};
+            check_sv_adaptive_opts(p, sao);
+        }
         rp4d_adaptive_opts ao{};
         if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
             ao = rp4d_adaptive_opts{o->ell, o->ell_hat, o->ell_max, o->eps_sk, o->seed, o->omega, o->vhat};
@@ -1944,6 +2146,10 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                     inf.kappa_sk = ai.kappa_sk;
                 } else if (o->sketch == RP4D_SINGLEVIEW) {
                     build_singleview(p, s->traj, so, s->pc);
+                } else if (o->sketch == RP4D_SINGLEVIEW_ADAPTIVE) {
+                    rp4d_adaptive_info ai{};
+                    build_singleview_adaptive(p, s->traj, sao, s->pc, &ai);
+                    inf.kappa_sk = ai.kappa_sk;
                 } else {
                     build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
                 }

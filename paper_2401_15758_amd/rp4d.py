@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32 = 0, 1
-NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW = 0, 1, 2, 3, 4
+NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE = 0, 1, 2, 3, 4, 5
 BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
@@ -61,7 +61,7 @@ class GnOpts(ctypes.Structure):
                 ("omega", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p),
                 ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
-                ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p)]
+                ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p), ("ell2_hat", ctypes.c_int)]
 
 
 class AdaptiveOpts(ctypes.Structure):
@@ -74,6 +74,21 @@ class SingleViewOpts(ctypes.Structure):
     _fields_ = [("ell1", ctypes.c_int), ("ell2", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_void_p), ("psi", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int),
                 ("serial", ctypes.c_int)]
+
+
+class SvAdaptiveOpts(ctypes.Structure):
+    _fields_ = [("ell1", ctypes.c_int), ("ell2", ctypes.c_int), ("ell1_hat", ctypes.c_int),
+                ("ell2_hat", ctypes.c_int), ("ell1_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p), ("psi", ctypes.c_void_p),
+                ("vtest", ctypes.c_void_p), ("serial", ctypes.c_int)]
+
+
+def sv_adaptive_sizes(m, ell1, ell1_hat, ell1_max, ell2=0, ell2_hat=0):
+    """(ell2, ell2_hat, l2_max) of an adaptive SingleView run after the defaults."""
+    ell2 = ell2 if ell2 else min(2 * ell1 + 1, m)
+    ell2_hat = ell2_hat if ell2_hat else 2 * ell1_hat
+    ext = (ell1_max - ell1) // ell1_hat if ell1_hat > 0 and ell1_max >= ell1 else 0
+    return ell2, ell2_hat, ell2 + ell2_hat * ext
 
 
 class AdaptiveInfo(ctypes.Structure):
@@ -116,6 +131,8 @@ _SIGS = {
     "rp4d_build_precond_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
                                      ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_build_precond_singleview": ([_P, _P, ctypes.POINTER(SingleViewOpts), ctypes.POINTER(_P)], _I),
+    "rp4d_build_precond_singleview_adaptive": ([_P, _P, ctypes.POINTER(SvAdaptiveOpts), ctypes.POINTER(_P),
+                                                ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_precond_destroy": ([_P], _I),
     "rp4d_precond_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
     "rp4d_precond_basis": ([_P, _P], _I),
@@ -354,6 +371,26 @@ class Problem:
         _check(_lib.rp4d_build_precond_singleview(self._h, traj._h, ctypes.byref(o), ctypes.byref(h)))
         return Precond(self, h, ell1)
 
+    def build_precond_singleview_adaptive(self, traj, ell1, ell1_hat, ell1_max, eps_sk=1.01, ell2=0, ell2_hat=0,
+                                          seed=0, omega=None, psi=None, vtest=None, serial=False):
+        """Adaptive SingleView; omega (n, ell1_max), psi (m, l2_max) and vtest (n)
+        are optional device tensors (l2_max from sv_adaptive_sizes).  Returns
+        (Precond, {"ell", "ell2", "kappa": [...], "kappa_sk", "nkappa"})."""
+        l2, l2h, l2max = sv_adaptive_sizes(self.m, ell1, ell1_hat, ell1_max, ell2, ell2_hat)
+        o = SvAdaptiveOpts(ell1=ell1, ell2=ell2, ell1_hat=ell1_hat, ell2_hat=ell2_hat, ell1_max=ell1_max,
+                           eps_sk=eps_sk, seed=seed,
+                           omega=_ptr(omega, torch.float64, self.n * ell1_max, "omega") if omega is not None else None,
+                           psi=_ptr(psi, torch.float64, self.m * l2max, "psi") if psi is not None else None,
+                           vtest=_ptr(vtest, torch.float64, self.n, "vtest") if vtest is not None else None,
+                           serial=1 if serial else 0)
+        h = ctypes.c_void_p()
+        info = AdaptiveInfo()
+        _check(_lib.rp4d_build_precond_singleview_adaptive(self._h, traj._h, ctypes.byref(o), ctypes.byref(h),
+                                                           ctypes.byref(info)))
+        return Precond(self, h, info.ell), dict(ell=info.ell, ell2=l2 + (info.nkappa - 1) * l2h,
+                                                 kappa=list(info.kappa[:min(16, info.nkappa)]),
+                                                 kappa_sk=info.kappa_sk, nkappa=info.nkappa)
+
     def pcg_solve(self, traj, b, precond=None, rtol=1e-6, maxit=0, x=None, raise_noconv=True):
         x = x if x is not None else torch.empty_like(b)
         info = PcgInfo()
@@ -375,19 +412,26 @@ class Problem:
         return GNState(self)
 
     def gn_step(self, state, sketch=NYSTROM, ell=20, seed=0, omega=None, sketch_dtype=F64, rtol=1e-6, maxit=0,
-                reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0, ell2=0, psi=None):
+                reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0, ell2=0, psi=None,
+                ell2_hat=0):
         """One GN step; sketch=RANDSVD_ADAPTIVE takes ell as the initial size and
         ell_hat, ell_max, eps_sk (omega then holds ell_max columns; vhat is also
         the test vector of kappa_sk); sketch=SINGLEVIEW takes ell as l1 and
-        ell2, psi (m, l2) for the co-range sketch."""
-        wide = ell_max if sketch == RANDSVD_ADAPTIVE else ell
-        l2 = ell2 if ell2 else min(2 * ell + 1, self.m)
+        ell2, psi (m, l2) for the co-range sketch; SINGLEVIEW_ADAPTIVE takes
+        ell, ell_hat, ell_max for the range sketch, ell2, ell2_hat for the
+        co-range sketch, psi (m, l2_max) and eps_sk."""
+        wide = ell_max if sketch in (RANDSVD_ADAPTIVE, SINGLEVIEW_ADAPTIVE) else ell
+        if sketch == SINGLEVIEW_ADAPTIVE:
+            l2 = sv_adaptive_sizes(self.m, ell, ell_hat, ell_max, ell2, ell2_hat)[2]
+        else:
+            l2 = ell2 if ell2 else min(2 * ell + 1, self.m)
         o = GnOpts(sketch=sketch, ell=ell, seed=seed,
                    omega=_ptr(omega, torch.float64, self.n * wide, "omega").value if omega is not None else None,
                    sketch_dtype=sketch_dtype, rtol=rtol, maxit=maxit, reuse_eps=reuse_eps,
                    vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None,
                    ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, ell2=ell2,
-                   psi=_ptr(psi, torch.float64, self.m * l2, "psi").value if psi is not None else None)
+                   psi=_ptr(psi, torch.float64, self.m * l2, "psi").value if psi is not None else None,
+                   ell2_hat=ell2_hat)
         info = GnInfo()
         rc = _lib.rp4d_gn_step(self._h, state._h, ctypes.byref(o), ctypes.byref(info))
         if rc != ENOCONV or raise_noconv:

@@ -144,3 +144,97 @@ def test_singleview_options_are_checked(small):
         assert e.value.code == rp4d.EINVAL
     with pytest.raises(rp4d.Rp4dError):
         pr.gpu.build_precond_singleview(pr.traj, 8, 17, sketch_dtype=7)
+
+
+# ---------------------------------------------------------------------------
+# adaptive SingleView (Sec. 3.1.2, Alg. 5)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("l1,l2,l1h,l2h,l1max,eps", [(8, 17, 8, 16, 40, 1.01), (6, 13, 5, 10, 36, 1.5),
+                                                     (8, 17, 8, 16, 16, 1.01)])
+def test_adaptive_singleview_parity(small, l1, l2, l1h, l2h, l1max, eps):
+    """The same blocks and test vector on both sides give the same kappa_sk
+    sequence, the same final sizes and the same approximation as the oracle."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    _, _, l2max = rp4d.sv_adaptive_sizes(pr.orc.m, l1, l1h, l1max, l2, l2h)
+    Om, Psi = _draws(pr, l1max, l2max, seed=2500 + l1)
+    v = inputs.omega(pr.orc.n, 1, seed=51)[:, 0]
+    V, lam, kap = ogn.build_precond_singleview_adaptive(pr.orc, pr.otraj, ogn.split_blocks(Om, l1, l1h),
+                                                        ogn.split_blocks(Psi, l2, l2h), v, eps)
+    pc, info = pr.gpu.build_precond_singleview_adaptive(pr.traj, l1, l1h, l1max, eps_sk=eps, ell2=l2, ell2_hat=l2h,
+                                                        omega=to_dev(Om), psi=to_dev(Psi), vtest=to_dev(v))
+    assert info["ell"] == len(lam) and info["nkappa"] == len(kap)
+    assert info["ell2"] == l2 + (len(kap) - 1) * l2h
+    assert np.allclose(info["kappa"], kap, rtol=1e-9)
+    glam, gnu = pc.info()
+    assert gnu == 0.0
+    assert np.max(np.abs(np.array(glam) - lam)) <= 1e-10 * lam[0]
+    R = _probe(pr.orc.n)
+    assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
+
+
+def test_adaptive_singleview_streams_are_bitwise_identical(small):
+    pr = small
+    a, ia = pr.gpu.build_precond_singleview_adaptive(pr.traj, 8, 8, 32, eps_sk=1.0, seed=31)
+    b, ib = pr.gpu.build_precond_singleview_adaptive(pr.traj, 8, 8, 32, eps_sk=1.0, seed=31, serial=True)
+    assert ia["kappa"] == ib["kappa"] and ia["ell"] == ib["ell"] == 32
+    assert np.array_equal(to_np(a.basis()), to_np(b.basis()))
+
+
+def test_adaptive_singleview_device_draws_stop_at_tolerance():
+    """With device draws the loop ends at the first kappa_sk <= eps_sk (or at
+    l1_max); the counters record every column and every kappa_sk product."""
+    need_gpu()
+    pr = Pair(inputs.CFG_SMALL, seed=6)
+    c0 = pr.gpu.counters()
+    pc, info = pr.gpu.build_precond_singleview_adaptive(pr.traj, 4, 4, 48, eps_sk=1.05, seed=99)
+    c1 = pr.gpu.counters()
+    k = info["kappa"]
+    assert k[-1] <= 1.05 or info["ell"] + 4 > 48
+    assert all(x > 1.05 for x in k[:-1])
+    assert info["ell"] == 4 + 4 * (info["nkappa"] - 1)
+    assert c1["tlm_offline"] - c0["tlm_offline"] == info["ell"] + info["nkappa"]
+    assert c1["adj_offline"] - c0["adj_offline"] == info["ell2"] + info["nkappa"]
+    b = to_dev(_probe(pr.orc.n, 1, seed=9)[:, 0])
+    _, i0 = pr.gpu.pcg_solve(pr.traj, b, None, rtol=1e-10)
+    _, i1 = pr.gpu.pcg_solve(pr.traj, b, pc, rtol=1e-10)
+    assert i1["converged"] and i1["iters"] < i0["iters"]
+
+
+def test_gn_step_adaptive_singleview_parity():
+    """A GN step with the adaptive SingleView preconditioner (host blocks and
+    test vector) matches the oracle's step to 1e-10."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    l1, l1h, l1max, l2, l2h = 8, 8, 40, 17, 16
+    _, _, l2max = rp4d.sv_adaptive_sizes(pr.orc.m, l1, l1h, l1max, l2, l2h)
+    Om, Psi = _draws(pr, l1max, l2max, seed=2600)
+    vh = inputs.omega(pr.orc.n, 1, seed=811)[:, 0]
+    st = pr.gpu.gn_state()
+    gi = pr.gpu.gn_step(st, sketch=rp4d.SINGLEVIEW_ADAPTIVE, ell=l1, ell_hat=l1h, ell_max=l1max, ell2=l2,
+                        ell2_hat=l2h, eps_sk=1.01, omega=to_dev(Om), psi=to_dev(Psi), vhat=to_dev(vh), rtol=1e-12)
+    _, x = st.get()
+    _, _, x1, oinf = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method='singleview_adaptive', Omega=(Om, Psi),
+                                 vhat=vh, rtol=1e-12,
+                                 adaptive=dict(ell0=l1, ell_hat=l1h, ell2=l2, ell2_hat=l2h, eps_sk=1.01))
+    assert relerr(to_np(x), x1) <= 1e-10
+    assert gi["sketch_ell"] == oinf["precond"][0].shape[1]
+    assert 0 < gi["kappa_sk"]
+    assert abs(gi["pcg_iters"] - oinf["pcg"]["iters"]) <= 1
+
+
+def test_adaptive_singleview_options_are_checked(small):
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    m = pr.orc.m
+    bad = [dict(ell1=0, ell1_hat=4, ell1_max=16), dict(ell1=8, ell1_hat=0, ell1_max=16),
+           dict(ell1=8, ell1_hat=4, ell1_max=4), dict(ell1=8, ell1_hat=4, ell1_max=200),
+           dict(ell1=8, ell1_hat=4, ell1_max=16, ell2=7), dict(ell1=8, ell1_hat=4, ell1_max=16, ell2_hat=3),
+           dict(ell1=8, ell1_hat=8, ell1_max=64, ell2=17, ell2_hat=m)]
+    for kw in bad:
+        with pytest.raises(rp4d.Rp4dError) as e:
+            pr.gpu.build_precond_singleview_adaptive(pr.traj, eps_sk=1.01, **kw)
+        assert e.value.code == rp4d.EINVAL
+    with pytest.raises(rp4d.Rp4dError):
+        pr.gpu.build_precond_singleview_adaptive(pr.traj, 8, 4, 16, eps_sk=0.0)
