@@ -70,7 +70,7 @@ def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
 
 
 def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
-            precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None):
+            precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None, solve='pcg'):
     """One GN step from control vector v.
 
     method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'singleview'
@@ -81,6 +81,8 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
     set it is kept when kappa_re(vhat) < reuse_eps, otherwise rebuilt from Omega.
     adaptive: dict(ell0, ell_hat, eps_sk) for Alg. 4, whose Gaussian blocks are
     Omega's columns [0, ell0), then ell_hat at a time; vhat is its test vector.
+    solve: 'pcg' (SketchPrec, Sec. 3.2.2) or 'sketch' (SketchSolv, Sec. 3.2.1:
+    eq. (dxsol) in the v-form, dv = (I + H_hat)^{-1} b by eq. (woodbury)).
     Returns (v_new, dv, x_new, info)."""
     c = counters if counters is not None else dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
     J, g, traj, x = prob.cost_grad(v)
@@ -121,7 +123,12 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
                 c['tlm_off'] += Omega.shape[1]
                 c['adj_off'] += Omega.shape[1]
     prec = (lambda r: _sketch.lmp_apply(P[0], P[1], r)) if P is not None else None
-    dv, pinfo = _pcg(lambda p: prob.hessian(traj, p), b, prec=prec, rtol=rtol, maxit=maxit)
+    if solve == 'sketch':
+        if prec is None:
+            raise ValueError("SketchSolv needs a sketch")
+        dv, pinfo = prec(b), dict(iters=0, converged=True, relres=None)
+    else:
+        dv, pinfo = _pcg(lambda p: prob.hessian(traj, p), b, prec=prec, rtol=rtol, maxit=maxit)
     c['tlm_on'] += pinfo['iters']
     c['adj_on'] += pinfo['iters']
     v_new = v + dv
