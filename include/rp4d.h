@@ -67,6 +67,10 @@ enum {
     RP4D_SINGLEVIEW_ADAPTIVE = 5
 };
 enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
+/* How a GN step obtains its direction from (I + H) dv = -g_v (eq. (gniterf1)):
+ * SketchPrec (PCG preconditioned by eq. (woodbury), Sec. 3.2.2) or SketchSolv
+ * (one application of eq. (woodbury), eq. (dxsol), Sec. 3.2.1). */
+enum { RP4D_SOLVE_PCG = 0, RP4D_SOLVE_SKETCH = 1 };
 
 /* Problem description (Sec. 2.1): model, window, observation layout, prior.
  *   Burgers:  nx grid points on [0,1) (ny ignored), viscosity nu.
@@ -136,6 +140,8 @@ typedef struct {
     const double* psi;      /* SingleView: device (m, ell2) test matrix -- adaptive: (m, l2_max),
                                see rp4d_sv_adaptive_opts -- or NULL (Philox) */
     int ell2_hat;           /* adaptive SingleView: co-range columns per extension (0: 2 ell_hat) */
+    int solve;              /* RP4D_SOLVE_PCG or RP4D_SOLVE_SKETCH (needs a sketch; no PCG, so
+                               pcg_iters = 0, pcg_converged = 1 and pcg_relres = -1) */
 } rp4d_gn_opts;
 
 typedef struct {

@@ -2069,6 +2069,8 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                          o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_SINGLEVIEW ||
                          o->sketch == RP4D_SINGLEVIEW_ADAPTIVE,
                      RP4D_EINVAL, "unknown sketch method");
+        RP4D_REQUIRE(o->solve == RP4D_SOLVE_PCG || (o->solve == RP4D_SOLVE_SKETCH && o->sketch != RP4D_NOPREC),
+                     RP4D_EINVAL, "solve must be RP4D_SOLVE_PCG, or RP4D_SOLVE_SKETCH with a sketch");
         rp4d_sv_adaptive_opts sao{};
         if (o->sketch == RP4D_SINGLEVIEW_ADAPTIVE) {
             sao = rp4d_sv_adaptive_opts{o->ell, o->ell2, o->ell_hat, o->ell2_hat, o->ell_max, o->eps_sk, o->seed,
@@ -2161,15 +2163,25 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         // join the gradient; J and |g|_inf arrive with PCG's first scalar read
         if (overlap) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
         double sch[SC_COUNT];
-        // 6. PCG
+        // 6. direction: PCG (SketchPrec) or one application of eq. (woodbury)
+        // (SketchSolv, eq. (dxsol) in the v-form: dv = (I + H_hat)^{-1} b)
         rp4d_pcg_info pi{};
         int pcg_rc = RP4D_OK;
-        try {
-            pcg_impl(p, s->traj, use, s->b.as<double>(), s->dv.as<double>(), o->rtol, o->maxit, &pi, false, vecs,
-                     sch);
-        } catch (const Error& e) {
-            if (e.code != RP4D_ENOCONV) throw;
-            pcg_rc = e.code;
+        if (o->solve == RP4D_SOLVE_SKETCH) {
+            precond_apply_impl(p, use, 1, s->b.as<double>(), s->dv.as<double>());
+            RP4D_HIP(hipMemcpyAsync(sch, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync(p);
+            RP4D_REQUIRE(std::isfinite(sch[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
+            pi.converged = 1;
+            pi.relres = -1.0;
+        } else {
+            try {
+                pcg_impl(p, s->traj, use, s->b.as<double>(), s->dv.as<double>(), o->rtol, o->maxit, &pi, false,
+                         vecs, sch);
+            } catch (const Error& e) {
+                if (e.code != RP4D_ENOCONV) throw;
+                pcg_rc = e.code;
+            }
         }
         inf.J = 0.5 * sch[SC_VV] + 0.5 * sch[SC_DD];
         inf.gnorm_inf = sch[SC_GI];
@@ -3189,6 +3201,7 @@ int rp4d_batch_hessian_block(rp4d_batch* b, rp4d_traj* const* trajs, int k, cons
 int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_gn_opts* o, rp4d_gn_info* infos) {
     return guarded([&] {
         RP4D_REQUIRE(b != nullptr && states != nullptr && o != nullptr, RP4D_EINVAL, "null argument");
+        RP4D_REQUIRE(o->solve == RP4D_SOLVE_PCG, RP4D_EINVAL, "batched GN step: SketchPrec (PCG) only");
         RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_NOPREC, RP4D_EINVAL,
                      "batched GN step supports Nystrom sketches or no preconditioner");
         RP4D_REQUIRE(o->omega == nullptr, RP4D_EINVAL, "batched GN step draws Omega on the device (omega must be NULL)");

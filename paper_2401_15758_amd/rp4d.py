@@ -26,6 +26,7 @@ BURGERS1D, BVE2D = 0, 1
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
 XCH_LDS, XCH_WAVE = 1, 2
+SOLVE_PCG, SOLVE_SKETCH = 0, 1
 TIMING_LAUNCH, TIMING_SPAN = 1, 2
 
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EUNSTABLE: "EUNSTABLE", ENOTSPD: "ENOTSPD",
@@ -61,7 +62,8 @@ class GnOpts(ctypes.Structure):
                 ("omega", ctypes.c_void_p), ("sketch_dtype", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p),
                 ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
-                ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p), ("ell2_hat", ctypes.c_int)]
+                ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p), ("ell2_hat", ctypes.c_int),
+                ("solve", ctypes.c_int)]
 
 
 class AdaptiveOpts(ctypes.Structure):
@@ -413,13 +415,15 @@ class Problem:
 
     def gn_step(self, state, sketch=NYSTROM, ell=20, seed=0, omega=None, sketch_dtype=F64, rtol=1e-6, maxit=0,
                 reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0, ell2=0, psi=None,
-                ell2_hat=0):
+                ell2_hat=0, solve=SOLVE_PCG):
         """One GN step; sketch=RANDSVD_ADAPTIVE takes ell as the initial size and
         ell_hat, ell_max, eps_sk (omega then holds ell_max columns; vhat is also
         the test vector of kappa_sk); sketch=SINGLEVIEW takes ell as l1 and
         ell2, psi (m, l2) for the co-range sketch; SINGLEVIEW_ADAPTIVE takes
         ell, ell_hat, ell_max for the range sketch, ell2, ell2_hat for the
-        co-range sketch, psi (m, l2_max) and eps_sk."""
+        co-range sketch, psi (m, l2_max) and eps_sk.  solve=SOLVE_SKETCH takes
+        the SketchSolv direction (one application of the preconditioner)
+        instead of PCG."""
         wide = ell_max if sketch in (RANDSVD_ADAPTIVE, SINGLEVIEW_ADAPTIVE) else ell
         if sketch == SINGLEVIEW_ADAPTIVE:
             l2 = sv_adaptive_sizes(self.m, ell, ell_hat, ell_max, ell2, ell2_hat)[2]
@@ -431,7 +435,7 @@ class Problem:
                    vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None,
                    ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, ell2=ell2,
                    psi=_ptr(psi, torch.float64, self.m * l2, "psi").value if psi is not None else None,
-                   ell2_hat=ell2_hat)
+                   ell2_hat=ell2_hat, solve=solve)
         info = GnInfo()
         rc = _lib.rp4d_gn_step(self._h, state._h, ctypes.byref(o), ctypes.byref(info))
         if rc != ENOCONV or raise_noconv:

@@ -291,3 +291,39 @@ def test_pcg_graph_replay_is_bitwise_eager(small, use_prec):
     pr.ctx.set_graphs(False)
     assert out[True][1] == out[False][1] and out[True][1] >= 5
     assert torch.equal(out[True][0], out[False][0])
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd", "singleview"])
+def test_gn_step_sketchsolv_parity(method):
+    """SketchSolv (Sec. 3.2.1, eq. (dxsol)): the direction is one application of
+    eq. (woodbury) to -g_v, no PCG; dv and x+ within 1e-10 of the oracle."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    ell = 20
+    Om = inputs.omega(pr.orc.n, ell, seed=1300)
+    Psi = np.random.default_rng(1301).standard_normal((pr.orc.m, 2 * ell + 1))
+    arg = (Om, Psi) if method == "singleview" else Om
+    _, dv, x1, info = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method=method, Omega=arg, solve='sketch')
+    code = dict(nystrom=rp4d.NYSTROM, randsvd=rp4d.RANDSVD, singleview=rp4d.SINGLEVIEW)[method]
+    st = pr.gpu.gn_state()
+    gi = pr.gpu.gn_step(st, sketch=code, ell=ell, omega=to_dev(Om),
+                        psi=to_dev(Psi) if method == "singleview" else None, solve=rp4d.SOLVE_SKETCH)
+    _, gx = st.get()
+    assert gi['pcg_iters'] == 0 and gi['pcg_converged'] == 1 and gi['pcg_relres'] == -1.0
+    assert gi['J'] == pytest.approx(info['J'], rel=1e-12)
+    assert gi['gnorm_inf'] == pytest.approx(info['gnorm_inf'], rel=1e-11)
+    assert relerr(to_np(st.last_step()), dv) <= TOL_GN
+    assert relerr(to_np(gx), x1) <= TOL_GN
+    c = pr.gpu.counters()
+    assert c['tlm_online'] == 0 and c['adj_online'] == 1
+
+
+def test_sketchsolv_requires_a_sketch():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    st = pr.gpu.gn_state()
+    with pytest.raises(rp4d.Rp4dError) as e:
+        pr.gpu.gn_step(st, sketch=rp4d.NOPREC, solve=rp4d.SOLVE_SKETCH)
+    assert e.value.code == rp4d.EINVAL
