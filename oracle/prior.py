@@ -78,3 +78,20 @@ def cov_matrix_2d(nx, ny, sigma_b, L_cells):
     Kx = circulant(cov_kernel(nx, 1.0, 1.0, L_cells))
     Ky = circulant(cov_kernel(ny, 1.0, 1.0, L_cells))
     return sigma_b ** 2 * np.kron(Ky, Kx)
+
+
+def bhalf_spde_1d(V, alpha, beta):
+    """Gamma^{1/2} V for the paper's 1-D prior Gamma = (alpha I - beta Lap*)^{-2}
+    (Sec. 5.1, 'Data and Background'; alpha = 0.5, beta = 500 there), i.e. the
+    solution X of the tridiagonal system (alpha I - beta Lap*) X = V with Lap*
+    the Dirichlet three-point Laplacian tridiag(1, -2, 1) on the interior nodes
+    (wall values zero).  Banded solve; V is (n,) or (n, k)."""
+    from scipy.linalg import solve_banded
+    V = np.asarray(V, dtype=np.float64)
+    n = V.shape[0]
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -beta
+    ab[1, :] = alpha + 2.0 * beta
+    ab[2, :-1] = -beta
+    return solve_banded((1, 1), ab, V)
+

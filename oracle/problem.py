@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import burgers as _burgers
+from . import burgers_dirichlet as _bwall
 from . import bve as _bve
 from . import prior as _prior
 
@@ -57,6 +58,37 @@ class BurgersModel:
 
     def bhalf(self, V, sigma_b, L):
         return _prior.bhalf_1d(V, self.dx, sigma_b, L)
+
+
+@dataclass
+class WallBurgersModel:
+    """The paper's Burgers setup: Dirichlet walls, RK3-TVD, the SPDE prior
+    (see ``oracle.burgers_dirichlet``, ``oracle.prior.bhalf_spde_1d``).
+    Observations at nodes stride-1, 2 stride-1, ... (x = stride dx, 2 stride dx, ...)."""
+    n: int
+    nu: float
+    dt: float
+    alpha: float
+    beta: float
+
+    @property
+    def dx(self):
+        return 1.0 / (self.n + 1)
+
+    def fwd(self, x0, nsteps):
+        return _bwall.fwd(np.asarray(x0, dtype=np.float64), self.dt, nsteps, self.nu, self.dx)
+
+    def tlm(self, traj, d0, obs_steps):
+        return _bwall.tlm(traj, d0, self.dt, self.nu, self.dx, obs_steps)
+
+    def adj(self, traj, forcings, obs_steps):
+        return _bwall.adj(traj, forcings, self.dt, self.nu, self.dx, obs_steps)
+
+    def obs_index(self, stride):
+        return np.arange(stride - 1, self.n, stride)
+
+    def bhalf(self, V, sigma_b, L):
+        return _prior.bhalf_spde_1d(V, self.alpha, self.beta)
 
 
 @dataclass
@@ -194,5 +226,22 @@ def bve_problem(cfg, draws=None):
     return prob
 
 
+def wall_burgers_problem(cfg, draws=None):
+    """The paper's Burgers setup from a config dict (keys: n, nu, dt, nsteps,
+    obs_stride, obs_every, sigma_o, prior_alpha, prior_beta) and optional draws."""
+    model = WallBurgersModel(n=int(cfg['n']), nu=float(cfg['nu']), dt=float(cfg['dt']),
+                             alpha=float(cfg['prior_alpha']), beta=float(cfg['prior_beta']))
+    prob = Problem(model=model, nsteps=int(cfg['nsteps']), obs_stride=int(cfg['obs_stride']),
+                   obs_every=int(cfg['obs_every']), sigma_o=float(cfg['sigma_o']), sigma_b=0.0, L_b=0.0)
+    if draws is not None:
+        prob.xb, prob.y = synthesize(prob, draws['x_true'], draws['xi'], draws['eta'])
+    return prob
+
+
 def make_problem(cfg, draws=None):
-    return bve_problem(cfg, draws) if cfg.get('model') == 'bve' else burgers_problem(cfg, draws)
+    kind = cfg.get('model')
+    if kind == 'bve':
+        return bve_problem(cfg, draws)
+    if kind == 'burgers_wall':
+        return wall_burgers_problem(cfg, draws)
+    return burgers_problem(cfg, draws)

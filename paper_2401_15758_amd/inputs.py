@@ -26,7 +26,17 @@ locations, a spun-up gyre truth -- are not available and not needed):
                  l = 100.  Truth: random-phase vorticity with |zeta_hat(k)| ~ 1/|k|
                  (energy spectrum k^-3) for 1 <= |k| <= n/3, scaled to unit rms.
 
-Truth: u0(x) = sin(2 pi x) + 0.5 sin(4 pi x) on x_j = j/n.
+  burgers-wall-399  the paper's Burgers setup (Sec. 5.1, Table 3): Dirichlet walls,
+                 n = 399 interior nodes (dx = 0.0025), nu = 0.1, RK3-TVD with
+                 dt = 2.5e-5, 20 observation times 0.01 apart (400 steps apart,
+                 8000 steps), 15 observed nodes (every 25th from node 24: the
+                 paper's locations are only drawn in a figure), R = 0.01 I,
+                 prior Gamma = (0.5 I - 500 Lap*)^{-2}; truth sin(pi x); l = 15.
+  burgers-wall-99   the same setup on 99 nodes, 400 steps, observations every 40
+                 steps at every 6th node (parity size).
+
+Truth: u0(x) = sin(2 pi x) + 0.5 sin(4 pi x) on x_j = j/n (periodic models);
+sin(pi x) on x_j = (j + 1)/(n + 1) (wall model).
 """
 import math
 import numpy as np
@@ -64,10 +74,25 @@ def bve_config(nx, nsteps=200, obs_stride=16, obs_every=20, dt=2e-3, nu=1e-4, si
 
 CFG_BVE = bve_config(256, name='bve-256')
 
+RK3_DIFFUSIVE_LIMIT = 2.51    # RK3-TVD real-axis stability interval (|z| <= 2.51)
+
+
+def wall_config(n, nsteps, obs_stride, obs_every, dt=2.5e-5, nu=0.1, sigma_o=0.1, prior_alpha=0.5,
+                prior_beta=500.0, ell=15, name=None):
+    return dict(model='burgers_wall', name=name or f'burgers-wall-{n}', n=int(n), nu=float(nu), dt=float(dt),
+                nsteps=int(nsteps), obs_stride=int(obs_stride), obs_every=int(obs_every), sigma_o=float(sigma_o),
+                prior_alpha=float(prior_alpha), prior_beta=float(prior_beta), sigma_b=0.0, L_b=0.0, ell=int(ell))
+
+
+CFG_WALL = wall_config(399, 8000, 25, 400, name='burgers-wall-399')
+CFG_WALL_SMALL = wall_config(99, 400, 6, 40, dt=2.5e-4, ell=12, name='burgers-wall-99')
+
 
 def n_obs(cfg):
     if cfg.get('model') == 'bve':
         return len(range(0, cfg['nx'], cfg['obs_stride'])) * len(range(0, cfg['ny'], cfg['obs_stride']))
+    if cfg.get('model') == 'burgers_wall':
+        return len(range(cfg['obs_stride'] - 1, cfg['n'], cfg['obs_stride']))
     return len(range(0, cfg['n'], cfg['obs_stride']))
 
 
@@ -76,6 +101,8 @@ def n_t(cfg):
 
 
 def truth(cfg):
+    if cfg.get('model') == 'burgers_wall':
+        return np.sin(np.pi * (np.arange(cfg['n']) + 1) / (cfg['n'] + 1))
     x = np.arange(cfg['n']) / cfg['n']
     return np.sin(2 * np.pi * x) + 0.5 * np.sin(4 * np.pi * x)
 
