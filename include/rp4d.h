@@ -66,7 +66,7 @@ enum {
     RP4D_SINGLEVIEW = 4,
     RP4D_SINGLEVIEW_ADAPTIVE = 5
 };
-enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1 };
+enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1, RP4D_BURGERS1D_WALL = 2 };
 /* How a GN step obtains its direction from (I + H) dv = -g_v (eq. (gniterf1)):
  * SketchPrec (PCG preconditioned by eq. (woodbury), Sec. 3.2.2) or SketchSolv
  * (one application of eq. (woodbury), eq. (dxsol), Sec. 3.2.1). */
@@ -74,6 +74,12 @@ enum { RP4D_SOLVE_PCG = 0, RP4D_SOLVE_SKETCH = 1 };
 
 /* Problem description (Sec. 2.1): model, window, observation layout, prior.
  *   Burgers:  nx grid points on [0,1) (ny ignored), viscosity nu.
+ *   Burgers, wall (the setup of Sec. 5.1): nx interior nodes x_j = (j+1)/(nx+1)
+ *     of (0,1) with homogeneous Dirichlet walls, central differences, RK3-TVD
+ *     (Shu-Osher form) instead of RK4; node j observed when (j+1) is a multiple
+ *     of obs_stride (n_obs = floor(nx/obs_stride)); prior Gamma^{1/2} =
+ *     (prior_alpha I - prior_beta Lap*)^{-1}, Lap* = tridiag(1,-2,1) with zero
+ *     walls (sigma_b, L_b ignored); nx <= 16384, batches not supported.
  *   BVE:      nx*ny periodic grid on [0,1)^2, viscosity nu.
  *   dt, nsteps: RK4 step and number of steps N of the window.
  *   obs_stride, obs_every: observe every obs_stride-th grid point (2-D: cell in
@@ -100,6 +106,7 @@ typedef struct {
     int obs_stride, obs_every;
     double sigma_o, sigma_b, L_b;
     int ckpt_every;
+    double prior_alpha, prior_beta;  /* wall model only: Gamma^{1/2} = (alpha I - beta Lap*)^{-1} */
 } rp4d_problem_desc;
 
 typedef struct {

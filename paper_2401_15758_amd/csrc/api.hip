@@ -270,8 +270,22 @@ Tiling heuristic_tiling(int n, int k) {
     return t;
 }
 
+// Wall-bounded sweeps run on wave regions: 4 points per lane (256-point
+// regions), 12 steps per launch (halo 52), tiles of up to 152 points, two
+// vectors per group for blocks.
+Tiling wall_tiling(int n, int k) {
+    Tiling t;
+    t.xch = XCH_WAVE;
+    t.ppt = 4;
+    t.kc = k >= 2 ? 2 : 1;
+    t.threads = 64;
+    t.steps = 12;
+    t.tile = std::min(n, 64 * t.ppt - 2 * (4 * t.steps + 4));
+    return t;
+}
+
 Tiling tiling_for(const rp4d_problem* p, int mode, int dtype, int k) {
-    Tiling t = heuristic_tiling(p->n, k);
+    Tiling t = p->wall ? wall_tiling(p->n, k) : heuristic_tiling(p->n, k);
     for (auto key : {std::make_tuple(mode, dtype, k), std::make_tuple(0, dtype, k), std::make_tuple(mode, dtype, 0),
                      std::make_tuple(0, dtype, 0)}) {
         auto it = p->tiling.find(key);
@@ -290,9 +304,9 @@ Tiling tiling_for(const rp4d_problem* p, int mode, int dtype, int k) {
 }
 
 Tiling fwd_tiling(const rp4d_problem* p) {
-    Tiling t = heuristic_tiling(p->n, 1);
+    Tiling t = p->wall ? wall_tiling(p->n, 1) : heuristic_tiling(p->n, 1);
     // the single nonlinear state: fewer, larger tiles amortise launches better
-    if (p->n >= 1024) {
+    if (p->n >= 1024 && !p->wall) {
         const int tiles = std::max(1, p->n / 512);
         t.tile = (p->n + tiles - 1) / tiles;
         t.steps = std::max(1, std::min(32, static_cast<int>((0.3 * t.tile - 8.0) / 8.0)));
@@ -351,6 +365,7 @@ void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* sto
     a.y = p->has_data ? p->y.as<double>() : nullptr;
     a.innov = p->has_data ? innov : nullptr;
     a.obs_out = obs_out;
+    a.wall = p->wall ? 1 : 0;
     SpanTimer span(p->ctx, RP4D_K_FWD);
     for (int s0 = s_from; s0 < s_to; s0 += t.steps) {
         a.s0 = s0;
@@ -385,6 +400,7 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
     a.n_t = p->n_t;
     a.inv_sigma_o = static_cast<T>(1.0 / p->d.sigma_o);
     a.z = z;
+    a.wall = p->wall ? 1 : 0;
     T* in = buf0;
     T* out = buf1;
     const int C = tr->C;
@@ -442,6 +458,7 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
     a.n_t = p->n_t;
     a.inv_sigma_o = static_cast<T>(1.0 / p->d.sigma_o);
     a.w = w;
+    a.wall = p->wall ? 1 : 0;
     T* in = buf0;
     T* out = buf1;
     const int C = tr->C;
@@ -646,6 +663,69 @@ rp4d_problem* create_bve(rp4d_ctx* ctx, const rp4d_problem_desc& d) {
 }
 }  // namespace
 
+// The paper's Burgers setup (Sec. 5.1): n interior nodes of (0, 1) with
+// Dirichlet walls, dx = 1/(n + 1), RK3-TVD, observations at nodes j with
+// (j + 1) a multiple of obs_stride, prior Gamma^{1/2} = (alpha I - beta Lap*)^{-1}.
+rp4d_problem* create_wall(rp4d_ctx* ctx, const rp4d_problem_desc& d) {
+    RP4D_REQUIRE(d.nx >= 8 && d.nx <= 16384, RP4D_EINVAL, "wall model: nx must be in [8, 16384]");
+    RP4D_REQUIRE(d.nsteps >= 1 && d.obs_every >= 1 && d.obs_stride >= 1 && d.obs_stride <= d.nx, RP4D_EINVAL,
+                 "bad window / observation layout");
+    RP4D_REQUIRE(d.nsteps / d.obs_every >= 1, RP4D_EINVAL, "window has no observation step");
+    RP4D_REQUIRE(d.dt > 0 && d.nu >= 0 && d.sigma_o > 0 && d.prior_alpha > 0 && d.prior_beta >= 0, RP4D_EINVAL,
+                 "bad physical parameters (wall model: prior_alpha > 0, prior_beta >= 0)");
+    const double dx = 1.0 / (d.nx + 1);
+    RP4D_REQUIRE(4.0 * d.nu * d.dt / (dx * dx) <= 2.51, RP4D_EUNSTABLE,
+                 "time step outside the RK3-TVD diffusive stability interval (4 nu dt/dx^2 > 2.51)");
+    RP4D_REQUIRE(10.0 * d.dt / dx <= 1.7, RP4D_EUNSTABLE,
+                 "time step outside the RK3-TVD advective stability interval for |u| <= 10");
+    auto* p = new rp4d_problem();
+    try {
+        p->ctx = ctx;
+        p->d = d;
+        p->wall = true;
+        p->n = d.nx;
+        p->n_obs = d.nx / d.obs_stride;
+        p->n_t = d.nsteps / d.obs_every;
+        p->m = p->n_obs * p->n_t;
+        p->s_last = p->n_t * d.obs_every;
+        p->dx = dx;
+        p->inv2dx = 1.0 / (2.0 * dx);
+        p->nu_dx2 = d.nu / (dx * dx);
+        if (p->d.ckpt_every < 1) p->d.ckpt_every = 1;
+        // (alpha I - beta Lap*) is diagonalised by the orthonormal sine basis
+        // S_ij = sqrt(2/(n+1)) sin((i+1)(j+1) pi/(n+1)), eigenvalues
+        // alpha + 4 beta sin^2((j+1) pi/(2(n+1))): Gamma^{1/2} = S diag(1/eig) S,
+        // applied by the spectral path with all n modes.
+        const int n = d.nx;
+        const long per = 2L * (n + 1);
+        std::vector<double> Fh(static_cast<size_t>(n) * n), lh(n);
+        const double c = std::sqrt(2.0 / (n + 1));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const long q = (static_cast<long>(i + 1) * (j + 1)) % per;
+                Fh[static_cast<size_t>(i) * n + j] = c * std::sin(M_PI * static_cast<double>(q) / (n + 1));
+            }
+        for (int j = 0; j < n; ++j) {
+            const double sj = std::sin(M_PI * (j + 1) / (2.0 * (n + 1)));
+            lh[j] = 1.0 / (d.prior_alpha + 4.0 * d.prior_beta * sj * sj);
+        }
+        p->spec = true;
+        p->r = n;
+        p->F.ensure(Fh.size() * sizeof(double));
+        p->lamF.ensure(lh.size() * sizeof(double));
+        RP4D_HIP(hipMemcpyAsync(p->F.p, Fh.data(), Fh.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        RP4D_HIP(hipMemcpyAsync(p->lamF.p, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        RP4D_HIP(hipStreamSynchronize(ctx->stream));  // the host staging vectors go out of scope
+        p->xb.ensure(p->n * sizeof(double));
+        p->y.ensure(static_cast<size_t>(p->m) * sizeof(double));
+        p->ws_scal.ensure(64 * sizeof(double));
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    return p;
+}
+
 // ===========================================================================
 // ABI
 // ===========================================================================
@@ -684,9 +764,14 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
         RP4D_REQUIRE(ctx != nullptr && desc != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
         set_device(ctx);
         const rp4d_problem_desc& d = *desc;
-        RP4D_REQUIRE(d.model == RP4D_BURGERS1D || d.model == RP4D_BVE2D, RP4D_EINVAL, "unknown model");
+        RP4D_REQUIRE(d.model == RP4D_BURGERS1D || d.model == RP4D_BVE2D || d.model == RP4D_BURGERS1D_WALL,
+                     RP4D_EINVAL, "unknown model");
         if (d.model == RP4D_BVE2D) {
             *out = create_bve(ctx, d);
+            return;
+        }
+        if (d.model == RP4D_BURGERS1D_WALL) {
+            *out = create_wall(ctx, d);
             return;
         }
         RP4D_REQUIRE(d.nx >= 8 && d.nx <= (1 << 22), RP4D_EINVAL, "nx out of range");

@@ -81,6 +81,7 @@ struct SweepArgs {
     T inv_sigma_o;
     T* z;                 // TLM observation output (n_t, n_obs, k)
     const T* w;           // ADJ observation forcing (n_t, n_obs, k)
+    int wall;             // 1: Dirichlet walls + RK3-TVD (wall-bounded sweeps)
 };
 
 struct FwdArgs {
@@ -96,6 +97,7 @@ struct FwdArgs {
     const double* y;      // observations (n_t, n_obs) or null
     double* innov;        // innovations out (n_t, n_obs) or null
     double* obs_out;      // O x_{s_i} out (n_t, n_obs) or null
+    int wall;             // 1: Dirichlet walls + RK3-TVD (wall-bounded sweeps)
 };
 
 void launch_burgers_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st);
@@ -107,6 +109,12 @@ void launch_burgers_sweep_batched(int mode, const SweepArgs<T>* args, const int4
                                   hipStream_t st);
 template <typename T>
 void launch_burgers_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st);
+// Wall-bounded RK3-TVD sweeps (wave regions only; the tiling's exchange field
+// is not consulted).  launch_burgers_fwd / launch_burgers_sweep forward here
+// when the arguments' wall flag is set.
+void launch_wall_fwd(const FwdArgs& a, const Tiling& t, hipStream_t st);
+template <typename T>
+void launch_wall_sweep(int mode, const SweepArgs<T>& a, const Tiling& t, int ngroups, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Prior square root, layouts and tall-skinny dense kernels
@@ -343,6 +351,7 @@ struct rp4d_problem {
     int D = 0;
     // spectral form of the circulant prior square root: F (n x r) real Fourier
     // basis of the retained modes, lam (r) their eigenvalues
+    bool wall = false;    // Dirichlet walls, RK3-TVD, SPDE prior (the paper's Burgers setup)
     bool spec = false;
     int r = 0;
     rp4d::DevBuf F, lamF, ws_bh;

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE = 0, 1, 2, 3, 4, 5
-BURGERS1D, BVE2D = 0, 1
+BURGERS1D, BVE2D, BURGERS1D_WALL = 0, 1, 2
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
 XCH_LDS, XCH_WAVE = 1, 2
@@ -43,7 +43,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nu", ctypes.c_double),
                 ("dt", ctypes.c_double), ("nsteps", ctypes.c_int), ("obs_stride", ctypes.c_int),
                 ("obs_every", ctypes.c_int), ("sigma_o", ctypes.c_double), ("sigma_b", ctypes.c_double),
-                ("L_b", ctypes.c_double), ("ckpt_every", ctypes.c_int)]
+                ("L_b", ctypes.c_double), ("ckpt_every", ctypes.c_int), ("prior_alpha", ctypes.c_double),
+                ("prior_beta", ctypes.c_double)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -251,12 +252,14 @@ class Problem:
     def __init__(self, ctx, cfg, ckpt_every=0):
         self.ctx = ctx
         self.cfg = dict(cfg)
-        d = ProblemDesc(model=BURGERS1D if cfg.get("model", "burgers") == "burgers" else BVE2D,
+        kind = cfg.get("model", "burgers")
+        d = ProblemDesc(model={"burgers": BURGERS1D, "bve": BVE2D, "burgers_wall": BURGERS1D_WALL}[kind],
                         nx=int(cfg["nx"] if cfg.get("model") == "bve" else cfg["n"]), ny=int(cfg.get("ny", 1)),
                         nu=float(cfg["nu"]),
                         dt=float(cfg["dt"]), nsteps=int(cfg["nsteps"]), obs_stride=int(cfg["obs_stride"]),
                         obs_every=int(cfg["obs_every"]), sigma_o=float(cfg["sigma_o"]),
-                        sigma_b=float(cfg["sigma_b"]), L_b=float(cfg["L_b"]), ckpt_every=int(ckpt_every))
+                        sigma_b=float(cfg["sigma_b"]), L_b=float(cfg["L_b"]), ckpt_every=int(ckpt_every),
+                        prior_alpha=float(cfg.get("prior_alpha", 0.0)), prior_beta=float(cfg.get("prior_beta", 0.0)))
         h = ctypes.c_void_p()
         _check(_lib.rp4d_problem_create(ctx._h, ctypes.byref(d), ctypes.byref(h)))
         self._h = h
