@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-bve", action="store_true", help="skip the bve-256 section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-64 section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serve-mix section")
+    ap.add_argument("--no-wall", action="store_true", help="skip the burgers-wall-399 section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB with a plain elementwise kernel "
                          "(reference dispatch for the HBM byte counters)")
@@ -51,7 +52,9 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "burgers_sweep_k64_traffic.json")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2401_15758_amd", "csrc", "burgers_sweep.hip")
+# the sources that define the periodic sweep kernels (hashed together, in this order)
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2401_15758_amd", "csrc", f)
+                 for f in ("burgers_sweep.hip", "sweep_common.hpp")]
 
 
 def measured_traffic(kname, tiling, cfg):
@@ -63,8 +66,11 @@ def measured_traffic(kname, tiling, cfg):
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(SWEEP_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in SWEEP_SOURCES:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
     except (OSError, ValueError):
         return None
     keys = ("ppt", "kc", "threads", "tile", "steps", "xch")
@@ -119,6 +125,59 @@ def bve_section(rp4d, inputs, torch, np):
                          "frac": gemm_tf / PEAK_FP64_VALU_TFLOPS, "traffic": None,
                          "avg_launch_us": 1e3 * g["total_ms"] / max(1, g["launches"]), "launches": g["launches"]},
             "stencil_ms": sten["total_ms"], "gemm_ms": g["total_ms"]}
+
+
+def wall_section(rp4d, inputs, torch, np, max_gn=8):
+    """burgers-wall-399: the paper's Burgers setup (Dirichlet walls, RK3-TVD,
+    8000 steps, 15 x 20 observations, prior (0.5 I - 500 Lap*)^{-2}) assimilated
+    from the background until |g_v|_inf falls below 1e-6 of its first value
+    (at most max_gn GN iterations), PCG to 1e-9, sketches of l = l1 = 15 and
+    l2 = 31 redrawn every iteration: Prec_Gamma, SketchPrec with each sketch and
+    SketchSolv with each sketch.  Counts in the style of the paper's Burgers
+    table (its own counts are not reproducible: observation locations unknown)."""
+    cfg = dict(inputs.CFG_WALL)
+    ell = cfg["ell"]
+    ctx = rp4d.Context(0)
+    p = rp4d.Problem(ctx, cfg)
+    d = inputs.draws(cfg, seed=0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    xb, y = p.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
+    p.set_data(xb, y.reshape(-1))
+    tr = p.traj()
+    methods = [("Prec_Gamma", rp4d.NOPREC, rp4d.SOLVE_PCG), ("SketchPrec RandSVD", rp4d.RANDSVD, rp4d.SOLVE_PCG),
+               ("SketchPrec Nystrom", rp4d.NYSTROM, rp4d.SOLVE_PCG),
+               ("SketchPrec SingleView", rp4d.SINGLEVIEW, rp4d.SOLVE_PCG),
+               ("SketchSolv RandSVD", rp4d.RANDSVD, rp4d.SOLVE_SKETCH),
+               ("SketchSolv Nystrom", rp4d.NYSTROM, rp4d.SOLVE_SKETCH),
+               ("SketchSolv SingleView", rp4d.SINGLEVIEW, rp4d.SOLVE_SKETCH)]
+    rows = []
+    for name, sk, solve in methods:
+        st = p.gn_state()
+        p.reset_counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g0, gn, pcg, ok = None, 0, 0, False
+        for it in range(max_gn):
+            info = p.gn_step(st, sketch=sk, ell=ell, ell2=2 * ell + 1, seed=5000 + it, rtol=1e-9, maxit=400,
+                             solve=solve, raise_noconv=False)
+            g0 = info["gnorm_inf"] if g0 is None else g0
+            gn += 1
+            pcg += info["pcg_iters"]
+            v, x = st.get()
+            p.fwd(x, tr, want_J=False)
+            g = p.gradient(tr, v)
+            if float(g.abs().max()) < 1e-6 * g0:
+                ok = True
+                break
+        torch.cuda.synchronize()
+        c = p.counters()
+        rows.append({"method": name, "gn_iters": gn, "converged": ok, "pcg_iters": pcg,
+                     "offline_tlm": c["tlm_offline"], "offline_adj": c["adj_offline"],
+                     "online_tlm": c["tlm_online"], "online_adj": c["adj_online"], "fwd": c["fwd"],
+                     "seconds": time.perf_counter() - t0})
+    return {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "m": p.m, "l": ell, "l2": 2 * ell + 1,
+            "stop": "|g_v|_inf < 1e-6 |g_v(0)|_inf (checked with one FWD + gradient after each step)",
+            "methods": rows}
 
 
 def batch_section(rp4d, inputs, torch, np):
@@ -455,6 +514,9 @@ def main():
         print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     note("burgers-4096 done")
+    if not args.no_wall:
+        note("burgers-wall-399 section")
+        out["wall"] = wall_section(rp4d, inputs, torch, np)
     if not args.no_bve:
         note("bve-256 section")
         out["bve"] = bve_section(rp4d, inputs, torch, np)

@@ -704,10 +704,16 @@ __global__ void __launch_bounds__(1024) jacobi64_kernel(const double* A, double*
                 double c = 1.0, s = 0.0;
                 const double apq = sA[p * LD + q], app = sA[p * LD + p], aqq = sA[q * LD + q];
                 if (fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs && fabs(apq) > 1e-300) {
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double tt = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                                 : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    // t = tan(theta) = sign(d) 2apq / (|d| + sqrt(d^2 + 4apq^2)), d = aqq - app (the
+                    // smaller root of t^2 + 2 t d/(2apq) - 1 = 0); c = 1/sqrt(1 + t^2) from the
+                    // hardware reciprocal square root and one Newton step (one sqrt and one
+                    // division on the critical path instead of two and three)
+                    const double d = aqq - app, e = 2.0 * apq;
+                    const double r = sqrt(fma(d, d, e * e));
+                    const double tt = (d >= 0.0 ? e : -e) / (fabs(d) + r);
+                    const double w = fma(tt, tt, 1.0);
+                    const double y = __builtin_amdgcn_rsq(w);
+                    c = y * fma(-0.5 * w * y, y, 1.5);
                     s = tt * c;
                     rotated = 1;
                 }
