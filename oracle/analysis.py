@@ -5,6 +5,8 @@ Test infrastructure only (see ``oracle/__init__``).
   * intrinsic dimension id_r = sum_{j>r} lambda_j / lambda_{r+1}   Sec. 4.2
   * Psi_H(r, p) = (1 + r/(p-1) id_r) lambda_{r+1}                   Thm. (RandSVD)
   * kappa_2 of (I + H_hat)^{-1/2}(I + H)(I + H_hat)^{-1/2}          Thm. (bound_loew)
+  * Theta_H(r) = 4 (sum_{j>r} lambda_1 lambda_j)^{1/2} + 4 sum_{j>r} lambda_j
+                                                                    Thm. (SingleView)
 """
 import numpy as np
 
@@ -32,3 +34,11 @@ def precond_kappa(Hd, Hhat):
     K = Pm @ (np.eye(n) + Hd) @ Pm
     w = np.linalg.eigvalsh(0.5 * (K + K.T))
     return float(w[-1] / w[0])
+
+
+def theta_bound(lam, r):
+    """Theta_H(r, p) of the SingleView theorem (l1 = 2r + 1, l2 = 2 l1 + 1)."""
+    lam = np.sort(np.asarray(lam, dtype=np.float64))[::-1]
+    tail = float(np.sum(lam[r:]))
+    return 4.0 * np.sqrt(lam[0] * tail) + 4.0 * tail
+

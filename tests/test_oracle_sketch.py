@@ -140,3 +140,34 @@ def test_sample_size_rule():
             continue
         psi = analysis.psi_bound(lam, r_eps, p)
         assert psi <= (1 + 5 * analysis.intrinsic_dimension(lam, r_eps)) * eps
+
+
+def test_singleview_expected_bounds(small_problem, small_dense):
+    """Thm. (SingleView) with l1 = 2r + 1, l2 = 2 l1 + 1: the sample means over
+    30 seeds of sqrt(kappa_2) and of the SketchSolv error |dv - dv_hat|/|dv|
+    (eq. (dxsol), the Gamma^{-1} norm of the x-step) stay within 1 + Theta_H(r)
+    and Theta_H(r).  SingleView's H - H_hat is not PSD in general, so each draw
+    also obeys the weaker deterministic bound sqrt(kappa_2) <= 1 + |E|_2 of
+    Thm. (bound_loew)."""
+    p = small_problem
+    traj, Hs, _ = small_dense
+    lamH = np.linalg.eigvalsh(Hs)[::-1]
+    A = p.A(traj, np.eye(p.n)).reshape(p.m, p.n)
+    r = 6
+    l1, l2 = 2 * r + 1, 2 * (2 * r + 1) + 1
+    b = np.random.default_rng(77).standard_normal(p.n)
+    dv = np.linalg.solve(np.eye(p.n) + Hs, b)
+    roots, errs = [], []
+    for seed in range(30):
+        rng = np.random.default_rng(6000 + seed)
+        V, lam = sketch.singleview(lambda X: A @ X, lambda W: A.T @ W, rng.standard_normal((p.n, l1)),
+                                   rng.standard_normal((p.m, l2)))
+        Hh = sketch.hhat_apply(V, lam, np.eye(p.n))
+        kap = analysis.precond_kappa(Hs, Hh)
+        E = np.linalg.norm(Hs - Hh, 2)
+        assert np.sqrt(kap) <= 1 + E + 1e-8 * (1 + E)
+        roots.append(np.sqrt(kap))
+        errs.append(np.linalg.norm(dv - sketch.lmp_apply(V, lam, b)) / np.linalg.norm(dv))
+    theta = analysis.theta_bound(lamH, r)
+    assert np.mean(roots) <= 1 + theta, (np.mean(roots), theta)
+    assert np.mean(errs) <= theta, (np.mean(errs), theta)
