@@ -46,6 +46,11 @@ def build_precond_singleview_adaptive(prob, traj, Omegas, Psis, v, eps_sk, qr='d
                                        lambda X: prob.misfit_hessian(traj, X), Omegas, Psis, v, eps_sk, qr=qr)
 
 
+def build_precond_nystrom_adaptive(prob, traj, Omegas, v, eps_sk):
+    """Adaptive Nystrom on the problem's H: returns (V, lam, nu, kappas)."""
+    return _sketch.nystrom_adaptive(lambda X: prob.misfit_hessian(traj, X), Omegas, v, eps_sk)
+
+
 def split_blocks(X, first, step):
     """Columns [0, first), then `step` at a time while whole blocks remain."""
     return [X[:, :first]] + [X[:, k:k + step] for k in range(first, X.shape[1] - step + 1, step)]
@@ -73,7 +78,7 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
             precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None, solve='pcg'):
     """One GN step from control vector v.
 
-    method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'singleview'
+    method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'nystrom_adaptive' | 'singleview'
     (Alg. 3; Omega is then the pair (Omega, Psi)) | 'singleview_adaptive'
     (Alg. 5; the pair again, split by adaptive['ell0'/'ell_hat'] and
     adaptive['ell2'/'ell2_hat']) | 'none' (Prec_Gamma).
@@ -101,6 +106,12 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
         if P is None and method == 'randsvd_adaptive':
             blocks = split_blocks(Omega, adaptive['ell0'], adaptive['ell_hat'])
             V, lam, kappas = build_precond_adaptive(prob, traj, blocks, vhat, adaptive['eps_sk'])
+            P = (V, lam)
+            c['tlm_off'] += V.shape[1] + len(kappas)
+            c['adj_off'] += V.shape[1] + len(kappas)
+        elif P is None and method == 'nystrom_adaptive':
+            blocks = split_blocks(Omega, adaptive['ell0'], adaptive['ell_hat'])
+            V, lam, _, kappas = build_precond_nystrom_adaptive(prob, traj, blocks, vhat, adaptive['eps_sk'])
             P = (V, lam)
             c['tlm_off'] += V.shape[1] + len(kappas)
             c['adj_off'] += V.shape[1] + len(kappas)

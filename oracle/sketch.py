@@ -8,7 +8,7 @@ Test infrastructure only (see ``oracle/__init__``).
   * LMP          eq. (woodbury): (I + V L V^T)^{-1} = I - V (L^{-1} + I)^{-1} V^T
   * W-form       Remark 1, eq. (randsvdsv): (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W
   * adaptive     Sec. 3.1.2, Alg. 4 (randsvd_adaptive) with the test kappa_sk of
-                 eq. (condtext)
+                 eq. (condtext); the Nystrom form (nystrom_adaptive)
   * SingleView   Sec. 3.1.1, Alg. 3 (singleview), the oblique-projector
                  approximation of eq. (singleviewlr); adaptive form Alg. 5
                  (singleview_adaptive) with the QR update of Alg. 6 (qr_update)
@@ -34,8 +34,13 @@ class NotSPDError(RuntimeError):
 def nystrom(H_apply, Omega, eps=EPS64, max_retries=3):
     """Alg. 2: returns (V_hat (n x l), lambda_hat (l,), nu)."""
     Omega = np.asarray(Omega, dtype=np.float64)
+    return nystrom_from_sketch(Omega, H_apply(Omega), eps, max_retries)   # step 2: Y = H Omega
+
+
+def nystrom_from_sketch(Omega, Y0, eps=EPS64, max_retries=3):
+    """Alg. 2 from step 3 on, given the sketch Y0 = H Omega."""
+    Omega = np.asarray(Omega, dtype=np.float64)
     n, ell = Omega.shape
-    Y0 = H_apply(Omega)                                  # step 2: Y = H Omega
     nu = np.sqrt(n) * eps * np.linalg.norm(Y0, 2)         # step 3
     for _ in range(max_retries + 1):
         Y = Y0 + nu * Omega                               # step 4
@@ -183,6 +188,29 @@ def singleview_adaptive(A_apply, AT_apply, H_apply, Omegas, Psis, v, eps_sk, qr=
         kappas.append(kappa_sk(H_apply, W, v))
     _, S, Vt = np.linalg.svd(W, full_matrices=False)
     return Vt.T.copy(), S * S, kappas
+
+
+def nystrom_adaptive(H_apply, Omegas, v, eps_sk, eps=EPS64):
+    """Adaptive Nystrom (Sec. 3.1.2).  The paper gives the loop for RandSVD
+    (Alg. 4) and calls the Nystrom form similar; read as: each round appends the
+    next Gaussian block of ``Omegas`` to Omega, sweeps only that block
+    (H Omega is formed column by column) and forms Alg. 2 on every column so
+    far; kappa_sk of eq. (condtext) uses (I + H_hat)^{-1} by eq. (woodbury);
+    the loop stops once kappa_sk <= eps_sk or no block remains.
+    Returns (V_hat, lambda_hat, nu, kappas)."""
+    vu = np.asarray(v, dtype=np.float64)
+    vu = vu / np.linalg.norm(vu)
+    cols, Ys, kappas = [], [], []
+    for blk in Omegas:
+        if kappas and kappas[-1] <= eps_sk:
+            break
+        blk = np.asarray(blk, dtype=np.float64)
+        cols.append(blk)
+        Ys.append(H_apply(blk))                            # sweep of the new block only
+        V, lam, nu = nystrom_from_sketch(np.hstack(cols), np.hstack(Ys), eps)
+        u = lmp_apply(V, lam, vu)
+        kappas.append(float(np.linalg.norm(u + H_apply(u[:, None])[:, 0])))
+    return V, lam, nu, kappas
 
 
 def lmp_diag(lam):
