@@ -64,7 +64,8 @@ enum {
     RP4D_NOPREC = 2,
     RP4D_RANDSVD_ADAPTIVE = 3,
     RP4D_SINGLEVIEW = 4,
-    RP4D_SINGLEVIEW_ADAPTIVE = 5
+    RP4D_SINGLEVIEW_ADAPTIVE = 5,
+    RP4D_NYSTROM_ADAPTIVE = 6
 };
 enum { RP4D_BURGERS1D = 0, RP4D_BVE2D = 1, RP4D_BURGERS1D_WALL = 2 };
 /* How a GN step obtains its direction from (I + H) dv = -g_v (eq. (gniterf1)):
@@ -129,8 +130,9 @@ typedef struct {
 /* Options of one Gauss-Newton step (Sec. 2.2, Sec. 3.2). */
 typedef struct {
     int sketch;             /* RP4D_NYSTROM, RP4D_RANDSVD, RP4D_NOPREC (Prec_Gamma),
-                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64), RP4D_SINGLEVIEW (Alg. 3) or
-                               RP4D_SINGLEVIEW_ADAPTIVE (Alg. 5, FP64) */
+                               RP4D_RANDSVD_ADAPTIVE (Alg. 4, FP64), RP4D_SINGLEVIEW (Alg. 3),
+                               RP4D_SINGLEVIEW_ADAPTIVE (Alg. 5, FP64) or RP4D_NYSTROM_ADAPTIVE
+                               (FP64; the adaptive options as for Alg. 4) */
     int ell;                /* sketch size l (adaptive: the initial size; SingleView: l1) */
     uint64_t seed;          /* Philox seed for Omega when omega == NULL */
     const double* omega;    /* device (n, ell) test matrix -- adaptive: (n, ell_max) -- or NULL */
@@ -260,6 +262,14 @@ typedef struct {
 } rp4d_adaptive_info;
 int rp4d_build_precond_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_adaptive_opts* opts,
                                 rp4d_precond** out, rp4d_adaptive_info* info);
+/* Adaptive Nystrom (Sec. 3.1.2; the paper gives the loop for RandSVD and calls
+ * the Nystrom form similar): the same options and stopping rule as
+ * rp4d_build_precond_adaptive.  Each round sweeps only the new block through
+ * the block Hessian, appends it to Omega and H Omega, forms Alg. 2 on all
+ * columns so far and evaluates kappa_sk with the new preconditioner.  FP64;
+ * counts every column and every kappa_sk product as offline TLM + ADJ. */
+int rp4d_build_precond_nystrom_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_adaptive_opts* opts,
+                                        rp4d_precond** out, rp4d_adaptive_info* info);
 /* SingleView (Sec. 3.1.1, Alg. 3): the range sketch Y = A Omega (l1 TLM columns)
  * and the co-range sketch Z = A^T Psi (l2 ADJ columns) are independent; the
  * approximation is A_SV = Q_Y (Psi^T Q_Y)^+ Z^T (eq. (singleviewlr)), returned

@@ -1132,10 +1132,19 @@ void sketch_misfit_hessian(rp4d_problem* p, const rp4d_traj* tr, int l, int dtyp
     }
 }
 
+void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc);
+
 void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc) {
+    sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
+    nystrom_core(p, l, dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23), s, pc);
+}
+
+// Alg. 2 from step 3 on: Omega (n x l) in s.Om and Y = H Omega in s.Yd, both
+// row-major with leading size l; eps is the unit roundoff of the sketch sweeps.
+// Writes pc->V and s.lam, s.D, s.nu.
+void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc) {
     hipStream_t st = stream_of(p);
     const int n = p->n;
-    sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
     // step 3: nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
     launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
     {
@@ -1144,7 +1153,6 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     }
     // nu stays on the device (s.nu); a non-finite sketch surfaces as a failed
     // Cholesky factorisation below
-    const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
     nystrom_nu_kernel<<<1, 1, 0, st>>>(s.lam, std::sqrt(static_cast<double>(n)) * eps, s.nu);
     RP4D_HIP(hipGetLastError());
     bool ok = false;
@@ -1425,6 +1433,81 @@ void build_randsvd_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_ada
     }
 }
 
+void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const double* R, double* Z);
+
+// Adaptive Nystrom (Sec. 3.1.2: the Nystrom form of the adaptive loop of
+// Alg. 4) into pc.  Each round draws the next Gaussian block (or reads omega's
+// columns [c, c + b)), sweeps only that block (Y_hat = H Omega_hat, one block
+// Hessian product), appends both to the accumulated Omega and Y (n x l_max,
+// leading size l_max) and forms Alg. 2 on all c columns; kappa_sk (eq.
+// (condtext)) applies the new preconditioner (eq. (woodbury)) to v and then
+// I + H.  The loop stops once kappa_sk <= eps_sk or the next block would pass
+// l_max.  FP64.  Host waits: the Nystrom Cholesky check and one scalar read
+// per round.
+void build_nystrom_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_adaptive_opts& o, rp4d_precond* pc,
+                            rp4d_adaptive_info* info) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n, L = o.ell_max;
+    Scratch s = sketch_scratch(p, L, RP4D_F64);
+    const size_t nL = static_cast<size_t>(n) * L;
+    p->ws_ad.ensure((2 * nL + 3 * static_cast<size_t>(n) + 1024 + 64) * sizeof(double));
+    double* Oa = p->ws_ad.as<double>();  // n x L: Omega
+    double* Ya = Oa + nL;                // n x L: H Omega
+    KappaWork kw{};
+    kw.vu = Ya + nL;
+    kw.u = kw.vu + n;
+    kw.q = kw.u + n;
+    kw.red = kw.q + n;
+    kappa_test_vector(p, o.vtest, adaptive_vseed(o.seed), kw);
+    double* sc = p->ws_scal.as<double>();
+    const double eps = std::ldexp(1.0, -52);
+    pc->p = p;
+    pc->host_ok = false;
+    int c = 0, r = 0, nk = 0;
+    double kappa = 0.0;
+    for (;;) {
+        const int b = r == 0 ? o.ell0 : o.ell_hat;
+        if (o.omega)
+            launch_relayout<double, double>(o.omega + c, L, s.Om, b, n, b, st);
+        else
+            launch_philox_normal(adaptive_seed(o.seed, r), static_cast<size_t>(n) * b, s.Om, st);
+        hessian_dispatch(p, tr, b, s.Om, s.Yd, RP4D_F64, false);        // Y_hat = H Omega_hat
+        launch_relayout<double, double>(s.Om, b, Oa + c, L, n, b, st);
+        launch_relayout<double, double>(s.Yd, b, Ya + c, L, n, b, st);
+        c += b;
+        ++r;
+        p->cnt.tlm_offline += b;
+        p->cnt.adj_offline += b;
+        // Alg. 2 on the c columns so far
+        launch_relayout<double, double>(Oa, L, s.Om, c, n, c, st);
+        launch_relayout<double, double>(Ya, L, s.Yd, c, n, c, st);
+        nystrom_core(p, c, eps, s, pc);
+        pc->ell = c;
+        pc->Dg.ensure(static_cast<size_t>(c) * sizeof(double));
+        launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, c, 1, st);
+        // kappa_sk = |(I + H) (I + H_hat)^{-1} v|
+        precond_apply_impl(p, pc, 1, kw.vu, kw.u);
+        hessian_dispatch(p, tr, 1, kw.u, kw.q, RP4D_F64, true);
+        p->cnt.tlm_offline += 1;
+        p->cnt.adj_offline += 1;
+        launch_dot(kw.q, kw.q, n, sc + SC_T1, kw.red, st);
+        kappa = std::sqrt(read_scalar(p, sc + SC_T1));
+        RP4D_REQUIRE(std::isfinite(kappa), RP4D_ENONFINITE, "adaptive sketch: non-finite kappa_sk");
+        if (info && nk < 16) info->kappa[nk] = kappa;
+        ++nk;
+        if (kappa <= o.eps_sk || c + o.ell_hat > L) break;
+    }
+    pc->lamd.ensure(static_cast<size_t>(c + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, c, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + c, 1, 1, 1, st);
+    p->cnt.sketches += 1;
+    if (info) {
+        info->ell = c;
+        info->nkappa = nk;
+        info->kappa_sk = kappa;
+    }
+}
+
 void check_adaptive_opts(const rp4d_problem* p, const rp4d_adaptive_opts& o) {
     RP4D_REQUIRE(o.ell0 >= 1 && o.ell_hat >= 1 && o.ell_max >= o.ell0 && o.ell_max <= 128 && o.ell_max <= p->n,
                  RP4D_EINVAL, "adaptive sketch: need 1 <= ell0 <= ell_max <= min(128, n) and ell_hat >= 1");
@@ -1523,6 +1606,25 @@ int rp4d_build_precond_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d
         auto* pc = new rp4d_precond();
         try {
             build_randsvd_adaptive(p, tr, *o, pc, info);
+            fetch_host(pc);
+        } catch (...) {
+            delete pc;
+            throw;
+        }
+        *out = pc;
+    });
+}
+
+int rp4d_build_precond_nystrom_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_adaptive_opts* o,
+                                        rp4d_precond** out, rp4d_adaptive_info* info) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && o != nullptr && out != nullptr, RP4D_EINVAL, "null argument");
+        check_traj(p, tr);
+        check_adaptive_opts(p, *o);
+        set_device(p->ctx);
+        auto* pc = new rp4d_precond();
+        try {
+            build_nystrom_adaptive(p, tr, *o, pc, info);
             fetch_host(pc);
         } catch (...) {
             delete pc;
@@ -2152,7 +2254,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         RP4D_REQUIRE(p != nullptr && s != nullptr && o != nullptr && s->p == p, RP4D_EINVAL, "bad argument");
         RP4D_REQUIRE(o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD || o->sketch == RP4D_NOPREC ||
                          o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_SINGLEVIEW ||
-                         o->sketch == RP4D_SINGLEVIEW_ADAPTIVE,
+                         o->sketch == RP4D_SINGLEVIEW_ADAPTIVE || o->sketch == RP4D_NYSTROM_ADAPTIVE,
                      RP4D_EINVAL, "unknown sketch method");
         RP4D_REQUIRE(o->solve == RP4D_SOLVE_PCG || (o->solve == RP4D_SOLVE_SKETCH && o->sketch != RP4D_NOPREC),
                      RP4D_EINVAL, "solve must be RP4D_SOLVE_PCG, or RP4D_SOLVE_SKETCH with a sketch");
@@ -2163,7 +2265,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
             check_sv_adaptive_opts(p, sao);
         }
         rp4d_adaptive_opts ao{};
-        if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
+        if (o->sketch == RP4D_RANDSVD_ADAPTIVE || o->sketch == RP4D_NYSTROM_ADAPTIVE) {
             ao = rp4d_adaptive_opts{o->ell, o->ell_hat, o->ell_max, o->eps_sk, o->seed, o->omega, o->vhat};
             check_adaptive_opts(p, ao);
         }
@@ -2230,6 +2332,10 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
                     rp4d_adaptive_info ai{};
                     build_randsvd_adaptive(p, s->traj, ao, s->pc, &ai);
+                    inf.kappa_sk = ai.kappa_sk;
+                } else if (o->sketch == RP4D_NYSTROM_ADAPTIVE) {
+                    rp4d_adaptive_info ai{};
+                    build_nystrom_adaptive(p, s->traj, ao, s->pc, &ai);
                     inf.kappa_sk = ai.kappa_sk;
                 } else if (o->sketch == RP4D_SINGLEVIEW) {
                     build_singleview(p, s->traj, so, s->pc);

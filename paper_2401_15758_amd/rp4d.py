@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32 = 0, 1
-NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE = 0, 1, 2, 3, 4, 5
+NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE, NYSTROM_ADAPTIVE = 0, 1, 2, 3, 4, 5, 6
 BURGERS1D, BVE2D, BURGERS1D_WALL = 0, 1, 2
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
@@ -134,6 +134,8 @@ _SIGS = {
     "rp4d_build_precond_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
                                      ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_build_precond_singleview": ([_P, _P, ctypes.POINTER(SingleViewOpts), ctypes.POINTER(_P)], _I),
+    "rp4d_build_precond_nystrom_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
+                                             ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_build_precond_singleview_adaptive": ([_P, _P, ctypes.POINTER(SvAdaptiveOpts), ctypes.POINTER(_P),
                                                 ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_precond_destroy": ([_P], _I),
@@ -350,16 +352,18 @@ class Problem:
         _check(_lib.rp4d_build_precond(self._h, traj._h, method, ell, seed, om, sketch_dtype, ctypes.byref(h)))
         return Precond(self, h, ell)
 
-    def build_precond_adaptive(self, traj, ell0, ell_hat, ell_max, eps_sk=1.01, seed=0, omega=None, vtest=None):
-        """Adaptive RandSVD; omega (n, ell_max) and vtest (n) are optional device
-        tensors.  Returns (Precond, {"ell", "kappa": [...]})."""
+    def build_precond_adaptive(self, traj, ell0, ell_hat, ell_max, eps_sk=1.01, seed=0, omega=None, vtest=None,
+                               method=RANDSVD):
+        """Adaptive RandSVD (method=RANDSVD) or Nystrom (method=NYSTROM); omega
+        (n, ell_max) and vtest (n) are optional device tensors.  Returns
+        (Precond, {"ell", "kappa": [...]})."""
         o = AdaptiveOpts(ell0=ell0, ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, seed=seed,
                          omega=_ptr(omega, torch.float64, self.n * ell_max, "omega") if omega is not None else None,
                          vtest=_ptr(vtest, torch.float64, self.n, "vtest") if vtest is not None else None)
         h = ctypes.c_void_p()
         info = AdaptiveInfo()
-        _check(_lib.rp4d_build_precond_adaptive(self._h, traj._h, ctypes.byref(o), ctypes.byref(h),
-                                                ctypes.byref(info)))
+        fn = _lib.rp4d_build_precond_nystrom_adaptive if method == NYSTROM else _lib.rp4d_build_precond_adaptive
+        _check(fn(self._h, traj._h, ctypes.byref(o), ctypes.byref(h), ctypes.byref(info)))
         return Precond(self, h, info.ell), dict(ell=info.ell, kappa=list(info.kappa[:min(16, info.nkappa)]),
                                                  kappa_sk=info.kappa_sk, nkappa=info.nkappa)
 
@@ -427,7 +431,7 @@ class Problem:
         co-range sketch, psi (m, l2_max) and eps_sk.  solve=SOLVE_SKETCH takes
         the SketchSolv direction (one application of the preconditioner)
         instead of PCG."""
-        wide = ell_max if sketch in (RANDSVD_ADAPTIVE, SINGLEVIEW_ADAPTIVE) else ell
+        wide = ell_max if sketch in (RANDSVD_ADAPTIVE, NYSTROM_ADAPTIVE, SINGLEVIEW_ADAPTIVE) else ell
         if sketch == SINGLEVIEW_ADAPTIVE:
             l2 = sv_adaptive_sizes(self.m, ell, ell_hat, ell_max, ell2, ell2_hat)[2]
         else:

@@ -327,3 +327,57 @@ def test_sketchsolv_requires_a_sketch():
     with pytest.raises(rp4d.Rp4dError) as e:
         pr.gpu.gn_step(st, sketch=rp4d.NOPREC, solve=rp4d.SOLVE_SKETCH)
     assert e.value.code == rp4d.EINVAL
+
+
+@pytest.mark.parametrize("ell0,ell_hat,ell_max,eps", [(8, 8, 40, 1.01), (6, 5, 36, 1.5), (8, 8, 16, 1.01)])
+def test_adaptive_nystrom_parity(small, ell0, ell_hat, ell_max, eps):
+    """Adaptive Nystrom: the same blocks and test vector give the same kappa_sk
+    sequence, final size, shift and approximation as the oracle."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    Om = inputs.omega(pr.orc.n, ell_max, seed=900 + ell0)
+    v = inputs.omega(pr.orc.n, 1, seed=52)[:, 0]
+    V, lam, nu, kap = ogn.build_precond_nystrom_adaptive(pr.orc, pr.otraj, ogn.split_blocks(Om, ell0, ell_hat), v, eps)
+    pc, info = pr.gpu.build_precond_adaptive(pr.traj, ell0, ell_hat, ell_max, eps_sk=eps, omega=to_dev(Om),
+                                             vtest=to_dev(v), method=rp4d.NYSTROM)
+    assert info["ell"] == len(lam) and info["nkappa"] == len(kap)
+    assert np.allclose(info["kappa"], kap, rtol=1e-9)
+    glam, gnu = pc.info()
+    assert gnu == pytest.approx(nu, rel=1e-12)
+    assert np.max(np.abs(np.array(glam) - lam)) <= 1e-10 * lam[0]
+    R = _probe(pr.orc.n)
+    assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
+
+
+def test_adaptive_nystrom_device_draws_stop_at_tolerance():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL, seed=9)
+    c0 = pr.gpu.counters()
+    pc, info = pr.gpu.build_precond_adaptive(pr.traj, 4, 4, 64, eps_sk=1.05, seed=123, method=rp4d.NYSTROM)
+    c1 = pr.gpu.counters()
+    k = info["kappa"]
+    assert k[-1] <= 1.05 or info["ell"] + 4 > 64
+    assert all(x > 1.05 for x in k[:-1])
+    assert c1["tlm_offline"] - c0["tlm_offline"] == info["ell"] + info["nkappa"]
+    b = to_dev(_probe(pr.orc.n, 1, seed=9)[:, 0])
+    _, i0 = pr.gpu.pcg_solve(pr.traj, b, None, rtol=1e-10)
+    _, i1 = pr.gpu.pcg_solve(pr.traj, b, pc, rtol=1e-10)
+    assert i1["iters"] < i0["iters"]
+
+
+def test_gn_step_adaptive_nystrom_parity():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    Om = inputs.omega(pr.orc.n, 40, seed=910)
+    vh = inputs.omega(pr.orc.n, 1, seed=911)[:, 0]
+    st = pr.gpu.gn_state()
+    info = pr.gpu.gn_step(st, sketch=rp4d.NYSTROM_ADAPTIVE, ell=8, ell_hat=8, ell_max=40, eps_sk=1.01,
+                          omega=to_dev(Om), vhat=to_dev(vh), rtol=1e-12)
+    _, x = st.get()
+    _, _, x1, oinf = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method='nystrom_adaptive', Omega=Om, vhat=vh,
+                                 rtol=1e-12, adaptive=dict(ell0=8, ell_hat=8, eps_sk=1.01))
+    assert relerr(to_np(x), x1) <= 1e-10
+    assert info["sketch_ell"] == oinf["precond"][0].shape[1]
+    assert abs(info["pcg_iters"] - oinf["pcg"]["iters"]) <= 1
