@@ -312,6 +312,8 @@ typedef struct {
                                floor((ell1_max - ell1) / ell1_hat) (<= m): ell2, then ell2_hat per extension */
     const double* vtest;    /* device (n) test vector (normalised here), or NULL */
     int serial;             /* 1: every sweep on the problem stream */
+    int qr_update;          /* 1: keep the thin QR of M = Psi^T Q_Y by the update of Alg. 6 (needs
+                               ell1_max + ell2_hat <= max(n, m)); 0: refactor M every round */
 } rp4d_sv_adaptive_opts;
 int rp4d_build_precond_singleview_adaptive(rp4d_problem* p, const rp4d_traj* traj, const rp4d_sv_adaptive_opts* opts,
                                            rp4d_precond** out, rp4d_adaptive_info* info);

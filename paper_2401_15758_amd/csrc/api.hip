@@ -1195,9 +1195,11 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
 // One Cholesky-QR pass on Y (rows x l, FP64, in s.Yd): G = Y^T Y + shift I = L L^T,
 // Y <- Y L^{-T}.  Returns the Cholesky info (0 = success; Y untouched otherwise).
 // With Rinv (l x l) the pass's R^{-1} = L^{-T} is accumulated: Rinv <- L^{-T}
-// on the first pass, Rinv <- Rinv L^{-T} after it, so that Q = Y_in Rinv.
+// on the first pass, Rinv <- Rinv L^{-T} after it, so that Q = Y_in Rinv; with
+// Rout (l x l) the factor itself: Rout <- L^T, then Rout <- L^T Rout, so that
+// Y_in = Q Rout.
 int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift, double* Rinv = nullptr,
-                bool first = true) {
+                bool first = true, double* Rout = nullptr) {
     hipStream_t st = stream_of(p);
     launch_gram<double, double>(s.Yd, l, s.Yd, l, rows, l, l, s.S2, s.gw, st);
     if (shift > 0) {
@@ -1221,17 +1223,25 @@ int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift, doub
         launch_small_gemm(Rinv, 0, s.S4, 0, s.S3, l, 1.0, st);
         launch_relayout<double, double>(s.S3, 1, Rinv, 1, l * l, 1, st);
     }
+    if (Rout && first) {
+        transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S2, Rout, l);  // L^T
+        RP4D_HIP(hipGetLastError());
+    } else if (Rout) {
+        launch_small_gemm(s.S2, 1, Rout, 0, s.S3, l, 1.0, st);  // L^T Rout
+        launch_relayout<double, double>(s.S3, 1, Rout, 1, l * l, 1, st);
+    }
     return 0;
 }
 
 // Thin QR of Y (rows x l) by CholeskyQR2; if the Gram matrix is numerically
 // indefinite, shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto,
 // Yanagisawa 2020): one pass with shift 11 (rows l + l(l+1)) u ||Y||_2^2, then two
-// plain passes.  Q overwrites s.Yd; Rinv (nullable, l x l) receives R^{-1}.
-void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s, double* Rinv = nullptr) {
+// plain passes.  Q overwrites s.Yd; Rinv (nullable, l x l) receives R^{-1} and
+// Rout (nullable, l x l) receives R.
+void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s, double* Rinv = nullptr, double* Rout = nullptr) {
     hipStream_t st = stream_of(p);
-    if (cholqr_pass(p, rows, l, s, 0.0, Rinv, true) == 0) {
-        RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD,
+    if (cholqr_pass(p, rows, l, s, 0.0, Rinv, true, Rout) == 0) {
+        RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false, Rout) == 0, RP4D_ENOTSPD,
                      "sketch: Cholesky QR second pass failed");
         return;
     }
@@ -1243,10 +1253,12 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s, double* Rinv = nullpt
     double ymax2 = 0.0;
     copy_host(p, &ymax2, s.lam, sizeof(double));
     const double sh = 11.0 * (static_cast<double>(rows) * l + l * (l + 1.0)) * std::ldexp(1.0, -53) * ymax2;
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, std::max(sh, 1e-300), Rinv, true) == 0, RP4D_ENOTSPD,
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, std::max(sh, 1e-300), Rinv, true, Rout) == 0, RP4D_ENOTSPD,
                  "sketch: shifted Cholesky QR failed");
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD, "sketch: Cholesky QR pass failed");
-    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false) == 0, RP4D_ENOTSPD, "sketch: Cholesky QR pass failed");
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false, Rout) == 0, RP4D_ENOTSPD,
+                 "sketch: Cholesky QR pass failed");
+    RP4D_REQUIRE(cholqr_pass(p, rows, l, s, 0.0, Rinv, false, Rout) == 0, RP4D_ENOTSPD,
+                 "sketch: Cholesky QR pass failed");
 }
 
 void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc) {
@@ -1838,6 +1850,55 @@ void check_sv_adaptive_opts(const rp4d_problem* p, rp4d_sv_adaptive_opts& o) {
     RP4D_REQUIRE(sv_adaptive_l2max(o) <= p->m, RP4D_EINVAL,
                  "adaptive SingleView: the largest co-range sketch exceeds the number of observations");
     RP4D_REQUIRE(o.eps_sk > 0 && std::isfinite(o.eps_sk), RP4D_EINVAL, "adaptive sketch: eps_sk must be positive");
+    RP4D_REQUIRE(!o.qr_update || o.ell1_max + o.ell2_hat <= std::max(p->n, p->m), RP4D_EINVAL,
+                 "adaptive SingleView: the QR update needs ell1_max + ell2_hat <= max(n, m)");
+}
+
+// Thin QR of M = Psi^T Q_Y kept across the rounds of the adaptive SingleView.
+// The first round factors M by Cholesky QR2.  Later rounds follow Alg. 6 with
+// A1 = Psi^T, A2 = Psi_hat^T, B1 = Q_Y (c1o old columns), B2 = Q_hat (b1 new
+// columns) and Q1 R1 = A1 B1 the previous factors.  Its first two thin QRs are
+// taken together, as the thin QR of [R1; A2 B1]: Alg. 6 first factors
+// A2 B1 = Q2 R2, which changes the Q factor of the stack by diag(I, Q2) only,
+// and A2 B1 is wider than tall whenever b2 < c1o.  Then Q3 = diag(Q1, I) Q3',
+// P1 = [A1; A2] B2, P2 = P1 - Q3 (Q3^T P1) = Q4 R4, Q5 = [Q3 Q4] and
+// R5 = [R3, Q3^T P1; 0, R4].  Q_M (c2 x c1) and R_M (c1 x c1) stay in Qm, Rm
+// with leading size L1; R4 and P1 are scratch.
+void sv_qr_update(rp4d_problem* p, Scratch& s, int m, int c1o, int c2o, int b1, int b2, int L1, int L2,
+                  const double* Pa, const double* Ph, const double* Qa, double* X, double* Qm, double* Rm,
+                  double* Qt, double* Tt, double* Rs, double* R4, double* P1, double* gwk) {
+    hipStream_t st = stream_of(p);
+    const int c1 = c1o + b1, c2 = c2o + b2;
+    if (c1o == 0) {
+        launch_gram<double, double>(Pa, L2, Qa, L1, m, c2, c1, X, gwk, st);     // M (c2 x c1)
+        launch_relayout<double, double>(X, 1, s.Yd, 1, c2 * c1, 1, st);
+        cholqr2(p, c2, c1, s, nullptr, Rs);
+        launch_relayout<double, double>(s.Yd, c1, Qm, L1, c2, c1, st);
+        launch_relayout<double, double>(Rs, c1, Rm, L1, c1, c1, st);
+        return;
+    }
+    // [R1; A2 B1] ((c1o + b2) x c1o) = Q3' R3
+    launch_gram<double, double>(Ph, b2, Qa, L1, m, b2, c1o, X, gwk, st);         // A2 B1 (b2 x c1o)
+    launch_relayout<double, double>(Rm, L1, s.Yd, c1o, c1o, c1o, st);
+    launch_relayout<double, double>(X, c1o, s.Yd + static_cast<size_t>(c1o) * c1o, c1o, b2, c1o, st);
+    cholqr2(p, c1o + b2, c1o, s, nullptr, Rs);                                    // s.Yd = Q3', Rs = R3
+    // Q3 = diag(Q1, I) Q3' (c2 x c1o)
+    launch_tsmm<double, double>(Qm, L1, s.Yd, nullptr, c2o, c1o, c1o, 1.0, nullptr, 0, 0.0, Qt, L1, st);
+    launch_relayout<double, double>(s.Yd + static_cast<size_t>(c1o) * c1o, c1o, Qt + static_cast<size_t>(c2o) * L1,
+                                    L1, b2, c1o, st);
+    // P1 = [A1; A2] B2 (c2 x b1), T = Q3^T P1, P2 = P1 - Q3 T = Q4 R4
+    launch_gram<double, double>(Pa, L2, Qa + c1o, L1, m, c2, b1, P1, gwk, st);
+    launch_gram<double, double>(Qt, L1, P1, b1, c2, c1o, b1, Tt, gwk, st);
+    launch_tsmm<double, double>(Qt, L1, Tt, nullptr, c2, c1o, b1, -1.0, P1, b1, 1.0, P1, b1, st);
+    launch_relayout<double, double>(P1, 1, s.Yd, 1, c2 * b1, 1, st);
+    cholqr2(p, c2, b1, s, nullptr, R4);                                           // s.Yd = Q4
+    // Q5 = [Q3 Q4], R5 = [R3, T; 0, R4]
+    launch_relayout<double, double>(Qt, L1, Qm, L1, c2, c1o, st);
+    launch_relayout<double, double>(s.Yd, b1, Qm + c1o, L1, c2, b1, st);
+    launch_fill<double>(Rm + static_cast<size_t>(c1o) * L1, static_cast<size_t>(b1) * L1, 0.0, st);
+    launch_relayout<double, double>(Rs, c1o, Rm, L1, c1o, c1o, st);
+    launch_relayout<double, double>(Tt, b1, Rm + c1o, L1, c1o, b1, st);
+    launch_relayout<double, double>(R4, b1, Rm + static_cast<size_t>(c1o) * L1 + c1o, L1, b1, b1, st);
 }
 
 // Adaptive SingleView (Sec. 3.1.2, Alg. 5) into pc.  Each round draws
@@ -1861,7 +1922,7 @@ void build_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_
     const size_t mL1 = static_cast<size_t>(m) * L1, nL1 = static_cast<size_t>(n) * L1;
     const size_t mL2 = static_cast<size_t>(m) * L2, nL2 = static_cast<size_t>(n) * L2;
     const size_t mB2 = static_cast<size_t>(m) * B2, nB2 = static_cast<size_t>(n) * B2;
-    p->ws_ad.ensure((mL1 + mL2 + nL2 + mB2 + nB2 + 2 * l21 + 4 * ll + nL1 + 3 * static_cast<size_t>(n) + 1024 +
+    p->ws_ad.ensure((mL1 + mL2 + nL2 + mB2 + nB2 + 4 * l21 + 7 * ll + nL1 + 3 * static_cast<size_t>(n) + 1024 +
                      4 * static_cast<size_t>(L1) + gw + 64) * sizeof(double));
     double* Qa = p->ws_ad.as<double>();  // m x L1: Q_Y
     double* Pa = Qa + mL1;               // m x L2: Psi
@@ -1884,6 +1945,12 @@ void build_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_
     kw.zv = kw.tv + L1;
     kw.gw = kw.zv + 2 * L1;
     s.gw = kw.gw;
+    // QR update (Alg. 6) state: Q_M (L2 x L1) and R_M (L1 x L1), leading size L1
+    double* Qm = kw.gw + gw + 64;
+    double* Rm = Qm + l21;
+    double* Qt = Rm + ll;                // L2 x L1: Q3
+    double* Tt = Qt + l21;               // L1 x L1: Q3^T P1
+    double* Rs = Tt + ll;                // L1 x L1: R from Cholesky QR
     kappa_test_vector(p, o.vtest, adaptive_vseed(o.seed), kw);
     const bool lane = !o.serial && p->bve == nullptr;
     int c1 = 0, c2 = 0, r = 0, nk = 0;
@@ -1924,12 +1991,22 @@ void build_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_
         p->cnt.tlm_offline += b1;
         p->cnt.adj_offline += b2;
         // M = Psi^T Q_Y = Q_M R_M (c2 x c1), P = Q_M R_M^{-T}
-        launch_gram<double, double>(Pa, L2, Qa, L1, m, c2, c1, Mb, kw.gw, st);
-        launch_relayout<double, double>(Mb, 1, s.Yd, 1, c2 * c1, 1, st);
-        cholqr2(p, c2, c1, s, Rinv);
-        transpose_small<<<nblk(static_cast<long>(c1) * c1), 256, 0, st>>>(Rinv, s.S4, c1);
-        RP4D_HIP(hipGetLastError());
-        launch_tsmm<double, double>(s.Yd, c1, s.S4, nullptr, c2, c1, c1, 1.0, nullptr, 0, 0.0, P, c1, st);
+        if (!o.qr_update) {
+            launch_gram<double, double>(Pa, L2, Qa, L1, m, c2, c1, Mb, kw.gw, st);
+            launch_relayout<double, double>(Mb, 1, s.Yd, 1, c2 * c1, 1, st);
+            cholqr2(p, c2, c1, s, Rinv);
+            transpose_small<<<nblk(static_cast<long>(c1) * c1), 256, 0, st>>>(Rinv, s.S4, c1);
+            RP4D_HIP(hipGetLastError());
+            launch_tsmm<double, double>(s.Yd, c1, s.S4, nullptr, c2, c1, c1, 1.0, nullptr, 0, 0.0, P, c1, st);
+        } else {
+            sv_qr_update(p, s, m, c1 - b1, c2 - b2, b1, b2, L1, L2, Pa, Ph, Qa, Mb, Qm, Rm, Qt, Tt, Rs, Rinv, P, kw.gw);
+            // P = Q_M R_M^{-T}: R_M^T is lower triangular and its inverse is R_M^{-T}
+            launch_relayout<double, double>(Rm, L1, Rs, c1, c1, c1, st);
+            transpose_small<<<nblk(static_cast<long>(c1) * c1), 256, 0, st>>>(Rs, s.S2, c1);
+            RP4D_HIP(hipGetLastError());
+            launch_trinv(s.S2, s.S4, c1, st);
+            launch_tsmm<double, double>(Qm, L1, s.S4, nullptr, c2, c1, c1, 1.0, nullptr, 0, 0.0, P, c1, st);
+        }
         if (lane) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
         // W^T = Z Q_M R_M^{-T} (n x c1)
         launch_tsmm<double, double>(Za, L2, P, nullptr, n, c2, c1, 1.0, nullptr, 0, 0.0, Wt, L1, st);

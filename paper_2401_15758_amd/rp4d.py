@@ -83,7 +83,7 @@ class SvAdaptiveOpts(ctypes.Structure):
     _fields_ = [("ell1", ctypes.c_int), ("ell2", ctypes.c_int), ("ell1_hat", ctypes.c_int),
                 ("ell2_hat", ctypes.c_int), ("ell1_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("omega", ctypes.c_void_p), ("psi", ctypes.c_void_p),
-                ("vtest", ctypes.c_void_p), ("serial", ctypes.c_int)]
+                ("vtest", ctypes.c_void_p), ("serial", ctypes.c_int), ("qr_update", ctypes.c_int)]
 
 
 def sv_adaptive_sizes(m, ell1, ell1_hat, ell1_max, ell2=0, ell2_hat=0):
@@ -381,7 +381,7 @@ class Problem:
         return Precond(self, h, ell1)
 
     def build_precond_singleview_adaptive(self, traj, ell1, ell1_hat, ell1_max, eps_sk=1.01, ell2=0, ell2_hat=0,
-                                          seed=0, omega=None, psi=None, vtest=None, serial=False):
+                                          seed=0, omega=None, psi=None, vtest=None, serial=False, qr_update=False):
         """Adaptive SingleView; omega (n, ell1_max), psi (m, l2_max) and vtest (n)
         are optional device tensors (l2_max from sv_adaptive_sizes).  Returns
         (Precond, {"ell", "ell2", "kappa": [...], "kappa_sk", "nkappa"})."""
@@ -391,7 +391,7 @@ class Problem:
                            omega=_ptr(omega, torch.float64, self.n * ell1_max, "omega") if omega is not None else None,
                            psi=_ptr(psi, torch.float64, self.m * l2max, "psi") if psi is not None else None,
                            vtest=_ptr(vtest, torch.float64, self.n, "vtest") if vtest is not None else None,
-                           serial=1 if serial else 0)
+                           serial=1 if serial else 0, qr_update=1 if qr_update else 0)
         h = ctypes.c_void_p()
         info = AdaptiveInfo()
         _check(_lib.rp4d_build_precond_singleview_adaptive(self._h, traj._h, ctypes.byref(o), ctypes.byref(h),

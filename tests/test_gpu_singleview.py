@@ -173,6 +173,32 @@ def test_adaptive_singleview_parity(small, l1, l2, l1h, l2h, l1max, eps):
     assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
 
 
+@pytest.mark.parametrize("l1,l2,l1h,l2h,l1max", [(8, 17, 8, 16, 40), (6, 13, 5, 10, 36), (12, 25, 4, 8, 32)])
+def test_adaptive_singleview_qr_update_parity(small, l1, l2, l1h, l2h, l1max):
+    """With the QR update of Alg. 6 (wide A2 B1 when l2_hat < l1) the device
+    matches the oracle's Alg. 6 run (qr='update'), which equals refactoring M."""
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    _, _, l2max = rp4d.sv_adaptive_sizes(pr.orc.m, l1, l1h, l1max, l2, l2h)
+    Om, Psi = _draws(pr, l1max, l2max, seed=2700 + l1)
+    v = inputs.omega(pr.orc.n, 1, seed=53)[:, 0]
+    m = pr.orc.m
+    A = lambda X: pr.orc.A(pr.otraj, X).reshape(m, -1)
+    AT = lambda W: pr.orc.AT(pr.otraj, W.reshape(pr.orc.n_t, pr.orc.n_obs, -1))
+    H = lambda X: pr.orc.misfit_hessian(pr.otraj, X)
+    V, lam, kap = osk.singleview_adaptive(A, AT, H, ogn.split_blocks(Om, l1, l1h), ogn.split_blocks(Psi, l2, l2h),
+                                          v, 0.5, qr='update')
+    pc, info = pr.gpu.build_precond_singleview_adaptive(pr.traj, l1, l1h, l1max, eps_sk=0.5, ell2=l2, ell2_hat=l2h,
+                                                        omega=to_dev(Om), psi=to_dev(Psi), vtest=to_dev(v),
+                                                        qr_update=True)
+    assert info["ell"] == len(lam) == l1max - (l1max - l1) % l1h and info["nkappa"] == len(kap)
+    assert np.allclose(info["kappa"], kap, rtol=1e-9)
+    glam, _ = pc.info()
+    assert np.max(np.abs(np.array(glam) - lam)) <= 1e-10 * lam[0]
+    R = _probe(pr.orc.n)
+    assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
+
+
 def test_adaptive_singleview_streams_are_bitwise_identical(small):
     pr = small
     a, ia = pr.gpu.build_precond_singleview_adaptive(pr.traj, 8, 8, 32, eps_sk=1.0, seed=31)
