@@ -74,8 +74,29 @@ def build_precond(prob, traj, method, Omega, eps=_sketch.EPS64):
     return V, lam
 
 
+ARMIJO_C = 1e-4
+ARMIJO_MAX_TRIALS = 20
+
+
+def armijo(prob, v, J0, g, dv, counters=None):
+    """Backtracking line search on the v-form cost: alpha = 1, 1/2, 1/4, ...
+    until J(v + alpha dv) <= J0 + c alpha g.dv (c = 1e-4), at most 20 trials
+    (the last trial's alpha is taken if none passes).  One FWD per trial.
+    Returns (alpha, trials)."""
+    slope = float(g @ dv)
+    alpha = 1.0
+    for t in range(1, ARMIJO_MAX_TRIALS + 1):
+        J = prob.cost(v + alpha * dv)
+        if counters is not None:
+            counters['fwd'] += 1
+        if J <= J0 + ARMIJO_C * alpha * slope or t == ARMIJO_MAX_TRIALS:
+            return alpha, t
+        alpha *= 0.5
+
+
 def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
-            precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None, solve='pcg'):
+            precond=None, reuse_eps=None, vhat=None, counters=None, adaptive=None, solve='pcg',
+            line_search=False):
     """One GN step from control vector v.
 
     method: 'nystrom' | 'randsvd' | 'randsvd_adaptive' (Alg. 4) | 'nystrom_adaptive' | 'singleview'
@@ -88,6 +109,7 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
     Omega's columns [0, ell0), then ell_hat at a time; vhat is its test vector.
     solve: 'pcg' (SketchPrec, Sec. 3.2.2) or 'sketch' (SketchSolv, Sec. 3.2.1:
     eq. (dxsol) in the v-form, dv = (I + H_hat)^{-1} b by eq. (woodbury)).
+    line_search: take v + alpha dv with alpha from ``armijo`` instead of alpha = 1.
     Returns (v_new, dv, x_new, info)."""
     c = counters if counters is not None else dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
     J, g, traj, x = prob.cost_grad(v)
@@ -142,8 +164,9 @@ def gn_step(prob, v, method='nystrom', Omega=None, rtol=1e-6, maxit=None,
         dv, pinfo = _pcg(lambda p: prob.hessian(traj, p), b, prec=prec, rtol=rtol, maxit=maxit)
     c['tlm_on'] += pinfo['iters']
     c['adj_on'] += pinfo['iters']
-    v_new = v + dv
+    alpha, trials = (armijo(prob, v, J, g, dv, c) if line_search else (1.0, 0))
+    v_new = v + alpha * dv
     x_new = prob.state(v_new)
     info = dict(J=J, gnorm_inf=float(np.max(np.abs(g))), g=g, pcg=pinfo, reused=reused,
-                kappa_re=kre, precond=P, counters=c, x=x)
+                kappa_re=kre, precond=P, counters=c, x=x, alpha=alpha, ls_trials=trials)
     return v_new, dv, x_new, info

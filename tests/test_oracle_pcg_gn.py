@@ -130,3 +130,43 @@ def test_kappa_re_exact_preconditioner_is_one(small_problem, small_dense):
     k2 = gn.kappa_re(p, traj, V, lam, inputs.unit_vector(p.n))
     Pm = sketch.lmp_apply(V, lam, np.eye(p.n))
     assert k2 <= np.linalg.norm((np.eye(p.n) + Hs) @ Pm, 2) * (1 + 1e-10)
+
+
+class _Toy:
+    """cost(v) = 1/2 |v|^2 + 5 sum v^4 (quartic: a full step along -grad overshoots)."""
+
+    @staticmethod
+    def cost(v):
+        return 0.5 * float(v @ v) + 5.0 * float(np.sum(v ** 4))
+
+
+def test_armijo_returns_the_largest_halving_that_passes():
+    from oracle import gn as ogn
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        v = rng.standard_normal(6)
+        g = v + 20.0 * v ** 3
+        dv = -3.0 * g
+        J0 = _Toy.cost(v)
+        alpha, trials = ogn.armijo(_Toy, v, J0, g, dv)
+        ok = lambda a: _Toy.cost(v + a * dv) <= J0 + 1e-4 * a * float(g @ dv)
+        assert ok(alpha)
+        assert alpha == 1.0 or not ok(2.0 * alpha)
+        assert trials == int(round(np.log2(1.0 / alpha))) + 1
+
+
+def test_line_search_on_an_inexact_sketchsolv_step():
+    """SketchSolv with a 2-column sketch on the wall-bounded workload: the full
+    step raises the cost 5.8-fold, half a step still raises it, a quarter step
+    lowers it (margins of 28-40 % of J, so the decision is robust)."""
+    from oracle import gn as ogn
+    from oracle.problem import make_problem
+    cfg = inputs.CFG_WALL_SMALL
+    orc = make_problem(cfg, inputs.draws(cfg, seed=0))
+    Om = inputs.omega(orc.n, 2, seed=1000)
+    c = dict(fwd=0, tlm_on=0, adj_on=0, tlm_off=0, adj_off=0)
+    v1, dv, _, info = ogn.gn_step(orc, np.zeros(orc.n), method='nystrom', Omega=Om, solve='sketch',
+                                  line_search=True, counters=c)
+    assert info['alpha'] == 0.25 and info['ls_trials'] == 3
+    assert np.allclose(v1, 0.25 * dv)
+    assert orc.cost(v1) < info['J'] and c['fwd'] == 1 + 3
