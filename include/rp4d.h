@@ -151,6 +151,9 @@ typedef struct {
     int ell2_hat;           /* adaptive SingleView: co-range columns per extension (0: 2 ell_hat) */
     int solve;              /* RP4D_SOLVE_PCG or RP4D_SOLVE_SKETCH (needs a sketch; no PCG, so
                                pcg_iters = 0, pcg_converged = 1 and pcg_relres = -1) */
+    int line_search;        /* 1: Armijo backtracking on the v-form cost, J(v + a dv) <= J(v) +
+                               1e-4 a g.dv with a = 1, 1/2, ... (at most 20 trials, the last taken
+                               if none passes; one FWD each); 0: a = 1 */
 } rp4d_gn_opts;
 
 typedef struct {
@@ -164,6 +167,8 @@ typedef struct {
     double kappa_re;        /* value of the reuse test, or -1 if not run */
     int sketch_ell;         /* size of the preconditioner in use (0 without one) */
     double kappa_sk;        /* last kappa_sk of an adaptive sketch built in this step, or -1 */
+    double alpha;           /* step length taken */
+    int ls_trials;          /* line-search trials (FWD solves), 0 without a line search */
 } rp4d_gn_info;
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -8,6 +8,8 @@
 #include <cstring>
 #include <string>
 
+#include <limits>
+
 #include "internal.hpp"
 
 namespace rp4d {
@@ -2326,6 +2328,9 @@ int rp4d_build_precond_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr,
     });
 }
 
+constexpr double kArmijoC = 1e-4;
+constexpr int kArmijoTrials = 20;
+
 int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_gn_info* info) {
     return guarded([&] {
         RP4D_REQUIRE(p != nullptr && s != nullptr && o != nullptr && s->p == p, RP4D_EINVAL, "bad argument");
@@ -2457,8 +2462,38 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         inf.pcg_converged = pi.converged;
         inf.pcg_relres = pi.relres;
         inf.sketch_ell = use ? use->ell : 0;
-        // 7. v <- v + dv ; x = x_b + Gamma^{1/2} v
-        launch_axpby(s->dv.as<double>(), 1.0, s->v.as<double>(), 1.0, n, st);
+        // 7. step length: alpha = 1, or Armijo backtracking on the v-form cost
+        // J(v + alpha dv) <= J(v) + c alpha g.dv (c = 1e-4; alpha halved, at
+        // most 20 trials, the last one taken if none passes; a trial whose state
+        // blows up counts as failed).  Each trial is one FWD on the step's
+        // trajectory; b and x serve as the trial v and x.
+        double alpha = 1.0;
+        int trials = 0;
+        if (o->line_search) {
+            double* vt = s->b.as<double>();
+            double* xt = s->x.as<double>();
+            launch_dot(s->g.as<double>(), s->dv.as<double>(), n, sc + SC_T2, red, st);
+            const double slope = read_scalar(p, sc + SC_T2);
+            for (trials = 1;; ++trials) {
+                launch_relayout<double, double>(s->v.as<double>(), 1, vt, 1, n, 1, st);
+                launch_axpby(s->dv.as<double>(), alpha, vt, 1.0, n, st);
+                bhalf_into<double>(p, 1, vt, 1, xt, 1, p->xb.as<double>());
+                double jo = 0.0;
+                const int frc = rp4d_fwd(p, xt, s->traj, &jo);
+                RP4D_REQUIRE(frc == RP4D_OK || frc == RP4D_ENONFINITE, frc, g_last_error);
+                double J = std::numeric_limits<double>::infinity();
+                if (frc == RP4D_OK) {
+                    launch_dot(vt, vt, n, sc + SC_T2, red, st);
+                    J = 0.5 * read_scalar(p, sc + SC_T2) + jo;
+                }
+                if (J <= inf.J + kArmijoC * alpha * slope || trials == kArmijoTrials) break;
+                alpha *= 0.5;
+            }
+        }
+        inf.alpha = alpha;
+        inf.ls_trials = trials;
+        // 8. v <- v + alpha dv ; x = x_b + Gamma^{1/2} v
+        launch_axpby(s->dv.as<double>(), alpha, s->v.as<double>(), 1.0, n, st);
         bhalf_into<double>(p, 1, s->v.as<double>(), 1, s->x.as<double>(), 1, p->xb.as<double>());
         if (info) *info = inf;
         if (pcg_rc != RP4D_OK) fail(pcg_rc, "PCG reached maxit before the tolerance (step applied)");

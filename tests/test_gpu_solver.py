@@ -381,3 +381,31 @@ def test_gn_step_adaptive_nystrom_parity():
     assert relerr(to_np(x), x1) <= 1e-10
     assert info["sketch_ell"] == oinf["precond"][0].shape[1]
     assert abs(info["pcg_iters"] - oinf["pcg"]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("which,ell,solve,alpha,trials", [("wall", 2, "sketch", 0.25, 3),
+                                                         ("periodic", 20, "pcg", 1.0, 1),
+                                                         ("periodic", 2, "sketch", None, None)])
+def test_gn_step_line_search_parity(which, ell, solve, alpha, trials):
+    """Armijo backtracking: the same step length and trial count as the oracle
+    and the same iterate to 1e-10.  The last case (SketchSolv with a 2-column
+    sketch on burgers-128) first tries steps whose trajectories overflow, which
+    count as failed trials on both sides."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    cfg = inputs.CFG_WALL_SMALL if which == "wall" else inputs.CFG_SMALL
+    pr = Pair(cfg, seed=0)
+    Om = inputs.omega(pr.orc.n, ell, seed=1000)
+    _, _, x1, info = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method='nystrom', Omega=Om, rtol=1e-12,
+                                 solve=solve, line_search=True)
+    if alpha is not None:
+        assert info['alpha'] == alpha and info['ls_trials'] == trials
+    st = pr.gpu.gn_state()
+    c0 = pr.gpu.counters()
+    gi = pr.gpu.gn_step(st, sketch=rp4d.NYSTROM, ell=ell, omega=to_dev(Om), rtol=1e-12, line_search=True,
+                        solve=rp4d.SOLVE_SKETCH if solve == "sketch" else rp4d.SOLVE_PCG)
+    c1 = pr.gpu.counters()
+    assert gi['alpha'] == info['alpha'] and gi['ls_trials'] == info['ls_trials']
+    assert c1['fwd'] - c0['fwd'] == 1 + gi['ls_trials']
+    _, gx = st.get()
+    assert relerr(to_np(gx), x1) <= 1e-10
