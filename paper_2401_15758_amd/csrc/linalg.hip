@@ -466,6 +466,49 @@ __global__ void __launch_bounds__(1024) chol_kernel(double* A, int l, int* info)
     if (tid == 0) info[0] = bad;
 }
 
+// X = L^{-1} for orders l <= 64.  Sixteen lanes share a column c (four columns
+// per wave): lane s keeps the entries X(j, c), j = s, s + 16, s + 32, s + 48, in
+// registers.  Row i of the column is -(L(i, c..i-1) . X(c..i-1, c)) / L(i, i):
+// each lane adds its (at most four) terms, the partial sums meet by xor
+// shuffles inside the 16-lane group, and the owning lane keeps the result.
+// The chain per column is l steps of four FMAs and four shuffles, with L read
+// from LDS (broadcast within the group) and its diagonal reciprocals precomputed.
+__global__ void __launch_bounds__(1024) trinv64_kernel(const double* L, double* X, int l) {
+    constexpr int LD = 65;
+    __shared__ double sL[64 * LD];
+    __shared__ double rd[64];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < l * l; e += 1024) sL[(e / l) * LD + e % l] = L[e];
+    __syncthreads();
+    if (tid < l) rd[tid] = 1.0 / sL[tid * LD + tid];
+    __syncthreads();
+    const int c = tid >> 4, s = tid & 15;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < l) {  // whole 16-lane groups are active or not
+        for (int i = c; i < l; ++i) {
+            double part = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = s + 16 * t;
+                if (j >= c && j < i) part = fma(sL[i * LD + j], x[t], part);
+            }
+            part += __shfl_xor(part, 8, 16);
+            part += __shfl_xor(part, 4, 16);
+            part += __shfl_xor(part, 2, 16);
+            part += __shfl_xor(part, 1, 16);
+            const double xi = (i == c) ? rd[i] : -part * rd[i];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (s + 16 * t == i) x[t] = xi;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int j = s + 16 * t;
+        if (c < l && j < l) X[j * l + c] = j >= c ? x[t] : 0.0;
+    }
+}
+
 // X = L^{-1} with L and X both in LDS: thread c forms column c by forward
 // substitution (orders with 2 l^2 doubles within the LDS budget).
 __global__ void __launch_bounds__(256) trinv_lds_kernel(const double* L, double* X, int l) {
@@ -972,6 +1015,11 @@ void launch_chol(double* A, int l, int* info, hipStream_t st) {
 
 void launch_trinv(const double* L, double* Linv, int l, hipStream_t st) {
     RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "trinv: l must be in [1, 128]");
+    if (l <= 64) {
+        trinv64_kernel<<<1, 1024, 0, st>>>(L, Linv, l);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
     const size_t both = 2 * static_cast<size_t>(l) * l * sizeof(double);
     if (lds_fits(reinterpret_cast<const void*>(&trinv_lds_kernel), both)) {
         if (both > 64 * 1024)
