@@ -287,3 +287,28 @@ def test_kernel_timing_counts_launches(small):
     launches = -(-50 // t['steps'])
     assert st['launches'] == launches and sa['launches'] == launches
     assert st['total_ms'] > 0 and st['alg_flops'] == pytest.approx(50 * 128 * (36 * 4 + 48))
+
+
+@pytest.mark.parametrize("k", [301, 4096])
+def test_wide_blocks_match_column_slices(small, k):
+    """Blocks of 301 columns (not a multiple of any vector group) and of the
+    largest accepted 4096 columns: every column equals the oracle's product
+    on sampled columns, and the block equals its own column slices computed as
+    separate smaller blocks (the column grouping does not touch any value)."""
+    torch = need_gpu()
+    pr = small
+    V = _rand((pr.orc.n, k), 7 + k)
+    HV = pr.gpu.hessian_block(pr.traj, to_dev(V))
+    cols = np.random.default_rng(k).choice(k, size=6, replace=False)
+    ref = pr.orc.hessian(pr.otraj, V[:, cols])
+    assert colwise_relerr(to_np(HV)[:, cols], ref) <= TOL_OP
+    lo, hi = 64, min(k, 64 + 37)
+    part = pr.gpu.hessian_block(pr.traj, to_dev(np.ascontiguousarray(V[:, lo:hi])))
+    assert colwise_relerr(to_np(HV)[:, lo:hi], to_np(part)) <= 1e-14
+
+
+def test_block_wider_than_4096_rejected(small):
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    with pytest.raises(rp4d.Rp4dError):
+        small.gpu.hessian_block(small.traj, to_dev(np.zeros((small.orc.n, 4097))))

@@ -409,3 +409,24 @@ def test_gn_step_line_search_parity(which, ell, solve, alpha, trials):
     assert c1['fwd'] - c0['fwd'] == 1 + gi['ls_trials']
     _, gx = st.get()
     assert relerr(to_np(gx), x1) <= 1e-10
+
+
+MED = inputs.burgers_config(512, 100, 4, 10, dt_cfg=1e-3, L_b=0.01, ell=128, name='burgers-512')  # rank(A) > 128
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_sketch_parity_at_the_largest_size(method):
+    """l = 128, the largest sketch (the order-128 Cholesky, triangular inverse
+    and Jacobi kernels, Gram tiles beyond 64 columns) on a 512-point problem
+    with m = 1280 observations."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(MED, seed=2)
+    Om = inputs.omega(pr.orc.n, 128, seed=1128)
+    V, lam = ogn.build_precond(pr.orc, pr.otraj, method, Om)
+    pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM if method == "nystrom" else rp4d.RANDSVD, 128,
+                              omega=to_dev(Om))
+    glam = np.array(pc.info()[0])
+    assert np.max(np.abs(glam - lam)) <= 1e-10 * lam[0]
+    R = _probe(pr.orc.n)
+    assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
