@@ -154,6 +154,12 @@ typedef struct {
     int line_search;        /* 1: Armijo backtracking on the v-form cost, J(v + a dv) <= J(v) +
                                1e-4 a g.dv with a = 1, 1/2, ... (at most 20 trials, the last taken
                                if none passes; one FWD each); 0: a = 1 */
+    int exact_lmp;          /* SketchPrec with RP4D_NYSTROM / RP4D_RANDSVD.  0 (default): PCG applies
+                               the preconditioner in factored form, (I + W^T W)^{-1} = I - F F^T,
+                               F = W^T chol(I + W W^T)^{-T} (eq. (randsvdsv)), with W the RandSVD W
+                               or, for Nystrom, W = B^T of Alg. 2 (H_hat = B B^T keeps the shift nu:
+                               at most nu from eq. (woodbury) in norm); no eigendecomposition is
+                               formed.  1: eq. (woodbury) with Alg. 1/2's V_hat, Lambda_hat. */
 } rp4d_gn_opts;
 
 typedef struct {

@@ -240,6 +240,15 @@ void set_device(const rp4d_ctx* c) {
 
 hipStream_t stream_of(const rp4d_problem* p) { return p->ctx->stream; }
 
+// Destruction waits for all work on the object's device and reads nothing
+// outside the object, so owners and children may be destroyed in any order
+// (a language runtime's finaliser may not respect ownership).
+void quiesce_device(int device) {
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
+}
+
 void sync(const rp4d_problem* p) { RP4D_HIP(hipStreamSynchronize(stream_of(p))); }
 
 double read_scalar(const rp4d_problem* p, const double* dptr) {
@@ -751,7 +760,10 @@ int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out) {
 }
 
 int rp4d_ctx_destroy(rp4d_ctx* ctx) {
-    return guarded([&] { delete ctx; });
+    return guarded([&] {
+        if (ctx) quiesce_device(ctx->device);
+        delete ctx;
+    });
 }
 
 int rp4d_ctx_set_stream(rp4d_ctx* ctx, void* hip_stream) {
@@ -870,10 +882,7 @@ int rp4d_problem_create(rp4d_ctx* ctx, const rp4d_problem_desc* desc, rp4d_probl
 
 int rp4d_problem_destroy(rp4d_problem* p) {
     return guarded([&] {
-        if (p) {
-            set_device(p->ctx);
-            (void)hipStreamSynchronize(p->ctx->stream);
-        }
+        if (p) quiesce_device(p->device);
         delete p;
     });
 }
@@ -926,10 +935,7 @@ int rp4d_traj_create(rp4d_problem* p, rp4d_traj** out) {
 
 int rp4d_traj_destroy(rp4d_traj* t) {
     return guarded([&] {
-        if (t && t->p) {
-            set_device(t->p->ctx);
-            (void)hipStreamSynchronize(t->p->ctx->stream);
-        }
+        if (t) quiesce_device(t->device);
         delete t;
     });
 }
@@ -1134,17 +1140,20 @@ void sketch_misfit_hessian(rp4d_problem* p, const rp4d_traj* tr, int l, int dtyp
     }
 }
 
-void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc);
+void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc, bool fast = false);
+void lmp_factor_fast(rp4d_problem* p, int l, const double* Wt, Scratch& s, rp4d_precond* pc);
 
-void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc) {
+void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc,
+                   bool fast = false) {
     sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
-    nystrom_core(p, l, dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23), s, pc);
+    nystrom_core(p, l, dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23), s, pc, fast);
 }
 
 // Alg. 2 from step 3 on: Omega (n x l) in s.Om and Y = H Omega in s.Yd, both
 // row-major with leading size l; eps is the unit roundoff of the sketch sweeps.
-// Writes pc->V and s.lam, s.D, s.nu.
-void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc) {
+// Writes pc->V and s.lam, s.D, s.nu; with `fast` the factored form of the
+// preconditioner instead (lmp_factor_fast on B, no eigendecomposition).
+void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc, bool fast) {
     hipStream_t st = stream_of(p);
     const int n = p->n;
     // step 3: nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
@@ -1181,6 +1190,10 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
     transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
     RP4D_HIP(hipGetLastError());
     launch_tsmm<double, double>(s.Y2, l, s.S4, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, s.S1, l, st);  // S1 = B
+    if (fast) {
+        lmp_factor_fast(p, l, s.S1, s, pc);
+        return;
+    }
     launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S4, s.gw, st);   // S4 = B^T B
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
@@ -1263,7 +1276,8 @@ void cholqr2(rp4d_problem* p, int rows, int l, Scratch& s, double* Rinv = nullpt
                  "sketch: Cholesky QR pass failed");
 }
 
-void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc) {
+void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc,
+                   bool fast = false) {
     hipStream_t st = stream_of(p);
     const int n = p->n, m = p->m;
     // step 2: Y = A Omega (m x l)
@@ -1284,6 +1298,11 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         adj_impl<float>(p, tr, l, static_cast<const float*>(s.Yt), static_cast<float*>(s.Wt), nullptr);
         launch_relayout<float, double>(static_cast<const float*>(s.Wt), l, s.S1, l, n, l, st);
     }
+    if (fast) {
+        lmp_factor_fast(p, l, s.S1, s, pc);
+        launch_fill<double>(s.nu, 1, 0.0, st);
+        return;
+    }
     // step 5: thin SVD of W via eig(W W^T): V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
     launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S2, s.gw, st);
     {
@@ -1301,6 +1320,29 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
 __global__ void add_identity(double* G, int l) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < l) G[static_cast<size_t>(i) * l + i] += 1.0;
+}
+
+// Factored limited-memory preconditioner of a sketch H_hat = W^T W, W^T (n x l)
+// FP64 row-major: (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W (eq. (randsvdsv))
+// = I - F F^T with F = W^T K^{-T}, I + W W^T = K K^T.  pc->V = F, pc->Dg = 1, so
+// the apply of eq. (woodbury) is unchanged.  I + W W^T has eigenvalues >= 1
+// (its Cholesky factorisation cannot fail on the finite sketches that reach
+// here), and no eigendecomposition is formed.
+void lmp_factor_fast(rp4d_problem* p, int l, const double* Wt, Scratch& s, rp4d_precond* pc) {
+    hipStream_t st = stream_of(p);
+    const int n = p->n;
+    launch_gram<double, double>(Wt, l, Wt, l, n, l, l, s.S4, s.gw, st);     // W W^T
+    add_identity<<<nblk(l), 256, 0, st>>>(s.S4, l);
+    RP4D_HIP(hipGetLastError());
+    launch_chol(s.S4, l, s.info, st);                                        // K
+    launch_trinv(s.S4, s.S3, l, st);                                         // K^{-1}
+    transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S2, l);  // K^{-T}
+    RP4D_HIP(hipGetLastError());
+    pc->V.ensure(static_cast<size_t>(n) * l * sizeof(double));
+    launch_tsmm<double, double>(Wt, l, s.S2, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
+    pc->Dg.ensure(static_cast<size_t>(l) * sizeof(double));
+    launch_fill<double>(pc->Dg.as<double>(), l, 1.0, st);
+    pc->fast = true;
 }
 
 // Seed of the Gaussian block drawn by extension r of the adaptive sketch, and of
@@ -1547,7 +1589,7 @@ void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const do
 // Nystrom core's Cholesky check.  Host copies of the eigenvalues and the shift
 // are fetched on demand (fetch_host).
 void build_precond_into(rp4d_problem* p, const rp4d_traj* tr, int method, int ell, uint64_t seed,
-                        const double* omega, int sketch_dtype, rp4d_precond* pc) {
+                        const double* omega, int sketch_dtype, rp4d_precond* pc, bool fast = false) {
     RP4D_REQUIRE(method == RP4D_NYSTROM || method == RP4D_RANDSVD, RP4D_EINVAL, "unknown sketch method");
     RP4D_REQUIRE(ell >= 1 && ell <= 128 && ell <= p->n, RP4D_EINVAL, "ell must be in [1, min(128, n)]");
     RP4D_REQUIRE(sketch_dtype == RP4D_F64 || sketch_dtype == RP4D_F32, RP4D_EINVAL, "bad sketch dtype");
@@ -1560,23 +1602,26 @@ void build_precond_into(rp4d_problem* p, const rp4d_traj* tr, int method, int el
     pc->p = p;
     pc->ell = ell;
     pc->host_ok = false;
+    pc->fast = false;
     if (method == RP4D_NYSTROM)
-        build_nystrom(p, tr, ell, sketch_dtype, s, pc);
+        build_nystrom(p, tr, ell, sketch_dtype, s, pc, fast);
     else
-        build_randsvd(p, tr, ell, sketch_dtype, s, pc);
+        build_randsvd(p, tr, ell, sketch_dtype, s, pc, fast);
+    p->cnt.tlm_offline += ell;
+    p->cnt.adj_offline += ell;
+    p->cnt.sketches += 1;
+    if (fast) return;
     pc->Dg.ensure(static_cast<size_t>(ell) * sizeof(double));
     launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, ell, 1, st);
     pc->lamd.ensure(static_cast<size_t>(ell + 1) * sizeof(double));
     launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, ell, 1, st);
     launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + ell, 1, 1, 1, st);
-    p->cnt.tlm_offline += ell;
-    p->cnt.adj_offline += ell;
-    p->cnt.sketches += 1;
 }
 
 // Host copies of Lambda_hat and nu (one copy and wait after each build).
 void fetch_host(const rp4d_precond* pc) {
     if (pc->host_ok) return;
+    RP4D_REQUIRE(!pc->fast, RP4D_ESTATE, "factored preconditioner: no eigenvalues were formed");
     std::vector<double> h(static_cast<size_t>(pc->ell) + 1);
     RP4D_HIP(hipMemcpyAsync(h.data(), pc->lamd.p, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                             stream_of(pc->p)));
@@ -1650,10 +1695,7 @@ int rp4d_build_precond_nystrom_adaptive(rp4d_problem* p, const rp4d_traj* tr, co
 
 int rp4d_precond_destroy(rp4d_precond* pc) {
     return guarded([&] {
-        if (pc && pc->p) {
-            set_device(pc->p->ctx);
-            (void)hipStreamSynchronize(pc->p->ctx->stream);
-        }
+        if (pc) quiesce_device(pc->device);
         delete pc;
     });
 }
@@ -2267,6 +2309,7 @@ int rp4d_gn_state_destroy(rp4d_gn_state* s) {
         if (!s) return;
         if (s->pc) rp4d_precond_destroy(s->pc);
         if (s->traj) rp4d_traj_destroy(s->traj);
+        quiesce_device(s->device);
         delete s;
     });
 }
@@ -2411,6 +2454,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 // rebuild in place: the object and its device buffers persist
                 s->pc_live = false;
                 if (!s->pc) s->pc = new rp4d_precond();
+                s->pc->fast = false;
                 if (o->sketch == RP4D_RANDSVD_ADAPTIVE) {
                     rp4d_adaptive_info ai{};
                     build_randsvd_adaptive(p, s->traj, ao, s->pc, &ai);
@@ -2426,7 +2470,11 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                     build_singleview_adaptive(p, s->traj, sao, s->pc, &ai);
                     inf.kappa_sk = ai.kappa_sk;
                 } else {
-                    build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc);
+                    // SketchPrec only needs the operator: the factored form unless the
+                    // eigendecomposition is asked for; SketchSolv keeps Alg. 1/2's form
+                    const bool fast = o->solve == RP4D_SOLVE_PCG && !o->exact_lmp;
+                    build_precond_into(p, s->traj, o->sketch, o->ell, o->seed, o->omega, o->sketch_dtype, s->pc,
+                                       fast);
                 }
                 s->pc_live = true;
                 use = s->pc;
@@ -2631,6 +2679,7 @@ int rp4d_get_sweep_tiling(const rp4d_problem* p, int mode, int dtype, int k, int
 // pinned host ring.
 // ===========================================================================
 struct rp4d_batch {
+    int device = rp4d::construction_device();
     rp4d_ctx* ctx = nullptr;
     std::vector<rp4d_problem*> probs;
     // staging ring: pinned host memory mirrored into device memory
@@ -3410,10 +3459,7 @@ int rp4d_batch_create(rp4d_ctx* ctx, int nprob, rp4d_problem* const* probs, rp4d
 
 int rp4d_batch_destroy(rp4d_batch* b) {
     return guarded([&] {
-        if (b) {
-            set_device(b->ctx);
-            (void)hipStreamSynchronize(b->ctx->stream);
-        }
+        if (b) quiesce_device(b->device);
         delete b;
     });
 }

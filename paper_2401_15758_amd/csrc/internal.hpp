@@ -36,6 +36,15 @@ struct Error {
     } while (0)
 
 // Growable device buffer owned by a library handle.
+// The HIP device current at construction: library objects keep it so that
+// their destruction never reads the object that created them (owners and
+// children may be destroyed in any order).
+inline int construction_device() {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -341,6 +350,7 @@ void bve_hessian(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV,
 }  // namespace rp4d
 
 struct rp4d_problem {
+    int device = rp4d::construction_device();
     rp4d_ctx* ctx = nullptr;
     rp4d_problem_desc d{};
     int n = 0, n_obs = 0, n_t = 0, m = 0, s_last = 0;
@@ -368,6 +378,7 @@ struct rp4d_problem {
 };
 
 struct rp4d_traj {
+    int device = rp4d::construction_device();
     rp4d_problem* p = nullptr;
     rp4d::DevBuf states;  // rows of u_s (every C-th when checkpointing)
     rp4d::DevBuf innov;   // (n_t, n_obs)
@@ -378,11 +389,13 @@ struct rp4d_traj {
 };
 
 struct rp4d_precond {
+    int device = rp4d::construction_device();
     rp4d_problem* p = nullptr;
     int ell = 0;
     rp4d::DevBuf V;       // (n, ell) row-major
-    rp4d::DevBuf Dg;      // lam / (1 + lam)
-    rp4d::DevBuf lamd;    // device: lam (ell), then nu
+    rp4d::DevBuf Dg;      // lam / (1 + lam); all ones in the factored form
+    rp4d::DevBuf lamd;    // device: lam (ell), then nu (not formed in the factored form)
+    bool fast = false;    // factored form V = W^T chol(I + W W^T)^{-T}, no eigenvalues
     // host copies of lamd, fetched on first use after a build
     mutable bool host_ok = false;
     mutable std::vector<double> lam;
@@ -390,6 +403,7 @@ struct rp4d_precond {
 };
 
 struct rp4d_gn_state {
+    int device = rp4d::construction_device();
     rp4d_problem* p = nullptr;
     rp4d::DevBuf v, x, dv, g, b;
     rp4d_traj* traj = nullptr;

@@ -64,7 +64,7 @@ class GnOpts(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("reuse_eps", ctypes.c_double), ("vhat", ctypes.c_void_p),
                 ("ell_hat", ctypes.c_int), ("ell_max", ctypes.c_int), ("eps_sk", ctypes.c_double),
                 ("ell2", ctypes.c_int), ("psi", ctypes.c_void_p), ("ell2_hat", ctypes.c_int),
-                ("solve", ctypes.c_int), ("line_search", ctypes.c_int)]
+                ("solve", ctypes.c_int), ("line_search", ctypes.c_int), ("exact_lmp", ctypes.c_int)]
 
 
 class AdaptiveOpts(ctypes.Structure):
@@ -422,7 +422,7 @@ class Problem:
 
     def gn_step(self, state, sketch=NYSTROM, ell=20, seed=0, omega=None, sketch_dtype=F64, rtol=1e-6, maxit=0,
                 reuse_eps=0.0, vhat=None, raise_noconv=True, ell_hat=0, ell_max=0, eps_sk=0.0, ell2=0, psi=None,
-                ell2_hat=0, solve=SOLVE_PCG, line_search=False):
+                ell2_hat=0, solve=SOLVE_PCG, line_search=False, exact_lmp=False):
         """One GN step; sketch=RANDSVD_ADAPTIVE takes ell as the initial size and
         ell_hat, ell_max, eps_sk (omega then holds ell_max columns; vhat is also
         the test vector of kappa_sk); sketch=SINGLEVIEW takes ell as l1 and
@@ -442,7 +442,8 @@ class Problem:
                    vhat=_ptr(vhat, torch.float64, self.n, "vhat").value if vhat is not None else None,
                    ell_hat=ell_hat, ell_max=ell_max, eps_sk=eps_sk, ell2=ell2,
                    psi=_ptr(psi, torch.float64, self.m * l2, "psi").value if psi is not None else None,
-                   ell2_hat=ell2_hat, solve=solve, line_search=1 if line_search else 0)
+                   ell2_hat=ell2_hat, solve=solve, line_search=1 if line_search else 0,
+                   exact_lmp=1 if exact_lmp else 0)
         info = GnInfo()
         rc = _lib.rp4d_gn_step(self._h, state._h, ctypes.byref(o), ctypes.byref(info))
         if rc != ENOCONV or raise_noconv:

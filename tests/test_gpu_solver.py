@@ -430,3 +430,44 @@ def test_sketch_parity_at_the_largest_size(method):
     assert np.max(np.abs(glam - lam)) <= 1e-10 * lam[0]
     R = _probe(pr.orc.n)
     assert colwise_relerr(to_np(pc.apply(to_dev(R))), osk.lmp_apply(V, lam, R)) <= 1e-10
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_gn_step_exact_and_factored_preconditioners_agree(method):
+    """SketchPrec with the eigen-decomposed preconditioner (exact_lmp) and with
+    the factored form (the default) reach the oracle's step to 1e-10 with the
+    same PCG iteration count."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    Om = inputs.omega(pr.orc.n, 12, seed=1400)
+    _, dv, x1, info = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method=method, Omega=Om, rtol=1e-12)
+    code = rp4d.NYSTROM if method == "nystrom" else rp4d.RANDSVD
+    its = []
+    for exact in (True, False):
+        st = pr.gpu.gn_state()
+        gi = pr.gpu.gn_step(st, sketch=code, ell=12, omega=to_dev(Om), rtol=1e-12, exact_lmp=exact)
+        _, gx = st.get()
+        assert relerr(to_np(st.last_step()), dv) <= TOL_GN
+        assert relerr(to_np(gx), x1) <= TOL_GN
+        its.append(gi['pcg_iters'])
+    # rtol 1e-12 is near the attainable accuracy: the two forms may differ by one iteration
+    assert abs(its[0] - its[1]) <= 1 and abs(its[0] - info['pcg']['iters']) <= 1
+
+
+def test_objects_can_be_destroyed_in_any_order():
+    """Destruction reads nothing outside the object: a context, problem,
+    trajectory, preconditioner and GN state closed owner-first (as a language
+    runtime's finaliser may do at exit) release cleanly."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = Pair(inputs.CFG_SMALL)
+    pc = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 8, seed=3)
+    st = pr.gpu.gn_state()
+    pr.gpu.gn_step(st, sketch=rp4d.NYSTROM, ell=8, seed=4)
+    pr.ctx.close()
+    pr.gpu.close()
+    pr.traj.close()
+    pc.close()
+    st.close()
+    torch.cuda.synchronize()
