@@ -466,46 +466,95 @@ __global__ void __launch_bounds__(1024) chol_kernel(double* A, int l, int* info)
     if (tid == 0) info[0] = bad;
 }
 
-// X = L^{-1} for orders l <= 64.  Sixteen lanes share a column c (four columns
-// per wave): lane s keeps the entries X(j, c), j = s, s + 16, s + 32, s + 48, in
-// registers.  Row i of the column is -(L(i, c..i-1) . X(c..i-1, c)) / L(i, i):
-// each lane adds its (at most four) terms, the partial sums meet by xor
-// shuffles inside the 16-lane group, and the owning lane keeps the result.
-// The chain per column is l steps of four FMAs and four shuffles, with L read
-// from LDS (broadcast within the group) and its diagonal reciprocals precomputed.
-__global__ void __launch_bounds__(1024) trinv64_kernel(const double* L, double* X, int l) {
+// The 64-bit value of `v` held by lane `lane` (uniform), through two 32-bit
+// lane reads.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), lane));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Cholesky factor of the symmetric part of an l x l matrix, l <= 64, on one
+// wave (right-looking).  Lane i keeps row i in registers (zero past l).  Step j
+// reads the pivot a(j, j) from lane j, every lane forms its entry of column j
+// (the pivot's square root on the diagonal, a(i, j) / L(j, j) below it), the
+// column passes through LDS, and each lane updates a(i, c) -= L(i, j) L(c, j)
+// for c > j.  Entries right of a lane's diagonal also receive updates; they are
+// never read and are written out as zeros.  info = first failing column + 1
+// (pivot not positive or not finite), 0 on success.
+__global__ void __launch_bounds__(64) chol64_kernel(double* A, int l, int* info) {
     constexpr int LD = 65;
-    __shared__ double sL[64 * LD];
-    __shared__ double rd[64];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < l * l; e += 1024) sL[(e / l) * LD + e % l] = L[e];
-    __syncthreads();
-    if (tid < l) rd[tid] = 1.0 / sL[tid * LD + tid];
-    __syncthreads();
-    const int c = tid >> 4, s = tid & 15;
-    double x[4] = {0.0, 0.0, 0.0, 0.0};
-    if (c < l) {  // whole 16-lane groups are active or not
-        for (int i = c; i < l; ++i) {
-            double part = 0.0;
+    __shared__ double sA[64 * LD];
+    __shared__ double col[64];
+    const int i = threadIdx.x;
+    const int li = i < l ? i : l - 1;
+    // stage A through LDS: coalesced rows, every load in bounds and unconditional
+    // (so they are all in flight together), entries past l replaced after the read
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int j = s + 16 * t;
-                if (j >= c && j < i) part = fma(sL[i * LD + j], x[t], part);
-            }
-            part += __shfl_xor(part, 8, 16);
-            part += __shfl_xor(part, 4, 16);
-            part += __shfl_xor(part, 2, 16);
-            part += __shfl_xor(part, 1, 16);
-            const double xi = (i == c) ? rd[i] : -part * rd[i];
+    for (int t = 0; t < 64; ++t) sA[t * LD + i] = A[(t < l ? t : l - 1) * l + li];
+    __syncthreads();
+    double a[64];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (s + 16 * t == i) x[t] = xi;
+    for (int c = 0; c < 64; ++c) a[c] = (i < l && c < l) ? 0.5 * (sA[i * LD + c] + sA[c * LD + i]) : 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        if (j >= l || bad) continue;  // uniform: l, and the pivot read from one lane
+        const double djj = readlane_f64(a[j], j);
+        if (!(djj > 0.0) || !isfinite(djj)) {
+            bad = j + 1;
+            continue;
         }
-    }
+        const double d = sqrt(djj);
+        const double lij = (i == j) ? d : a[j] / d;
+        a[j] = lij;
+        col[i] = lij;
+        __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int j = s + 16 * t;
-        if (c < l && j < l) X[j * l + c] = j >= c ? x[t] : 0.0;
+        for (int c = j + 1; c < 64; ++c) a[c] = fma(-lij, col[c], a[c]);
+        __syncthreads();
+    }
+    if (i < l) {
+#pragma unroll
+        for (int c = 0; c < 64; ++c)
+            if (c < l) A[i * l + c] = (c <= i) ? a[c] : 0.0;
+    }
+    if (i == 0) info[0] = bad;
+}
+
+// X = L^{-1} for orders l <= 64 on one wave: lane c forms column c by forward
+// substitution, X(r, c) = -(sum_{k<r} L(r, k) X(k, c)) / L(r, r) for r > c and
+// X(c, c) = 1 / L(c, c), keeping the column in registers (zero above c, so the
+// sum may run over every k < r).  L sits in LDS as 64 x 64; its rows are read at
+// one address across the wave (broadcasts), and the lanes exchange nothing.
+// Four partial sums shorten the dependent chain.
+__global__ void __launch_bounds__(64) trinv64_kernel(const double* L, double* X, int l) {
+    __shared__ __align__(16) double sL[64 * 64];
+    __shared__ double rd[64];
+    const int c = threadIdx.x;
+    const int lc = c < l ? c : l - 1;
+    // coalesced rows, every load in bounds and unconditional (all in flight
+    // together).  Rows and columns past l hold clamped copies: row r < l reads
+    // only k < r, and rows r >= l and lanes c >= l are never written out.
+#pragma unroll
+    for (int r = 0; r < 64; ++r) sL[r * 64 + c] = L[(r < l ? r : l - 1) * l + lc];
+    const double dc = L[lc * l + lc];
+    rd[c] = c < l ? 1.0 / dc : 0.0;
+    __syncthreads();
+    double x[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < r; ++k) s[k & 3] = fma(sL[r * 64 + k], x[k], s[k & 3]);
+        const double sum = (s[0] + s[1]) + (s[2] + s[3]);
+        x[r] = (r == c) ? rd[r] : (r > c ? -sum * rd[r] : 0.0);
+    }
+    if (c < l) {
+#pragma unroll
+        for (int r = 0; r < 64; ++r)
+            if (r < l) X[r * l + c] = x[r];
     }
 }
 
@@ -1009,6 +1058,11 @@ void launch_chol(double* A, int l, int* info, hipStream_t st) {
     if (shmem > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(shmem));
+    if (l <= 64) {
+        chol64_kernel<<<1, 64, 0, st>>>(A, l, info);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
     chol_kernel<<<1, 1024, shmem, st>>>(A, l, info);
     RP4D_HIP(hipGetLastError());
 }
@@ -1016,7 +1070,7 @@ void launch_chol(double* A, int l, int* info, hipStream_t st) {
 void launch_trinv(const double* L, double* Linv, int l, hipStream_t st) {
     RP4D_REQUIRE(l >= 1 && l <= 128, RP4D_EINVAL, "trinv: l must be in [1, 128]");
     if (l <= 64) {
-        trinv64_kernel<<<1, 1024, 0, st>>>(L, Linv, l);
+        trinv64_kernel<<<1, 64, 0, st>>>(L, Linv, l);
         RP4D_HIP(hipGetLastError());
         return;
     }
