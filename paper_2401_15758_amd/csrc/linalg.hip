@@ -864,26 +864,38 @@ __global__ void __launch_bounds__(1024) jacobi64_kernel(const double* A, double*
 }
 
 // Largest eigenvalue of a symmetric PSD l x l matrix G (l <= 64), padded with
-// zeros to 64 x 64 (which adds only zero eigenvalues).  NSQ normalised squarings
+// zeros to 64 x 64 (which adds only zero eigenvalues).  Normalised squarings
 // B <- B^2 / max diag(B^2), each a 64 x 64 x 64 product on FP64 MFMA (one
 // 16 x 16 output block per wave), concentrate B on the top eigenspace; the
 // Rayleigh quotient of G at B's heaviest column is then lambda_max.  Its error
-// is second order in the angle to that eigenspace: at most ~2^-(NSQ+1) relative
-// when the two largest eigenvalues nearly coincide, and rounding otherwise.
+// is second order in the angle to that eigenspace.  After k squarings the
+// components outside it carry weights (lambda_m / lambda_1)^(2^k), which move
+// max diag(B^2) by about that much per squaring; once it changes by at most
+// 1e-12 relative (after at least 6 squarings) one more squaring squares the
+// weights again and the loop stops.  At most 24 squarings: then the error is at
+// most ~2^-25 relative when the two largest eigenvalues nearly coincide, and
+// rounding otherwise.
 constexpr int LMAX_SQUARINGS = 24;
+constexpr int LMAX_MIN_SQUARINGS = 6;
+constexpr double LMAX_STALL_TOL = 1e-12;
 typedef double lmax_v4d __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(1024) lmax_squaring_kernel(const double* __restrict__ G, int l, double* out) {
     constexpr int M = 64, LD = 65;
     __shared__ double S[2][M * LD];
     __shared__ double w[M];
-    __shared__ double scal[2];
+    __shared__ double scal[5];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int e = tid; e < M * M; e += 1024) {
         const int i = e / M, j = e % M;
         S[0][i * LD + j] = (i < l && j < l) ? 0.5 * (G[i * l + j] + G[j * l + i]) : 0.0;
     }
-    if (tid == 0) scal[0] = 1.0;
+    if (tid == 0) {
+        scal[0] = 1.0;
+        scal[2] = -1.0;  // largest diagonal of the previous product
+        scal[3] = 0.0;   // 1: the largest diagonal has stalled
+        scal[4] = 0.0;   // 1: stop after this squaring
+    }
     __syncthreads();
     const int bi = wave >> 2, bj = wave & 3;   // this wave's 16 x 16 output block
     const int fr = lane >> 4, fc = lane & 15;
@@ -906,10 +918,18 @@ __global__ void __launch_bounds__(1024) lmax_squaring_kernel(const double* __res
         if (wave == 0) {
             double d = B2[lane * LD + lane];
             for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o));
-            if (lane == 0) scal[0] = d > 0.0 ? 1.0 / d : 1.0;
+            if (lane == 0) {
+                scal[0] = d > 0.0 ? 1.0 / d : 1.0;
+                if (scal[3] != 0.0)
+                    scal[4] = 1.0;  // the one squaring after the stall is done
+                else if (it + 1 >= LMAX_MIN_SQUARINGS && fabs(d - scal[2]) <= LMAX_STALL_TOL * d)
+                    scal[3] = 1.0;
+                scal[2] = d;
+            }
         }
         __syncthreads();
         cur ^= 1;
+        if (scal[4] != 0.0) break;  // uniform: every thread reads it after the barrier
     }
     // heaviest column of B (largest diagonal entry; lowest index on ties)
     const double* B = S[cur];
