@@ -2147,22 +2147,6 @@ void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, cons
     launch_relayout<double, double>(z, 1, pv, 1, n, 1, st);
     launch_dot(r, z, n, sc + SC_RZ, red, st);
     launch_dot(b, b, n, sc + SC_BB, red, st);
-    double bb = 0.0;
-    if (snap) {
-        RP4D_HIP(hipMemcpyAsync(snap, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-        sync(p);
-        bb = snap[SC_BB];
-    } else {
-        bb = read_scalar(p, sc + SC_BB);
-    }
-    const double bnorm = std::sqrt(bb);
-    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_DD]), RP4D_ENONFINITE,
-                 "non-finite innovations (state blew up or bad input)");
-    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
-    RP4D_REQUIRE(std::isfinite(bnorm), RP4D_ENONFINITE, "non-finite right-hand side");
-    double rnorm = bnorm;
-    int it = 0;
-    bool conv = bnorm == 0.0 || rnorm <= rtol * bnorm;
     // One iteration: q = (I+H)p, alpha, x, r, |r|^2, then speculatively z = P r,
     // beta and the next p (unused once |r| meets the tolerance).  The stream is
     // read at each launch so that the same body can be captured into a graph.
@@ -2183,6 +2167,31 @@ void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, cons
         scal_copy<<<1, 1, 0, s>>>(sc, SC_RZ, SC_RZN);
         RP4D_HIP(hipGetLastError());
     };
+    // The first iteration is enqueued before |b| reaches the host, so that one
+    // wait returns |b|, the first residual and (with snap) the caller's scalars.
+    // With b = 0 its output is discarded: x = 0 after no iteration.
+    body();
+    double hs[SC_COUNT];
+    double* h = snap ? snap : hs;
+    RP4D_HIP(hipMemcpyAsync(h, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(p);
+    const double bnorm = std::sqrt(h[SC_BB]);
+    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_DD]), RP4D_ENONFINITE,
+                 "non-finite innovations (state blew up or bad input)");
+    RP4D_REQUIRE(!snap || std::isfinite(snap[SC_GI]), RP4D_ENONFINITE, "non-finite gradient");
+    RP4D_REQUIRE(std::isfinite(bnorm), RP4D_ENONFINITE, "non-finite right-hand side");
+    double rnorm = bnorm;
+    int it = 0;
+    bool conv = true;
+    if (bnorm == 0.0) {
+        launch_fill<double>(x, n, 0.0, st);
+        p->cnt.hv_columns -= 1;
+    } else {
+        it = 1;
+        rnorm = std::sqrt(h[SC_RR]);
+        RP4D_REQUIRE(std::isfinite(rnorm), RP4D_ENONFINITE, "non-finite PCG residual");
+        conv = rnorm <= rtol * bnorm;
+    }
     // Long solves replay the body as a graph from the third iteration on (the
     // first two run eagerly and size every workspace the body touches).
     GraphExec gx;

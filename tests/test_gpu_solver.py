@@ -190,6 +190,26 @@ def test_pcg_noconv_keeps_iterate(small):
     assert e.value.code == rp4d.ENOCONV
 
 
+def test_pcg_zero_rhs(small):
+    """b = 0: x = 0 after no iteration, whatever x held.  The first iteration,
+    enqueued before |b| is read, is discarded and not counted; the one product
+    counted is pcg_solve's true-residual check."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    pc12 = pr.gpu.build_precond(pr.traj, rp4d.NYSTROM, 12, omega=to_dev(inputs.omega(pr.orc.n, 12)))
+    for pc in (None, pc12):
+        b = torch.zeros(pr.orc.n, dtype=torch.float64, device="cuda")
+        x = torch.full_like(b, float("nan"))
+        before = pr.gpu.counters()
+        x, info = pr.gpu.pcg_solve(pr.traj, b, precond=pc, rtol=1e-10, x=x)
+        after = pr.gpu.counters()
+        assert info['iters'] == 0 and info['converged'] and info['relres'] == 0.0
+        assert torch.count_nonzero(x).item() == 0
+        assert info['true_relres'] == 0.0
+        assert after['hv_columns'] == before['hv_columns'] + 1 and after['tlm_online'] == before['tlm_online']
+
+
 def test_kappa_re_parity(small):
     from paper_2401_15758_amd import rp4d
     pr = small
