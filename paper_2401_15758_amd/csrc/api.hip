@@ -346,23 +346,14 @@ void check_traj(const rp4d_problem* p, const rp4d_traj* tr) {
 
 // Run the nonlinear model over steps [s_from, s_to) starting from state x (n),
 // storing u_s for s % store_every == 0 at store rows s/store_every - store_row0.
-void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* store, int store_every, int store_row0,
-             int store_rows, double* innov, double* obs_out) {
-    const int n = p->n;
-    hipStream_t st = stream_of(p);
-    Tiling t = fwd_tiling(p);
-    p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, 2 * n * sizeof(double) + 64));
-    double* bufA = p->ws_red.as<double>();
-    double* bufB = bufA + n;
-    launch_relayout<double, double>(x, 1, bufA, 1, n, 1, st);
-    double* in = bufA;
-    double* out = bufB;
+FwdArgs fwd_args(const rp4d_problem* p, const Tiling& t, double* store, int store_every, int store_row0,
+                 int store_rows, double* innov, double* obs_out) {
     FwdArgs a{};
     a.store = store;
     a.store_every = store_every;
     a.store_row0 = store_row0;
     a.store_rows = store_rows;
-    a.n = n;
+    a.n = p->n;
     a.h = p->d.dt;
     a.inv2dx = p->inv2dx;
     a.nu_dx2 = p->nu_dx2;
@@ -377,6 +368,21 @@ void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* sto
     a.innov = p->has_data ? innov : nullptr;
     a.obs_out = obs_out;
     a.wall = p->wall ? 1 : 0;
+    return a;
+}
+
+void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* store, int store_every, int store_row0,
+             int store_rows, double* innov, double* obs_out) {
+    const int n = p->n;
+    hipStream_t st = stream_of(p);
+    Tiling t = fwd_tiling(p);
+    p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, 2 * n * sizeof(double) + 64));
+    double* bufA = p->ws_red.as<double>();
+    double* bufB = bufA + n;
+    launch_relayout<double, double>(x, 1, bufA, 1, n, 1, st);
+    double* in = bufA;
+    double* out = bufB;
+    FwdArgs a = fwd_args(p, t, store, store_every, store_row0, store_rows, innov, obs_out);
     SpanTimer span(p->ctx, RP4D_K_FWD);
     for (int s0 = s_from; s0 < s_to; s0 += t.steps) {
         a.s0 = s0;
@@ -388,6 +394,109 @@ void run_fwd(rp4d_problem* p, const double* x, int s_from, int s_to, double* sto
             launch_burgers_fwd(a, t, st);
         }
         std::swap(in, out);
+    }
+}
+
+// The planned FWD (every row stored) over [0, s_last) from x0 into tr, on the
+// current stream; its launches are enqueued by fwd_plan_need / fwd_plan_finish.
+// The ping-pong states and the scratch at 2n.. of ws_red belong to it until it
+// is finished.
+void fwd_plan_start(rp4d_problem* p, const double* x0, rp4d_traj* tr) {
+    RP4D_REQUIRE(tr->C == 1 && !p->bve, RP4D_ESTATE, "planned FWD needs the 1-D model with every row stored");
+    rp4d_ctx* c = p->ctx;
+    FwdPlan& f = p->fwd_plan;
+    const int n = p->n;
+    f.st = stream_of(p);
+    f.t = fwd_tiling(p);
+    p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, (2 * static_cast<size_t>(n) + 1024) * sizeof(double)));
+    f.in = p->ws_red.as<double>();
+    f.out = f.in + n;
+    double* innov = tr->innov.as<double>();
+    f.a = fwd_args(p, f.t, tr->states.as<double>(), 1, 0, tr->rows, innov, innov + p->m);
+    launch_relayout<double, double>(x0, 1, tr->states.as<double>(), 1, n, 1, f.st);  // row 0 = x0
+    launch_relayout<double, double>(x0, 1, f.in, 1, n, 1, f.st);
+    f.span = nullptr;
+    if (c->timing && !c->capturing) {
+        f.span = pooled_event(c);
+        if (f.span == nullptr) RP4D_HIP(hipErrorOutOfMemory);
+        RP4D_HIP(hipEventRecord(f.span, f.st));
+    }
+    f.tr = tr;
+    f.s_next = 0;
+    f.s_to = p->s_last;
+    f.enq_row = 0;
+    f.marked_row = -1;
+    f.waited_row = -1;
+    f.waited_st = nullptr;
+    f.launches = 0;
+    f.next_ev = 0;
+    f.last_ev = nullptr;
+    f.active = true;
+    tr->valid = true;
+    tr->has_innov = p->has_data;
+    p->cnt.fwd += 1;
+}
+
+// Enqueue planned FWD launches until rows 0..row are covered, then mark the
+// point with an event on the FWD's stream.
+void fwd_plan_enqueue(rp4d_problem* p, int row) {
+    FwdPlan& f = p->fwd_plan;
+    while (f.s_next < f.s_to && f.enq_row < row) {
+        f.a.s0 = f.s_next;
+        f.a.S = std::min(f.t.steps, f.s_to - f.s_next);
+        f.a.xin = f.in;
+        f.a.xout = f.out;
+        launch_burgers_fwd(f.a, f.t, f.st);
+        f.launches += 1;
+        f.s_next += f.a.S;
+        f.enq_row = f.s_next;
+        std::swap(f.in, f.out);
+    }
+    if (f.marked_row >= f.enq_row) return;
+    if (f.next_ev == static_cast<int>(f.ev.size())) {
+        hipEvent_t e = nullptr;
+        RP4D_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        f.ev.push_back(e);
+    }
+    f.last_ev = f.ev[f.next_ev++];  // one event per mark within a plan
+    RP4D_HIP(hipEventRecord(f.last_ev, f.st));
+    f.marked_row = f.enq_row;
+}
+
+// A sweep on stream st is about to read rows 0..row of tr: if tr is being
+// produced by the planned FWD, enqueue it far enough and make st wait.  Each
+// mark runs FWD_PLAN_AHEAD launches past the rows asked for, so that the next
+// sweep launches find their rows marked already: fewer events and waits to
+// enqueue, and the host stays ahead of the device.
+constexpr int FWD_PLAN_AHEAD = 3;
+
+void fwd_plan_need(rp4d_problem* p, const rp4d_traj* tr, int row, hipStream_t st) {
+    FwdPlan& f = p->fwd_plan;
+    if (!f.active || f.tr != tr) return;
+    row = std::min(row, f.s_to);
+    if (f.marked_row < row) fwd_plan_enqueue(p, row + FWD_PLAN_AHEAD * f.t.steps);
+    if (st == f.st) return;
+    if (f.waited_st != st) {
+        f.waited_st = st;
+        f.waited_row = -1;
+    }
+    if (f.waited_row >= row) return;
+    RP4D_HIP(hipStreamWaitEvent(st, f.last_ev, 0));
+    f.waited_row = f.marked_row;
+}
+
+// Enqueue the rest of the planned FWD (on its stream) and close its timing span.
+void fwd_plan_finish(rp4d_problem* p) {
+    FwdPlan& f = p->fwd_plan;
+    if (!f.active) return;
+    fwd_plan_enqueue(p, f.s_to);
+    if (f.span) {
+        rp4d_ctx* c = p->ctx;
+        hipStream_t keep = c->stream;
+        c->stream = f.st;
+        close_pair(c, RP4D_K_FWD, f.span, FL_FWD * f.s_to * static_cast<double>(p->n), f.launches);
+        c->stream = keep;
+        f.span = nullptr;
     }
 }
 
@@ -438,6 +547,7 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
             a.S = std::min(t.steps, seg1 - s0);
             a.xin = in;
             a.xout = out;
+            if (C == 1) fwd_plan_need(p, tr, s0 + a.S - 1, st);  // the launch reads u_s0 .. u_{s0+S-1}
             {
                 KernelTimer kt(p->ctx, k == 1 ? RP4D_K_TLM1 : RP4D_K_TLM,
                                static_cast<double>(a.S) * n * (FL_TLM_VEC * k + FL_TLM_BASE));
@@ -445,6 +555,11 @@ void run_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* bu
             }
             std::swap(in, out);
         }
+    }
+    if (p->after_tlm && st != p->ctx->side) {
+        auto f = std::move(p->after_tlm);
+        p->after_tlm = nullptr;
+        f();
     }
 }
 
@@ -454,6 +569,7 @@ T* run_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const Tiling& t, T* buf0
     const int n = p->n;
     hipStream_t st = stream_of(p);
     const int groups = (k + t.kc - 1) / t.kc;
+    fwd_plan_need(p, tr, p->s_last, st);  // the backward sweep starts at the last row
     launch_fill<T>(buf0, static_cast<size_t>(groups) * t.kc * n, T(0), st);
     SweepArgs<T> a{};
     a.n = n;
@@ -618,6 +734,22 @@ void check_common(const rp4d_problem* p, int k, const void* a, const void* b) {
     RP4D_REQUIRE(p != nullptr, RP4D_EINVAL, "null problem");
     RP4D_REQUIRE(k >= 1 && k <= 4096, RP4D_EINVAL, "k must be in [1, 4096]");
     RP4D_REQUIRE(a != nullptr && b != nullptr, RP4D_EINVAL, "null buffer");
+}
+
+void fwd_impl(rp4d_problem* p, const double* x0, rp4d_traj* tr) {
+    hipStream_t st = stream_of(p);
+    double* rows = tr->states.as<double>();
+    double* innov = tr->innov.as<double>();
+    double* obs = innov + p->m;
+    if (p->bve) {
+        bve_fwd(p, x0, tr, innov, obs);
+    } else {
+        launch_relayout<double, double>(x0, 1, rows, 1, p->n, 1, st);  // row 0 = x0
+        run_fwd(p, x0, 0, p->s_last, rows, tr->C, 0, tr->rows, innov, obs);
+    }
+    tr->valid = true;
+    tr->has_innov = p->has_data;
+    p->cnt.fwd += 1;
 }
 
 }  // namespace
@@ -945,18 +1077,8 @@ int rp4d_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* J_obs) {
         RP4D_REQUIRE(p != nullptr && x0 != nullptr && tr != nullptr && tr->p == p, RP4D_EINVAL, "bad argument");
         set_device(p->ctx);
         hipStream_t st = stream_of(p);
-        double* rows = tr->states.as<double>();
         double* innov = tr->innov.as<double>();
-        double* obs = innov + p->m;
-        if (p->bve) {
-            bve_fwd(p, x0, tr, innov, obs);
-        } else {
-            launch_relayout<double, double>(x0, 1, rows, 1, p->n, 1, st);  // row 0 = x0
-            run_fwd(p, x0, 0, p->s_last, rows, tr->C, 0, tr->rows, innov, obs);
-        }
-        tr->valid = true;
-        tr->has_innov = p->has_data;
-        p->cnt.fwd += 1;
+        fwd_impl(p, x0, tr);
         if (J_obs != nullptr) {
             RP4D_REQUIRE(p->has_data, RP4D_ESTATE, "J requested but data not set");
             double* sc = p->ws_scal.as<double>();
@@ -1774,6 +1896,35 @@ void on_side_lane(rp4d_problem* p, F&& f) {
     RP4D_HIP(hipEventRecord(c->ev_join, c->side));
 }
 
+// Enqueue `f` on the side stream after the work already there (no wait on the
+// main stream), with the side workspaces swapped in; ev_join marks its end.
+template <typename F>
+void continue_on_side(rp4d_problem* p, F&& f) {
+    rp4d_ctx* c = p->ctx;
+    RP4D_REQUIRE(c->side != nullptr, RP4D_ESTATE, "no side stream to continue on");
+    hipStream_t main = c->stream;
+    auto swap_all = [p]() {
+        p->ws_s0.swap(p->side_s0);
+        p->ws_s1.swap(p->side_s1);
+        p->ws_obs.swap(p->side_obs);
+        p->ws_bh.swap(p->side_bh);
+        p->ws_seg.swap(p->side_seg);
+        p->ws_red.swap(p->side_red);
+    };
+    swap_all();
+    c->stream = c->side;
+    try {
+        f();
+    } catch (...) {
+        c->stream = main;
+        swap_all();
+        throw;
+    }
+    c->stream = main;
+    swap_all();
+    RP4D_HIP(hipEventRecord(c->ev_join, c->side));
+}
+
 inline uint64_t singleview_psi_seed(uint64_t seed) { return seed ^ 0x2545F4914F6CDD1DULL; }
 
 void check_singleview_opts(const rp4d_problem* p, rp4d_singleview_opts& o) {
@@ -2415,12 +2566,6 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         rp4d::DevBuf& vecs = pcg_buf(p);
         vecs.ensure(5 * static_cast<size_t>(n) * sizeof(double) + 1024 * sizeof(double));
         double* red = vecs.as<double>() + 5 * static_cast<size_t>(n);
-        // 1. FWD at x; |d|^2 and |v|^2 stay on the device until the join below
-        int rc = rp4d_fwd(p, s->x.as<double>(), s->traj, nullptr);
-        RP4D_REQUIRE(rc == RP4D_OK, rc, g_last_error);
-        RP4D_REQUIRE(s->traj->has_innov, RP4D_ESTATE, "data not set");
-        launch_dot(s->traj->innov.as<double>(), s->traj->innov.as<double>(), p->m, sc + SC_DD, red, st);
-        launch_dot(s->v.as<double>(), s->v.as<double>(), n, sc + SC_VV, red, st);
         // 2-3. gradient g = v + A^T d and b = -g.  The 1-D model runs them on the
         // side stream with the side workspaces, overlapping the sketch below.
         const bool overlap = p->bve == nullptr;
@@ -2432,10 +2577,54 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
             launch_fill<double>(s->b.as<double>(), n, 0.0, gs);
             launch_axpby(s->g.as<double>(), -1.0, s->b.as<double>(), 0.0, n, gs);
         };
-        if (overlap) {
-            on_side_lane(p, gradient);
+        // 1. FWD at x; |d|^2 and |v|^2 stay on the device until the join below.
+        // With a Nystrom or RandSVD sketch on the 1-D model (every row stored)
+        // the FWD runs on the side stream and the sketch's TLM sweep on the main
+        // stream follows it: the TLM's host loop enqueues the FWD launches one
+        // step ahead of its own and waits for their rows by events, so the two
+        // overlap on the device; the ADJ sweep waits for the last row.  The
+        // dot products of the cost and the gradient follow the FWD on the side
+        // stream, enqueued once the TLM has been.
+        const bool pipelined = overlap && s->traj->C == 1 &&
+                               (o->sketch == RP4D_NYSTROM || o->sketch == RP4D_RANDSVD ||
+                                o->sketch == RP4D_NYSTROM_ADAPTIVE || o->sketch == RP4D_RANDSVD_ADAPTIVE);
+        struct PipeGuard {  // on any exit: no pending hook or plan, and the main stream after the side's work
+            rp4d_problem* p;
+            bool on = false;
+            ~PipeGuard() {
+                if (!on) return;
+                p->after_tlm = nullptr;
+                FwdPlan& f = p->fwd_plan;
+                if (f.active && f.s_next < f.s_to) const_cast<rp4d_traj*>(f.tr)->valid = false;  // left unfinished
+                f.active = false;
+                (void)hipStreamWaitEvent(p->ctx->stream, p->ctx->ev_join, 0);
+            }
+        } guard{p};
+        if (pipelined) {
+            on_side_lane(p, [&]() { fwd_plan_start(p, s->x.as<double>(), s->traj); });
+            guard.on = true;
+            RP4D_REQUIRE(s->traj->has_innov, RP4D_ESTATE, "data not set");
+            p->after_tlm = [&]() {
+                continue_on_side(p, [&]() {
+                    hipStream_t fs = stream_of(p);
+                    fwd_plan_finish(p);
+                    double* fred = p->ws_red.as<double>() + 2 * static_cast<size_t>(n);  // sized by the plan
+                    launch_dot(s->traj->innov.as<double>(), s->traj->innov.as<double>(), p->m, sc + SC_DD, fred, fs);
+                    launch_dot(s->v.as<double>(), s->v.as<double>(), n, sc + SC_VV, fred, fs);
+                    gradient();
+                });
+            };
         } else {
-            gradient();
+            int rc = rp4d_fwd(p, s->x.as<double>(), s->traj, nullptr);
+            RP4D_REQUIRE(rc == RP4D_OK, rc, g_last_error);
+            RP4D_REQUIRE(s->traj->has_innov, RP4D_ESTATE, "data not set");
+            launch_dot(s->traj->innov.as<double>(), s->traj->innov.as<double>(), p->m, sc + SC_DD, red, st);
+            launch_dot(s->v.as<double>(), s->v.as<double>(), n, sc + SC_VV, red, st);
+            if (overlap) {
+                on_side_lane(p, gradient);
+            } else {
+                gradient();
+            }
         }
         p->cnt.adj_online += 1;
         rp4d_gn_info inf{};
@@ -2491,7 +2680,14 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
             }
         }
         // join the gradient; J and |g|_inf arrive with PCG's first scalar read
+        if (p->after_tlm) {  // no TLM sweep ran on the main stream
+            auto f = std::move(p->after_tlm);
+            p->after_tlm = nullptr;
+            f();
+        }
         if (overlap) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
+        p->fwd_plan.active = false;
+        guard.on = false;
         double sch[SC_COUNT];
         // 6. direction: PCG (SketchPrec) or one application of eq. (woodbury)
         // (SketchSolv, eq. (dxsol) in the v-form: dv = (I + H_hat)^{-1} b)

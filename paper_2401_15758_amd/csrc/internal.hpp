@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -349,9 +350,43 @@ template <typename T>
 void bve_hessian(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV, bool add_identity);
 }  // namespace rp4d
 
+// A FWD whose launches are enqueued on another stream on demand, just ahead of
+// the sweeps that read its rows: the GN step runs its FWD on the side stream
+// while the sketch's TLM sweep follows on the main stream, and enqueueing the two
+// launch by launch lets them overlap on the device.  Every row is stored (C = 1).
+struct FwdPlan {
+    bool active = false;
+    const rp4d_traj* tr = nullptr;
+    rp4d::FwdArgs a{};
+    rp4d::Tiling t{};
+    hipStream_t st = nullptr;       // the stream the FWD runs on
+    double* in = nullptr;           // ping-pong states
+    double* out = nullptr;
+    int s_next = 0, s_to = 0;       // next step to enqueue, end of the window
+    int enq_row = 0;                // rows 0..enq_row are enqueued
+    int marked_row = 0;             // rows 0..marked_row precede the last event
+    int waited_row = -1;            // rows the consumer stream has waited for
+    hipStream_t waited_st = nullptr;
+    int launches = 0;
+    hipEvent_t span = nullptr;      // timing: start of the FWD (pooled event)
+    std::vector<hipEvent_t> ev;     // one per mark; reused by the next plan
+    int next_ev = 0;
+    hipEvent_t last_ev = nullptr;
+    FwdPlan() = default;
+    FwdPlan(const FwdPlan&) = delete;
+    FwdPlan& operator=(const FwdPlan&) = delete;
+    ~FwdPlan() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 struct rp4d_problem {
     int device = rp4d::construction_device();
     rp4d_ctx* ctx = nullptr;
+    // work to enqueue on the side stream once the next TLM sweep on the main
+    // stream has been enqueued (set by a GN step; run at most once)
+    std::function<void()> after_tlm;
+    FwdPlan fwd_plan;
     rp4d_problem_desc d{};
     int n = 0, n_obs = 0, n_t = 0, m = 0, s_last = 0;
     double dx = 0, inv2dx = 0, nu_dx2 = 0;
@@ -387,6 +422,7 @@ struct rp4d_traj {
     int rows = 0;
     bool valid = false, has_innov = false;
 };
+
 
 struct rp4d_precond {
     int device = rp4d::construction_device();

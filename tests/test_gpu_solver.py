@@ -491,3 +491,39 @@ def test_objects_can_be_destroyed_in_any_order():
     pc.close()
     st.close()
     torch.cuda.synchronize()
+
+
+def test_pipelined_gn_steps_match_sequential():
+    """burgers-4096: with every row stored, a Nystrom or RandSVD GN step runs its
+    FWD on the side stream and the sketch's TLM sweep follows it launch by launch;
+    with checkpointing (ckpt_every = 10) the two run one after the other.  The
+    checkpointed trajectory is bitwise the stored one, so the iterates of three
+    Nystrom steps (and one RandSVD step) agree bit for bit -- also with the FWD
+    cut into two-step launches, which makes the TLM wait on many more events."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    cfg = inputs.CFG_LARGE
+    d = inputs.draws(cfg, seed=0)
+    ctx = rp4d.Context(0)
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+    def run(ckpt, sketch, steps, short_fwd=False):
+        prob = rp4d.Problem(ctx, cfg, ckpt_every=ckpt)
+        xb, y = prob.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
+        prob.set_data(xb, y.reshape(-1))
+        if short_fwd:
+            prob.set_sweep_tiling(mode=rp4d.MODE_FWD, ppt=2, threads=64, tile=96, steps=2, xch=rp4d.XCH_WAVE)
+        st = prob.gn_state()
+        infos = [prob.gn_step(st, sketch=sketch, ell=64, seed=500 + i, rtol=1e-8) for i in range(steps)]
+        v, x = st.get()
+        torch.cuda.synchronize()
+        return [(i["J"], i["pcg_iters"], i["gnorm_inf"]) for i in infos], v.clone(), x.clone()
+
+    for sketch, steps in ((rp4d.NYSTROM, 3), (rp4d.RANDSVD, 1)):
+        ref = run(10, sketch, steps)
+        for short in (False, True):
+            got = run(0, sketch, steps, short_fwd=short)
+            assert got[0] == ref[0], (sketch, short)
+            assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2]), (sketch, short)
