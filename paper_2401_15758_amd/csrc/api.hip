@@ -464,17 +464,18 @@ void fwd_plan_enqueue(rp4d_problem* p, int row) {
 }
 
 // A sweep on stream st is about to read rows 0..row of tr: if tr is being
-// produced by the planned FWD, enqueue it far enough and make st wait.  Each
-// mark runs FWD_PLAN_AHEAD launches past the rows asked for, so that the next
+// produced by the planned FWD, enqueue it far enough and make st wait.  The
+// first mark covers one FWD launch past the rows asked for (the sweep starts
+// early); later marks run FWD_PLAN_AHEAD launches past them, so that the next
 // sweep launches find their rows marked already: fewer events and waits to
 // enqueue, and the host stays ahead of the device.
-constexpr int FWD_PLAN_AHEAD = 3;
+constexpr int FWD_PLAN_AHEAD = 5;
 
 void fwd_plan_need(rp4d_problem* p, const rp4d_traj* tr, int row, hipStream_t st) {
     FwdPlan& f = p->fwd_plan;
     if (!f.active || f.tr != tr) return;
     row = std::min(row, f.s_to);
-    if (f.marked_row < row) fwd_plan_enqueue(p, row + FWD_PLAN_AHEAD * f.t.steps);
+    if (f.marked_row < row) fwd_plan_enqueue(p, row + (f.marked_row < 0 ? 1 : FWD_PLAN_AHEAD) * f.t.steps);
     if (st == f.st) return;
     if (f.waited_st != st) {
         f.waited_st = st;
