@@ -2596,7 +2596,7 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 if (!on) return;
                 p->after_tlm = nullptr;
                 FwdPlan& f = p->fwd_plan;
-                if (f.active && f.s_next < f.s_to) const_cast<rp4d_traj*>(f.tr)->valid = false;  // left unfinished
+                if (f.active && f.s_next < f.s_to) f.tr->valid = false;  // left unfinished
                 f.active = false;
                 (void)hipStreamWaitEvent(p->ctx->stream, p->ctx->ev_join, 0);
             }

@@ -356,7 +356,7 @@ void bve_hessian(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV,
 // launch by launch lets them overlap on the device.  Every row is stored (C = 1).
 struct FwdPlan {
     bool active = false;
-    const rp4d_traj* tr = nullptr;
+    rp4d_traj* tr = nullptr;
     rp4d::FwdArgs a{};
     rp4d::Tiling t{};
     hipStream_t st = nullptr;       // the stream the FWD runs on
