@@ -1861,6 +1861,16 @@ int rp4d_precond_apply(const rp4d_precond* pc, int k, const double* R, double* Z
 namespace rp4d {
 namespace {
 
+// Exchange the problem's sweep workspaces with their side-stream copies.
+void swap_side_workspaces(rp4d_problem* p) {
+    p->ws_s0.swap(p->side_s0);
+    p->ws_s1.swap(p->side_s1);
+    p->ws_obs.swap(p->side_obs);
+    p->ws_bh.swap(p->side_bh);
+    p->ws_seg.swap(p->side_seg);
+    p->ws_red.swap(p->side_red);
+}
+
 // Enqueue the work `f` on the context's side stream after everything already on
 // the main stream, with the problem's side workspaces swapped in (the kernels
 // capture the buffer addresses at launch); ev_join marks its completion.
@@ -1875,14 +1885,7 @@ void on_side_lane(rp4d_problem* p, F&& f) {
     hipStream_t main = c->stream;
     RP4D_HIP(hipEventRecord(c->ev_fork, main));
     RP4D_HIP(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    auto swap_all = [p]() {
-        p->ws_s0.swap(p->side_s0);
-        p->ws_s1.swap(p->side_s1);
-        p->ws_obs.swap(p->side_obs);
-        p->ws_bh.swap(p->side_bh);
-        p->ws_seg.swap(p->side_seg);
-        p->ws_red.swap(p->side_red);
-    };
+    auto swap_all = [p]() { swap_side_workspaces(p); };
     swap_all();
     c->stream = c->side;
     try {
@@ -1904,14 +1907,7 @@ void continue_on_side(rp4d_problem* p, F&& f) {
     rp4d_ctx* c = p->ctx;
     RP4D_REQUIRE(c->side != nullptr, RP4D_ESTATE, "no side stream to continue on");
     hipStream_t main = c->stream;
-    auto swap_all = [p]() {
-        p->ws_s0.swap(p->side_s0);
-        p->ws_s1.swap(p->side_s1);
-        p->ws_obs.swap(p->side_obs);
-        p->ws_bh.swap(p->side_bh);
-        p->ws_seg.swap(p->side_seg);
-        p->ws_red.swap(p->side_red);
-    };
+    auto swap_all = [p]() { swap_side_workspaces(p); };
     swap_all();
     c->stream = c->side;
     try {
