@@ -428,12 +428,10 @@ def main():
     # SketchPrec with SingleView (Alg. 3): l1 = ell TLM columns and l2 = 2 l1 + 1
     # ADJ columns (the paper's pairing), the ADJ block on a second stream beside
     # the TLM block or both on one stream; RandSVD / Nystrom builds of the same
-    # l for comparison.  The l2-column sweeps take the l-column tiling (more
-    # column groups of the same tile shape).
+    # l for comparison.  The l2-column sweeps have tilings of their own (tuned
+    # on the device unless cached).
     l2 = 2 * ell + 1
-    tk = tilings[f"k{ell}-f64"]
-    for mode, name in ((rp4d.MODE_TLM, "tlm"), (rp4d.MODE_ADJ, "adj")):
-        prob.set_sweep_tiling(rp4d.F64, l2, mode=mode, **{f: tk[name].get(f, 0) for f in autotune.FIELDS})
+    autotune.tune_or_load(prob, traj, cfg["nsteps"], l2, rp4d.F64, budget_s=args.tune_budget, cache_path=cache_path)
 
     def build_ms(fn, reps=5):
         fn()

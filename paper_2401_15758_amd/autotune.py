@@ -62,7 +62,7 @@ def candidates(n, k, dtype=rp4d.F64, min_groups_tiles=32):
 
 # (ppt, kc) pairs with a wave-region kernel instance
 WAVE_PK = ((1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (8, 1))
-WAVE_STEPS = (2, 3, 4, 6, 8, 12, 16, 25, 32, 50)
+WAVE_STEPS = (2, 3, 4, 6, 8, 10, 12, 13, 14, 15, 16, 20, 25, 32, 50)
 
 
 def wave_candidates(n, pk):
