@@ -359,6 +359,10 @@ int rp4d_gn_state_last_step(const rp4d_gn_state* s, double* dv);
 
 /* One GN step (Sec. 2.2 / 3.2): FWD at x, gradient, optional kappa_re reuse test
  * of the resident preconditioner, sketch, PCG, v <- v + dv, x <- x_b + Gamma^{1/2} v.
+ * On the 1-D model part of the work runs on a second stream of the context (the
+ * gradient; with a Nystrom or RandSVD sketch and every trajectory row stored, the
+ * FWD too, launch by launch ahead of the sketch's TLM sweep); it is joined back to
+ * the context stream before the PCG, so the step stays ordered on that stream.
  * Returns RP4D_ENOCONV if PCG hit maxit (the step is still applied). */
 int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* opts, rp4d_gn_info* info);
 
