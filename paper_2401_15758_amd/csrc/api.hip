@@ -2593,6 +2593,8 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 p->after_tlm = nullptr;
                 FwdPlan& f = p->fwd_plan;
                 if (f.active && f.s_next < f.s_to) f.tr->valid = false;  // left unfinished
+                if (f.span) p->ctx->event_pool.push_back(f.span);       // timing span never closed
+                f.span = nullptr;
                 f.active = false;
                 (void)hipStreamWaitEvent(p->ctx->stream, p->ctx->ev_join, 0);
             }
