@@ -2577,9 +2577,9 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
         // 1. FWD at x; |d|^2 and |v|^2 stay on the device until the join below.
         // With a Nystrom or RandSVD sketch on the 1-D model (every row stored)
         // the FWD runs on the side stream and the sketch's TLM sweep on the main
-        // stream follows it: the TLM's host loop enqueues the FWD launches one
-        // step ahead of its own and waits for their rows by events, so the two
-        // overlap on the device; the ADJ sweep waits for the last row.  The
+        // stream follows it: the TLM's host loop enqueues the FWD launches a few
+        // launches ahead of its own and waits for their rows by events, so the
+        // two overlap on the device; the ADJ sweep waits for the last row.  The
         // dot products of the cost and the gradient follow the FWD on the side
         // stream, enqueued once the TLM has been.
         const bool pipelined = overlap && s->traj->C == 1 &&
