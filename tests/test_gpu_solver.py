@@ -499,7 +499,8 @@ def test_pipelined_gn_steps_match_sequential():
     with checkpointing (ckpt_every = 10) the two run one after the other.  The
     checkpointed trajectory is bitwise the stored one, so the iterates of three
     Nystrom steps (and one RandSVD step) agree bit for bit -- also with the FWD
-    cut into two-step launches, which makes the TLM wait on many more events."""
+    cut into two-step launches, which makes the TLM wait on many more events, and
+    with the committed tuned tilings."""
     torch = need_gpu()
     from paper_2401_15758_amd import rp4d
     cfg = inputs.CFG_LARGE
@@ -509,10 +510,14 @@ def test_pipelined_gn_steps_match_sequential():
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
-    def run(ckpt, sketch, steps, short_fwd=False):
+    def run(ckpt, sketch, steps, short_fwd=False, tuned=False):
         prob = rp4d.Problem(ctx, cfg, ckpt_every=ckpt)
         xb, y = prob.synthesize(dev(d["x_true"]), dev(d["xi"]), dev(d["eta"].reshape(-1)))
         prob.set_data(xb, y.reshape(-1))
+        if tuned:  # the committed tilings (sweeps and FWD with different steps per launch)
+            from paper_2401_15758_amd import autotune
+            for k in (64, 1):
+                autotune.apply_cached(prob, cfg["nsteps"], k)
         if short_fwd:
             prob.set_sweep_tiling(mode=rp4d.MODE_FWD, ppt=2, threads=64, tile=96, steps=2, xch=rp4d.XCH_WAVE)
         st = prob.gn_state()
@@ -523,7 +528,7 @@ def test_pipelined_gn_steps_match_sequential():
 
     for sketch, steps in ((rp4d.NYSTROM, 3), (rp4d.RANDSVD, 1)):
         ref = run(10, sketch, steps)
-        for short in (False, True):
-            got = run(0, sketch, steps, short_fwd=short)
-            assert got[0] == ref[0], (sketch, short)
-            assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2]), (sketch, short)
+        for short, tuned in ((False, False), (True, False), (False, True)):
+            got = run(0, sketch, steps, short_fwd=short, tuned=tuned)
+            assert got[0] == ref[0], (sketch, short, tuned)
+            assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2]), (sketch, short, tuned)
