@@ -469,7 +469,7 @@ void fwd_plan_enqueue(rp4d_problem* p, int row) {
 // early); later marks run FWD_PLAN_AHEAD launches past them, so that the next
 // sweep launches find their rows marked already: fewer events and waits to
 // enqueue, and the host stays ahead of the device.
-constexpr int FWD_PLAN_AHEAD = 5;
+constexpr int FWD_PLAN_AHEAD = 3;
 
 void fwd_plan_need(rp4d_problem* p, const rp4d_traj* tr, int row, hipStream_t st) {
     FwdPlan& f = p->fwd_plan;
