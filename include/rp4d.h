@@ -370,8 +370,16 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* opts, rp
 int rp4d_counters_get(const rp4d_problem* p, rp4d_counters* out);
 int rp4d_counters_reset(rp4d_problem* p);
 
-/* Fill `count` doubles with standard normals from Philox4x32-10 (Salmon et al.
- * 2011) + Box-Muller: element i uses counter (i/4 pairs) under key `seed`. */
+/* Fill `count` doubles (device buffer `out`) with standard normals from
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11: ten rounds, multipliers
+ * 0xD2511F53 / 0xCD9E8D57, key bumps 0x9E3779B9 / 0xBB67AE85) and Box-Muller.
+ * Pair q = i / 2 of the output uses the counter (q mod 2^32, q >> 32, 0, 0)
+ * under the key (seed mod 2^32, seed >> 32); of its output words (x0..x3),
+ * a = ((x0 << 21) ^ (x1 >> 11)) mod 2^53 and b = ((x2 << 21) ^ (x3 >> 11)) mod 2^53
+ * give u1 = (a + 1) 2^-53 in (0, 1] and u2 = b 2^-53, and the pair is
+ * (r cos(2 pi u2), r sin(2 pi u2)) with r = sqrt(-2 ln u1); an odd count drops
+ * the last sine.  Every random draw of the library (Omega, Psi, test vectors)
+ * comes from this generator.  Stream-ordered; EINVAL on null arguments. */
 int rp4d_philox_normal(rp4d_ctx* ctx, uint64_t seed, size_t count, double* out);
 
 /* Problem synthesis (Sec. 5.1 'Data and Background'), all device buffers:

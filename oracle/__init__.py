@@ -27,6 +27,9 @@ sketch    RandSVD (Alg. 1), Nystrom (Alg. 2), Woodbury LMP (eq. (woodbury)),
 pcg       preconditioned CG on (I + H) dx = b (Sec. 2.2.2, eq. (pcgsystem))
 gn        one Gauss-Newton step and the reuse test kappa_re (eq. (condtext2))
 analysis  intrinsic dimension, Psi_H bound, condition numbers (Sec. 4)
+rng       the library's counter-based Gaussian stream (Philox4x32-10 +
+          Box-Muller), written from its published definition, so that the
+          oracle can reproduce draws the library makes on the device
 
 Parity unpinned: none of the functions above is unpinned; see tests/test_oracle_*.
 """

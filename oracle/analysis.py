@@ -3,7 +3,7 @@
 Test infrastructure only (see ``oracle/__init__``).
 
   * intrinsic dimension id_r = sum_{j>r} lambda_j / lambda_{r+1}   Sec. 4.2
-  * Psi_H(r, p) = (1 + r/(p-1) id_r) lambda_{r+1}                   Thm. (RandSVD)
+  * Psi_H(r, p) = lambda_{r+1} + r/(p-1) sum_{j>r} lambda_j         Thm. (RandSVD)
   * kappa_2 of (I + H_hat)^{-1/2}(I + H)(I + H_hat)^{-1/2}          Thm. (bound_loew)
   * Theta_H(r) = 4 (sum_{j>r} lambda_1 lambda_j)^{1/2} + 4 sum_{j>r} lambda_j
                                                                     Thm. (SingleView)
@@ -17,8 +17,11 @@ def intrinsic_dimension(lam, r):
 
 
 def psi_bound(lam, r, p):
+    """Psi_H(r, p) = lambda_{r+1} + r/(p-1) sum_{j>r} lambda_j, the form of the
+    definition that stays finite when lambda_{r+1} = 0 (the equal form
+    (1 + r/(p-1) id_r) lambda_{r+1} is then 0/0)."""
     lam = np.sort(np.asarray(lam, dtype=np.float64))[::-1]
-    return float((1.0 + r / (p - 1.0) * intrinsic_dimension(lam, r)) * lam[r])
+    return float(lam[r] + r / (p - 1.0) * np.sum(lam[r:]))
 
 
 def _sym_power(M, power):

@@ -3,8 +3,10 @@ limited-memory preconditioner they define.
 
 Test infrastructure only (see ``oracle/__init__``).
 
-  * RandSVD      Sec. 3.1.1, Alg. 1 (randsvd)
-  * Nystrom      Sec. 3.1.1, Alg. 2 (nystrom), Tropp et al. fixed-rank Nystrom
+  * RandSVD      Sec. 3.1.1, Alg. 1 (randsvd): H = A^T A approximated by the
+                 projection A^T Q Q^T A onto the range of A Omega
+  * Nystrom      Sec. 3.1.1, Alg. 2 (nystrom): the shifted Nystrom approximant
+                 (H Omega)(Omega^T H Omega)^{-1}(H Omega)^T (Tropp et al.)
   * LMP          eq. (woodbury): (I + V L V^T)^{-1} = I - V (L^{-1} + I)^{-1} V^T
   * W-form       Remark 1, eq. (randsvdsv): (I + W^T W)^{-1} = I - W^T (I + W W^T)^{-1} W
   * adaptive     Sec. 3.1.2, Alg. 4 (randsvd_adaptive) with the test kappa_sk of
@@ -32,62 +34,81 @@ class NotSPDError(RuntimeError):
 
 
 def nystrom(H_apply, Omega, eps=EPS64, max_retries=3):
-    """Alg. 2: returns (V_hat (n x l), lambda_hat (l,), nu)."""
+    """Nystrom approximation of H from the sketch H Omega (Sec. 3.1.1, Alg. 2):
+    returns (V_hat (n x l), lambda_hat (l,), nu)."""
     Omega = np.asarray(Omega, dtype=np.float64)
-    return nystrom_from_sketch(Omega, H_apply(Omega), eps, max_retries)   # step 2: Y = H Omega
+    return nystrom_from_sketch(Omega, H_apply(Omega), eps, max_retries)
 
 
 def nystrom_from_sketch(Omega, Y0, eps=EPS64, max_retries=3):
-    """Alg. 2 from step 3 on, given the sketch Y0 = H Omega."""
+    """Nystrom approximation given the sketch Y0 = H Omega.
+
+    The approximant is built for the shifted operator H + nu I, whose sketch is
+    Y0 + nu Omega, and the shift is removed from its eigenvalues afterwards:
+
+        H_nu_hat = Y_nu (Omega^T Y_nu)^{-1} Y_nu^T,   Y_nu = Y0 + nu Omega,
+        nu = sqrt(n) eps ||Y0||_2.
+
+    With the Cholesky factor C_nu = L L^T of the (symmetrised) core
+    C_nu = Omega^T Y_nu, H_nu_hat = B B^T for B = Y_nu L^{-T}; the thin SVD
+    B = V Sigma U^T gives the eigenpairs (V, Sigma^2) of H_nu_hat, and the
+    approximation of H keeps V with lambda = max(0, Sigma^2 - nu).  A core that
+    is not numerically positive definite is retried with the shift multiplied
+    by 10, at most ``max_retries`` times."""
     Omega = np.asarray(Omega, dtype=np.float64)
     n, ell = Omega.shape
-    nu = np.sqrt(n) * eps * np.linalg.norm(Y0, 2)         # step 3
+    nu = np.sqrt(n) * eps * np.linalg.norm(Y0, 2)
     for _ in range(max_retries + 1):
-        Y = Y0 + nu * Omega                               # step 4
-        C = Omega.T @ Y                                   # step 5
+        Y = Y0 + nu * Omega
+        C = Omega.T @ Y
         try:
             L = np.linalg.cholesky(0.5 * (C + C.T))
         except np.linalg.LinAlgError:
             nu *= 10.0
             continue
-        W = solve_triangular(L, Y.T, lower=True)          # step 6: W = L^{-1} Y^T
-        _, S, Vt = np.linalg.svd(W, full_matrices=False)  # step 7: thin SVD
-        lam = np.maximum(0.0, S * S - nu)                 # return Lambda = max(0, S^2 - nu)
+        Bt = solve_triangular(L, Y.T, lower=True)         # B^T = L^{-1} Y_nu^T
+        _, S, Vt = np.linalg.svd(Bt, full_matrices=False)
+        lam = np.maximum(0.0, S * S - nu)
         return Vt.T.copy(), lam, nu
     raise NotSPDError("Nystrom core matrix not positive definite after shift retries")
 
 
 def randsvd(A_apply, AT_apply, Omega):
-    """Alg. 1: Y = A Omega, Y = QR, W^T = A^T Q, thin SVD of W, Lambda = Sigma^2.
-    A_apply maps (n, l) -> (m, l); AT_apply maps (m, l) -> (n, l)."""
+    """Randomized SVD of A, hence eigendecomposition of H = A^T A (Sec. 3.1.1,
+    Alg. 1): with Q an orthonormal basis of range(A Omega), H is approximated
+    by A^T Q Q^T A = W^T W for W = Q^T A, whose thin SVD W = U Sigma V^T gives
+    H_hat = V Sigma^2 V^T.  A_apply maps (n, l) -> (m, l); AT_apply maps
+    (m, l) -> (n, l).  Returns (V_hat, lambda_hat)."""
     Omega = np.asarray(Omega, dtype=np.float64)
-    Y = A_apply(Omega)                                    # step 2
-    Q, _ = np.linalg.qr(Y)                                # step 3 (Householder)
-    Wt = AT_apply(Q)                                      # step 4: W^T = A^T Q
-    _, S, Vt = np.linalg.svd(Wt.T, full_matrices=False)   # step 5
+    Q, _ = np.linalg.qr(A_apply(Omega))                   # Householder thin QR
+    Wt = AT_apply(Q)                                      # W^T = A^T Q
+    _, S, Vt = np.linalg.svd(Wt.T, full_matrices=False)
     return Vt.T.copy(), S * S
 
 
 def randsvd_W(A_apply, AT_apply, Omega):
-    """Alg. 1 steps 1-4 only: returns W (l x n) with H_hat = W^T W (Remark 1)."""
+    """The factor W = Q^T A (l x n) of the randomized SVD, H_hat = W^T W, without
+    its SVD (the form used by Remark 1)."""
     Y = A_apply(np.asarray(Omega, dtype=np.float64))
     Q, _ = np.linalg.qr(Y)
     return AT_apply(Q).T.copy()
 
 
 def singleview(A_apply, AT_apply, Omega, Psi):
-    """Alg. 3: Y = A Omega (m x l1) and Z = A^T Psi (n x l2) are independent
-    sketches; Y = Q_Y R_Y; M = Psi^T Q_Y = Q_M R_M; W = R_M^+ (Z Q_M)^T and its
-    thin SVD W = U S V^T give H_hat = V diag(S^2) V^T.  Thin QRs by Householder,
-    R_M^+ by a triangular solve (M has full column rank for Gaussian Psi with
-    l2 >= l1)."""
+    """SingleView approximation (Sec. 3.1.1, Alg. 3, eq. (singleviewlr)): from
+    the independent sketches Y = A Omega (m x l1) and Z = A^T Psi (n x l2),
+    A is approximated by Q_Y M^+ Z^T with Q_Y an orthonormal basis of range(Y)
+    and M = Psi^T Q_Y = Q_M R_M (thin QR), so M^+ = R_M^{-1} Q_M^T.  Then
+    H = A^T A is approximated by W^T W with W = R_M^{-1} (Z Q_M)^T, whose thin
+    SVD gives H_hat = V Sigma^2 V^T.  Thin QRs by Householder; M has full
+    column rank for Gaussian Psi with l2 >= l1."""
     Omega = np.asarray(Omega, dtype=np.float64)
     Psi = np.asarray(Psi, dtype=np.float64)
-    Y = A_apply(Omega)                                     # step 2 (both sketches)
+    Y = A_apply(Omega)
     Z = AT_apply(Psi)
-    Qy, _ = np.linalg.qr(Y)                                # step 3
-    Qm, Rm = np.linalg.qr(Psi.T @ Qy)                      # step 4
-    W = solve_triangular(Rm, (Z @ Qm).T, lower=False)      # step 5: W = R_M^{-1} (Z Q_M)^T
+    Qy, _ = np.linalg.qr(Y)
+    Qm, Rm = np.linalg.qr(Psi.T @ Qy)
+    W = solve_triangular(Rm, (Z @ Qm).T, lower=False)
     _, S, Vt = np.linalg.svd(W, full_matrices=False)
     return Vt.T.copy(), S * S
 
@@ -108,8 +129,9 @@ def randsvd_adaptive(A_apply, AT_apply, H_apply, Omegas, v, eps_sk):
     the sketch while kappa_sk > eps_sk and blocks remain (the caller's cap on
     l).  Returns (V_hat, lambda_hat, kappas) with one kappa_sk per evaluation.
     Readings: the new block is orthogonalised against the accumulated Q twice
-    (classical Gram-Schmidt with one re-orthogonalisation, the "additional
-    steps if necessary" of the algorithm); thin QR by Householder."""
+    (classical Gram-Schmidt with one re-orthogonalisation: the optional extra
+    Gram-Schmidt passes the algorithm allows, always taken); thin QR by
+    Householder."""
     Om = np.asarray(Omegas[0], dtype=np.float64)
     Y = A_apply(Om)                                        # forward pass Y = A Omega
     Qh, _ = np.linalg.qr(Y)                                # thin QR
@@ -131,18 +153,24 @@ def randsvd_adaptive(A_apply, AT_apply, H_apply, Omegas, v, eps_sk):
 
 
 def qr_update(A1, A2, B1, B2, Q1, R1):
-    """Alg. 6: thin QR of [A1; A2] [B1 B2] given the thin QR Q1 R1 = A1 B1
-    (B1, B2 with orthonormal columns).  Thin QRs by Householder; A2 B1 may be
-    wider than tall, whose reduced QR has a trapezoidal R.  Returns (Q5, R5)."""
-    Q2, R2 = np.linalg.qr(A2 @ B1)                         # step 1
-    Q3, R3 = np.linalg.qr(np.vstack([R1, R2]))             # step 2
+    """Thin QR of the stacked product [A1; A2] [B1 B2] given the thin QR
+    Q1 R1 = A1 B1 (Sec. 3.1.2, Alg. 6; B1, B2 with orthonormal columns).
+
+    The first block column [A1 B1; A2 B1] = diag(Q1, Q2) [R1; R2] once
+    A2 B1 = Q2 R2 is factored, and one more QR [R1; R2] = Q3' R3 gives its thin
+    QR Q3 R3 with Q3 = diag(Q1, Q2) Q3'.  The second block column P1 = [A1; A2] B2
+    is split into its component T = Q3^T P1 in range(Q3) and the remainder
+    P2 = P1 - Q3 T = Q4 R4, so [Q3 Q4] [[R3, T], [0, R4]] is the thin QR of the
+    whole.  Thin QRs by Householder; A2 B1 may be wider than tall, whose reduced
+    QR has a trapezoidal R.  Returns (Q5, R5)."""
+    Q2, R2 = np.linalg.qr(A2 @ B1)
+    Q3s, R3 = np.linalg.qr(np.vstack([R1, R2]))
     k1 = R1.shape[0]
-    Q3 = np.vstack([Q1 @ Q3[:k1], Q2 @ Q3[k1:]])           # step 3: diag(Q1, Q2) Q3
-    P1 = np.vstack([A1, A2]) @ B2                          # step 4
+    Q3 = np.vstack([Q1 @ Q3s[:k1], Q2 @ Q3s[k1:]])
+    P1 = np.vstack([A1, A2]) @ B2
     T = Q3.T @ P1
-    P2 = P1 - Q3 @ T                                       # step 5
-    Q4, R4 = np.linalg.qr(P2)                              # step 6
-    Q5 = np.hstack([Q3, Q4])                               # step 7
+    Q4, R4 = np.linalg.qr(P1 - Q3 @ T)
+    Q5 = np.hstack([Q3, Q4])
     R5 = np.block([[R3, T], [np.zeros((R4.shape[0], R3.shape[1])), R4]])
     return Q5, R5
 

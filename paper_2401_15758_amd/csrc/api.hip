@@ -1268,18 +1268,18 @@ void lmp_factor_fast(rp4d_problem* p, int l, const double* Wt, Scratch& s, rp4d_
 
 void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scratch& s, rp4d_precond* pc,
                    bool fast = false) {
-    sketch_misfit_hessian(p, tr, l, dtype, s);                       // step 2: Y = H Omega
+    sketch_misfit_hessian(p, tr, l, dtype, s);                       // Y = H Omega
     nystrom_core(p, l, dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23), s, pc, fast);
 }
 
-// Alg. 2 from step 3 on: Omega (n x l) in s.Om and Y = H Omega in s.Yd, both
+// Nystrom approximation (Alg. 2) from its sketch: Omega (n x l) in s.Om and Y = H Omega in s.Yd, both
 // row-major with leading size l; eps is the unit roundoff of the sketch sweeps.
 // Writes pc->V and s.lam, s.D, s.nu; with `fast` the factored form of the
 // preconditioner instead (lmp_factor_fast on B, no eigendecomposition).
 void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* pc, bool fast) {
     hipStream_t st = stream_of(p);
     const int n = p->n;
-    // step 3: nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
+    // shift nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
     launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
@@ -1291,7 +1291,7 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
     RP4D_HIP(hipGetLastError());
     bool ok = false;
     for (int attempt = 0; attempt <= 3; ++attempt) {
-        // step 4: Y <- Y + nu Omega ; step 5: C = Omega^T Y, L = chol((C + C^T)/2)
+        // shifted sketch Y_nu = Y + nu Omega, core C = Omega^T Y_nu = L L^T (symmetrised)
         launch_relayout<double, double>(s.Yd, 1, s.Y2, 1, n * l, 1, st);
         const size_t cnt = static_cast<size_t>(n) * l;
         axpy_dev<<<nblk(static_cast<long>(cnt)), 256, 0, st>>>(s.Om, s.nu, s.Y2, cnt);
@@ -1306,7 +1306,7 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
         RP4D_HIP(hipGetLastError());
     }
     RP4D_REQUIRE(ok, RP4D_ENOTSPD, "Nystrom core matrix not positive definite after shift retries (or non-finite sketch)");
-    // step 6-7: B = Y L^{-T} (n x l); B^T B = U Sigma^2 U^T.  Forming B before the
+    // B = Y_nu L^{-T} (n x l), B B^T the shifted approximant; B^T B = U Sigma^2 U^T.  Forming B before the
     // Gram keeps the error at eps cond(L) |B|^2 (the Gram of Y between two
     // triangular inverses would square cond(L)).
     launch_trinv(s.S2, s.S3, l, st);                                  // S3 = L^{-1}
@@ -1403,7 +1403,7 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
                    bool fast = false) {
     hipStream_t st = stream_of(p);
     const int n = p->n, m = p->m;
-    // step 2: Y = A Omega (m x l)
+    // Y = A Omega (m x l)
     if (dtype == RP4D_F64) {
         tlm_impl<double>(p, tr, l, s.Om, s.Yd);
     } else {
@@ -1411,9 +1411,9 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         tlm_impl<float>(p, tr, l, static_cast<const float*>(s.Omt), static_cast<float*>(s.Yt));
         launch_relayout<float, double>(static_cast<const float*>(s.Yt), l, s.Yd, l, m, l, st);
     }
-    // step 3: thin QR (CholeskyQR2 in FP64)
+    // thin QR Y = Q R (CholeskyQR2 in FP64)
     cholqr2(p, m, l, s);
-    // step 4: W^T = A^T Q (n x l)
+    // W^T = A^T Q (n x l)
     if (dtype == RP4D_F64) {
         adj_impl<double>(p, tr, l, s.Yd, s.S1, nullptr);
     } else {
@@ -1426,7 +1426,7 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         launch_fill<double>(s.nu, 1, 0.0, st);
         return;
     }
-    // step 5: thin SVD of W via eig(W W^T): V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
+    // thin SVD of W via eig(W W^T): V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
     launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S2, s.gw, st);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
@@ -1959,7 +1959,7 @@ void build_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singlevie
     s.gw = Rinv + static_cast<size_t>(l1) * l1;
     float* Psit = reinterpret_cast<float*>(s.gw + gw + 64);
     float* Zt = Psit + ml2;
-    // step 1: Omega (n x l1), Psi (m x l2)
+    // Gaussian Omega (n x l1) and Psi (m x l2)
     if (o.omega)
         launch_relayout<double, double>(o.omega, 1, s.Om, 1, n * l1, 1, st);
     else
@@ -1968,7 +1968,7 @@ void build_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singlevie
         launch_relayout<double, double>(o.psi, 1, Psi, 1, m * l2, 1, st);
     else
         launch_philox_normal(singleview_psi_seed(o.seed), ml2, Psi, st);
-    // step 2: Z = A^T Psi beside Y = A Omega
+    // co-range sketch Z = A^T Psi beside the range sketch Y = A Omega
     auto corange = [&]() {
         hipStream_t zs = stream_of(p);
         if (f64) {
@@ -1991,15 +1991,15 @@ void build_singleview(rp4d_problem* p, const rp4d_traj* tr, const rp4d_singlevie
         tlm_impl<float>(p, tr, l1, static_cast<const float*>(s.Omt), static_cast<float*>(s.Yt));
         launch_relayout<float, double>(static_cast<const float*>(s.Yt), l1, s.Yd, l1, m, l1, st);
     }
-    cholqr2(p, m, l1, s);                                                        // step 3: Y = Q_Y R_Y
-    launch_gram<double, double>(Psi, l2, s.Yd, l1, m, l2, l1, Mb, s.gw, st);   // step 4: M = Psi^T Q_Y
+    cholqr2(p, m, l1, s);                                                        // Y = Q_Y R_Y
+    launch_gram<double, double>(Psi, l2, s.Yd, l1, m, l2, l1, Mb, s.gw, st);   // M = Psi^T Q_Y
     launch_relayout<double, double>(Mb, 1, s.Yd, 1, l2 * l1, 1, st);
     cholqr2(p, l2, l1, s, Rinv);                                                 // M = Q_M R_M
     transpose_small<<<nblk(static_cast<long>(l1) * l1), 256, 0, st>>>(Rinv, s.S4, l1);  // S4 = R_M^{-T}
     RP4D_HIP(hipGetLastError());
     launch_tsmm<double, double>(s.Yd, l1, s.S4, nullptr, l2, l1, l1, 1.0, nullptr, 0, 0.0, P, l1, st);
     if (lane) RP4D_HIP(hipStreamWaitEvent(st, p->ctx->ev_join, 0));
-    // step 5: W^T = Z Q_M R_M^{-T} (n x l1); thin SVD of W by eig(W W^T)
+    // W^T = Z Q_M R_M^{-T} (n x l1); thin SVD of W by eig(W W^T)
     launch_tsmm<double, double>(Z, l2, P, nullptr, n, l2, l1, 1.0, nullptr, 0, 0.0, s.S1, l1, st);
     launch_gram<double, double>(s.S1, l1, s.S1, l1, n, l1, l1, s.S2, s.gw, st);
     {

@@ -171,3 +171,95 @@ def test_singleview_expected_bounds(small_problem, small_dense):
     theta = analysis.theta_bound(lamH, r)
     assert np.mean(roots) <= 1 + theta, (np.mean(roots), theta)
     assert np.mean(errs) <= theta, (np.mean(errs), theta)
+
+
+# --- the Nystrom shift and its retries (Alg. 2; reading: x10 per retry, at most 3) ---
+
+def _indefinite_sketch(n, delta, ratio, seed):
+    """A square Gaussian Omega (n x n, invertible) and Y0 = H Omega for a
+    symmetric H with one eigenvalue -delta and the others positive, scaled so
+    that the first shift nu0 = sqrt(n) eps ||Y0||_2 equals delta / ratio."""
+    rng = np.random.default_rng(seed)
+    Om = rng.standard_normal((n, n))
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.linspace(1.0, 2.0, n)
+    lam[-1] = 0.0
+    # the positive part sets ||Y0||_2; choose its scale c so that nu0 = delta / ratio
+    base = np.linalg.norm((U * lam) @ U.T @ Om, 2)
+    c = delta / ratio / (np.sqrt(n) * sketch.EPS64 * base)
+    lam = c * lam
+    lam[-1] = -delta
+    H = (U * lam) @ U.T
+    return Om, H @ Om, H, lam
+
+
+@pytest.mark.parametrize("ratio, retries", [(3.0, 1), (30.0, 2), (300.0, 3)])
+def test_nystrom_shift_retries(ratio, retries):
+    """With H + nu I indefinite at the first shift (one eigenvalue -delta, and
+    nu0 = delta / ratio), the core Omega^T (H + nu I) Omega of a square,
+    invertible Omega is positive definite exactly when nu > delta: the shift
+    must be retried `retries` times, ending at nu = 10^retries nu0.  For a
+    square Omega the Nystrom approximant of H + nu I is H + nu I itself, so the
+    returned eigenvalues are max(0, eig(H))."""
+    n, delta = 12, 1e-3
+    Om, Y0, H, lam = _indefinite_sketch(n, delta, ratio, seed=11)
+    nu0 = np.sqrt(n) * sketch.EPS64 * np.linalg.norm(Y0, 2)
+    assert nu0 == pytest.approx(delta / ratio, rel=1e-12)
+    V, lh, nu = sketch.nystrom_from_sketch(Om, Y0)
+    assert nu == pytest.approx(10.0 ** retries * nu0, rel=1e-14)
+    ref = np.sort(np.maximum(0.0, lam))[::-1]
+    got = np.sort(lh)[::-1]
+    # the clamped direction keeps an error of order nu (its shifted eigenvalue
+    # nu - delta > 0 loses nu); the rest are exact up to cond(Omega) eps |H|
+    assert np.max(np.abs(got - ref)) <= 1e-8 * ref[0]
+
+
+def test_nystrom_shift_gives_up_after_three_retries():
+    n, delta = 12, 1e-3
+    Om, Y0, _, _ = _indefinite_sketch(n, delta, 3000.0, seed=12)   # 1000 nu0 < delta
+    with pytest.raises(sketch.NotSPDError):
+        sketch.nystrom_from_sketch(Om, Y0)
+    # with more retries allowed the fourth one (10^4 nu0 > delta) succeeds
+    _, _, nu = sketch.nystrom_from_sketch(Om, Y0, max_retries=4)
+    assert nu == pytest.approx(1e4 * np.sqrt(n) * sketch.EPS64 * np.linalg.norm(Y0, 2), rel=1e-14)
+
+
+def test_nystrom_zero_column_is_never_positive_definite():
+    """A zero column of Omega gives a zero row and column of the core at every
+    shift: every retry fails."""
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((30, 40))
+    Om = rng.standard_normal((40, 8))
+    Om[:, 5] = 0.0
+    with pytest.raises(sketch.NotSPDError):
+        sketch.nystrom(lambda X: A.T @ (A @ X), Om)
+
+
+# --- Sec. 4 bounds, exact values on a closed-form spectrum ---
+
+def test_psi_and_theta_exact_on_a_geometric_spectrum():
+    """lambda_j = 2^{-(j-1)}, j = 1..10.  The tail sums are geometric:
+    sum_{j>r} lambda_j = 2^{-r} (2 - 2^{-(9-r)}) ... written out for r = 2:
+    lambda_3 = 1/4, sum_{j>2} lambda_j = 1/4 (1 + 1/2 + ... + 1/128) = 255/512.
+    Psi_H(r, p) = lambda_{r+1} + r/(p-1) sum_{j>r} lambda_j (the first form of
+    the definition), with r = 2, p = 3: 1/4 + 255/512 = 383/512.
+    Theta_H(r) in its second form, (sqrt(lambda_1/lambda_{r+1}) sqrt(id_r) + id_r)
+    4 lambda_{r+1} with id_r = (255/512)/(1/4) = 255/128: (2 sqrt(255/128) +
+    255/128)."""
+    lam = 2.0 ** -np.arange(10)
+    rng = np.random.default_rng(0)
+    shuffled = rng.permutation(lam)                  # the functions sort themselves
+    assert analysis.intrinsic_dimension(shuffled, 2) == 255.0 / 128.0
+    assert analysis.psi_bound(shuffled, 2, 3) == 383.0 / 512.0
+    # the second form of the definition, (1 + r/(p-1) id_r) lambda_{r+1}, agrees
+    assert (1.0 + 255.0 / 128.0) / 4.0 == 383.0 / 512.0
+    idr = 255.0 / 128.0
+    assert analysis.theta_bound(shuffled, 2) == pytest.approx((2.0 * np.sqrt(idr) + idr), rel=1e-15)
+    # r = 0: Psi = lambda_1 + 0 = 1, Theta = 4 sqrt(sum) + 4 sum with sum = 1023/512
+    s0 = 1023.0 / 512.0
+    assert analysis.psi_bound(lam, 0, 2) == 1.0
+    assert analysis.theta_bound(lam, 0) == pytest.approx(4.0 * np.sqrt(s0) + 4.0 * s0, rel=1e-15)
+    # a flat spectrum of rank 5: Psi vanishes once r reaches the rank
+    flat = np.r_[np.ones(5), np.zeros(5)]
+    assert analysis.psi_bound(flat, 5, 3) == 0.0 and analysis.theta_bound(flat, 5) == 0.0
+    assert analysis.psi_bound(flat, 4, 3) == 1.0 + 4.0 / 2.0 * 1.0
