@@ -248,6 +248,15 @@ int rp4d_gradient(rp4d_problem* p, const rp4d_traj* traj, const double* v, doubl
  * Nystrom core matrix stays indefinite after 3 tenfold shift increases. */
 int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* traj, int method, int ell, uint64_t seed,
                        const double* omega, int sketch_dtype, rp4d_precond** out);
+/* Nystrom approximation (Sec. 3.1.1, Alg. 2) of a symmetric operator of the
+ * problem's size from a caller-supplied sketch: omega (n, ell) and Y = H omega
+ * (n, ell), both device buffers, row-major FP64, read only (the caller keeps
+ * them).  The shift nu = sqrt(n) 2^-52 ||Y||_2 is retried tenfold, at most 3
+ * times, while the shifted core omega^T (Y + nu omega) is not numerically
+ * positive definite; then RP4D_ENOTSPD.  No sweep runs and no counter moves.
+ * EINVAL on null arguments or ell outside [1, min(128, n)]. */
+int rp4d_build_precond_from_sketch(rp4d_problem* p, int ell, const double* omega, const double* Y,
+                                   rp4d_precond** out);
 /* Adaptive RandSVD (Sec. 3.1.2, Alg. 4): start from ell0 Gaussian columns and
  * add ell_hat columns while kappa_sk = ||(I + H)(I + H_hat)^{-1} v||_2
  * (eq. (condtext), (I + H_hat)^{-1} by eq. (randsvdsv)) exceeds eps_sk and the

@@ -231,3 +231,113 @@ def tune_or_load(prob, traj, nsteps, k, dtype=rp4d.F64, budget_s=30.0, cache_pat
             pass
     return best
 
+
+
+# ---------------------------------------------------------------------------
+# Batched sweeps (rp4d_batch_set_tiling): one tiling per (mode, dtype) for the
+# whole batch; the tile follows from the region and the halo.
+# (ppt, kc) pairs with a batched wave-region instance, and with a batched
+# workgroup-region instance
+BATCH_WAVE_PK = ((1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2))
+BATCH_LDS_PK = ((1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2))
+BATCH_STEPS = (4, 6, 8, 10, 12, 16, 20)
+
+
+def batch_candidates(dtype=rp4d.F64):
+    """Every batched sweep tiling the batch search tries: wave regions with 64,
+    128 or 256 threads per workgroup and workgroup regions of 256 or 512
+    threads, for every steps-per-launch value whose halo leaves owned points."""
+    es = 8 if dtype == rp4d.F64 else 4
+    out = []
+    for ppt, kc in BATCH_WAVE_PK:
+        for steps in BATCH_STEPS:
+            if 64 * ppt - 2 * (4 * steps + 4) < 1:
+                continue
+            for threads in (64, 128, 256):
+                out.append(dict(xch=rp4d.XCH_WAVE, ppt=ppt, kc=kc, threads=threads, steps=steps))
+    for ppt, kc in BATCH_LDS_PK:
+        for threads in (256, 512):
+            if threads > (512 if ppt * kc >= 8 else 1024) or 2 * 2 * threads * (1 + kc) * es > LDS_LIMIT:
+                continue
+            for steps in BATCH_STEPS:
+                if threads * ppt - 2 * (4 * steps + 4) < 1:
+                    continue
+                out.append(dict(xch=rp4d.XCH_LDS, ppt=ppt, kc=kc, threads=threads, steps=steps))
+    return out
+
+
+def batch_key(problems, k, dtype):
+    """Cache key of a batch shape: the multiset of (n, nsteps) and k, dtype."""
+    import hashlib
+    dims = sorted((p.n, int(p.cfg["nsteps"])) for p in problems)
+    h = hashlib.sha1(repr(dims).encode()).hexdigest()[:12]
+    return f"batch{len(dims)}-{h}-k{k}-{'f64' if dtype == rp4d.F64 else 'f32'}"
+
+
+def tune_batch(batch, trajs, k, dtype=rp4d.F64, reps=2, budget_s=60.0, verbose=False):
+    """Search the batched sweep tiling (one for the TLM and the ADJ sweep of
+    rp4d_batch_hessian_block) by timing the batched block Hessian of k vectors
+    over the whole batch with each candidate; applies and returns the best
+    {"sweep": {...tiling, ms}}.  Candidates are tried cheapest-looking first
+    (more steps per launch, larger regions) until the budget is spent."""
+    tdtype = torch.float64 if dtype == rp4d.F64 else torch.float32
+    Vs = []
+    for i, p in enumerate(batch.problems):
+        V = torch.empty((p.n, k), dtype=torch.float64, device=p.dev)
+        batch.ctx.philox_normal(100 + i, V.numel(), V)
+        Vs.append(V.to(tdtype))
+    HVs = [torch.empty_like(v) for v in Vs]
+    op = lambda: batch.hessian_block(trajs, Vs, HVs)
+    for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+        batch.set_tiling(mode, dtype)                          # library default
+    best, best_ms = None, _time(op, reps)
+    cands = batch_candidates(dtype)
+    cands.sort(key=lambda c: (-c["steps"] * c["ppt"], -c["kc"], c["threads"]))
+    t_end = time.perf_counter() + budget_s
+    for c in cands:
+        if time.perf_counter() > t_end:
+            break
+        for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+            batch.set_tiling(mode, dtype, **c)
+        try:
+            ms = _time(op, reps)
+        except rp4d.Rp4dError:                                 # e.g. a staged group beyond the ring
+            continue
+        if verbose:
+            print(f"batch {c} {ms:.3f} ms", flush=True)
+        if ms < best_ms:
+            best, best_ms = dict(c), ms
+    for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+        if best is None:
+            batch.set_tiling(mode, dtype)
+        else:
+            batch.set_tiling(mode, dtype, **best)
+    return {"sweep": dict(best or {}, ms=best_ms, default=best is None)}
+
+
+def apply_cached_batch(batch, k, dtype=rp4d.F64, cache=None):
+    cache = load_cache() if cache is None else cache
+    ent = cache.get(batch_key(batch.problems, k, dtype))
+    if not ent or "sweep" not in ent:
+        return None
+    t = {f: ent["sweep"].get(f, 0) for f in ("xch", "ppt", "kc", "threads", "steps")}
+    for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+        batch.set_tiling(mode, dtype, **t)
+    return ent
+
+
+def tune_batch_or_load(batch, trajs, k, dtype=rp4d.F64, budget_s=60.0, cache_path=CACHE_PATH, save=True,
+                       verbose=False):
+    cache = load_cache(cache_path)
+    ent = apply_cached_batch(batch, k, dtype, cache)
+    if ent is not None:
+        return ent
+    best = tune_batch(batch, trajs, k, dtype, budget_s=budget_s, verbose=verbose)
+    cache[batch_key(batch.problems, k, dtype)] = best
+    if save:
+        try:
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return best

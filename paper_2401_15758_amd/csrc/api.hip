@@ -7,9 +7,12 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
+#include <type_traits>
 
 #include <limits>
 
+#include "batch_plan.hpp"
 #include "internal.hpp"
 
 namespace rp4d {
@@ -1707,6 +1710,16 @@ void precond_apply_impl(rp4d_problem* p, const rp4d_precond* pc, int k, const do
     launch_tsmm<double, double>(pc->V.as<double>(), l, T, pc->Dg.as<double>(), n, l, k, -1.0, R, k, 1.0, Z, k, st);
 }
 
+// Keep D = lambda/(1+lambda), Lambda_hat and nu of a sketch in the preconditioner.
+void keep_eigs(rp4d_problem* p, int ell, const Scratch& s, rp4d_precond* pc) {
+    hipStream_t st = stream_of(p);
+    pc->Dg.ensure(static_cast<size_t>(ell) * sizeof(double));
+    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, ell, 1, st);
+    pc->lamd.ensure(static_cast<size_t>(ell + 1) * sizeof(double));
+    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, ell, 1, st);
+    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + ell, 1, 1, 1, st);
+}
+
 // Sketch and factor into `pc` (its buffers are reused when large enough).
 // Everything is enqueued on the problem stream; the only host wait is the
 // Nystrom core's Cholesky check.  Host copies of the eigenvalues and the shift
@@ -1734,11 +1747,23 @@ void build_precond_into(rp4d_problem* p, const rp4d_traj* tr, int method, int el
     p->cnt.adj_offline += ell;
     p->cnt.sketches += 1;
     if (fast) return;
-    pc->Dg.ensure(static_cast<size_t>(ell) * sizeof(double));
-    launch_relayout<double, double>(s.D, 1, pc->Dg.as<double>(), 1, ell, 1, st);
-    pc->lamd.ensure(static_cast<size_t>(ell + 1) * sizeof(double));
-    launch_relayout<double, double>(s.lam, 1, pc->lamd.as<double>(), 1, ell, 1, st);
-    launch_relayout<double, double>(s.nu, 1, pc->lamd.as<double>() + ell, 1, 1, 1, st);
+    keep_eigs(p, ell, s, pc);
+}
+
+// Nystrom approximation from a caller-supplied sketch: Omega (n x l) and
+// Y = H Omega (n x l), device, row-major, FP64.
+void build_nystrom_from_sketch(rp4d_problem* p, int ell, const double* omega, const double* Y, rp4d_precond* pc) {
+    RP4D_REQUIRE(ell >= 1 && ell <= 128 && ell <= p->n, RP4D_EINVAL, "ell must be in [1, min(128, n)]");
+    hipStream_t st = stream_of(p);
+    Scratch s = sketch_scratch(p, ell, RP4D_F64);
+    launch_relayout<double, double>(omega, 1, s.Om, 1, p->n * ell, 1, st);
+    launch_relayout<double, double>(Y, 1, s.Yd, 1, p->n * ell, 1, st);
+    pc->p = p;
+    pc->ell = ell;
+    pc->host_ok = false;
+    pc->fast = false;
+    nystrom_core(p, ell, std::ldexp(1.0, -52), s, pc);
+    keep_eigs(p, ell, s, pc);
 }
 
 // Host copies of Lambda_hat and nu (one copy and wait after each build).
@@ -1769,6 +1794,24 @@ int rp4d_build_precond(rp4d_problem* p, const rp4d_traj* tr, int method, int ell
         auto* pc = new rp4d_precond();
         try {
             build_precond_into(p, tr, method, ell, seed, omega, sketch_dtype, pc);
+            fetch_host(pc);
+        } catch (...) {
+            delete pc;
+            throw;
+        }
+        *out = pc;
+    });
+}
+
+int rp4d_build_precond_from_sketch(rp4d_problem* p, int ell, const double* omega, const double* Y,
+                                   rp4d_precond** out) {
+    return guarded([&] {
+        RP4D_REQUIRE(p != nullptr && omega != nullptr && Y != nullptr && out != nullptr, RP4D_EINVAL,
+                     "null argument");
+        set_device(p->ctx);
+        auto* pc = new rp4d_precond();
+        try {
+            build_nystrom_from_sketch(p, ell, omega, Y, pc);
             fetch_host(pc);
         } catch (...) {
             delete pc;
@@ -2331,7 +2374,9 @@ void pcg_impl(rp4d_problem* p, const rp4d_traj* tr, const rp4d_precond* pc, cons
     double rnorm = bnorm;
     int it = 0;
     bool conv = true;
-    if (bnorm == 0.0) {
+    if (bnorm == 0.0 || bnorm <= rtol * bnorm) {
+        // b = 0, or rtol >= 1: x_0 = 0 already meets the tolerance, and the
+        // speculative first iteration is discarded
         launch_fill<double>(x, n, 0.0, st);
         p->cnt.hv_columns -= 1;
     } else {
@@ -2596,7 +2641,12 @@ int rp4d_gn_step(rp4d_problem* p, rp4d_gn_state* s, const rp4d_gn_opts* o, rp4d_
                 if (f.span) p->ctx->event_pool.push_back(f.span);       // timing span never closed
                 f.span = nullptr;
                 f.active = false;
-                (void)hipStreamWaitEvent(p->ctx->stream, p->ctx->ev_join, 0);
+                // join everything enqueued on the side stream so far: planned FWD
+                // launches enqueued after on_side_lane recorded ev_join must not
+                // outlive the step (a later main-stream FWD reuses the trajectory)
+                rp4d_ctx* c = p->ctx;
+                if (c->side) (void)hipEventRecord(c->ev_join, c->side);
+                (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
             }
         } guard{p};
         if (pipelined) {
@@ -2902,29 +2952,43 @@ struct rp4d_batch {
 namespace rp4d {
 namespace {
 
-// Descriptor tables are staged through a pinned host ring and its device copy,
-// used as two halves.  A table never straddles the halves; when the current
-// half is full the stream is drained (every launch that read the other half has
-// completed) and staging moves to the other half.  Tables staged together for
-// one launch therefore stay intact until that launch is enqueued: a switch
-// never overwrites the half holding the earlier tables of the same group.
+// Descriptor tables are staged through a pinned host ring and its device copy
+// (ring placement: batch_plan.hpp).  stage() places the tables that one set of
+// launches reads as one group, enqueues their copies and returns their device
+// addresses; the caller enqueues those launches before it stages anything
+// else, so no table outlives the next group.
+inline void ring_copy(rp4d_batch* b, size_t at, const void* src, size_t bytes) {
+    if (bytes == 0) return;
+    char* h = b->host + at;
+    std::memcpy(h, src, bytes);
+    RP4D_HIP(hipMemcpyAsync(b->dev.as<char>() + at, h, bytes, hipMemcpyHostToDevice, b->ctx->stream));
+}
+
+template <typename... V>
+std::tuple<typename V::value_type*...> stage(rp4d_batch* b, const V&... v) {
+    const size_t sizes[] = {ring_round(v.size() * sizeof(typename V::value_type))...};
+    size_t total = 0;
+    for (size_t x : sizes) total += x;
+    const RingPlace r = ring_place_group(b->off, b->cap, total);
+    RP4D_REQUIRE(r.fits, RP4D_ENOMEM, "batch staging ring too small for the descriptor tables of one launch");
+    if (r.drain) RP4D_HIP(hipStreamSynchronize(b->ctx->stream));
+    size_t at = r.first;
+    int q = 0;
+    auto put = [&](const auto& vec) {
+        typedef typename std::decay_t<decltype(vec)>::value_type E;
+        E* d = vec.empty() ? nullptr : reinterpret_cast<E*>(b->dev.as<char>() + at);
+        ring_copy(b, at, vec.data(), vec.size() * sizeof(E));
+        at += sizes[q++];
+        return d;
+    };
+    std::tuple<typename V::value_type*...> out{put(v)...};
+    b->off = r.next;
+    return out;
+}
+
 template <typename T>
-T* stage(rp4d_batch* b, const std::vector<T>& v) {
-    const size_t bytes = ((v.size() * sizeof(T)) + 255) / 256 * 256;
-    if (bytes == 0) return nullptr;
-    const size_t half = b->cap / 2;
-    RP4D_REQUIRE(bytes <= half, RP4D_ENOMEM, "batch staging ring too small for a descriptor table");
-    const size_t base = b->off < half ? 0 : half;
-    if (b->off + bytes > base + half) {
-        RP4D_HIP(hipStreamSynchronize(b->ctx->stream));
-        b->off = base == 0 ? half : 0;
-    }
-    char* h = b->host + b->off;
-    char* d = b->dev.as<char>() + b->off;
-    std::memcpy(h, v.data(), v.size() * sizeof(T));
-    RP4D_HIP(hipMemcpyAsync(d, h, v.size() * sizeof(T), hipMemcpyHostToDevice, b->ctx->stream));
-    b->off += bytes;
-    return reinterpret_cast<T*>(d);
+T* stage1(rp4d_batch* b, const std::vector<T>& v) {
+    return std::get<0>(stage(b, v));
 }
 
 // Work items (problem, block) covering count_p elements per problem in blocks of 2048.
@@ -2959,15 +3023,6 @@ Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd) {
     return t;
 }
 
-// Tile (owned points per region) of an n-point problem under tiling t.
-int batch_tile(const Tiling& t, int n) {
-    RP4D_REQUIRE(t.threads >= 64 && t.threads <= 1024 && t.threads % 64 == 0 && t.steps >= 1, RP4D_EINVAL,
-                 "batch tiling: threads must be a multiple of 64 in [64, 1024] and steps >= 1");
-    const int halo = 4 * t.steps + 4;
-    const int room = (t.xch == XCH_WAVE ? 64 : t.threads) * t.ppt - 2 * halo;
-    RP4D_REQUIRE(room >= 1, RP4D_EINVAL, "batch tiling: region too small for the halo of steps per launch");
-    return std::min(n, room);
-}
 
 // Batched Gram matrices: each descriptor's chunking and partial-sum buffer come
 // from its problem (rows per chunk depend on n only); `owner[i]` is the problem
@@ -2990,13 +3045,54 @@ void batch_gram(rp4d_batch* b, std::vector<BGram> gd, const std::vector<rp4d_pro
         for (size_t blk = 0; blk * 256 < stride; ++blk) ritems.push_back(make_int4(static_cast<int>(i), static_cast<int>(blk), 0, 0));
     }
     if (gd.empty()) return;
-    launch_bgram<TX, TY>(stage(b, gd), stage(b, items), static_cast<int>(items.size()), stage(b, ritems),
-                         static_cast<int>(ritems.size()), b->ctx->stream);
+    auto [dgd, dit, drit] = stage(b, gd, items, ritems);
+    launch_bgram<TX, TY>(dgd, dit, static_cast<int>(items.size()), drit, static_cast<int>(ritems.size()),
+                         b->ctx->stream);
 }
 
 void check_batch_traj(const rp4d_problem* p, const rp4d_traj* tr) {
     check_traj(p, tr);
     RP4D_REQUIRE(tr->C == 1, RP4D_EINVAL, "batched sweeps need full trajectory storage (ckpt_every <= 1)");
+}
+
+// The planner's view of a batch problem and its stored trajectory.
+BatchProb batch_prob(const rp4d_problem* p, const rp4d_traj* tr) {
+    BatchProb q{};
+    q.n = p->n;
+    q.s_last = p->s_last;
+    q.dt = p->d.dt;
+    q.inv2dx = p->inv2dx;
+    q.nu_dx2 = p->nu_dx2;
+    q.obs_stride = p->d.obs_stride;
+    q.obs_every = p->d.obs_every;
+    q.n_obs = p->n_obs;
+    q.n_t = p->n_t;
+    q.sigma_o = p->d.sigma_o;
+    q.traj = tr->states.as<double>();
+    q.traj_rows = tr->rows;
+    return q;
+}
+
+// Run f(j0, j1) over chunks of the nl time intervals of a batched sweep (or
+// FWD) whose argument blocks and work items take at most a quarter of the
+// staging ring, so that each chunk is one staged group.
+template <typename F>
+void for_interval_chunks(rp4d_batch* b, const std::vector<BatchProb>& bp, const Tiling& t, int groups,
+                         size_t arg_bytes, F&& f) {
+    const int nl = batch_intervals(bp, t);
+    std::vector<int> ntile(bp.size()), nlp(bp.size());
+    for (size_t i = 0; i < bp.size(); ++i) {
+        ntile[i] = (bp[i].n + batch_tile(t, bp[i].n) - 1) / batch_tile(t, bp[i].n);
+        nlp[i] = (bp[i].s_last + t.steps - 1) / t.steps;
+    }
+    auto items_of = [&](int j) {
+        long c = 0;
+        for (size_t i = 0; i < bp.size(); ++i)
+            if (j < nlp[i]) c += static_cast<long>(ntile[i]) * groups;
+        return c;
+    };
+    const std::vector<int> cuts = interval_chunks(nl, arg_bytes * bp.size() + 2 * kRingAlign, items_of, b->cap / 4);
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) f(cuts[c], cuts[c + 1]);
 }
 
 // Fused FWD of every problem in `sel` (indices into b->probs): u_0 = x0[i].
@@ -3006,13 +3102,11 @@ void batch_fwd_run(rp4d_batch* b, const std::vector<int>& sel, const std::vector
     const Tiling t = batch_tiling(b, MODE_TLM, RP4D_F64, true);
     const int np = static_cast<int>(sel.size());
     std::vector<double*> bufA(np), bufB(np);
-    int nl = 0;
     for (int i = 0; i < np; ++i) {
         rp4d_problem* p = b->probs[sel[i]];
         p->ws_red.ensure(std::max<size_t>(p->ws_red.bytes, (2 * static_cast<size_t>(p->n) + 512) * sizeof(double)));
         bufA[i] = p->ws_red.as<double>();
         bufB[i] = bufA[i] + p->n;
-        nl = std::max(nl, (p->s_last + t.steps - 1) / t.steps);
     }
     // initial state and trajectory row 0
     {
@@ -3026,57 +3120,27 @@ void batch_fwd_run(rp4d_batch* b, const std::vector<int>& sel, const std::vector
             cnt.push_back(p->n);
         }
         auto it = elem_items(cnt);
-        launch_bcopy<double, double>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_cd, d_it] = stage(b, cd, it);
+        launch_bcopy<double, double>(d_cd, d_it, static_cast<int>(it.size()), st);
     }
-    std::vector<FwdArgs> args;
-    std::vector<int4> items;
-    std::vector<int> off(nl + 1, 0), aoff(nl + 1, 0);
-    for (int j = 0; j < nl; ++j) {
-        off[j] = static_cast<int>(items.size());
-        aoff[j] = static_cast<int>(args.size());
-        for (int i = 0; i < np; ++i) {
-            rp4d_problem* p = b->probs[sel[i]];
-            const int s0 = j * t.steps;
-            FwdArgs a{};
-            if (s0 < p->s_last) {
-                a.xin = (j % 2 == 0) ? bufA[i] : bufB[i];
-                a.xout = (j % 2 == 0) ? bufB[i] : bufA[i];
-                a.store = trajs[i]->states.as<double>();
-                a.store_every = 1;
-                a.store_row0 = 0;
-                a.store_rows = trajs[i]->rows;
-                a.n = p->n;
-                a.h = p->d.dt;
-                a.inv2dx = p->inv2dx;
-                a.nu_dx2 = p->nu_dx2;
-                a.s0 = s0;
-                a.S = std::min(t.steps, p->s_last - s0);
-                a.tile = batch_tile(t, p->n);
-                a.halo = 4 * t.steps + 4;
-                a.obs_stride = p->d.obs_stride;
-                a.obs_every = p->d.obs_every;
-                a.n_obs = p->n_obs;
-                a.n_t = p->n_t;
-                a.inv_sigma_o = 1.0 / p->d.sigma_o;
-                a.y = p->has_data ? p->y.as<double>() : nullptr;
-                a.innov = p->has_data ? trajs[i]->innov.as<double>() : nullptr;
-                a.obs_out = trajs[i]->innov.as<double>() + p->m;
-                const int ntile = (p->n + a.tile - 1) / a.tile;
-                for (int tl = 0; tl < ntile; ++tl)
-                    items.push_back(make_int4(static_cast<int>(args.size()) - aoff[j], tl, 0, 0));
-            } else {
-                a.n = p->n;  // inactive: no work items reference it
-            }
-            args.push_back(a);
+    std::vector<BatchProb> bp(np);
+    for (int i = 0; i < np; ++i) {
+        rp4d_problem* p = b->probs[sel[i]];
+        bp[i] = batch_prob(p, trajs[i]);
+        bp[i].y = p->has_data ? p->y.as<double>() : nullptr;
+        bp[i].innov = p->has_data ? trajs[i]->innov.as<double>() : nullptr;
+        bp[i].obs_out = trajs[i]->innov.as<double>() + p->m;
+    }
+    for_interval_chunks(b, bp, t, 1, sizeof(FwdArgs), [&](int j0, int j1) {
+        const IntervalTables<FwdArgs> tb = plan_fwd(bp, t, bufA, bufB, j0, j1, FL_FWD);
+        auto [dargs, ditems] = stage(b, tb.args, tb.items);
+        const int4* dit = reinterpret_cast<const int4*>(ditems);
+        for (int j = j0; j < j1; ++j) {
+            const int q = j - j0;
+            KernelTimer kt(b->ctx, RP4D_K_FWD, tb.flops[q]);
+            launch_burgers_fwd_batched(dargs + tb.aoff[q], dit + tb.off[q], tb.off[q + 1] - tb.off[q], t, st);
         }
-    }
-    off[nl] = static_cast<int>(items.size());
-    FwdArgs* dargs = stage(b, args);
-    int4* ditems = stage(b, items);
-    for (int j = 0; j < nl; ++j) {
-        KernelTimer kt(b->ctx, RP4D_K_FWD, 0.0);
-        launch_burgers_fwd_batched(dargs + aoff[j], ditems + off[j], off[j + 1] - off[j], t, st);
-    }
+    });
     for (int i = 0; i < np; ++i) {
         trajs[i]->valid = true;
         trajs[i]->has_innov = b->probs[sel[i]]->has_data;
@@ -3095,8 +3159,6 @@ std::vector<T*> batch_sweep_run(rp4d_batch* b, int mode, const std::vector<int>&
     hipStream_t st = b->ctx->stream;
     const int np = static_cast<int>(sel.size());
     const int groups = (k + t.kc - 1) / t.kc;
-    int nl = 0;
-    for (int i = 0; i < np; ++i) nl = std::max(nl, (b->probs[sel[i]]->s_last + t.steps - 1) / t.steps);
     if (mode == MODE_ADJ) {
         std::vector<BCopy> cd;
         std::vector<size_t> cnt;
@@ -3106,68 +3168,24 @@ std::vector<T*> batch_sweep_run(rp4d_batch* b, int mode, const std::vector<int>&
             cnt.push_back(static_cast<size_t>(p->n) * groups * t.kc);
         }
         auto it = elem_items(cnt);
-        launch_bcopy<T, T>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_cd, d_it] = stage(b, cd, it);
+        launch_bcopy<T, T>(d_cd, d_it, static_cast<int>(it.size()), st);
     }
-    std::vector<SweepArgs<T>> args;
-    std::vector<int4> items;
-    std::vector<int> off(nl + 1, 0), aoff(nl + 1, 0);
-    std::vector<double> flops(nl, 0.0);
-    std::vector<T*> result(np);
-    for (int j = 0; j < nl; ++j) {
-        off[j] = static_cast<int>(items.size());
-        aoff[j] = static_cast<int>(args.size());
-        for (int i = 0; i < np; ++i) {
-            rp4d_problem* p = b->probs[sel[i]];
-            const int nlp = (p->s_last + t.steps - 1) / t.steps;
-            SweepArgs<T> a{};
-            a.n = p->n;
-            if (j < nlp) {
-                a.base = trajs[i]->states.as<double>();
-                a.base_row0 = 0;
-                a.h = static_cast<T>(p->d.dt);
-                a.inv2dx = static_cast<T>(p->inv2dx);
-                a.nu_dx2 = static_cast<T>(p->nu_dx2);
-                if (mode == MODE_TLM) {
-                    a.s0 = j * t.steps;
-                    a.S = std::min(t.steps, p->s_last - a.s0);
-                } else {
-                    const int s_hi = p->s_last - j * t.steps;
-                    a.s0 = std::max(0, s_hi - t.steps);
-                    a.S = s_hi - a.s0;
-                }
-                a.tile = batch_tile(t, p->n);
-                a.halo = 4 * t.steps + 4;
-                a.k = k;
-                a.xin = (j % 2 == 0) ? buf0[i] : buf1[i];
-                a.xout = (j % 2 == 0) ? buf1[i] : buf0[i];
-                a.obs_stride = p->d.obs_stride;
-                a.obs_every = p->d.obs_every;
-                a.n_obs = p->n_obs;
-                a.n_t = p->n_t;
-                a.inv_sigma_o = static_cast<T>(1.0 / p->d.sigma_o);
-                a.z = mode == MODE_TLM ? z[i] : nullptr;
-                a.w = mode == MODE_ADJ ? w[i] : nullptr;
-                const int ntile = (p->n + a.tile - 1) / a.tile;
-                for (int g = 0; g < groups; ++g)
-                    for (int tl = 0; tl < ntile; ++tl)
-                        items.push_back(make_int4(static_cast<int>(args.size()) - aoff[j], tl, g, 0));
-                flops[j] += static_cast<double>(a.S) * p->n *
-                            (mode == MODE_TLM ? (FL_TLM_VEC * k + FL_TLM_BASE) : (FL_ADJ_VEC * k + FL_ADJ_BASE));
-                if (j == nlp - 1) result[i] = a.xout;
-            }
-            args.push_back(a);
+    std::vector<BatchProb> bp(np);
+    for (int i = 0; i < np; ++i) bp[i] = batch_prob(b->probs[sel[i]], trajs[i]);
+    const double fv = mode == MODE_TLM ? FL_TLM_VEC : FL_ADJ_VEC, fb = mode == MODE_TLM ? FL_TLM_BASE : FL_ADJ_BASE;
+    for_interval_chunks(b, bp, t, groups, sizeof(SweepArgs<T>), [&](int j0, int j1) {
+        const IntervalTables<SweepArgs<T>> tb = plan_sweep<T>(mode, bp, k, t, buf0, buf1, z, w, j0, j1, fv, fb);
+        auto [dargs, ditems] = stage(b, tb.args, tb.items);
+        const int4* dit = reinterpret_cast<const int4*>(ditems);
+        for (int j = j0; j < j1; ++j) {
+            const int q = j - j0;
+            KernelTimer kt(b->ctx, mode == MODE_TLM ? RP4D_K_TLM : RP4D_K_ADJ, tb.flops[q]);
+            launch_burgers_sweep_batched<T>(mode, dargs + tb.aoff[q], dit + tb.off[q], tb.off[q + 1] - tb.off[q], t,
+                                            st);
         }
-    }
-    off[nl] = static_cast<int>(items.size());
-    SweepArgs<T>* dargs = stage(b, args);
-    int4* ditems = stage(b, items);
-    for (int j = 0; j < nl; ++j) {
-        KernelTimer kt(b->ctx, mode == MODE_TLM ? RP4D_K_TLM : RP4D_K_ADJ, flops[j]);
-        launch_burgers_sweep_batched<T>(mode, dargs + aoff[j], ditems + off[j], off[j + 1] - off[j], t, st);
-    }
-    for (int i = 0; i < np; ++i)
-        if (!result[i]) result[i] = buf0[i];  // no steps: state unchanged
-    return result;
+    });
+    return sweep_result<T>(bp, t, buf0, buf1);
 }
 
 // Gamma^{1/2} for every selected problem: out[i] (layout out_kc) = Gamma^{1/2} in[i]
@@ -3198,7 +3216,8 @@ void batch_bhalf(rp4d_batch* b, const std::vector<int>& sel, int k, const std::v
     }
     if (gd.empty()) return;
     batch_gram<double, T>(b, gd, gown);
-    launch_btsmm<double, T>(stage(b, md), stage(b, items), static_cast<int>(items.size()), st);
+    auto [d_md, d_items] = stage(b, md, items);
+    launch_btsmm<double, T>(d_md, d_items, static_cast<int>(items.size()), st);
 }
 
 // Workspace of the batched block sweeps of problem p for k vectors.
@@ -3239,7 +3258,8 @@ void batch_hessian(rp4d_batch* b, const std::vector<int>& sel, const std::vector
             cnt.push_back(static_cast<size_t>(b->probs[sel[i]]->n) * gt * tt.kc);
         }
         auto it = elem_items(cnt);
-        launch_bcopy<T, T>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_cd, d_it] = stage(b, cd, it);
+        launch_bcopy<T, T>(d_cd, d_it, static_cast<int>(it.size()), st);
     }
     batch_bhalf<T>(b, sel, k, V, k, s0, tt.kc, none);
     batch_sweep_run<T>(b, MODE_TLM, sel, trajs, k, tt, s0, s1, obs, none);
@@ -3302,11 +3322,13 @@ void batch_precond_apply(rp4d_batch* b, const std::vector<int>& sel, const std::
     }
     if (!cd.empty()) {
         auto it = elem_items(cnt);
-        launch_bcopy<double, double>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_cd, d_it] = stage(b, cd, it);
+        launch_bcopy<double, double>(d_cd, d_it, static_cast<int>(it.size()), st);
     }
     if (!gd.empty()) {
         batch_gram<double, double>(b, gd, gown);
-        launch_btsmm<double, double>(stage(b, md), stage(b, items), static_cast<int>(items.size()), st);
+        auto [d_md, d_items] = stage(b, md, items);
+        launch_btsmm<double, double>(d_md, d_items, static_cast<int>(items.size()), st);
     }
 }
 
@@ -3316,7 +3338,7 @@ void batch_dot(rp4d_batch* b, const std::vector<int>& sel, const std::vector<con
     std::vector<BVec> vd;
     for (size_t i = 0; i < sel.size(); ++i)
         vd.push_back(BVec{x[i], y[i], b->scal.as<double>() + 16 * sel[i] + slot, b->probs[sel[i]]->n});
-    launch_bdot(stage(b, vd), static_cast<int>(vd.size()), absmax, b->ctx->stream);
+    launch_bdot(stage1(b, vd), static_cast<int>(vd.size()), absmax, b->ctx->stream);
 }
 
 std::vector<double> batch_read_scal(rp4d_batch* b) {
@@ -3330,7 +3352,8 @@ void batch_axpby(rp4d_batch* b, std::vector<BAxpby> ad) {
     std::vector<size_t> cnt;
     for (auto& a : ad) cnt.push_back(a.count);
     auto it = elem_items(cnt);
-    launch_baxpby(stage(b, ad), stage(b, it), static_cast<int>(it.size()), b->ctx->stream);
+    auto [d_ad, d_it] = stage(b, ad, it);
+    launch_baxpby(d_ad, d_it, static_cast<int>(it.size()), b->ctx->stream);
 }
 
 // Batched lockstep PCG (FP64) on (I + H_i) x_i = b_i; returns per-problem iterations.
@@ -3376,8 +3399,8 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
     for (int i = 0; i < np; ++i) {
         bnorm[i] = std::sqrt(sc[16 * sel[i] + SC_BB]);
         RP4D_REQUIRE(std::isfinite(bnorm[i]), RP4D_ENONFINITE, "non-finite right-hand side in batch");
-        if (bnorm[i] == 0.0)
-            conv[i] = 1;
+        if (bnorm[i] == 0.0 || bnorm[i] <= rtol * bnorm[i])
+            conv[i] = 1;  // b = 0 or rtol >= 1: x_0 = 0 meets the tolerance
         else
             act.push_back(i);
     }
@@ -3406,8 +3429,7 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
         std::vector<const double*> caq(aq.begin(), aq.end());
         batch_dot(b, asel, ap, caq, SC_PQ);
         auto items = elem_items(cnt);
-        BPcg* dpd = stage(b, apd);
-        int4* dit = stage(b, items);
+        auto [dpd, dit] = stage(b, apd, items);
         launch_bpcg_xr(dpd, dit, static_cast<int>(items.size()), st);
         std::vector<const double*> ar, az;
         std::vector<double*> azm;
@@ -3450,7 +3472,8 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
         std::vector<const double*> csz(sz.begin(), sz.end());
         batch_dot(b, ssel2, sr, csz, SC_RZN);
         auto sitems = elem_items(scnt);
-        launch_bpcg_p(stage(b, spd), stage(b, sitems), static_cast<int>(sitems.size()),
+        auto [d_spd, d_sitems] = stage(b, spd, sitems);
+        launch_bpcg_p(d_spd, d_sitems, static_cast<int>(sitems.size()),
                       static_cast<int>(spd.size()), st);
         act = still;
     }
@@ -3479,7 +3502,8 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
             cnt.push_back((c + 1) / 2);
         }
         auto it = elem_items(cnt);
-        launch_bphilox(stage(b, rd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_rd, d_it] = stage(b, rd, it);
+        launch_bphilox(d_rd, d_it, static_cast<int>(it.size()), st);
     }
     auto copyall = [&](auto tag_in, auto tag_out, auto src, auto dst, bool rows_m) {
         using TI = decltype(tag_in);
@@ -3493,7 +3517,8 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
             cnt.push_back(static_cast<size_t>(rows) * l);
         }
         auto it = elem_items(cnt);
-        launch_bcopy<TI, TO>(stage(b, cd), stage(b, it), static_cast<int>(it.size()), st);
+        auto [d_cd, d_it] = stage(b, cd, it);
+        launch_bcopy<TI, TO>(d_cd, d_it, static_cast<int>(it.size()), st);
     };
     // Y0 = H Omega (data-misfit part) in the sketch precision, kept as FP64 in Yd
     if (dtype == RP4D_F64) {
@@ -3530,10 +3555,9 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
         sk[i] = BSketch{S[i].ev, S[i].nu, S[i].lam, S[i].D, S[i].S2, p->n};
     }
     batch_gram<double, double>(b, gd, owners);
-    launch_bjacobi(stage(b, sm), np, l, false, st);
+    launch_bjacobi(stage1(b, sm), np, l, false, st);
     const double eps = dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
-    BSketch* dsk = stage(b, sk);
-    launch_bnu(dsk, np, eps, st);
+    launch_bnu(stage1(b, sk), np, eps, st);
     // shifted core matrix and its Cholesky factor, with tenfold shift retries
     std::vector<int> todo(np);
     for (int i = 0; i < np; ++i) todo[i] = i;
@@ -3560,7 +3584,7 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
         std::vector<rp4d_problem*> cown;
         for (int i : todo) cown.push_back(b->probs[sel[i]]);
         batch_gram<double, double>(b, cg, cown);
-        launch_bchol(stage(b, cs), static_cast<int>(cs.size()), l, st);
+        launch_bchol(stage1(b, cs), static_cast<int>(cs.size()), l, st);
         std::vector<int> failed;
         std::vector<int> infos(todo.size(), 0);
         for (size_t q = 0; q < todo.size(); ++q)
@@ -3600,14 +3624,15 @@ std::vector<rp4d_precond*> batch_nystrom(rp4d_batch* b, const std::vector<int>& 
             for (int cb = 0; cb * 64 < l; ++cb) vit.push_back(make_int4(i, rb, cb, 0));
     }
     try {
-        launch_btrinv(stage(b, t1), np, l, st);
+        launch_btrinv(stage1(b, t1), np, l, st);
         batch_gram<double, double>(b, yy, owners);
-        launch_bgemm_small(stage(b, g1), np, l, 0, 0, 1.0, st);
-        launch_bgemm_small(stage(b, g2), np, l, 0, 1, 1.0, st);
-        launch_bjacobi(stage(b, ej), np, l, true, st);
-        launch_bfinalize(dsk, np, l, true, st);  // lam, D and U <- U diag(1/sigma)
-        launch_bgemm_small(stage(b, g3), np, l, 1, 0, 1.0, st);
-        launch_btsmm<double, double>(stage(b, vm), stage(b, vit), static_cast<int>(vit.size()), st);
+        launch_bgemm_small(stage1(b, g1), np, l, 0, 0, 1.0, st);
+        launch_bgemm_small(stage1(b, g2), np, l, 0, 1, 1.0, st);
+        launch_bjacobi(stage1(b, ej), np, l, true, st);
+        launch_bfinalize(stage1(b, sk), np, l, true, st);  // lam, D and U <- U diag(1/sigma)
+        launch_bgemm_small(stage1(b, g3), np, l, 1, 0, 1.0, st);
+        auto [d_vm, d_vit] = stage(b, vm, vit);
+        launch_btsmm<double, double>(d_vm, d_vit, static_cast<int>(vit.size()), st);
         std::vector<double> nuh(np);
         for (int i = 0; i < np; ++i) {
             launch_relayout<double, double>(S[i].D, 1, out[i]->Dg.as<double>(), 1, l, 1, st);
@@ -3707,7 +3732,7 @@ int rp4d_batch_fwd(rp4d_batch* b, const double* const* x0, rp4d_traj* const* tra
             }
             std::vector<BVec> vd;
             for (int i = 0; i < np; ++i) vd.push_back(BVec{in[i], in[i], b->scal.as<double>() + 16 * i + SC_T0, b->probs[i]->m});
-            launch_bdot(stage(b, vd), np, false, b->ctx->stream);
+            launch_bdot(stage1(b, vd), np, false, b->ctx->stream);
             std::vector<double> sc = batch_read_scal(b);
             for (int i = 0; i < np; ++i) J_obs[i] = 0.5 * sc[16 * i + SC_T0];
         }
@@ -3793,7 +3818,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
                 vd.push_back(BVec{in, in, b->scal.as<double>() + 16 * i + SC_T0, b->probs[i]->m});
                 vd.push_back(BVec{v[i], v[i], b->scal.as<double>() + 16 * i + SC_T2, b->probs[i]->n});
             }
-            launch_bdot(stage(b, vd), static_cast<int>(vd.size()), false, st);
+            launch_bdot(stage1(b, vd), static_cast<int>(vd.size()), false, st);
         }
         // 2. gradient, |g|_inf, b = -g
         batch_gradient(b, sel, ctr, v, gm);
@@ -3840,7 +3865,8 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
                     ttr.push_back(tr[i]);
                 }
                 auto it = elem_items(cnt);
-                launch_bphilox(stage(b, rd), stage(b, it), static_cast<int>(it.size()), st);
+                auto [d_rd, d_it] = stage(b, rd, it);
+                launch_bphilox(d_rd, d_it, static_cast<int>(it.size()), st);
                 batch_precond_apply(b, test, tp, vh, zz);
                 cz.assign(zz.begin(), zz.end());
                 batch_hessian<double>(b, test, ttr, 1, cz, qq, true);

@@ -131,6 +131,7 @@ _SIGS = {
     "rp4d_gradient": ([_P, _P, _P, _P], _I),
     "rp4d_bve_inv_laplacian": ([_P, _I, _P, _P, _I], _I),
     "rp4d_build_precond": ([_P, _P, _I, _I, ctypes.c_uint64, _P, _I, ctypes.POINTER(_P)], _I),
+    "rp4d_build_precond_from_sketch": ([_P, _I, _P, _P, ctypes.POINTER(_P)], _I),
     "rp4d_build_precond_adaptive": ([_P, _P, ctypes.POINTER(AdaptiveOpts), ctypes.POINTER(_P),
                                      ctypes.POINTER(AdaptiveInfo)], _I),
     "rp4d_build_precond_singleview": ([_P, _P, ctypes.POINTER(SingleViewOpts), ctypes.POINTER(_P)], _I),
@@ -350,6 +351,15 @@ class Problem:
         h = ctypes.c_void_p()
         om = _ptr(omega, torch.float64, self.n * ell, "omega") if omega is not None else None
         _check(_lib.rp4d_build_precond(self._h, traj._h, method, ell, seed, om, sketch_dtype, ctypes.byref(h)))
+        return Precond(self, h, ell)
+
+    def build_precond_from_sketch(self, omega, Y):
+        """Nystrom approximation from a given sketch: omega and Y = H omega,
+        device (n, ell) FP64 tensors."""
+        ell = omega.shape[1]
+        h = ctypes.c_void_p()
+        _check(_lib.rp4d_build_precond_from_sketch(self._h, ell, _ptr(omega, torch.float64, self.n * ell, "omega"),
+                                                   _ptr(Y, torch.float64, self.n * ell, "Y"), ctypes.byref(h)))
         return Precond(self, h, ell)
 
     def build_precond_adaptive(self, traj, ell0, ell_hat, ell_max, eps_sk=1.01, seed=0, omega=None, vtest=None,

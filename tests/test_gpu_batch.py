@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from gpu_util import colwise_relerr, need_gpu, relerr, to_dev, to_np
+from oracle import rng as orng
 from paper_2401_15758_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -140,9 +141,9 @@ def test_batched_gn_step_matches_oracle():
     ell, seed = 12, 77
     infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=ell, seed=seed, rtol=1e-12)
     for i, (o, p) in enumerate(zip(orcs, probs)):
-        om = torch.empty(o.n * ell, dtype=torch.float64, device="cuda")
-        ctx.philox_normal(_omega_seed(seed, 100 + i), om.numel(), om)
-        Om = to_np(om).reshape(o.n, ell)
+        # the batch draws Omega on the device from the problem id; the oracle
+        # reproduces the same stream with its own generator
+        Om = orng.gaussian_matrix(_omega_seed(seed, 100 + i), o.n, ell)
         v1, dv, x1, info = ogn.gn_step(o, np.zeros(o.n), method='nystrom', Omega=Om, rtol=1e-12)
         gv, gx = states[i].get()
         assert infos[i]['J'] == pytest.approx(info['J'], rel=1e-12)
@@ -178,3 +179,32 @@ def test_batched_gn_fp32_sketch_and_mix_invariance():
     torch.cuda.synchronize()
     # random draws follow the problem id, reductions are per problem: bitwise equal
     assert torch.equal(xa, xm)
+
+
+# the extremes of batch-64's ranges: n 256 and 4096 (the 4096-point problems at
+# the stability-limited step), windows of 50 and 500 steps
+EXTREMES = [inputs.burgers_config(256, 50, 4, 10, dt_cfg=1e-3, name='b256-50'),
+            inputs.burgers_config(4096, 500, 4, 10, dt_cfg=1e-3, name='b4096-500'),
+            inputs.burgers_config(256, 500, 4, 10, dt_cfg=1e-3, name='b256-500'),
+            inputs.burgers_config(4096, 50, 4, 10, dt_cfg=1e-3, name='b4096-50')]
+
+
+def test_batched_gn_step_at_the_extremes_matches_oracle():
+    """One batched GN step (32-column Nystrom sketches drawn on the device,
+    FP64, rtol 1e-12) over problems at the corners of batch-64's size and window
+    ranges, against the oracle per problem: x+ within 1e-10."""
+    need_gpu()
+    from oracle import gn as ogn
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(EXTREMES, seeds=[11, 12, 13, 14])
+    b = rp4d.Batch(ctx, probs)
+    states = [p.gn_state() for p in probs]
+    ell, seed = 32, 91
+    infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=ell, seed=seed, rtol=1e-12)
+    for i, (o, p) in enumerate(zip(orcs, probs)):
+        Om = orng.gaussian_matrix(_omega_seed(seed, 100 + i), o.n, ell)
+        _, dv, x1, info = ogn.gn_step(o, np.zeros(o.n), method='nystrom', Omega=Om, rtol=1e-12)
+        _, gx = states[i].get()
+        assert infos[i]['J'] == pytest.approx(info['J'], rel=1e-12), i
+        assert infos[i]['pcg_converged'], i
+        assert relerr(to_np(gx), x1) <= 1e-10, i

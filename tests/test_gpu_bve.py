@@ -198,3 +198,46 @@ def test_gn_step_graph_replay_bitwise():
     pr.ctx.set_graphs(False)
     assert its[0] == its[1] and its[0] >= 5
     assert torch.equal(xs[0], xs[1])
+
+
+# --- bve-256 over its whole 200-step window (the measured 2-D workload) ---
+# The oracle's pieces are cached per module so that each test stays within a
+# minute of host time: the trajectory, then the TLM of two columns, then their
+# ADJ.
+
+@pytest.fixture(scope="module")
+def bve256():
+    need_gpu()
+    pr = Pair(inputs.CFG_BVE, seed=0)
+    _ = pr.otraj
+    return pr
+
+
+@pytest.fixture(scope="module")
+def bve256_tlm(bve256):
+    V = _rand((bve256.orc.n, 2), 256)
+    return V, bve256.orc.A(bve256.otraj, V)
+
+
+def test_bve256_full_window_observations(bve256):
+    pr = bve256
+    obs = to_np(pr.gpu.observe(pr.traj))
+    assert relerr(obs, pr.orc.observe(pr.otraj)) <= 1e-12
+
+
+def test_bve256_full_window_tlm(bve256, bve256_tlm):
+    """Two TLM columns over 200 steps (800 RK4 stages, one spectral Poisson
+    solve per stage and column) against the oracle at 1e-12 per column."""
+    pr = bve256
+    V, Z = bve256_tlm
+    got = to_np(pr.gpu.tlm(pr.traj, to_dev(V))).reshape(Z.shape)
+    assert colwise_relerr(got.reshape(-1, 2), Z.reshape(-1, 2)) <= TOL_OP
+
+
+def test_bve256_full_window_hessian(bve256, bve256_tlm):
+    """(I + A^T A) V for the same two columns: 1e-12 per column."""
+    pr = bve256
+    V, Z = bve256_tlm
+    ref = V + pr.orc.AT(pr.otraj, Z)
+    HV = to_np(pr.gpu.hessian_block(pr.traj, to_dev(V)))
+    assert colwise_relerr(HV, ref) <= TOL_OP

@@ -455,8 +455,10 @@ def test_sketch_parity_at_the_largest_size(method):
 @pytest.mark.parametrize("method", ["nystrom", "randsvd"])
 def test_gn_step_exact_and_factored_preconditioners_agree(method):
     """SketchPrec with the eigen-decomposed preconditioner (exact_lmp) and with
-    the factored form (the default) reach the oracle's step to 1e-10 with the
-    same PCG iteration count."""
+    the factored form (the default) reach the oracle's step to 1e-10.  The two
+    operators differ by at most the Nystrom shift nu in norm (the factored form
+    keeps the shift), so at rtol 1e-12, the attainable accuracy, their PCG
+    iteration counts may differ by one, and from the oracle's by one."""
     need_gpu()
     from paper_2401_15758_amd import rp4d
     pr = Pair(inputs.CFG_SMALL)
