@@ -198,7 +198,11 @@ def batch_section(rp4d, inputs, torch, np):
         probs.append(p)
         states.append(p.gn_state())
     b = rp4d.Batch(ctx, probs)
-    res = {"workload": "batch-64", "problems": len(cfgs), "k": 32}
+    from paper_2401_15758_amd import autotune
+    # the batched sweep tilings found by the batched search (tuning.json), per precision
+    tuned = {name: autotune.apply_cached_batch(b, 32, dt) for name, dt in (("f64", rp4d.F64), ("f32", rp4d.F32))}
+    res = {"workload": "batch-64", "problems": len(cfgs), "k": 32,
+           "tiling": {name: (ent["sweep"] if ent else "library default") for name, ent in tuned.items()}}
     for name, skd in (("f64", rp4d.F64), ("f32", rp4d.F32)):
         times = []
         for rep in range(3):

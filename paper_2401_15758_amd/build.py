@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librp4d.so")
 
-SOURCES = ["api.hip", "burgers_sweep.hip", "burgers_wall.hip", "linalg.hip", "batch_kernels.hip", "bve.hip"]
+SOURCES = ["api.hip", "burgers_sweep.hip", "burgers_wall.hip", "linalg.hip", "batch_kernels.hip", "bve.hip",
+           "fft2d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

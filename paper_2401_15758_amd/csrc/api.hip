@@ -775,8 +775,8 @@ using namespace rp4d;
 
 namespace {
 rp4d_problem* create_bve(rp4d_ctx* ctx, const rp4d_problem_desc& d) {
-    RP4D_REQUIRE(d.nx == d.ny && d.nx >= 16 && d.nx <= 2048 && d.nx % 16 == 0, RP4D_EINVAL,
-                 "2-D grid must be square with nx a multiple of 16 in [16, 2048]");
+    RP4D_REQUIRE(d.nx == d.ny && fft_size_supported(d.nx), RP4D_EINVAL,
+                 "2-D grid must be square with side 16 B, B in {2,3,4,5,6,8,10,12,16,20,24,32}");
     RP4D_REQUIRE(d.nsteps >= 1 && d.obs_every >= 1 && d.obs_stride >= 1 && d.obs_stride <= d.nx, RP4D_EINVAL,
                  "bad window / observation layout");
     RP4D_REQUIRE(d.nsteps / d.obs_every >= 1, RP4D_EINVAL, "window has no observation step");

@@ -1,8 +1,8 @@
 // Barotropic vorticity model on the periodic unit square (the 2-D workload of
 // Sec. 5.2 in periodic form): nonlinear RK4 sweep, discrete RK4 tangent-linear
 // and adjoint sweeps over blocks of k perturbations, the separable Gaussian
-// prior square root, and the spectral inverse Laplacian as dense products with
-// the real Fourier basis on the matrix cores.
+// prior square root, and the spectral inverse Laplacian by fast Fourier
+// transforms.
 //
 //   zeta_t = f(zeta) = -J_A(L zeta, zeta) + nu lap(zeta),   L = lap^{-1} (zero mean)
 //   TLM:  f'(Y) w     = -J_A(L w, Y) - J_A(psi_Y, w) + nu lap(w)
@@ -18,9 +18,9 @@
 // state zeta_s and, per step, the RK4 stage values Y2..Y4 and their stream
 // functions psi1..psi4, so the linearised sweeps recompute nothing.
 //
-// L and the prior are diagonal in the tensor product of 1-D real Fourier bases
-// B (orthonormal cos/sin columns): X -> B_y (D .* (B_y^T X B_x)) B_x^T, four
-// dense products per field, each an MFMA GEMM over the whole block.
+// L and the prior are diagonal in the 2-D Fourier basis with even diagonals, so
+// both are applied as F^{-1} (D .* F X) by the FFTs of fft2d.hip, two real fields
+// per complex transform.
 #include <cmath>
 #include <vector>
 
@@ -30,182 +30,6 @@ namespace rp4d {
 namespace {
 
 #pragma clang fp contract(off)
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    typedef v4d acc_t;
-    static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // accumulator element r of lane l holds row 4r + l/16 (column l%16)
-    static __device__ __forceinline__ int row(int quad, int r) { return 4 * r + quad; }
-};
-template <>
-struct Mfma<float> {
-    typedef v4f acc_t;
-    static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // accumulator element r of lane l holds row 4(l/16) + r (column l%16)
-    static __device__ __forceinline__ int row(int quad, int r) { return 4 * quad + r; }
-};
-
-// C[b] (M x N) = A[b] (M x K) B[b] (K x N), all row-major, optionally scaled
-// element-wise by D[m * ldd + n / cdiv] (the spectral diagonal).
-template <typename T>
-struct GemmArgs {
-    const T* A;
-    long lda, sA;
-    const T* B;
-    long ldb, sB;
-    T* C;
-    long ldc, sC;
-    const T* D;
-    long ldd;
-    int cdiv;
-    int M, N, K;
-};
-
-constexpr int GBK = 16, GPAD = 16;
-
-// Output tile (32 TM) x (32 TN) per workgroup of four waves (2 x 2), each wave
-// TM x TN MFMA 16x16x4 blocks.  Operand fragments: lane l holds A[l%16][l/16]
-// and B[l/16][l%16]; the accumulator rows held by a lane differ between the
-// FP64 and FP32 instructions (Mfma<T>::row).  K is consumed in chunks of 16
-// staged through LDS (k-major, rows padded by 16 elements so the two
-// half-waves of a fragment read hit disjoint banks); the next chunk's global
-// loads are issued before the current chunk's MFMAs.
-template <typename T, int TM, int TN>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs<T> g) {
-    constexpr int BM = 32 * TM, BN = 32 * TN;
-    constexpr int AQ = BM * GBK / 256, BQ = BN * GBK / 256;  // elements per thread per chunk
-    __shared__ T As[GBK][BM + GPAD];
-    __shared__ T Bs[GBK][BN + GPAD];
-    typedef typename Mfma<T>::acc_t acc_t;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 16 * TM, wn = (wave & 1) * 16 * TN;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const long b = blockIdx.z;
-    const T* A = g.A + b * g.sA;
-    const T* B = g.B + b * g.sB;
-    T* C = g.C + b * g.sC;
-    // loader coordinates: AQ consecutive k of one A row, BQ consecutive columns of one B row
-    const int ar = tid / (GBK / AQ), ak = (tid % (GBK / AQ)) * AQ;
-    const int bk = tid / (BN / BQ), bn = (tid % (BN / BQ)) * BQ;
-    const bool arow_ok = m0 + ar < g.M;
-    T ra[AQ], rb[BQ];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < AQ; ++q) {
-            const int kk = k0 + ak + q;
-            ra[q] = (arow_ok && kk < g.K) ? A[static_cast<long>(m0 + ar) * g.lda + kk] : T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < BQ; ++q) {
-            const int cc = n0 + bn + q;
-            rb[q] = (k0 + bk < g.K && cc < g.N) ? B[static_cast<long>(k0 + bk) * g.ldb + cc] : T(0);
-        }
-    };
-    acc_t acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    load(0);
-    const int fr = lane >> 4, fc = lane & 15;
-    for (int k0 = 0; k0 < g.K; k0 += GBK) {
-#pragma unroll
-        for (int q = 0; q < AQ; ++q) As[ak + q][ar] = ra[q];
-#pragma unroll
-        for (int q = 0; q < BQ; ++q) Bs[bk][bn + q] = rb[q];
-        __syncthreads();
-        if (k0 + GBK < g.K) load(k0 + GBK);
-#pragma unroll
-        for (int kk = 0; kk < GBK; kk += 4) {
-            T af[TM], bf[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = As[kk + fr][wm + i * 16 + fc];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) bf[j] = Bs[kk + fr][wn + j * 16 + fc];
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(af[i], bf[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm + i * 16 + Mfma<T>::row(fr, r);
-                const int col = n0 + wn + j * 16 + fc;
-                if (row < g.M && col < g.N) {
-                    T v = acc[i][j][r];
-                    if (g.D) v = v * g.D[static_cast<long>(row) * g.ldd + col / g.cdiv];
-                    C[static_cast<long>(row) * g.ldc + col] = v;
-                }
-            }
-}
-
-// Small products (single fields): a 16 x 16 output tile per workgroup of four
-// waves, each wave accumulating a contiguous quarter of K straight from global
-// memory into registers (16 MFMA steps per batch of loads, so one memory
-// latency per batch), then the four partial tiles are summed in a fixed order
-// through LDS.  K must be a multiple of 16.
-template <typename T>
-__global__ void __launch_bounds__(256) gemm_ksplit_kernel(GemmArgs<T> g) {
-    typedef typename Mfma<T>::acc_t acc_t;
-    __shared__ T part[3][64][4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
-    const long b = blockIdx.z;
-    const T* A = g.A + b * g.sA;
-    const T* B = g.B + b * g.sB;
-    T* C = g.C + b * g.sC;
-    const int fr = lane >> 4, fc = lane & 15;
-    const int arow = m0 + fc, bcol = n0 + fc;
-    const bool aok = arow < g.M, bok = bcol < g.N;
-    const int kq = g.K / 4, kw0 = wave * kq, kw1 = kw0 + kq;
-    acc_t acc = acc_t{0, 0, 0, 0};
-    for (int kb = kw0; kb < kw1; kb += 64) {
-        T a[16], bb[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int k = kb + 4 * s + fr;
-            const bool kin = k < kw1;
-            a[s] = (aok && kin) ? A[static_cast<long>(arow) * g.lda + k] : T(0);
-            bb[s] = (bok && kin) ? B[static_cast<long>(k) * g.ldb + bcol] : T(0);
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s) acc = Mfma<T>::mac(a[s], bb[s], acc);
-    }
-    if (wave > 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) part[wave - 1][lane][r] = acc[r];
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const T v0 = acc[r] + part[0][lane][r];
-            const T v1 = part[1][lane][r] + part[2][lane][r];
-            const int row = m0 + Mfma<T>::row(fr, r), col = n0 + fc;
-            if (row < g.M && col < g.N) {
-                T v = v0 + v1;
-                if (g.D) v = v * g.D[static_cast<long>(row) * g.ldd + col / g.cdiv];
-                C[static_cast<long>(row) * g.ldc + col] = v;
-            }
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // stencils
@@ -395,64 +219,38 @@ inline unsigned ublk(long count, int t = 256) { return static_cast<unsigned>((co
 // ---------------------------------------------------------------------------
 inline hipStream_t bst(const rp4d_problem* p) { return p->ctx->stream; }
 
+// Twiddles exp(-2 pi i m / n) of the two axes and the two diagonals (ny x nx,
+// FFT order, 1/(nx ny) folded in) in the working precision.
 template <typename T>
-struct Basis {
-    const T *Bx, *BxT, *By, *ByT, *Dlap, *Dpri;
+struct Spec {
+    const T *Wx, *Wy, *Dlap, *Dpri;
 };
 
 template <typename T>
-Basis<T> basis_of(const rp4d_problem* p) {
+Spec<T> spec_of(const rp4d_problem* p) {
     const BveData& b = *p->bve;
-    const T* base = sizeof(T) == 8 ? b.basis.as<T>() : b.basis_f.as<T>();
-    const size_t sx = static_cast<size_t>(b.nx) * b.nx, sy = static_cast<size_t>(b.ny) * b.ny;
-    Basis<T> r;
-    r.Bx = base;
-    r.BxT = base + sx;
-    r.By = base + 2 * sx;
-    r.ByT = base + 2 * sx + sy;
+    const T* tw = sizeof(T) == 8 ? b.tw.as<T>() : b.tw_f.as<T>();
+    Spec<T> r;
+    r.Wx = tw;
+    r.Wy = tw + 2 * b.nx;
     r.Dlap = sizeof(T) == 8 ? b.dlap.as<T>() : b.dlap_f.as<T>();
     r.Dpri = sizeof(T) == 8 ? b.dpri.as<T>() : b.dpri_f.as<T>();
     return r;
 }
 
-template <typename T>
-void gemm(rp4d_problem* p, const GemmArgs<T>& g, int batch) {
-    const double fl = 2.0 * g.M * static_cast<double>(g.N) * g.K * batch;
-    KernelTimer kt(p->ctx, RP4D_K_GEMM, fl);
-    RP4D_REQUIRE(g.K % 16 == 0, RP4D_EINVAL, "Fourier-basis product: K must be a multiple of 16");
-    // 64 x 64 tiles when they give at least two workgroups per CU, 32 x 32 when
-    // those fill the CUs, else (single fields) 16 x 16 tiles with K split over waves
-    const long big = static_cast<long>((g.N + 63) / 64) * ((g.M + 63) / 64) * batch;
-    const long mid = static_cast<long>((g.N + 31) / 32) * ((g.M + 31) / 32) * batch;
-    if (big >= 512) {
-        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch);
-        gemm_kernel<T, 2, 2><<<grid, 256, 0, bst(p)>>>(g);
-    } else if (mid >= 256) {
-        dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, batch);
-        gemm_kernel<T, 1, 1><<<grid, 256, 0, bst(p)>>>(g);
-    } else {
-        dim3 grid((g.N + 15) / 16, (g.M + 15) / 16, batch);
-        gemm_ksplit_kernel<T><<<grid, 256, 0, bst(p)>>>(g);
-    }
-    RP4D_HIP(hipGetLastError());
-}
-
-// out = B_y (D .* (B_y^T X B_x)) B_x^T for k field-major fields X; t1, t2 scratch (k fields).
-// out may alias X.
+// out = F^{-1} (D .* F X) for k field-major fields X (out may alias X): the
+// fields go through the FFT as ceil(k/2) complex pairs held in t1 .. t1 + 2kn,
+// which must be the two consecutive k-field scratch blocks t1, t2.
 template <typename T>
 void spectral_apply(rp4d_problem* p, int k, const T* X, const T* D, T* out, T* t1, T* t2) {
     const BveData& b = *p->bve;
-    const Basis<T> bs = basis_of<T>(p);
-    const int nx = b.nx, ny = b.ny;
-    const long n = static_cast<long>(nx) * ny;
-    // T1 = X B_x   ((k ny) x nx)
-    gemm<T>(p, GemmArgs<T>{X, nx, 0, bs.Bx, nx, 0, t1, nx, 0, nullptr, 0, 1, k * ny, nx, nx}, 1);
-    // T2_v = D .* (B_y^T T1_v)
-    gemm<T>(p, GemmArgs<T>{bs.ByT, ny, 0, t1, nx, n, t2, nx, n, D, nx, 1, ny, nx, ny}, k);
-    // T1_v = B_y T2_v
-    gemm<T>(p, GemmArgs<T>{bs.By, ny, 0, t2, nx, n, t1, nx, n, nullptr, 0, 1, ny, nx, ny}, k);
-    // out = T1 B_x^T
-    gemm<T>(p, GemmArgs<T>{t1, nx, 0, bs.BxT, nx, 0, out, nx, 0, nullptr, 0, 1, k * ny, nx, nx}, 1);
+    const long n = static_cast<long>(b.nx) * b.ny;
+    RP4D_REQUIRE(t2 == t1 + static_cast<long>(k) * n, RP4D_EINVAL, "spectral scratch must be two consecutive blocks");
+    // FFT-equivalent flops: one complex 2-D transform pair (5 N log2 N each) per two fields
+    const double fl = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(n)) * k;
+    KernelTimer kt(p->ctx, RP4D_K_GEMM, fl);
+    const Spec<T> sp = spec_of<T>(p);
+    launch_spectral_diag<T>(X, k, b.nx, b.ny, D, sp.Wx, sp.Wy, t1, out, bst(p));
 }
 
 // Per-point flop counts of the stencil kernels (Arakawa form 34 incl. the
@@ -488,66 +286,45 @@ void bve_setup(rp4d_problem* p) {
     b->ny = d.ny;
     b->d = 1.0 / d.nx;
     const int nx = d.nx, ny = d.ny;
-    // 1-D orthonormal real Fourier basis: column 0 constant, 2m-1 / 2m cos / sin of
-    // wavenumber m (1 <= m < n/2), n-1 the alternating Nyquist mode.
-    auto make_basis = [](int n, std::vector<double>& B, std::vector<double>& BT, std::vector<int>& wn) {
-        B.assign(static_cast<size_t>(n) * n, 0.0);
-        BT.assign(static_cast<size_t>(n) * n, 0.0);
-        wn.assign(n, 0);
-        const double c0 = 1.0 / std::sqrt(static_cast<double>(n)), c1 = std::sqrt(2.0 / n);
-        for (int c = 0; c < n; ++c) wn[c] = c == 0 ? 0 : (c == n - 1 ? n / 2 : (c + 1) / 2);
-        for (int i = 0; i < n; ++i)
-            for (int c = 0; c < n; ++c) {
-                double v;
-                const long q = (static_cast<long>(wn[c]) * i) % n;
-                const double th = 2.0 * M_PI * static_cast<double>(q) / n;
-                if (c == 0)
-                    v = c0;
-                else if (c == n - 1)
-                    v = (i & 1) ? -c0 : c0;
-                else if (c & 1)
-                    v = c1 * std::cos(th);
-                else
-                    v = c1 * std::sin(th);
-                B[static_cast<size_t>(i) * n + c] = v;
-                BT[static_cast<size_t>(c) * n + i] = v;
-            }
-    };
+    RP4D_REQUIRE(fft_size_supported(nx) && fft_size_supported(ny), RP4D_EINVAL,
+                 "2-D grid: sides must be 16 B with B in {2,3,4,5,6,8,10,12,16,20,24,32}");
+    // wavenumber of FFT index c on an n-point axis (|.| is what the diagonals need)
+    auto wn = [](int c, int n) { return c <= n / 2 ? c : n - c; };
     // eigenvalues of the circulant square root of the Gaussian kernel (cell units):
     // s(m) = sum_i g(min(i, n-i)) cos(2 pi m i / n), g(r) = a exp(-r^2/L^2), a^2 = 1/(L sqrt(pi/2))
-    auto root_eigs = [&](int n, const std::vector<int>& wn) {
+    auto root_eigs = [&](int n) {
         const double L = d.L_b;
         const double a = std::sqrt(1.0 / (L * std::sqrt(M_PI / 2.0)));
-        std::vector<double> s(n);
-        for (int c = 0; c < n; ++c) {
+        std::vector<double> s(n / 2 + 1);
+        for (int m = 0; m <= n / 2; ++m) {
             double acc = 0.0;
             for (int i = 0; i < n; ++i) {
                 const double r = std::min(i, n - i);
-                const long q = (static_cast<long>(wn[c]) * i) % n;
+                const long q = (static_cast<long>(m) * i) % n;
                 acc += a * std::exp(-(r * r) / (L * L)) * std::cos(2.0 * M_PI * static_cast<double>(q) / n);
             }
-            s[c] = acc;
+            s[m] = acc;
         }
         return s;
     };
-    std::vector<double> Bx, BxT, By, ByT;
-    std::vector<int> wx, wy;
-    make_basis(nx, Bx, BxT, wx);
-    make_basis(ny, By, ByT, wy);
-    const std::vector<double> sx = root_eigs(nx, wx), sy = root_eigs(ny, wy);
-    std::vector<double> all;
-    all.reserve(2 * Bx.size() + 2 * By.size());
-    all.insert(all.end(), Bx.begin(), Bx.end());
-    all.insert(all.end(), BxT.begin(), BxT.end());
-    all.insert(all.end(), By.begin(), By.end());
-    all.insert(all.end(), ByT.begin(), ByT.end());
+    // twiddles exp(-2 pi i m / n), m < n, of the x axis then the y axis
+    std::vector<double> tw;
+    tw.reserve(2 * (nx + ny));
+    for (int n : {nx, ny})
+        for (int m = 0; m < n; ++m) {
+            const double th = 2.0 * M_PI * static_cast<double>(m) / n;
+            tw.push_back(std::cos(th));
+            tw.push_back(-std::sin(th));
+        }
+    const std::vector<double> sx = root_eigs(nx), sy = root_eigs(ny);
     std::vector<double> dl(static_cast<size_t>(nx) * ny), dp(dl.size());
-    const double tp2 = 4.0 * M_PI * M_PI;
+    const double tp2 = 4.0 * M_PI * M_PI, inv_n = 1.0 / (static_cast<double>(nx) * ny);
     for (int r = 0; r < ny; ++r)
         for (int c = 0; c < nx; ++c) {
-            const double k2 = tp2 * (static_cast<double>(wy[r]) * wy[r] + static_cast<double>(wx[c]) * wx[c]);
-            dl[static_cast<size_t>(r) * nx + c] = k2 > 0 ? -1.0 / k2 : 0.0;
-            dp[static_cast<size_t>(r) * nx + c] = d.sigma_b * sy[r] * sx[c];
+            const int my = wn(r, ny), mx = wn(c, nx);
+            const double k2 = tp2 * (static_cast<double>(my) * my + static_cast<double>(mx) * mx);
+            dl[static_cast<size_t>(r) * nx + c] = (k2 > 0 ? -1.0 / k2 : 0.0) * inv_n;
+            dp[static_cast<size_t>(r) * nx + c] = d.sigma_b * sy[my] * sx[mx] * inv_n;
         }
     // copies on the context stream (never the legacy stream), completed before the
     // host tables go out of scope
@@ -559,7 +336,7 @@ void bve_setup(rp4d_problem* p) {
         RP4D_HIP(hipMemcpyAsync(dstf.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, bst(p)));
         RP4D_HIP(hipStreamSynchronize(bst(p)));
     };
-    upload(b->basis, b->basis_f, all);
+    upload(b->tw, b->tw_f, tw);
     upload(b->dlap, b->dlap_f, dl);
     upload(b->dpri, b->dpri_f, dp);
 }
@@ -595,7 +372,7 @@ void bve_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* innov, do
     };
     RP4D_HIP(hipMemcpyAsync(zrow(0), x0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     const double cn[3] = {0.5 * h, 0.5 * h, h};
-    const double* Dl = basis_of<double>(p).Dlap;
+    const double* Dl = spec_of<double>(p).Dlap;
     for (int s = 0; s < p->s_last; ++s) {
         const double* z = zrow(s);
         for (int i = 0; i < 4; ++i) {
@@ -630,7 +407,7 @@ void bve_bhalf(rp4d_problem* p, int k, const T* in, int in_kc, T* out, int out_k
     T* t2 = t1 + static_cast<size_t>(k) * n;
     const long cnt = static_cast<long>(k) * n;
     bve_to_fields<T><<<ublk(cnt), 256, 0, st>>>(in, in_kc, n, k, f);
-    spectral_apply<T>(p, k, f, basis_of<T>(p).Dpri, f, t1, t2);
+    spectral_apply<T>(p, k, f, spec_of<T>(p).Dpri, f, t1, t2);
     bve_from_fields<T><<<ublk(cnt), 256, 0, st>>>(f, n, k, out, out_kc, addv);
     RP4D_HIP(hipGetLastError());
 }
@@ -645,7 +422,7 @@ void bve_inv_laplacian(rp4d_problem* p, int k, const T* in, T* out) {
     T* t2 = t1 + static_cast<size_t>(k) * n;
     const long cnt = static_cast<long>(k) * n;
     bve_to_fields<T><<<ublk(cnt), 256, 0, st>>>(in, k, n, k, f);
-    spectral_apply<T>(p, k, f, basis_of<T>(p).Dlap, f, t1, t2);
+    spectral_apply<T>(p, k, f, spec_of<T>(p).Dlap, f, t1, t2);
     bve_from_fields<T><<<ublk(cnt), 256, 0, st>>>(f, n, k, out, k, nullptr);
     RP4D_HIP(hipGetLastError());
 }
@@ -669,7 +446,7 @@ void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) 
     const int stride = p->d.obs_stride, nox = (nx + stride - 1) / stride;
     const T cn[3] = {static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};
     const dim3 grid(ublk(n), k);
-    const T* Dl = basis_of<T>(p).Dlap;
+    const T* Dl = spec_of<T>(p).Dlap;
     for (int s = 0; s < p->s_last; ++s) {
         for (int i = 0; i < 4; ++i) {
             const T* w = i == 0 ? dz : (i == 2 ? wB : wA);
@@ -707,7 +484,7 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
     const T inv12d2 = static_cast<T>(1.0 / (12.0 * dd * dd)), nu_d2 = static_cast<T>(p->d.nu / (dd * dd));
     const int stride = p->d.obs_stride, nox = (nx + stride - 1) / stride;
     const dim3 grid(ublk(n), k);
-    const T* Dl = basis_of<T>(p).Dlap;
+    const T* Dl = spec_of<T>(p).Dlap;
     // mu of the next (lower) stage: (h/3, h), (h/3, h/2), (h/6, h/2)
     const T cl[4] = {T(0), static_cast<T>(h / 6.0), static_cast<T>(h / 3.0), static_cast<T>(h / 3.0)};
     const T ct[4] = {T(0), static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};

@@ -287,12 +287,20 @@ namespace rp4d {
 struct BveData {
     int nx = 0, ny = 0;
     double d = 0;               // grid spacing 1/nx
-    DevBuf basis, basis_f;      // Bx, Bx^T (nx x nx), By, By^T (ny x ny): FP64 and FP32
-    DevBuf dlap, dlap_f;        // (ny, nx): -1/|k|^2 in the product basis, 0 for k = 0
-    DevBuf dpri, dpri_f;        // (ny, nx): sigma_b s_y s_x, the prior square root's eigenvalues
+    DevBuf tw, tw_f;            // exp(-2 pi i m / nx), m < nx, then exp(-2 pi i m / ny): (re, im) pairs
+    DevBuf dlap, dlap_f;        // (ny, nx) in FFT order: -1/|k|^2 (0 for k = 0), divided by nx ny
+    DevBuf dpri, dpri_f;        // (ny, nx) in FFT order: sigma_b s_y s_x, the prior root's eigenvalues, / (nx ny)
     DevBuf ws, ws_fwd, ws_bh, ws_obs;
 };
 void bve_setup(rp4d_problem* p);
+// Periodic spectral operators by FFT (fft2d.hip): out = F^{-1}(D .* F in) for k
+// field-major fields of an nx x ny grid; D (ny x nx) in FFT order with the
+// inverse's 1/(nx ny) folded in; W* twiddle tables; z scratch of
+// 2 ceil(k/2) nx ny elements.  out may alias in.
+bool fft_size_supported(int n);
+template <typename T>
+void launch_spectral_diag(const T* in, int k, int nx, int ny, const T* D, const T* Wx, const T* Wy, T* z, T* out,
+                          hipStream_t st);
 size_t bve_traj_stage_bytes(const rp4d_problem* p);
 void bve_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* innov, double* obs_out);
 template <typename T>

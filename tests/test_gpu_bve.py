@@ -34,8 +34,12 @@ def _rand(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)
 
 
-@pytest.mark.parametrize("nx,k", [(32, 3), (64, 1), (256, 2)])
+@pytest.mark.parametrize("nx,k", [(32, 3), (48, 2), (64, 1), (80, 3), (96, 1), (128, 2), (160, 1), (192, 2),
+                                  (256, 2), (320, 1), (384, 3), (512, 2)])
 def test_inverse_laplacian_parity(nx, k):
+    """Every supported side 16 B (B in {2,3,4,5,6,8,10,12,16,20,24,32}): the
+    FFT path (four-step 16 x B line transforms, fields in complex pairs, odd k
+    with an empty imaginary part) against the oracle's library FFT."""
     torch = need_gpu()
     from oracle import bve
     from paper_2401_15758_amd import rp4d
@@ -49,7 +53,17 @@ def test_inverse_laplacian_parity(nx, k):
     assert colwise_relerr(got32, ref) <= 2e-6
 
 
-@pytest.mark.parametrize("nx,k,L", [(32, 2, 3.0), (64, 3, 8.0), (256, 1, 8.0)])
+def test_unsupported_grid_sides_are_rejected():
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx = rp4d.Context(0)
+    for nx in (112, 208, 40, 1024):
+        with pytest.raises(rp4d.Rp4dError) as e:
+            rp4d.Problem(ctx, inputs.bve_config(nx, nsteps=4, obs_stride=8, obs_every=2))
+        assert e.value.code == rp4d.EINVAL
+
+
+@pytest.mark.parametrize("nx,k,L", [(32, 2, 3.0), (64, 3, 8.0), (160, 2, 8.0), (256, 1, 8.0)])
 def test_prior_sqrt_parity(nx, k, L):
     need_gpu()
     from oracle import prior
