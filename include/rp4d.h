@@ -234,6 +234,20 @@ int rp4d_adj(rp4d_problem* p, const rp4d_traj* traj, int k, const void* W, void*
  * must not alias. */
 int rp4d_hessian_block(rp4d_problem* p, const rp4d_traj* traj, int k, const void* V, void* HV,
                        int dtype, int add_identity);
+/* The block Hessian product of rp4d_hessian_block, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, layouts, kernels and results
+ * (bitwise) as rp4d_hessian_block, 1-D models only (EINVAL for the 2-D model).
+ * Its workspaces (two blocked copies of the block, the k observation columns,
+ * the prior's Gram scratch and, with checkpoints, one recomputed segment) live
+ * in a static 64 MiB scratch array that each GPU holds from library load until
+ * the process ends; the call allocates and frees nothing, and returns EINVAL
+ * when the workspaces of (n, m, k) exceed 64 MiB (about k * (2 n + m) * w bytes
+ * with w = 8 for FP64, 4 for FP32).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race.  The
+ * caller still owns V and HV.  Kernel timing is suspended during the call. */
+int rp4d_hessian_block_noalloc(rp4d_problem* p, const rp4d_traj* traj, int k, const void* V, void* HV,
+                               int dtype, int add_identity);
 
 /* g (n) = v + A^T d: gradient of the v-form cost (eq. (4dvar_gradient) times
  * Gamma^{1/2}) using the innovations recorded by the last rp4d_fwd on `traj`.

@@ -11,6 +11,8 @@
 #include <type_traits>
 
 #include <limits>
+#include <map>
+#include <mutex>
 
 #include "batch_plan.hpp"
 #include "internal.hpp"
@@ -23,6 +25,10 @@ static thread_local std::string g_last_error;
 
 void DevBuf::ensure(size_t b) {
     if (b <= bytes && p != nullptr) return;
+    if (borrowed) {
+        if (b == 0) return;
+        fail(RP4D_ENOMEM, "no-allocation call: a workspace exceeds its scratch view");
+    }
     release();
     if (b == 0) return;
     hipError_t e = hipMalloc(&p, b);
@@ -36,9 +42,10 @@ void DevBuf::ensure(size_t b) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
 }
 
 namespace {
@@ -876,6 +883,36 @@ rp4d_problem* create_wall(rp4d_ctx* ctx, const rp4d_problem_desc& d) {
 // ===========================================================================
 // ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation entry point (rp4d_hessian_block_noalloc).
+// Each device holds its own copy of `scratch` for the life of the process; host
+// code reaches a device's copy only through the address hipGetSymbolAddress
+// returned for it (the array's name on the host is a stand-in, not a device
+// address).  The address is resolved once per device, with that device current,
+// when the first context on the device is created.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+void resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return;
+    void* ptr = nullptr;
+    RP4D_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    RP4D_REQUIRE(ptr != nullptr, RP4D_EHIP, "no device address for the static scratch");
+    g_scratch_ptr[device] = ptr;
+}
+
+void* scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+}  // namespace
+
 extern "C" {
 
 const char* rp4d_last_error(void) { return g_last_error.c_str(); }
@@ -888,6 +925,8 @@ int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out) {
         int ndev = 0;
         RP4D_HIP(hipGetDeviceCount(&ndev));
         RP4D_REQUIRE(device >= 0 && device < ndev, RP4D_EINVAL, "no such HIP device");
+        RP4D_HIP(hipSetDevice(device));
+        resolve_scratch(device);
         auto* c = new rp4d_ctx();
         c->device = device;
         c->stream = static_cast<hipStream_t>(hip_stream);
@@ -1152,6 +1191,59 @@ int rp4d_hessian_block(rp4d_problem* p, const rp4d_traj* tr, int k, const void* 
         RP4D_REQUIRE(V != HV, RP4D_EINVAL, "V and HV must not alias");
         check_traj(p, tr);
         set_device(p->ctx);
+        hessian_dispatch(p, tr, k, V, HV, dtype, add_identity != 0);
+    });
+}
+
+int rp4d_hessian_block_noalloc(rp4d_problem* p, const rp4d_traj* tr, int k, const void* V, void* HV, int dtype,
+                               int add_identity) {
+    return guarded([&] {
+        check_common(p, k, V, HV);
+        RP4D_REQUIRE(V != HV, RP4D_EINVAL, "V and HV must not alias");
+        check_traj(p, tr);
+        RP4D_REQUIRE(!p->bve, RP4D_EINVAL, "no-allocation Hessian: 1-D models only");
+        RP4D_REQUIRE(dtype == RP4D_F64 || dtype == RP4D_F32, RP4D_EINVAL, "dtype must be RP4D_F64 or RP4D_F32");
+        set_device(p->ctx);
+        unsigned char* base = static_cast<unsigned char*>(scratch_of(p->ctx->device));
+        RP4D_REQUIRE(base != nullptr, RP4D_ESTATE, "no-allocation Hessian: scratch not resolved for this device");
+        // the workspaces hessian_impl asks for, carved out of the scratch
+        const size_t es = dtype == RP4D_F64 ? 8 : 4;
+        const Tiling tt = tiling_for(p, MODE_TLM, dtype, k), ta = tiling_for(p, MODE_ADJ, dtype, k);
+        const int kcmax = std::max(tt.kc, ta.kc);
+        const size_t blk = static_cast<size_t>((k + kcmax - 1) / kcmax + 1) * kcmax * p->n * es;
+        const size_t obs = static_cast<size_t>(p->m) * k * es;
+        const size_t bh = p->spec ? (static_cast<size_t>(p->r) * k + gram_work_doubles(p->n, p->r, k)) * 8 : 0;
+        const size_t seg = tr->C > 1 ? static_cast<size_t>(tr->C + 1) * p->n * 8 : 0;
+        const size_t red = tr->C > 1 ? 2 * static_cast<size_t>(p->n) * 8 + 64 : 0;
+        DevBuf* bufs[6] = {&p->ws_s0, &p->ws_s1, &p->ws_obs, &p->ws_bh, &p->ws_seg, &p->ws_red};
+        const size_t need[6] = {blk, blk, obs, bh, seg, red};
+        size_t total = 0;
+        for (size_t b : need) total += ring_round(b);
+        RP4D_REQUIRE(total <= kScratchBytes, RP4D_EINVAL,
+                     "no-allocation Hessian: workspaces of " + std::to_string(total) +
+                         " bytes exceed the 64 MiB scratch (smaller k or n)");
+        // swap views of the scratch in for the problem's own workspaces; put them
+        // back on every exit.  Timing events are suspended (their pool may create).
+        struct Borrow {
+            DevBuf view[6];
+            DevBuf** slots;
+            rp4d_ctx* c;
+            int timing;
+            ~Borrow() {
+                for (int i = 0; i < 6; ++i) slots[i]->swap(view[i]);
+                for (auto& v : view) v.release();
+                c->timing = timing;
+            }
+        } g{{}, bufs, p->ctx, p->ctx->timing};
+        size_t off = 0;
+        for (int i = 0; i < 6; ++i) {
+            g.view[i].p = need[i] ? base + off : nullptr;
+            g.view[i].bytes = need[i];
+            g.view[i].borrowed = true;
+            off += ring_round(need[i]);
+        }
+        for (int i = 0; i < 6; ++i) bufs[i]->swap(g.view[i]);
+        p->ctx->timing = 0;
         hessian_dispatch(p, tr, k, V, HV, dtype, add_identity != 0);
     });
 }

@@ -50,6 +50,9 @@ inline int construction_device() {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    // a view of memory the buffer does not own (the no-allocation entry point's
+    // static scratch): ensure() fails instead of reallocating, release() frees nothing
+    bool borrowed = false;
     void ensure(size_t b);
     void release();
     template <typename T>
@@ -57,6 +60,7 @@ struct DevBuf {
     void swap(DevBuf& o) {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(borrowed, o.borrowed);
     }
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;

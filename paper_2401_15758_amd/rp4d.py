@@ -128,6 +128,7 @@ _SIGS = {
     "rp4d_tlm": ([_P, _P, _I, _P, _P, _I], _I),
     "rp4d_adj": ([_P, _P, _I, _P, _P, _I], _I),
     "rp4d_hessian_block": ([_P, _P, _I, _P, _P, _I, _I], _I),
+    "rp4d_hessian_block_noalloc": ([_P, _P, _I, _P, _P, _I, _I], _I),
     "rp4d_gradient": ([_P, _P, _P, _P], _I),
     "rp4d_bve_inv_laplacian": ([_P, _I, _P, _P, _I], _I),
     "rp4d_build_precond": ([_P, _P, _I, _I, ctypes.c_uint64, _P, _I, ctypes.POINTER(_P)], _I),
@@ -337,6 +338,13 @@ class Problem:
         k = V.shape[1] if V.dim() == 2 else 1
         out = out if out is not None else torch.empty_like(V)
         _check(_lib.rp4d_hessian_block(self._h, traj._h, k, _ptr(V, None, self.n * k, "V"),
+                                       _ptr(out, V.dtype, self.n * k, "HV"), _dt(V), 1 if add_identity else 0))
+        return out
+
+    def hessian_block_noalloc(self, traj, V, out=None, add_identity=True):
+        k = V.shape[1] if V.dim() == 2 else 1
+        out = out if out is not None else torch.empty_like(V)
+        _check(_lib.rp4d_hessian_block_noalloc(self._h, traj._h, k, _ptr(V, None, self.n * k, "V"),
                                        _ptr(out, V.dtype, self.n * k, "HV"), _dt(V), 1 if add_identity else 0))
         return out
 
