@@ -183,8 +183,18 @@ const char* rp4d_last_error(void);
 const char* rp4d_version(void);
 
 /* Context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t;
- * NULL = the null stream).  The stream must outlive the context. */
-int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out);
+ * NULL = the null stream).  The stream must outlive the context.
+ * hbm_budget_bytes caps the device memory held through the context's objects
+ * (problems, trajectories, preconditioners, GN states, batches and their
+ * workspaces; counted when allocated, released when freed, whichever object is
+ * destroyed first): an allocation that would exceed it fails with RP4D_ENOMEM
+ * and leaves the objects usable.  0 = no cap (the device's memory).  The
+ * admission of work by footprint (Sec. 3.2 serving) reads the count with
+ * rp4d_ctx_hbm. */
+int rp4d_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, rp4d_ctx** out);
+/* Device bytes currently held through the context (used) and its budget
+ * (0 = none), host outputs (either may be NULL). */
+int rp4d_ctx_hbm(const rp4d_ctx* ctx, size_t* used, size_t* budget);
 int rp4d_ctx_destroy(rp4d_ctx* ctx);
 /* Change the stream subsequent calls are enqueued on. */
 int rp4d_ctx_set_stream(rp4d_ctx* ctx, void* hip_stream);

@@ -23,14 +23,20 @@ static thread_local std::string g_last_error;
 
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
+thread_local std::shared_ptr<HbmAcct> tl_acct;
+
 void DevBuf::ensure(size_t b) {
     if (b <= bytes && p != nullptr) return;
     if (borrowed) {
         if (b == 0) return;
         fail(RP4D_ENOMEM, "no-allocation call: a workspace exceeds its scratch view");
     }
+    std::shared_ptr<HbmAcct> a = acct ? acct : tl_acct;
     release();
     if (b == 0) return;
+    if (a && a->budget > 0 && a->used.load() + static_cast<long long>(b) > a->budget)
+        fail(RP4D_ENOMEM, "context HBM budget exceeded: " + std::to_string(a->used.load()) + " bytes held, " +
+                              std::to_string(b) + " more asked, budget " + std::to_string(a->budget));
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
         p = nullptr;
@@ -39,13 +45,19 @@ void DevBuf::ensure(size_t b) {
         fail(RP4D_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
     }
     bytes = b;
+    acct = a;
+    if (acct) acct->used += static_cast<long long>(b);
 }
 
 void DevBuf::release() {
-    if (p && !borrowed) (void)hipFree(p);
+    if (p && !borrowed) {
+        (void)hipFree(p);
+        if (acct) acct->used -= static_cast<long long>(bytes);
+    }
     p = nullptr;
     bytes = 0;
     borrowed = false;
+    acct.reset();
 }
 
 namespace {
@@ -139,6 +151,10 @@ constexpr double FL_FWD = 48.0;
 
 template <typename F>
 int guarded(F&& f) {
+    struct ClearAcct {
+        ClearAcct() { tl_acct.reset(); }
+        ~ClearAcct() { tl_acct.reset(); }
+    } clear_acct;
     try {
         f();
         g_last_error.clear();
@@ -246,6 +262,7 @@ inline int nblk(long count, int t = 256) {
 void set_device(const rp4d_ctx* c) {
     RP4D_HIP(hipSetDevice(c->device));
     (void)hipGetLastError();  // drop errors left by calls outside this library
+    tl_acct = c->acct;        // allocations of this call count against c's budget
 }
 
 hipStream_t stream_of(const rp4d_problem* p) { return p->ctx->stream; }
@@ -919,7 +936,7 @@ const char* rp4d_last_error(void) { return g_last_error.c_str(); }
 
 const char* rp4d_version(void) { return "rp4d 0.1 (gfx950)"; }
 
-int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out) {
+int rp4d_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, rp4d_ctx** out) {
     return guarded([&] {
         RP4D_REQUIRE(out != nullptr, RP4D_EINVAL, "null output handle");
         int ndev = 0;
@@ -927,10 +944,21 @@ int rp4d_ctx_create(int device, void* hip_stream, rp4d_ctx** out) {
         RP4D_REQUIRE(device >= 0 && device < ndev, RP4D_EINVAL, "no such HIP device");
         RP4D_HIP(hipSetDevice(device));
         resolve_scratch(device);
+        RP4D_REQUIRE(hbm_budget_bytes <= static_cast<size_t>(std::numeric_limits<long long>::max()), RP4D_EINVAL,
+                     "HBM budget out of range");
         auto* c = new rp4d_ctx();
         c->device = device;
         c->stream = static_cast<hipStream_t>(hip_stream);
+        c->acct->budget = static_cast<long long>(hbm_budget_bytes);
         *out = c;
+    });
+}
+
+int rp4d_ctx_hbm(const rp4d_ctx* ctx, size_t* used, size_t* budget) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
+        if (used) *used = static_cast<size_t>(std::max(0LL, ctx->acct->used.load()));
+        if (budget) *budget = static_cast<size_t>(ctx->acct->budget);
     });
 }
 

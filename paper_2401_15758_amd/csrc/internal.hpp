@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <functional>
@@ -47,9 +48,21 @@ inline int construction_device() {
     return d;
 }
 
+// Device bytes held through one context's objects, against the context's budget
+// (0: none).  Shared by the context and every buffer allocated for it, so either
+// may be destroyed first.
+struct HbmAcct {
+    std::atomic<long long> used{0};
+    long long budget = 0;
+};
+// The accounting of the context whose call is running on this thread (set with
+// the device at the start of a call, cleared at its end).
+extern thread_local std::shared_ptr<HbmAcct> tl_acct;
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    std::shared_ptr<HbmAcct> acct;  // the context the bytes are counted against
     // a view of memory the buffer does not own (the no-allocation entry point's
     // static scratch): ensure() fails instead of reallocating, release() frees nothing
     bool borrowed = false;
@@ -61,6 +74,7 @@ struct DevBuf {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
         std::swap(borrowed, o.borrowed);
+        std::swap(acct, o.acct);
     }
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
@@ -235,6 +249,7 @@ void launch_bcopy(const BCopy* d, const int4* items, int nitems, hipStream_t st)
 struct rp4d_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    std::shared_ptr<rp4d::HbmAcct> acct = std::make_shared<rp4d::HbmAcct>();
     // kernel timing: 0 off, 1 an event pair around every launch of the timed
     // classes, 2 one pair around each Burgers sweep's launch loop (SpanTimer)
     int timing = 0;

@@ -112,7 +112,8 @@ _D = ctypes.c_double
 _SIGS = {
     "rp4d_last_error": ([], ctypes.c_char_p),
     "rp4d_version": ([], ctypes.c_char_p),
-    "rp4d_ctx_create": ([_I, _P, ctypes.POINTER(_P)], _I),
+    "rp4d_ctx_create": ([_I, _P, ctypes.c_size_t, ctypes.POINTER(_P)], _I),
+    "rp4d_ctx_hbm": ([_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], _I),
     "rp4d_ctx_destroy": ([_P], _I),
     "rp4d_ctx_set_stream": ([_P, _P], _I),
     "rp4d_problem_create": ([_P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(_P)], _I),
@@ -211,14 +212,22 @@ def version():
 class Context:
     """rp4d_ctx on `device`, enqueueing on the current torch stream."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, hbm_budget=0):
+        """hbm_budget: bytes of device memory the context's objects may hold (0: no cap)."""
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         h = ctypes.c_void_p()
-        _check(_lib.rp4d_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        _check(_lib.rp4d_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.c_size_t(int(hbm_budget)),
+                                    ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", device)
+
+    def hbm(self):
+        """{"used": bytes held through the context, "budget": its cap (0: none)}."""
+        u, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.rp4d_ctx_hbm(self._h, ctypes.byref(u), ctypes.byref(b)))
+        return dict(used=u.value, budget=b.value)
 
     def philox_normal(self, seed, count, out):
         _check(_lib.rp4d_philox_normal(self._h, seed, count, _ptr(out, torch.float64, count, "out")))

@@ -50,6 +50,7 @@ class Request:
     reused: int = 0
     J: list = field(default_factory=list)
     x: np.ndarray = None    # final state (host copy)
+    hbm_peak: int = 0       # peak device bytes the served run's contexts held (library count)
 
     @property
     def model(self):
@@ -60,12 +61,23 @@ class Request:
         return self.done - self.arrival
 
 
+# grid sides of the 2-D model's FFTs: 16 B, B in {2,3,4,5,6,8,10,12,16,20,24,32}
+BVE_SIDES = (32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512)
+
+
+def bve_side(x, lim):
+    """The supported side within [lim[0], lim[1]] nearest to x in log scale."""
+    cands = [s for s in BVE_SIDES if lim[0] <= s <= lim[1]] or [min(BVE_SIDES, key=lambda s: abs(s - x))]
+    return min(cands, key=lambda s: abs(math.log(s / x)))
+
+
 def make_trace(nreq, rate, seed=0, frac_burgers=0.7, burgers_n=(512, 8192), burgers_N=(100, 500),
                bve_nx=(128, 512), bve_N=(100, 300)):
     """Poisson arrivals at `rate` per second of a mix of solves: Burgers with n
     log-uniform in `burgers_n` and N uniform in `burgers_N` (observations every 4th
-    point every 10 steps, sketch 32); vorticity with nx a multiple of 16 uniform in
-    `bve_nx` and N uniform in `bve_N` (every 16th cell every 20 steps, sketch 100)."""
+    point every 10 steps, sketch 32); vorticity with nx log-uniform in `bve_nx`,
+    rounded to the nearest side the FFTs take, and N uniform in `bve_N` (every
+    16th cell every 20 steps, sketch 100)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -76,7 +88,7 @@ def make_trace(nreq, rate, seed=0, frac_burgers=0.7, burgers_n=(512, 8192), burg
             N = int(rng.integers(burgers_N[0], burgers_N[1] + 1))
             cfg = inputs.burgers_config(n, N, 4, 10, dt_cfg=1e-3, ell=32, name=f"req{rid}-burgers-{n}")
         else:
-            nx = 16 * int(rng.integers(bve_nx[0] // 16, bve_nx[1] // 16 + 1))
+            nx = bve_side(math.exp(rng.uniform(math.log(bve_nx[0]), math.log(bve_nx[1]))), bve_nx)
             N = int(rng.integers(bve_N[0], bve_N[1] + 1))
             cfg = inputs.bve_config(nx, nsteps=N, obs_stride=16, obs_every=20, ell=100, name=f"req{rid}-bve-{nx}")
         out.append(Request(rid=rid, cfg=cfg, arrival=t, seed=int(rng.integers(0, 2 ** 31))))
@@ -163,6 +175,19 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
         sketch_dtype = rp4d.F64
     t0 = time.perf_counter()
     budget = _Budget(budget_bytes)
+    # each lane's context carries the served budget as its hard cap in the
+    # library: the reservations above keep the lanes' sum within it, and an
+    # estimate that fell short would surface as ENOMEM, not as an overcommit
+    lane_ctx = []
+    peak = [0]
+
+    def lane_context():
+        c = rp4d.Context(0, stream=torch.cuda.Stream(), hbm_budget=budget_bytes)
+        lane_ctx.append(c)
+        return c
+
+    def note_usage():
+        peak[0] = max(peak[0], sum(c.hbm()["used"] for c in list(lane_ctx)))
     pend_b = [r for r in trace if r.model == "burgers"]
     pend_v = [r for r in trace if r.model != "burgers"]
     vlock = threading.Lock()
@@ -172,7 +197,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
         return time.perf_counter() - t0
 
     def burgers_lane():
-        ctx = rp4d.Context(0, stream=torch.cuda.Stream())
+        ctx = lane_context()
         active = []   # (req, problem, state, footprint)
         queue = list(pend_b)
         batch, members = None, ()
@@ -198,6 +223,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 batch, members = rp4d.Batch(ctx, [a[1] for a in active]), ids
             infos = batch.gn_step([a[2] for a in active], ell=32, seed=12345, sketch_dtype=sketch_dtype, rtol=rtol,
                                   reuse_eps=reuse_eps)
+            note_usage()
             keep = []
             for (r, p, st, fp), inf in zip(active, infos):
                 r.gn_done += 1
@@ -221,7 +247,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
             batch.close()
 
     def bve_lane():
-        ctx = rp4d.Context(0, stream=torch.cuda.Stream())
+        ctx = lane_context()
         while True:
             with vlock:
                 if not pend_v:
@@ -243,6 +269,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 r.pcg_iters.append(inf["pcg_iters"])
                 r.J.append(inf["J"])
                 r.reused += inf["reused"]
+                note_usage()
             _finish(torch, ctx, r, st, t0)
             st.close()
             p.close()
@@ -264,6 +291,8 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
         t.join()
     if errors:
         raise errors[0]
+    for r in trace:
+        r.hbm_peak = peak[0]
     return trace
 
 
@@ -297,7 +326,8 @@ def summary(trace):
     return {"requests": len(trace), "solves_per_s": len(trace) / span, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "makespan_s": span,
             "pcg_iters_total": int(sum(sum(r.pcg_iters) for r in trace)),
-            "reuses": int(sum(r.reused for r in trace))}
+            "reuses": int(sum(r.reused for r in trace)),
+            "hbm_peak_bytes": int(max(r.hbm_peak for r in trace))}
 
 
 def clone_trace(trace):
