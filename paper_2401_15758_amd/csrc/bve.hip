@@ -24,6 +24,7 @@
 #include <cmath>
 #include <vector>
 
+#include "fft_line.hpp"
 #include "internal.hpp"
 
 namespace rp4d {
@@ -90,66 +91,6 @@ __global__ void __launch_bounds__(256) bve_fwd_stage(const double* __restrict__ 
     }
 }
 
-// TLM stage for k fields (grid.y = vector): kv = -J_A(phi, Y) - J_A(psi, w) + nu lap(w).
-template <typename T>
-__global__ void __launch_bounds__(256) bve_tlm_stage(const T* __restrict__ w, const T* __restrict__ phi,
-                                                      const double* __restrict__ Y, const double* __restrict__ psi,
-                                                      T* dz, T* __restrict__ acc, T* __restrict__ wnext, int stage,
-                                                      T cnext, T h, T inv12d2, T nu_d2, int nx, int ny) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = nx * ny;
-    if (p >= n) return;
-    const long off = static_cast<long>(blockIdx.y) * n;
-    const Nbr q = nbr(p, nx, ny);
-    const T kv = -(arakawa12<T>(phi + off, T(1), Y, T(1), q) * inv12d2) -
-                 arakawa12<T>(psi, T(1), w + off, T(1), q) * inv12d2 + nu_d2 * lap5x<T>(w + off, T(1), q);
-    const T dv = dz[off + p];
-    if (stage == 0) {
-        acc[off + p] = kv * T(kRkB[0]);
-        wnext[off + p] = dv + cnext * kv;
-    } else if (stage < 3) {
-        acc[off + p] = acc[off + p] + kv * T(kRkB[stage]);
-        wnext[off + p] = dv + cnext * kv;
-    } else {
-        dz[off + p] = dv + h * (acc[off + p] + kv * T(kRkB[3]));
-    }
-}
-
-// ADJ stage, first half: jq = J_A(Y, a mu) (input of L), r = J_A(psi, a mu) + nu lap(a mu).
-template <typename T>
-__global__ void __launch_bounds__(256) bve_adj_stencil(const T* __restrict__ mu, T a, const double* __restrict__ Y,
-                                                        const double* __restrict__ psi, T* __restrict__ jq,
-                                                        T* __restrict__ r, T inv12d2, T nu_d2, int nx, int ny) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = nx * ny;
-    if (p >= n) return;
-    const long off = static_cast<long>(blockIdx.y) * n;
-    const Nbr q = nbr(p, nx, ny);
-    jq[off + p] = arakawa12<T>(Y, T(1), mu + off, a, q) * inv12d2;
-    r[off + p] = arakawa12<T>(psi, T(1), mu + off, a, q) * inv12d2 + nu_d2 * lap5x<T>(mu + off, a, q);
-}
-
-// ADJ stage, second half: theta = -P + r, then (stage 3) acc = lam + theta,
-// (2, 1) acc += theta, with the next stage's mu = cl lam + ct theta; (0) lam = acc + theta.
-template <typename T>
-__global__ void __launch_bounds__(256) bve_adj_combine(const T* __restrict__ P, const T* __restrict__ r, T* lam,
-                                                        T* __restrict__ acc, T* __restrict__ mu, int stage, T cl,
-                                                        T ct, long count) {
-    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    const T th = -P[e] + r[e];
-    if (stage == 3) {
-        const T l = lam[e];
-        acc[e] = l + th;
-        mu[e] = cl * l + ct * th;
-    } else if (stage > 0) {
-        acc[e] = acc[e] + th;
-        mu[e] = cl * lam[e] + ct * th;
-    } else {
-        lam[e] = acc[e] + th;
-    }
-}
-
 // Observations of k fields at one observation step: z[o][v] = x_v[idx(o)] / sigma_o.
 template <typename T>
 __global__ void bve_obs_gather(const T* __restrict__ x, int k, int n, int nx, int stride, int nox, int n_obs,
@@ -159,18 +100,6 @@ __global__ void bve_obs_gather(const T* __restrict__ x, int k, int n, int nx, in
     const int o = e / k, v = e - o * k;
     const int idx = (o / nox) * stride * nx + (o % nox) * stride;
     z[e] = x[static_cast<long>(v) * n + idx] * inv_sigma;
-}
-
-// Adjoint of the above: lam_v[idx(o)] += w[o][v] / sigma_o.
-template <typename T>
-__global__ void bve_obs_scatter(const T* __restrict__ w, int k, int n, int nx, int stride, int nox, int n_obs,
-                                T inv_sigma, T* __restrict__ lam) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_obs * k) return;
-    const int o = e / k, v = e - o * k;
-    const int idx = (o / nox) * stride * nx + (o % nox) * stride;
-    const long a = static_cast<long>(v) * n + idx;
-    lam[a] = lam[a] + w[e] * inv_sigma;
 }
 
 // Nonlinear observations and innovations of one state.
@@ -210,6 +139,502 @@ template <typename T>
 __global__ void bve_zero(T* x, long count) {
     const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e < count) x[e] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Fused row stages of the linearised sweeps.  One launch per RK stage does the
+// row-local work of the stage -- the inverse row FFTs of the column-passed
+// spectra (the Poisson solve's last pass), the stencils and RK updates, and
+// the forward row FFTs of the next stage's input (the next solve's first pass)
+// -- so that a stage is this launch plus the column pass.  A workgroup owns
+// kRowsOwn rows of one field pair and transforms one halo row on each side
+// (the stencils reach one row out); 16 threads per row line, as in fft2d.hip.
+// ---------------------------------------------------------------------------
+constexpr int kRowsOwn = fftl::kLines - 2;
+
+// 12 d^2 J_A(a, b) and the 5-point Laplacian times d^2 on 3 x 3 neighbourhoods
+// v[dj + 1][di + 1] (the same operations, in the same order, as arakawa12 / lap5x).
+template <typename T>
+__device__ __forceinline__ T arakawa12_nb(const T (&a)[3][3], const T (&b)[3][3]) {
+    const T ae = a[1][2], aw = a[1][0], an = a[2][1], as = a[0][1];
+    const T ane = a[2][2], ase = a[0][2], anw = a[2][0], asw = a[0][0];
+    const T be = b[1][2], bw = b[1][0], bn = b[2][1], bs = b[0][1];
+    const T bne = b[2][2], bse = b[0][2], bnw = b[2][0], bsw = b[0][0];
+    const T jpp = (ae - aw) * (bn - bs) - (an - as) * (be - bw);
+    const T jpx = ae * (bne - bse) - aw * (bnw - bsw) - an * (bne - bnw) + as * (bse - bsw);
+    const T jxp = bn * (ane - anw) - bs * (ase - asw) - be * (ane - ase) + bw * (anw - asw);
+    return jpp + jpx + jxp;
+}
+
+template <typename T>
+__device__ __forceinline__ T lap5_nb(const T (&a)[3][3]) {
+    return a[1][2] + a[1][0] + a[2][1] + a[0][1] - T(4) * a[1][1];
+}
+
+// 3 x 3 neighbourhood of (j, i) of a global field (periodic).
+template <typename T, typename S>
+__device__ __forceinline__ void load9(const S* __restrict__ f, int nx, int ny, int j, int i, T (&o)[3][3]) {
+    const int r[3] = {j == 0 ? ny - 1 : j - 1, j, j + 1 == ny ? 0 : j + 1};
+    const int c[3] = {i == 0 ? nx - 1 : i - 1, i, i + 1 == nx ? 0 : i + 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) o[a][b] = static_cast<T>(f[static_cast<size_t>(r[a]) * nx + c[b]]);
+}
+
+// 3 x 3 neighbourhood of (owned row jr, column i) from the LDS row lines
+// (line 0 is the row above the block), real (f = 0) or imaginary (f = 1) part.
+template <typename T, int N>
+__device__ __forceinline__ void lds9(const fftl::C2<T>* lds, int jr, int i, int f, T (&o)[3][3]) {
+    const int c[3] = {i == 0 ? N - 1 : i - 1, i, i + 1 == N ? 0 : i + 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const fftl::C2<T> v = lds[(jr + a) * fftl::padded(N) + fftl::padded(c[b])];
+            o[a][b] = f ? v.i : v.r;
+        }
+}
+
+// Rows j0-1 .. j0+rown (periodic) of an n-point field, staged in LDS row r at
+// dst + r N: stage_load issues a thread's loads (coalesced along the rows),
+// stage_store writes them, so that a kernel can issue every load first.
+template <typename S, int N>
+__device__ __forceinline__ void stage_load(const S* __restrict__ f, int j0, int rown, int ny, S (&v)[N / 16]) {
+#pragma unroll
+    for (int r = 0; r < N / 16; ++r) {
+        const int e = threadIdx.x + r * 16 * fftl::kLines;
+        const int lr = e / N, i = e - lr * N;
+        int j = j0 - 1 + min(lr, rown + 1);
+        j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+        v[r] = f[static_cast<size_t>(j) * N + i];
+    }
+}
+
+template <typename T, typename S, int N>
+__device__ __forceinline__ void stage_store(T* dst, const S (&v)[N / 16], int rown) {
+#pragma unroll
+    for (int r = 0; r < N / 16; ++r) {
+        const int e = threadIdx.x + r * 16 * fftl::kLines;
+        if (e < (rown + 2) * N) dst[e] = static_cast<T>(v[r]);
+    }
+}
+
+// 3 x 3 neighbourhood of (owned row jr, column i) from rows staged by stage_rows.
+template <typename T, int N>
+__device__ __forceinline__ void st9(const T* rows, int jr, int i, T (&o)[3][3]) {
+    const int c[3] = {i == 0 ? N - 1 : i - 1, i, i + 1 == N ? 0 : i + 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) o[a][b] = rows[(jr + a) * N + c[b]];
+}
+
+// Row spectra of line l = threadIdx / 16 (row j0 - 1 + l, periodic) of pair p:
+// the B values of thread q, or nothing on lines past rown + 1.
+template <typename T, int B>
+__device__ __forceinline__ void rows_spec_load(const T* __restrict__ z, int p, int j0, int rown, int ny,
+                                               fftl::C2<T> (&v)[B]) {
+    constexpr int N = 16 * B;
+    const int l = threadIdx.x >> 4, q = threadIdx.x & 15;
+    if (l < rown + 2) {
+        int jj = j0 - 1 + l;
+        jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+        const T* zr = z + (static_cast<size_t>(p) * N * ny + static_cast<size_t>(jj) * N) * 2;
+#pragma unroll
+        for (int e = 0; e < B; ++e) {
+            const int i = q + 16 * e;
+            v[e] = fftl::C2<T>{zr[2 * i], zr[2 * i + 1]};
+        }
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void rows_spec_store(fftl::C2<T>* lds, int rown, const fftl::C2<T> (&v)[B]) {
+    constexpr int N = 16 * B;
+    const int l = threadIdx.x >> 4, q = threadIdx.x & 15;
+    if (l < rown + 2) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) lds[l * fftl::padded(N) + fftl::padded(q + 16 * e)] = v[e];
+    }
+}
+
+// Inverse transform of the LDS lines 0 .. rown + 1 (after a barrier).
+template <typename T, int B>
+__device__ __forceinline__ void rows_inverse(fftl::C2<T>* lds, int rown, const fftl::C2<T>* wl) {
+    constexpr int N = 16 * B;
+    const int l = threadIdx.x >> 4, q = threadIdx.x & 15;
+    fftl::line_fft<T, B>(lds + l * fftl::padded(N), q, l < rown + 2, wl, true);
+}
+
+// Forward row FFTs of `out` (owned rows, values of the pair's two fields per
+// point) into the row spectra z of pair p.
+template <typename T, int B, int PER>
+__device__ __forceinline__ void rows_forward(fftl::C2<T>* lds, const T (&out)[2][PER], T* __restrict__ z, int p,
+                                             int j0, int rown, int ny, const fftl::C2<T>* wl) {
+    constexpr int N = 16 * B;
+    const int tid = threadIdx.x, l = tid >> 4, q = tid & 15;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = tid + t * 16 * fftl::kLines;
+        if (e < rown * N) {
+            const int jr = e / N, i = e - jr * N;
+            lds[jr * fftl::padded(N) + fftl::padded(i)] = fftl::C2<T>{out[0][t], out[1][t]};
+        }
+    }
+    __syncthreads();
+    fftl::C2<T>* line = lds + l * fftl::padded(N);
+    const bool act = l < rown;
+    fftl::line_fft<T, B>(line, q, act, wl, false);
+    if (act) {
+        T* zr = z + (static_cast<size_t>(p) * N * ny + static_cast<size_t>(j0 + l) * N) * 2;
+#pragma unroll
+        for (int e = 0; e < B; ++e) {
+            const int i = q + 16 * e;
+            const fftl::C2<T> v = line[fftl::padded(i)];
+            zr[2 * i] = v.r;
+            zr[2 * i + 1] = v.i;
+        }
+    }
+}
+
+template <typename T>
+struct TlmRowArgs {
+    const T* zc;          // column-passed row spectra of the stage input (pairs): L w after the inverse rows
+    const T* w;           // stage input fields (k x n)
+    const double* Y;      // base stage value and its stream function
+    const double* psi;
+    T* dz;                // state fields (read; the new state at stage 3)
+    T* acc;               // RK accumulator fields
+    T* wnext;             // next stage input (stages 0-2)
+    T* znext;             // row spectra of the next stage input (pairs), or null
+    const T* W;           // x twiddles
+    int k, ny, stage;
+    T cnext, h, inv12d2, nu_d2;
+};
+
+// TLM stage (grid: row blocks x pairs): kv = -J_A(L w, Y) - J_A(psi, w) + nu lap w
+// on the owned rows of both fields of the pair, the RK update, and the row
+// spectra of the next stage input.
+// STAGE: the rows of Y, psi and w the stencils read are staged in LDS with
+// coalesced loads first (few pairs: latency-bound launches); otherwise each
+// point loads its neighbourhoods itself (many pairs: more workgroups per CU).
+template <typename T, int B, bool STAGE>
+__global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> a) {
+    constexpr int N = 16 * B;
+    constexpr int PER = (kRowsOwn * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
+    constexpr int SR = fftl::kLines * N;  // one staged field
+    __shared__ fftl::C2<T> lds[fftl::kLines * fftl::padded(N)];
+    __shared__ T stg[STAGE ? 4 * SR : 1];
+    __shared__ fftl::C2<T> wl[N];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.y, j0 = blockIdx.x * kRowsOwn, ny = a.ny;
+    const int rown = min(kRowsOwn, ny - j0);
+    const size_t n = static_cast<size_t>(N) * ny;
+    const int nf = 2 * p + 1 < a.k ? 2 : 1;
+    {  // every global load of the prologue in flight before the first LDS store
+        fftl::C2<T> tw[fftl::twiddles_per_thread<N>()];
+        fftl::load_twiddles<T, N>(a.W, tw);
+        fftl::C2<T> zv[B];
+        rows_spec_load<T, B>(a.zc, p, j0, rown, ny, zv);
+        if constexpr (STAGE) {
+            double yv[B], pv[B];
+            T wv[2][B];
+            stage_load<double, N>(a.Y, j0, rown, ny, yv);
+            stage_load<double, N>(a.psi, j0, rown, ny, pv);
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+                stage_load<T, N>(a.w + static_cast<size_t>(2 * p + min(f, nf - 1)) * n, j0, rown, ny, wv[f]);
+            stage_store<T, double, N>(stg, yv, rown);
+            stage_store<T, double, N>(stg + SR, pv, rown);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) stage_store<T, T, N>(stg + (2 + f) * SR, wv[f], rown);
+        }
+        fftl::store_twiddles<T, N>(wl, tw);
+        rows_spec_store<T, B>(lds, rown, zv);
+    }
+    __syncthreads();
+    rows_inverse<T, B>(lds, rown, wl);
+    const T bst = static_cast<T>(kRkB[a.stage]);
+    // the points' own dz and acc, loaded together before any arithmetic
+    T dzv[2][PER], acv[2][PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = min(tid + t * 16 * fftl::kLines, rown * N - 1);
+        const int jr = e / N, i = e - jr * N;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const size_t g = static_cast<size_t>(2 * p + min(f, nf - 1)) * n + static_cast<size_t>(j0 + jr) * N + i;
+            dzv[f][t] = a.dz[g];
+            acv[f][t] = a.stage == 0 ? T(0) : a.acc[g];
+        }
+    }
+    T out[2][PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        out[0][t] = T(0);
+        out[1][t] = T(0);
+        const int e = tid + t * 16 * fftl::kLines;
+        if (e < rown * N) {
+            const int jr = e / N, i = e - jr * N, j = j0 + jr;
+            T Yn[3][3], Pn[3][3];
+            if constexpr (STAGE) {
+                st9<T, N>(stg, jr, i, Yn);
+                st9<T, N>(stg + SR, jr, i, Pn);
+            } else {
+                load9<T, double>(a.Y, N, ny, j, i, Yn);
+                load9<T, double>(a.psi, N, ny, j, i, Pn);
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (f < nf) {
+                    const size_t off = static_cast<size_t>(2 * p + f) * n;
+                    T phn[3][3], wn[3][3];
+                    lds9<T, N>(lds, jr, i, f, phn);
+                    if constexpr (STAGE)
+                        st9<T, N>(stg + (2 + f) * SR, jr, i, wn);
+                    else
+                        load9<T, T>(a.w + off, N, ny, j, i, wn);
+                    const T kv = -(arakawa12_nb<T>(phn, Yn) * a.inv12d2) - arakawa12_nb<T>(Pn, wn) * a.inv12d2 +
+                                 a.nu_d2 * lap5_nb<T>(wn);
+                    const size_t g = off + static_cast<size_t>(j) * N + i;
+                    const T dv = dzv[f][t];
+                    T o;
+                    if (a.stage == 0) {
+                        a.acc[g] = kv * bst;
+                        o = dv + a.cnext * kv;
+                        a.wnext[g] = o;
+                    } else if (a.stage < 3) {
+                        a.acc[g] = acv[f][t] + kv * bst;
+                        o = dv + a.cnext * kv;
+                        a.wnext[g] = o;
+                    } else {
+                        o = dv + a.h * (acv[f][t] + kv * bst);
+                        a.dz[g] = o;
+                    }
+                    out[f][t] = o;
+                }
+            }
+        }
+    }
+    if (a.znext) rows_forward<T, B, PER>(lds, out, a.znext, p, j0, rown, ny, wl);
+}
+
+template <typename T>
+struct AdjRowArgs {
+    // combine of stage m (m = -1: none): P = L jq from the column-passed
+    // spectra zc, theta = -P + r_in, then (m = 3) acc = lam + theta,
+    // (m = 2, 1) acc += theta, each with mu = cl lam + ct theta, or (m = 0)
+    // lam = acc + theta
+    const T* zc;
+    const T* r_in;
+    int m;
+    T cl, ct;
+    T* lam;
+    T* acc;
+    // observation forcing added to the new lambda (m = 0) or to lam (m = -1):
+    // lam[o] += W[force_it][o] / sigma_o at the observed cells; force_it < 0: none
+    const T* Wobs;
+    int force_it, stride, nox, n_obs;
+    T inv_sigma;
+    // stencil of stage s (-1: none) on mu' = mu (s < 3) or a3 lam (s = 3):
+    // jq = J_A(Y, mu'), r_out = J_A(psi, mu') + nu lap mu', row spectra of jq to znext
+    int s;
+    T a3;
+    const double* Y;
+    const double* psi;
+    T* r_out;
+    T* znext;
+    const T* W;  // x twiddles
+    int k, ny;
+    T inv12d2, nu_d2;
+};
+
+// ADJ row stage (grid: row blocks x pairs): the combine of one stage and the
+// stencil of the next, with the combine recomputed on the halo rows so that
+// the stencil has its neighbours without another launch.
+template <typename T, int B, bool STAGE>
+__global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> a) {
+    constexpr int N = 16 * B;
+    constexpr int PER = (kRowsOwn * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
+    constexpr int PERH = (fftl::kLines * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
+    constexpr int SR = fftl::kLines * N;
+    __shared__ fftl::C2<T> lds[fftl::kLines * fftl::padded(N)];
+    __shared__ T stg[STAGE ? 2 * SR : 1];
+    __shared__ fftl::C2<T> wl[N];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.y, j0 = blockIdx.x * kRowsOwn, ny = a.ny;
+    const int rown = min(kRowsOwn, ny - j0);
+    const size_t n = static_cast<size_t>(N) * ny;
+    const int nf = 2 * p + 1 < a.k ? 2 : 1;
+    {  // every global load of the prologue in flight before the first LDS store
+        fftl::C2<T> tw[fftl::twiddles_per_thread<N>()];
+        fftl::load_twiddles<T, N>(a.W, tw);
+        fftl::C2<T> zv[B];
+        if (a.m >= 0) rows_spec_load<T, B>(a.zc, p, j0, rown, ny, zv);
+        if constexpr (STAGE) {
+            if (a.s >= 0) {
+                double yv[B], pv[B];
+                stage_load<double, N>(a.Y, j0, rown, ny, yv);
+                stage_load<double, N>(a.psi, j0, rown, ny, pv);
+                stage_store<T, double, N>(stg, yv, rown);
+                stage_store<T, double, N>(stg + SR, pv, rown);
+            }
+        }
+        fftl::store_twiddles<T, N>(wl, tw);
+        if (a.m >= 0) rows_spec_store<T, B>(lds, rown, zv);
+    }
+    __syncthreads();
+    if (a.m >= 0) rows_inverse<T, B>(lds, rown, wl);
+    // mu' on the owned rows and one halo row on each side, into the LDS lines;
+    // in chunks of CH points per thread, each chunk's global loads issued together
+    constexpr int CH = PERH < 8 ? PERH : 8;
+    const bool need_r = a.m >= 0, need_lam = a.m != 0, need_acc = a.m == 0 || a.m == 1 || a.m == 2;
+#pragma unroll
+    for (int t0 = 0; t0 < PERH; t0 += CH) {
+        T rv[2][CH], lv[2][CH], av[2][CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = min(tid + (t0 + u) * 16 * fftl::kLines, (rown + 2) * N - 1);
+            const int lr = e / N, i = e - lr * N;
+            int j = j0 - 1 + lr;
+            j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const size_t g =
+                    static_cast<size_t>(2 * p + min(f, nf - 1)) * n + static_cast<size_t>(j) * N + i;
+                rv[f][u] = need_r ? a.r_in[g] : T(0);
+                lv[f][u] = need_lam ? a.lam[g] : T(0);
+                av[f][u] = need_acc ? a.acc[g] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = tid + (t0 + u) * 16 * fftl::kLines;
+            if (e < (rown + 2) * N) {
+                const int lr = e / N, i = e - lr * N;
+                int j = j0 - 1 + lr;
+                j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+                const bool owned = lr >= 1 && lr <= rown;
+                const bool obs = a.force_it >= 0 && (j % a.stride) == 0 && (i % a.stride) == 0;
+                const int o = (j / a.stride) * a.nox + i / a.stride;
+                fftl::C2<T>& slot = lds[lr * fftl::padded(N) + fftl::padded(i)];
+                T mu2[2] = {T(0), T(0)};
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    if (f < nf) {
+                        const int v = 2 * p + f;
+                        const size_t g = static_cast<size_t>(v) * n + static_cast<size_t>(j) * N + i;
+                        T mu;
+                        if (a.m >= 0) {
+                            const T P = f ? slot.i : slot.r;
+                            const T th = -P + rv[f][u];
+                            if (a.m == 3) {
+                                const T l = lv[f][u];
+                                if (owned) a.acc[g] = l + th;
+                                mu = a.cl * l + a.ct * th;
+                            } else if (a.m > 0) {
+                                if (owned) a.acc[g] = av[f][u] + th;
+                                mu = a.cl * lv[f][u] + a.ct * th;
+                            } else {
+                                T l = av[f][u] + th;
+                                if (obs)
+                                    l = l + a.Wobs[(static_cast<size_t>(a.force_it) * a.n_obs + o) * a.k + v] *
+                                                a.inv_sigma;
+                                if (owned) a.lam[g] = l;
+                                mu = a.a3 * l;
+                            }
+                        } else {
+                            T l = lv[f][u];
+                            if (obs) {
+                                l = l + a.Wobs[(static_cast<size_t>(a.force_it) * a.n_obs + o) * a.k + v] *
+                                            a.inv_sigma;
+                                if (owned) a.lam[g] = l;
+                            }
+                            mu = a.a3 * l;
+                        }
+                        mu2[f] = mu;
+                    }
+                }
+                slot = fftl::C2<T>{mu2[0], mu2[1]};
+            }
+        }
+    }
+    if (a.s < 0) return;  // uniform across the workgroup
+    __syncthreads();
+    T out[2][PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        out[0][t] = T(0);
+        out[1][t] = T(0);
+        const int e = tid + t * 16 * fftl::kLines;
+        if (e < rown * N) {
+            const int jr = e / N, i = e - jr * N, j = j0 + jr;
+            T Yn[3][3], Pn[3][3];
+            if constexpr (STAGE) {
+                st9<T, N>(stg, jr, i, Yn);
+                st9<T, N>(stg + SR, jr, i, Pn);
+            } else {
+                load9<T, double>(a.Y, N, ny, j, i, Yn);
+                load9<T, double>(a.psi, N, ny, j, i, Pn);
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (f < nf) {
+                    T mn[3][3];
+                    lds9<T, N>(lds, jr, i, f, mn);
+                    const size_t g = static_cast<size_t>(2 * p + f) * n + static_cast<size_t>(j) * N + i;
+                    out[f][t] = arakawa12_nb<T>(Yn, mn) * a.inv12d2;
+                    a.r_out[g] = arakawa12_nb<T>(Pn, mn) * a.inv12d2 + a.nu_d2 * lap5_nb<T>(mn);
+                }
+            }
+        }
+    }
+    rows_forward<T, B, PER>(lds, out, a.znext, p, j0, rown, ny, wl);
+}
+
+// Rows staged in LDS while the grid has at most this many field pairs.
+constexpr int kStagePairs = 4;
+
+template <typename T>
+void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
+    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
+    const bool stage = (a.k + 1) / 2 <= kStagePairs;
+    switch (nx / 16) {
+#define RP4D_TLM_ROWS(b)                                                    \
+    case b:                                                                 \
+        if (stage && b <= 16)                                               \
+            bve_tlm_rows<T, b, (b <= 16)><<<grid, blk, 0, st>>>(a);          \
+        else                                                                \
+            bve_tlm_rows<T, b, false><<<grid, blk, 0, st>>>(a);              \
+        break;
+        RP4D_TLM_ROWS(2) RP4D_TLM_ROWS(3) RP4D_TLM_ROWS(4) RP4D_TLM_ROWS(5) RP4D_TLM_ROWS(6) RP4D_TLM_ROWS(8)
+        RP4D_TLM_ROWS(10) RP4D_TLM_ROWS(12) RP4D_TLM_ROWS(16) RP4D_TLM_ROWS(20) RP4D_TLM_ROWS(24) RP4D_TLM_ROWS(32)
+#undef RP4D_TLM_ROWS
+        default: fail(RP4D_EINVAL, "2-D grid: unsupported nx");
+    }
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_adj_rows(const AdjRowArgs<T>& a, int nx, hipStream_t st) {
+    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
+    const bool stage = (a.k + 1) / 2 <= kStagePairs;
+    switch (nx / 16) {
+#define RP4D_ADJ_ROWS(b)                                                    \
+    case b:                                                                 \
+        if (stage && b <= 16)                                               \
+            bve_adj_rows<T, b, (b <= 16)><<<grid, blk, 0, st>>>(a);          \
+        else                                                                \
+            bve_adj_rows<T, b, false><<<grid, blk, 0, st>>>(a);              \
+        break;
+        RP4D_ADJ_ROWS(2) RP4D_ADJ_ROWS(3) RP4D_ADJ_ROWS(4) RP4D_ADJ_ROWS(5) RP4D_ADJ_ROWS(6) RP4D_ADJ_ROWS(8)
+        RP4D_ADJ_ROWS(10) RP4D_ADJ_ROWS(12) RP4D_ADJ_ROWS(16) RP4D_ADJ_ROWS(20) RP4D_ADJ_ROWS(24) RP4D_ADJ_ROWS(32)
+#undef RP4D_ADJ_ROWS
+        default: fail(RP4D_EINVAL, "2-D grid: unsupported nx");
+    }
+    RP4D_HIP(hipGetLastError());
 }
 
 inline unsigned ublk(long count, int t = 256) { return static_cast<unsigned>((count + t - 1) / t); }
@@ -429,7 +854,10 @@ void bve_inv_laplacian(rp4d_problem* p, int k, const T* in, T* out) {
 
 namespace {
 
-// TLM sweep of k field-major perturbations dz (overwritten); observations to Z (n_t, n_obs, k).
+// TLM sweep of k field-major perturbations dz (overwritten); observations to Z
+// (n_t, n_obs, k).  Each RK stage is one fused row launch (bve_tlm_rows) and
+// one column pass.  ws holds 8 blocks of k fields: wA, wB, acc, the two
+// double-width row-spectra buffers zA (blocks 3-4) and zB (5-6); dz is block 7.
 template <typename T>
 void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) {
     const int n = p->n, nx = p->bve->nx, ny = p->bve->ny;
@@ -437,24 +865,51 @@ void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) 
     const size_t fk = static_cast<size_t>(k) * n;
     T* wA = ws;
     T* wB = ws + fk;
-    T* phi = ws + 2 * fk;
-    T* acc = ws + 3 * fk;
-    T* t1 = ws + 4 * fk;
-    T* t2 = ws + 5 * fk;
+    T* acc = ws + 2 * fk;
+    T* zc = ws + 3 * fk;
+    T* zn = ws + 5 * fk;
     const double h = p->d.dt, dd = p->bve->d;
     const T inv12d2 = static_cast<T>(1.0 / (12.0 * dd * dd)), nu_d2 = static_cast<T>(p->d.nu / (dd * dd));
     const int stride = p->d.obs_stride, nox = (nx + stride - 1) / stride;
     const T cn[3] = {static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};
-    const dim3 grid(ublk(n), k);
-    const T* Dl = spec_of<T>(p).Dlap;
+    const Spec<T> sp = spec_of<T>(p);
+    // FFT-equivalent flops of one solve of k fields, and the stencil work of a stage
+    const double fl_solve = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(n)) * k;
+    const double fl_sten = (2 * FL_ARAKAWA + FL_LAP + 6.0) * static_cast<double>(fk);
+    {
+        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+        launch_fft_rows_fwd<T>(dz, k, nx, ny, zc, sp.Wx, st);
+        launch_fft_cols<T>(zc, k, nx, ny, sp.Dlap, sp.Wy, st);
+    }
     for (int s = 0; s < p->s_last; ++s) {
         for (int i = 0; i < 4; ++i) {
-            const T* w = i == 0 ? dz : (i == 2 ? wB : wA);
-            T* wn = i == 1 ? wB : wA;  // stage 0 -> A, 1 -> B, 2 -> A
-            spectral_apply<T>(p, k, w, Dl, phi, t1, t2);
-            KernelTimer kt(p->ctx, RP4D_K_STENCIL, (2 * FL_ARAKAWA + FL_LAP + 6.0) * static_cast<double>(fk));
-            bve_tlm_stage<T><<<grid, 256, 0, st>>>(w, phi, stage_Y(tr, s, i), stage_psi(tr, s, i), dz, acc, wn, i,
-                                                    i < 3 ? cn[i] : T(0), static_cast<T>(h), inv12d2, nu_d2, nx, ny);
+            const bool last = s + 1 == p->s_last && i == 3;
+            TlmRowArgs<T> a{};
+            a.zc = zc;
+            a.w = i == 0 ? dz : (i == 2 ? wB : wA);
+            a.Y = stage_Y(tr, s, i);
+            a.psi = stage_psi(tr, s, i);
+            a.dz = dz;
+            a.acc = acc;
+            a.wnext = i == 1 ? wB : wA;  // stage 0 -> A, 1 -> B, 2 -> A
+            a.znext = last ? nullptr : zn;
+            a.W = sp.Wx;
+            a.k = k;
+            a.ny = ny;
+            a.stage = i;
+            a.cnext = i < 3 ? cn[i] : T(0);
+            a.h = static_cast<T>(h);
+            a.inv12d2 = inv12d2;
+            a.nu_d2 = nu_d2;
+            {
+                KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+                launch_tlm_rows<T>(a, nx, st);
+            }
+            if (!last) {
+                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+                launch_fft_cols<T>(zn, k, nx, ny, sp.Dlap, sp.Wy, st);
+                std::swap(zc, zn);
+            }
         }
         const int s1 = s + 1;
         if (s1 % p->d.obs_every == 0 && s1 / p->d.obs_every <= p->n_t) {
@@ -468,43 +923,98 @@ void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) 
 }
 
 // ADJ sweep with forcing W (n_t, n_obs, k); lambda_0 (field-major) left in lam.
+// Each RK stage is one fused row launch (bve_adj_rows: the combine of the
+// stage, the observation forcing between steps, and the stencil of the next
+// stage) and one column pass.  ws: r_a, r_b, acc, zA (blocks 3-4), zB (5-6).
 template <typename T>
 void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, T* ws) {
     const int n = p->n, nx = p->bve->nx, ny = p->bve->ny;
     hipStream_t st = bst(p);
     const size_t fk = static_cast<size_t>(k) * n;
-    T* mu = ws;
-    T* jq = ws + fk;
-    T* r = ws + 2 * fk;
-    T* P = ws + 3 * fk;
-    T* acc = ws + 4 * fk;
-    T* t1 = ws + 5 * fk;
-    T* t2 = ws + 6 * fk;
+    T* rc = ws;
+    T* rn = ws + fk;
+    T* acc = ws + 2 * fk;
+    T* zc = ws + 3 * fk;
+    T* zn = ws + 5 * fk;
     const double h = p->d.dt, dd = p->bve->d;
     const T inv12d2 = static_cast<T>(1.0 / (12.0 * dd * dd)), nu_d2 = static_cast<T>(p->d.nu / (dd * dd));
     const int stride = p->d.obs_stride, nox = (nx + stride - 1) / stride;
-    const dim3 grid(ublk(n), k);
-    const T* Dl = spec_of<T>(p).Dlap;
-    // mu of the next (lower) stage: (h/3, h), (h/3, h/2), (h/6, h/2)
+    const Spec<T> sp = spec_of<T>(p);
+    // mu of the next (lower) stage after the combine of stage i: (h/3, h), (h/3, h/2), (h/6, h/2)
     const T cl[4] = {T(0), static_cast<T>(h / 6.0), static_cast<T>(h / 3.0), static_cast<T>(h / 3.0)};
     const T ct[4] = {T(0), static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};
+    const double fl_solve = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(n)) * k;
+    const double fl_sten = (2 * FL_ARAKAWA + FL_LAP + 2.0) * static_cast<double>(fk);
+    auto obs_it = [&](int s) {  // observation index of state s, or -1
+        return (s % p->d.obs_every == 0 && s / p->d.obs_every <= p->n_t && s >= 1) ? s / p->d.obs_every - 1 : -1;
+    };
+    auto base = [&](AdjRowArgs<T>& a) {
+        a.lam = lam;
+        a.acc = acc;
+        a.Wobs = W;
+        a.stride = stride;
+        a.nox = nox;
+        a.n_obs = p->n_obs;
+        a.inv_sigma = static_cast<T>(1.0 / p->d.sigma_o);
+        a.a3 = static_cast<T>(h / 6.0);
+        a.W = sp.Wx;
+        a.k = k;
+        a.ny = ny;
+        a.inv12d2 = inv12d2;
+        a.nu_d2 = nu_d2;
+    };
     bve_zero<T><<<ublk(fk), 256, 0, st>>>(lam, static_cast<long>(fk));
-    for (int s = p->s_last; s >= 1; --s) {
-        if (s % p->d.obs_every == 0 && s / p->d.obs_every <= p->n_t) {
-            const int it = s / p->d.obs_every - 1;
-            bve_obs_scatter<T><<<ublk(static_cast<long>(p->n_obs) * k), 256, 0, st>>>(
-                W + static_cast<size_t>(it) * p->n_obs * k, k, n, nx, stride, nox, p->n_obs,
-                static_cast<T>(1.0 / p->d.sigma_o), lam);
+    {
+        // the forcing of the last state and the stencil of stage 3 of the last step
+        AdjRowArgs<T> a{};
+        base(a);
+        a.m = -1;
+        a.force_it = obs_it(p->s_last);
+        a.s = 3;
+        a.Y = stage_Y(tr, p->s_last - 1, 3);
+        a.psi = stage_psi(tr, p->s_last - 1, 3);
+        a.r_out = rc;
+        a.znext = zc;
+        {
+            KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+            launch_adj_rows<T>(a, nx, st);
         }
+        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+        launch_fft_cols<T>(zc, k, nx, ny, sp.Dlap, sp.Wy, st);
+    }
+    for (int s = p->s_last; s >= 1; --s) {
         for (int i = 3; i >= 0; --i) {
-            {
-                KernelTimer kt(p->ctx, RP4D_K_STENCIL, (2 * FL_ARAKAWA + FL_LAP + 2.0) * static_cast<double>(fk));
-                bve_adj_stencil<T><<<grid, 256, 0, st>>>(i == 3 ? lam : mu, i == 3 ? static_cast<T>(h / 6.0) : T(1),
-                                                          stage_Y(tr, s - 1, i), stage_psi(tr, s - 1, i), jq, r,
-                                                          inv12d2, nu_d2, nx, ny);
+            AdjRowArgs<T> a{};
+            base(a);
+            a.zc = zc;
+            a.r_in = rc;
+            a.m = i;
+            a.cl = cl[i];
+            a.ct = ct[i];
+            a.force_it = -1;
+            a.s = -1;
+            if (i > 0) {  // stencil of the next stage of this step
+                a.s = i - 1;
+                a.Y = stage_Y(tr, s - 1, i - 1);
+                a.psi = stage_psi(tr, s - 1, i - 1);
+            } else if (s > 1) {  // forcing of state s-1, stencil of stage 3 of step s-1
+                a.force_it = obs_it(s - 1);
+                a.s = 3;
+                a.Y = stage_Y(tr, s - 2, 3);
+                a.psi = stage_psi(tr, s - 2, 3);
             }
-            spectral_apply<T>(p, k, jq, Dl, P, t1, t2);
-            bve_adj_combine<T><<<ublk(fk), 256, 0, st>>>(P, r, lam, acc, mu, i, cl[i], ct[i], static_cast<long>(fk));
+            a.r_out = rn;
+            a.znext = a.s >= 0 ? zn : nullptr;
+            {
+                KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+                launch_adj_rows<T>(a, nx, st);
+            }
+            if (a.s >= 0) {
+                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+                launch_fft_cols<T>(zn, k, nx, ny, sp.Dlap, sp.Wy, st);
+                std::swap(zc, zn);
+                std::swap(rc, rn);
+            }
         }
     }
     RP4D_HIP(hipGetLastError());
@@ -515,7 +1025,7 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
 template <typename T>
 void bve_tlm(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* Z) {
     T* ws = ws_fields<T>(p, k, 8);
-    T* dz = ws + static_cast<size_t>(6) * k * p->n;
+    T* dz = ws + static_cast<size_t>(7) * k * p->n;
     bve_bhalf<T>(p, k, V, k, dz, 1, nullptr);  // blocked kc = 1 is field-major
     tlm_sweep<T>(p, tr, k, dz, Z, ws);
 }
@@ -528,13 +1038,15 @@ void bve_adj(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* U, cons
     bve_bhalf<T>(p, k, lam, 1, U, k, addv);
 }
 
+// The TLM's state (block 7) is dead once its observations are in Z, so the
+// ADJ's lambda takes the same block.
 template <typename T>
 void bve_hessian(rp4d_problem* p, const rp4d_traj* tr, int k, const T* V, T* HV, bool add_identity) {
     T* ws = ws_fields<T>(p, k, 8);
     p->bve->ws_obs.ensure(static_cast<size_t>(p->m) * k * sizeof(T));
     T* Z = p->bve->ws_obs.as<T>();
-    T* dz = ws + static_cast<size_t>(6) * k * p->n;
-    T* lam = ws + static_cast<size_t>(7) * k * p->n;
+    T* dz = ws + static_cast<size_t>(7) * k * p->n;
+    T* lam = dz;
     bve_bhalf<T>(p, k, V, k, dz, 1, nullptr);
     tlm_sweep<T>(p, tr, k, dz, Z, ws);
     adj_sweep<T>(p, tr, k, Z, lam, ws);

@@ -26,6 +26,7 @@
 // vector units.
 #include <cmath>
 
+#include "fft_line.hpp"
 #include "internal.hpp"
 
 namespace rp4d {
@@ -33,149 +34,11 @@ namespace {
 
 #pragma clang fp contract(off)
 
-constexpr int kLines = 8;  // lines (rows or columns) per workgroup, 16 threads each
+using namespace fftl;
 
-__host__ __device__ constexpr int padded(int e) { return e + (e >> 4); }
-
-template <typename T>
-struct C2 {
-    T r, i;
-};
-
-template <typename T>
-__device__ __forceinline__ C2<T> cmul(C2<T> a, T wr, T wi) {
-    return C2<T>{a.r * wr - a.i * wi, a.r * wi + a.i * wr};
-}
-
-// In-place forward 4-point DFT of (a, b, c, d) (W4 = -i).
-template <typename T>
-__device__ __forceinline__ void dft4(C2<T>& a, C2<T>& b, C2<T>& c, C2<T>& d) {
-    const C2<T> t0{a.r + c.r, a.i + c.i}, t1{a.r - c.r, a.i - c.i};
-    const C2<T> t2{b.r + d.r, b.i + d.i}, t3{b.r - d.r, b.i - d.i};
-    a = C2<T>{t0.r + t2.r, t0.i + t2.i};
-    c = C2<T>{t0.r - t2.r, t0.i - t2.i};
-    b = C2<T>{t1.r + t3.i, t1.i - t3.r};  // t1 - i t3
-    d = C2<T>{t1.r - t3.i, t1.i + t3.r};  // t1 + i t3
-}
-
-// Forward 16-point DFT of x (natural order in, natural order out): 4 x 4 with
-// n = n1 + 4 n2, k = 4 k1 + k2.
-template <typename T>
-__device__ __forceinline__ void fft16(C2<T> (&x)[16]) {
-    // cos / sin of 2 pi m / 16
-    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
-    constexpr double c2 = 0.70710678118654752440;
-#pragma unroll
-    for (int n1 = 0; n1 < 4; ++n1) dft4(x[n1], x[n1 + 4], x[n1 + 8], x[n1 + 12]);
-    // now x[n1 + 4 k2] = y[n1][k2]; twiddle by W16^{n1 k2} = exp(-2 pi i n1 k2 / 16)
-    x[5] = cmul(x[5], T(c1), T(-s1));    // n1 = 1, k2 = 1: m = 1
-    x[9] = cmul(x[9], T(c2), T(-c2));    // n1 = 1, k2 = 2: m = 2
-    x[13] = cmul(x[13], T(s1), T(-c1));  // n1 = 1, k2 = 3: m = 3
-    x[6] = cmul(x[6], T(c2), T(-c2));    // n1 = 2, k2 = 1: m = 2
-    x[10] = C2<T>{x[10].i, -x[10].r};    // n1 = 2, k2 = 2: m = 4 (times -i)
-    x[14] = cmul(x[14], T(-c2), T(-c2)); // n1 = 2, k2 = 3: m = 6
-    x[7] = cmul(x[7], T(s1), T(-c1));    // n1 = 3, k2 = 1: m = 3
-    x[11] = cmul(x[11], T(-c2), T(-c2)); // n1 = 3, k2 = 2: m = 6
-    x[15] = cmul(x[15], T(-c1), T(s1));  // n1 = 3, k2 = 3: m = 9
-    // 4-point DFTs over n1 for each k2: X[4 k1 + k2] from y[0..3][k2] at 4 k2 + n1
-    C2<T> o[16];
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-        C2<T> a = x[4 * k2], b = x[4 * k2 + 1], c = x[4 * k2 + 2], d = x[4 * k2 + 3];
-        dft4(a, b, c, d);
-        o[k2] = a;
-        o[4 + k2] = b;
-        o[8 + k2] = c;
-        o[12 + k2] = d;
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = o[e];
-}
-
-// Forward B-point DFT of x with W_B^m = W_N^{m N/B} (W holds exp(-2 pi i m / N)
-// as (re, im) pairs).
-template <typename T, int B>
-__device__ __forceinline__ void dft_small(C2<T> (&x)[B], const T* __restrict__ W, int N) {
-    if constexpr (B == 16) {
-        fft16<T>(x);
-    } else if constexpr (B == 4) {
-        dft4(x[0], x[1], x[2], x[3]);
-    } else {
-        T wr[B], wi[B];
-        const int st = N / B;
-#pragma unroll
-        for (int m = 0; m < B; ++m) {
-            wr[m] = W[2 * m * st];
-            wi[m] = W[2 * m * st + 1];
-        }
-        C2<T> y[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            T ar = x[0].r, ai = x[0].i;
-#pragma unroll
-            for (int n = 1; n < B; ++n) {
-                const int m = (n * k) % B;
-                ar = ar + (x[n].r * wr[m] - x[n].i * wi[m]);
-                ai = ai + (x[n].r * wi[m] + x[n].i * wr[m]);
-            }
-            y[k] = C2<T>{ar, ai};
-        }
-#pragma unroll
-        for (int k = 0; k < B; ++k) x[k] = y[k];
-    }
-}
-
-// Transform the line of N = 16 B complex values at `line` (LDS, padded) in place
-// with 16 threads (q = 0..15); conj = true gives the unnormalised inverse.
-// Every thread of the workgroup must call it (it holds a barrier).
-template <typename T, int B>
-__device__ __forceinline__ void line_fft(C2<T>* line, int q, bool active, const T* __restrict__ W, bool conj) {
-    constexpr int N = 16 * B;
-    const T sg = conj ? T(-1) : T(1);
-    if (active) {
-        // step 1: thread n1 = q, B-point DFT over n2 of x[q + 16 n2], then W_N^{q k2}
-        C2<T> x[B];
-#pragma unroll
-        for (int n2 = 0; n2 < B; ++n2) {
-            const C2<T> v = line[padded(q + 16 * n2)];
-            x[n2] = C2<T>{v.r, sg * v.i};
-        }
-        dft_small<T, B>(x, W, N);
-#pragma unroll
-        for (int k2 = 0; k2 < B; ++k2) {
-            const int m = q * k2;
-            x[k2] = cmul(x[k2], W[2 * m], W[2 * m + 1]);
-            line[padded(q + 16 * k2)] = x[k2];
-        }
-    }
-    __syncthreads();
-    // step 3: for k2 = q, q + 16, ...: 16-point DFT over n1 of block k2, to X[B k1 + k2]
-    constexpr int R = (B + 15) / 16;
-    C2<T> y[R][16];
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k2 = q + 16 * r;
-            if (k2 < B) {
-#pragma unroll
-                for (int n1 = 0; n1 < 16; ++n1) y[r][n1] = line[padded(n1 + 16 * k2)];
-                fft16<T>(y[r]);
-            }
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k2 = q + 16 * r;
-            if (k2 < B) {
-#pragma unroll
-                for (int k1 = 0; k1 < 16; ++k1) line[padded(B * k1 + k2)] = C2<T>{y[r][k1].r, sg * y[r][k1].i};
-            }
-        }
-    }
-    __syncthreads();
-}
+// Every kernel below issues all of its global loads (data, twiddles and, for
+// the columns, the diagonal) before its first LDS store, so that one memory
+// latency is paid per kernel rather than one per loop iteration.
 
 // Rows forward: pair p of k real fields (field-major, nx * ny each) -> complex
 // row spectra z[p][j][kx] (interleaved re, im).
@@ -184,31 +47,38 @@ __global__ void __launch_bounds__(16 * kLines) fft_rows_fwd(const T* __restrict_
                                                             T* __restrict__ z, const T* __restrict__ W) {
     constexpr int N = 16 * B;  // nx
     __shared__ C2<T> lds[kLines * padded(N)];
+    __shared__ C2<T> wl[N];
     const int l = threadIdx.x >> 4, q = threadIdx.x & 15;
     const int j = blockIdx.x * kLines + l, p = blockIdx.y;
     const bool active = j < ny;
     C2<T>* line = lds + l * padded(N);
     const size_t n = static_cast<size_t>(N) * ny;
-    if (active) {
-        const T* a = in + (2 * p) * n + static_cast<size_t>(j) * N;
-        const bool hasb = 2 * p + 1 < k;
-        const T* b = a + n;
+    C2<T> tw[twiddles_per_thread<N>()];
+    load_twiddles<T, N>(W, tw);
+    const bool hasb = 2 * p + 1 < k;
+    const T* a = in + (2 * p) * n + static_cast<size_t>(active ? j : 0) * N;
+    const T* b = hasb ? a + n : a;
+    C2<T> v[B];
 #pragma unroll
-        for (int e = 0; e < B; ++e) {
-            const int i = q + 16 * e;
-            line[padded(i)] = C2<T>{a[i], hasb ? b[i] : T(0)};
-        }
+    for (int e = 0; e < B; ++e) {
+        const int i = q + 16 * e;
+        v[e] = C2<T>{a[i], b[i]};
+    }
+    store_twiddles<T, N>(wl, tw);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) line[padded(q + 16 * e)] = C2<T>{v[e].r, hasb ? v[e].i : T(0)};
     }
     __syncthreads();
-    line_fft<T, B>(line, q, active, W, false);
+    line_fft<T, B>(line, q, active, wl, false);
     if (active) {
         T* zo = z + (static_cast<size_t>(p) * n + static_cast<size_t>(j) * N) * 2;
 #pragma unroll
         for (int e = 0; e < B; ++e) {
             const int i = q + 16 * e;
-            const C2<T> v = line[padded(i)];
-            zo[2 * i] = v.r;
-            zo[2 * i + 1] = v.i;
+            const C2<T> u = line[padded(i)];
+            zo[2 * i] = u.r;
+            zo[2 * i + 1] = u.i;
         }
     }
 }
@@ -220,41 +90,52 @@ __global__ void __launch_bounds__(16 * kLines) fft_cols(T* __restrict__ z, int n
                                                         const T* __restrict__ W) {
     constexpr int N = 16 * B;  // ny
     __shared__ C2<T> lds[kLines * padded(N)];
+    __shared__ C2<T> wl[N];
     const int tid = threadIdx.x;
     const int l = tid >> 4, q = tid & 15;
     const int kx0 = blockIdx.x * kLines, p = blockIdx.y;
     const bool active = kx0 + l < nx;
     T* zp = z + static_cast<size_t>(p) * N * nx * 2;
-    // load: element (j, c) of the tile, consecutive threads along c
-    for (int e = tid; e < N * kLines; e += 16 * kLines) {
-        const int j = e / kLines, c = e - j * kLines;
-        if (kx0 + c < nx) {
-            const T* s = zp + (static_cast<size_t>(j) * nx + kx0 + c) * 2;
-            lds[c * padded(N) + padded(j)] = C2<T>{s[0], s[1]};
-        }
+    // thread tid loads rows j = tid / kLines + 16 r of column kx0 + tid % kLines
+    const int c = tid % kLines, jb = tid / kLines;
+    const bool cok = kx0 + c < nx;
+    C2<T> tw[twiddles_per_thread<N>()];
+    load_twiddles<T, N>(W, tw);
+    C2<T> v[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        const T* s = zp + (static_cast<size_t>(jb + 16 * r) * nx + (cok ? kx0 + c : 0)) * 2;
+        v[r] = C2<T>{s[0], s[1]};
     }
+    // the diagonal at (ky = q + 16 e, kx0 + l), used after the forward transform
+    T d[B];
+    const int kx = active ? kx0 + l : 0;
+#pragma unroll
+    for (int e = 0; e < B; ++e) d[e] = D[static_cast<size_t>(q + 16 * e) * nx + kx];
+    store_twiddles<T, N>(wl, tw);
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+        if (cok) lds[c * padded(N) + padded(jb + 16 * r)] = v[r];
     __syncthreads();
     C2<T>* line = lds + l * padded(N);
-    line_fft<T, B>(line, q, active, W, false);
+    line_fft<T, B>(line, q, active, wl, false);
     if (active) {
-        const int kx = kx0 + l;
 #pragma unroll
         for (int e = 0; e < B; ++e) {
             const int ky = q + 16 * e;
-            const T d = D[static_cast<size_t>(ky) * nx + kx];
-            const C2<T> v = line[padded(ky)];
-            line[padded(ky)] = C2<T>{v.r * d, v.i * d};
+            const C2<T> u = line[padded(ky)];
+            line[padded(ky)] = C2<T>{u.r * d[e], u.i * d[e]};
         }
     }
     __syncthreads();
-    line_fft<T, B>(line, q, active, W, true);
-    for (int e = tid; e < N * kLines; e += 16 * kLines) {
-        const int j = e / kLines, c = e - j * kLines;
-        if (kx0 + c < nx) {
-            T* s = zp + (static_cast<size_t>(j) * nx + kx0 + c) * 2;
-            const C2<T> v = lds[c * padded(N) + padded(j)];
-            s[0] = v.r;
-            s[1] = v.i;
+    line_fft<T, B>(line, q, active, wl, true);
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        if (cok) {
+            T* s = zp + (static_cast<size_t>(jb + 16 * r) * nx + kx0 + c) * 2;
+            const C2<T> u = lds[c * padded(N) + padded(jb + 16 * r)];
+            s[0] = u.r;
+            s[1] = u.i;
         }
     }
 }
@@ -265,21 +146,28 @@ __global__ void __launch_bounds__(16 * kLines) fft_rows_inv(const T* __restrict_
                                                             T* __restrict__ out, const T* __restrict__ W) {
     constexpr int N = 16 * B;  // nx
     __shared__ C2<T> lds[kLines * padded(N)];
+    __shared__ C2<T> wl[N];
     const int l = threadIdx.x >> 4, q = threadIdx.x & 15;
     const int j = blockIdx.x * kLines + l, p = blockIdx.y;
     const bool active = j < ny;
     C2<T>* line = lds + l * padded(N);
     const size_t n = static_cast<size_t>(N) * ny;
-    if (active) {
-        const T* zi = z + (static_cast<size_t>(p) * n + static_cast<size_t>(j) * N) * 2;
+    C2<T> tw[twiddles_per_thread<N>()];
+    load_twiddles<T, N>(W, tw);
+    const T* zi = z + (static_cast<size_t>(p) * n + static_cast<size_t>(active ? j : 0) * N) * 2;
+    C2<T> v[B];
 #pragma unroll
-        for (int e = 0; e < B; ++e) {
-            const int i = q + 16 * e;
-            line[padded(i)] = C2<T>{zi[2 * i], zi[2 * i + 1]};
-        }
+    for (int e = 0; e < B; ++e) {
+        const int i = q + 16 * e;
+        v[e] = C2<T>{zi[2 * i], zi[2 * i + 1]};
+    }
+    store_twiddles<T, N>(wl, tw);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) line[padded(q + 16 * e)] = v[e];
     }
     __syncthreads();
-    line_fft<T, B>(line, q, active, W, true);
+    line_fft<T, B>(line, q, active, wl, true);
     if (active) {
         T* a = out + (2 * p) * n + static_cast<size_t>(j) * N;
         const bool hasb = 2 * p + 1 < k;
@@ -287,9 +175,9 @@ __global__ void __launch_bounds__(16 * kLines) fft_rows_inv(const T* __restrict_
 #pragma unroll
         for (int e = 0; e < B; ++e) {
             const int i = q + 16 * e;
-            const C2<T> v = line[padded(i)];
-            a[i] = v.r;
-            if (hasb) b[i] = v.i;
+            const C2<T> u = line[padded(i)];
+            a[i] = u.r;
+            if (hasb) b[i] = u.i;
         }
     }
 }
@@ -348,6 +236,22 @@ void launch_spectral_diag(const T* in, int k, int nx, int ny, const T* D, const 
     RP4D_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_fft_rows_fwd(const T* in, int k, int nx, int ny, T* z, const T* Wx, hipStream_t st) {
+    launch_rows<T>(false, in, k, nx, ny, z, nullptr, Wx, st);
+    RP4D_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_fft_cols(T* z, int k, int nx, int ny, const T* D, const T* Wy, hipStream_t st) {
+    launch_cols<T>(z, k, nx, ny, D, Wy, st);
+    RP4D_HIP(hipGetLastError());
+}
+
+template void launch_fft_rows_fwd<double>(const double*, int, int, int, double*, const double*, hipStream_t);
+template void launch_fft_rows_fwd<float>(const float*, int, int, int, float*, const float*, hipStream_t);
+template void launch_fft_cols<double>(double*, int, int, int, const double*, const double*, hipStream_t);
+template void launch_fft_cols<float>(float*, int, int, int, const float*, const float*, hipStream_t);
 template void launch_spectral_diag<double>(const double*, int, int, int, const double*, const double*,
                                            const double*, double*, double*, hipStream_t);
 template void launch_spectral_diag<float>(const float*, int, int, int, const float*, const float*, const float*,

@@ -320,6 +320,12 @@ bool fft_size_supported(int n);
 template <typename T>
 void launch_spectral_diag(const T* in, int k, int nx, int ny, const T* D, const T* Wx, const T* Wy, T* z, T* out,
                           hipStream_t st);
+// The passes on their own: row spectra of the ceil(k/2) field pairs of `in`
+// into z, and the column pass (forward, times D, inverse) of z in place.
+template <typename T>
+void launch_fft_rows_fwd(const T* in, int k, int nx, int ny, T* z, const T* Wx, hipStream_t st);
+template <typename T>
+void launch_fft_cols(T* z, int k, int nx, int ny, const T* D, const T* Wy, hipStream_t st);
 size_t bve_traj_stage_bytes(const rp4d_problem* p);
 void bve_fwd(rp4d_problem* p, const double* x0, rp4d_traj* tr, double* innov, double* obs_out);
 template <typename T>
