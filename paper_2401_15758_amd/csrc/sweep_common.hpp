@@ -59,9 +59,10 @@ struct LdsExchange {
 };
 
 // DPP wave shifts by one lane (lane i reads lane i - 1, resp. i + 1); the end
-// lane of the shift keeps its own value.  Every lane of the wave must be active.
-__device__ __forceinline__ int lane_from_lower(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int lane_from_upper(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+// lane of the shift reads zero (bound_ctrl), which spares the copy of the old
+// value that a keep-own-value shift needs.  Every lane of the wave must be active.
+__device__ __forceinline__ int lane_from_lower(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int lane_from_upper(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 
 template <bool FromLower>
 __device__ __forceinline__ double lane_shift(double v) {
