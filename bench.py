@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-64 section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serve-mix section")
     ap.add_argument("--no-wall", action="store_true", help="skip the burgers-wall-399 section")
+    ap.add_argument("--gn-only", action="store_true",
+                    help="burgers-4096: only the timed GN steps and the isolated block products (no reuse, "
+                         "adaptive or SingleView runs), so that a profile holds the k = ell sweeps alone")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB with a plain elementwise kernel "
                          "(reference dispatch for the HBM byte counters)")
@@ -272,8 +275,10 @@ def serve_section():
             "p99_ratio": seq["p99_latency_s"] / served["p99_latency_s"]}
 
 
-def cpu_baseline(cfg, ell, rtol):
-    """The oracle as it stands, one GN iteration of the same workload."""
+def cpu_baseline(cfg, ell, rtol, runs=3):
+    """The oracle as it stands: one GN iteration of the same workload with BLAS
+    threads on every core of the process's affinity, and four Hessian columns on
+    one thread; each the median of `runs` timings."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -281,24 +286,34 @@ def cpu_baseline(cfg, ell, rtol):
     from oracle.problem import burgers_problem
     from paper_2401_15758_amd import inputs
     cores = len(os.sched_getaffinity(0))
+    rates, secs = [], []
     with threadpool_limits(limits=cores):
         orc = burgers_problem(cfg, inputs.draws(cfg, seed=0))
         Om = inputs.omega(cfg["n"], ell, seed=1000)
-        t0 = time.perf_counter()
-        _, _, _, info = ogn.gn_step(orc, np.zeros(cfg["n"]), method="nystrom", Omega=Om, rtol=rtol)
-        dt = time.perf_counter() - t0
-    hv = ell + info["pcg"]["iters"]
-    # one thread: four Hessian columns around the background trajectory
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            _, _, _, info = ogn.gn_step(orc, np.zeros(cfg["n"]), method="nystrom", Omega=Om, rtol=rtol)
+            dt = time.perf_counter() - t0
+            secs.append(dt)
+            rates.append((ell + info["pcg"]["iters"]) / dt)
+    rates1, secs1 = [], []
     with threadpool_limits(limits=1):
         tr = orc.fwd(orc.xb)
-        t0 = time.perf_counter()
-        orc.hessian(tr, Om[:, :4])
-        dt1 = time.perf_counter() - t0
-    return {"value": hv / dt, "unit": "Hv/s", "cores": cores, "kind": "oracle",
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            orc.hessian(tr, Om[:, :4])
+            dt1 = time.perf_counter() - t0
+            secs1.append(dt1)
+            rates1.append(4 / dt1)
+    return {"value": float(np.median(rates)), "unit": "Hv/s", "cores": cores, "kind": "oracle",
+            "runs": [float(r) for r in rates],
             "sample": f"one GN iteration of burgers-4096 ({ell}-column Nystrom sketch + "
-                      f"{info['pcg']['iters']} PCG products to rtol {rtol:g}), FP64 numpy, {dt:.1f} s",
-            "one_thread": {"value": 4 / dt1, "unit": "Hv/s", "cores": 1,
-                           "sample": f"4 Hessian columns of burgers-4096, {dt1:.1f} s"}}
+                      f"{info['pcg']['iters']} PCG products to rtol {rtol:g}), FP64 numpy, median of {runs} "
+                      f"runs of {min(secs):.1f}-{max(secs):.1f} s",
+            "one_thread": {"value": float(np.median(rates1)), "unit": "Hv/s", "cores": 1,
+                           "runs": [float(r) for r in rates1],
+                           "sample": f"4 Hessian columns of burgers-4096, median of {runs} runs of "
+                                     f"{min(secs1):.1f}-{max(secs1):.1f} s"}}
 
 
 def main():
@@ -387,36 +402,38 @@ def main():
                 "launches": ks["launches"],
                 "timing": "HIP events on the library stream, one pair around each sweep's launches"}
 
-    # the same assimilation with the sketch-reuse test (kappa_re < 10 keeps the
-    # resident preconditioner, Sec. 3.2): fewer products per GN step
-    state.reset()
-    torch.cuda.synchronize()
-    tr0 = time.perf_counter()
-    reuse_infos = [prob.gn_step(state, sketch=sk, ell=ell, seed=1000 + it, sketch_dtype=skd, rtol=rtol, reuse_eps=10.0)
-                   for it in range(args.gn_iters)]
-    torch.cuda.synchronize()
-    reuse_ms = 1e3 * (time.perf_counter() - tr0) / args.gn_iters
-
-    # SketchPrecA: adaptive RandSVD (Alg. 4; 32 columns, 16 more while kappa_sk >
-    # 1.01, at most 128) with the kappa_re < 10 reuse test, as in the paper's
-    # adaptive runs; one warm-up assimilation, then one timed
-    def adaptive_run():
+    reuse_ms, reuse_infos, adaptive = None, [], None
+    if not args.gn_only:
+        # the same assimilation with the sketch-reuse test (kappa_re < 10 keeps the
+        # resident preconditioner, Sec. 3.2): fewer products per GN step
         state.reset()
-        return [prob.gn_step(state, sketch=rp4d.RANDSVD_ADAPTIVE, ell=32, ell_hat=16, ell_max=128, eps_sk=1.01,
-                             seed=2000 + it, rtol=rtol, reuse_eps=10.0) for it in range(args.gn_iters)]
-    adaptive_run()
-    torch.cuda.synchronize()
-    prob.reset_counters()
-    ta0 = time.perf_counter()
-    ad_infos = adaptive_run()
-    torch.cuda.synchronize()
-    ad_ms = 1e3 * (time.perf_counter() - ta0) / args.gn_iters
-    ad_cnt = prob.counters()
-    adaptive = {"method": "adaptive RandSVD (Alg. 4) + reuse test", "ell0": 32, "ell_hat": 16, "ell_max": 128,
-                "eps_sk": 1.01, "reuse_eps": 10.0, "gn_step_ms": ad_ms,
-                "sketch_ell": [i["sketch_ell"] for i in ad_infos], "kappa_sk": [i["kappa_sk"] for i in ad_infos],
-                "reused": [i["reused"] for i in ad_infos], "pcg_iters": [i["pcg_iters"] for i in ad_infos],
-                "offline_tlm": ad_cnt["tlm_offline"], "online_tlm": ad_cnt["tlm_online"]}
+        torch.cuda.synchronize()
+        tr0 = time.perf_counter()
+        reuse_infos = [prob.gn_step(state, sketch=sk, ell=ell, seed=1000 + it, sketch_dtype=skd, rtol=rtol,
+                                    reuse_eps=10.0) for it in range(args.gn_iters)]
+        torch.cuda.synchronize()
+        reuse_ms = 1e3 * (time.perf_counter() - tr0) / args.gn_iters
+
+        # SketchPrecA: adaptive RandSVD (Alg. 4; 32 columns, 16 more while kappa_sk >
+        # 1.01, at most 128) with the kappa_re < 10 reuse test, as in the paper's
+        # adaptive runs; one warm-up assimilation, then one timed
+        def adaptive_run():
+            state.reset()
+            return [prob.gn_step(state, sketch=rp4d.RANDSVD_ADAPTIVE, ell=32, ell_hat=16, ell_max=128, eps_sk=1.01,
+                                 seed=2000 + it, rtol=rtol, reuse_eps=10.0) for it in range(args.gn_iters)]
+        adaptive_run()
+        torch.cuda.synchronize()
+        prob.reset_counters()
+        ta0 = time.perf_counter()
+        ad_infos = adaptive_run()
+        torch.cuda.synchronize()
+        ad_ms = 1e3 * (time.perf_counter() - ta0) / args.gn_iters
+        ad_cnt = prob.counters()
+        adaptive = {"method": "adaptive RandSVD (Alg. 4) + reuse test", "ell0": 32, "ell_hat": 16, "ell_max": 128,
+                    "eps_sk": 1.01, "reuse_eps": 10.0, "gn_step_ms": ad_ms,
+                    "sketch_ell": [i["sketch_ell"] for i in ad_infos], "kappa_sk": [i["kappa_sk"] for i in ad_infos],
+                    "reused": [i["reused"] for i in ad_infos], "pcg_iters": [i["pcg_iters"] for i in ad_infos],
+                    "offline_tlm": ad_cnt["tlm_offline"], "online_tlm": ad_cnt["tlm_online"]}
 
     # isolated block Hessian product, k = 64, FP64 (sketch shape)
     traj = prob.traj()
@@ -449,42 +466,44 @@ def main():
     torch.cuda.synchronize()
     hv1_ms = e0.elapsed_time(e1) / reps1
 
-    # SketchPrec with SingleView (Alg. 3): l1 = ell TLM columns and l2 = 2 l1 + 1
-    # ADJ columns (the paper's pairing), the ADJ block on a second stream beside
-    # the TLM block or both on one stream; RandSVD / Nystrom builds of the same
-    # l for comparison.  The l2-column sweeps have tilings of their own (tuned
-    # on the device unless cached).
-    l2 = 2 * ell + 1
-    autotune.tune_or_load(prob, traj, cfg["nsteps"], l2, rp4d.F64, budget_s=args.tune_budget, cache_path=cache_path)
+    singleview = None
+    if not args.gn_only:
+        # SketchPrec with SingleView (Alg. 3): l1 = ell TLM columns and l2 = 2 l1 + 1
+        # ADJ columns (the paper's pairing), the ADJ block on a second stream beside
+        # the TLM block or both on one stream; RandSVD / Nystrom builds of the same
+        # l for comparison.  The l2-column sweeps have tilings of their own (tuned
+        # on the device unless cached).
+        l2 = 2 * ell + 1
+        autotune.tune_or_load(prob, traj, cfg["nsteps"], l2, rp4d.F64, budget_s=args.tune_budget, cache_path=cache_path)
 
-    def build_ms(fn, reps=5):
-        fn()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        for _ in range(reps):
+        def build_ms(fn, reps=5):
             fn()
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - tb) / reps
+
+        sv_two = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5))
+        sv_one = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5, serial=True))
+        rs_build = build_ms(lambda: prob.build_precond(traj, rp4d.RANDSVD, ell, seed=5))
+        ny_build = build_ms(lambda: prob.build_precond(traj, rp4d.NYSTROM, ell, seed=5))
+
+        def sv_run():
+            state.reset()
+            return [prob.gn_step(state, sketch=rp4d.SINGLEVIEW, ell=ell, ell2=l2, seed=3000 + it, rtol=rtol)
+                    for it in range(args.gn_iters)]
+        sv_run()
         torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - tb) / reps
-
-    sv_two = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5))
-    sv_one = build_ms(lambda: prob.build_precond_singleview(traj, ell, l2, seed=5, serial=True))
-    rs_build = build_ms(lambda: prob.build_precond(traj, rp4d.RANDSVD, ell, seed=5))
-    ny_build = build_ms(lambda: prob.build_precond(traj, rp4d.NYSTROM, ell, seed=5))
-
-    def sv_run():
-        state.reset()
-        return [prob.gn_step(state, sketch=rp4d.SINGLEVIEW, ell=ell, ell2=l2, seed=3000 + it, rtol=rtol)
-                for it in range(args.gn_iters)]
-    sv_run()
-    torch.cuda.synchronize()
-    tv0 = time.perf_counter()
-    sv_infos = sv_run()
-    torch.cuda.synchronize()
-    singleview = {"method": "SingleView (Alg. 3)", "l1": ell, "l2": l2,
-                  "build_ms_two_streams": sv_two, "build_ms_one_stream": sv_one,
-                  "randsvd_build_ms": rs_build, "nystrom_build_ms": ny_build,
-                  "gn_step_ms": 1e3 * (time.perf_counter() - tv0) / args.gn_iters,
-                  "pcg_iters": [i["pcg_iters"] for i in sv_infos]}
+        tv0 = time.perf_counter()
+        sv_infos = sv_run()
+        torch.cuda.synchronize()
+        singleview = {"method": "SingleView (Alg. 3)", "l1": ell, "l2": l2,
+                      "build_ms_two_streams": sv_two, "build_ms_one_stream": sv_one,
+                      "randsvd_build_ms": rs_build, "nystrom_build_ms": ny_build,
+                      "gn_step_ms": 1e3 * (time.perf_counter() - tv0) / args.gn_iters,
+                      "pcg_iters": [i["pcg_iters"] for i in sv_infos]}
 
     # achievable HBM bandwidth: a plain 1 GiB device copy (reads and writes 1 GiB)
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
