@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-64 section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serve-mix section")
     ap.add_argument("--no-wall", action="store_true", help="skip the burgers-wall-399 section")
+    ap.add_argument("--only", choices=["bve", "batch", "serve", "wall"],
+                    help="run this section alone and print its record (for profiling; no headline line)")
     ap.add_argument("--gn-only", action="store_true",
                     help="burgers-4096: only the timed GN steps and the isolated block products (no reuse, "
                          "adaptive or SingleView runs), so that a profile holds the k = ell sweeps alone")
@@ -86,10 +88,11 @@ def measured_traffic(kname, tiling, cfg):
 
 
 def bve_section(rp4d, inputs, torch, np):
-    """bve-256: the 2-D workload.  One FP64 block Hessian product with k = 100
-    (timed per kernel class: the Fourier-basis MFMA GEMMs are the dominant
-    kernel) and one Gauss-Newton iteration (100-column Nystrom sketch, PCG to
-    1e-6) from the background."""
+    """bve-256: the 2-D workload.  One FP64 block Hessian product with k = 100,
+    timed per kernel class (the column passes of the spectral solves and the
+    fused row passes of the RK stages), one k = 1 product (the PCG's) and one
+    Gauss-Newton iteration (100-column Nystrom sketch, PCG to 1e-6) from the
+    background."""
     cfg = dict(inputs.CFG_BVE)
     ell = cfg["ell"]
     ctx = rp4d.Context(0)
@@ -110,7 +113,7 @@ def bve_section(rp4d, inputs, torch, np):
     p.hessian_block(tr, V, HV)
     torch.cuda.synchronize()
     hb = time.perf_counter() - t0
-    g, sten = ctx.kernel_stats(rp4d.K_GEMM), ctx.kernel_stats(rp4d.K_STENCIL)
+    g, sten = ctx.kernel_stats(rp4d.K_SPECTRAL), ctx.kernel_stats(rp4d.K_STENCIL)
     ctx.set_timing(False)
     # single-vector product (the PCG's), median of 5
     v1 = V[:, :1].contiguous()
@@ -124,11 +127,14 @@ def bve_section(rp4d, inputs, torch, np):
         torch.cuda.synchronize()
         t1s.append(time.perf_counter() - t0)
     hk1 = float(np.median(t1s))
-    # spectral solves (three FFT launches each) of the k = 100 product: their
-    # algorithmic traffic is the k fields in and out, 2 k n 8 bytes per solve
+    # column passes of the k = 100 product's spectral solves (one launch per RK
+    # stage: the column DFTs, the diagonal and the inverse column DFTs of k/2
+    # complex pairs in place): algorithmic traffic the k fields' spectra in and
+    # out, 2 k n 8 bytes per launch
     solve_s = g["total_ms"] * 1e-3 / max(1, g["launches"])
     fft_tf = g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12
     solve_gbs = 2.0 * ell * cfg["n"] * 8 / solve_s / 1e9
+    row_tf = sten["alg_flops"] / (sten["total_ms"] * 1e-3) / 1e12 if sten["total_ms"] > 0 else 0.0
     st = p.gn_state()
     p.reset_counters()
     torch.cuda.synchronize()
@@ -142,12 +148,16 @@ def bve_section(rp4d, inputs, torch, np):
             "hessian_block_k100_ms": 1e3 * hb, "hessian_block_hv_per_s": ell / hb,
             "hessian_k1_ms": 1e3 * hk1, "hessian_k1_hv_per_s": 1.0 / hk1,
             "roofline": {"bound": "hbm",
-                         "kernel": "spectral solve: fft_rows_fwd + fft_cols + fft_rows_inv (FP64, k=100)",
+                         "kernel": "fft_cols<double, 16>: column pass of the stage solves (FP64, k=100)",
                          "achieved": solve_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": solve_gbs / PEAK_HBM_GBS, "traffic": None,
                          "fft_equivalent_tflops": fft_tf,
-                         "avg_solve_us": 1e6 * solve_s, "solves": g["launches"]},
-            "stencil_ms": sten["total_ms"], "spectral_ms": g["total_ms"]}
+                         "avg_launch_us": 1e6 * solve_s, "launches": g["launches"]},
+            "row_pass": {"kernel": "bve_tlm_rows / bve_adj_rows (FP64, k=100)", "total_ms": sten["total_ms"],
+                         "launches": sten["launches"],
+                         "avg_launch_us": 1e3 * sten["total_ms"] / max(1, sten["launches"]),
+                         "tflops_stencil_plus_fft_equivalent": row_tf},
+            "row_pass_ms": sten["total_ms"], "column_pass_ms": g["total_ms"]}
 
 
 def wall_section(rp4d, inputs, torch, np, max_gn=8):
@@ -330,6 +340,12 @@ def main():
     from paper_2401_15758_amd import autotune, inputs, rp4d
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only:
+        sec = {"bve": lambda: bve_section(rp4d, inputs, torch, np),
+               "batch": lambda: batch_section(rp4d, inputs, torch, np),
+               "serve": serve_section, "wall": lambda: wall_section(rp4d, inputs, torch, np)}[args.only]
+        print(json.dumps({args.only: sec()}), flush=True)
+        return
     cfg = dict(inputs.CFG_LARGE)
     ell, rtol = cfg["ell"], 1e-6
     sk = rp4d.NYSTROM if args.sketch == "nystrom" else rp4d.RANDSVD

@@ -440,15 +440,18 @@ int rp4d_gn_state_reset(rp4d_gn_state* s);
  * Classes: RP4D_K_TLM, RP4D_K_ADJ (block sweeps, k > 1), RP4D_K_FWD, RP4D_K_BHALF,
  * RP4D_K_TLM1, RP4D_K_ADJ1 (single-vector sweeps, k = 1) and RP4D_K_EIG (the
  * small symmetric eigensolves of the sketch post-processing; flops reported 0),
- * and for the 2-D model RP4D_K_GEMM (the dense Fourier-basis products of the
- * spectral inverse Laplacian and prior, 2MNK flops each) and RP4D_K_STENCIL
- * (the Arakawa / Laplacian stage kernels).
+ * and for the 2-D model RP4D_K_SPECTRAL (= RP4D_K_GEMM, its earlier name: the
+ * column passes of the TLM/ADJ stages' spectral solves and the whole FFT solves
+ * of the prior root and the FWD) and RP4D_K_STENCIL (the fused row passes of
+ * the TLM/ADJ stages -- row FFT halves, Arakawa / Laplacian stencils, RK update
+ * or adjoint combine -- and the FWD stage kernels); 2-D FFT work is counted as
+ * FFT-equivalent flops, 5 N log2 N per complex transform of N points.
  * rp4d_ctx_kernel_stats synchronises the stream and returns the number of
  * launches, their summed duration (ms) and the algorithmic flops they performed
  * (owned grid points only; FP64 or FP32 as launched). */
 enum {
     RP4D_K_TLM = 0, RP4D_K_ADJ = 1, RP4D_K_FWD = 2, RP4D_K_BHALF = 3,
-    RP4D_K_TLM1 = 4, RP4D_K_ADJ1 = 5, RP4D_K_EIG = 6, RP4D_K_GEMM = 7, RP4D_K_STENCIL = 8,
+    RP4D_K_TLM1 = 4, RP4D_K_ADJ1 = 5, RP4D_K_EIG = 6, RP4D_K_GEMM = 7, RP4D_K_SPECTRAL = 7, RP4D_K_STENCIL = 8,
     RP4D_K_COUNT = 9
 };
 int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);

@@ -873,11 +873,14 @@ void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) 
     const int stride = p->d.obs_stride, nox = (nx + stride - 1) / stride;
     const T cn[3] = {static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};
     const Spec<T> sp = spec_of<T>(p);
-    // FFT-equivalent flops of one solve of k fields, and the stencil work of a stage
-    const double fl_solve = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(n)) * k;
+    // FFT-equivalent flops (5 N log2 N per complex 2-D transform, k/2 pairs, a
+    // forward and an inverse transform per solve) split into the column passes'
+    // and the row passes' halves, and the stencil work of a stage
+    const double fl_col = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(ny)) * k;
+    const double fl_row = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(nx)) * k;
     const double fl_sten = (2 * FL_ARAKAWA + FL_LAP + 6.0) * static_cast<double>(fk);
     {
-        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_col + 0.5 * fl_row);
         launch_fft_rows_fwd<T>(dz, k, nx, ny, zc, sp.Wx, st);
         launch_fft_cols<T>(zc, k, nx, ny, sp.Dlap, sp.Wy, st);
     }
@@ -902,11 +905,11 @@ void tlm_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, T* dz, T* Z, T* ws) 
             a.inv12d2 = inv12d2;
             a.nu_d2 = nu_d2;
             {
-                KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+                KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten + (last ? 0.5 : 1.0) * fl_row);
                 launch_tlm_rows<T>(a, nx, st);
             }
             if (!last) {
-                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_col);
                 launch_fft_cols<T>(zn, k, nx, ny, sp.Dlap, sp.Wy, st);
                 std::swap(zc, zn);
             }
@@ -943,7 +946,10 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
     // mu of the next (lower) stage after the combine of stage i: (h/3, h), (h/3, h/2), (h/6, h/2)
     const T cl[4] = {T(0), static_cast<T>(h / 6.0), static_cast<T>(h / 3.0), static_cast<T>(h / 3.0)};
     const T ct[4] = {T(0), static_cast<T>(0.5 * h), static_cast<T>(0.5 * h), static_cast<T>(h)};
-    const double fl_solve = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(n)) * k;
+    // FFT-equivalent flops of the column passes and of the row passes' halves
+    // (as in tlm_sweep), and the stencil work of a stage
+    const double fl_col = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(ny)) * k;
+    const double fl_row = 5.0 * static_cast<double>(n) * std::log2(static_cast<double>(nx)) * k;
     const double fl_sten = (2 * FL_ARAKAWA + FL_LAP + 2.0) * static_cast<double>(fk);
     auto obs_it = [&](int s) {  // observation index of state s, or -1
         return (s % p->d.obs_every == 0 && s / p->d.obs_every <= p->n_t && s >= 1) ? s / p->d.obs_every - 1 : -1;
@@ -976,10 +982,10 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
         a.r_out = rc;
         a.znext = zc;
         {
-            KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+            KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten + 0.5 * fl_row);
             launch_adj_rows<T>(a, nx, st);
         }
-        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+        KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_col);
         launch_fft_cols<T>(zc, k, nx, ny, sp.Dlap, sp.Wy, st);
     }
     for (int s = p->s_last; s >= 1; --s) {
@@ -1006,11 +1012,13 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
             a.r_out = rn;
             a.znext = a.s >= 0 ? zn : nullptr;
             {
-                KernelTimer kt(p->ctx, RP4D_K_STENCIL, fl_sten);
+                // the combine: theta 1, accumulator 1, next mu 3 per point and field
+                KernelTimer kt(p->ctx, RP4D_K_STENCIL,
+                               (a.s >= 0 ? fl_sten + fl_row : 0.5 * fl_row) + 5.0 * static_cast<double>(fk));
                 launch_adj_rows<T>(a, nx, st);
             }
             if (a.s >= 0) {
-                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_solve);
+                KernelTimer kt(p->ctx, RP4D_K_GEMM, fl_col);
                 launch_fft_cols<T>(zn, k, nx, ny, sp.Dlap, sp.Wy, st);
                 std::swap(zc, zn);
                 std::swap(rc, rn);

@@ -24,6 +24,7 @@ F64, F32 = 0, 1
 NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE, NYSTROM_ADAPTIVE = 0, 1, 2, 3, 4, 5, 6
 BURGERS1D, BVE2D, BURGERS1D_WALL = 0, 1, 2
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
+K_SPECTRAL = K_GEMM
 MODE_BOTH, MODE_TLM, MODE_ADJ, MODE_FWD = 0, 1, 2, 3
 XCH_LDS, XCH_WAVE = 1, 2
 SOLVE_PCG, SOLVE_SKETCH = 0, 1
