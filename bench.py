@@ -61,19 +61,24 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "burgers_sweep_k64_traffic.json")
 # the sources that define the periodic sweep kernels (hashed together, in this order)
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2401_15758_amd", "csrc", f)
                  for f in ("burgers_sweep.hip", "sweep_common.hpp")]
+FFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bve256_k100_traffic.json")
+# the sources that define the 2-D column pass (hashed together, in this order)
+FFT_SOURCES = [os.path.join(ROOT, "paper_2401_15758_amd", "csrc", f) for f in ("fft2d.hip", "fft_line.hpp")]
 
 
-def measured_traffic(kname, tiling, cfg):
-    """HBM bytes per launch of the dominant sweep kernel, from the counter runs
-    recorded next to the profiles (FETCH_SIZE + WRITE_SIZE, scaled by the same
-    counters on a plain copy).  None unless the record is for this kernel source,
-    kernel instantiation, tiling and workload."""
+def measured_traffic(kname, tiling, cfg, sources=None, path=None):
+    """HBM bytes per launch of a kernel, from the counter runs recorded next to
+    the profiles (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
+    copy).  None unless the record is for this kernel source, kernel
+    instantiation, tiling and workload."""
     import hashlib
+    sources = SWEEP_SOURCES if sources is None else sources
+    path = (TRAFFIC_FILE if sources is SWEEP_SOURCES else FFT_TRAFFIC_FILE) if path is None else path
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
         h = hashlib.sha256()
-        for src in SWEEP_SOURCES:
+        for src in sources:
             with open(src, "rb") as f:
                 h.update(f.read())
         sha = h.hexdigest()
@@ -87,7 +92,7 @@ def measured_traffic(kname, tiling, cfg):
     return None
 
 
-def bve_section(rp4d, inputs, torch, np):
+def bve_section(rp4d, inputs, torch, np, gn=True):
     """bve-256: the 2-D workload.  One FP64 block Hessian product with k = 100,
     timed per kernel class (the column passes of the spectral solves and the
     fused row passes of the RK stages), one k = 1 product (the PCG's) and one
@@ -135,22 +140,24 @@ def bve_section(rp4d, inputs, torch, np):
     fft_tf = g["alg_flops"] / (g["total_ms"] * 1e-3) / 1e12
     solve_gbs = 2.0 * ell * cfg["n"] * 8 / solve_s / 1e9
     row_tf = sten["alg_flops"] / (sten["total_ms"] * 1e-3) / 1e12 if sten["total_ms"] > 0 else 0.0
-    st = p.gn_state()
-    p.reset_counters()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = p.gn_step(st, sketch=rp4d.NYSTROM, ell=ell, seed=1000, sketch_dtype=rp4d.F64, rtol=1e-6)
-    torch.cuda.synchronize()
-    gn = time.perf_counter() - t0
-    cnt = p.counters()
-    return {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "k": ell,
-            "gn_step_s": gn, "pcg_iters": info["pcg_iters"], "hv_per_s": cnt["hv_columns"] / gn,
+    gn_rec = {}
+    if gn:
+        st = p.gn_state()
+        p.reset_counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = p.gn_step(st, sketch=rp4d.NYSTROM, ell=ell, seed=1000, sketch_dtype=rp4d.F64, rtol=1e-6)
+        torch.cuda.synchronize()
+        gn_s = time.perf_counter() - t0
+        gn_rec = {"gn_step_s": gn_s, "pcg_iters": info["pcg_iters"], "hv_per_s": p.counters()["hv_columns"] / gn_s}
+    return {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "k": ell, **gn_rec,
             "hessian_block_k100_ms": 1e3 * hb, "hessian_block_hv_per_s": ell / hb,
             "hessian_k1_ms": 1e3 * hk1, "hessian_k1_hv_per_s": 1.0 / hk1,
             "roofline": {"bound": "hbm",
                          "kernel": "fft_cols<double, 16>: column pass of the stage solves (FP64, k=100)",
                          "achieved": solve_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": solve_gbs / PEAK_HBM_GBS, "traffic": None,
+                         "frac": solve_gbs / PEAK_HBM_GBS,
+                         "traffic": measured_traffic("fft_cols<double, 16>", {}, cfg, FFT_SOURCES),
                          "fft_equivalent_tflops": fft_tf,
                          "avg_launch_us": 1e6 * solve_s, "launches": g["launches"]},
             "row_pass": {"kernel": "bve_tlm_rows / bve_adj_rows (FP64, k=100)", "total_ms": sten["total_ms"],
@@ -216,8 +223,9 @@ def wall_section(rp4d, inputs, torch, np, max_gn=8):
 def batch_section(rp4d, inputs, torch, np):
     """batch-64: 64 uneven Burgers problems (n in [256, 4096], N in [50, 500]),
     one batched Gauss-Newton iteration each (32-column Nystrom sketch, FP64 PCG
-    to 1e-6), with FP64 and with FP32 sketch sweeps, against the same 64
-    iterations run one problem at a time through the single-problem FP64 path."""
+    to 1e-6), with FP64 and with FP32 sketch sweeps, each with the lock-step
+    PCG eager and graph-replayed, against the same 64 iterations run one
+    problem at a time through the single-problem FP64 path."""
     cfgs = inputs.batch_configs(64, seed=0)
     ctx = rp4d.Context(0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
@@ -236,7 +244,11 @@ def batch_section(rp4d, inputs, torch, np):
     tuned = {name: autotune.apply_cached_batch(b, 32, dt) for name, dt in (("f64", rp4d.F64), ("f32", rp4d.F32))}
     res = {"workload": "batch-64", "problems": len(cfgs), "k": 32,
            "tiling": {name: (ent["sweep"] if ent else "library default") for name, ent in tuned.items()}}
-    for name, skd in (("f64", rp4d.F64), ("f32", rp4d.F32)):
+    # the lock-step PCG eager and with its iteration body replayed as a HIP
+    # graph (captured again whenever a problem converges)
+    for name, skd, graphs in (("f64", rp4d.F64, False), ("f64_graph", rp4d.F64, True),
+                              ("f32", rp4d.F32, False), ("f32_graph", rp4d.F32, True)):
+        ctx.set_graphs(graphs)
         times = []
         for rep in range(3):
             for s in states:
@@ -253,6 +265,7 @@ def batch_section(rp4d, inputs, torch, np):
         res[f"sketch_{name}"] = {"gn_step_ms": 1e3 * t, "hv_per_s": hv / t,
                                  "pcg_iters_max": max(i["pcg_iters"] for i in infos),
                                  "pcg_iters_total": sum(i["pcg_iters"] for i in infos)}
+    ctx.set_graphs(False)
     for s in states:
         s.reset()
     torch.cuda.synchronize()
@@ -326,6 +339,18 @@ def cpu_baseline(cfg, ell, rtol, runs=3):
                                      f"{min(secs1):.1f}-{max(secs1):.1f} s"}}
 
 
+def calib_copy(torch, mib, rec):
+    """One elementwise copy that reads and writes `mib` MiB: the reference
+    dispatch for the HBM byte counters of a profiled run."""
+    if mib <= 0:
+        return
+    src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    rec["calib_copy_mib"] = mib
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -341,10 +366,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only:
-        sec = {"bve": lambda: bve_section(rp4d, inputs, torch, np),
+        sec = {"bve": lambda: bve_section(rp4d, inputs, torch, np, gn=args.gn_iters > 0),
                "batch": lambda: batch_section(rp4d, inputs, torch, np),
                "serve": serve_section, "wall": lambda: wall_section(rp4d, inputs, torch, np)}[args.only]
-        print(json.dumps({args.only: sec()}), flush=True)
+        rec = {args.only: sec()}
+        calib_copy(torch, args.calib_copy_mib, rec)
+        print(json.dumps(rec), flush=True)
         return
     cfg = dict(inputs.CFG_LARGE)
     ell, rtol = cfg["ell"], 1e-6
@@ -589,12 +616,7 @@ def main():
     if not args.no_cpu_baseline:
         note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, ell, rtol)
-    if args.calib_copy_mib > 0:
-        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)      # reads and writes calib_copy_mib MiB once
-        torch.cuda.synchronize()
-        out["calib_copy_mib"] = args.calib_copy_mib
+    calib_copy(torch, args.calib_copy_mib, out)
     print(json.dumps(out), flush=True)
 
 

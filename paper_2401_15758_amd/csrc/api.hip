@@ -2402,13 +2402,18 @@ void build_singleview_adaptive(rp4d_problem* p, const rp4d_traj* tr, const rp4d_
 // (recorded on a library-owned stream; nothing runs during capture).
 struct GraphExec {
     hipGraphExec_t ex = nullptr;
-    ~GraphExec() {
+    GraphExec() = default;
+    GraphExec(const GraphExec&) = delete;
+    GraphExec& operator=(const GraphExec&) = delete;
+    void reset() {
         if (ex) (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
     }
+    ~GraphExec() { reset(); }
 };
 
 template <typename F>
-void capture(rp4d_ctx* c, F&& f, GraphExec& out) {
+void capture(rp4d_ctx* c, F&& f, GraphExec& out, bool instantiate = true) {
     if (!c->cap_stream) RP4D_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t orig = c->stream;
     RP4D_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -2428,6 +2433,10 @@ void capture(rp4d_ctx* c, F&& f, GraphExec& out) {
     c->stream = orig;
     c->capturing = false;
     RP4D_HIP(e);
+    if (!instantiate) {
+        (void)hipGraphDestroy(g);
+        return;
+    }
     const hipError_t e2 = hipGraphInstantiate(&out.ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     RP4D_HIP(e2);
@@ -3064,6 +3073,14 @@ struct rp4d_batch {
     // [mode-1][dtype] overrides (ppt, kc, threads, steps, xch; <= 0: default)
     rp4d::Tiling bt[2][2] = {{{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}, {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}};
     rp4d::Tiling bt_fwd = {0, 0, 0, 0, 0, 0};  // forward-sweep overrides
+    // Staging for graph capture of the lock-step PCG body (gmode != 0): instead
+    // of the ring, tables go to offsets of a device arena.  gmode 1 sizes them
+    // (the graph of that pass is discarded); gmode 2 records them in arena_host
+    // at addresses in arena_dev, and they are copied there after the capture.
+    int gmode = 0;
+    std::vector<char> arena_host;
+    rp4d::DevBuf arena_dev;
+    size_t arena_off = 0;
     ~rp4d_batch() {
         if (host) (void)hipHostFree(host);
     }
@@ -3084,9 +3101,36 @@ inline void ring_copy(rp4d_batch* b, size_t at, const void* src, size_t bytes) {
     RP4D_HIP(hipMemcpyAsync(b->dev.as<char>() + at, h, bytes, hipMemcpyHostToDevice, b->ctx->stream));
 }
 
+// Arena staging (graph capture): the tables of the body at consecutive
+// offsets.  The sizing pass only advances the offset; the recording pass
+// copies each table into arena_host at its offset and returns its address in
+// arena_dev, which the sizing pass made large enough (tables may hold the
+// addresses of tables staged before them, so they are built against the final
+// arena).
+inline char* arena_put(rp4d_batch* b, const void* src, size_t bytes, size_t rounded) {
+    const size_t at = b->arena_off;
+    b->arena_off += rounded;
+    if (b->gmode == 2) {
+        RP4D_REQUIRE(b->arena_off <= b->arena_dev.bytes, RP4D_ESTATE,
+                     "batched PCG graph: the body staged more tables than on its sizing pass");
+        if (b->arena_host.size() < b->arena_off) b->arena_host.resize(b->arena_off);
+        if (bytes) std::memcpy(b->arena_host.data() + at, src, bytes);
+    }
+    return b->arena_dev.as<char>() + at;  // not valid on the sizing pass (that graph is discarded)
+}
+
 template <typename... V>
 std::tuple<typename V::value_type*...> stage(rp4d_batch* b, const V&... v) {
     const size_t sizes[] = {ring_round(v.size() * sizeof(typename V::value_type))...};
+    if (b->gmode != 0) {
+        int q = 0;
+        auto put = [&](const auto& vec) {
+            typedef typename std::decay_t<decltype(vec)>::value_type E;
+            char* d = arena_put(b, vec.data(), vec.size() * sizeof(E), sizes[q++]);
+            return vec.empty() ? nullptr : reinterpret_cast<E*>(d);
+        };
+        return std::tuple<typename V::value_type*...>{put(v)...};
+    }
     size_t total = 0;
     for (size_t x : sizes) total += x;
     const RingPlace r = ring_place_group(b->off, b->cap, total);
@@ -3476,6 +3520,32 @@ void batch_axpby(rp4d_batch* b, std::vector<BAxpby> ad) {
     launch_baxpby(d_ad, d_it, static_cast<int>(it.size()), b->ctx->stream);
 }
 
+// Capture a batched body that stages descriptor tables: a first capture sizes
+// its tables (its graph is discarded unlaunched), the second records them
+// against the device arena, and one copy moves them there before any replay.
+// The stream must be idle (no earlier graph still reading the arena).
+template <typename F>
+void capture_batch(rp4d_batch* b, F&& f, GraphExec& out) {
+    struct Mode {
+        rp4d_batch* b;
+        ~Mode() { b->gmode = 0; }
+    } mode{b};
+    b->arena_off = 0;
+    b->gmode = 1;
+    {
+        GraphExec sizing;
+        capture(b->ctx, f, sizing, false);
+    }
+    b->arena_dev.ensure(std::max<size_t>(b->arena_off, 256));
+    b->arena_host.assign(b->arena_off, 0);
+    b->arena_off = 0;
+    b->gmode = 2;
+    capture(b->ctx, f, out, true);
+    RP4D_HIP(hipMemcpyAsync(b->arena_dev.p, b->arena_host.data(), b->arena_off, hipMemcpyHostToDevice,
+                            b->ctx->stream));
+    RP4D_HIP(hipStreamSynchronize(b->ctx->stream));
+}
+
 // Batched lockstep PCG (FP64) on (I + H_i) x_i = b_i; returns per-problem iterations.
 std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs,
                            const std::vector<const rp4d_precond*>& pcs, const std::vector<const double*>& rhs,
@@ -3528,42 +3598,68 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
         maxit = 1;
         for (int i = 0; i < np; ++i) maxit = std::max(maxit, b->probs[sel[i]]->n);
     }
-    for (int it = 0; it < maxit && !act.empty(); ++it) {
+    // One iteration for the active problems A: q = (I+H)p, alpha, x, r, |r|^2,
+    // then speculatively z = P r, r.z and the next p (unused by problems whose
+    // |r| meets the tolerance).  The stream is read at each launch, so the same
+    // body can be captured into a graph.
+    auto body = [&](const std::vector<int>& A) {
+        hipStream_t s = b->ctx->stream;
         std::vector<int> asel;
         std::vector<const rp4d_traj*> atr;
-        std::vector<const double*> ap;
-        std::vector<double*> aq;
+        std::vector<const double*> ap, ar;
+        std::vector<double*> aq, az;
         std::vector<const rp4d_precond*> apc;
         std::vector<BPcg> apd;
         std::vector<size_t> cnt;
-        for (int i : act) {
+        for (int i : A) {
             asel.push_back(sel[i]);
             atr.push_back(trajs[i]);
             ap.push_back(pv[i]);
             aq.push_back(q[i]);
+            ar.push_back(r[i]);
+            az.push_back(z[i]);
             apc.push_back(pcs[i]);
             apd.push_back(pd[i]);
             cnt.push_back(b->probs[sel[i]]->n);
         }
         batch_hessian<double>(b, asel, atr, 1, ap, aq, true);
-        std::vector<const double*> caq(aq.begin(), aq.end());
+        std::vector<const double*> caq(aq.begin(), aq.end()), caz(az.begin(), az.end());
         batch_dot(b, asel, ap, caq, SC_PQ);
-        auto items = elem_items(cnt);
-        auto [dpd, dit] = stage(b, apd, items);
-        launch_bpcg_xr(dpd, dit, static_cast<int>(items.size()), st);
-        std::vector<const double*> ar, az;
-        std::vector<double*> azm;
-        for (int i : act) {
-            ar.push_back(r[i]);
-            az.push_back(z[i]);
-            azm.push_back(z[i]);
+        const auto items = elem_items(cnt);
+        {
+            auto [dpd, dit] = stage(b, apd, items);
+            launch_bpcg_xr(dpd, dit, static_cast<int>(items.size()), s);
         }
         batch_dot(b, asel, ar, ar, SC_RR);
+        batch_precond_apply(b, asel, apc, ar, az);
+        batch_dot(b, asel, ar, caz, SC_RZN);
+        auto [dpd, dit] = stage(b, apd, items);
+        launch_bpcg_p(dpd, dit, static_cast<int>(items.size()), static_cast<int>(apd.size()), s);
+    };
+    // With graphs on, iterations after the first (which sizes every workspace
+    // the body touches) replay the body captured for the current active set; a
+    // change of the set captures it again.
+    const bool use_graph = b->ctx->graphs;
+    GraphExec gx;
+    std::vector<int> gact;
+    for (int it = 0; it < maxit && !act.empty(); ++it) {
+        if (use_graph && it >= 1) {
+            if (!gx.ex || gact != act) {
+                gx.reset();
+                std::vector<long long> hv(np);
+                for (int i = 0; i < np; ++i) hv[i] = b->probs[sel[i]]->cnt.hv_columns;
+                capture_batch(b, [&] { body(act); }, gx);
+                for (int i = 0; i < np; ++i) b->probs[sel[i]]->cnt.hv_columns = hv[i];
+                gact = act;
+            }
+            RP4D_HIP(hipGraphLaunch(gx.ex, st));
+            for (int i : act) b->probs[sel[i]]->cnt.hv_columns += 1;
+        } else {
+            body(act);
+        }
         std::vector<double> s2 = batch_read_scal(b);
         std::vector<int> still;
-        std::vector<int> ssel;
-        for (size_t a = 0; a < act.size(); ++a) {
-            const int i = act[a];
+        for (int i : act) {
             iters[i] += 1;
             const double rn = std::sqrt(s2[16 * sel[i] + SC_RR]);
             RP4D_REQUIRE(std::isfinite(rn), RP4D_ENONFINITE, "non-finite PCG residual in batch");
@@ -3572,29 +3668,6 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
             else
                 still.push_back(i);
         }
-        if (still.empty()) break;
-        // z = P r, rz_new = r.z, p = z + beta p for problems still iterating
-        std::vector<int> ssel2;
-        std::vector<const rp4d_precond*> spc;
-        std::vector<const double*> sr;
-        std::vector<double*> sz;
-        std::vector<BPcg> spd;
-        std::vector<size_t> scnt;
-        for (int i : still) {
-            ssel2.push_back(sel[i]);
-            spc.push_back(pcs[i]);
-            sr.push_back(r[i]);
-            sz.push_back(z[i]);
-            spd.push_back(pd[i]);
-            scnt.push_back(b->probs[sel[i]]->n);
-        }
-        batch_precond_apply(b, ssel2, spc, sr, sz);
-        std::vector<const double*> csz(sz.begin(), sz.end());
-        batch_dot(b, ssel2, sr, csz, SC_RZN);
-        auto sitems = elem_items(scnt);
-        auto [d_spd, d_sitems] = stage(b, spd, sitems);
-        launch_bpcg_p(d_spd, d_sitems, static_cast<int>(sitems.size()),
-                      static_cast<int>(spd.size()), st);
         act = still;
     }
     for (int i = 0; i < np; ++i) {

@@ -208,3 +208,34 @@ def test_batched_gn_step_at_the_extremes_matches_oracle():
         assert infos[i]['J'] == pytest.approx(info['J'], rel=1e-12), i
         assert infos[i]['pcg_converged'], i
         assert relerr(to_np(gx), x1) <= 1e-10, i
+
+
+def test_batched_pcg_graph_replay_is_bitwise_eager():
+    """With graphs on, the lock-step PCG replays its iteration body captured
+    for the current set of unconverged problems (captured again whenever a
+    problem drops out; every replay is followed by the eager residual
+    read-back).  Uneven problems converge at different iterations, so several
+    captures happen; every problem's iteration count and solution must equal
+    the all-eager run bit for bit, and stay within 1e-10 of the oracle."""
+    torch = need_gpu()
+    from oracle import gn as ogn
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    ell, seed = 12, 78
+    out = {}
+    for graphs in (False, True):
+        ctx.set_graphs(graphs)
+        states = [p.gn_state() for p in probs]
+        infos = b.gn_step(states, sketch=rp4d.NYSTROM, ell=ell, seed=seed, rtol=1e-12)
+        torch.cuda.synchronize()
+        out[graphs] = ([inf['pcg_iters'] for inf in infos], [s.get()[1].clone() for s in states])
+    ctx.set_graphs(False)
+    iters = out[False][0]
+    assert out[True][0] == iters and min(iters) >= 5 and len(set(iters)) >= 2
+    for i in range(len(probs)):
+        assert torch.equal(out[True][1][i], out[False][1][i]), i
+    for i, o in enumerate(orcs):
+        Om = orng.gaussian_matrix(_omega_seed(seed, 100 + i), o.n, ell)
+        _, _, x1, _ = ogn.gn_step(o, np.zeros(o.n), method='nystrom', Omega=Om, rtol=1e-12)
+        assert relerr(to_np(out[True][1][i]), x1) <= 1e-10, i
