@@ -279,23 +279,33 @@ def batch_section(rp4d, inputs, torch, np):
     return res
 
 
-def serve_section():
-    """serve-mix: a Poisson stream of 24 solves (70 % Burgers, n 512-8192, 100-500
-    steps; 30 % vorticity at 64^2-128^2, 100-200 steps; 3 GN iterations to 1e-6
-    each).  The served path's capacity is measured with every request queued at
-    once; the same stream then arrives at 0.7 x that rate and runs through the
-    served path and through the plain FP64 one-at-a-time path."""
-    from paper_2401_15758_amd import serve
+def serve_section(nreq=100):
+    """serve-mix at reduced 2-D sizes: a Poisson stream of `nreq` solves (70 %
+    Burgers, n 512-8192, 100-500 steps; 30 % vorticity at 64^2-128^2, 100-200
+    steps; 3 GN iterations to 1e-6 each).  The served path's capacity is
+    measured with every request queued at once (FP32 sketch sweeps); the same
+    stream then arrives at 0.7 x that rate and runs through the served path with
+    FP32 sketch sweeps (the mixed-precision form) and with FP64 ones, and
+    through the plain FP64 one-at-a-time path.  The configured 2-D sizes
+    (128^2-512^2, 100-300 steps) take minutes per request in the plain path:
+    that run is `python -m paper_2401_15758_amd.serve`."""
+    from paper_2401_15758_amd import rp4d, serve
     kw = dict(bve_nx=(64, 128), bve_N=(100, 200))
-    cap = serve.summary(serve.serve(serve.make_trace(24, 0.0, seed=7, **kw)))
+    cap = serve.summary(serve.serve(serve.make_trace(nreq, 0.0, seed=7, **kw), sketch_dtype=rp4d.F32))
     rate = 0.7 * cap["solves_per_s"]
-    trace = serve.make_trace(24, rate, seed=7, **kw)
-    served = serve.summary(serve.serve(serve.clone_trace(trace)))
-    seq = serve.summary(serve.serve_sequential(serve.clone_trace(trace)))
-    return {"workload": "serve-mix", "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate": rate,
-            "served": served, "sequential_fp64": seq,
-            "throughput_ratio": served["solves_per_s"] / seq["solves_per_s"],
-            "p99_ratio": seq["p99_latency_s"] / served["p99_latency_s"]}
+    trace = serve.make_trace(nreq, rate, seed=7, **kw)
+    mixed = serve.serve(serve.clone_trace(trace), sketch_dtype=rp4d.F32)
+    f64 = serve.serve(serve.clone_trace(trace), sketch_dtype=rp4d.F64)
+    seq = serve.serve_sequential(serve.clone_trace(trace))
+    sm, sf, ss = serve.summary(mixed), serve.summary(f64), serve.summary(seq)
+    sm["vs_sequential"], sf["vs_sequential"] = serve.compare(mixed, seq), serve.compare(f64, seq)
+    return {"workload": "serve-mix (2-D at 64^2-128^2)", "requests": nreq,
+            "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate": rate,
+            "served_mixed": sm, "served_fp64": sf, "sequential_fp64": ss,
+            "throughput_ratio": sm["solves_per_s"] / ss["solves_per_s"],
+            "p99_ratio": ss["p99_latency_s"] / sm["p99_latency_s"],
+            "throughput_ratio_fp64": sf["solves_per_s"] / ss["solves_per_s"],
+            "p99_ratio_fp64": ss["p99_latency_s"] / sf["p99_latency_s"]}
 
 
 def cpu_baseline(cfg, ell, rtol, runs=3):

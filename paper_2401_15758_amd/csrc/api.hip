@@ -3549,7 +3549,8 @@ void capture_batch(rp4d_batch* b, F&& f, GraphExec& out) {
 // Batched lockstep PCG (FP64) on (I + H_i) x_i = b_i; returns per-problem iterations.
 std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs,
                            const std::vector<const rp4d_precond*>& pcs, const std::vector<const double*>& rhs,
-                           const std::vector<double*>& x, double rtol, int maxit, std::vector<int>& conv) {
+                           const std::vector<double*>& x, double rtol, int maxit, std::vector<int>& conv,
+                           std::vector<double>* relres = nullptr) {
     hipStream_t st = b->ctx->stream;
     const int np = static_cast<int>(sel.size());
     std::vector<double*> r(np), z(np), pv(np), q(np);
@@ -3585,6 +3586,7 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
     std::vector<double> bnorm(np);
     std::vector<int> iters(np, 0);
     conv.assign(np, 0);
+    if (relres) relres->assign(np, 0.0);
     std::vector<int> act;
     for (int i = 0; i < np; ++i) {
         bnorm[i] = std::sqrt(sc[16 * sel[i] + SC_BB]);
@@ -3663,6 +3665,7 @@ std::vector<int> batch_pcg(rp4d_batch* b, const std::vector<int>& sel, const std
             iters[i] += 1;
             const double rn = std::sqrt(s2[16 * sel[i] + SC_RR]);
             RP4D_REQUIRE(std::isfinite(rn), RP4D_ENONFINITE, "non-finite PCG residual in batch");
+            if (relres) (*relres)[i] = rn / bnorm[i];
             if (rn <= rtol * bnorm[i])
                 conv[i] = 1;
             else
@@ -4098,7 +4101,8 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
         // 5. PCG
         std::vector<const double*> rhs(bm.begin(), bm.end());
         std::vector<int> conv;
-        std::vector<int> its = batch_pcg(b, sel, ctr, use, rhs, dv, o->rtol, o->maxit, conv);
+        std::vector<double> relres;
+        std::vector<int> its = batch_pcg(b, sel, ctr, use, rhs, dv, o->rtol, o->maxit, conv, &relres);
         // 6. v += dv, x = x_b + Gamma^{1/2} v
         {
             std::vector<BAxpby> ad;
@@ -4111,6 +4115,7 @@ int rp4d_batch_gn_step(rp4d_batch* b, rp4d_gn_state* const* states, const rp4d_g
             inf[i].pcg_iters = its[i];
             inf[i].sketch_ell = use[i] ? use[i]->ell : 0;
             inf[i].pcg_converged = conv[i];
+            inf[i].pcg_relres = relres[i];
             all_conv = all_conv && conv[i];
             if (infos) infos[i] = inf[i];
         }

@@ -25,6 +25,7 @@ The baseline is the plain path: FP64, one request at a time in arrival order,
 single-problem calls, a new sketch every iteration.
 """
 import math
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -49,6 +50,7 @@ class Request:
     pcg_iters: list = field(default_factory=list)
     reused: int = 0
     J: list = field(default_factory=list)
+    relres: list = field(default_factory=list)   # final PCG relative residual of each GN step
     x: np.ndarray = None    # final state (host copy)
     hbm_peak: int = 0       # peak device bytes the served run's contexts held (library count)
 
@@ -137,11 +139,14 @@ def _setup(rp4d, torch, ctx, req, pid=None):
     return p, st
 
 
-def _finish(torch, ctx, req, st, t0):
+def _finish(torch, ctx, req, st, t0, verbose=False):
     with torch.cuda.stream(ctx.stream):
         _, x = st.get()
         req.x = x.cpu().numpy()
     req.done = time.perf_counter() - t0
+    if verbose:
+        print(f"serve: request {req.rid} ({req.cfg['name']}, {req.cfg['nsteps']} steps) done at {req.done:.1f} s, "
+              f"PCG iterations {req.pcg_iters}", file=sys.stderr, flush=True)
 
 
 def _step_seed(req, it):
@@ -165,7 +170,8 @@ class _Budget:
             self.used -= b
 
 
-def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, sketch_dtype=None, bve_lanes=2):
+def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, sketch_dtype=None, bve_lanes=2,
+          verbose=False):
     """Run `trace` through the served path; returns the requests with their
     timings and final states.  Arrival times are honoured from the start."""
     import torch
@@ -229,9 +235,10 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 r.gn_done += 1
                 r.pcg_iters.append(inf["pcg_iters"])
                 r.J.append(inf["J"])
+                r.relres.append(inf["pcg_relres"])
                 r.reused += inf["reused"]
                 if r.gn_done >= gn_steps:
-                    _finish(torch, ctx, r, st, t0)
+                    _finish(torch, ctx, r, st, t0, verbose)
                     st.close()
                     budget.give(fp)
                 else:
@@ -268,9 +275,13 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 r.gn_done += 1
                 r.pcg_iters.append(inf["pcg_iters"])
                 r.J.append(inf["J"])
+                r.relres.append(inf["pcg_relres"])
                 r.reused += inf["reused"]
                 note_usage()
-            _finish(torch, ctx, r, st, t0)
+                if verbose:
+                    print(f"serve: request {r.rid} GN step {it + 1} at {now():.1f} s, {inf['pcg_iters']} PCG iterations",
+                          file=sys.stderr, flush=True)
+            _finish(torch, ctx, r, st, t0, verbose)
             st.close()
             p.close()
             budget.give(fp)
@@ -296,7 +307,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
     return trace
 
 
-def serve_sequential(trace, gn_steps=3, rtol=1e-6):
+def serve_sequential(trace, gn_steps=3, rtol=1e-6, verbose=False):
     """The plain path: FP64, one request at a time in arrival order, a new
     sketch every iteration, single-problem calls."""
     import torch
@@ -314,7 +325,11 @@ def serve_sequential(trace, gn_steps=3, rtol=1e-6):
             r.gn_done += 1
             r.pcg_iters.append(inf["pcg_iters"])
             r.J.append(inf["J"])
-        _finish(torch, ctx, r, st, t0)
+            r.relres.append(inf["pcg_relres"])
+            if verbose:
+                print(f"serve: request {r.rid} GN step {it + 1} at {time.perf_counter() - t0:.1f} s, "
+                      f"{inf['pcg_iters']} PCG iterations (sequential)", file=sys.stderr, flush=True)
+        _finish(torch, ctx, r, st, t0, verbose)
         st.close()
         p.close()
     return trace
@@ -323,11 +338,22 @@ def serve_sequential(trace, gn_steps=3, rtol=1e-6):
 def summary(trace):
     lat = np.array([r.latency for r in trace])
     span = max(r.done for r in trace) - min(r.arrival for r in trace)
+    last_res = [r.relres[-1] for r in trace if r.relres]
     return {"requests": len(trace), "solves_per_s": len(trace) / span, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "makespan_s": span,
             "pcg_iters_total": int(sum(sum(r.pcg_iters) for r in trace)),
             "reuses": int(sum(r.reused for r in trace)),
+            "final_relres_max": float(max(last_res)) if last_res else None,
             "hbm_peak_bytes": int(max(r.hbm_peak for r in trace))}
+
+
+def compare(a, b):
+    """Per-request agreement of two runs of the same trace: the final cost J
+    after the last GN step (relative difference) and the final PCG residuals."""
+    by = {r.rid: r for r in b}
+    dj = [abs(r.J[-1] - by[r.rid].J[-1]) / abs(by[r.rid].J[-1]) for r in a]
+    return {"J_final_reldiff_max": float(max(dj)), "J_final_reldiff_median": float(np.median(dj)),
+            "relres_final_max": [float(max(r.relres[-1] for r in a)), float(max(r.relres[-1] for r in b))]}
 
 
 def clone_trace(trace):
@@ -344,18 +370,35 @@ def main():
     ap.add_argument("--bve-nx", type=int, nargs=2, default=(128, 512))
     ap.add_argument("--bve-steps", type=int, nargs=2, default=(100, 300))
     ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--sketch", choices=["f32", "f64", "both"], default="both",
+                    help="sketch sweeps of the served path: FP32 (the mixed-precision form), FP64, or both")
     args = ap.parse_args()
+    from . import rp4d
     kw = dict(bve_nx=tuple(args.bve_nx), bve_N=tuple(args.bve_steps))
+    budget = int(args.budget_gib * 2 ** 30)
     rate = args.rate
-    out = {}
+    out = {"requests": args.requests, "bve_nx": list(args.bve_nx), "bve_steps": list(args.bve_steps)}
+
+    def note(msg):
+        print(f"serve: {msg}", file=sys.stderr, flush=True)
     if rate <= 0:
-        cap = serve(make_trace(args.requests, 0.0, seed=args.seed, **kw), budget_bytes=int(args.budget_gib * 2 ** 30))
+        cap = serve(make_trace(args.requests, 0.0, seed=args.seed, **kw), budget_bytes=budget, verbose=True)
         out["capacity_solves_per_s"] = summary(cap)["solves_per_s"]
         rate = 0.7 * out["capacity_solves_per_s"]
+        note(f"capacity {out['capacity_solves_per_s']:.3f} solves/s")
     trace = make_trace(args.requests, rate, seed=args.seed, **kw)
     out["rate"] = rate
-    out["served"] = summary(serve(clone_trace(trace), budget_bytes=int(args.budget_gib * 2 ** 30)))
-    out["sequential_fp64"] = summary(serve_sequential(clone_trace(trace)))
+    runs = {}
+    chosen = {"f32": ("served_mixed",), "f64": ("served_fp64",), "both": ("served_mixed", "served_fp64")}[args.sketch]
+    for name, dt in (("served_mixed", rp4d.F32), ("served_fp64", rp4d.F64)):
+        if name in chosen:
+            runs[name] = serve(clone_trace(trace), budget_bytes=budget, sketch_dtype=dt, verbose=True)
+            out[name] = summary(runs[name])
+            note(f"{name} done")
+    seq = serve_sequential(clone_trace(trace), verbose=True)
+    out["sequential_fp64"] = summary(seq)
+    for name, run in runs.items():
+        out[name]["vs_sequential"] = compare(run, seq)
     print(json.dumps(out))
 
 

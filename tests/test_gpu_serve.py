@@ -13,16 +13,37 @@ pytestmark = pytest.mark.gpu
 SMALL_MIX = dict(burgers_n=(256, 700), burgers_N=(40, 80), bve_nx=(32, 48), bve_N=(20, 40))
 
 
-def test_alone_and_in_mix_bitwise():
+@pytest.mark.parametrize("sketch", ["f64", "f32"])
+def test_alone_and_in_mix_bitwise(sketch):
+    """Served in a mix and alone, every request ends bitwise the same, with FP64
+    sketch sweeps and with FP32 ones (the mixed-precision served form); every
+    GN step's PCG meets the tolerance."""
     need_gpu()
+    from paper_2401_15758_amd import rp4d
+    dt = rp4d.F64 if sketch == "f64" else rp4d.F32
     trace = serve.make_trace(8, rate=40.0, seed=11, frac_burgers=0.65, **SMALL_MIX)
     assert {r.model for r in trace} == {"burgers", "bve"}
-    mixed = serve.serve(serve.clone_trace(trace))
+    mixed = serve.serve(serve.clone_trace(trace), sketch_dtype=dt)
     for r in mixed:
         assert r.gn_done == 3 and len(r.J) == 3 and r.J[-1] < r.J[0]
-        alone = serve.serve([serve.Request(rid=r.rid, cfg=dict(r.cfg), arrival=0.0, seed=r.seed)])[0]
+        assert len(r.relres) == 3 and max(r.relres) <= 1e-6, r.cfg["name"]
+        alone = serve.serve([serve.Request(rid=r.rid, cfg=dict(r.cfg), arrival=0.0, seed=r.seed)], sketch_dtype=dt)[0]
         assert np.array_equal(alone.x, r.x), r.cfg["name"]
         assert alone.pcg_iters == r.pcg_iters and alone.reused == r.reused
+
+
+def test_served_and_sequential_reach_the_same_cost():
+    """The served mixed-precision path and the plain FP64 one-at-a-time path
+    solve each GN step to the same PCG tolerance, so after three GN steps each
+    request's cost J agrees to well within the tolerance's effect."""
+    need_gpu()
+    from paper_2401_15758_amd import rp4d
+    trace = serve.make_trace(8, rate=0.0, seed=13, frac_burgers=0.65, **SMALL_MIX)
+    served = serve.serve(serve.clone_trace(trace), sketch_dtype=rp4d.F32)
+    seq = serve.serve_sequential(serve.clone_trace(trace))
+    cmp = serve.compare(served, seq)
+    assert max(cmp["relres_final_max"]) <= 1e-6
+    assert cmp["J_final_reldiff_max"] <= 1e-6
 
 
 def test_admission_respects_budget():
