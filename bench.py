@@ -150,6 +150,22 @@ def bve_section(rp4d, inputs, torch, np, gn=True):
         torch.cuda.synchronize()
         gn_s = time.perf_counter() - t0
         gn_rec = {"gn_step_s": gn_s, "pcg_iters": info["pcg_iters"], "hv_per_s": p.counters()["hv_columns"] / gn_s}
+        # the configured precision of this workload: FP32 sketch sweeps and the
+        # BF16 Gram of the eigendecomposition, FP64 PCG and Hessian products
+        ctx.set_gram_precision(rp4d.BF16)
+        st2 = p.gn_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info2 = p.gn_step(st2, sketch=rp4d.NYSTROM, ell=ell, seed=1000, sketch_dtype=rp4d.F32, rtol=1e-6,
+                          exact_lmp=True)
+        torch.cuda.synchronize()
+        gn2 = time.perf_counter() - t0
+        ctx.set_gram_precision(rp4d.F64)
+        gn_rec["configured_precision"] = {"sketch_sweeps": "f32", "gram": "bf16", "pcg": "f64",
+                                          "gn_step_s": gn2, "pcg_iters": info2["pcg_iters"],
+                                          "pcg_relres": info2["pcg_relres"],
+                                          "x_reldiff_vs_f64": float(torch.linalg.norm(st2.get()[1] - st.get()[1])
+                                                                    / torch.linalg.norm(st.get()[1]))}
     return {"workload": cfg["name"], "n": cfg["n"], "nsteps": cfg["nsteps"], "k": ell, **gn_rec,
             "hessian_block_k100_ms": 1e3 * hb, "hessian_block_hv_per_s": ell / hb,
             "hessian_k1_ms": 1e3 * hk1, "hessian_k1_hv_per_s": 1.0 / hk1,

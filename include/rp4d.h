@@ -57,7 +57,7 @@ typedef struct rp4d_traj rp4d_traj;
 typedef struct rp4d_precond rp4d_precond;
 typedef struct rp4d_gn_state rp4d_gn_state;
 
-enum { RP4D_F64 = 0, RP4D_F32 = 1 };
+enum { RP4D_F64 = 0, RP4D_F32 = 1, RP4D_BF16 = 2 };
 enum {
     RP4D_NYSTROM = 0,
     RP4D_RANDSVD = 1,
@@ -465,6 +465,17 @@ int rp4d_ctx_set_timing(rp4d_ctx* ctx, int enable);
  * frees) issued by other threads of the process, so enable it only where one
  * thread drives the device. */
 int rp4d_ctx_set_graphs(rp4d_ctx* ctx, int enable);
+
+/* Precision of the tall-skinny Gram products in the sketch post-processing
+ * that feed an eigenvalue estimate or an eigendecomposition (Alg. 2's shift
+ * estimate lambda_max(Y^T Y) and the Gram B^T B of its eigendecomposition; the
+ * Gram W W^T of the randomized EVD's eigendecomposition): RP4D_F64 (default)
+ * or RP4D_BF16 (operands rounded to bfloat16 on the BF16 matrix cores, FP32
+ * accumulation per row chunk, chunks summed in FP64: relative errors of order
+ * 2^-8 in those Grams, which cost PCG iterations, not correctness).  The Grams
+ * that are Cholesky-factored (the Nystrom core Omega^T Y_nu, Cholesky-QR, the
+ * factored preconditioner's I + W W^T) stay FP64.  RP4D_EINVAL for another dtype. */
+int rp4d_ctx_set_gram_precision(rp4d_ctx* ctx, int dtype);
 int rp4d_ctx_kernel_stats(rp4d_ctx* ctx, int kind, long long* launches, double* total_ms, double* alg_flops);
 
 /* ---------------------------------------------------------------------------

@@ -1395,6 +1395,16 @@ void build_nystrom(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
     nystrom_core(p, l, dtype == RP4D_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23), s, pc, fast);
 }
 
+// A Gram of the sketch post-processing that feeds an eigenvalue estimate or an
+// eigendecomposition (FP64 X, Y): FP64, or BF16 when the context asks for it.
+void eigen_gram(rp4d_problem* p, const double* X, int lx, const double* Y, int ly, int n, int a, int b, double* C,
+                double* work) {
+    if (p->ctx->gram_dtype == RP4D_BF16)
+        launch_gram_bf16<double, double>(X, lx, Y, ly, n, a, b, C, work, stream_of(p));
+    else
+        launch_gram<double, double>(X, lx, Y, ly, n, a, b, C, work, stream_of(p));
+}
+
 // Nystrom approximation (Alg. 2) from its sketch: Omega (n x l) in s.Om and Y = H Omega in s.Yd, both
 // row-major with leading size l; eps is the unit roundoff of the sketch sweeps.
 // Writes pc->V and s.lam, s.D, s.nu; with `fast` the factored form of the
@@ -1403,7 +1413,7 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
     hipStream_t st = stream_of(p);
     const int n = p->n;
     // shift nu = sqrt(n) eps ||Y||_2, ||Y||_2^2 = lambda_max(Y^T Y)
-    launch_gram<double, double>(s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw, st);
+    eigen_gram(p, s.Yd, l, s.Yd, l, n, l, l, s.S2, s.gw);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_sym_lmax(s.S2, l, s.lam, s.S3, st);
@@ -1440,7 +1450,7 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
         lmp_factor_fast(p, l, s.S1, s, pc);
         return;
     }
-    launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S4, s.gw, st);   // S4 = B^T B
+    eigen_gram(p, s.S1, l, s.S1, l, n, l, l, s.S4, s.gw);   // S4 = B^T B
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_jacobi_eig(s.S4, s.ev, s.S2, l, st);                       // ev = Sigma^2, S2 = U
@@ -1550,7 +1560,7 @@ void build_randsvd(rp4d_problem* p, const rp4d_traj* tr, int l, int dtype, Scrat
         return;
     }
     // thin SVD of W via eig(W W^T): V_hat = W^T U Sigma^{-1}, Lambda = Sigma^2
-    launch_gram<double, double>(s.S1, l, s.S1, l, n, l, l, s.S2, s.gw, st);
+    eigen_gram(p, s.S1, l, s.S1, l, n, l, l, s.S2, s.gw);
     {
         KernelTimer kt(p->ctx, RP4D_K_EIG, 0.0);
         launch_jacobi_eig(s.S2, s.ev, s.S3, l, st);
@@ -2978,6 +2988,14 @@ int rp4d_ctx_set_graphs(rp4d_ctx* ctx, int enable) {
     return guarded([&] {
         RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
         ctx->graphs = enable != 0;
+    });
+}
+
+int rp4d_ctx_set_gram_precision(rp4d_ctx* ctx, int dtype) {
+    return guarded([&] {
+        RP4D_REQUIRE(ctx != nullptr, RP4D_EINVAL, "null context");
+        RP4D_REQUIRE(dtype == RP4D_F64 || dtype == RP4D_BF16, RP4D_EINVAL, "Gram precision: RP4D_F64 or RP4D_BF16");
+        ctx->gram_dtype = dtype;
     });
 }
 

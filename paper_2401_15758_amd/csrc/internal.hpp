@@ -123,6 +123,11 @@ template <typename TX, typename TY>
 void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
                  hipStream_t st);
 size_t gram_work_doubles(int n, int a, int b);
+// The same Gram with both operands rounded to bfloat16 on the BF16 matrix cores
+// (FP32 accumulation per chunk, chunks summed in FP64); same `work`.
+template <typename TX, typename TY>
+void launch_gram_bf16(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
+                      hipStream_t st);
 // Out (n x b) = beta * Cin + alpha * X (n x a) * diag(dscale) * M (a x b); M row-major a x b (FP64).
 // Cin may equal Out (in-place) ; dscale may be null.
 template <typename TX, typename TO>
@@ -271,6 +276,7 @@ struct rp4d_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graph replay of the PCG iteration body (captured on a library stream)
     bool graphs = false;
+    int gram_dtype = RP4D_F64;  // Grams of the sketch's eigen-estimates: RP4D_F64 or RP4D_BF16
     bool capturing = false;
     hipStream_t cap_stream = nullptr;
     long long launches[RP4D_K_COUNT] = {};

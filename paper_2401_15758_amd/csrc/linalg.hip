@@ -223,6 +223,97 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const TX* X, int lx, 
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 Gram (an option of the sketch post-processing): the same chunked X^T Y
+// with both operands rounded to bfloat16 (via FP32, round to nearest even) on
+// the BF16 matrix cores, FP32 accumulation within a chunk, and the chunks
+// summed in FP64 by reduce_chunks_kernel.  v_mfma_f32_16x16x16_bf16 operands,
+// as measured on gfx950: lane l holds A[l%16][4(l/16) + j] and
+// B[4(l/16) + j][l%16], j = 0..3; accumulator element r of lane l is
+// D[4(l/16) + r][l%16].  LDS holds each operand column with its GR rows
+// contiguous (a lane's four k values are one 8-byte read).
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int LDB = GR + 8;  // bf16 column stride in LDS
+
+__device__ __forceinline__ unsigned short to_bf16(double v) {
+    const float f = static_cast<float>(v);
+    const unsigned u = __builtin_bit_cast(unsigned, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<unsigned short>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    return static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) gram_partial_bf16_kernel(const TX* X, int lx, const TY* Y, int ly, int n,
+                                                                int a, int b, int rows, double* part) {
+    __shared__ __align__(16) unsigned short Xs[64 * LDB];
+    __shared__ __align__(16) unsigned short Ys[64 * LDB];
+    const int chunk = blockIdx.x;
+    const int tiles_b = (b + 63) / 64;
+    const int i0 = (blockIdx.y / tiles_b) * 64, j0 = (blockIdx.y % tiles_b) * 64;
+    const int r0 = chunk * rows;
+    const int r1 = min(n, r0 + rows);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int PER = GR * 64 / 256;
+    const TsBlock bx{lx >= 16}, by{ly >= 16};
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int rb = r0; rb < r1; rb += GR) {
+        double xv[PER], yv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            xv[q] = ts_ld(X, lx, n, rb + k, i0 + c, r1, a);
+            by.coords(e, k, c);
+            yv[q] = ts_ld(Y, ly, n, rb + k, j0 + c, r1, b);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            int k, c;
+            bx.coords(e, k, c);
+            Xs[c * LDB + k] = to_bf16(xv[q]);
+            by.coords(e, k, c);
+            Ys[c * LDB + k] = to_bf16(yv[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k0 = 0; k0 < GR; k0 += 16) {
+            const int kk = k0 + 4 * (lane >> 4);
+            bf16x4 fa[2], fb[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                fa[u] = *reinterpret_cast<const bf16x4*>(Xs + (wi + 16 * u + (lane & 15)) * LDB + kk);
+                fb[u] = *reinterpret_cast<const bf16x4*>(Ys + (wj + 16 * u + (lane & 15)) * LDB + kk);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[u], fb[v], acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* P = part + static_cast<size_t>(chunk) * a * b;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * u + 4 * (lane >> 4) + r;
+                const int j = j0 + wj + 16 * v + (lane & 15);
+                if (i < a && j < b) P[static_cast<size_t>(i) * b + j] = static_cast<double>(acc[u][v][r]);
+            }
+}
+
 // out[idx] = sum_c part[c][idx], c in increasing order; loads issued 16 at a time.
 __global__ void reduce_chunks_kernel(const double* part, int nchunks, size_t stride, double* out) {
     const size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
@@ -1040,6 +1131,20 @@ void launch_gram(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, 
     RP4D_HIP(hipGetLastError());
 }
 
+template <typename TX, typename TY>
+void launch_gram_bf16(const TX* X, int lx, const TY* Y, int ly, int n, int a, int b, double* C, double* work,
+                      hipStream_t st) {
+    check_ts_layout(lx, a);
+    check_ts_layout(ly, b);
+    const int nchunks = gram_chunks(n);
+    dim3 grid(nchunks, ((a + 63) / 64) * ((b + 63) / 64));
+    gram_partial_bf16_kernel<TX, TY><<<grid, 256, 0, st>>>(X, lx, Y, ly, n, a, b, gram_rows(n), work);
+    RP4D_HIP(hipGetLastError());
+    const size_t stride = static_cast<size_t>(a) * b;
+    reduce_chunks_kernel<<<grid_for(stride), 256, 0, st>>>(work, nchunks, stride, C);
+    RP4D_HIP(hipGetLastError());
+}
+
 template <typename TX, typename TO>
 void launch_tsmm(const TX* X, int lx, const double* M, const double* dscale, int n, int a, int b, double alpha,
                  const TO* Cin, int lc, double beta, TO* Out, int lo, hipStream_t st) {
@@ -1182,6 +1287,8 @@ template void launch_relayout<float, double>(const float*, int, double*, int, in
 template void launch_relayout<float, float>(const float*, int, float*, int, int, int, hipStream_t);
 template void launch_fill<double>(double*, size_t, double, hipStream_t);
 template void launch_fill<float>(float*, size_t, float, hipStream_t);
+template void launch_gram_bf16<double, double>(const double*, int, const double*, int, int, int, int, double*,
+                                               double*, hipStream_t);
 template void launch_gram<double, double>(const double*, int, const double*, int, int, int, int, double*, double*,
                                           hipStream_t);
 template void launch_gram<float, float>(const float*, int, const float*, int, int, int, int, double*, double*,

@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ENOTSPD, ENOCONV, ENONFINITE, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-F64, F32 = 0, 1
+F64, F32, BF16 = 0, 1, 2
 NYSTROM, RANDSVD, NOPREC, RANDSVD_ADAPTIVE, SINGLEVIEW, SINGLEVIEW_ADAPTIVE, NYSTROM_ADAPTIVE = 0, 1, 2, 3, 4, 5, 6
 BURGERS1D, BVE2D, BURGERS1D_WALL = 0, 1, 2
 K_TLM, K_ADJ, K_FWD, K_BHALF, K_TLM1, K_ADJ1, K_EIG, K_GEMM, K_STENCIL = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -160,6 +160,7 @@ _SIGS = {
     "rp4d_gn_state_reset": ([_P], _I),
     "rp4d_ctx_set_timing": ([_P, _I], _I),
     "rp4d_ctx_set_graphs": ([_P, _I], _I),
+    "rp4d_ctx_set_gram_precision": ([_P, _I], _I),
     "rp4d_ctx_kernel_stats": ([_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
     "rp4d_batch_create": ([_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
     "rp4d_batch_destroy": ([_P], _I),
@@ -242,6 +243,9 @@ class Context:
 
     def set_graphs(self, enable=True):
         _check(_lib.rp4d_ctx_set_graphs(self._h, 1 if enable else 0))
+
+    def set_gram_precision(self, dtype=F64):
+        _check(_lib.rp4d_ctx_set_gram_precision(self._h, dtype))
 
     def kernel_stats(self, kind):
         n, ms, fl = ctypes.c_longlong(), _D(), _D()

@@ -534,3 +534,32 @@ def test_pipelined_gn_steps_match_sequential():
             got = run(0, sketch, steps, short_fwd=short, tuned=tuned)
             assert got[0] == ref[0], (sketch, short, tuned)
             assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2]), (sketch, short, tuned)
+
+
+@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
+def test_bf16_gram_option(small, method):
+    """The BF16 Gram option of the sketch post-processing: Lambda_hat within the
+    bfloat16 rounding scale of the FP64 build (Weyl: the eigenvalues move by at
+    most the Gram's perturbation, here entries off by O(2^-8) of their
+    Cauchy-Schwarz bound), and PCG with that preconditioner still meets a
+    1e-10 residual against the oracle's solution.  Other dtypes are rejected."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    pr = small
+    m = rp4d.NYSTROM if method == "nystrom" else rp4d.RANDSVD
+    om = to_dev(inputs.omega(pr.orc.n, 20))
+    lam64 = np.array(pr.gpu.build_precond(pr.traj, m, 20, omega=om).info()[0])
+    pr.ctx.set_gram_precision(rp4d.BF16)
+    try:
+        pc = pr.gpu.build_precond(pr.traj, m, 20, omega=om)
+        lam16 = np.array(pc.info()[0])
+        b = _probe(pr.orc.n, 1, seed=41)[:, 0]
+        x, info = pr.gpu.pcg_solve(pr.traj, to_dev(b), precond=pc, rtol=1e-12)
+    finally:
+        pr.ctx.set_gram_precision(rp4d.F64)
+    assert np.max(np.abs(lam16 - lam64)) <= 2.0 ** -6 * lam64.max()
+    assert np.max(np.abs(lam16 - lam64)) > 0          # the option changed the arithmetic
+    xo = np.linalg.solve(pr.orc.hessian(pr.otraj, np.eye(pr.orc.n)), b)   # the oracle's (I + H)
+    assert relerr(to_np(x), xo) <= 1e-10
+    with pytest.raises(rp4d.Rp4dError):
+        pr.ctx.set_gram_precision(rp4d.F32)
