@@ -15,7 +15,11 @@ Requests arrive as a Poisson stream and are served with:
   overlaps the batch on the device;
 * residency: each request's trajectory and preconditioner stay in its GN state
   across its iterations, and the reuse test kappa_re < reuse_eps decides
-  whether to keep the preconditioner or sketch again.
+  whether to keep the preconditioner or sketch again;
+* cancellation: a request whose `cancel_at` has passed (or that has done
+  `cancel_after` GN steps) is dropped from the queue, or leaves service at its
+  next GN-step boundary (its memory and budget released, its state at that
+  point kept in `x`); the others are unaffected.
 
 Every random draw of a request is keyed by the request id and its iteration
 number, and all reductions are per problem, so a request's result does not
@@ -53,6 +57,12 @@ class Request:
     relres: list = field(default_factory=list)   # final PCG relative residual of each GN step
     x: np.ndarray = None    # final state (host copy)
     hbm_peak: int = 0       # peak device bytes the served run's contexts held (library count)
+    cancel_at: float = math.inf   # cancellation time (seconds after the start of the run)
+    cancel_after: int = None      # or: cancelled once this many GN steps are done
+    cancelled: bool = False
+
+    def cancel_due(self, now):
+        return self.cancel_at <= now or (self.cancel_after is not None and self.gn_done >= self.cancel_after)
 
     @property
     def model(self):
@@ -208,6 +218,10 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
         queue = list(pend_b)
         batch, members = None, ()
         while queue or active:
+            # drop queued requests whose cancellation time has passed
+            for r in [q for q in queue if q.cancel_due(now())]:
+                queue.remove(r)
+                r.cancelled, r.done = True, now()
             # admit arrived requests in FIFO order while their footprint fits
             while queue and queue[0].arrival <= now():
                 fp = footprint_bytes(queue[0].cfg)
@@ -237,7 +251,9 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 r.J.append(inf["J"])
                 r.relres.append(inf["pcg_relres"])
                 r.reused += inf["reused"]
-                if r.gn_done >= gn_steps:
+                if r.gn_done < gn_steps and r.cancel_due(now()):
+                    r.cancelled = True
+                if r.gn_done >= gn_steps or r.cancelled:
                     _finish(torch, ctx, r, st, t0, verbose)
                     st.close()
                     budget.give(fp)
@@ -247,7 +263,7 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 batch.close()
                 batch, members = None, ()
             for (r, p, st, fp) in active:
-                if r.gn_done >= gn_steps:
+                if r.gn_done >= gn_steps or r.cancelled:
                     p.close()
             active = keep
         if batch is not None:
@@ -260,6 +276,10 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
                 if not pend_v:
                     return
                 r = pend_v[0]
+                if r.cancel_due(now()):          # cancelled while queued
+                    pend_v.pop(0)
+                    r.cancelled, r.done = True, now()
+                    continue
                 take = r.arrival <= now() and budget.try_take(footprint_bytes(r.cfg))
                 if take:
                     pend_v.pop(0)
@@ -270,6 +290,9 @@ def serve(trace, budget_bytes=64 << 30, gn_steps=3, rtol=1e-6, reuse_eps=10.0, s
             r.admitted = now()
             p, st = _setup(rp4d, torch, ctx, r)
             for it in range(gn_steps):
+                if it > 0 and r.cancel_due(now()):
+                    r.cancelled = True
+                    break
                 inf = p.gn_step(st, ell=r.cfg["ell"], seed=_step_seed(r, it), sketch_dtype=sketch_dtype, rtol=rtol,
                                 reuse_eps=reuse_eps)
                 r.gn_done += 1
@@ -336,10 +359,12 @@ def serve_sequential(trace, gn_steps=3, rtol=1e-6, verbose=False):
 
 
 def summary(trace):
+    cancelled = sum(1 for r in trace if r.cancelled)
+    trace = [r for r in trace if not r.cancelled]
     lat = np.array([r.latency for r in trace])
     span = max(r.done for r in trace) - min(r.arrival for r in trace)
     last_res = [r.relres[-1] for r in trace if r.relres]
-    return {"requests": len(trace), "solves_per_s": len(trace) / span, "p50_latency_s": float(np.percentile(lat, 50)),
+    return {"requests": len(trace), "cancelled": cancelled, "solves_per_s": len(trace) / span, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "makespan_s": span,
             "pcg_iters_total": int(sum(sum(r.pcg_iters) for r in trace)),
             "reuses": int(sum(r.reused for r in trace)),
@@ -357,7 +382,8 @@ def compare(a, b):
 
 
 def clone_trace(trace):
-    return [Request(rid=r.rid, cfg=dict(r.cfg), arrival=r.arrival, seed=r.seed) for r in trace]
+    return [Request(rid=r.rid, cfg=dict(r.cfg), arrival=r.arrival, seed=r.seed, cancel_at=r.cancel_at,
+                    cancel_after=r.cancel_after) for r in trace]
 
 
 def main():

@@ -101,3 +101,32 @@ def test_ring_group_placement():
     assert place(768, 256) == (768, 1024, False)
     assert place(800, 256) == (0, 256, True)
     assert place(0, 513) is None
+
+
+@pytest.fixture(scope="module")
+def checker_sanitized(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path_factory.mktemp("plan_san") / "batch_plan_check_san")
+    r = subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"),
+                        "-I", os.path.join(ROOT, "paper_2401_15758_amd", "csrc"), SRC, "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0 and "asan" in (r.stderr + r.stdout).lower():
+        pytest.skip("host sanitizer runtime not available")
+    assert r.returncode == 0, r.stderr[-2000:]
+    return exe
+
+
+def test_planner_under_address_and_undefined_behaviour_sanitizers(checker_sanitized):
+    """The host planner and ring placement (the library's own header code) built
+    with AddressSanitizer and UndefinedBehaviorSanitizer, on a sample of the
+    batch-64 problems and of the searched tilings: no sanitizer report, and the
+    same verdicts as the plain build."""
+    cfgs = inputs.batch_configs(64, seed=0)[::4]
+    tilings = autotune.batch_candidates()[::9]
+    rc, out = _run(checker_sanitized, cfgs, tilings, [32, 1])
+    last = out.strip().splitlines()[-1]
+    assert rc == 0, out[-4000:]
+    assert last.startswith("planned") and last.endswith("violations 0"), last

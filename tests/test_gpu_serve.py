@@ -46,6 +46,36 @@ def test_served_and_sequential_reach_the_same_cost():
     assert cmp["J_final_reldiff_max"] <= 1e-6
 
 
+def test_cancellation_leaves_other_requests_unchanged():
+    """One request cancelled while queued and one after its first GN step: the
+    first is never admitted, the second ends with its state after one step
+    (bitwise that of the same request served alone for one step), and every
+    other request ends bitwise as in the run without cancellations."""
+    need_gpu()
+    import math
+    trace = serve.make_trace(6, rate=0.0, seed=14, frac_burgers=0.65, **SMALL_MIX)
+    base = {r.rid: r for r in serve.serve(serve.clone_trace(trace))}
+    tr = serve.clone_trace(trace)
+    burg = [r for r in tr if r.model == "burgers"]
+    bve = [r for r in tr if r.model == "bve"]
+    queued, mid = burg[0], (bve or burg[1:])[0]
+    queued.cancel_at = 0.0
+    mid.cancel_after = 1
+    done = {r.rid: r for r in serve.serve(tr)}
+    assert done[queued.rid].cancelled and done[queued.rid].gn_done == 0 and done[queued.rid].x is None
+    m = done[mid.rid]
+    assert m.cancelled and m.gn_done == 1
+    one = serve.serve([serve.Request(rid=mid.rid, cfg=dict(mid.cfg), arrival=0.0, seed=mid.seed)], gn_steps=1)[0]
+    assert np.array_equal(one.x, m.x)
+    for rid, r in done.items():
+        if rid in (queued.rid, mid.rid):
+            continue
+        assert not r.cancelled and r.gn_done == 3
+        assert np.array_equal(r.x, base[rid].x), r.cfg["name"]
+    s = serve.summary(list(done.values()))
+    assert s["cancelled"] == 2 and s["requests"] == len(trace) - 2 and math.isfinite(s["p99_latency_s"])
+
+
 def test_admission_respects_budget():
     need_gpu()
     trace = serve.make_trace(10, rate=0.0, seed=12, frac_burgers=0.8, **SMALL_MIX)
