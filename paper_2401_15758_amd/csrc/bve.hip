@@ -354,10 +354,8 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> 
         fftl::store_twiddles<T, N>(wl, tw);
         rows_spec_store<T, B>(lds, rown, zv);
     }
-    __syncthreads();
-    rows_inverse<T, B>(lds, rown, wl);
-    const T bst = static_cast<T>(kRkB[a.stage]);
-    // the points' own dz and acc, loaded together before any arithmetic
+    // the points' own dz and acc, issued before the inverse row FFTs so that
+    // their latency overlaps the transforms
     T dzv[2][PER], acv[2][PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
@@ -370,6 +368,9 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> 
             acv[f][t] = a.stage == 0 ? T(0) : a.acc[g];
         }
     }
+    __syncthreads();
+    rows_inverse<T, B>(lds, rown, wl);
+    const T bst = static_cast<T>(kRkB[a.stage]);
     T out[2][PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
@@ -485,15 +486,13 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
         fftl::store_twiddles<T, N>(wl, tw);
         if (a.m >= 0) rows_spec_store<T, B>(lds, rown, zv);
     }
-    __syncthreads();
-    if (a.m >= 0) rows_inverse<T, B>(lds, rown, wl);
     // mu' on the owned rows and one halo row on each side, into the LDS lines;
-    // in chunks of CH points per thread, each chunk's global loads issued together
+    // in chunks of CH points per thread, each chunk's global loads issued
+    // together, the first chunk's before the inverse row FFTs so that their
+    // latency overlaps the transforms
     constexpr int CH = PERH < 8 ? PERH : 8;
     const bool need_r = a.m >= 0, need_lam = a.m != 0, need_acc = a.m == 0 || a.m == 1 || a.m == 2;
-#pragma unroll
-    for (int t0 = 0; t0 < PERH; t0 += CH) {
-        T rv[2][CH], lv[2][CH], av[2][CH];
+    auto load_chunk = [&](int t0, T (&rv)[2][CH], T (&lv)[2][CH], T (&av)[2][CH]) {
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int e = min(tid + (t0 + u) * 16 * fftl::kLines, (rown + 2) * N - 1);
@@ -509,6 +508,14 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
                 av[f][u] = need_acc ? a.acc[g] : T(0);
             }
         }
+    };
+    T rv[2][CH], lv[2][CH], av[2][CH];
+    load_chunk(0, rv, lv, av);
+    __syncthreads();
+    if (a.m >= 0) rows_inverse<T, B>(lds, rown, wl);
+#pragma unroll
+    for (int t0 = 0; t0 < PERH; t0 += CH) {
+        if (t0 > 0) load_chunk(t0, rv, lv, av);
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int e = tid + (t0 + u) * 16 * fftl::kLines;
