@@ -6,10 +6,10 @@
       keeps launches whose grid_x (work-items) equals X.
 
   python -m paper_2401_15758_amd.profile_summary traffic FETCH_DB WRITE_DB --kernel S --grid X
-      --calib-mib M [--tiling JSON] [--workload W] [--sources F ...] [--out JSON]
-      HBM bytes per launch of the launches of kernel S with grid_x X, from a
-      FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch, summed over the
-      counter's instances).  Each counter is scaled by what it reads on the run's
+      [--grid-y Y] --calib-mib M [--tiling JSON] [--workload W] [--sources F ...] [--out JSON]
+      HBM bytes per launch of the launches of kernel S with grid_x X (and
+      grid_y Y), from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch,
+      summed over the counter's instances).  Each counter is scaled by what it reads on the run's
       calibration dispatch: the last elementwise copy kernel, which reads and
       writes M MiB.  --sources records the sha256 of the kernel's source files, so
       that a reader can tell whether the record still matches the code.
@@ -23,7 +23,7 @@ import sys
 
 def _kernels(db):
     con = sqlite3.connect(db)
-    rows = con.execute("select name, duration, grid_x, dispatch_id from kernels order by dispatch_id").fetchall()
+    rows = con.execute("select name, duration, grid_x, dispatch_id, grid_y from kernels order by dispatch_id").fetchall()
     con.close()
     return rows
 
@@ -40,7 +40,7 @@ def stats(db, match=None, grid=None):
     total_all = sum(r[1] for r in rows)
     sel = [r for r in rows if (match is None or match in r[0]) and (grid is None or r[2] == grid)]
     agg = {}
-    for name, dur, _, _ in sel:
+    for name, dur, *_ in sel:
         a = agg.setdefault(name, [0, 0])
         a[0] += 1
         a[1] += dur
@@ -60,8 +60,8 @@ def _counter_per_dispatch(db, counter):
     return dict(rows)
 
 
-def traffic(fetch_db, write_db, kernel, grid, calib_mib, tiling=None, workload=None, sources=()):
-    rec = {"kernel": kernel, "grid_x": grid, "workload": workload, "tiling": tiling or {}}
+def traffic(fetch_db, write_db, kernel, grid, calib_mib, tiling=None, workload=None, sources=(), grid_y=None):
+    rec = {"kernel": kernel, "grid_x": grid, "grid_y": grid_y, "workload": workload, "tiling": tiling or {}}
     if sources:
         h = hashlib.sha256()
         for s in sources:
@@ -72,8 +72,9 @@ def traffic(fetch_db, write_db, kernel, grid, calib_mib, tiling=None, workload=N
     for db, counter, key in ((fetch_db, "FETCH_SIZE", "fetch"), (write_db, "WRITE_SIZE", "write")):
         per = _counter_per_dispatch(db, counter)
         ks = _kernels(db)
-        sel = [per[d] for name, _, g, d in ks if kernel in name and g == grid and d in per]
-        copies = [per[d] for name, _, g, d in ks if "elementwise" in name.lower() and d in per]
+        sel = [per[d] for name, _, g, d, gy in ks
+               if kernel in name and g == grid and (grid_y is None or gy == grid_y) and d in per]
+        copies = [per[d] for name, _, g, d, _ in ks if "elementwise" in name.lower() and d in per]
         if not sel or not copies:
             raise SystemExit(f"{db}: no {counter} values for {kernel!r} at grid {grid} or no calibration copy")
         calib = copies[-1]
@@ -100,6 +101,7 @@ def main(argv=None):
     t.add_argument("write_db")
     t.add_argument("--kernel", required=True)
     t.add_argument("--grid", type=int, required=True)
+    t.add_argument("--grid-y", type=int)
     t.add_argument("--calib-mib", type=int, required=True)
     t.add_argument("--tiling")
     t.add_argument("--workload")
@@ -110,7 +112,7 @@ def main(argv=None):
         print(stats(a.db, a.match, a.grid))
         return
     rec = traffic(a.fetch_db, a.write_db, a.kernel, a.grid, a.calib_mib,
-                  json.loads(a.tiling) if a.tiling else None, a.workload, a.sources)
+                  json.loads(a.tiling) if a.tiling else None, a.workload, a.sources, a.grid_y)
     if a.out:
         try:
             with open(a.out) as f:
