@@ -4,8 +4,9 @@
 // A line of N = 16 B complex values is transformed in padded LDS by sixteen
 // threads with the four-step factorisation n = n1 + 16 n2, k = B k1 + k2:
 // X[k] = sum_{n1} W16^{n1 k1} W_N^{n1 k2} sum_{n2} x[n1 + 16 n2] W_B^{n2 k2}.
-// Thread n1 takes the B-point DFT over n2 (radix 4 x 4 when B = 16, a direct
-// sum otherwise) and the twiddle W_N^{n1 k2}; after a barrier, thread k2 takes
+// Thread n1 takes the B-point DFT over n2 (radix 4 x 4 when B = 16, radix-2
+// decimation in time down to 16, 4 or an odd 3 or 5 otherwise) and the
+// twiddle W_N^{n1 k2}; after a barrier, thread k2 takes
 // the radix-4 x 4 16-point DFT of the contiguous block k2.  The inverse is the
 // conjugate of the forward transform of the conjugate.  Storage is padded by
 // one complex value per 16, which keeps both access patterns free of LDS bank
@@ -78,14 +79,36 @@ __device__ __forceinline__ void fft16(C2<T> (&x)[16]) {
     for (int e = 0; e < 16; ++e) x[e] = o[e];
 }
 
-// Forward B-point DFT of x with W_B^m = W_N^{m N/B} (Wl: exp(-2 pi i m / N),
-// m < N, in LDS).
+// Forward B-point DFT of x in registers with W_B^m = W_N^{m N/B} (Wl:
+// exp(-2 pi i m / N), m < N, in LDS).  B = 16: radix 4 x 4; B = 4: one
+// radix-4 butterfly; other even B: decimation in time, the DFTs of the even
+// and the odd samples combined with the twiddles W_B^k; odd B (3, 5): the
+// direct sum.
 template <typename T, int B>
 __device__ __forceinline__ void dft_small(C2<T> (&x)[B], const C2<T>* Wl, int N) {
     if constexpr (B == 16) {
         fft16<T>(x);
     } else if constexpr (B == 4) {
         dft4(x[0], x[1], x[2], x[3]);
+    } else if constexpr (B == 1) {
+    } else if constexpr (B % 2 == 0) {
+        constexpr int M = B / 2;
+        C2<T> e[M], o[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            e[m] = x[2 * m];
+            o[m] = x[2 * m + 1];
+        }
+        dft_small<T, M>(e, Wl, N);
+        dft_small<T, M>(o, Wl, N);
+        const int st = N / B;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const C2<T> w = Wl[k * st];
+            const C2<T> t = cmul(o[k], w.r, w.i);
+            x[k] = C2<T>{e[k].r + t.r, e[k].i + t.i};
+            x[k + M] = C2<T>{e[k].r - t.r, e[k].i - t.i};
+        }
     } else {
         T wr[B], wi[B];
         const int st = N / B;
