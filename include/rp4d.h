@@ -92,7 +92,9 @@ enum { RP4D_SOLVE_PCG = 0, RP4D_SOLVE_SKETCH = 1 };
  *     Burgers only: the 2-D model always stores every state and, per step, its
  *     RK4 stage values and stream functions (7 fields per step).
  * 2-D model (Sec. 5.2, periodic form): vorticity zeta on a square grid
- * (nx == ny, a multiple of 16, 16..2048), flattened j*nx + i; stream function
+ * (nx == ny = 16 B with B in {2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}, the
+ * sides the line FFTs take, i.e. 32..512; others are RP4D_EINVAL at creation),
+ * flattened j*nx + i; stream function
  * psi = L zeta with L the spectral inverse Laplacian (zero mean); RHS
  * -J_A(psi, zeta) + nu lap(zeta) with Arakawa's Jacobian J_A and the 5-point
  * Laplacian; separable prior sigma_b (S_y kron S_x), S the circulant square
@@ -423,8 +425,10 @@ int rp4d_problem_synthesize(rp4d_problem* p, const double* x_true, const double*
                             double* xb_out, double* y_out);
 
 /* 2-D model only: psi = L zeta for k fields, in and out row-major (n x k) in
- * `dtype` on the device (in == out allowed).  L is applied as four dense
- * products with the real Fourier basis (MFMA).  RP4D_EINVAL for a 1-D problem. */
+ * `dtype` on the device (in == out allowed).  L is the spectral inverse
+ * Laplacian (Sec. 5.2), diagonal in the 2-D Fourier basis, applied by FFT:
+ * the fields go through row, column (times the diagonal) and inverse row
+ * transforms as ceil(k/2) complex pairs.  RP4D_EINVAL for a 1-D problem. */
 int rp4d_bve_inv_laplacian(rp4d_problem* p, int k, const void* in, void* out, int dtype);
 
 /* Reset a GN state to v = 0, x = x_b and drop its resident preconditioner. */
