@@ -258,6 +258,8 @@ def batch_section(rp4d, inputs, torch, np):
     from paper_2401_15758_amd import autotune
     # the batched sweep tilings found by the batched search (tuning.json), per precision
     tuned = {name: autotune.apply_cached_batch(b, 32, dt) for name, dt in (("f64", rp4d.F64), ("f32", rp4d.F32))}
+    # and the single-vector sweeps' own tiling (gradient and PCG products, FP64)
+    tuned["k1_f64"] = autotune.apply_cached_batch(b, 1, rp4d.F64)
     res = {"workload": "batch-64", "problems": len(cfgs), "k": 32,
            "tiling": {name: (ent["sweep"] if ent else "library default") for name, ent in tuned.items()}}
     # the lock-step PCG eager and with its iteration body replayed as a HIP

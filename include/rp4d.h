@@ -504,6 +504,13 @@ int rp4d_batch_destroy(rp4d_batch* b);
  * kc 2 for the block sweeps, ppt 2 for the forward sweep; 256 threads).
  * Results do not depend on the tiling. */
 int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps, int xch);
+/* As rp4d_batch_set_tiling for k = 0; k = 1 sets the tiling of the batch's
+ * single-vector TLM/ADJ sweeps (the gradient and the PCG products; kc <= 1),
+ * which takes precedence over the k = 0 entry for them.  Default of those
+ * sweeps: wave regions, 4 points per lane, 256 threads, 16 steps per launch.
+ * RP4D_EINVAL for another k, for k = 1 with the FWD mode or kc > 1. */
+int rp4d_batch_set_tiling_k(rp4d_batch* b, int mode, int dtype, int k, int ppt, int kc, int threads, int steps,
+                            int xch);
 /* FWD of every problem from x0[i] (device, n_i) into trajs[i]; J_obs (host, nprob,
  * nullable) receives 1/2 |d_i|^2. */
 int rp4d_batch_fwd(rp4d_batch* b, const double* const* x0, rp4d_traj* const* trajs, double* J_obs);

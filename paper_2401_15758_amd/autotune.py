@@ -278,7 +278,9 @@ def tune_batch(batch, trajs, k, dtype=rp4d.F64, reps=2, budget_s=60.0, verbose=F
     """Search the batched sweep tiling (one for the TLM and the ADJ sweep of
     rp4d_batch_hessian_block) by timing the batched block Hessian of k vectors
     over the whole batch with each candidate; applies and returns the best
-    {"sweep": {...tiling, ms}}.  Candidates are tried cheapest-looking first
+    {"sweep": {...tiling, ms}}.  k = 1 searches the single-vector sweeps' own
+    entry (the gradient and PCG products; one vector per group), any other k
+    the entry of every sweep.  Candidates are tried cheapest-looking first
     (more steps per launch, larger regions) until the budget is spent."""
     tdtype = torch.float64 if dtype == rp4d.F64 else torch.float32
     Vs = []
@@ -288,17 +290,18 @@ def tune_batch(batch, trajs, k, dtype=rp4d.F64, reps=2, budget_s=60.0, verbose=F
         Vs.append(V.to(tdtype))
     HVs = [torch.empty_like(v) for v in Vs]
     op = lambda: batch.hessian_block(trajs, Vs, HVs)
+    kk = 1 if k == 1 else 0
     for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
-        batch.set_tiling(mode, dtype)                          # library default
+        batch.set_tiling(mode, dtype, k=kk)                    # library default
     best, best_ms = None, _time(op, reps)
-    cands = batch_candidates(dtype)
+    cands = [c for c in batch_candidates(dtype) if kk == 0 or c["kc"] == 1]
     cands.sort(key=lambda c: (-c["steps"] * c["ppt"], -c["kc"], c["threads"]))
     t_end = time.perf_counter() + budget_s
     for c in cands:
         if time.perf_counter() > t_end:
             break
         for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
-            batch.set_tiling(mode, dtype, **c)
+            batch.set_tiling(mode, dtype, k=kk, **c)
         try:
             ms = _time(op, reps)
         except rp4d.Rp4dError:                                 # e.g. a staged group beyond the ring
@@ -309,9 +312,9 @@ def tune_batch(batch, trajs, k, dtype=rp4d.F64, reps=2, budget_s=60.0, verbose=F
             best, best_ms = dict(c), ms
     for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
         if best is None:
-            batch.set_tiling(mode, dtype)
+            batch.set_tiling(mode, dtype, k=kk)
         else:
-            batch.set_tiling(mode, dtype, **best)
+            batch.set_tiling(mode, dtype, k=kk, **best)
     return {"sweep": dict(best or {}, ms=best_ms, default=best is None)}
 
 
@@ -322,7 +325,7 @@ def apply_cached_batch(batch, k, dtype=rp4d.F64, cache=None):
         return None
     t = {f: ent["sweep"].get(f, 0) for f in ("xch", "ppt", "kc", "threads", "steps")}
     for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
-        batch.set_tiling(mode, dtype, **t)
+        batch.set_tiling(mode, dtype, k=1 if k == 1 else 0, **t)
     return ent
 
 

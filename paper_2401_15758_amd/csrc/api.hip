@@ -3090,6 +3090,8 @@ struct rp4d_batch {
     rp4d::DevBuf scal;  // 16 doubles per problem of batch scalars
     // [mode-1][dtype] overrides (ppt, kc, threads, steps, xch; <= 0: default)
     rp4d::Tiling bt[2][2] = {{{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}, {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}};
+    // [mode-1][dtype] overrides of the single-vector sweeps (gradient, PCG products)
+    rp4d::Tiling bt1[2][2] = {{{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}, {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}}};
     rp4d::Tiling bt_fwd = {0, 0, 0, 0, 0, 0};  // forward-sweep overrides
     // Staging for graph capture of the lock-step PCG body (gmode != 0): instead
     // of the ring, tables go to offsets of a device arena.  gmode 1 sizes them
@@ -3182,9 +3184,14 @@ std::vector<int4> elem_items(const std::vector<size_t>& counts) {
 }
 
 // Batched sweep tilings.  Defaults: wave regions (64 ppt points per wave, one
-// work item per wave), 12 steps per launch; overrides per (mode, dtype) and for
-// the forward sweep through rp4d_batch_set_tiling.
-Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd) {
+// work item per wave), 12 steps per launch (single-vector sweeps: 4 points per
+// lane, 16 steps, the best of a search over wave and workgroup regions on
+// batch-64's PCG product); overrides per (mode, dtype) and for the forward
+// sweep through rp4d_batch_set_tiling, and for single-vector sweeps (k = 1)
+// through rp4d_batch_set_tiling_k, which take precedence there.
+inline bool tiling_set(const Tiling& o) { return o.ppt > 0 || o.kc > 0 || o.threads > 0 || o.steps > 0 || o.xch > 0; }
+
+Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd, int k = 0) {
     Tiling t;
     t.xch = XCH_WAVE;
     t.threads = 256;
@@ -3193,9 +3200,11 @@ Tiling batch_tiling(const rp4d_batch* b, int mode, int dtype, bool fwd) {
     t.ppt = 2;
     const Tiling* o = &b->bt_fwd;
     if (!fwd) {
+        const int d = dtype == RP4D_F64 ? 0 : 1;
         t.ppt = 4;
-        t.kc = 2;
-        o = &b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+        t.kc = k == 1 ? 1 : 2;
+        if (k == 1) t.steps = 16;
+        o = (k == 1 && tiling_set(b->bt1[mode - 1][d])) ? &b->bt1[mode - 1][d] : &b->bt[mode - 1][d];
     }
     if (o->ppt > 0) t.ppt = o->ppt;
     if (o->kc > 0 && !fwd) t.kc = o->kc;
@@ -3417,7 +3426,7 @@ void batch_hessian(rp4d_batch* b, const std::vector<int>& sel, const std::vector
                    const std::vector<const T*>& V, const std::vector<T*>& HV, bool add_identity) {
     hipStream_t st = b->ctx->stream;
     const int dt = sizeof(T) == 8 ? RP4D_F64 : RP4D_F32;
-    Tiling tt = batch_tiling(b, MODE_TLM, dt, false), ta = batch_tiling(b, MODE_ADJ, dt, false);
+    Tiling tt = batch_tiling(b, MODE_TLM, dt, false, k), ta = batch_tiling(b, MODE_ADJ, dt, false, k);
     while (tt.kc > 1 && tt.kc > k) tt.kc /= 2;   // no padded vectors for small k
     while (ta.kc > 1 && ta.kc > k) ta.kc /= 2;
     const int np = static_cast<int>(sel.size());
@@ -3456,7 +3465,7 @@ void batch_hessian(rp4d_batch* b, const std::vector<int>& sel, const std::vector
 // Batched gradient g[i] = v[i] + A_i^T d_i (FP64, one ADJ sweep per problem).
 void batch_gradient(rp4d_batch* b, const std::vector<int>& sel, const std::vector<const rp4d_traj*>& trajs,
                     const std::vector<const double*>& v, const std::vector<double*>& g) {
-    const Tiling ta = batch_tiling(b, MODE_ADJ, RP4D_F64, false);
+    const Tiling ta = batch_tiling(b, MODE_ADJ, RP4D_F64, false, 1);
     Tiling t1 = ta;
     t1.kc = 1;
     const int np = static_cast<int>(sel.size());
@@ -3908,12 +3917,20 @@ int rp4d_batch_destroy(rp4d_batch* b) {
 }
 
 int rp4d_batch_set_tiling(rp4d_batch* b, int mode, int dtype, int ppt, int kc, int threads, int steps, int xch) {
+    return rp4d_batch_set_tiling_k(b, mode, dtype, 0, ppt, kc, threads, steps, xch);
+}
+
+int rp4d_batch_set_tiling_k(rp4d_batch* b, int mode, int dtype, int k, int ppt, int kc, int threads, int steps,
+                            int xch) {
     return guarded([&] {
         RP4D_REQUIRE(b != nullptr && (mode == MODE_TLM || mode == MODE_ADJ || mode == RP4D_MODE_FWD) &&
                          (dtype == RP4D_F64 || dtype == RP4D_F32), RP4D_EINVAL, "bad argument");
+        RP4D_REQUIRE(k == 0 || (k == 1 && mode != RP4D_MODE_FWD && kc <= 1), RP4D_EINVAL,
+                     "batched tiling: k is 0 (every sweep) or 1 (single-vector TLM/ADJ sweeps, kc <= 1)");
         RP4D_REQUIRE(xch <= 0 || xch == XCH_LDS || xch == XCH_WAVE, RP4D_EINVAL,
                      "batched sweeps: workgroup (1) or wave (2) regions");
-        Tiling& t = mode == RP4D_MODE_FWD ? b->bt_fwd : b->bt[mode - 1][dtype == RP4D_F64 ? 0 : 1];
+        const int d = dtype == RP4D_F64 ? 0 : 1;
+        Tiling& t = mode == RP4D_MODE_FWD ? b->bt_fwd : (k == 1 ? b->bt1[mode - 1][d] : b->bt[mode - 1][d]);
         t.ppt = ppt;
         t.kc = kc;
         t.threads = threads;

@@ -165,6 +165,7 @@ _SIGS = {
     "rp4d_batch_create": ([_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
     "rp4d_batch_destroy": ([_P], _I),
     "rp4d_batch_set_tiling": ([_P, _I, _I, _I, _I, _I, _I, _I], _I),
+    "rp4d_batch_set_tiling_k": ([_P, _I, _I, _I, _I, _I, _I, _I, _I], _I),
     "rp4d_batch_fwd": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_D)], _I),
     "rp4d_batch_hessian_block": ([_P, ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P), _I, _I], _I),
     "rp4d_batch_gn_step": ([_P, ctypes.POINTER(_P), ctypes.POINTER(GnOpts), ctypes.POINTER(GnInfo)], _I),
@@ -616,8 +617,8 @@ class Batch:
                                       ctypes.byref(h)))
         self._h = h
 
-    def set_tiling(self, mode, dtype=F64, ppt=0, kc=0, threads=0, steps=0, xch=0):
-        _check(_lib.rp4d_batch_set_tiling(self._h, mode, dtype, ppt, kc, threads, steps, xch))
+    def set_tiling(self, mode, dtype=F64, ppt=0, kc=0, threads=0, steps=0, xch=0, k=0):
+        _check(_lib.rp4d_batch_set_tiling_k(self._h, mode, dtype, k, ppt, kc, threads, steps, xch))
 
     def fwd(self, x0s, trajs, want_J=True):
         J = (_D * len(self.problems))()

@@ -239,3 +239,32 @@ def test_batched_pcg_graph_replay_is_bitwise_eager():
         Om = orng.gaussian_matrix(_omega_seed(seed, 100 + i), o.n, ell)
         _, _, x1, _ = ogn.gn_step(o, np.zeros(o.n), method='nystrom', Omega=Om, rtol=1e-12)
         assert relerr(to_np(out[True][1][i]), x1) <= 1e-10, i
+
+
+def test_single_vector_batched_tiling_entry():
+    """The k = 1 tiling entry of a batch (rp4d_batch_set_tiling_k) drives the
+    single-vector sweeps and only them: another valid entry gives bitwise the
+    same products, an entry too small for its halo fails the k = 1 product but
+    not a k = 5 one, and kc > 1 is rejected for it."""
+    torch = need_gpu()
+    from paper_2401_15758_amd import rp4d
+    ctx, orcs, probs, trajs = _setup(CFGS)
+    b = rp4d.Batch(ctx, probs)
+    b.fwd([to_dev(o.xb) for o in orcs], trajs, want_J=False)
+    V1 = [to_dev(np.random.default_rng(60 + i).standard_normal((o.n, 1))) for i, o in enumerate(orcs)]
+    V5 = [to_dev(np.random.default_rng(70 + i).standard_normal((o.n, 5))) for i, o in enumerate(orcs)]
+    ref = [h.clone() for h in b.hessian_block(trajs, V1)]
+    for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+        b.set_tiling(mode, k=1, xch=rp4d.XCH_LDS, ppt=1, threads=256, steps=5)
+    out = b.hessian_block(trajs, V1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(out, ref))
+    b.set_tiling(rp4d.MODE_ADJ, k=1, xch=rp4d.XCH_WAVE, ppt=1, threads=64, steps=20)
+    with pytest.raises(rp4d.Rp4dError):
+        b.hessian_block(trajs, V1)
+    b.hessian_block(trajs, V5)
+    with pytest.raises(rp4d.Rp4dError):
+        b.set_tiling(rp4d.MODE_TLM, k=1, kc=2)
+    for mode in (rp4d.MODE_TLM, rp4d.MODE_ADJ):
+        b.set_tiling(mode, k=1)
+    torch.cuda.synchronize()
