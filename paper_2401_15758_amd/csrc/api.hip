@@ -285,26 +285,27 @@ double read_scalar(const rp4d_problem* p, const double* dptr) {
     return v;
 }
 
+// Tiling of a sweep with no tuned one set: wave regions in the shapes the
+// tiling search picked for burgers-4096 -- single vectors 2 points per lane,
+// 13 steps per launch, 16 owned points per 128-point region; blocks 4 points x
+// 2 vectors per lane, 15 steps, 128 owned of 256 -- with the tiles balanced
+// over n (a region may wrap a small ring more than once).
 Tiling heuristic_tiling(int n, int k) {
     Tiling t;
-    t.kc = 1;
-    const int groups = (k + t.kc - 1) / t.kc;
-    const int tmin = std::min(n, 128);
-    int tiles = std::max(1, (512 + groups - 1) / groups);
-    tiles = std::min(tiles, std::max(1, (n + tmin - 1) / tmin));
-    int T = (n + tiles - 1) / tiles;
-    T = std::min(T, 3200);
-    int S = static_cast<int>(std::floor((0.3 * T - 8.0) / 8.0));
-    S = std::max(1, std::min(S, 32));
-    const int R = T + 2 * (4 * S + 4);
-    t.ppt = R > 2048 ? 4 : (R > 512 ? 2 : 1);
-    t.threads = ((R + t.ppt - 1) / t.ppt + 63) / 64 * 64;
-    if (t.threads > 1024) {
+    t.xch = XCH_WAVE;
+    t.threads = 64;
+    if (k == 1) {
+        t.ppt = 2;
+        t.kc = 1;
+        t.steps = 13;
+    } else {
         t.ppt = 4;
-        t.threads = ((R + 3) / 4 + 63) / 64 * 64;
+        t.kc = 2;
+        t.steps = 15;
     }
-    t.tile = T;
-    t.steps = S;
+    const int room = 64 * t.ppt - 2 * (4 * t.steps + 4);
+    const int tiles = std::max(1, (n + room - 1) / room);
+    t.tile = (n + tiles - 1) / tiles;
     return t;
 }
 
@@ -345,6 +346,7 @@ Tiling fwd_tiling(const rp4d_problem* p) {
     Tiling t = p->wall ? wall_tiling(p->n, 1) : heuristic_tiling(p->n, 1);
     // the single nonlinear state: fewer, larger tiles amortise launches better
     if (p->n >= 1024 && !p->wall) {
+        t.xch = XCH_LDS;
         const int tiles = std::max(1, p->n / 512);
         t.tile = (p->n + tiles - 1) / tiles;
         t.steps = std::max(1, std::min(32, static_cast<int>((0.3 * t.tile - 8.0) / 8.0)));
