@@ -18,7 +18,9 @@
 namespace rp4d {
 namespace fftl {
 
-#pragma clang fp contract(off)
+// A multiply-add within one expression may fuse: the 2-D kernels have one
+// arithmetic per operator (no tiling choices), so results stay reproducible.
+#pragma clang fp contract(on)
 
 constexpr int kLines = 8;  // lines (rows or columns) per workgroup, 16 threads each
 
@@ -31,7 +33,7 @@ struct C2 {
 
 template <typename T>
 __device__ __forceinline__ C2<T> cmul(C2<T> a, T wr, T wi) {
-    return C2<T>{a.r * wr - a.i * wi, a.r * wi + a.i * wr};
+    return C2<T>{fma(a.r, wr, -(a.i * wi)), fma(a.r, wi, a.i * wr)};
 }
 
 // In-place forward 4-point DFT of (a, b, c, d) (W4 = -i).
