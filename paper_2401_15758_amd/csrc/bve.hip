@@ -137,12 +137,6 @@ __global__ void bve_to_fields(const T* __restrict__ in, int in_kc, int n, int k,
     out[e] = in[(static_cast<long>(v / in_kc) * n + p) * in_kc + v % in_kc];
 }
 
-template <typename T>
-__global__ void bve_zero(T* x, long count) {
-    const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e < count) x[e] = T(0);
-}
-
 // ---------------------------------------------------------------------------
 // Fused row stages of the linearised sweeps.  One launch per RK stage does the
 // row-local work of the stage -- the inverse row FFTs of the column-passed
@@ -436,8 +430,12 @@ struct AdjRowArgs {
     T cl, ct;
     T* lam;
     T* acc;
-    // observation forcing added to the new lambda (m = 0) or to lam (m = -1):
-    // lam[o] += W[force_it][o] / sigma_o at the observed cells; force_it < 0: none
+    // observation forcing added to the new lambda (m = 0), or (m = -1, the
+    // sweep's first launch, lambda zero before it) lambda set to the forcing
+    // alone: W[force_it][o] / sigma_o at the observed cells, 0 elsewhere;
+    // force_it < 0: none.  With m = -1 the kernel writes lambda on its owned
+    // rows and never reads it: a neighbour's halo would otherwise race with
+    // those writes.
     const T* Wobs;
     int force_it, stride, nox, n_obs;
     T inv_sigma;
@@ -493,7 +491,7 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
     // together, the first chunk's before the inverse row FFTs so that their
     // latency overlaps the transforms
     constexpr int CH = PERH < 8 ? PERH : 8;
-    const bool need_r = a.m >= 0, need_lam = a.m != 0, need_acc = a.m == 0 || a.m == 1 || a.m == 2;
+    const bool need_r = a.m >= 0, need_lam = a.m > 0, need_acc = a.m == 0 || a.m == 1 || a.m == 2;
     auto load_chunk = [&](int t0, T (&rv)[2][CH], T (&lv)[2][CH], T (&av)[2][CH]) {
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -555,12 +553,11 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
                                 mu = a.a3 * l;
                             }
                         } else {
-                            T l = lv[f][u];
-                            if (obs) {
+                            T l = T(0);
+                            if (obs)
                                 l = l + a.Wobs[(static_cast<size_t>(a.force_it) * a.n_obs + o) * a.k + v] *
                                             a.inv_sigma;
-                                if (owned) a.lam[g] = l;
-                            }
+                            if (owned) a.lam[g] = l;
                             mu = a.a3 * l;
                         }
                         mu2[f] = mu;
@@ -603,13 +600,307 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
     rows_forward<T, B, PER>(lds, out, a.znext, p, j0, rown, ny, wl);
 }
 
+// ---------------------------------------------------------------------------
+// The same row stages with one wave per row line, for few field pairs and
+// power-of-two nx from 64 to 256 (latency-bound launches).  A workgroup of L
+// waves owns L - 2 rows; wave w holds line w (row j0 - 1 + w), loads it,
+// transforms it, and on the owned lines runs the stencils and the update on
+// its points i = lane + 64 u.  The line transforms need no workgroup barrier;
+// the rows the stencils read (the twiddles, Y, psi and the inputs staged in
+// LDS, and the neighbours' transformed lines) need one barrier each, and a
+// last one keeps the neighbours' lines until every stencil has read them.
+// ---------------------------------------------------------------------------
+#ifndef RP4D_BVE_WAVE_LINES
+#define RP4D_BVE_WAVE_LINES 4
+#endif
+constexpr int kWaveLines = RP4D_BVE_WAVE_LINES;
+
+template <typename T, int N, int L>
+__global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
+    constexpr int P = N / 64, NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
+    __shared__ fftl::C2<T> lds[L * fftl::padded(N)];
+    __shared__ T stg[4 * SR];
+    __shared__ fftl::C2<T> wl[N];
+    const int tid = threadIdx.x, w = tid >> 6, q = tid & 63;
+    const int p = blockIdx.y, j0 = blockIdx.x * OWN, ny = a.ny;
+    const int rown = min(OWN, ny - j0);
+    const size_t n = static_cast<size_t>(N) * ny;
+    const int nf = 2 * p + 1 < a.k ? 2 : 1;
+    const bool live = w < rown + 2, own = w >= 1 && w <= rown;
+    int jl = j0 - 1 + min(w, rown + 1);
+    jl = jl < 0 ? jl + ny : (jl >= ny ? jl - ny : jl);
+    fftl::C2<T>* line = lds + w * fftl::padded(N);
+    T dzv[2][P], acv[2][P];
+    {  // every global load first, then the LDS stores
+        fftl::C2<T> tw[TW];
+#pragma unroll
+        for (int r = 0; r < TW; ++r) {
+            const int m = min(tid + r * NT, N - 1);
+            tw[r] = fftl::C2<T>{a.W[2 * m], a.W[2 * m + 1]};
+        }
+        fftl::C2<T> zv[P];
+        double yv[P], pv[P];
+        T wv[2][P];
+        const T* zr = a.zc + (static_cast<size_t>(p) * n + static_cast<size_t>(jl) * N) * 2;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            const size_t r = static_cast<size_t>(jl) * N + i;
+            zv[u] = fftl::C2<T>{zr[2 * i], zr[2 * i + 1]};
+            yv[u] = a.Y[r];
+            pv[u] = a.psi[r];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const size_t g = static_cast<size_t>(2 * p + min(f, nf - 1)) * n + r;
+                wv[f][u] = a.w[g];
+                dzv[f][u] = own ? a.dz[g] : T(0);
+                acv[f][u] = own && a.stage > 0 ? a.acc[g] : T(0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TW; ++r) {
+            const int m = tid + r * NT;
+            if (m < N) wl[m] = tw[r];
+        }
+        if (live) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int i = q + 64 * u;
+                line[fftl::padded(i)] = zv[u];
+                stg[w * N + i] = static_cast<T>(yv[u]);
+                stg[SR + w * N + i] = static_cast<T>(pv[u]);
+                stg[2 * SR + w * N + i] = wv[0][u];
+                stg[3 * SR + w * N + i] = wv[1][u];
+            }
+        }
+    }
+    __syncthreads();
+    if (live) fftl::line_fft_wave<T, N>(line, q, wl, true);
+    __syncthreads();
+    const T bst = static_cast<T>(kRkB[a.stage]);
+    T out[2][P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) out[0][u] = out[1][u] = T(0);
+    if (own) {
+        const int jr = w - 1, j = j0 + jr;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            T Yn[3][3], Pn[3][3];
+            st9<T, N>(stg, jr, i, Yn);
+            st9<T, N>(stg + SR, jr, i, Pn);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (f < nf) {
+                    T phn[3][3], wn[3][3];
+                    lds9<T, N>(lds, jr, i, f, phn);
+                    st9<T, N>(stg + (2 + f) * SR, jr, i, wn);
+                    const T kv = -(arakawa12_nb<T>(phn, Yn) * a.inv12d2) - arakawa12_nb<T>(Pn, wn) * a.inv12d2 +
+                                 a.nu_d2 * lap5_nb<T>(wn);
+                    const size_t g = static_cast<size_t>(2 * p + f) * n + static_cast<size_t>(j) * N + i;
+                    const T dv = dzv[f][u];
+                    T o;
+                    if (a.stage == 0) {
+                        a.acc[g] = kv * bst;
+                        o = dv + a.cnext * kv;
+                        a.wnext[g] = o;
+                    } else if (a.stage < 3) {
+                        a.acc[g] = acv[f][u] + kv * bst;
+                        o = dv + a.cnext * kv;
+                        a.wnext[g] = o;
+                    } else {
+                        o = dv + a.h * (acv[f][u] + kv * bst);
+                        a.dz[g] = o;
+                    }
+                    out[f][u] = o;
+                }
+            }
+        }
+    }
+    if (!a.znext) return;  // uniform across the workgroup
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
+        fftl::wave_sync();
+        fftl::line_fft_wave<T, N>(line, q, wl, false);
+        T* zo = a.znext + (static_cast<size_t>(p) * n + static_cast<size_t>(j0 + w - 1) * N) * 2;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            const fftl::C2<T> v = line[fftl::padded(i)];
+            zo[2 * i] = v.r;
+            zo[2 * i + 1] = v.i;
+        }
+    }
+}
+
+template <typename T, int N, int L>
+__global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
+    constexpr int P = N / 64, NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
+    __shared__ fftl::C2<T> lds[L * fftl::padded(N)];
+    __shared__ T stg[2 * SR];
+    __shared__ fftl::C2<T> wl[N];
+    const int tid = threadIdx.x, w = tid >> 6, q = tid & 63;
+    const int p = blockIdx.y, j0 = blockIdx.x * OWN, ny = a.ny;
+    const int rown = min(OWN, ny - j0);
+    const size_t n = static_cast<size_t>(N) * ny;
+    const int nf = 2 * p + 1 < a.k ? 2 : 1;
+    const bool live = w < rown + 2, own = w >= 1 && w <= rown;
+    int jl = j0 - 1 + min(w, rown + 1);
+    jl = jl < 0 ? jl + ny : (jl >= ny ? jl - ny : jl);
+    fftl::C2<T>* line = lds + w * fftl::padded(N);
+    const bool need_r = a.m >= 0, need_lam = a.m > 0, need_acc = a.m == 0 || a.m == 1 || a.m == 2;
+    T rv[2][P], lv[2][P], av[2][P];
+    {  // every global load first, then the LDS stores
+        fftl::C2<T> tw[TW];
+#pragma unroll
+        for (int r = 0; r < TW; ++r) {
+            const int m = min(tid + r * NT, N - 1);
+            tw[r] = fftl::C2<T>{a.W[2 * m], a.W[2 * m + 1]};
+        }
+        fftl::C2<T> zv[P];
+        double yv[P], pv[P];
+        const T* zr = a.zc + (static_cast<size_t>(p) * n + static_cast<size_t>(jl) * N) * 2;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            const size_t r = static_cast<size_t>(jl) * N + i;
+            zv[u] = a.m >= 0 ? fftl::C2<T>{zr[2 * i], zr[2 * i + 1]} : fftl::C2<T>{T(0), T(0)};
+            yv[u] = a.s >= 0 ? a.Y[r] : 0.0;
+            pv[u] = a.s >= 0 ? a.psi[r] : 0.0;
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const size_t g = static_cast<size_t>(2 * p + min(f, nf - 1)) * n + r;
+                rv[f][u] = need_r ? a.r_in[g] : T(0);
+                lv[f][u] = need_lam ? a.lam[g] : T(0);
+                av[f][u] = need_acc ? a.acc[g] : T(0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TW; ++r) {
+            const int m = tid + r * NT;
+            if (m < N) wl[m] = tw[r];
+        }
+        if (live) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int i = q + 64 * u;
+                line[fftl::padded(i)] = zv[u];
+                stg[w * N + i] = static_cast<T>(yv[u]);
+                stg[SR + w * N + i] = static_cast<T>(pv[u]);
+            }
+        }
+    }
+    __syncthreads();
+    // the combine of stage m on the wave's own line (owned rows and the halo)
+    if (live) {
+        if (a.m >= 0) fftl::line_fft_wave<T, N>(line, q, wl, true);
+        const int j = jl;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            const bool obs = a.force_it >= 0 && (j % a.stride) == 0 && (i % a.stride) == 0;
+            const int o = (j / a.stride) * a.nox + i / a.stride;
+            fftl::C2<T>& slot = line[fftl::padded(i)];
+            T mu2[2] = {T(0), T(0)};
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (f < nf) {
+                    const int v = 2 * p + f;
+                    const size_t g = static_cast<size_t>(v) * n + static_cast<size_t>(j) * N + i;
+                    T mu;
+                    if (a.m >= 0) {
+                        const T Pv = f ? slot.i : slot.r;
+                        const T th = -Pv + rv[f][u];
+                        if (a.m == 3) {
+                            const T l = lv[f][u];
+                            if (own) a.acc[g] = l + th;
+                            mu = a.cl * l + a.ct * th;
+                        } else if (a.m > 0) {
+                            if (own) a.acc[g] = av[f][u] + th;
+                            mu = a.cl * lv[f][u] + a.ct * th;
+                        } else {
+                            T l = av[f][u] + th;
+                            if (obs)
+                                l = l + a.Wobs[(static_cast<size_t>(a.force_it) * a.n_obs + o) * a.k + v] * a.inv_sigma;
+                            if (own) a.lam[g] = l;
+                            mu = a.a3 * l;
+                        }
+                    } else {
+                        T l = T(0);
+                        if (obs)
+                            l = l + a.Wobs[(static_cast<size_t>(a.force_it) * a.n_obs + o) * a.k + v] * a.inv_sigma;
+                        if (own) a.lam[g] = l;
+                        mu = a.a3 * l;
+                    }
+                    mu2[f] = mu;
+                }
+            }
+            slot = fftl::C2<T>{mu2[0], mu2[1]};
+        }
+    }
+    if (a.s < 0) return;  // uniform across the workgroup
+    __syncthreads();
+    T out[2][P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) out[0][u] = out[1][u] = T(0);
+    if (own) {
+        const int jr = w - 1, j = j0 + jr;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            T Yn[3][3], Pn[3][3];
+            st9<T, N>(stg, jr, i, Yn);
+            st9<T, N>(stg + SR, jr, i, Pn);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (f < nf) {
+                    T mn[3][3];
+                    lds9<T, N>(lds, jr, i, f, mn);
+                    const size_t g = static_cast<size_t>(2 * p + f) * n + static_cast<size_t>(j) * N + i;
+                    out[f][u] = arakawa12_nb<T>(Yn, mn) * a.inv12d2;
+                    a.r_out[g] = arakawa12_nb<T>(Pn, mn) * a.inv12d2 + a.nu_d2 * lap5_nb<T>(mn);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
+        fftl::wave_sync();
+        fftl::line_fft_wave<T, N>(line, q, wl, false);
+        T* zo = a.znext + (static_cast<size_t>(p) * n + static_cast<size_t>(j0 + w - 1) * N) * 2;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int i = q + 64 * u;
+            const fftl::C2<T> v = line[fftl::padded(i)];
+            zo[2 * i] = v.r;
+            zo[2 * i + 1] = v.i;
+        }
+    }
+}
+
 // Rows staged in LDS while the grid has at most this many field pairs.
 constexpr int kStagePairs = 4;
 
+// Sides with one wave per row line (64 .. 256, powers of 2).
+inline bool wave_rows(int nx) { return nx == 64 || nx == 128 || nx == 256; }
+
 template <typename T>
 void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
-    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     const bool stage = (a.k + 1) / 2 <= kStagePairs;
+    if (stage && wave_rows(nx)) {
+        constexpr int L = kWaveLines;
+        const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
+        if (nx == 64) bve_tlm_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a);
+        if (nx == 128) bve_tlm_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a);
+        if (nx == 256) bve_tlm_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     switch (nx / 16) {
 #define RP4D_TLM_ROWS(b)                                                    \
     case b:                                                                 \
@@ -628,8 +919,17 @@ void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
 
 template <typename T>
 void launch_adj_rows(const AdjRowArgs<T>& a, int nx, hipStream_t st) {
-    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     const bool stage = (a.k + 1) / 2 <= kStagePairs;
+    if (stage && wave_rows(nx)) {
+        constexpr int L = kWaveLines;
+        const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
+        if (nx == 64) bve_adj_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a);
+        if (nx == 128) bve_adj_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a);
+        if (nx == 256) bve_adj_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a);
+        RP4D_HIP(hipGetLastError());
+        return;
+    }
+    const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     switch (nx / 16) {
 #define RP4D_ADJ_ROWS(b)                                                    \
     case b:                                                                 \
@@ -978,9 +1278,9 @@ void adj_sweep(rp4d_problem* p, const rp4d_traj* tr, int k, const T* W, T* lam, 
         a.inv12d2 = inv12d2;
         a.nu_d2 = nu_d2;
     };
-    bve_zero<T><<<ublk(fk), 256, 0, st>>>(lam, static_cast<long>(fk));
     {
-        // the forcing of the last state and the stencil of stage 3 of the last step
+        // lambda set to the forcing of the last state (every point written),
+        // and the stencil of stage 3 of the last step
         AdjRowArgs<T> a{};
         base(a);
         a.m = -1;

@@ -142,6 +142,77 @@ __global__ void __launch_bounds__(16 * kLines) fft_cols(T* __restrict__ z, int n
     }
 }
 
+// The same column pass with one wave per column (few field pairs, power-of-two
+// ny from 64 to 512): L columns per workgroup, loaded and stored row-wise
+// (coalesced) through LDS; wave c transforms column c, scales it by the
+// diagonal and transforms it back with no workgroup barrier in between.
+#ifndef RP4D_COL_WAVE_LINES
+#define RP4D_COL_WAVE_LINES 4
+#endif
+constexpr int kColWaveLines = RP4D_COL_WAVE_LINES;
+
+template <typename T, int N, int L>
+__global__ void __launch_bounds__(64 * L) fft_cols_w(T* __restrict__ z, int nx, const T* __restrict__ D,
+                                                   const T* __restrict__ W) {
+    constexpr int NT = 64 * L, P = N / 64, RW = N * L / NT, TW = (N + NT - 1) / NT;
+    __shared__ C2<T> lds[L * padded(N)];
+    __shared__ C2<T> wl[N];
+    const int tid = threadIdx.x, wv = tid >> 6, q = tid & 63;
+    const int kx0 = blockIdx.x * L, p = blockIdx.y;
+    T* zp = z + static_cast<size_t>(p) * N * nx * 2;
+    // thread tid moves rows jb + 64 r of column kx0 + c (c = tid % L)
+    const int c = tid % L, jb = tid / L;
+    const bool cok = kx0 + c < nx;
+    C2<T> tw[TW];
+#pragma unroll
+    for (int r = 0; r < TW; ++r) {
+        const int m = min(tid + r * NT, N - 1);
+        tw[r] = C2<T>{W[2 * m], W[2 * m + 1]};
+    }
+    C2<T> v[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const T* s = zp + (static_cast<size_t>(jb + 64 * r) * nx + (cok ? kx0 + c : 0)) * 2;
+        v[r] = C2<T>{s[0], s[1]};
+    }
+    const bool active = kx0 + wv < nx;
+    const int kx = active ? kx0 + wv : 0;
+    T d[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) d[u] = D[static_cast<size_t>(q + 64 * u) * nx + kx];
+#pragma unroll
+    for (int r = 0; r < TW; ++r) {
+        const int m = tid + r * NT;
+        if (m < N) wl[m] = tw[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+        if (cok) lds[c * padded(N) + padded(jb + 64 * r)] = v[r];
+    __syncthreads();
+    if (active) {
+        C2<T>* line = lds + wv * padded(N);
+        line_fft_wave<T, N>(line, q, wl, false);
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int ky = q + 64 * u;
+            const C2<T> x = line[padded(ky)];
+            line[padded(ky)] = C2<T>{x.r * d[u], x.i * d[u]};
+        }
+        wave_sync();
+        line_fft_wave<T, N>(line, q, wl, true);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        if (cok) {
+            T* s = zp + (static_cast<size_t>(jb + 64 * r) * nx + kx0 + c) * 2;
+            const C2<T> x = lds[c * padded(N) + padded(jb + 64 * r)];
+            s[0] = x.r;
+            s[1] = x.i;
+        }
+    }
+}
+
 // Rows inverse: z[p] -> fields 2p (real part) and 2p+1 (imaginary part, if any).
 template <typename T, int B>
 __global__ void __launch_bounds__(16 * kLines) fft_rows_inv(const T* __restrict__ z, int k, int ny,
@@ -203,8 +274,21 @@ void launch_rows(bool inverse, const T* in, int k, int nx, int ny, T* z, T* out,
     }
 }
 
+// Column passes with one wave per column while the grid has at most this many
+// field pairs (latency-bound launches).
+constexpr int kWaveColPairs = 4;
+
 template <typename T>
 void launch_cols(T* z, int k, int nx, int ny, const T* D, const T* Wy, hipStream_t st) {
+    if ((k + 1) / 2 <= kWaveColPairs && (ny == 64 || ny == 128 || ny == 256 || ny == 512)) {
+        constexpr int L = kColWaveLines;
+        const dim3 gw((nx + L - 1) / L, (k + 1) / 2), bw(64 * L);
+        if (ny == 64) fft_cols_w<T, 64, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
+        if (ny == 128) fft_cols_w<T, 128, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
+        if (ny == 256) fft_cols_w<T, 256, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
+        if (ny == 512) fft_cols_w<T, 512, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
+        return;
+    }
     const dim3 grid((nx + kLines - 1) / kLines, (k + 1) / 2), blk(16 * kLines);
     switch (ny / 16) {
 #define RP4D_COLS(b) \

@@ -215,5 +215,84 @@ __device__ __forceinline__ void store_twiddles(C2<T>* wl, const C2<T> (&v)[twidd
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Lines transformed by one wave each (64 threads, lane q), for power-of-two N
+// from 64 to 512: self-sorting (Stockham) radix-4 passes, with one radix-2
+// pass last when N is not a power of 4.  The pass that follows sub-transforms
+// of length NS takes, for each butterfly j < N/R, the R values j + r N/R,
+// multiplies value r by W_N^{(j mod NS) r N/(NS R)}, transforms them and writes
+// them to (j div NS) NS R + (j mod NS) + r NS.  The line is transformed in
+// place: the wave reads all of it before it writes any of it, and a wave's LDS
+// operations take effect in program order, so no pass needs a workgroup
+// barrier -- only the compiler must keep the order (wave_sync).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int N, int R, int NS>
+__device__ __forceinline__ void stockham_pass(C2<T>* line, int q, const C2<T>* Wl, bool conj_in, bool conj_out) {
+    constexpr int J = N / R, U = (J + 63) / 64;
+    C2<T> v[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = q + 64 * u;
+        if (J % 64 == 0 || j < J) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const C2<T> x = line[padded(j + r * J)];
+                v[u][r] = C2<T>{x.r, conj_in ? -x.i : x.i};
+            }
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = q + 64 * u;
+        if (J % 64 == 0 || j < J) {
+            const int jm = j & (NS - 1);
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const C2<T> w = Wl[jm * r * (N / (NS * R))];
+                    v[u][r] = cmul(v[u][r], w.r, w.i);
+                }
+            }
+            if constexpr (R == 4) {
+                dft4(v[u][0], v[u][1], v[u][2], v[u][3]);
+            } else {
+                const C2<T> a = v[u][0], b = v[u][1];
+                v[u][0] = C2<T>{a.r + b.r, a.i + b.i};
+                v[u][1] = C2<T>{a.r - b.r, a.i - b.i};
+            }
+            const int base = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                line[padded(base + r * NS)] = C2<T>{v[u][r].r, conj_out ? -v[u][r].i : v[u][r].i};
+        }
+    }
+    wave_sync();
+}
+
+template <typename T, int N, int NS>
+__device__ __forceinline__ void stockham_from(C2<T>* line, int q, const C2<T>* Wl, bool conj) {
+    constexpr int R = (N / NS) % 4 == 0 ? 4 : 2;
+    stockham_pass<T, N, R, NS>(line, q, Wl, NS == 1 && conj, NS * R == N && conj);
+    if constexpr (NS * R < N) stockham_from<T, N, NS * R>(line, q, Wl, conj);
+}
+
+// Transform the line of N complex values at `line` (LDS, padded) in place with
+// the 64 lanes of one wave (q = lane), twiddles Wl (W_N^m, m < N) in LDS;
+// conj = true gives the unnormalised inverse.  Only the line's own wave calls
+// it; it holds no workgroup barrier.
+template <typename T, int N>
+__device__ __forceinline__ void line_fft_wave(C2<T>* line, int q, const C2<T>* Wl, bool conj) {
+    static_assert(N >= 64 && N <= 512 && (N & (N - 1)) == 0, "wave line FFTs take N = 64 .. 512, a power of 2");
+    stockham_from<T, N, 1>(line, q, Wl, conj);
+}
+
 }  // namespace fftl
 }  // namespace rp4d

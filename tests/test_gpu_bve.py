@@ -1,13 +1,14 @@
 """GPU parity of the barotropic-vorticity path (2-D model) with the FP64 oracle:
-the spectral inverse Laplacian and the separable prior square root (dense
-Fourier-basis products on the matrix cores), the RK4 trajectory and cost, the
-TLM / ADJ block sweeps, the block Hessian, the gradient and one Gauss-Newton
-step; sampled checks at the 256 x 256 size; FP32 sweeps; argument errors.
+the spectral inverse Laplacian and the separable prior square root, the RK4
+trajectory and cost, the TLM / ADJ block sweeps (both row-stage layouts: one
+wave per row line for few field pairs on power-of-two sides, sixteen threads
+per line otherwise), the block Hessian, the gradient and one Gauss-Newton step;
+sampled checks at the 256 x 256 size; FP32 sweeps; argument errors.
 
 The oracle computes L with a library FFT and the prior with dense circulant
-matrices, the GPU with the real Fourier basis, so the two share no arithmetic;
-they differ by rounding only (~1e-15 per operator application, ~1e-13 after a
-few hundred RK4 stages)."""
+matrices, the GPU with its own line FFTs, so the two share no arithmetic; they
+differ by rounding only (~1e-15 per operator application, ~1e-13 after a few
+hundred RK4 stages)."""
 import numpy as np
 import pytest
 
@@ -22,6 +23,10 @@ SMALL = inputs.bve_config(32, nsteps=12, obs_stride=8, obs_every=4, L_cells=3.0,
 RAGGED = inputs.bve_config(48, nsteps=9, obs_stride=5, obs_every=4, L_cells=2.5, ell=6, name='bve-48')
 # grid width not a multiple of 64 (the stencils' column strips are 40 wide)
 WIDE = inputs.bve_config(80, nsteps=6, obs_stride=16, obs_every=3, L_cells=3.0, ell=6, name='bve-80')
+# power-of-two sides: with at most four field pairs the row stages run one wave
+# per row line (64 / 128 points per line, 64 rows over 11 blocks of 6: ragged)
+P64 = inputs.bve_config(64, nsteps=6, obs_stride=8, obs_every=3, L_cells=3.0, ell=6, name='bve-64')
+P128 = inputs.bve_config(128, nsteps=4, obs_stride=16, obs_every=2, L_cells=3.0, ell=6, name='bve-128')
 
 
 @pytest.fixture(scope="module")
@@ -86,12 +91,13 @@ def test_fwd_observations_and_cost(cfg):
     assert pr.Jobs == pytest.approx(0.5 * float(np.sum(d * d)), rel=1e-12)
 
 
-@pytest.mark.parametrize("cfg", [SMALL, RAGGED, WIDE], ids=["bve-32", "bve-48-ragged", "bve-80"])
-def test_tlm_adj_hessian_parity(cfg):
+@pytest.mark.parametrize("cfg,k", [(SMALL, 3), (RAGGED, 3), (WIDE, 3), (P64, 3), (P64, 9), (P128, 1)],
+                         ids=["bve-32", "bve-48-ragged", "bve-80", "bve-64-wave-rows", "bve-64-5-pairs",
+                              "bve-128-wave-rows"])
+def test_tlm_adj_hessian_parity(cfg, k):
     need_gpu()
     pr = Pair(cfg, seed=3)
     o, g = pr.orc, pr.gpu
-    k = 3
     V = _rand((o.n, k), 7)
     Z = to_np(g.tlm(pr.traj, to_dev(V)))
     assert colwise_relerr(Z.reshape(-1, k), o.A(pr.otraj, V).reshape(-1, k)) <= TOL_OP
@@ -121,9 +127,10 @@ def test_gradient_parity(small):
     assert relerr(g, gref) <= TOL_OP
 
 
-def test_fp32_sweeps_close_to_oracle(small):
+@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64-wave-rows"])
+def test_fp32_sweeps_close_to_oracle(cfg):
     torch = need_gpu()
-    pr = small
+    pr = Pair(cfg, seed=2)
     V = _rand((pr.orc.n, 4), 11)
     HV = to_np(pr.gpu.hessian_block(pr.traj, to_dev(V, torch.float32)))
     assert colwise_relerr(HV, pr.orc.hessian(pr.otraj, V)) <= 1e-4
@@ -142,13 +149,14 @@ def test_synthesis_parity():
     assert relerr(to_np(y), orc.y) <= 1e-13
 
 
-@pytest.mark.parametrize("method", ["nystrom", "randsvd"])
-def test_gn_step_parity(method):
+@pytest.mark.parametrize("method,cfg", [("nystrom", SMALL), ("randsvd", SMALL), ("nystrom", P64)],
+                         ids=["nystrom-bve-32", "randsvd-bve-32", "nystrom-bve-64-wave-rows"])
+def test_gn_step_parity(method, cfg):
     need_gpu()
     from oracle import gn as ogn
     from paper_2401_15758_amd import rp4d
-    pr = Pair(SMALL, seed=5)
-    ell = SMALL['ell']
+    pr = Pair(cfg, seed=5)
+    ell = cfg['ell']
     Om = inputs.omega(pr.orc.n, ell, seed=1000)
     v1, dv, x1, info = ogn.gn_step(pr.orc, np.zeros(pr.orc.n), method=method, Omega=Om, rtol=1e-12)
     st = pr.gpu.gn_state()
