@@ -601,8 +601,8 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
 }
 
 // ---------------------------------------------------------------------------
-// The same row stages with one wave per row line, for few field pairs and
-// power-of-two nx from 64 to 256 (latency-bound launches).  A workgroup of L
+// The same row stages with one wave per row line, for few field pairs and nx
+// a multiple of 64 the wave line FFTs take (latency-bound launches).  A workgroup of L
 // waves owns L - 2 rows; wave w holds line w (row j0 - 1 + w), loads it,
 // transforms it, and on the owned lines runs the stencils and the update on
 // its points i = lane + 64 u.  The line transforms need no workgroup barrier;
@@ -610,10 +610,10 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
 // LDS, and the neighbours' transformed lines) need one barrier each, and a
 // last one keeps the neighbours' lines until every stencil has read them.
 // ---------------------------------------------------------------------------
-#ifndef RP4D_BVE_WAVE_LINES
-#define RP4D_BVE_WAVE_LINES 4
-#endif
-constexpr int kWaveLines = RP4D_BVE_WAVE_LINES;
+// Lines per row workgroup: 4 (2 owned rows) spread a latency-bound stage over
+// more CUs than 8 lines (6 owned) and ran 30.8 -> 26.3 ms per bve-256 k = 1
+// product; 3 lines were no faster.
+constexpr int kWaveLines = 4;
 
 template <typename T, int N, int L>
 __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
@@ -885,8 +885,10 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
 // Rows staged in LDS while the grid has at most this many field pairs.
 constexpr int kStagePairs = 4;
 
-// Sides with one wave per row line (64 .. 256, powers of 2).
-inline bool wave_rows(int nx) { return nx == 64 || nx == 128 || nx == 256; }
+// Sides with one wave per row line: the multiples of 64 the line FFTs take.
+inline bool wave_rows(int nx) {
+    return nx == 64 || nx == 128 || nx == 192 || nx == 256 || nx == 320 || nx == 384 || nx == 512;
+}
 
 template <typename T>
 void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
@@ -894,9 +896,15 @@ void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
     if (stage && wave_rows(nx)) {
         constexpr int L = kWaveLines;
         const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
-        if (nx == 64) bve_tlm_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a);
-        if (nx == 128) bve_tlm_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a);
-        if (nx == 256) bve_tlm_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a);
+        switch (nx) {
+            case 64: bve_tlm_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a); break;
+            case 128: bve_tlm_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a); break;
+            case 192: bve_tlm_rows_w<T, 192, L><<<gw, bw, 0, st>>>(a); break;
+            case 256: bve_tlm_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a); break;
+            case 320: bve_tlm_rows_w<T, 320, L><<<gw, bw, 0, st>>>(a); break;
+            case 384: bve_tlm_rows_w<T, 384, L><<<gw, bw, 0, st>>>(a); break;
+            default: bve_tlm_rows_w<T, 512, L><<<gw, bw, 0, st>>>(a); break;
+        }
         RP4D_HIP(hipGetLastError());
         return;
     }
@@ -923,9 +931,15 @@ void launch_adj_rows(const AdjRowArgs<T>& a, int nx, hipStream_t st) {
     if (stage && wave_rows(nx)) {
         constexpr int L = kWaveLines;
         const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
-        if (nx == 64) bve_adj_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a);
-        if (nx == 128) bve_adj_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a);
-        if (nx == 256) bve_adj_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a);
+        switch (nx) {
+            case 64: bve_adj_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a); break;
+            case 128: bve_adj_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a); break;
+            case 192: bve_adj_rows_w<T, 192, L><<<gw, bw, 0, st>>>(a); break;
+            case 256: bve_adj_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a); break;
+            case 320: bve_adj_rows_w<T, 320, L><<<gw, bw, 0, st>>>(a); break;
+            case 384: bve_adj_rows_w<T, 384, L><<<gw, bw, 0, st>>>(a); break;
+            default: bve_adj_rows_w<T, 512, L><<<gw, bw, 0, st>>>(a); break;
+        }
         RP4D_HIP(hipGetLastError());
         return;
     }

@@ -142,14 +142,13 @@ __global__ void __launch_bounds__(16 * kLines) fft_cols(T* __restrict__ z, int n
     }
 }
 
-// The same column pass with one wave per column (few field pairs, power-of-two
-// ny from 64 to 512): L columns per workgroup, loaded and stored row-wise
+// The same column pass with one wave per column (few field pairs, ny a
+// multiple of 64 the wave line FFTs take): L columns per workgroup, loaded and stored row-wise
 // (coalesced) through LDS; wave c transforms column c, scales it by the
 // diagonal and transforms it back with no workgroup barrier in between.
-#ifndef RP4D_COL_WAVE_LINES
-#define RP4D_COL_WAVE_LINES 4
-#endif
-constexpr int kColWaveLines = RP4D_COL_WAVE_LINES;
+// Columns per workgroup: 2 (22.2 ms per bve-256 k = 1 product) against 4
+// (22.7 ms) and 8 (25.8 ms).
+constexpr int kColWaveLines = 2;
 
 template <typename T, int N, int L>
 __global__ void __launch_bounds__(64 * L) fft_cols_w(T* __restrict__ z, int nx, const T* __restrict__ D,
@@ -280,14 +279,19 @@ constexpr int kWaveColPairs = 4;
 
 template <typename T>
 void launch_cols(T* z, int k, int nx, int ny, const T* D, const T* Wy, hipStream_t st) {
-    if ((k + 1) / 2 <= kWaveColPairs && (ny == 64 || ny == 128 || ny == 256 || ny == 512)) {
+    if ((k + 1) / 2 <= kWaveColPairs && ny % 64 == 0) {
         constexpr int L = kColWaveLines;
         const dim3 gw((nx + L - 1) / L, (k + 1) / 2), bw(64 * L);
-        if (ny == 64) fft_cols_w<T, 64, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
-        if (ny == 128) fft_cols_w<T, 128, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
-        if (ny == 256) fft_cols_w<T, 256, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
-        if (ny == 512) fft_cols_w<T, 512, L><<<gw, bw, 0, st>>>(z, nx, D, Wy);
-        return;
+        switch (ny) {
+            case 64: fft_cols_w<T, 64, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 128: fft_cols_w<T, 128, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 192: fft_cols_w<T, 192, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 256: fft_cols_w<T, 256, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 320: fft_cols_w<T, 320, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 384: fft_cols_w<T, 384, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            case 512: fft_cols_w<T, 512, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            default: break;
+        }
     }
     const dim3 grid((nx + kLines - 1) / kLines, (k + 1) / 2), blk(16 * kLines);
     switch (ny / 16) {

@@ -217,9 +217,10 @@ __device__ __forceinline__ void store_twiddles(C2<T>* wl, const C2<T> (&v)[twidd
 
 
 // ---------------------------------------------------------------------------
-// Lines transformed by one wave each (64 threads, lane q), for power-of-two N
-// from 64 to 512: self-sorting (Stockham) radix-4 passes, with one radix-2
-// pass last when N is not a power of 4.  The pass that follows sub-transforms
+// Lines transformed by one wave each (64 threads, lane q), for N a multiple
+// of 64 up to 512 whose factors are 2, 3 and 5 (64, 128, 192, 256, 320, 384,
+// 512): self-sorting (Stockham) passes of radix 4 while 4 divides what is
+// left, then one of radix 2, 3 or 5.  The pass that follows sub-transforms
 // of length NS takes, for each butterfly j < N/R, the R values j + r N/R,
 // multiplies value r by W_N^{(j mod NS) r N/(NS R)}, transforms them and writes
 // them to (j div NS) NS R + (j mod NS) + r NS.  The line is transformed in
@@ -253,7 +254,7 @@ __device__ __forceinline__ void stockham_pass(C2<T>* line, int q, const C2<T>* W
     for (int u = 0; u < U; ++u) {
         const int j = q + 64 * u;
         if (J % 64 == 0 || j < J) {
-            const int jm = j & (NS - 1);
+            const int jm = j % NS;
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -263,10 +264,12 @@ __device__ __forceinline__ void stockham_pass(C2<T>* line, int q, const C2<T>* W
             }
             if constexpr (R == 4) {
                 dft4(v[u][0], v[u][1], v[u][2], v[u][3]);
-            } else {
+            } else if constexpr (R == 2) {
                 const C2<T> a = v[u][0], b = v[u][1];
                 v[u][0] = C2<T>{a.r + b.r, a.i + b.i};
                 v[u][1] = C2<T>{a.r - b.r, a.i - b.i};
+            } else {
+                dft_small<T, R>(v[u], Wl, N);  // 3 or 5: the direct sum
             }
             const int base = (j - jm) * R + jm;
 #pragma unroll
@@ -279,18 +282,21 @@ __device__ __forceinline__ void stockham_pass(C2<T>* line, int q, const C2<T>* W
 
 template <typename T, int N, int NS>
 __device__ __forceinline__ void stockham_from(C2<T>* line, int q, const C2<T>* Wl, bool conj) {
-    constexpr int R = (N / NS) % 4 == 0 ? 4 : 2;
+    constexpr int left = N / NS;
+    constexpr int R = left % 4 == 0 ? 4 : (left % 2 == 0 ? 2 : (left % 3 == 0 ? 3 : 5));
+    static_assert(left % R == 0, "wave line FFTs take sides whose factors are 2, 3 and 5");
     stockham_pass<T, N, R, NS>(line, q, Wl, NS == 1 && conj, NS * R == N && conj);
     if constexpr (NS * R < N) stockham_from<T, N, NS * R>(line, q, Wl, conj);
 }
 
 // Transform the line of N complex values at `line` (LDS, padded) in place with
-// the 64 lanes of one wave (q = lane), twiddles Wl (W_N^m, m < N) in LDS;
+// the 64 lanes of one wave (q = lane), twiddles Wl (W_N^m, m < N) in LDS
+// (N = 64, 128, 192, 256, 320, 384 or 512);
 // conj = true gives the unnormalised inverse.  Only the line's own wave calls
 // it; it holds no workgroup barrier.
 template <typename T, int N>
 __device__ __forceinline__ void line_fft_wave(C2<T>* line, int q, const C2<T>* Wl, bool conj) {
-    static_assert(N >= 64 && N <= 512 && (N & (N - 1)) == 0, "wave line FFTs take N = 64 .. 512, a power of 2");
+    static_assert(N >= 64 && N <= 512 && N % 64 == 0, "wave line FFTs take N = 64 .. 512, a multiple of 64");
     stockham_from<T, N, 1>(line, q, Wl, conj);
 }
 

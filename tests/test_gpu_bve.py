@@ -27,6 +27,9 @@ WIDE = inputs.bve_config(80, nsteps=6, obs_stride=16, obs_every=3, L_cells=3.0, 
 # per row line (64 / 128 points per line, 64 rows over 11 blocks of 6: ragged)
 P64 = inputs.bve_config(64, nsteps=6, obs_stride=8, obs_every=3, L_cells=3.0, ell=6, name='bve-64')
 P128 = inputs.bve_config(128, nsteps=4, obs_stride=16, obs_every=2, L_cells=3.0, ell=6, name='bve-128')
+# the other multiples of 64: mixed-radix wave line FFTs (4 x 4 x 4 x 3, x 5, x 2 x 3; 512 = 4^4 x 2)
+P_MIXED = [inputs.bve_config(nx, nsteps=2, obs_stride=16, obs_every=1, L_cells=3.0, ell=6, name=f'bve-{nx}')
+           for nx in (192, 320, 384, 512)]
 
 
 @pytest.fixture(scope="module")
@@ -91,9 +94,10 @@ def test_fwd_observations_and_cost(cfg):
     assert pr.Jobs == pytest.approx(0.5 * float(np.sum(d * d)), rel=1e-12)
 
 
-@pytest.mark.parametrize("cfg,k", [(SMALL, 3), (RAGGED, 3), (WIDE, 3), (P64, 3), (P64, 9), (P128, 1)],
+@pytest.mark.parametrize("cfg,k", [(SMALL, 3), (RAGGED, 3), (WIDE, 3), (P64, 3), (P64, 9), (P128, 1)]
+                         + [(c, 2) for c in P_MIXED],
                          ids=["bve-32", "bve-48-ragged", "bve-80", "bve-64-wave-rows", "bve-64-5-pairs",
-                              "bve-128-wave-rows"])
+                              "bve-128-wave-rows"] + [c["name"] + "-wave-rows" for c in P_MIXED])
 def test_tlm_adj_hessian_parity(cfg, k):
     need_gpu()
     pr = Pair(cfg, seed=3)
