@@ -1424,7 +1424,7 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
     // Cholesky factorisation below
     nystrom_nu_kernel<<<1, 1, 0, st>>>(s.lam, std::sqrt(static_cast<double>(n)) * eps, s.nu);
     RP4D_HIP(hipGetLastError());
-    bool ok = false;
+    bool ok = false, fused = false;
     for (int attempt = 0; attempt <= 3; ++attempt) {
         // shifted sketch Y_nu = Y + nu Omega, core C = Omega^T Y_nu = L L^T (symmetrised)
         launch_relayout<double, double>(s.Yd, 1, s.Y2, 1, n * l, 1, st);
@@ -1432,7 +1432,8 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
         axpy_dev<<<nblk(static_cast<long>(cnt)), 256, 0, st>>>(s.Om, s.nu, s.Y2, cnt);
         RP4D_HIP(hipGetLastError());
         launch_gram<double, double>(s.Om, l, s.Y2, l, n, l, l, s.S2, s.gw, st);
-        launch_chol(s.S2, l, s.info, st);
+        fused = launch_chol_invt(s.S2, l, s.info, s.S4, st);  // S2 = L, and S4 = L^{-T} if fused
+        if (!fused) launch_chol(s.S2, l, s.info, st);
         if (read_info(p, s.info) == 0) {
             ok = true;
             break;
@@ -1444,9 +1445,11 @@ void nystrom_core(rp4d_problem* p, int l, double eps, Scratch& s, rp4d_precond* 
     // B = Y_nu L^{-T} (n x l), B B^T the shifted approximant; B^T B = U Sigma^2 U^T.  Forming B before the
     // Gram keeps the error at eps cond(L) |B|^2 (the Gram of Y between two
     // triangular inverses would square cond(L)).
-    launch_trinv(s.S2, s.S3, l, st);                                  // S3 = L^{-1}
-    transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
-    RP4D_HIP(hipGetLastError());
+    if (!fused) {
+        launch_trinv(s.S2, s.S3, l, st);                                  // S3 = L^{-1}
+        transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
+        RP4D_HIP(hipGetLastError());
+    }
     launch_tsmm<double, double>(s.Y2, l, s.S4, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, s.S1, l, st);  // S1 = B
     if (fast) {
         lmp_factor_fast(p, l, s.S1, s, pc);
@@ -1482,12 +1485,15 @@ int cholqr_pass(rp4d_problem* p, int rows, int l, Scratch& s, double shift, doub
         launch_axpby(s.S4, 1.0, s.S2, 1.0, static_cast<size_t>(l) * l, st);
         sync(p);  // the host staging vector must outlive the copy
     }
-    launch_chol(s.S2, l, s.info, st);
+    const bool fused = launch_chol_invt(s.S2, l, s.info, s.S4, st);  // S2 = L, and S4 = L^{-T} if fused
+    if (!fused) launch_chol(s.S2, l, s.info, st);
     const int info = read_info(p, s.info);
     if (info != 0) return info;
-    launch_trinv(s.S2, s.S3, l, st);
-    transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
-    RP4D_HIP(hipGetLastError());
+    if (!fused) {
+        launch_trinv(s.S2, s.S3, l, st);
+        transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S4, l);  // S4 = L^{-T}
+        RP4D_HIP(hipGetLastError());
+    }
     launch_tsmm<double, double>(s.Yd, l, s.S4, nullptr, rows, l, l, 1.0, nullptr, 0, 0.0, s.Y2, l, st);
     launch_relayout<double, double>(s.Y2, 1, s.Yd, 1, rows * l, 1, st);
     if (Rinv && first) {
@@ -1592,10 +1598,12 @@ void lmp_factor_fast(rp4d_problem* p, int l, const double* Wt, Scratch& s, rp4d_
     launch_gram<double, double>(Wt, l, Wt, l, n, l, l, s.S4, s.gw, st);     // W W^T
     add_identity<<<nblk(l), 256, 0, st>>>(s.S4, l);
     RP4D_HIP(hipGetLastError());
-    launch_chol(s.S4, l, s.info, st);                                        // K
-    launch_trinv(s.S4, s.S3, l, st);                                         // K^{-1}
-    transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S2, l);  // K^{-T}
-    RP4D_HIP(hipGetLastError());
+    if (!launch_chol_invt(s.S4, l, s.info, s.S2, st)) {                       // K, and K^{-T}
+        launch_chol(s.S4, l, s.info, st);
+        launch_trinv(s.S4, s.S3, l, st);                                     // K^{-1}
+        transpose_small<<<nblk(static_cast<long>(l) * l), 256, 0, st>>>(s.S3, s.S2, l);  // K^{-T}
+        RP4D_HIP(hipGetLastError());
+    }
     pc->V.ensure(static_cast<size_t>(n) * l * sizeof(double));
     launch_tsmm<double, double>(Wt, l, s.S2, nullptr, n, l, l, 1.0, nullptr, 0, 0.0, pc->V.as<double>(), l, st);
     pc->Dg.ensure(static_cast<size_t>(l) * sizeof(double));

@@ -143,6 +143,10 @@ void launch_axpby(const double* x, double alpha, double* y, double beta, size_t 
 void launch_chol(double* A, int l, int* info, hipStream_t st);
 // Linv = inverse of lower-triangular L (both l x l row-major).
 void launch_trinv(const double* L, double* Linv, int l, hipStream_t st);
+// The Cholesky factor of A (as launch_chol, in place) and L^{-T} into LinvT in
+// one launch, for l <= 64 (bitwise the results of launch_chol, launch_trinv and
+// a transpose); false (nothing launched) for larger orders.
+bool launch_chol_invt(double* A, int l, int* info, double* LinvT, hipStream_t st);
 // C = op(A) op(B) (l x l row-major each); ta/tb: transpose flags; alpha scaling.
 void launch_small_gemm(const double* A, int ta, const double* B, int tb, double* C, int l, double alpha,
                        hipStream_t st);

@@ -649,6 +649,71 @@ __global__ void __launch_bounds__(64) trinv64_kernel(const double* L, double* X,
     }
 }
 
+// chol64_kernel followed by trinv64_kernel's forward substitution in the same
+// wave: the same operations in the same order, so L (written to A) and L^{-1}
+// are bitwise those of the two kernels, without L's trip through global memory
+// and two launches.  Lane c stores column c of L^{-1} as row c of
+// LinvT = L^{-T}.  After a failed factorisation (info != 0) LinvT is untouched.
+__global__ void __launch_bounds__(64) chol_invt64_kernel(double* A, int l, int* info, double* LinvT) {
+    constexpr int LD = 65;
+    __shared__ double sA[64 * LD];
+    __shared__ double col[64];
+    __shared__ double rd[64];
+    const int i = threadIdx.x;
+    const int li = i < l ? i : l - 1;
+#pragma unroll
+    for (int t = 0; t < 64; ++t) sA[t * LD + i] = A[(t < l ? t : l - 1) * l + li];
+    __syncthreads();
+    double a[64];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) a[c] = (i < l && c < l) ? 0.5 * (sA[i * LD + c] + sA[c * LD + i]) : 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        if (j >= l || bad) continue;  // uniform: l, and the pivot read from one lane
+        const double djj = readlane_f64(a[j], j);
+        if (!(djj > 0.0) || !isfinite(djj)) {
+            bad = j + 1;
+            continue;
+        }
+        const double d = sqrt(djj);
+        const double lij = (i == j) ? d : a[j] / d;
+        a[j] = lij;
+        col[i] = lij;
+        __syncthreads();
+#pragma unroll
+        for (int c = j + 1; c < 64; ++c) a[c] = fma(-lij, col[c], a[c]);
+        __syncthreads();
+    }
+    if (i < l) {
+#pragma unroll
+        for (int c = 0; c < 64; ++c)
+            if (c < l) A[i * l + c] = (c <= i) ? a[c] : 0.0;
+    }
+    if (i == 0) info[0] = bad;
+    if (bad) return;  // uniform
+    // L by rows in LDS (the entries the substitution reads: k < r < l, and the
+    // diagonal), then lane c forms column c of L^{-1} exactly as trinv64_kernel
+#pragma unroll
+    for (int c = 0; c < 64; ++c) sA[i * LD + c] = (c <= i) ? a[c] : 0.0;
+    rd[i] = i < l ? 1.0 / sA[i * LD + i] : 0.0;  // L(i, i), read back: a[] takes no lane-dependent index
+    __syncthreads();
+    double x[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < r; ++k) s4[k & 3] = fma(sA[r * LD + k], x[k], s4[k & 3]);
+        const double sum = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        x[r] = (r == i) ? rd[r] : (r > i ? -sum * rd[r] : 0.0);
+    }
+    if (i < l) {
+#pragma unroll
+        for (int r = 0; r < 64; ++r)
+            if (r < l) LinvT[i * l + r] = x[r];
+    }
+}
+
 // X = L^{-1} with L and X both in LDS: thread c forms column c by forward
 // substitution (orders with 2 l^2 doubles within the LDS budget).
 __global__ void __launch_bounds__(256) trinv_lds_kernel(const double* L, double* X, int l) {
@@ -1190,6 +1255,13 @@ void launch_chol(double* A, int l, int* info, hipStream_t st) {
     }
     chol_kernel<<<1, 1024, shmem, st>>>(A, l, info);
     RP4D_HIP(hipGetLastError());
+}
+
+bool launch_chol_invt(double* A, int l, int* info, double* LinvT, hipStream_t st) {
+    if (l < 1 || l > 64) return false;
+    chol_invt64_kernel<<<1, 64, 0, st>>>(A, l, info, LinvT);
+    RP4D_HIP(hipGetLastError());
+    return true;
 }
 
 void launch_trinv(const double* L, double* Linv, int l, hipStream_t st) {
