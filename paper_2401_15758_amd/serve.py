@@ -398,6 +398,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--sketch", choices=["f32", "f64", "both"], default="both",
                     help="sketch sweeps of the served path: FP32 (the mixed-precision form), FP64, or both")
+    ap.add_argument("--bve-lanes", type=int, default=2, help="2-D requests served concurrently (own stream each)")
+    ap.add_argument("--no-sequential", action="store_true", help="skip the one-request-at-a-time comparison")
     args = ap.parse_args()
     from . import rp4d
     kw = dict(bve_nx=tuple(args.bve_nx), bve_N=tuple(args.bve_steps))
@@ -408,7 +410,8 @@ def main():
     def note(msg):
         print(f"serve: {msg}", file=sys.stderr, flush=True)
     if rate <= 0:
-        cap = serve(make_trace(args.requests, 0.0, seed=args.seed, **kw), budget_bytes=budget, verbose=True)
+        cap = serve(make_trace(args.requests, 0.0, seed=args.seed, **kw), budget_bytes=budget, bve_lanes=args.bve_lanes,
+                    verbose=True)
         out["capacity_solves_per_s"] = summary(cap)["solves_per_s"]
         rate = 0.7 * out["capacity_solves_per_s"]
         note(f"capacity {out['capacity_solves_per_s']:.3f} solves/s")
@@ -418,13 +421,16 @@ def main():
     chosen = {"f32": ("served_mixed",), "f64": ("served_fp64",), "both": ("served_mixed", "served_fp64")}[args.sketch]
     for name, dt in (("served_mixed", rp4d.F32), ("served_fp64", rp4d.F64)):
         if name in chosen:
-            runs[name] = serve(clone_trace(trace), budget_bytes=budget, sketch_dtype=dt, verbose=True)
+            runs[name] = serve(clone_trace(trace), budget_bytes=budget, sketch_dtype=dt, bve_lanes=args.bve_lanes,
+                               verbose=True)
             out[name] = summary(runs[name])
             note(f"{name} done")
-    seq = serve_sequential(clone_trace(trace), verbose=True)
-    out["sequential_fp64"] = summary(seq)
-    for name, run in runs.items():
-        out[name]["vs_sequential"] = compare(run, seq)
+    out["bve_lanes"] = args.bve_lanes
+    if not args.no_sequential:
+        seq = serve_sequential(clone_trace(trace), verbose=True)
+        out["sequential_fp64"] = summary(seq)
+        for name, run in runs.items():
+            out[name]["vs_sequential"] = compare(run, seq)
     print(json.dumps(out))
 
 
