@@ -112,6 +112,23 @@ def test_tlm_adj_hessian_parity(cfg, k):
     assert colwise_relerr(HV, o.hessian(pr.otraj, V)) <= TOL_OP
 
 
+@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64-wave-rows"])
+def test_adjoint_ignores_stale_workspace(cfg):
+    """The adjoint sweep's first launch sets lambda on every point and reads none
+    of it (a neighbour's halo would race with those writes), so nothing clears
+    lambda first: an adjoint run after another one, whose lambda is still in the
+    workspace, equals the same run on a fresh problem bit for bit."""
+    need_gpu()
+    pr, fresh = Pair(cfg, seed=4), Pair(cfg, seed=4)
+    shape = (pr.orc.n_t, pr.orc.n_obs, 2)
+    _ = to_np(pr.gpu.adj(pr.traj, to_dev(_rand(shape, 20))))
+    W = _rand(shape, 21)
+    again = to_np(pr.gpu.adj(pr.traj, to_dev(W)))
+    first = to_np(fresh.gpu.adj(fresh.traj, to_dev(W)))
+    assert np.array_equal(again, first)
+    assert colwise_relerr(again, pr.orc.AT(pr.otraj, W)) <= TOL_OP
+
+
 def test_dot_product_identity(small):
     """<A v, w> = <v, A^T w> on the GPU alone (FP64)."""
     pr = small
