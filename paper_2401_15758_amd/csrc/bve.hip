@@ -192,31 +192,8 @@ __device__ __forceinline__ void lds9(const fftl::C2<T>* lds, int jr, int i, int 
         }
 }
 
-// Rows j0-1 .. j0+rown (periodic) of an n-point field, staged in LDS row r at
-// dst + r N: stage_load issues a thread's loads (coalesced along the rows),
-// stage_store writes them, so that a kernel can issue every load first.
-template <typename S, int N>
-__device__ __forceinline__ void stage_load(const S* __restrict__ f, int j0, int rown, int ny, S (&v)[N / 16]) {
-#pragma unroll
-    for (int r = 0; r < N / 16; ++r) {
-        const int e = threadIdx.x + r * 16 * fftl::kLines;
-        const int lr = e / N, i = e - lr * N;
-        int j = j0 - 1 + min(lr, rown + 1);
-        j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
-        v[r] = f[static_cast<size_t>(j) * N + i];
-    }
-}
-
-template <typename T, typename S, int N>
-__device__ __forceinline__ void stage_store(T* dst, const S (&v)[N / 16], int rown) {
-#pragma unroll
-    for (int r = 0; r < N / 16; ++r) {
-        const int e = threadIdx.x + r * 16 * fftl::kLines;
-        if (e < (rown + 2) * N) dst[e] = static_cast<T>(v[r]);
-    }
-}
-
-// 3 x 3 neighbourhood of (owned row jr, column i) from rows staged by stage_rows.
+// 3 x 3 neighbourhood of (owned row jr, column i) from rows staged in LDS, row r
+// at rows + r N.
 template <typename T, int N>
 __device__ __forceinline__ void st9(const T* rows, int jr, int i, T (&o)[3][3]) {
     const int c[3] = {i == 0 ? N - 1 : i - 1, i, i + 1 == N ? 0 : i + 1};
@@ -312,17 +289,14 @@ struct TlmRowArgs {
 
 // TLM stage (grid: row blocks x pairs): kv = -J_A(L w, Y) - J_A(psi, w) + nu lap w
 // on the owned rows of both fields of the pair, the RK update, and the row
-// spectra of the next stage input.
-// STAGE: the rows of Y, psi and w the stencils read are staged in LDS with
-// coalesced loads first (few pairs: latency-bound launches); otherwise each
-// point loads its neighbourhoods itself (many pairs: more workgroups per CU).
-template <typename T, int B, bool STAGE>
+// spectra of the next stage input.  For many pairs (few pairs take the wave
+// layout below): each point loads its stencil neighbourhoods itself, which
+// keeps LDS small and more workgroups per CU.
+template <typename T, int B>
 __global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> a) {
     constexpr int N = 16 * B;
     constexpr int PER = (kRowsOwn * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
-    constexpr int SR = fftl::kLines * N;  // one staged field
     __shared__ fftl::C2<T> lds[fftl::kLines * fftl::padded(N)];
-    __shared__ T stg[STAGE ? 4 * SR : 1];
     __shared__ fftl::C2<T> wl[N];
     const int tid = threadIdx.x;
     const int p = blockIdx.y, j0 = blockIdx.x * kRowsOwn, ny = a.ny;
@@ -334,19 +308,6 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> 
         fftl::load_twiddles<T, N>(a.W, tw);
         fftl::C2<T> zv[B];
         rows_spec_load<T, B>(a.zc, p, j0, rown, ny, zv);
-        if constexpr (STAGE) {
-            double yv[B], pv[B];
-            T wv[2][B];
-            stage_load<double, N>(a.Y, j0, rown, ny, yv);
-            stage_load<double, N>(a.psi, j0, rown, ny, pv);
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-                stage_load<T, N>(a.w + static_cast<size_t>(2 * p + min(f, nf - 1)) * n, j0, rown, ny, wv[f]);
-            stage_store<T, double, N>(stg, yv, rown);
-            stage_store<T, double, N>(stg + SR, pv, rown);
-#pragma unroll
-            for (int f = 0; f < 2; ++f) stage_store<T, T, N>(stg + (2 + f) * SR, wv[f], rown);
-        }
         fftl::store_twiddles<T, N>(wl, tw);
         rows_spec_store<T, B>(lds, rown, zv);
     }
@@ -376,23 +337,15 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_tlm_rows(TlmRowArgs<T> 
         if (e < rown * N) {
             const int jr = e / N, i = e - jr * N, j = j0 + jr;
             T Yn[3][3], Pn[3][3];
-            if constexpr (STAGE) {
-                st9<T, N>(stg, jr, i, Yn);
-                st9<T, N>(stg + SR, jr, i, Pn);
-            } else {
-                load9<T, double>(a.Y, N, ny, j, i, Yn);
-                load9<T, double>(a.psi, N, ny, j, i, Pn);
-            }
+            load9<T, double>(a.Y, N, ny, j, i, Yn);
+            load9<T, double>(a.psi, N, ny, j, i, Pn);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 if (f < nf) {
                     const size_t off = static_cast<size_t>(2 * p + f) * n;
                     T phn[3][3], wn[3][3];
                     lds9<T, N>(lds, jr, i, f, phn);
-                    if constexpr (STAGE)
-                        st9<T, N>(stg + (2 + f) * SR, jr, i, wn);
-                    else
-                        load9<T, T>(a.w + off, N, ny, j, i, wn);
+                    load9<T, T>(a.w + off, N, ny, j, i, wn);
                     const T kv = -(arakawa12_nb<T>(phn, Yn) * a.inv12d2) - arakawa12_nb<T>(Pn, wn) * a.inv12d2 +
                                  a.nu_d2 * lap5_nb<T>(wn);
                     const size_t g = off + static_cast<size_t>(j) * N + i;
@@ -455,14 +408,12 @@ struct AdjRowArgs {
 // ADJ row stage (grid: row blocks x pairs): the combine of one stage and the
 // stencil of the next, with the combine recomputed on the halo rows so that
 // the stencil has its neighbours without another launch.
-template <typename T, int B, bool STAGE>
+template <typename T, int B>
 __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> a) {
     constexpr int N = 16 * B;
     constexpr int PER = (kRowsOwn * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
     constexpr int PERH = (fftl::kLines * N + 16 * fftl::kLines - 1) / (16 * fftl::kLines);
-    constexpr int SR = fftl::kLines * N;
     __shared__ fftl::C2<T> lds[fftl::kLines * fftl::padded(N)];
-    __shared__ T stg[STAGE ? 2 * SR : 1];
     __shared__ fftl::C2<T> wl[N];
     const int tid = threadIdx.x;
     const int p = blockIdx.y, j0 = blockIdx.x * kRowsOwn, ny = a.ny;
@@ -474,15 +425,6 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
         fftl::load_twiddles<T, N>(a.W, tw);
         fftl::C2<T> zv[B];
         if (a.m >= 0) rows_spec_load<T, B>(a.zc, p, j0, rown, ny, zv);
-        if constexpr (STAGE) {
-            if (a.s >= 0) {
-                double yv[B], pv[B];
-                stage_load<double, N>(a.Y, j0, rown, ny, yv);
-                stage_load<double, N>(a.psi, j0, rown, ny, pv);
-                stage_store<T, double, N>(stg, yv, rown);
-                stage_store<T, double, N>(stg + SR, pv, rown);
-            }
-        }
         fftl::store_twiddles<T, N>(wl, tw);
         if (a.m >= 0) rows_spec_store<T, B>(lds, rown, zv);
     }
@@ -578,13 +520,8 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
         if (e < rown * N) {
             const int jr = e / N, i = e - jr * N, j = j0 + jr;
             T Yn[3][3], Pn[3][3];
-            if constexpr (STAGE) {
-                st9<T, N>(stg, jr, i, Yn);
-                st9<T, N>(stg + SR, jr, i, Pn);
-            } else {
-                load9<T, double>(a.Y, N, ny, j, i, Yn);
-                load9<T, double>(a.psi, N, ny, j, i, Pn);
-            }
+            load9<T, double>(a.Y, N, ny, j, i, Yn);
+            load9<T, double>(a.psi, N, ny, j, i, Pn);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 if (f < nf) {
@@ -601,11 +538,11 @@ __global__ void __launch_bounds__(16 * fftl::kLines) bve_adj_rows(AdjRowArgs<T> 
 }
 
 // ---------------------------------------------------------------------------
-// The same row stages with one wave per row line, for few field pairs and nx
-// a multiple of 64 the wave line FFTs take (latency-bound launches).  A workgroup of L
+// The same row stages with one wave per row line, for few field pairs
+// (latency-bound launches), on every supported side.  A workgroup of L
 // waves owns L - 2 rows; wave w holds line w (row j0 - 1 + w), loads it,
 // transforms it, and on the owned lines runs the stencils and the update on
-// its points i = lane + 64 u.  The line transforms need no workgroup barrier;
+// its points i = lane + 64 u (ragged past N when 64 does not divide N).  The line transforms need no workgroup barrier;
 // the rows the stencils read (the twiddles, Y, psi and the inputs staged in
 // LDS, and the neighbours' transformed lines) need one barrier each, and a
 // last one keeps the neighbours' lines until every stencil has read them.
@@ -617,7 +554,7 @@ constexpr int kWaveLines = 4;
 
 template <typename T, int N, int L>
 __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
-    constexpr int P = N / 64, NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
+    constexpr int P = fftl::wave_points<N>(), NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
     __shared__ fftl::C2<T> lds[L * fftl::padded(N)];
     __shared__ T stg[4 * SR];
     __shared__ fftl::C2<T> wl[N];
@@ -644,7 +581,7 @@ __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
         const T* zr = a.zc + (static_cast<size_t>(p) * n + static_cast<size_t>(jl) * N) * 2;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
-            const int i = q + 64 * u;
+            const int i = fftl::wave_point<N>(q, u);
             const size_t r = static_cast<size_t>(jl) * N + i;
             zv[u] = fftl::C2<T>{zr[2 * i], zr[2 * i + 1]};
             yv[u] = a.Y[r];
@@ -665,6 +602,7 @@ __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
         if (live) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
+                if (!fftl::wave_has<N>(q, u)) continue;
                 const int i = q + 64 * u;
                 line[fftl::padded(i)] = zv[u];
                 stg[w * N + i] = static_cast<T>(yv[u]);
@@ -685,6 +623,7 @@ __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
         const int jr = w - 1, j = j0 + jr;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!fftl::wave_has<N>(q, u)) continue;
             const int i = q + 64 * u;
             T Yn[3][3], Pn[3][3];
             st9<T, N>(stg, jr, i, Yn);
@@ -721,12 +660,14 @@ __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
     __syncthreads();
     if (own) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
+        for (int u = 0; u < P; ++u)
+            if (fftl::wave_has<N>(q, u)) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
         fftl::wave_sync();
         fftl::line_fft_wave<T, N>(line, q, wl, false);
         T* zo = a.znext + (static_cast<size_t>(p) * n + static_cast<size_t>(j0 + w - 1) * N) * 2;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!fftl::wave_has<N>(q, u)) continue;
             const int i = q + 64 * u;
             const fftl::C2<T> v = line[fftl::padded(i)];
             zo[2 * i] = v.r;
@@ -737,7 +678,7 @@ __global__ void __launch_bounds__(64 * L) bve_tlm_rows_w(TlmRowArgs<T> a) {
 
 template <typename T, int N, int L>
 __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
-    constexpr int P = N / 64, NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
+    constexpr int P = fftl::wave_points<N>(), NT = 64 * L, OWN = L - 2, TW = (N + NT - 1) / NT, SR = L * N;
     __shared__ fftl::C2<T> lds[L * fftl::padded(N)];
     __shared__ T stg[2 * SR];
     __shared__ fftl::C2<T> wl[N];
@@ -764,7 +705,7 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
         const T* zr = a.zc + (static_cast<size_t>(p) * n + static_cast<size_t>(jl) * N) * 2;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
-            const int i = q + 64 * u;
+            const int i = fftl::wave_point<N>(q, u);
             const size_t r = static_cast<size_t>(jl) * N + i;
             zv[u] = a.m >= 0 ? fftl::C2<T>{zr[2 * i], zr[2 * i + 1]} : fftl::C2<T>{T(0), T(0)};
             yv[u] = a.s >= 0 ? a.Y[r] : 0.0;
@@ -785,6 +726,7 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
         if (live) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
+                if (!fftl::wave_has<N>(q, u)) continue;
                 const int i = q + 64 * u;
                 line[fftl::padded(i)] = zv[u];
                 stg[w * N + i] = static_cast<T>(yv[u]);
@@ -799,6 +741,7 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
         const int j = jl;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!fftl::wave_has<N>(q, u)) continue;
             const int i = q + 64 * u;
             const bool obs = a.force_it >= 0 && (j % a.stride) == 0 && (i % a.stride) == 0;
             const int o = (j / a.stride) * a.nox + i / a.stride;
@@ -849,6 +792,7 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
         const int jr = w - 1, j = j0 + jr;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!fftl::wave_has<N>(q, u)) continue;
             const int i = q + 64 * u;
             T Yn[3][3], Pn[3][3];
             st9<T, N>(stg, jr, i, Yn);
@@ -868,12 +812,14 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
     __syncthreads();
     if (own) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
+        for (int u = 0; u < P; ++u)
+            if (fftl::wave_has<N>(q, u)) line[fftl::padded(q + 64 * u)] = fftl::C2<T>{out[0][u], out[1][u]};
         fftl::wave_sync();
         fftl::line_fft_wave<T, N>(line, q, wl, false);
         T* zo = a.znext + (static_cast<size_t>(p) * n + static_cast<size_t>(j0 + w - 1) * N) * 2;
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!fftl::wave_has<N>(q, u)) continue;
             const int i = q + 64 * u;
             const fftl::C2<T> v = line[fftl::padded(i)];
             zo[2 * i] = v.r;
@@ -882,41 +828,33 @@ __global__ void __launch_bounds__(64 * L) bve_adj_rows_w(AdjRowArgs<T> a) {
     }
 }
 
-// Rows staged in LDS while the grid has at most this many field pairs.
+// Row stages with one wave per line while the grid has at most this many field
+// pairs; sixteen threads per line beyond.
 constexpr int kStagePairs = 4;
 
-// Sides with one wave per row line: the multiples of 64 the line FFTs take.
-inline bool wave_rows(int nx) {
-    return nx == 64 || nx == 128 || nx == 192 || nx == 256 || nx == 320 || nx == 384 || nx == 512;
-}
 
 template <typename T>
 void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
     const bool stage = (a.k + 1) / 2 <= kStagePairs;
-    if (stage && wave_rows(nx)) {
+    if (stage) {
         constexpr int L = kWaveLines;
         const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
-        switch (nx) {
-            case 64: bve_tlm_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a); break;
-            case 128: bve_tlm_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a); break;
-            case 192: bve_tlm_rows_w<T, 192, L><<<gw, bw, 0, st>>>(a); break;
-            case 256: bve_tlm_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a); break;
-            case 320: bve_tlm_rows_w<T, 320, L><<<gw, bw, 0, st>>>(a); break;
-            case 384: bve_tlm_rows_w<T, 384, L><<<gw, bw, 0, st>>>(a); break;
-            default: bve_tlm_rows_w<T, 512, L><<<gw, bw, 0, st>>>(a); break;
+        switch (nx / 16) {
+#define RP4D_WAVE_ROWS(b) \
+    case b: bve_tlm_rows_w<T, 16 * b, L><<<gw, bw, 0, st>>>(a); break;
+            RP4D_WAVE_ROWS(2) RP4D_WAVE_ROWS(3) RP4D_WAVE_ROWS(4) RP4D_WAVE_ROWS(5) RP4D_WAVE_ROWS(6)
+            RP4D_WAVE_ROWS(8) RP4D_WAVE_ROWS(10) RP4D_WAVE_ROWS(12) RP4D_WAVE_ROWS(16) RP4D_WAVE_ROWS(20)
+            RP4D_WAVE_ROWS(24) RP4D_WAVE_ROWS(32)
+#undef RP4D_WAVE_ROWS
+            default: fail(RP4D_EINVAL, "2-D grid: unsupported nx");
         }
         RP4D_HIP(hipGetLastError());
         return;
     }
     const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     switch (nx / 16) {
-#define RP4D_TLM_ROWS(b)                                                    \
-    case b:                                                                 \
-        if (stage && b <= 16)                                               \
-            bve_tlm_rows<T, b, (b <= 16)><<<grid, blk, 0, st>>>(a);          \
-        else                                                                \
-            bve_tlm_rows<T, b, false><<<grid, blk, 0, st>>>(a);              \
-        break;
+#define RP4D_TLM_ROWS(b) \
+    case b: bve_tlm_rows<T, b><<<grid, blk, 0, st>>>(a); break;
         RP4D_TLM_ROWS(2) RP4D_TLM_ROWS(3) RP4D_TLM_ROWS(4) RP4D_TLM_ROWS(5) RP4D_TLM_ROWS(6) RP4D_TLM_ROWS(8)
         RP4D_TLM_ROWS(10) RP4D_TLM_ROWS(12) RP4D_TLM_ROWS(16) RP4D_TLM_ROWS(20) RP4D_TLM_ROWS(24) RP4D_TLM_ROWS(32)
 #undef RP4D_TLM_ROWS
@@ -928,30 +866,25 @@ void launch_tlm_rows(const TlmRowArgs<T>& a, int nx, hipStream_t st) {
 template <typename T>
 void launch_adj_rows(const AdjRowArgs<T>& a, int nx, hipStream_t st) {
     const bool stage = (a.k + 1) / 2 <= kStagePairs;
-    if (stage && wave_rows(nx)) {
+    if (stage) {
         constexpr int L = kWaveLines;
         const dim3 gw((a.ny + L - 3) / (L - 2), (a.k + 1) / 2), bw(64 * L);
-        switch (nx) {
-            case 64: bve_adj_rows_w<T, 64, L><<<gw, bw, 0, st>>>(a); break;
-            case 128: bve_adj_rows_w<T, 128, L><<<gw, bw, 0, st>>>(a); break;
-            case 192: bve_adj_rows_w<T, 192, L><<<gw, bw, 0, st>>>(a); break;
-            case 256: bve_adj_rows_w<T, 256, L><<<gw, bw, 0, st>>>(a); break;
-            case 320: bve_adj_rows_w<T, 320, L><<<gw, bw, 0, st>>>(a); break;
-            case 384: bve_adj_rows_w<T, 384, L><<<gw, bw, 0, st>>>(a); break;
-            default: bve_adj_rows_w<T, 512, L><<<gw, bw, 0, st>>>(a); break;
+        switch (nx / 16) {
+#define RP4D_WAVE_ROWS(b) \
+    case b: bve_adj_rows_w<T, 16 * b, L><<<gw, bw, 0, st>>>(a); break;
+            RP4D_WAVE_ROWS(2) RP4D_WAVE_ROWS(3) RP4D_WAVE_ROWS(4) RP4D_WAVE_ROWS(5) RP4D_WAVE_ROWS(6)
+            RP4D_WAVE_ROWS(8) RP4D_WAVE_ROWS(10) RP4D_WAVE_ROWS(12) RP4D_WAVE_ROWS(16) RP4D_WAVE_ROWS(20)
+            RP4D_WAVE_ROWS(24) RP4D_WAVE_ROWS(32)
+#undef RP4D_WAVE_ROWS
+            default: fail(RP4D_EINVAL, "2-D grid: unsupported nx");
         }
         RP4D_HIP(hipGetLastError());
         return;
     }
     const dim3 grid((a.ny + kRowsOwn - 1) / kRowsOwn, (a.k + 1) / 2), blk(16 * fftl::kLines);
     switch (nx / 16) {
-#define RP4D_ADJ_ROWS(b)                                                    \
-    case b:                                                                 \
-        if (stage && b <= 16)                                               \
-            bve_adj_rows<T, b, (b <= 16)><<<grid, blk, 0, st>>>(a);          \
-        else                                                                \
-            bve_adj_rows<T, b, false><<<grid, blk, 0, st>>>(a);              \
-        break;
+#define RP4D_ADJ_ROWS(b) \
+    case b: bve_adj_rows<T, b><<<grid, blk, 0, st>>>(a); break;
         RP4D_ADJ_ROWS(2) RP4D_ADJ_ROWS(3) RP4D_ADJ_ROWS(4) RP4D_ADJ_ROWS(5) RP4D_ADJ_ROWS(6) RP4D_ADJ_ROWS(8)
         RP4D_ADJ_ROWS(10) RP4D_ADJ_ROWS(12) RP4D_ADJ_ROWS(16) RP4D_ADJ_ROWS(20) RP4D_ADJ_ROWS(24) RP4D_ADJ_ROWS(32)
 #undef RP4D_ADJ_ROWS

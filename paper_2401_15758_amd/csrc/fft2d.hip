@@ -142,8 +142,8 @@ __global__ void __launch_bounds__(16 * kLines) fft_cols(T* __restrict__ z, int n
     }
 }
 
-// The same column pass with one wave per column (few field pairs, ny a
-// multiple of 64 the wave line FFTs take): L columns per workgroup, loaded and stored row-wise
+// The same column pass with one wave per column (few field pairs, every
+// supported ny): L columns per workgroup, loaded and stored row-wise
 // (coalesced) through LDS; wave c transforms column c, scales it by the
 // diagonal and transforms it back with no workgroup barrier in between.
 // Columns per workgroup: 2 (22.2 ms per bve-256 k = 1 product) against 4
@@ -153,13 +153,13 @@ constexpr int kColWaveLines = 2;
 template <typename T, int N, int L>
 __global__ void __launch_bounds__(64 * L) fft_cols_w(T* __restrict__ z, int nx, const T* __restrict__ D,
                                                    const T* __restrict__ W) {
-    constexpr int NT = 64 * L, P = N / 64, RW = N * L / NT, TW = (N + NT - 1) / NT;
+    constexpr int NT = 64 * L, P = wave_points<N>(), TW = (N + NT - 1) / NT;
     __shared__ C2<T> lds[L * padded(N)];
     __shared__ C2<T> wl[N];
     const int tid = threadIdx.x, wv = tid >> 6, q = tid & 63;
     const int kx0 = blockIdx.x * L, p = blockIdx.y;
     T* zp = z + static_cast<size_t>(p) * N * nx * 2;
-    // thread tid moves rows jb + 64 r of column kx0 + c (c = tid % L)
+    // thread tid moves rows jb + 64 r < N of column kx0 + c (c = tid % L)
     const int c = tid % L, jb = tid / L;
     const bool cok = kx0 + c < nx;
     C2<T> tw[TW];
@@ -168,31 +168,32 @@ __global__ void __launch_bounds__(64 * L) fft_cols_w(T* __restrict__ z, int nx, 
         const int m = min(tid + r * NT, N - 1);
         tw[r] = C2<T>{W[2 * m], W[2 * m + 1]};
     }
-    C2<T> v[RW];
+    C2<T> v[P];
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const T* s = zp + (static_cast<size_t>(jb + 64 * r) * nx + (cok ? kx0 + c : 0)) * 2;
+    for (int r = 0; r < P; ++r) {
+        const T* s = zp + (static_cast<size_t>(wave_point<N>(jb, r)) * nx + (cok ? kx0 + c : 0)) * 2;
         v[r] = C2<T>{s[0], s[1]};
     }
     const bool active = kx0 + wv < nx;
     const int kx = active ? kx0 + wv : 0;
     T d[P];
 #pragma unroll
-    for (int u = 0; u < P; ++u) d[u] = D[static_cast<size_t>(q + 64 * u) * nx + kx];
+    for (int u = 0; u < P; ++u) d[u] = D[static_cast<size_t>(wave_point<N>(q, u)) * nx + kx];
 #pragma unroll
     for (int r = 0; r < TW; ++r) {
         const int m = tid + r * NT;
         if (m < N) wl[m] = tw[r];
     }
 #pragma unroll
-    for (int r = 0; r < RW; ++r)
-        if (cok) lds[c * padded(N) + padded(jb + 64 * r)] = v[r];
+    for (int r = 0; r < P; ++r)
+        if (cok && wave_has<N>(jb, r)) lds[c * padded(N) + padded(jb + 64 * r)] = v[r];
     __syncthreads();
     if (active) {
         C2<T>* line = lds + wv * padded(N);
         line_fft_wave<T, N>(line, q, wl, false);
 #pragma unroll
         for (int u = 0; u < P; ++u) {
+            if (!wave_has<N>(q, u)) continue;
             const int ky = q + 64 * u;
             const C2<T> x = line[padded(ky)];
             line[padded(ky)] = C2<T>{x.r * d[u], x.i * d[u]};
@@ -202,8 +203,8 @@ __global__ void __launch_bounds__(64 * L) fft_cols_w(T* __restrict__ z, int nx, 
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        if (cok) {
+    for (int r = 0; r < P; ++r) {
+        if (cok && wave_has<N>(jb, r)) {
             T* s = zp + (static_cast<size_t>(jb + 64 * r) * nx + kx0 + c) * 2;
             const C2<T> x = lds[c * padded(N) + padded(jb + 64 * r)];
             s[0] = x.r;
@@ -279,18 +280,15 @@ constexpr int kWaveColPairs = 4;
 
 template <typename T>
 void launch_cols(T* z, int k, int nx, int ny, const T* D, const T* Wy, hipStream_t st) {
-    if ((k + 1) / 2 <= kWaveColPairs && ny % 64 == 0) {
+    if ((k + 1) / 2 <= kWaveColPairs) {
         constexpr int L = kColWaveLines;
         const dim3 gw((nx + L - 1) / L, (k + 1) / 2), bw(64 * L);
-        switch (ny) {
-            case 64: fft_cols_w<T, 64, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 128: fft_cols_w<T, 128, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 192: fft_cols_w<T, 192, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 256: fft_cols_w<T, 256, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 320: fft_cols_w<T, 320, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 384: fft_cols_w<T, 384, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            case 512: fft_cols_w<T, 512, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
-            default: break;
+        switch (ny / 16) {
+#define RP4D_WAVE_COLS(b) \
+    case b: fft_cols_w<T, 16 * b, L><<<gw, bw, 0, st>>>(z, nx, D, Wy); return;
+            RP4D_FFT_SIZES(RP4D_WAVE_COLS)
+#undef RP4D_WAVE_COLS
+            default: fail(RP4D_EINVAL, "2-D grid: unsupported ny");
         }
     }
     const dim3 grid((nx + kLines - 1) / kLines, (k + 1) / 2), blk(16 * kLines);

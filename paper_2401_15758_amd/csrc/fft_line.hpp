@@ -217,10 +217,11 @@ __device__ __forceinline__ void store_twiddles(C2<T>* wl, const C2<T> (&v)[twidd
 
 
 // ---------------------------------------------------------------------------
-// Lines transformed by one wave each (64 threads, lane q), for N a multiple
-// of 64 up to 512 whose factors are 2, 3 and 5 (64, 128, 192, 256, 320, 384,
-// 512): self-sorting (Stockham) passes of radix 4 while 4 divides what is
-// left, then one of radix 2, 3 or 5.  The pass that follows sub-transforms
+// Lines transformed by one wave each (64 threads, lane q), for every side
+// N = 16 B the 2-D model takes (32 to 512; factors 2, 3 and 5): self-sorting
+// (Stockham) passes of radix 4 while 4 divides what is left, then radix 2, 3
+// or 5 (160 = 4 4 2 5, 384 = 4 4 4 2 3); lanes past a pass's N/R butterflies
+// idle.  The pass that follows sub-transforms
 // of length NS takes, for each butterfly j < N/R, the R values j + r N/R,
 // multiplies value r by W_N^{(j mod NS) r N/(NS R)}, transforms them and writes
 // them to (j div NS) NS R + (j mod NS) + r NS.  The line is transformed in
@@ -290,15 +291,27 @@ __device__ __forceinline__ void stockham_from(C2<T>* line, int q, const C2<T>* W
 }
 
 // Transform the line of N complex values at `line` (LDS, padded) in place with
-// the 64 lanes of one wave (q = lane), twiddles Wl (W_N^m, m < N) in LDS
-// (N = 64, 128, 192, 256, 320, 384 or 512);
+// the 64 lanes of one wave (q = lane), twiddles Wl (W_N^m, m < N) in LDS;
 // conj = true gives the unnormalised inverse.  Only the line's own wave calls
 // it; it holds no workgroup barrier.
 template <typename T, int N>
 __device__ __forceinline__ void line_fft_wave(C2<T>* line, int q, const C2<T>* Wl, bool conj) {
-    static_assert(N >= 64 && N <= 512 && N % 64 == 0, "wave line FFTs take N = 64 .. 512, a multiple of 64");
+    static_assert(N >= 32 && N <= 512 && N % 16 == 0, "wave line FFTs take N = 16 B from 32 to 512");
     stockham_from<T, N, 1>(line, q, Wl, conj);
 }
+
+// Points of a wave line: lane q holds i = q + 64 u for u < wave_points<N>().
+// When 64 does not divide N the last u is ragged: wave_has is false on the
+// lanes past the end, where wave_point returns N - 1 so that their loads stay
+// in bounds; their stores and arithmetic are skipped.
+template <int N>
+constexpr int wave_points() { return (N + 63) / 64; }
+
+template <int N>
+__device__ __forceinline__ bool wave_has(int q, int u) { return N % 64 == 0 || q + 64 * u < N; }
+
+template <int N>
+__device__ __forceinline__ int wave_point(int q, int u) { return wave_has<N>(q, u) ? q + 64 * u : N - 1; }
 
 }  // namespace fftl
 }  // namespace rp4d

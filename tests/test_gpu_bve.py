@@ -23,11 +23,12 @@ SMALL = inputs.bve_config(32, nsteps=12, obs_stride=8, obs_every=4, L_cells=3.0,
 RAGGED = inputs.bve_config(48, nsteps=9, obs_stride=5, obs_every=4, L_cells=2.5, ell=6, name='bve-48')
 # grid width not a multiple of 64 (the stencils' column strips are 40 wide)
 WIDE = inputs.bve_config(80, nsteps=6, obs_stride=16, obs_every=3, L_cells=3.0, ell=6, name='bve-80')
-# power-of-two sides: with at most four field pairs the row stages run one wave
-# per row line (64 / 128 points per line, 64 rows over 11 blocks of 6: ragged)
+# with at most four field pairs (k <= 8) the row stages and column passes run
+# one wave per line on every side (32, 48 and 80 leave lanes idle: ragged
+# lines); five or more pairs take sixteen threads per line (k = 9 cases)
 P64 = inputs.bve_config(64, nsteps=6, obs_stride=8, obs_every=3, L_cells=3.0, ell=6, name='bve-64')
 P128 = inputs.bve_config(128, nsteps=4, obs_stride=16, obs_every=2, L_cells=3.0, ell=6, name='bve-128')
-# the other multiples of 64: mixed-radix wave line FFTs (4 x 4 x 4 x 3, x 5, x 2 x 3; 512 = 4^4 x 2)
+# mixed-radix wave line FFTs (4 x 4 x 4 x 3, x 5, x 2 x 3; 512 = 4^4 x 2)
 P_MIXED = [inputs.bve_config(nx, nsteps=2, obs_stride=16, obs_every=1, L_cells=3.0, ell=6, name=f'bve-{nx}')
            for nx in (192, 320, 384, 512)]
 
@@ -94,10 +95,10 @@ def test_fwd_observations_and_cost(cfg):
     assert pr.Jobs == pytest.approx(0.5 * float(np.sum(d * d)), rel=1e-12)
 
 
-@pytest.mark.parametrize("cfg,k", [(SMALL, 3), (RAGGED, 3), (WIDE, 3), (P64, 3), (P64, 9), (P128, 1)]
+@pytest.mark.parametrize("cfg,k", [(SMALL, 3), (RAGGED, 3), (WIDE, 3), (WIDE, 9), (P64, 3), (P64, 9), (P128, 1)]
                          + [(c, 2) for c in P_MIXED],
-                         ids=["bve-32", "bve-48-ragged", "bve-80", "bve-64-wave-rows", "bve-64-5-pairs",
-                              "bve-128-wave-rows"] + [c["name"] + "-wave-rows" for c in P_MIXED])
+                         ids=["bve-32", "bve-48-ragged", "bve-80", "bve-80-5-pairs", "bve-64", "bve-64-5-pairs",
+                              "bve-128"] + [c["name"] for c in P_MIXED])
 def test_tlm_adj_hessian_parity(cfg, k):
     need_gpu()
     pr = Pair(cfg, seed=3)
@@ -112,7 +113,7 @@ def test_tlm_adj_hessian_parity(cfg, k):
     assert colwise_relerr(HV, o.hessian(pr.otraj, V)) <= TOL_OP
 
 
-@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64-wave-rows"])
+@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64"])
 def test_adjoint_ignores_stale_workspace(cfg):
     """The adjoint sweep's first launch sets lambda on every point and reads none
     of it (a neighbour's halo would race with those writes), so nothing clears
@@ -148,7 +149,7 @@ def test_gradient_parity(small):
     assert relerr(g, gref) <= TOL_OP
 
 
-@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64-wave-rows"])
+@pytest.mark.parametrize("cfg", [SMALL, P64], ids=["bve-32", "bve-64"])
 def test_fp32_sweeps_close_to_oracle(cfg):
     torch = need_gpu()
     pr = Pair(cfg, seed=2)
@@ -171,7 +172,7 @@ def test_synthesis_parity():
 
 
 @pytest.mark.parametrize("method,cfg", [("nystrom", SMALL), ("randsvd", SMALL), ("nystrom", P64)],
-                         ids=["nystrom-bve-32", "randsvd-bve-32", "nystrom-bve-64-wave-rows"])
+                         ids=["nystrom-bve-32", "randsvd-bve-32", "nystrom-bve-64"])
 def test_gn_step_parity(method, cfg):
     need_gpu()
     from oracle import gn as ogn
