@@ -119,17 +119,24 @@ constexpr int LDK = GR + 4;       // col-major operand: S[col * LDK + k]
 // Offset of element (j, c) of an n-row matrix in the blocked layout with kc
 // vectors per block.  Blocked layouts have power-of-two kc (shifts and masks);
 // any other kc is a row-major matrix of width <= kc (checked by the launchers).
+// Written without branches (the two forms agree for c < kc, so only the block
+// index and the column within it are selected): a branch between a tile's
+// loads splits them into basic blocks that each wait for their data.
 __device__ __forceinline__ size_t ts_off(int j, int c, int kc, int n) {
-    if ((kc & (kc - 1)) == 0) {
-        const int sh = __builtin_ctz(kc);
-        return ((static_cast<size_t>(c >> sh) * n + j) << sh) + (c & (kc - 1));
-    }
-    return static_cast<size_t>(j) * kc + c;
+    const bool p2 = (kc & (kc - 1)) == 0;
+    const int blk = p2 ? (c >> __builtin_ctz(kc)) : 0;
+    const int in = p2 ? (c & (kc - 1)) : c;
+    return (static_cast<size_t>(blk) * n + j) * static_cast<size_t>(kc) + in;
 }
 
+// The load is unconditional (element (0, 0) stands in outside the matrix) and
+// the zero is selected after it: a guarded load compiles to a branch with a
+// wait for its data, which made a tile's loads one memory round trip each.
 template <typename TX>
 __device__ __forceinline__ double ts_ld(const TX* X, int lx, int n, int row, int col, int nrow, int ncol) {
-    return (row < nrow && col < ncol) ? static_cast<double>(X[ts_off(row, col, lx, n)]) : 0.0;
+    const bool ok = row < nrow && col < ncol;
+    const double v = static_cast<double>(X[ts_off(ok ? row : 0, ok ? col : 0, lx, n)]);
+    return ok ? v : 0.0;
 }
 
 // An operand block of GR rows x 64 columns in LDS.  Loaded with lanes walking
@@ -357,6 +364,11 @@ __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const do
     // X(row, k): "columns" of the operand block are rows of the output
     const TsBlock bx{lx < 16};
     double xv[PER], mv[PER];
+    // every load of a block unconditional and in one basic block, so that all
+    // of them are in flight together: out-of-range elements load a stand-in
+    // (element 0; the scales from M when there are none) and select zero
+    const bool has_ds = ds != nullptr;
+    const double* dsrc = has_ds ? ds : M;
     auto load = [&](int kk) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -365,9 +377,11 @@ __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const do
             bx.coords(e, k, c);
             xv[q] = ts_ld(X, lx, n, r0 + c, kk + k, n, a);
             const int mk = e / 64, mj = e % 64;
-            double m = (kk + mk < a && j0 + mj < b) ? M[static_cast<size_t>(kk + mk) * b + j0 + mj] : 0.0;
-            if (ds != nullptr && kk + mk < a) m *= ds[kk + mk];
-            mv[q] = m;
+            const bool krow = kk + mk < a, okm = krow && j0 + mj < b;
+            const double m = M[okm ? static_cast<size_t>(kk + mk) * b + j0 + mj : 0];
+            const double dk = dsrc[krow ? kk + mk : 0];
+            const double mm = okm ? m : 0.0;
+            mv[q] = (has_ds && krow) ? mm * dk : mm;
         }
     };
     const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
@@ -406,18 +420,21 @@ __global__ void __launch_bounds__(256) tsmm_kernel(const TX* X, int lx, const do
     }
     // Out may alias C: every C element of the lane is read before any store, so
     // the loads go out together instead of one round trip per output
-    double cv[2][2][4];
+    double cv[2][2][4] = {};
+    if (beta != 0.0) {  // uniform; the loads unconditional, as in ts_ld
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+            for (int v = 0; v < 2; ++v)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = r0 + wi + 16 * u + 4 * r + (lane >> 4);
-                const int col = j0 + wj + 16 * v + (lane & 15);
-                cv[u][v][r] = (beta != 0.0 && row < n && col < b) ? static_cast<double>(C[ts_off(row, col, lc, n)])
-                                                                  : 0.0;
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = r0 + wi + 16 * u + 4 * r + (lane >> 4);
+                    const int col = j0 + wj + 16 * v + (lane & 15);
+                    const bool ok = row < n && col < b;
+                    const double c = static_cast<double>(C[ts_off(ok ? row : 0, ok ? col : 0, lc, n)]);
+                    cv[u][v][r] = ok ? c : 0.0;
+                }
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
